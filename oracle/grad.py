@@ -1,0 +1,147 @@
+"""Gradient of the MSE fitness with respect to program constants -- test infrastructure.
+
+The paper evolves structure and constants together and has no gradient step;
+the library adds a reverse-mode adjoint over the postfix tape so a program's
+ephemeral constants can be tuned by gradient descent.  This module is the
+float64 reference for it.
+
+For F = (1/M) sum_i (y_hat_i - y_i)^2 the seed is dF/dy_hat_i = 2 (y_hat_i - y_i) / M.
+Adjoints flow from each token to its operands (reverse token order) with
+these partial derivatives, matching the operator conventions of
+``oracle.interp`` (derivative taken as 0 where a protected branch replaces
+the operator by a constant):
+  ADD (1, 1)   SUB (1, -1)   MUL (b, a)
+  DIV (1/b, -a/b^2) if b != 0, else (0, 0)
+  SIN cos x    COS -sin x
+  EXP exp x inside [-80, 80], else 0
+  LOG 1/x if x != 0, else 0
+  SQRT sign(x) / (2 sqrt|x|) if x != 0, else 0
+A constant slot's gradient is the sum over cases of the adjoints of every
+CONST token that reads it.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import interp
+
+ADD, SUB, MUL, DIV, SIN, COS, EXP, LOG, SQRT, VAR, CONST = range(11)
+
+
+def _mse64(y_hat, y64):
+    d = y_hat - y64
+    return math.fsum((d * d).tolist()) / y_hat.shape[0]
+
+
+def mse_and_grad(tokens, consts, X, y):
+    """(F, dF/dconsts float64[len(consts)]) in binary64 throughout."""
+    X64 = np.asarray(X, dtype=np.float32).astype(np.float64)
+    y64 = np.asarray(y, dtype=np.float32).astype(np.float64)
+    c64 = np.asarray(consts, dtype=np.float32).astype(np.float64)
+    return mse_and_grad64(tokens, c64, X64, y64)
+
+
+def mse_and_grad64(tokens, c64, X64, y64):
+    values, children = interp.run_tape(tokens, c64, X64)
+    M = X64.shape[0]
+    L = len(tokens)
+    y_hat = values[-1]
+    F = _mse64(y_hat, y64)
+    adj = [None] * L
+    adj[L - 1] = 2.0 * (y_hat - y64) / M
+    g = [[] for _ in range(len(c64))]
+    with np.errstate(all="ignore"):
+        for t in range(L - 1, -1, -1):
+            op, arg = int(tokens[t]) & 0xFF, int(tokens[t]) >> 8
+            a_t = adj[t]
+            if op == VAR:
+                continue
+            if op == CONST:
+                g[arg].append(math.fsum(a_t.tolist()))
+                continue
+            kids = children[t]
+            if len(kids) == 2:
+                ia, ib = kids
+                a, b = values[ia], values[ib]
+                if op == ADD:
+                    da, db = a_t, a_t
+                elif op == SUB:
+                    da, db = a_t, -a_t
+                elif op == MUL:
+                    da, db = a_t * b, a_t * a
+                elif op == DIV:
+                    nz = b != 0.0
+                    bs = np.where(nz, b, 1.0)
+                    da = np.where(nz, a_t / bs, 0.0)
+                    db = np.where(nz, -a_t * a / (bs * bs), 0.0)
+                else:
+                    raise ValueError(op)
+                adj[ia], adj[ib] = da, db
+            else:
+                (ix,) = kids
+                x = values[ix]
+                if op == SIN:
+                    dx = a_t * np.cos(x)
+                elif op == COS:
+                    dx = -a_t * np.sin(x)
+                elif op == EXP:
+                    inside = ~((x > 80.0) | (x < -80.0))
+                    dx = np.where(inside, a_t * np.exp(np.where(inside, x, 0.0)), 0.0)
+                elif op == LOG:
+                    nz = x != 0.0
+                    dx = np.where(nz, a_t / np.where(nz, x, 1.0), 0.0)
+                elif op == SQRT:
+                    nz = x != 0.0
+                    dx = np.where(nz, a_t * np.sign(x) / (2.0 * np.sqrt(np.abs(np.where(nz, x, 1.0)))), 0.0)
+                else:
+                    raise ValueError(op)
+                adj[ix] = dx
+    grad = np.array([math.fsum(v) for v in g], dtype=np.float64)
+    return F, grad
+
+
+def branch_masks(tokens, c64, X64):
+    """Boolean masks of every protected-branch decision (for FD admissibility)."""
+    values, children = interp.run_tape(tokens, c64, X64)
+    masks = []
+    for t, tk in enumerate(tokens):
+        op = int(tk) & 0xFF
+        if op == DIV:
+            masks.append(values[children[t][1]] == 0.0)
+        elif op == EXP:
+            x = values[children[t][0]]
+            masks.append(x > 80.0)
+            masks.append(x < -80.0)
+        elif op == LOG or op == SQRT:
+            masks.append(values[children[t][0]] == 0.0)
+    return masks
+
+
+def central_fd(tokens, consts, X, y, rel_step: float = 1e-5):
+    """Central finite differences of the binary64 MSE, and which slots are admissible.
+
+    Step h_j = rel_step * max(1, |c_j|).  A slot is inadmissible when the +-h
+    perturbation flips any protected-branch decision in any case.
+    """
+    X64 = np.asarray(X, dtype=np.float32).astype(np.float64)
+    y64 = np.asarray(y, dtype=np.float32).astype(np.float64)
+    c64 = np.asarray(consts, dtype=np.float32).astype(np.float64)
+    base = branch_masks(tokens, c64, X64)
+    fd = np.zeros(len(c64))
+    ok = np.ones(len(c64), dtype=bool)
+    for j in range(len(c64)):
+        h = rel_step * max(1.0, abs(c64[j]))
+        cp = c64.copy()
+        cm = c64.copy()
+        cp[j] += h
+        cm[j] -= h
+        for cc in (cp, cm):
+            for m0, m1 in zip(base, branch_masks(tokens, cc, X64)):
+                if np.any(m0 != m1):
+                    ok[j] = False
+        fp = _mse64(interp.run_tape(tokens, cp, X64)[0][-1], y64)
+        fm = _mse64(interp.run_tape(tokens, cm, X64)[0][-1], y64)
+        fd[j] = (fp - fm) / (cp[j] - cm[j])
+    return fd, ok

@@ -1,0 +1,134 @@
+"""Independent recursive tree evaluator -- test infrastructure.
+
+A second reading of the same reverse-Polish programs (paper, section 2.1.4):
+the postfix tokens are parsed into an explicit expression tree, which is then
+evaluated case by case with scalar Python arithmetic.  It shares no code with
+``oracle.interp`` (explicit tree instead of a value stack, one case at a time
+instead of whole vectors), so agreement between the two pins operand order,
+arity handling and the operator conventions.  The elementary functions sin,
+cos, exp and log are taken from numpy (called on one-element arrays, which
+numpy evaluates exactly as it does inside longer arrays) so that the two
+evaluators can be compared bit for bit.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+_NAMES = {0: "+", 1: "-", 2: "*", 3: "/", 4: "sin", 5: "cos", 6: "exp", 7: "log", 8: "sqrt"}
+
+
+class Node:
+    __slots__ = ("kind", "arg", "kids")
+
+    def __init__(self, kind, arg, kids):
+        self.kind = kind
+        self.arg = arg
+        self.kids = kids
+
+
+def parse(tokens) -> Node:
+    """Postfix tokens -> expression tree (raises on malformed programs)."""
+    st = []
+    for t in tokens:
+        op, arg = int(t) & 0xFF, int(t) >> 8
+        if op == 9:
+            st.append(Node("var", arg, []))
+        elif op == 10:
+            st.append(Node("const", arg, []))
+        elif op in (0, 1, 2, 3):
+            right = st.pop()
+            left = st.pop()
+            st.append(Node(_NAMES[op], 0, [left, right]))
+        elif op in (4, 5, 6, 7, 8):
+            st.append(Node(_NAMES[op], 0, [st.pop()]))
+        else:
+            raise ValueError(op)
+    if len(st) != 1:
+        raise ValueError("program does not reduce to one value")
+    return st[0]
+
+
+def to_postfix(node: Node):
+    """Serialise a tree back to tokens (left subtree first)."""
+    codes = {v: k for k, v in _NAMES.items()}
+    out = []
+
+    def walk(n):
+        for k in n.kids:
+            walk(k)
+        if n.kind == "var":
+            out.append(9 | (n.arg << 8))
+        elif n.kind == "const":
+            out.append(10 | (n.arg << 8))
+        else:
+            out.append(codes[n.kind])
+
+    walk(node)
+    return out
+
+
+def size(node: Node) -> int:
+    return 1 + sum(size(k) for k in node.kids)
+
+
+def _r32(v: float) -> float:
+    with np.errstate(over="ignore"):
+        return float(np.float32(v))
+
+
+def _np1(f, x: float) -> float:
+    with np.errstate(all="ignore"):
+        return float(f(np.array([x], dtype=np.float64))[0])
+
+
+def _scalar(kind, vals):
+    if kind == "+":
+        return vals[0] + vals[1]
+    if kind == "-":
+        return vals[0] - vals[1]
+    if kind == "*":
+        return vals[0] * vals[1]
+    if kind == "/":
+        a, b = vals
+        if b == 0.0:
+            return 1.0
+        return a / b
+    x = vals[0]
+    if kind in ("sin", "cos"):
+        if math.isinf(x):
+            return math.nan
+        return _np1(np.sin if kind == "sin" else np.cos, x)
+    if kind == "exp":
+        if x > 80.0:
+            x = 80.0
+        elif x < -80.0:
+            x = -80.0
+        return _np1(np.exp, x)  # NaN stays NaN
+    if kind == "log":
+        if x == 0.0:
+            return 0.0
+        if math.isnan(x):
+            return math.nan
+        return _np1(np.log, abs(x))
+    if kind == "sqrt":
+        return math.sqrt(abs(x))
+    raise ValueError(kind)
+
+
+def evaluate(node: Node, xrow, consts, round32: bool = False) -> float:
+    """Value of the tree for one fitness case (a row of X)."""
+    if node.kind == "var":
+        return float(xrow[node.arg])
+    if node.kind == "const":
+        return float(consts[node.arg])
+    v = _scalar(node.kind, [evaluate(k, xrow, consts, round32) for k in node.kids])
+    return _r32(v) if round32 else v
+
+
+def run(tokens, consts, X, round32: bool = False) -> np.ndarray:
+    root = parse(tokens)
+    c = [float(np.float32(v)) for v in consts]
+    Xf = np.asarray(X, dtype=np.float32)
+    return np.array([evaluate(root, [float(v) for v in row], c, round32) for row in Xf])
