@@ -1,0 +1,158 @@
+"""Benchmark of the population evaluator on one MI355X.
+
+One step = one beagle_eval call on the plain-mid workload: N = 4096 postfix
+programs (lengths uniform 5..64, up to 8 constants, op set + - * / sin cos exp
+log sqrt), D = 5, M = 100000 fitness cases, correlation fitness 1 - r^2 with
+binary64 sums.  Inputs are resident on the GPU before timing starts.  A step
+covers program validation and decoding, case staging, the interpreter, the
+per-case fitness terms, the reductions and the finalize.
+
+Prints one JSON line:
+  value          GPop/s = (sum of program lengths) * M * steps / seconds / 1e9
+  roofline       the interpreter kernel against the chip's fp32 VALU lane
+                 rate (see the roofline note below), with its duration
+                 measured by HIP events on the kernel's stream
+  cpu_baseline   the float64 CPU oracle on a bounded sample of the same
+                 workload, on this host's cores
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# fp32 VALU issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = one
+# non-packed fp32 lane operation per lane per clock (the 157.3 TFLOP/s figure
+# counts a packed two-wide FMA as 4 flops; a stack interpreter issues neither).
+PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+HBM_PEAK = 8.0e12
+EVAL_SOURCES = ["eval.hip", "beagle_device.h", "kernels.h"]
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in EVAL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2603_12292_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def function_nodes(ps) -> int:
+    ops = ps.tokens & 0xFF
+    return int(np.count_nonzero(ops < 9))
+
+
+def traffic_from_profile():
+    """HBM bytes per launch of the interpreter kernel from the committed counter
+    summary, or None when the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "k_eval_fast_corr_plain_mid_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_hash") != source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(w, kind_id, budget_programs: int):
+    from oracle import population as opop
+    ps = w.programs
+    cores = min(16, len(os.sched_getaffinity(0)))
+    step = max(1, ps.n // budget_programs)
+    sub = list(range(0, ps.n, step))[:budget_programs]
+    nodes = int(ps.tok_len[sub].astype(np.int64).sum())
+    t0 = time.perf_counter()
+    opop.evaluate_population(ps.tokens, ps.tok_offset, ps.tok_len, ps.consts, ps.const_offset, ps.const_count,
+                             w.data.X, w.data.y, kind_id, "o64", subset=sub, processes=cores)
+    dt = time.perf_counter() - t0
+    return {"value": nodes * w.data.M / dt / 1e9, "unit": "GPop/s", "cores": cores, "kind": "oracle",
+            "sample": f"{len(sub)} of {ps.n} programs (every {step}th), all {w.data.M} cases, "
+                      f"correlation fitness, float64 oracle, {dt:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-programs", type=int, default=512)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (one process, one device)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2603_12292_amd import api
+    from paper_2603_12292_amd import workloads as wl
+
+    w = wl.config_mid()
+    ps = w.programs
+    dev = torch.device("cuda:0")
+    progs = api.DevicePrograms.from_programset(ps, dev)
+    X = torch.from_numpy(w.data.X).to(dev)
+    y = torch.from_numpy(w.data.y).to(dev)
+    ctx = api.context(0)
+    nodes = ps.node_count()
+    M = w.data.M
+
+    for _ in range(args.warmup):
+        api.evaluate(progs, X, y, "corr", ctx=ctx)
+    torch.cuda.synchronize()
+    ctx.enable_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        fit = api.evaluate(progs, X, y, "corr", ctx=ctx)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    k_ms, k_n = ctx.kernel_time()
+    ctx.enable_timing(False)
+    dt = t1 - t0
+    gpops = nodes * M * args.steps / dt / 1e9
+    assert np.isfinite(fit.cpu().numpy()).sum() > 0
+
+    k_avg_s = k_ms / 1e3 / max(k_n, 1)
+    fn = function_nodes(ps)
+    alg_ops = fn * M                       # one fp32 op per operator application
+    achieved = alg_ops / k_avg_s
+    traffic = traffic_from_profile()
+    out = {
+        "metric": "GPop/s (program-node x fitness-case evals/s), fwd and fwd+adjoint, 1 MI355X",
+        "value": round(gpops, 2),
+        "unit": "GPop/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (binary64 sums)",
+        "data": "synthetic",
+        "config": {"workload": "plain-mid: N=4096 programs, L~U{5..64}, D=5, M=100000, X~U(1,10), "
+                               "20-token target, correlation fitness 1-r^2",
+                   "programs": ps.n, "fitness_cases": M, "nodes": nodes, "kind": "corr"},
+        "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 4), "peak": round(PEAK_LANE_OPS / 1e12, 2),
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_LANE_OPS, 4),
+                     "traffic": traffic, "kernel": "k_eval_fast<corr>",
+                     "kernel_ms": round(k_avg_s * 1e3, 4), "alg_ops_per_launch": alg_ops,
+                     "kernel_gpops": round(nodes * M / k_avg_s / 1e9, 2)},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, 1, args.cpu_programs)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,214 @@
+/*
+ * beagle.h -- C ABI of the MI355X population evaluator for genetic
+ * programming symbolic regression (arXiv 2603.12292, "GPU-Accelerated
+ * Genetic Programming for Symbolic Regression with Beagle Framework").
+ *
+ * The paper's GPU side runs every genome of the population on a batch of
+ * fitness cases and returns one aggregate fitness per individual (section
+ * 2.1.2); genomes are reverse-Polish programs (section 2.1.4); the fitness is
+ * point-to-point or correlation based (section 2.1.5, Eq. 1).  This library
+ * is that evaluation step, plus a reverse-mode gradient with respect to the
+ * programs' constants and a generation step (selection and variation) that
+ * keeps the population on the device.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Array pointers are DEVICE pointers owned by the caller; the library
+ *    never frees them and keeps no reference after the call returns.
+ *  - Calls are asynchronous: they check their scalar arguments on the host,
+ *    enqueue kernels on `stream` (a hipStream_t; NULL = the null stream) and
+ *    return.  Argument errors are reported synchronously by the return code
+ *    and beagle_last_error(); per-program problems (malformed programs) are
+ *    reported asynchronously in the optional `status` array.
+ *  - A context owns its device workspace, grown on demand (hipMalloc; the
+ *    growth synchronises the device) and released by beagle_ctx_destroy.
+ *    One context must not be used by two host threads at once.
+ *  - Nothing here takes the device's scalar data cache for writing, and no
+ *    result depends on the order in which workgroups run: every reduction
+ *    has a fixed order, so repeated calls give bit-identical outputs.
+ *
+ * Token format (section 2.1.4: the genome is a reverse-Polish program)
+ * --------------------------------------------------------------------
+ *  One uint16 per token: opcode | (arg << 8).
+ *    0 ADD  1 SUB  2 MUL  3 DIV  4 SIN  5 COS  6 EXP  7 LOG  8 SQRT
+ *    9 VAR   (arg = input variable k < D)
+ *   10 CONST (arg = slot j < const_count of the program)
+ *  A binary operator pops b (top) then a and pushes a op b.  The arg of an
+ *  operator token is ignored.  Operator conventions (the paper keeps invalid
+ *  values rather than protecting operators; these protected forms are the
+ *  library's):
+ *    DIV  b == 0 ? 1 : a / b         EXP  exp(clamp(x, -80, 80)), NaN -> NaN
+ *    LOG  x == 0 ? 0 : log|x|        SQRT sqrt|x|        SIN, COS: IEEE
+ *  Evaluation is in binary32 per fitness case.
+ */
+#ifndef BEAGLE_H
+#define BEAGLE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BEAGLE_ABI_VERSION 1
+
+typedef struct beagle_ctx beagle_ctx;
+typedef void* beagle_stream; /* hipStream_t */
+
+/* Return codes of every entry point. */
+typedef enum {
+  BEAGLE_OK = 0,
+  BEAGLE_E_INVALID_ARG = -1, /* a scalar argument or a NULL pointer is wrong      */
+  BEAGLE_E_HIP = -2,         /* a HIP runtime call or kernel launch failed         */
+  BEAGLE_E_NOMEM = -3,       /* workspace allocation failed or exceeds the cap     */
+  BEAGLE_E_UNSUPPORTED = -4  /* a size beyond the limits below                     */
+} beagle_status;
+
+/* Fitness kinds (section 2.1.5).  MSE = (1/M) sum (yhat - y)^2.  CORR =
+ * 1 - r^2 with r Pearson's correlation (Eq. 1), its sums accumulated in
+ * binary64 and clamped to [0, 1].  Classification: MSE is NaN if any yhat is
+ * NaN, else +Inf if any yhat is +-Inf; CORR is NaN if any yhat is not
+ * finite, 1 if every yhat is equal, NaN if every y is equal. */
+typedef enum { BEAGLE_FIT_MSE = 0, BEAGLE_FIT_CORR = 1 } beagle_fitness_kind;
+
+/* Per-program status codes written to the optional status[] outputs.  A
+ * program with a non-zero status gets fitness NaN.  Tokens are checked in
+ * order; the first faulty token decides, checking opcode range, variable
+ * index, constant slot, then stack underflow. */
+enum {
+  BEAGLE_PROG_OK = 0,
+  BEAGLE_PROG_EMPTY = 1,           /* tok_len == 0                              */
+  BEAGLE_PROG_BAD_OPCODE = 2,      /* opcode > 10                               */
+  BEAGLE_PROG_UNDERFLOW = 3,       /* an operator finds too few operands        */
+  BEAGLE_PROG_BAD_FINAL_DEPTH = 4, /* the program leaves != 1 value             */
+  BEAGLE_PROG_BAD_VAR = 5,         /* VAR arg >= D                              */
+  BEAGLE_PROG_BAD_CONST = 6,       /* CONST arg >= const_count                  */
+  BEAGLE_PROG_TOO_LONG = 7,        /* tok_len > BEAGLE_MAX_LEN                  */
+  BEAGLE_PROG_BAD_LAYOUT = 8       /* offsets/lengths outside the given arrays  */
+};
+
+#define BEAGLE_MAX_LEN 4096 /* tokens per program                               */
+#define BEAGLE_MAX_D 16     /* input variables                                   */
+
+/* A population in packed layout.  Program p is
+ *   tokens[tok_offset[p] .. tok_offset[p] + tok_len[p])
+ * and its constant table is
+ *   consts[const_offset[p] .. const_offset[p] + const_count[p]).
+ * n_tokens and n_consts are the lengths of tokens[] and consts[]; ranges
+ * outside them give BEAGLE_PROG_BAD_LAYOUT. */
+typedef struct {
+  const uint16_t* tokens;
+  int64_t n_tokens;
+  const int64_t* tok_offset; /* [n_programs] */
+  const int32_t* tok_len;    /* [n_programs] */
+  const float* consts;
+  int64_t n_consts;
+  const int64_t* const_offset; /* [n_programs] */
+  const int32_t* const_count;  /* [n_programs] */
+  int32_t n_programs;
+} beagle_programs;
+
+/* Fitness cases: X[M x D] row-major (case-major) binary32, y[M] binary32. */
+typedef struct {
+  const float* X;
+  const float* y;
+  int64_t M;
+  int32_t D;
+} beagle_dataset;
+
+int beagle_abi_version(void);
+
+/* Message describing the last failure on the calling host thread ("" if none). */
+const char* beagle_last_error(void);
+
+/* Create a context on HIP device `device`.  max_workspace_bytes caps the
+ * workspace (0 = no cap); an evaluation that would need more is split into
+ * several passes over slices of the population, with identical results. */
+beagle_status beagle_ctx_create(beagle_ctx** out, int device, size_t max_workspace_bytes);
+void beagle_ctx_destroy(beagle_ctx* ctx);
+
+/* Kernel timing (instrumentation).  While enabled, every beagle_eval call
+ * records a pair of HIP events on its stream around its main evaluation
+ * kernel (the fast-path interpreter launch).  beagle_ctx_kernel_time waits
+ * for the recorded events and returns the summed elapsed time and the
+ * number of launches since timing was last enabled.  Enabling resets. */
+beagle_status beagle_ctx_enable_timing(beagle_ctx* ctx, int enable);
+beagle_status beagle_ctx_kernel_time(beagle_ctx* ctx, double* total_ms, int64_t* launches);
+
+/* Whole-population evaluation (section 2.1.2: every program runs on every
+ * fitness case and one aggregate fitness per program comes back).
+ *   fitness  double[n_programs] out, device
+ *   status   int8[n_programs] out, device, may be NULL
+ * Needs M >= 1 (M >= 2 for CORR), 1 <= D <= BEAGLE_MAX_D. */
+beagle_status beagle_eval(beagle_ctx* ctx, const beagle_programs* progs, const beagle_dataset* data,
+                          int kind, double* fitness, int8_t* status, beagle_stream stream);
+
+/* Workspace bytes beagle_eval needs for this population and dataset in one
+ * pass (before any capping); only the sizes in `progs` and `data` are read. */
+beagle_status beagle_eval_workspace_size(const beagle_programs* progs, const beagle_dataset* data, int kind,
+                                         size_t* bytes);
+
+/* Per-case outputs yhat[p * M + i] (binary32) of every program: a debugging
+ * and testing aid for small populations (n_programs * M <= 2^31).  Invalid
+ * programs give NaN rows. */
+beagle_status beagle_predict(beagle_ctx* ctx, const beagle_programs* progs, const beagle_dataset* data,
+                             float* yhat, int8_t* status, beagle_stream stream);
+
+/* MSE fitness and its gradient with respect to every program's constants
+ * (not in the paper: reverse-mode differentiation over the postfix tape so a
+ * program's ephemeral constants can be tuned by gradient steps).
+ *   grad_consts  float[n_consts] out, device, same layout as consts; slots
+ *                outside every program's range are left untouched
+ * Derivatives are taken as 0 where a protected branch replaces the
+ * operator by a constant (DIV by 0, EXP outside [-80, 80], LOG of 0, SQRT of
+ * 0).  Only BEAGLE_FIT_MSE is supported (BEAGLE_E_UNSUPPORTED otherwise). */
+beagle_status beagle_eval_grad(beagle_ctx* ctx, const beagle_programs* progs, const beagle_dataset* data,
+                               int kind, double* fitness, float* grad_consts, int8_t* status,
+                               beagle_stream stream);
+
+/* Parameters of initialisation and of one generation step. */
+typedef struct {
+  int32_t tournament;     /* entrants per tournament, >= 1                       */
+  float p_crossover;      /* probability of subtree crossover                    */
+  float p_mutation;       /* probability of point mutation; rest = copy          */
+  int32_t max_len;        /* token capacity of a child slot, <= BEAGLE_MAX_LEN    */
+  int32_t max_consts;     /* constant capacity of a child slot, <= 255           */
+  float const_lo;         /* new constants ~ U(const_lo, const_hi)               */
+  float const_hi;
+  int32_t init_depth_min; /* ramped half-and-half depths, 2^(max+1)-1 <= max_len */
+  int32_t init_depth_max;
+} beagle_gen_params;
+
+/* Ramped half-and-half initial population of n programs over D variables
+ * into fixed-capacity slots: tokens[c * max_len ...] (zero padded),
+ * len[c], consts[c * max_consts ...] (zero padded), const_count[c].
+ * Random draws come from Philox4x32-10 keyed by `seed` (see
+ * beagle_generation for the counter layout; initialisation uses generation
+ * field 0 and tag 0x80000000 | problem). */
+beagle_status beagle_init_population(beagle_ctx* ctx, const beagle_gen_params* params, int32_t n, int32_t D,
+                                     uint64_t seed, uint32_t problem, uint16_t* tokens, int32_t* len,
+                                     float* consts, int32_t* const_count, beagle_stream stream);
+
+/* One generation: for every child slot c in [0, n_programs), size-t
+ * tournament selection on `fitness` (lower is better, NaN worst, ties to
+ * the lower index), then subtree crossover, point mutation or a copy, into
+ * fixed-capacity child slots laid out as for beagle_init_population.
+ * Child c draws from Philox4x32-10 with key = seed (low word first) and
+ * counter (c, generation, block, problem); draw j is word j % 4 of block
+ * j / 4, in this layout: 0 operator choice, 1..t tournament A, t+1..2t
+ * tournament B, 2t+1 and 2t+2 crossover points in A and B, 2t+3 mutation
+ * position, 2t+4 mutation symbol, 2t+5 mutation constant.  Children are
+ * bit-exact functions of (parents, fitness, params, D, seed, generation,
+ * problem).  Parents must be valid programs (use the status output of an
+ * evaluation); the child arrays must not overlap the parents. */
+beagle_status beagle_generation(beagle_ctx* ctx, const beagle_programs* parents, const double* fitness,
+                                const beagle_gen_params* params, int32_t D, uint64_t seed, uint64_t generation,
+                                uint32_t problem, uint16_t* child_tokens, int32_t* child_len,
+                                float* child_consts, int32_t* child_const_count, beagle_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BEAGLE_H */

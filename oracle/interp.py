@@ -27,6 +27,12 @@ Modes
          fp32 arithmetic exactly (binary64 has more than 2*24+2 bits, so the
          double rounding is innocuous); for sin, cos, exp, log it is the
          binary64 libm value rounded once.
+  "o32p" o32e with each token's binary64 result first scaled by (1 + e),
+         e uniform in [-2^-22, 2^-22] (a few binary32 ulps), drawn from a
+         seeded generator: a model of any binary32 implementation whose
+         operations are accurate to a few ulps.  Used only to decide whether
+         a program's fitness is stable under such differences (conditioning),
+         never as a reference value.
 """
 from __future__ import annotations
 
@@ -113,14 +119,15 @@ def apply_op(op: int, a, b, x):
     raise ValueError(f"not an operator: {op}")
 
 
-def run(tokens, consts, X, mode: str = "o64") -> np.ndarray:
+def run(tokens, consts, X, mode: str = "o64", seed: int = 0) -> np.ndarray:
     """Evaluate one valid program on every row of X; returns y_hat float64 [M].
 
     ``consts`` and ``X`` are the fp32 arrays the GPU receives; they are
-    widened to binary64 exactly.
+    widened to binary64 exactly.  ``seed`` drives the "o32p" perturbations.
     """
-    if mode not in ("o64", "o32e"):
+    if mode not in ("o64", "o32e", "o32p"):
         raise ValueError(mode)
+    rng = np.random.default_rng(seed) if mode == "o32p" else None
     X64 = np.asarray(X, dtype=np.float32).astype(np.float64)
     c64 = np.asarray(consts, dtype=np.float32).astype(np.float64)
     M = X64.shape[0]
@@ -139,7 +146,10 @@ def run(tokens, consts, X, mode: str = "o64") -> np.ndarray:
             v = apply_op(op, a, b, None)
         else:
             v = apply_op(op, None, None, stack.pop())
-        if mode == "o32e":
+        if mode == "o32p":
+            with np.errstate(all="ignore"):
+                v = v * (1.0 + rng.uniform(-2.0 ** -22, 2.0 ** -22, size=M))
+        if mode != "o64":
             v = _round32(v)
         stack.append(v)
     (y_hat,) = stack

@@ -23,30 +23,30 @@ def program_slices(tok_offset, tok_len, const_offset, const_count):
         yield (int(tok_offset[p]), int(tok_len[p]), int(const_offset[p]), int(const_count[p]))
 
 
-def evaluate_one(tokens, consts, X, y, kind: int, mode: str = "o64"):
+def evaluate_one(tokens, consts, X, y, kind: int, mode: str = "o64", seed: int = 0):
     """(fitness, status) of one program."""
     D = X.shape[1]
     st, _ = interp.validate(tokens, len(consts), D)
     if st != interp.ST_OK:
         return math.nan, st
-    yh = interp.run(tokens, consts, X, mode)
+    yh = interp.run(tokens, consts, X, mode, seed)
     return fit.fitness(kind, yh, y), st
 
 
 def _worker(args):
-    tokens, consts, tok_offset, tok_len, const_offset, const_count, X, y, kind, mode, lo, hi = args
+    tokens, consts, tok_offset, tok_len, const_offset, const_count, X, y, kind, mode, lo, hi, seed = args
     out = np.empty(hi - lo)
     sts = np.empty(hi - lo, dtype=np.int8)
     for i, p in enumerate(range(lo, hi)):
         o, l = int(tok_offset[p]), int(tok_len[p])
         co, cc = int(const_offset[p]), int(const_count[p])
-        out[i], sts[i] = evaluate_one(tokens[o:o + l], consts[co:co + cc], X, y, kind, mode)
+        out[i], sts[i] = evaluate_one(tokens[o:o + l], consts[co:co + cc], X, y, kind, mode, seed * 1_000_003 + p)
     return lo, out, sts
 
 
 def evaluate_population(tokens, tok_offset, tok_len, consts, const_offset, const_count,
                         X, y, kind: int, mode: str = "o64", processes: Optional[int] = None,
-                        subset=None):
+                        subset=None, seed: int = 0):
     """fitness float64[N] (or [len(subset)]) and status int8[...].
 
     ``subset`` restricts the evaluation to the listed program indices (in
@@ -63,14 +63,14 @@ def evaluate_population(tokens, tok_offset, tok_len, consts, const_offset, const
     N = len(tok_len)
     if not processes or processes <= 1 or N < 2:
         _, f, s = _worker((tokens, consts, tok_offset, tok_len, const_offset, const_count,
-                           X, y, kind, mode, 0, N))
+                           X, y, kind, mode, 0, N, seed))
         return f, s
     import multiprocessing as mp
     chunks = []
     step = max(1, math.ceil(N / (processes * 4)))
     for lo in range(0, N, step):
         chunks.append((tokens, consts, tok_offset, tok_len, const_offset, const_count,
-                       X, y, kind, mode, lo, min(N, lo + step)))
+                       X, y, kind, mode, lo, min(N, lo + step), seed))
     f = np.empty(N)
     s = np.empty(N, dtype=np.int8)
     env_before = os.environ.get("OMP_NUM_THREADS")

@@ -1,0 +1,207 @@
+"""Python binding of the C ABI: torch device tensors in, torch device tensors out.
+
+Argument marshalling only -- every step of the evaluation runs in the HIP
+kernels of libbeagle.so.  Calls are enqueued on torch's current stream of the
+tensors' device.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import Optional, Tuple
+
+import numpy as np
+import torch
+
+from . import _lib
+
+_FIT_NAMES = {"mse": _lib.FIT_MSE, "corr": _lib.FIT_CORR}
+
+
+def _kind(kind) -> int:
+    """Fitness kind as the C enum value; unknown integers pass through so the
+    library reports them."""
+    if isinstance(kind, str):
+        if kind not in _FIT_NAMES:
+            raise ValueError(f"unknown fitness kind {kind!r}")
+        return _FIT_NAMES[kind]
+    return int(kind)
+
+
+class BeagleError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"beagle error {code}: {msg}")
+        self.code = code
+
+
+def _check(code: int):
+    if code != _lib.OK:
+        lib = _lib.load()
+        raise BeagleError(code, lib.beagle_last_error().decode())
+
+
+class Context:
+    """A library context (device workspace) on one HIP device."""
+
+    def __init__(self, device: int = 0, max_workspace_bytes: int = 0):
+        self.lib = _lib.load()
+        self.device = device
+        h = ctypes.c_void_p()
+        _check(self.lib.beagle_ctx_create(ctypes.byref(h), device, max_workspace_bytes))
+        self.handle = h
+
+    def enable_timing(self, enable: bool = True):
+        _check(self.lib.beagle_ctx_enable_timing(self.handle, 1 if enable else 0))
+
+    def kernel_time(self):
+        """(total ms, launches) of the main evaluation kernel since timing was enabled."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(self.lib.beagle_ctx_kernel_time(self.handle, ctypes.byref(ms), ctypes.byref(n)))
+        return float(ms.value), int(n.value)
+
+    def close(self):
+        if self.handle:
+            self.lib.beagle_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_contexts = {}
+
+
+def context(device: int = 0) -> Context:
+    ctx = _contexts.get(device)
+    if ctx is None:
+        ctx = Context(device)
+        _contexts[device] = ctx
+    return ctx
+
+
+@dataclasses.dataclass
+class DevicePrograms:
+    """A population in the library's packed layout, resident on a GPU.
+
+    tokens are stored as int16 tensors holding the uint16 token bits.
+    """
+
+    tokens: torch.Tensor        # int16 [n_tokens]
+    tok_offset: torch.Tensor    # int64 [N]
+    tok_len: torch.Tensor       # int32 [N]
+    consts: torch.Tensor        # float32 [n_consts]
+    const_offset: torch.Tensor  # int64 [N]
+    const_count: torch.Tensor   # int32 [N]
+
+    @property
+    def n(self) -> int:
+        return int(self.tok_len.shape[0])
+
+    @property
+    def device(self) -> torch.device:
+        return self.tok_len.device
+
+    @staticmethod
+    def from_arrays(tokens, tok_offset, tok_len, consts, const_offset, const_count, device="cuda") -> "DevicePrograms":
+        t = torch.from_numpy(np.ascontiguousarray(np.asarray(tokens, dtype=np.uint16)).view(np.int16))
+        return DevicePrograms(
+            t.to(device),
+            torch.as_tensor(np.asarray(tok_offset, dtype=np.int64)).to(device),
+            torch.as_tensor(np.asarray(tok_len, dtype=np.int32)).to(device),
+            torch.as_tensor(np.asarray(consts, dtype=np.float32)).to(device),
+            torch.as_tensor(np.asarray(const_offset, dtype=np.int64)).to(device),
+            torch.as_tensor(np.asarray(const_count, dtype=np.int32)).to(device))
+
+    @staticmethod
+    def from_programset(ps, device="cuda") -> "DevicePrograms":
+        return DevicePrograms.from_arrays(ps.tokens, ps.tok_offset, ps.tok_len, ps.consts, ps.const_offset,
+                                          ps.const_count, device)
+
+    @staticmethod
+    def from_fixed(tokens: torch.Tensor, lens: torch.Tensor, consts: torch.Tensor,
+                   const_count: torch.Tensor) -> "DevicePrograms":
+        """View fixed-capacity slot arrays ([N, max_len], [N, max_consts]) as a population."""
+        N, max_len = tokens.shape
+        max_c = consts.shape[1]
+        dev = tokens.device
+        return DevicePrograms(tokens.reshape(-1), torch.arange(N, device=dev, dtype=torch.int64) * max_len,
+                              lens, consts.reshape(-1), torch.arange(N, device=dev, dtype=torch.int64) * max_c,
+                              const_count)
+
+    def struct(self) -> _lib.Programs:
+        for name, t, dt in (("tokens", self.tokens, torch.int16), ("tok_offset", self.tok_offset, torch.int64),
+                            ("tok_len", self.tok_len, torch.int32), ("consts", self.consts, torch.float32),
+                            ("const_offset", self.const_offset, torch.int64),
+                            ("const_count", self.const_count, torch.int32)):
+            if t.dtype != dt:
+                raise TypeError(f"{name} must be {dt}, got {t.dtype}")
+            if not t.is_contiguous():
+                raise ValueError(f"{name} must be contiguous")
+            if t.device != self.device:
+                raise ValueError(f"{name} is on {t.device}, expected {self.device}")
+        if self.device.type != "cuda":
+            raise ValueError("programs must live on a GPU")
+        return _lib.Programs(self.tokens.data_ptr(), self.tokens.numel(), self.tok_offset.data_ptr(),
+                             self.tok_len.data_ptr(), self.consts.data_ptr(), self.consts.numel(),
+                             self.const_offset.data_ptr(), self.const_count.data_ptr(), self.n)
+
+
+def _dataset(X: torch.Tensor, y: torch.Tensor, device) -> _lib.Dataset:
+    if X.dtype != torch.float32 or y.dtype != torch.float32:
+        raise TypeError("X and y must be float32")
+    if X.dim() != 2 or y.dim() != 1 or y.shape[0] != X.shape[0]:
+        raise ValueError("X must be [M, D] and y [M]")
+    if not X.is_contiguous() or not y.is_contiguous():
+        raise ValueError("X and y must be contiguous")
+    if X.device != device or y.device != device:
+        raise ValueError("X and y must be on the programs' device")
+    return _lib.Dataset(X.data_ptr(), y.data_ptr(), X.shape[0], X.shape[1])
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ctx_for(device: torch.device, ctx: Optional[Context]) -> Context:
+    return ctx if ctx is not None else context(device.index or 0)
+
+
+def evaluate(progs: DevicePrograms, X: torch.Tensor, y: torch.Tensor, kind="mse", *,
+             with_status: bool = False, ctx: Optional[Context] = None):
+    """fitness float64 [N] (and int8 status [N]) -- beagle_eval."""
+    dev = progs.device
+    c = _ctx_for(dev, ctx)
+    ps = progs.struct()
+    ds = _dataset(X, y, dev)
+    fit = torch.empty(progs.n, dtype=torch.float64, device=dev)
+    st = torch.empty(progs.n, dtype=torch.int8, device=dev) if with_status else None
+    _check(c.lib.beagle_eval(c.handle, ctypes.byref(ps), ctypes.byref(ds), _kind(kind), fit.data_ptr(),
+                             st.data_ptr() if st is not None else None, _stream(dev)))
+    return (fit, st) if with_status else fit
+
+
+def eval_workspace_bytes(progs: DevicePrograms, X: torch.Tensor, y: torch.Tensor, kind="mse") -> int:
+    lib = _lib.load()
+    ps = progs.struct()
+    ds = _dataset(X, y, progs.device)
+    out = ctypes.c_size_t()
+    _check(lib.beagle_eval_workspace_size(ctypes.byref(ps), ctypes.byref(ds), _kind(kind), ctypes.byref(out)))
+    return int(out.value)
+
+
+def predict(progs: DevicePrograms, X: torch.Tensor, *, with_status: bool = False, ctx: Optional[Context] = None):
+    """Per-case outputs float32 [N, M] -- beagle_predict."""
+    dev = progs.device
+    c = _ctx_for(dev, ctx)
+    ps = progs.struct()
+    y = torch.zeros(X.shape[0], dtype=torch.float32, device=dev)
+    ds = _dataset(X, y, dev)
+    out = torch.empty((progs.n, X.shape[0]), dtype=torch.float32, device=dev)
+    st = torch.empty(progs.n, dtype=torch.int8, device=dev) if with_status else None
+    _check(c.lib.beagle_predict(c.handle, ctypes.byref(ps), ctypes.byref(ds), out.data_ptr(),
+                                st.data_ptr() if st is not None else None, _stream(dev)))
+    return (out, st) if with_status else out

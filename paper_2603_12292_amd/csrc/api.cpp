@@ -1,0 +1,414 @@
+// C ABI of the library: contexts, workspace, argument checks and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/beagle.h"
+#include "beagle_device.h"
+#include "kernels.h"
+
+struct beagle_ctx {
+  int device = 0;
+  size_t cap = 0;       // 0 = unlimited
+  char* ws = nullptr;   // device workspace
+  size_t ws_size = 0;
+  bool timing = false;  // record events around the main evaluation kernel
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+};
+
+namespace {
+
+thread_local std::string g_error;
+
+beagle_status fail(beagle_status s, const std::string& msg) {
+  g_error = msg;
+  return s;
+}
+
+beagle_status hip_fail(hipError_t e, const char* where) {
+  return fail(BEAGLE_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+// Makes ctx->device current for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  hipError_t err = hipSuccess;
+  explicit DeviceGuard(int dev) {
+    err = hipGetDevice(&prev);
+    if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+// Bump allocator over the context workspace (256-byte aligned pieces).
+struct Carve {
+  size_t used = 0;
+  template <class T>
+  size_t take(size_t count) {
+    const size_t at = (used + 255) & ~size_t(255);
+    used = at + count * sizeof(T);
+    return at;
+  }
+};
+
+beagle_status reserve(beagle_ctx* ctx, size_t bytes) {
+  if (ctx->cap && bytes > ctx->cap)
+    return fail(BEAGLE_E_NOMEM, "workspace of " + std::to_string(bytes) + " bytes exceeds the context cap of " +
+                                    std::to_string(ctx->cap));
+  if (bytes <= ctx->ws_size) return BEAGLE_OK;
+  // the old workspace may still be in use by queued work on any stream
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  ctx->ws = nullptr;
+  ctx->ws_size = 0;
+  size_t want = std::max(bytes, size_t(1) << 20);
+  if (!ctx->cap) want = std::max(want, bytes + bytes / 4);
+  if (ctx->cap) want = std::min(want, ctx->cap);
+  e = hipMalloc(reinterpret_cast<void**>(&ctx->ws), want);
+  if (e != hipSuccess) {
+    ctx->ws = nullptr;
+    return fail(BEAGLE_E_NOMEM, std::string("hipMalloc of workspace failed: ") + hipGetErrorString(e));
+  }
+  ctx->ws_size = want;
+  return BEAGLE_OK;
+}
+
+beagle_status check_programs(const beagle_programs* p) {
+  if (!p) return fail(BEAGLE_E_INVALID_ARG, "programs is NULL");
+  if (p->n_programs < 0) return fail(BEAGLE_E_INVALID_ARG, "n_programs < 0");
+  if (p->n_tokens < 0 || p->n_consts < 0) return fail(BEAGLE_E_INVALID_ARG, "n_tokens or n_consts < 0");
+  if (p->n_programs == 0) return BEAGLE_OK;
+  if (!p->tok_offset || !p->tok_len || !p->const_offset || !p->const_count)
+    return fail(BEAGLE_E_INVALID_ARG, "a program array pointer is NULL");
+  if (p->n_tokens > 0 && !p->tokens) return fail(BEAGLE_E_INVALID_ARG, "tokens is NULL");
+  if (p->n_consts > 0 && !p->consts) return fail(BEAGLE_E_INVALID_ARG, "consts is NULL");
+  if (p->n_tokens >= (int64_t(1) << 31)) return fail(BEAGLE_E_UNSUPPORTED, "n_tokens >= 2^31");
+  return BEAGLE_OK;
+}
+
+beagle_status check_data(const beagle_dataset* d, int kind) {
+  if (!d) return fail(BEAGLE_E_INVALID_ARG, "data is NULL");
+  if (d->D < 1 || d->D > BEAGLE_MAX_D) return fail(BEAGLE_E_UNSUPPORTED, "D must be in [1, 16]");
+  if (d->M < 1) return fail(BEAGLE_E_INVALID_ARG, "M must be >= 1");
+  if (kind == BEAGLE_FIT_CORR && d->M < 2) return fail(BEAGLE_E_INVALID_ARG, "correlation fitness needs M >= 2");
+  if (d->M > (int64_t(1) << 40)) return fail(BEAGLE_E_UNSUPPORTED, "M too large");
+  if (!d->X || !d->y) return fail(BEAGLE_E_INVALID_ARG, "X or y is NULL");
+  return BEAGLE_OK;
+}
+
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+// Case chunking of the evaluation grid: about 32K cases per chunk, more
+// chunks when the population alone gives too few workgroups to fill the GPU.
+void choose_chunks(int64_t M, int64_t N, int64_t* chunk, int32_t* n_chunks) {
+  const int64_t unit = bgl::CASES_PER_BLOCK_ITER;
+  const int64_t max_chunks = std::max<int64_t>(1, (M + unit - 1) / unit);
+  int64_t C = std::max<int64_t>(1, (M + 32767) / 32768);
+  const int64_t target_blocks = 4096;
+  if (N * C < target_blocks) C = std::max<int64_t>(C, (target_blocks + N - 1) / std::max<int64_t>(N, 1));
+  C = std::min(C, max_chunks);
+  const int64_t ch = round_up((M + C - 1) / C, unit);
+  *chunk = ch;
+  *n_chunks = int32_t((M + ch - 1) / ch);
+}
+
+// The pieces of workspace one evaluation uses.
+struct EvalLayout {
+  size_t code, cval, s_stack, s_start, s_need, meta, deep_count, deep_list, Xt, yp, stats, part, total;
+  int64_t Mp, chunk;
+  int32_t n_chunks, slice;
+};
+
+EvalLayout eval_layout(const beagle_programs* P, const beagle_dataset* d, int n_sums, int32_t slice) {
+  EvalLayout L{};
+  Carve c;
+  const int64_t nt = std::max<int64_t>(P->n_tokens, 1);
+  const int64_t N = std::max<int32_t>(P->n_programs, 1);
+  L.code = c.take<uint32_t>(nt);
+  L.cval = c.take<float>(nt);
+  L.s_stack = c.take<int32_t>(nt);
+  L.s_start = c.take<int32_t>(nt);
+  L.s_need = c.take<int32_t>(nt);
+  L.meta = c.take<bgl::ProgMeta>(N);
+  L.deep_count = c.take<int32_t>(64);
+  L.deep_list = c.take<int32_t>(N);
+  L.Mp = round_up(d->M, bgl::CASES_PER_WAVE_ITER);
+  L.Xt = c.take<float>(size_t(d->D) * L.Mp);
+  L.yp = c.take<float>(L.Mp);
+  L.stats = c.take<double>(4);
+  L.slice = slice;
+  // the chunking depends on the whole population only, so that a sliced
+  // evaluation sums every program's partials in the same order
+  choose_chunks(d->M, N, &L.chunk, &L.n_chunks);
+  L.part = c.take<double>(size_t(n_sums) * L.n_chunks * slice);
+  L.total = c.used + 256;
+  return L;
+}
+
+__global__ void k_zero_i32(int32_t* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// Validation + decoding of the programs and staging of the cases (shared by
+// evaluation, prediction and the gradient).
+beagle_status prepare(beagle_ctx* ctx, const beagle_programs* P, const beagle_dataset* d, const EvalLayout& L,
+                      int8_t* status, hipStream_t s) {
+  char* ws = ctx->ws;
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, reinterpret_cast<int32_t*>(ws + L.deep_count), 64);
+  bgl::PrepareArgs pa;
+  pa.tokens = P->tokens;
+  pa.n_tokens = P->n_tokens;
+  pa.tok_offset = P->tok_offset;
+  pa.tok_len = P->tok_len;
+  pa.consts = P->consts;
+  pa.n_consts = P->n_consts;
+  pa.const_offset = P->const_offset;
+  pa.const_count = P->const_count;
+  pa.n_programs = P->n_programs;
+  pa.D = d->D;
+  pa.code = reinterpret_cast<uint32_t*>(ws + L.code);
+  pa.cval = reinterpret_cast<float*>(ws + L.cval);
+  pa.scr_stack = reinterpret_cast<int32_t*>(ws + L.s_stack);
+  pa.scr_start = reinterpret_cast<int32_t*>(ws + L.s_start);
+  pa.scr_need = reinterpret_cast<int32_t*>(ws + L.s_need);
+  pa.meta = reinterpret_cast<bgl::ProgMeta*>(ws + L.meta);
+  pa.status_out = status;
+  pa.deep_count = reinterpret_cast<int32_t*>(ws + L.deep_count);
+  pa.deep_list = reinterpret_cast<int32_t*>(ws + L.deep_list);
+  hipLaunchKernelGGL(bgl::k_prepare, dim3((P->n_programs + 63) / 64), dim3(64), 0, s, pa);
+  bgl::StageArgs sa;
+  sa.X = d->X;
+  sa.y = d->y;
+  sa.M = d->M;
+  sa.Mp = L.Mp;
+  sa.D = d->D;
+  sa.Xt = reinterpret_cast<float*>(ws + L.Xt);
+  sa.yp = reinterpret_cast<float*>(ws + L.yp);
+  hipLaunchKernelGGL(bgl::k_stage_cases, dim3(uint32_t((L.Mp + 255) / 256)), dim3(256), 0, s, sa);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "prepare launch");
+  return BEAGLE_OK;
+}
+
+beagle_status launch_values(beagle_ctx* ctx, const beagle_programs* P, const beagle_dataset* d,
+                            const EvalLayout& L, int64_t m, float* out, int shift_mode, hipStream_t s) {
+  bgl::ValuesArgs va;
+  char* ws = ctx->ws;
+  va.code = reinterpret_cast<const uint32_t*>(ws + L.code);
+  va.cval = reinterpret_cast<const float*>(ws + L.cval);
+  va.tok_offset = P->tok_offset;
+  va.meta = reinterpret_cast<bgl::ProgMeta*>(ws + L.meta);
+  va.Xt = reinterpret_cast<const float*>(ws + L.Xt);
+  va.Mp = L.Mp;
+  va.m = m;
+  va.D = d->D;
+  va.n_programs = P->n_programs;
+  va.out = out;
+  va.shift_mode = shift_mode;
+  const int64_t tiles = (m + 63) / 64;
+  if (tiles > 65535) return fail(BEAGLE_E_UNSUPPORTED, "predict: M > 4194240");
+  hipLaunchKernelGGL(bgl::k_values, dim3(P->n_programs, uint32_t(tiles)), dim3(64), 0, s, va);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "values launch");
+  return BEAGLE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int beagle_abi_version(void) { return BEAGLE_ABI_VERSION; }
+
+const char* beagle_last_error(void) { return g_error.c_str(); }
+
+beagle_status beagle_ctx_create(beagle_ctx** out, int device, size_t max_workspace_bytes) {
+  if (!out) return fail(BEAGLE_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+  if (device < 0 || device >= n) return fail(BEAGLE_E_INVALID_ARG, "no such device");
+  beagle_ctx* c = new beagle_ctx;
+  c->device = device;
+  c->cap = max_workspace_bytes;
+  *out = c;
+  g_error.clear();
+  return BEAGLE_OK;
+}
+
+static void release_events(beagle_ctx* ctx) {
+  for (auto& pr : ctx->events) {
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  ctx->events.clear();
+}
+
+beagle_status beagle_ctx_enable_timing(beagle_ctx* ctx, int enable) {
+  if (!ctx) return fail(BEAGLE_E_INVALID_ARG, "ctx is NULL");
+  DeviceGuard g(ctx->device);
+  (void)hipDeviceSynchronize();
+  release_events(ctx);
+  ctx->timing = enable != 0;
+  return BEAGLE_OK;
+}
+
+beagle_status beagle_ctx_kernel_time(beagle_ctx* ctx, double* total_ms, int64_t* launches) {
+  if (!ctx || !total_ms || !launches) return fail(BEAGLE_E_INVALID_ARG, "NULL argument");
+  DeviceGuard g(ctx->device);
+  double total = 0.0;
+  for (auto& pr : ctx->events) {
+    hipError_t e = hipEventSynchronize(pr.second);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    float ms = 0.0f;
+    e = hipEventElapsedTime(&ms, pr.first, pr.second);
+    if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    total += ms;
+  }
+  *total_ms = total;
+  *launches = int64_t(ctx->events.size());
+  return BEAGLE_OK;
+}
+
+void beagle_ctx_destroy(beagle_ctx* ctx) {
+  if (!ctx) return;
+  {
+    DeviceGuard g(ctx->device);
+    (void)hipDeviceSynchronize();
+    release_events(ctx);
+  }
+  if (ctx->ws) {
+    DeviceGuard g(ctx->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(ctx->ws);
+  }
+  delete ctx;
+}
+
+beagle_status beagle_eval(beagle_ctx* ctx, const beagle_programs* progs, const beagle_dataset* data, int kind,
+                          double* fitness, int8_t* status, beagle_stream stream) {
+  if (!ctx) return fail(BEAGLE_E_INVALID_ARG, "ctx is NULL");
+  if (kind != BEAGLE_FIT_MSE && kind != BEAGLE_FIT_CORR) return fail(BEAGLE_E_INVALID_ARG, "unknown fitness kind");
+  beagle_status st = check_programs(progs);
+  if (st != BEAGLE_OK) return st;
+  st = check_data(data, kind);
+  if (st != BEAGLE_OK) return st;
+  if (progs->n_programs == 0) return BEAGLE_OK;
+  if (!fitness) return fail(BEAGLE_E_INVALID_ARG, "fitness is NULL");
+  DeviceGuard g(ctx->device);
+  if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int n_sums = kind == BEAGLE_FIT_MSE ? 1 : 3;
+  // largest program slice whose partials fit the cap (the whole population
+  // when there is no cap)
+  int32_t slice = progs->n_programs;
+  EvalLayout L = eval_layout(progs, data, n_sums, slice);
+  while (ctx->cap && L.total > ctx->cap && slice > 1) {
+    slice = (slice + 1) / 2;
+    L = eval_layout(progs, data, n_sums, slice);
+  }
+  st = reserve(ctx, L.total);
+  if (st != BEAGLE_OK) return st;
+  st = prepare(ctx, progs, data, L, status, s);
+  if (st != BEAGLE_OK) return st;
+  char* ws = ctx->ws;
+  if (kind == BEAGLE_FIT_CORR) {
+    hipLaunchKernelGGL(bgl::k_target_stats, dim3(1), dim3(1024), 0, s, data->y, data->M,
+                       reinterpret_cast<double*>(ws + L.stats));
+    st = launch_values(ctx, progs, data, L, 1, nullptr, 1, s);
+    if (st != BEAGLE_OK) return st;
+  }
+  for (int32_t p0 = 0; p0 < progs->n_programs; p0 += slice) {
+    const int32_t np = std::min(slice, progs->n_programs - p0);
+    bgl::EvalArgs ea;
+    ea.code = reinterpret_cast<const uint32_t*>(ws + L.code);
+    ea.cval = reinterpret_cast<const float*>(ws + L.cval);
+    ea.tok_offset = progs->tok_offset + p0;
+    ea.meta = reinterpret_cast<const bgl::ProgMeta*>(ws + L.meta) + p0;
+    ea.Xt = reinterpret_cast<const float*>(ws + L.Xt);
+    ea.yp = reinterpret_cast<const float*>(ws + L.yp);
+    ea.M = data->M;
+    ea.Mp = L.Mp;
+    ea.D = data->D;
+    ea.n_programs = np;
+    ea.n_chunks = L.n_chunks;
+    ea.chunk = L.chunk;
+    ea.part = reinterpret_cast<double*>(ws + L.part);
+    ea.stats = reinterpret_cast<const double*>(ws + L.stats);
+    ea.deep_count = reinterpret_cast<const int32_t*>(ws + L.deep_count);
+    ea.deep_list = reinterpret_cast<const int32_t*>(ws + L.deep_list);
+    ea.prog_begin = p0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (ctx->timing) {
+      if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
+        return fail(BEAGLE_E_HIP, "hipEventCreate");
+      ctx->events.emplace_back(ev0, ev1);
+    }
+    hipError_t e = bgl::launch_eval(kind, ea, s, ev0, ev1);
+    if (e != hipSuccess) return hip_fail(e, "eval launch");
+    bgl::FinalizeArgs fa;
+    fa.meta = ea.meta;
+    fa.part = ea.part;
+    fa.stats = ea.stats;
+    fa.M = data->M;
+    fa.n_programs = np;
+    fa.n_chunks = L.n_chunks;
+    fa.kind = kind;
+    fa.fitness = fitness + p0;
+    hipLaunchKernelGGL(bgl::k_finalize, dim3((np + 255) / 256), dim3(256), 0, s, fa);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "finalize launch");
+  }
+  g_error.clear();
+  return BEAGLE_OK;
+}
+
+beagle_status beagle_eval_workspace_size(const beagle_programs* progs, const beagle_dataset* data, int kind,
+                                         size_t* bytes) {
+  if (!bytes) return fail(BEAGLE_E_INVALID_ARG, "bytes is NULL");
+  if (kind != BEAGLE_FIT_MSE && kind != BEAGLE_FIT_CORR) return fail(BEAGLE_E_INVALID_ARG, "unknown fitness kind");
+  beagle_status st = check_programs(progs);
+  if (st != BEAGLE_OK) return st;
+  st = check_data(data, kind);
+  if (st != BEAGLE_OK) return st;
+  *bytes = eval_layout(progs, data, kind == BEAGLE_FIT_MSE ? 1 : 3, std::max(progs->n_programs, 1)).total;
+  return BEAGLE_OK;
+}
+
+beagle_status beagle_predict(beagle_ctx* ctx, const beagle_programs* progs, const beagle_dataset* data,
+                             float* yhat, int8_t* status, beagle_stream stream) {
+  if (!ctx) return fail(BEAGLE_E_INVALID_ARG, "ctx is NULL");
+  beagle_status st = check_programs(progs);
+  if (st != BEAGLE_OK) return st;
+  st = check_data(data, BEAGLE_FIT_MSE);
+  if (st != BEAGLE_OK) return st;
+  if (progs->n_programs == 0) return BEAGLE_OK;
+  if (!yhat) return fail(BEAGLE_E_INVALID_ARG, "yhat is NULL");
+  if (int64_t(progs->n_programs) * data->M > (int64_t(1) << 31))
+    return fail(BEAGLE_E_UNSUPPORTED, "predict: n_programs * M > 2^31");
+  DeviceGuard g(ctx->device);
+  if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  EvalLayout L = eval_layout(progs, data, 1, 1);
+  st = reserve(ctx, L.total);
+  if (st != BEAGLE_OK) return st;
+  st = prepare(ctx, progs, data, L, status, s);
+  if (st != BEAGLE_OK) return st;
+  st = launch_values(ctx, progs, data, L, data->M, yhat, 0, s);
+  if (st != BEAGLE_OK) return st;
+  g_error.clear();
+  return BEAGLE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,81 @@
+// Device-side definitions shared by the library's kernels: token format,
+// the decoded instruction word, and the operator conventions.
+//
+// Programs arrive as reverse-Polish token arrays (paper, section 2.1.4).
+// A preparation kernel validates each program, re-serialises it so that its
+// stack never holds more values than the register need of its expression
+// tree (Sethi-Ullman order: at every binary node the operand with the larger
+// need is evaluated first; for SUB and DIV the swap is recorded as a
+// reversed operator, so values are unchanged), and writes one 32-bit
+// instruction word per token:
+//
+//     word = handler | (arg << 8)
+//
+// where the handler fixes the operation AND the stack size n (number of
+// values on the stack before the token) at which it runs, so every operand
+// lives in a register named at compile time:
+//
+//     [0, 16)            VAR push with n = 0..15 values already on the stack
+//     [16, 32)           CONST push with n = 0..15 (value in the side table)
+//     32 + 15*o + (n-2)  binary operator o at n = 2..16 values, o in
+//                        ADD, SUB, MUL, DIV, RSUB (b - a), RDIV (b / a)
+//     122 + u            unary operator u in SIN, COS, EXP, LOG, SQRT
+//
+// The value on top of the stack is kept in `top`; the n-1 values below it
+// in stk[0..n-2].
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bgl {
+
+enum Opcode : uint32_t {
+  OP_ADD = 0,
+  OP_SUB = 1,
+  OP_MUL = 2,
+  OP_DIV = 3,
+  OP_SIN = 4,
+  OP_COS = 5,
+  OP_EXP = 6,
+  OP_LOG = 7,
+  OP_SQRT = 8,
+  OP_VAR = 9,
+  OP_CONST = 10,
+  N_OPCODES = 11
+};
+
+enum BinIdx : uint32_t { B_ADD = 0, B_SUB = 1, B_MUL = 2, B_DIV = 3, B_RSUB = 4, B_RDIV = 5 };
+
+constexpr int MAX_STACK = 16;       // largest register need any kernel supports
+constexpr int FAST_STACK = 8;       // register need handled by the fast kernels
+constexpr uint32_t H_VAR = 0;
+constexpr uint32_t H_CONST = 16;
+constexpr uint32_t H_BIN = 32;
+constexpr uint32_t H_UN = 32 + 15 * 6;  // 122
+constexpr int MAX_LEN = 4096;
+constexpr int MAX_D = 16;
+
+__host__ __device__ constexpr uint32_t h_bin(uint32_t o, int n) { return H_BIN + 15u * o + uint32_t(n - 2); }
+
+__device__ __forceinline__ int arity(uint32_t op) { return op < 4 ? 2 : (op < 9 ? 1 : 0); }
+
+// ---- operator conventions (binary32) -------------------------------------
+__device__ __forceinline__ float op_div(float a, float b) { return b == 0.0f ? 1.0f : a / b; }
+__device__ __forceinline__ float op_exp(float x) {
+  // comparisons keep NaN as NaN and map +-Inf to the clamp bounds
+  float c = x > 80.0f ? 80.0f : (x < -80.0f ? -80.0f : x);
+  return expf(c);
+}
+__device__ __forceinline__ float op_log(float x) { return x == 0.0f ? 0.0f : logf(fabsf(x)); }
+__device__ __forceinline__ float op_sqrt(float x) { return sqrtf(fabsf(x)); }
+
+// Per-program metadata written by the preparation kernel.
+struct ProgMeta {
+  int32_t status;  // BEAGLE_PROG_* code
+  int32_t need;    // register need of the expression tree (max stack size)
+  int32_t len;     // tokens
+  float shift;     // correlation fitness: the program's output at case 0
+};
+
+}  // namespace bgl

@@ -1,0 +1,106 @@
+// Kernel argument blocks and host-side launchers of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/beagle.h"
+#include "beagle_device.h"
+
+namespace bgl {
+
+struct PrepareArgs {
+  const uint16_t* tokens;
+  int64_t n_tokens;
+  const int64_t* tok_offset;
+  const int32_t* tok_len;
+  const float* consts;
+  int64_t n_consts;
+  const int64_t* const_offset;
+  const int32_t* const_count;
+  int32_t n_programs;
+  int32_t D;
+  uint32_t* code;      // [n_tokens] decoded words
+  float* cval;         // [n_tokens] CONST values by output position
+  int32_t* scr_stack;  // [n_tokens] scratch
+  int32_t* scr_start;  // [n_tokens] scratch
+  int32_t* scr_need;   // [n_tokens] scratch
+  ProgMeta* meta;      // [n_programs]
+  int8_t* status_out;  // [n_programs] or null
+  int32_t* deep_count; // programs whose register need exceeds FAST_STACK
+  int32_t* deep_list;  // [n_programs]
+};
+
+struct StageArgs {
+  const float* X;
+  const float* y;
+  int64_t M;
+  int64_t Mp;
+  int32_t D;
+  float* Xt;  // [D x Mp]
+  float* yp;  // [Mp]
+};
+
+struct EvalArgs {
+  const uint32_t* code;
+  const float* cval;
+  const int64_t* tok_offset;
+  const ProgMeta* meta;
+  const float* Xt;  // [D x Mp]
+  const float* yp;  // [Mp]
+  int64_t M;
+  int64_t Mp;
+  int32_t D;
+  int32_t n_programs;
+  int32_t n_chunks;
+  int64_t chunk;          // cases per chunk, a multiple of CASES_PER_BLOCK_ITER
+  double* part;           // [n_sums][n_chunks][n_programs]
+  const double* stats;    // target statistics (correlation fitness)
+  const int32_t* deep_count;
+  const int32_t* deep_list;  // global program indices
+  int32_t prog_begin;        // first program of this launch (slice-local index 0)
+};
+
+struct FinalizeArgs {
+  const ProgMeta* meta;
+  const double* part;
+  const double* stats;
+  int64_t M;
+  int32_t n_programs;
+  int32_t n_chunks;
+  int32_t kind;
+  double* fitness;
+};
+
+struct ValuesArgs {
+  const uint32_t* code;
+  const float* cval;
+  const int64_t* tok_offset;
+  ProgMeta* meta;
+  const float* Xt;
+  int64_t Mp;
+  int64_t m;        // cases evaluated: [0, m)
+  int32_t D;
+  int32_t n_programs;
+  float* out;       // [n_programs x m] or null (shift mode)
+  int32_t shift_mode;
+};
+
+constexpr int EVAL_WAVES = 4;
+constexpr int EVAL_K = 4;                                        // cases per lane
+constexpr int CASES_PER_WAVE_ITER = 64 * EVAL_K;                 // 256
+constexpr int CASES_PER_BLOCK_ITER = CASES_PER_WAVE_ITER * EVAL_WAVES;  // 1024
+constexpr int DEEP_K = 2;
+
+__global__ void k_prepare(PrepareArgs a);
+__global__ void k_stage_cases(StageArgs a);
+__global__ void k_target_stats(const float* __restrict__ y, int64_t M, double* __restrict__ stats);
+__global__ void k_finalize(FinalizeArgs a);
+__global__ void k_values(ValuesArgs a);
+
+// host launchers of the templated evaluation kernels (eval.hip)
+// ev0/ev1 (may be null) are recorded on `s` right before and after the
+// fast-path kernel.
+hipError_t launch_eval(int kind, const EvalArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
+
+}  // namespace bgl

@@ -1,0 +1,188 @@
+// Program preparation (validation, Sethi-Ullman re-serialisation, decoding)
+// and fitness-case staging.
+#include "beagle_device.h"
+#include "kernels.h"
+
+namespace bgl {
+
+// One thread per program.  Three passes over the tokens, with per-token
+// scratch in global memory (each program owns tokens[off, off + L) of
+// every scratch array):
+//  1. forward: validate, and for every token record the start of its
+//     subtree and its register need (Strahler number),
+//  2. backward from the root: place every subtree in the output order
+//     (operand with the larger need first) and write the re-ordered
+//     (opcode, arg) at its output position,
+//  3. forward over the output: track the stack size n before each token and
+//     write the handler word; CONST values go to the side table cval.
+__global__ void k_prepare(PrepareArgs a) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.n_programs) return;
+  const int64_t off = a.tok_offset[p];
+  const int32_t L = a.tok_len[p];
+  const int64_t coff = a.const_offset[p];
+  const int32_t cc = a.const_count[p];
+  int status = BEAGLE_PROG_OK;
+  int need_root = 0;
+  if (L <= 0) {
+    status = L == 0 ? BEAGLE_PROG_EMPTY : BEAGLE_PROG_BAD_LAYOUT;
+  } else if (L > MAX_LEN) {
+    status = BEAGLE_PROG_TOO_LONG;
+  } else if (off < 0 || off + L > a.n_tokens || cc < 0 ||
+             (cc > 0 && (coff < 0 || coff + cc > a.n_consts))) {
+    status = BEAGLE_PROG_BAD_LAYOUT;
+  }
+  if (status == BEAGLE_PROG_OK) {
+    const uint16_t* tok = a.tokens + off;
+    int32_t* stack = a.scr_stack + off;   // pass 1: node stack; pass 2: output starts
+    int32_t* start = a.scr_start + off;
+    int32_t* need = a.scr_need + off;
+    int depth = 0;
+    for (int i = 0; i < L; ++i) {
+      const uint32_t t = tok[i];
+      const uint32_t op = t & 0xFFu, arg = t >> 8;
+      if (op >= N_OPCODES) { status = BEAGLE_PROG_BAD_OPCODE; break; }
+      if (op == OP_VAR && int(arg) >= a.D) { status = BEAGLE_PROG_BAD_VAR; break; }
+      if (op == OP_CONST && int(arg) >= cc) { status = BEAGLE_PROG_BAD_CONST; break; }
+      const int ar = arity(op);
+      if (depth < ar) { status = BEAGLE_PROG_UNDERFLOW; break; }
+      if (ar == 0) {
+        start[i] = i;
+        need[i] = 1;
+      } else if (ar == 1) {
+        const int c = stack[depth - 1];
+        start[i] = start[c];
+        need[i] = need[c];
+      } else {
+        const int r = stack[depth - 1], l = stack[depth - 2];
+        start[i] = start[l];
+        const int nl = need[l], nr = need[r];
+        need[i] = nl == nr ? nl + 1 : (nl > nr ? nl : nr);
+      }
+      depth += 1 - ar;
+      stack[depth - 1] = i;
+    }
+    if (status == BEAGLE_PROG_OK && depth != 1) status = BEAGLE_PROG_BAD_FINAL_DEPTH;
+    if (status == BEAGLE_PROG_OK) {
+      need_root = need[L - 1];
+      uint32_t* code = a.code + off;
+      // pass 2: output start of every subtree, root first
+      int32_t* ostart = stack;
+      ostart[L - 1] = 0;
+      for (int i = L - 1; i >= 0; --i) {
+        const uint32_t t = tok[i];
+        uint32_t op = t & 0xFFu;
+        const uint32_t arg = t >> 8;
+        const int o = ostart[i];
+        const int size = i - start[i] + 1;
+        const int ar = arity(op);
+        if (ar == 1) {
+          ostart[i - 1] = o;
+        } else if (ar == 2) {
+          const int r = i - 1, l = start[r] - 1;
+          const int size_l = l - start[l] + 1;
+          const int size_r = r - start[r] + 1;
+          if (need[r] > need[l]) {
+            ostart[r] = o;
+            ostart[l] = o + size_r;
+            op = op == OP_SUB ? 100u + B_RSUB : (op == OP_DIV ? 100u + B_RDIV : op);
+          } else {
+            ostart[l] = o;
+            ostart[r] = o + size_l;
+          }
+        }
+        code[o + size - 1] = op | (arg << 8);
+      }
+      // pass 3: handler words at the output positions
+      float* cv = a.cval + off;
+      int n = 0, nmax = 0;
+      for (int i = 0; i < L; ++i) {
+        const uint32_t w = code[i];
+        const uint32_t op = w & 0xFFu, arg = w >> 8;
+        uint32_t h;
+        if (op == OP_VAR || op == OP_CONST) {
+          h = (op == OP_VAR ? H_VAR : H_CONST) + uint32_t(n);
+          if (op == OP_CONST) cv[i] = a.consts[coff + arg];
+          ++n;
+        } else if (op >= 100u) {
+          h = h_bin(op - 100u, n);
+          --n;
+        } else if (op < 4) {
+          h = h_bin(op, n);  // ADD..DIV have BinIdx equal to their opcode
+          --n;
+        } else {
+          h = H_UN + (op - OP_SIN);
+        }
+        nmax = n > nmax ? n : nmax;
+        code[i] = h | (arg << 8);
+      }
+      // nmax == need_root by construction; the larger one is kept defensively
+      need_root = nmax > need_root ? nmax : need_root;
+      if (need_root > MAX_STACK) status = BEAGLE_PROG_TOO_LONG;
+    }
+  }
+  ProgMeta m;
+  m.status = status;
+  m.need = need_root;
+  m.len = status == BEAGLE_PROG_OK ? L : 0;
+  m.shift = 0.0f;
+  a.meta[p] = m;
+  if (a.status_out) a.status_out[p] = int8_t(status);
+  if (status == BEAGLE_PROG_OK && need_root > FAST_STACK) {
+    const int slot = atomicAdd(a.deep_count, 1);
+    a.deep_list[slot] = p;
+  }
+}
+
+// X [M x D] row-major -> Xt [D x Mp] (case index fastest), y -> yp [Mp];
+// cases M..Mp-1 repeat case 0 (their outputs are masked out of every sum).
+__global__ void k_stage_cases(StageArgs a) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= a.Mp) return;
+  const int64_t src = i < a.M ? i : 0;
+  for (int d = 0; d < a.D; ++d) a.Xt[int64_t(d) * a.Mp + i] = a.X[src * a.D + d];
+  a.yp[i] = a.y[src];
+}
+
+// Target statistics for correlation fitness, one workgroup, fixed order:
+//   ybar = y0 + sum(y - y0) / M,  w_i = y_i - ybar (binary64),
+//   stats = {ybar, sum w, sum w^2 - (sum w)^2 / M}.
+__global__ void __launch_bounds__(1024) k_target_stats(const float* __restrict__ y, int64_t M,
+                                                       double* __restrict__ stats) {
+  __shared__ double red[2][1024];
+  const int t = threadIdx.x;
+  const double y0 = double(y[0]);
+  double s = 0.0;
+  for (int64_t i = t; i < M; i += 1024) s += double(y[i]) - y0;
+  red[0][t] = s;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (t < w) red[0][t] += red[0][t + w];
+    __syncthreads();
+  }
+  const double ybar = y0 + red[0][0] / double(M);
+  __syncthreads();
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t i = t; i < M; i += 1024) {
+    const double w = double(y[i]) - ybar;
+    s1 += w;
+    s2 += w * w;
+  }
+  red[0][t] = s1;
+  red[1][t] = s2;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (t < w) {
+      red[0][t] += red[0][t + w];
+      red[1][t] += red[1][t + w];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    stats[0] = ybar;
+    stats[1] = red[0][0];
+    stats[2] = red[1][0] - red[0][0] * red[0][0] / double(M);
+  }
+}
+
+}  // namespace bgl

@@ -1,0 +1,247 @@
+"""GPU evaluator parity against the CPU oracle (beagle_eval, beagle_predict)."""
+import math
+
+import numpy as np
+import pytest
+
+import gates
+from oracle import fitness as ofit
+from oracle import interp
+from paper_2603_12292_amd import workloads as wl
+from progtext import parse
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _api():
+    from paper_2603_12292_amd import api
+    return api
+
+
+def _dev(ps):
+    return _api().DevicePrograms.from_programset(ps)
+
+
+def _xy(data):
+    return torch.from_numpy(data.X).cuda(), torch.from_numpy(data.y).cuda()
+
+
+def _run(ps, data, kind, **kw):
+    X, y = _xy(data)
+    f, st = _api().evaluate(_dev(ps), X, y, "mse" if kind == ofit.MSE else "corr", with_status=True, **kw)
+    torch.cuda.synchronize()
+    return f.cpu().numpy(), st.cpu().numpy()
+
+
+@pytest.mark.parametrize("kind", [ofit.MSE, ofit.CORR])
+def test_tiny_population_parity(kind):
+    """N=256, L in 3..32, D=3, M=1000 (1% noise): every program."""
+    w = wl.config_tiny()
+    gpu, st = _run(w.programs, w.data, kind)
+    f64, s64, f32, pert = gates.references(w.programs, w.data.X, w.data.y, kind)
+    assert np.array_equal(st, s64)
+    # MSE of programs with exp of large arguments amplifies fp32 rounding
+    # (d exp(x) / exp(x) = x dx), so more of them fall outside the
+    # well-conditioned set than for correlation fitness
+    n, ill = gates.check(gpu, f64, f32, kind, w.data.y, max_ill_frac=0.15, label=f"tiny kind={kind}",
+                         perturbed=pert)
+    print(f"compared {n}, ill-conditioned {ill}")
+    assert n > 150
+
+
+@pytest.mark.parametrize("kind", [ofit.MSE, ofit.CORR])
+def test_ragged_tiles_and_chunks(kind):
+    """M not a multiple of any tile (several chunks, ragged tail), D=5."""
+    ps = wl.random_population(77, 300, 5, 64, 5)
+    data = wl.make_dataset(77, 70_001, 5, x_range=(1.0, 10.0), target_len=20)
+    gpu, _ = _run(ps, data, kind)
+    sub = list(range(0, 300, 5))
+    f64, _, f32, pert = gates.references(ps, data.X, data.y, kind, subset=sub, processes=4)
+    n, _ = gates.check(gpu[sub], f64, f32, kind, data.y, max_ill_frac=0.25, label="ragged", perturbed=pert)
+    assert n > 40
+
+
+def test_mid_workload_sampled():
+    """The benchmark workload (N=4096, L 5..64, D=5, M=100000, correlation
+    fitness) in the benchmark's launch configuration, oracle on a sample."""
+    w = wl.config_mid()
+    gpu, st = _run(w.programs, w.data, ofit.CORR)
+    assert np.all(st == 0)
+    rng = np.random.default_rng(1)
+    sub = sorted(rng.choice(w.programs.n, size=48, replace=False).tolist())
+    f64, _, f32, pert = gates.references(w.programs, w.data.X, w.data.y, ofit.CORR, subset=sub, processes=8)
+    n, ill = gates.check(gpu[sub], f64, f32, ofit.CORR, w.data.y, label="mid sample", perturbed=pert)
+    assert n >= 40
+    # every fitness is a valid correlation fitness or NaN
+    fin = gpu[np.isfinite(gpu)]
+    assert np.all((fin >= 0) & (fin <= 1))
+
+
+def _single(prog, consts, data, kind):
+    ps = wl.pack_programs([(parse(prog) if isinstance(prog, str) else prog, consts)])
+    return _run(ps, data, kind)
+
+
+def test_special_programs():
+    data = wl.make_dataset(5, 1000, 3, x_range=(1.0, 5.0), target_len=10)
+    # constant output: correlation fitness 1, MSE = mean (c - y)^2
+    f, _ = _single("c0", [2.5], data, ofit.CORR)
+    assert f[0] == 1.0
+    f, _ = _single("x0 x0 -", [], data, ofit.CORR)
+    assert f[0] == 1.0
+    f, _ = _single("c0", [2.5], data, ofit.MSE)
+    y = data.y.astype(np.float64)
+    assert f[0] == pytest.approx(float(np.mean((2.5 - y) ** 2)), rel=1e-12)
+    # exact formula: the target program itself
+    t, c = data.target_tokens, data.target_consts
+    f, _ = _single(t, c, data, ofit.MSE)
+    assert f[0] <= 1e-10 * float(np.mean(y * y))
+    f, _ = _single(t, c, data, ofit.CORR)
+    assert f[0] <= 1e-9
+    # affine transform of the target: correlation fitness stays ~0
+    f, _ = _single(list(t) + [10 | (len(c) << 8), 2, 10 | ((len(c) + 1) << 8), 0], list(c) + [-3.0, 7.0],
+                   data, ofit.CORR)
+    assert f[0] <= 1e-9
+    # fp32 overflow: e^80^3 is +Inf in fp32 -> MSE +Inf, correlation NaN; sin of it NaN
+    X = np.full((300, 1), 100.0, dtype=np.float32)
+    d1 = wl.Dataset(X, np.linspace(0, 1, 300).astype(np.float32), [], [])
+    f, _ = _single("x0 exp x0 exp * x0 exp *", [], d1, ofit.MSE)
+    assert f[0] == math.inf
+    f, _ = _single("x0 exp x0 exp * x0 exp *", [], d1, ofit.CORR)
+    assert math.isnan(f[0])
+    f, _ = _single("x0 exp x0 exp * x0 exp * sin", [], d1, ofit.MSE)
+    assert math.isnan(f[0])
+    # protected operators never produce NaN on finite inputs
+    f, _ = _single("x0 x0 - log x0 x0 - / x0 x0 - sqrt +", [], d1, ofit.MSE)
+    assert math.isfinite(f[0])
+
+
+def test_invalid_programs_status_and_nan():
+    data = wl.make_dataset(6, 500, 2, x_range=(1.0, 5.0), target_len=6)
+    progs = [("x0 +", []), ("x0 x1", []), ("x5", []), ("c3", [1.0]), ([11], []), ([], []),
+             ("x0 x1 +", []), ([9] * 4097, [])]
+    ps = wl.pack_programs([(parse(p) if isinstance(p, str) else p, c) for p, c in progs])
+    f, st = _run(ps, data, ofit.MSE)
+    expect = [interp.validate(parse(p) if isinstance(p, str) else p, len(c), 2)[0] for p, c in progs]
+    assert list(st) == expect
+    assert all(math.isnan(f[i]) for i in range(len(progs)) if expect[i] != 0)
+    assert math.isfinite(f[6])
+
+
+def test_deep_and_long_programs():
+    """Register need above 8 (deep kernel) and programs longer than 128 tokens."""
+    data = wl.make_dataset(8, 3000, 4, x_range=(1.0, 5.0), target_len=10)
+    rng = np.random.default_rng(3)
+    progs = []
+    # a balanced tree of 512 leaves has register need 10
+    def balanced(depth):
+        if depth == 0:
+            return [9 | (int(rng.integers(4)) << 8)]
+        return balanced(depth - 1) + balanced(depth - 1) + [int(rng.choice([0, 1, 2]))]
+    progs.append((balanced(9), []))
+    progs.append((balanced(7), []))          # need 8: the fast kernel's limit
+    for L in (65, 127, 128, 129, 300, 1000):
+        progs.append(wl.random_program(rng, L, 4))
+    ps = wl.pack_programs(progs)
+    for kind in (ofit.MSE, ofit.CORR):
+        gpu, st = _run(ps, data, kind)
+        assert np.all(st == 0)
+        f64, _, f32, pert = gates.references(ps, data.X, data.y, kind)
+        gates.check(gpu, f64, f32, kind, data.y, max_ill_frac=1.0, label=f"deep kind={kind}", perturbed=pert)
+
+
+@pytest.mark.parametrize("M,D", [(1, 1), (2, 16), (255, 7), (257, 2), (1025, 9)])
+def test_edge_sizes(M, D):
+    ps = wl.random_population(11, 40, 1, 30, D)
+    if M == 1:
+        X = np.array([[2.5]], dtype=np.float32)
+        data = wl.Dataset(X, np.array([1.25], dtype=np.float32), [], [])
+    else:
+        data = wl.make_dataset(12, M, D, x_range=(1.0, 5.0), target_len=5)
+    kinds = [ofit.MSE] if M < 2 else [ofit.MSE, ofit.CORR]
+    for kind in kinds:
+        if kind == ofit.CORR and np.ptp(data.y) == 0:
+            continue
+        gpu, _ = _run(ps, data, kind)
+        f64, _, f32, pert = gates.references(ps, data.X, data.y, kind)
+        gates.check(gpu, f64, f32, kind, data.y, max_ill_frac=1.0, label=f"M={M} D={D}", perturbed=pert)
+
+
+def test_empty_population():
+    api = _api()
+    ps = api.DevicePrograms.from_arrays([], [], [], [], [], [])
+    X = torch.ones((10, 2), device="cuda")
+    y = torch.ones(10, device="cuda")
+    assert api.evaluate(ps, X, y).numel() == 0
+
+
+def test_predict_against_o32e():
+    """Per-case outputs.  Programs of + - * / only: bit-identical to O32e
+    (IEEE fp32 with correctly rounded division).  Any program: identical
+    NaN pattern, and within 1e-5 of O64 on every case whose value is stable
+    under few-ulp perturbations (O32p, two seeds)."""
+    data = wl.make_dataset(13, 600, 3, x_range=(-3.0, 5.0), target_len=8)
+    ps = wl.random_population(14, 64, 1, 40, 3)
+    rng = np.random.default_rng(5)
+    arith = []
+    for _ in range(32):
+        toks, consts = wl.random_program(rng, int(rng.integers(1, 40)), 3)
+        arith.append(([t if (t & 0xFF) >= 9 or (t & 0xFF) < 4 else 2 for t in toks], consts))
+    ps2 = wl.pack_programs(arith)
+    api = _api()
+    X = torch.from_numpy(data.X).cuda()
+    for pset, exact in ((ps, False), (ps2, True)):
+        out, st = api.predict(_dev(pset), X, with_status=True)
+        out = out.cpu().numpy().astype(np.float64)
+        assert np.all(st.cpu().numpy() == 0)
+        for p in range(pset.n):
+            t, c = pset.program(p)
+            y32 = interp.run(t, c, data.X, "o32e")
+            if exact:
+                assert np.array_equal(out[p].view(np.uint64), y32.view(np.uint64)) or \
+                    np.array_equal(out[p], y32, equal_nan=True), p
+                continue
+            y64 = interp.run(t, c, data.X, "o64")
+            assert np.array_equal(np.isnan(out[p]), np.isnan(y32)), p
+            spread = np.abs(y32 - y64)
+            for s in (1, 2):
+                spread = np.maximum(spread, np.abs(interp.run(t, c, data.X, "o32p", seed=s) - y64))
+            well = np.isfinite(y64) & (spread <= 1e-6 * np.abs(y64))
+            assert np.all(np.abs(out[p][well] - y64[well]) <= 1e-5 * np.abs(y64[well])), p
+
+
+def test_determinism():
+    w = wl.config_tiny()
+    a, _ = _run(w.programs, w.data, ofit.CORR)
+    b, _ = _run(w.programs, w.data, ofit.CORR)
+    assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
+
+
+def test_workspace_cap_gives_identical_results():
+    api = _api()
+    ps = wl.random_population(21, 2000, 5, 40, 3)
+    data = wl.make_dataset(22, 20_000, 3, x_range=(1.0, 5.0), target_len=10)
+    full, _ = _run(ps, data, ofit.CORR)
+    X, y = _xy(data)
+    need = api.eval_workspace_bytes(_dev(ps), X, y, "corr")
+    ctx = api.Context(0, max_workspace_bytes=need - 4096)
+    capped, _ = _run(ps, data, ofit.CORR, ctx=ctx)
+    assert np.array_equal(full.view(np.uint64), capped.view(np.uint64))
+    tiny = api.Context(0, max_workspace_bytes=1000)
+    with pytest.raises(api.BeagleError):
+        _run(ps, data, ofit.CORR, ctx=tiny)
+
+
+def test_argument_errors():
+    api = _api()
+    ps = _dev(wl.random_population(1, 4, 3, 9, 2))
+    X = torch.ones((10, 2), device="cuda")
+    y = torch.ones(10, device="cuda")
+    with pytest.raises(api.BeagleError):
+        api.evaluate(ps, X, y, kind=7)
+    with pytest.raises(api.BeagleError):
+        api.evaluate(ps, torch.ones((10, 17), device="cuda"), y)
+    with pytest.raises(api.BeagleError):
+        api.evaluate(ps, X[:1], y[:1], kind="corr")
