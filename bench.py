@@ -18,7 +18,6 @@ Prints one JSON line:
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -34,15 +33,6 @@ sys.path.insert(0, ROOT)
 # counts a packed two-wide FMA as 4 flops; a stack interpreter issues neither).
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 HBM_PEAK = 8.0e12
-EVAL_SOURCES = ["eval.hip", "beagle_device.h", "kernels.h"]
-
-
-def source_hash():
-    h = hashlib.sha256()
-    for f in EVAL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2603_12292_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
 
 
 def function_nodes(ps) -> int:
@@ -53,7 +43,8 @@ def function_nodes(ps) -> int:
 def traffic_from_profile():
     """HBM bytes per launch of the interpreter kernel from the committed counter
     summary, or None when the kernel source changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", "k_eval_fast_corr_plain_mid_traffic.json")
+    from paper_2603_12292_amd.profiling import source_hash
+    path = os.path.join(ROOT, "profiles", "k_eval_class_corr_plain_mid_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -145,7 +136,7 @@ def main():
                    "programs": ps.n, "fitness_cases": M, "nodes": nodes, "kind": "corr"},
         "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 4), "peak": round(PEAK_LANE_OPS / 1e12, 2),
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_LANE_OPS, 4),
-                     "traffic": traffic, "kernel": "k_eval_fast<corr>",
+                     "traffic": traffic, "kernel": "k_eval_class<corr, need<=4, 8 cases/lane>",
                      "kernel_ms": round(k_avg_s * 1e3, 4), "alg_ops_per_launch": alg_ops,
                      "kernel_gpops": round(nodes * M / k_avg_s / 1e9, 2)},
     }

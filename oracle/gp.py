@@ -28,6 +28,9 @@ binary32).
 Tournament: lowest fitness wins, NaN is worse than everything (+Inf
 included), ties go to the lowest population index.
 
+A parent that is empty or longer than max_len yields an empty child (the
+operators are meant for valid parents; this keeps the result defined).
+
 Subtree crossover: the subtree of postfix token i is the contiguous run
 [s, i] whose net stack effect is one value (found by scanning back from i).
 Child = A[:sA] + B[sB:iB+1] + A[iA+1:]; a child longer than max_len is
@@ -112,12 +115,11 @@ def operator_thresholds(params: GenParams):
 def subtree_start(tokens: Sequence[int], i: int) -> int:
     """Start of the subtree whose root is postfix token i."""
     need = 1
-    j = i
-    while True:
+    for j in range(i, -1, -1):
         need += arity(int(tokens[j]) & 0xFF) - 1
         if need == 0:
             return j
-        j -= 1
+    return 0  # malformed parent
 
 
 def tournament(fitness: np.ndarray, entrants: Sequence[int]) -> int:
@@ -151,7 +153,8 @@ def _with_values(tokens, consts):
     for t in tokens:
         t = int(t)
         if (t & 0xFF) == CONST:
-            out.append((t, float(consts[t >> 8])))
+            slot = t >> 8
+            out.append((t, float(consts[slot]) if slot < len(consts) else 0.0))
         else:
             out.append((t, 0.0))
     return out
@@ -169,13 +172,17 @@ def make_child(c: int, parents_tok, parents_const, fitness: np.ndarray, D: int,
     A, Ac = parents_tok[ia], parents_const[ia]
     B, Bc = parents_tok[ib], parents_const[ib]
     LA, LB = len(A), len(B)
-    xa = below(s.draw(2 * t + 1), LA)
-    xb = below(s.draw(2 * t + 2), LB)
-    mpos = below(s.draw(2 * t + 3), LA)
+    okA = 0 < LA <= params.max_len
+    okB = 0 < LB <= params.max_len
+    xa = below(s.draw(2 * t + 1), LA if okA else 0)
+    xb = below(s.draw(2 * t + 2), LB if okB else 0)
+    mpos = below(s.draw(2 * t + 3), LA if okA else 0)
     msym_u = s.draw(2 * t + 4)
     mconst_u = s.draw(2 * t + 5)
     pa = _with_values(A, Ac)
     t_cross, t_mut = operator_thresholds(params)
+    if not okA or (choice < t_cross and not okB):
+        return [], []
     if choice < t_cross:
         sa = subtree_start(A, xa)
         sb = subtree_start(B, xb)

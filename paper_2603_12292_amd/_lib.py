@@ -11,7 +11,9 @@ from ctypes import POINTER, c_char_p, c_double, c_float, c_int, c_int8, c_int32,
     c_uint64, c_void_p
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libbeagle.so")
+# BEAGLE_LIBRARY selects another build of the same library (e.g. a variant
+# with different tile parameters)
+LIB_PATH = os.environ.get("BEAGLE_LIBRARY") or os.path.join(HERE, "libbeagle.so")
 
 # return codes
 OK = 0

@@ -205,3 +205,79 @@ def predict(progs: DevicePrograms, X: torch.Tensor, *, with_status: bool = False
     _check(c.lib.beagle_predict(c.handle, ctypes.byref(ps), ctypes.byref(ds), out.data_ptr(),
                                 st.data_ptr() if st is not None else None, _stream(dev)))
     return (out, st) if with_status else out
+
+
+@dataclasses.dataclass
+class GenParams:
+    """beagle_gen_params: selection and variation settings."""
+
+    tournament: int = 4
+    p_crossover: float = 0.9
+    p_mutation: float = 0.1
+    max_len: int = 128
+    max_consts: int = 8
+    const_lo: float = -5.0
+    const_hi: float = 5.0
+    init_depth_min: int = 2
+    init_depth_max: int = 6
+
+    def struct(self) -> _lib.GenParams:
+        return _lib.GenParams(self.tournament, self.p_crossover, self.p_mutation, self.max_len, self.max_consts,
+                              self.const_lo, self.const_hi, self.init_depth_min, self.init_depth_max)
+
+
+@dataclasses.dataclass
+class Slots:
+    """A population in fixed-capacity slots (what initialisation and the
+    generation step write): tokens [N, max_len] (uint16 bits in int16),
+    len [N], consts [N, max_consts], const_count [N]."""
+
+    tokens: torch.Tensor
+    len: torch.Tensor
+    consts: torch.Tensor
+    const_count: torch.Tensor
+
+    @staticmethod
+    def empty(n: int, max_len: int, max_consts: int, device="cuda") -> "Slots":
+        return Slots(torch.empty((n, max_len), dtype=torch.int16, device=device),
+                     torch.empty(n, dtype=torch.int32, device=device),
+                     torch.empty((n, max(max_consts, 1)), dtype=torch.float32, device=device)[:, :max_consts],
+                     torch.empty(n, dtype=torch.int32, device=device))
+
+    @property
+    def n(self) -> int:
+        return int(self.len.shape[0])
+
+    def programs(self) -> DevicePrograms:
+        return DevicePrograms.from_fixed(self.tokens, self.len, self.consts.contiguous(), self.const_count)
+
+
+def init_population(n: int, D: int, params: GenParams, seed: int, problem: int = 0, device="cuda",
+                    ctx: Optional[Context] = None) -> Slots:
+    """Ramped half-and-half population -- beagle_init_population."""
+    dev = torch.device(device)
+    c = _ctx_for(dev, ctx)
+    out = Slots.empty(n, params.max_len, params.max_consts, dev)
+    p = params.struct()
+    _check(c.lib.beagle_init_population(c.handle, ctypes.byref(p), n, D, seed, problem, out.tokens.data_ptr(),
+                                        out.len.data_ptr(), out.consts.data_ptr(), out.const_count.data_ptr(),
+                                        _stream(dev)))
+    return out
+
+
+def generation(parents: DevicePrograms, fitness: torch.Tensor, params: GenParams, D: int, seed: int,
+               generation_index: int, problem: int = 0, out: Optional[Slots] = None,
+               ctx: Optional[Context] = None) -> Slots:
+    """One selection + variation step -- beagle_generation."""
+    dev = parents.device
+    c = _ctx_for(dev, ctx)
+    if fitness.dtype != torch.float64 or fitness.device != dev or fitness.numel() != parents.n:
+        raise ValueError("fitness must be float64 [N] on the parents' device")
+    if out is None:
+        out = Slots.empty(parents.n, params.max_len, params.max_consts, dev)
+    ps = parents.struct()
+    p = params.struct()
+    _check(c.lib.beagle_generation(c.handle, ctypes.byref(ps), fitness.data_ptr(), ctypes.byref(p), D, seed,
+                                   generation_index, problem, out.tokens.data_ptr(), out.len.data_ptr(),
+                                   out.consts.data_ptr(), out.const_count.data_ptr(), _stream(dev)))
+    return out

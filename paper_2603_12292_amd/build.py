@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbeagle.so")
-SOURCES = ["api.cpp", "prepare.hip", "eval.hip"]
+SOURCES = ["api.cpp", "prepare.hip", "eval.hip", "gen.hip"]
 ARCH = "gfx950"
 
 FLAGS = [
@@ -23,6 +23,9 @@ FLAGS = [
     # no packed-FP32 instructions in any kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-ffp-contract=fast",
+    # the interpreter's dispatch branches on a wave-uniform value: leave such
+    # regions unstructurized (fewer scalar flag operations per token)
+    "-mllvm", "-structurizecfg-skip-uniform-regions",
 ]
 
 
@@ -33,28 +36,33 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc()] + FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(src: str, build_dir: str = BUILD, defines=(), extra=()) -> str:
+    obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
+    cmd = [hipcc()] + FLAGS + list(extra) + [f"-D{d}" for d in defines] + \
+        ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose: bool = False, out: str = LIB, defines=(), extra=()) -> str:
+    """Compile and link; ``out`` and ``defines`` (NAME=VALUE) select a
+    variant build (tile parameters) placed elsewhere."""
+    build_dir = BUILD if out == LIB else os.path.splitext(out)[0] + "_build"
+    os.makedirs(build_dir, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda s: _compile(s, build_dir, defines, extra), SOURCES))
+    LIBOUT = out
+    tmp = LIBOUT + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, LIBOUT)
     if verbose:
-        print(f"built {LIB}")
-    return LIB
+        print(f"built {LIBOUT}")
+    return LIBOUT
 
 
 if __name__ == "__main__":

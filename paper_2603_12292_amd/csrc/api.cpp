@@ -11,6 +11,7 @@
 
 #include "../../include/beagle.h"
 #include "beagle_device.h"
+#include "gen.h"
 #include "kernels.h"
 
 struct beagle_ctx {
@@ -124,7 +125,7 @@ void choose_chunks(int64_t M, int64_t N, int64_t* chunk, int32_t* n_chunks) {
 
 // The pieces of workspace one evaluation uses.
 struct EvalLayout {
-  size_t code, cval, s_stack, s_start, s_need, meta, deep_count, deep_list, Xt, yp, stats, part, total;
+  size_t code, cval, s_stack, s_start, s_need, meta, class_count, class_list, work, Xt, yp, stats, part, total;
   int64_t Mp, chunk;
   int32_t n_chunks, slice;
 };
@@ -140,8 +141,9 @@ EvalLayout eval_layout(const beagle_programs* P, const beagle_dataset* d, int n_
   L.s_start = c.take<int32_t>(nt);
   L.s_need = c.take<int32_t>(nt);
   L.meta = c.take<bgl::ProgMeta>(N);
-  L.deep_count = c.take<int32_t>(64);
-  L.deep_list = c.take<int32_t>(N);
+  L.class_count = c.take<int32_t>(64);
+  L.class_list = c.take<int32_t>(size_t(bgl::N_CLASSES) * N);
+  L.work = c.take<unsigned long long>(bgl::N_CLASSES);
   L.Mp = round_up(d->M, bgl::CASES_PER_WAVE_ITER);
   L.Xt = c.take<float>(size_t(d->D) * L.Mp);
   L.yp = c.take<float>(L.Mp);
@@ -165,7 +167,7 @@ __global__ void k_zero_i32(int32_t* p, int n) {
 beagle_status prepare(beagle_ctx* ctx, const beagle_programs* P, const beagle_dataset* d, const EvalLayout& L,
                       int8_t* status, hipStream_t s) {
   char* ws = ctx->ws;
-  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, reinterpret_cast<int32_t*>(ws + L.deep_count), 64);
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, reinterpret_cast<int32_t*>(ws + L.class_count), 64);
   bgl::PrepareArgs pa;
   pa.tokens = P->tokens;
   pa.n_tokens = P->n_tokens;
@@ -184,8 +186,8 @@ beagle_status prepare(beagle_ctx* ctx, const beagle_programs* P, const beagle_da
   pa.scr_need = reinterpret_cast<int32_t*>(ws + L.s_need);
   pa.meta = reinterpret_cast<bgl::ProgMeta*>(ws + L.meta);
   pa.status_out = status;
-  pa.deep_count = reinterpret_cast<int32_t*>(ws + L.deep_count);
-  pa.deep_list = reinterpret_cast<int32_t*>(ws + L.deep_list);
+  pa.class_count = reinterpret_cast<int32_t*>(ws + L.class_count);
+  pa.class_list = reinterpret_cast<int32_t*>(ws + L.class_list);
   hipLaunchKernelGGL(bgl::k_prepare, dim3((P->n_programs + 63) / 64), dim3(64), 0, s, pa);
   bgl::StageArgs sa;
   sa.X = d->X;
@@ -346,8 +348,10 @@ beagle_status beagle_eval(beagle_ctx* ctx, const beagle_programs* progs, const b
     ea.chunk = L.chunk;
     ea.part = reinterpret_cast<double*>(ws + L.part);
     ea.stats = reinterpret_cast<const double*>(ws + L.stats);
-    ea.deep_count = reinterpret_cast<const int32_t*>(ws + L.deep_count);
-    ea.deep_list = reinterpret_cast<const int32_t*>(ws + L.deep_list);
+    ea.class_count = reinterpret_cast<const int32_t*>(ws + L.class_count);
+    ea.class_list = reinterpret_cast<const int32_t*>(ws + L.class_list);
+    ea.work = reinterpret_cast<unsigned long long*>(ws + L.work);
+    ea.n_total = progs->n_programs;
     ea.prog_begin = p0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (ctx->timing) {
@@ -407,6 +411,113 @@ beagle_status beagle_predict(beagle_ctx* ctx, const beagle_programs* progs, cons
   if (st != BEAGLE_OK) return st;
   st = launch_values(ctx, progs, data, L, data->M, yhat, 0, s);
   if (st != BEAGLE_OK) return st;
+  g_error.clear();
+  return BEAGLE_OK;
+}
+
+static beagle_status check_gen_params(const beagle_gen_params* p, int32_t D) {
+  if (!p) return fail(BEAGLE_E_INVALID_ARG, "params is NULL");
+  if (D < 1 || D > BEAGLE_MAX_D) return fail(BEAGLE_E_UNSUPPORTED, "D must be in [1, 16]");
+  if (p->tournament < 1 || p->tournament > 64) return fail(BEAGLE_E_INVALID_ARG, "tournament must be in [1, 64]");
+  if (!(p->p_crossover >= 0.0f && p->p_mutation >= 0.0f && p->p_crossover + p->p_mutation <= 1.0f + 1e-6f))
+    return fail(BEAGLE_E_INVALID_ARG, "operator probabilities must be >= 0 and sum to <= 1");
+  if (p->max_len < 1 || p->max_len > BEAGLE_MAX_LEN) return fail(BEAGLE_E_UNSUPPORTED, "max_len must be in [1, 4096]");
+  if (p->max_consts < 0 || p->max_consts > 255) return fail(BEAGLE_E_UNSUPPORTED, "max_consts must be in [0, 255]");
+  if (!(p->const_lo <= p->const_hi)) return fail(BEAGLE_E_INVALID_ARG, "const_lo > const_hi");
+  return BEAGLE_OK;
+}
+
+beagle_status beagle_init_population(beagle_ctx* ctx, const beagle_gen_params* params, int32_t n, int32_t D,
+                                     uint64_t seed, uint32_t problem, uint16_t* tokens, int32_t* len,
+                                     float* consts, int32_t* const_count, beagle_stream stream) {
+  if (!ctx) return fail(BEAGLE_E_INVALID_ARG, "ctx is NULL");
+  beagle_status st = check_gen_params(params, D);
+  if (st != BEAGLE_OK) return st;
+  if (n < 0) return fail(BEAGLE_E_INVALID_ARG, "n < 0");
+  if (params->init_depth_min < 0 || params->init_depth_max < params->init_depth_min ||
+      params->init_depth_max > bgl::MAX_INIT_DEPTH)
+    return fail(BEAGLE_E_INVALID_ARG, "init depths must satisfy 0 <= min <= max <= 11");
+  if ((int64_t(1) << (params->init_depth_max + 1)) - 1 > params->max_len)
+    return fail(BEAGLE_E_INVALID_ARG, "2^(init_depth_max+1) - 1 exceeds max_len");
+  if (problem & 0x80000000u) return fail(BEAGLE_E_INVALID_ARG, "problem id must be < 2^31");
+  if (n == 0) return BEAGLE_OK;
+  if (!tokens || !len || !const_count || (params->max_consts > 0 && !consts))
+    return fail(BEAGLE_E_INVALID_ARG, "an output pointer is NULL");
+  DeviceGuard g(ctx->device);
+  if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+  bgl::InitArgs a;
+  a.n = n;
+  a.D = D;
+  a.depth_min = params->init_depth_min;
+  a.depth_max = params->init_depth_max;
+  a.max_len = params->max_len;
+  a.max_consts = params->max_consts;
+  a.const_lo = params->const_lo;
+  a.const_hi = params->const_hi;
+  a.seed = seed;
+  a.tag = 0x80000000u | problem;
+  a.tokens = tokens;
+  a.len = len;
+  a.consts = consts;
+  a.const_count = const_count;
+  hipLaunchKernelGGL(bgl::k_init_population, dim3((n + 63) / 64), dim3(64), 0,
+                     reinterpret_cast<hipStream_t>(stream), a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "init launch");
+  g_error.clear();
+  return BEAGLE_OK;
+}
+
+beagle_status beagle_generation(beagle_ctx* ctx, const beagle_programs* parents, const double* fitness,
+                                const beagle_gen_params* params, int32_t D, uint64_t seed, uint64_t generation,
+                                uint32_t problem, uint16_t* child_tokens, int32_t* child_len,
+                                float* child_consts, int32_t* child_const_count, beagle_stream stream) {
+  if (!ctx) return fail(BEAGLE_E_INVALID_ARG, "ctx is NULL");
+  beagle_status st = check_programs(parents);
+  if (st != BEAGLE_OK) return st;
+  st = check_gen_params(params, D);
+  if (st != BEAGLE_OK) return st;
+  if (problem & 0x80000000u) return fail(BEAGLE_E_INVALID_ARG, "problem id must be < 2^31");
+  const int32_t n = parents->n_programs;
+  if (n == 0) return BEAGLE_OK;
+  if (!fitness) return fail(BEAGLE_E_INVALID_ARG, "fitness is NULL");
+  if (!child_tokens || !child_len || !child_const_count || (params->max_consts > 0 && !child_consts))
+    return fail(BEAGLE_E_INVALID_ARG, "an output pointer is NULL");
+  DeviceGuard g(ctx->device);
+  if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+  bgl::GenStepArgs a;
+  a.tokens = parents->tokens;
+  a.n_tokens = parents->n_tokens;
+  a.tok_offset = parents->tok_offset;
+  a.tok_len = parents->tok_len;
+  a.consts = parents->consts;
+  a.n_consts = parents->n_consts;
+  a.const_offset = parents->const_offset;
+  a.const_count = parents->const_count;
+  a.fitness = fitness;
+  a.n = n;
+  a.D = D;
+  a.tournament = params->tournament;
+  // operator thresholds in binary32: p_crossover and p_crossover + p_mutation
+  const float pc = params->p_crossover;
+  volatile float sum = pc + params->p_mutation;
+  a.t_cross = pc;
+  a.t_mut = sum;
+  a.max_len = params->max_len;
+  a.max_consts = params->max_consts;
+  a.const_lo = params->const_lo;
+  a.const_hi = params->const_hi;
+  a.seed = seed;
+  a.generation = uint32_t(generation);
+  a.tag = problem;
+  a.child_tokens = child_tokens;
+  a.child_len = child_len;
+  a.child_consts = child_consts;
+  a.child_const_count = child_const_count;
+  hipLaunchKernelGGL(bgl::k_generation, dim3((n + 63) / 64), dim3(64), 0, reinterpret_cast<hipStream_t>(stream),
+                     a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "generation launch");
   g_error.clear();
   return BEAGLE_OK;
 }

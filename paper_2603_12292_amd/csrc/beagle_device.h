@@ -9,20 +9,36 @@
 // reversed operator, so values are unchanged), and writes one 32-bit
 // instruction word per token:
 //
-//     word = handler | (arg << 8)
+//     word = handler | (arg << 8) | (wslot << 16)
 //
-// where the handler fixes the operation AND the stack size n (number of
-// values on the stack before the token) at which it runs, so every operand
-// lives in a register named at compile time:
+// arg is the variable index of VAR and fused-VAR words and 0 in every other
+// word, so it always addresses a valid row of the input tile (the
+// interpreter reads the next word's row one token ahead).
 //
-//     [0, 16)            VAR push with n = 0..15 values already on the stack
-//     [16, 32)           CONST push with n = 0..15 (value in the side table)
-//     32 + 15*o + (n-2)  binary operator o at n = 2..16 values, o in
-//                        ADD, SUB, MUL, DIV, RSUB (b - a), RDIV (b / a)
-//     122 + u            unary operator u in SIN, COS, EXP, LOG, SQRT
+// The interpreter keeps the value on top of the stack in `top` and the n-1
+// values below it in stk[0..n-2] (n = stack size before the token).  Every
+// token first stores `top` into stk[wslot] with wslot = max(n-1, 0): for a
+// push that is the push itself, for any other token it writes a dead slot.
+// That store is unconditional, so the stack array has one definition per
+// token and the compiler keeps it in place (an indexed register write)
+// instead of copying it at the join after the dispatch.  Handlers:
 //
-// The value on top of the stack is kept in `top`; the n-1 values below it
-// in stk[0..n-2].
+//     0                  VAR push (arg = variable)
+//     1                  CONST push (value in the side table)
+//     2 + 15*o + (n-2)   binary operator o at n = 2..16 values, o in
+//                        ADD, SUB, MUL, DIV, RSUB (b - a), RDIV (b / a);
+//                        its left operand is stk[n-2], a register named at
+//                        compile time
+//     92 + u             unary operator u in SIN, COS, EXP, LOG, SQRT
+//     97 + 6*s + o       fused "push a terminal, then binary operator o"
+//                        (s = 0 VAR, 1 CONST): top = top op value; the
+//                        stack below top is untouched, so the pair costs one
+//                        dispatch and no stack traffic
+//
+// Fused pairs make the decoded program shorter than the token program;
+// ProgMeta::len counts decoded words.  Programs are grouped by register
+// need into classes of 4, 8 and 16 stack slots, each run by a kernel
+// instantiated for that stack size.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -47,12 +63,15 @@ enum Opcode : uint32_t {
 
 enum BinIdx : uint32_t { B_ADD = 0, B_SUB = 1, B_MUL = 2, B_DIV = 3, B_RSUB = 4, B_RDIV = 5 };
 
-constexpr int MAX_STACK = 16;       // largest register need any kernel supports
-constexpr int FAST_STACK = 8;       // register need handled by the fast kernels
+constexpr int MAX_STACK = 16;  // largest register need any kernel supports
+constexpr int N_CLASSES = 3;   // register-need classes: <= 4, <= 8, <= 16
+__host__ __device__ constexpr int class_stack(int c) { return c == 0 ? 4 : (c == 1 ? 8 : 16); }
+__host__ __device__ constexpr int need_class(int need) { return need <= 4 ? 0 : (need <= 8 ? 1 : 2); }
 constexpr uint32_t H_VAR = 0;
-constexpr uint32_t H_CONST = 16;
-constexpr uint32_t H_BIN = 32;
-constexpr uint32_t H_UN = 32 + 15 * 6;  // 122
+constexpr uint32_t H_CONST = 1;
+constexpr uint32_t H_BIN = 2;
+constexpr uint32_t H_UN = 2 + 15 * 6;  // 92
+constexpr uint32_t H_FUSED = H_UN + 5;  // 97
 constexpr int MAX_LEN = 4096;
 constexpr int MAX_D = 16;
 
@@ -74,7 +93,7 @@ __device__ __forceinline__ float op_sqrt(float x) { return sqrtf(fabsf(x)); }
 struct ProgMeta {
   int32_t status;  // BEAGLE_PROG_* code
   int32_t need;    // register need of the expression tree (max stack size)
-  int32_t len;     // tokens
+  int32_t len;     // decoded instruction words (fused pairs count once)
   float shift;     // correlation fitness: the program's output at case 0
 };
 

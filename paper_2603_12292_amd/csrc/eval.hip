@@ -31,27 +31,66 @@ __device__ __forceinline__ float binop(float a, float b) {
   return 0.0f;
 }
 
-// K consecutive floats read as one LDS access.
+// The wave's input tile in LDS: variable d of case k (k-th of this lane's K
+// cases) lives at  ((d * G + k / 4) * 64 + lane) * 4 + k % 4  floats, G =
+// ceil(K / 4): every 16-byte access of a wave is contiguous across lanes
+// (no bank conflicts).  xl points at lane * 4 floats of the tile.
 template <int K>
-struct alignas(4 * K) Vec {
+struct XRow {
   float v[K];
 };
+
+template <int K>
+__device__ __forceinline__ XRow<K> load_row(const float* xl, uint32_t d) {
+  constexpr int G = (K + 3) / 4;
+  XRow<K> r;
+  if constexpr (K >= 4) {
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const float4 q = *reinterpret_cast<const float4*>(xl + (d * G + g) * 256);
+      r.v[4 * g + 0] = q.x;
+      r.v[4 * g + 1] = q.y;
+      r.v[4 * g + 2] = q.z;
+      r.v[4 * g + 3] = q.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < K; ++k) r.v[k] = xl[d * 256 + k];
+  }
+  return r;
+}
+
+template <int K>
+__device__ __forceinline__ void store_row(float* xl, uint32_t d, const XRow<K>& r) {
+  constexpr int G = (K + 3) / 4;
+  if constexpr (K >= 4) {
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      *reinterpret_cast<float4*>(xl + (d * G + g) * 256) =
+          make_float4(r.v[4 * g + 0], r.v[4 * g + 1], r.v[4 * g + 2], r.v[4 * g + 3]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < K; ++k) xl[d * 256 + k] = r.v[k];
+  }
+}
 
 // The stack interpreter for one program on K cases per lane.
 //   vc0/vv0, vc1/vv1: instruction words / constant values of tokens 0..63
 //   and 64..127 (one per lane); longer programs read later tokens from
-//   memory.  xl points at this lane's inputs in the wave's LDS tile:
-//   variable d of case k is xl[d * 64 * K + k].
+//   memory.  xl points at this lane's inputs in the wave's LDS tile (see
+//   load_row).
 template <int K, int S>
 __device__ __forceinline__ void interpret(uint32_t vc0, float vv0, uint32_t vc1, float vv1,
                                           const uint32_t* __restrict__ code, const float* __restrict__ cval,
                                           int L, int lane, const float* xl, float (&top)[K]) {
-  float stk[K][S - 1];
+  // S slots: the unconditional store of a token at stack size n = S lands in
+  // slot S-1, above the S-1 live values
+  float stk[K][S];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     top[k] = 0.0f;
 #pragma unroll
-    for (int j = 0; j < S - 1; ++j) stk[k][j] = 0.0f;
+    for (int j = 0; j < S; ++j) stk[k][j] = 0.0f;
   }
   for (int base = 0; base < L; base += 64) {
     uint32_t vc;
@@ -67,31 +106,26 @@ __device__ __forceinline__ void interpret(uint32_t vc0, float vv0, uint32_t vc1,
       vc = i < L ? code[i] : 0u;
       vv = i < L ? cval[i] : 0.0f;
     }
-    const int n = L - base < 64 ? L - base : 64;
+    const int n = __builtin_amdgcn_readfirstlane(L - base < 64 ? L - base : 64);
     for (int t = 0; t < n; ++t) {
       const uint32_t w = __builtin_amdgcn_readlane(vc, t);
-      const uint32_t arg = w >> 8;
+      const uint32_t arg = (w >> 8) & 0xFFu;
+      const uint32_t ws = w >> 16;
+#pragma unroll
+      for (int k = 0; k < K; ++k) stk[k][ws] = top[k];
       switch (w & 0xFFu) {
-#define BGL_PUSH_VAR(N)                                                        \
-  case H_VAR + N:                                                              \
-    if constexpr (N < S) {                                                     \
-      if constexpr (N > 0) {                                                   \
-        _Pragma("unroll") for (int k = 0; k < K; ++k) stk[k][N > 0 ? N - 1 : 0] = top[k]; \
-      }                                                                        \
-      const Vec<K> xv = *reinterpret_cast<const Vec<K>*>(xl + arg * (64 * K)); \
-      _Pragma("unroll") for (int k = 0; k < K; ++k) top[k] = xv.v[k];          \
-    }                                                                          \
-    break;
-#define BGL_PUSH_CONST(N)                                                      \
-  case H_CONST + N:                                                            \
-    if constexpr (N < S) {                                                     \
-      if constexpr (N > 0) {                                                   \
-        _Pragma("unroll") for (int k = 0; k < K; ++k) stk[k][N > 0 ? N - 1 : 0] = top[k]; \
-      }                                                                        \
-      const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vv), t)); \
-      _Pragma("unroll") for (int k = 0; k < K; ++k) top[k] = v;                \
-    }                                                                          \
-    break;
+        case H_VAR: {
+          const XRow<K> xv = load_row<K>(xl, arg);
+#pragma unroll
+          for (int k = 0; k < K; ++k) top[k] = xv.v[k];
+          break;
+        }
+        case H_CONST: {
+          const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vv), t));
+#pragma unroll
+          for (int k = 0; k < K; ++k) top[k] = v;
+          break;
+        }
 #define BGL_BIN(O, N)                                                          \
   case H_BIN + 15 * O + (N - 2):                                               \
     if constexpr (N <= S) {                                                    \
@@ -103,21 +137,32 @@ __device__ __forceinline__ void interpret(uint32_t vc0, float vv0, uint32_t vc1,
   BGL_BIN(O, 2) BGL_BIN(O, 3) BGL_BIN(O, 4) BGL_BIN(O, 5) BGL_BIN(O, 6) BGL_BIN(O, 7) \
   BGL_BIN(O, 8) BGL_BIN(O, 9) BGL_BIN(O, 10) BGL_BIN(O, 11) BGL_BIN(O, 12)     \
   BGL_BIN(O, 13) BGL_BIN(O, 14) BGL_BIN(O, 15) BGL_BIN(O, 16)
-#define BGL_PUSH_ALL(M)                                                         \
-  M(0) M(1) M(2) M(3) M(4) M(5) M(6) M(7) M(8) M(9) M(10) M(11) M(12) M(13) M(14) M(15)
-        BGL_PUSH_ALL(BGL_PUSH_VAR)
-        BGL_PUSH_ALL(BGL_PUSH_CONST)
         BGL_BIN_ALL(B_ADD)
         BGL_BIN_ALL(B_SUB)
         BGL_BIN_ALL(B_MUL)
         BGL_BIN_ALL(B_DIV)
         BGL_BIN_ALL(B_RSUB)
         BGL_BIN_ALL(B_RDIV)
-#undef BGL_PUSH_VAR
-#undef BGL_PUSH_CONST
 #undef BGL_BIN
 #undef BGL_BIN_ALL
-#undef BGL_PUSH_ALL
+#define BGL_FUSED(O)                                                           \
+  case H_FUSED + O: {                                                          \
+    const XRow<K> xv = load_row<K>(xl, arg);                                   \
+    _Pragma("unroll") for (int k = 0; k < K; ++k) top[k] = binop<O>(top[k], xv.v[k]); \
+    break;                                                                     \
+  }                                                                            \
+  case H_FUSED + 6 + O: {                                                      \
+    const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vv), t)); \
+    _Pragma("unroll") for (int k = 0; k < K; ++k) top[k] = binop<O>(top[k], v); \
+    break;                                                                     \
+  }
+        BGL_FUSED(B_ADD)
+        BGL_FUSED(B_SUB)
+        BGL_FUSED(B_MUL)
+        BGL_FUSED(B_DIV)
+        BGL_FUSED(B_RSUB)
+        BGL_FUSED(B_RDIV)
+#undef BGL_FUSED
         case H_UN + 0:
 #pragma unroll
           for (int k = 0; k < K; ++k) top[k] = sinf(top[k]);
@@ -172,9 +217,10 @@ __device__ __forceinline__ void eval_block(const EvalArgs& a, int p, int c, doub
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
   const int64_t c0 = int64_t(c) * a.chunk;
   const int64_t c1 = c0 + a.chunk < a.M ? c0 + a.chunk : a.M;
-  // this wave's input tile: [d][lane][k], K consecutive cases per lane
-  float* xw = xtile + wave * (a.D * 64 * K);
-  float* xl = xw + lane * K;
+  // this wave's input tile (layout: load_row); G * 256 floats per variable
+  constexpr int G = (K + 3) / 4;
+  float* xw = xtile + wave * (a.D * G * 256);
+  float* xl = xw + lane * 4;
   for (int64_t base = c0 + int64_t(wave) * (64 * K); base < c1; base += int64_t(EVAL_WAVES) * 64 * K) {
     float yk[K];
 #pragma unroll
@@ -182,11 +228,11 @@ __device__ __forceinline__ void eval_block(const EvalArgs& a, int p, int c, doub
     // coalesced global reads (case = base + k*64 + lane), one LDS write per
     // variable; the wave's tile is private to it, so a wave barrier suffices
     for (int d = 0; d < a.D; ++d) {
-      Vec<K> xv;
+      XRow<K> xv;
 #pragma unroll
       for (int k = 0; k < K; ++k) xv.v[k] = a.Xt[int64_t(d) * a.Mp + base + k * 64 + lane];
       __builtin_amdgcn_wave_barrier();
-      *reinterpret_cast<Vec<K>*>(xl + d * (64 * K)) = xv;
+      store_row<K>(xl, d, xv);
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the tile is in LDS
@@ -227,30 +273,30 @@ __device__ __forceinline__ void eval_block(const EvalArgs& a, int p, int c, doub
   __syncthreads();
 }
 
-template <int KIND>
-__global__ void __launch_bounds__(256) k_eval_fast(EvalArgs a) {
+// One register-need class: a persistent grid pulls (chunk, program) work
+// items from an atomic counter, chunk-major so that the workgroups running
+// at any moment share one chunk of cases in L2.  Which workgroup takes which
+// item does not change any result: each item writes its own partial.
+template <int KIND, int CLS, int KV>
+__global__ void __launch_bounds__(256) k_eval_class(EvalArgs a) {
+  constexpr int S = class_stack(CLS);
+  constexpr int K = class_k(CLS, KV);
   __shared__ double red[12];
+  __shared__ long long s_item;
   extern __shared__ float xtile[];
-  const int p = int(blockIdx.x % uint32_t(a.n_programs));
-  const int c = int(blockIdx.x / uint32_t(a.n_programs));
-  const ProgMeta m = a.meta[p];
-  if (m.status != BEAGLE_PROG_OK || m.need > FAST_STACK) return;
-  eval_block<KIND, EVAL_K, FAST_STACK>(a, p, c, red, xtile);
-}
-
-// Programs whose register need exceeds FAST_STACK (long, bushy trees): a
-// grid-stride loop over (program, chunk) pairs of the list built by the
-// preparation kernel; an empty list makes every workgroup exit at once.
-template <int KIND>
-__global__ void __launch_bounds__(256) k_eval_deep(EvalArgs a) {
-  __shared__ double red[12];
-  extern __shared__ float xtile[];
-  const int64_t items = int64_t(*a.deep_count) * a.n_chunks;
-  for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
-    const int p = a.deep_list[it / a.n_chunks] - a.prog_begin;
-    const int c = int(it % a.n_chunks);
-    if (p < 0 || p >= a.n_programs) continue;  // another slice's program (uniform)
-    eval_block<KIND, DEEP_K, MAX_STACK>(a, p, c, red, xtile);
+  const int32_t count = a.class_count[CLS];
+  const int64_t items = int64_t(count) * a.n_chunks;
+  const int32_t* list = a.class_list + int64_t(CLS) * a.n_total;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (long long)atomicAdd(a.work + CLS, 1ull);
+    __syncthreads();
+    const int64_t it = s_item;
+    __syncthreads();
+    if (it >= items) break;  // uniform across the workgroup
+    const int c = int(it / count);
+    const int p = list[it % count] - a.prog_begin;
+    if (p < 0 || p >= a.n_programs) continue;  // a program of another slice
+    eval_block<KIND, K, S>(a, p, c, red, xtile);
   }
 }
 
@@ -258,7 +304,7 @@ __global__ void __launch_bounds__(256) k_eval_deep(EvalArgs a) {
 // (program, 64 cases).  In shift mode (m = 1) it stores the output at case
 // 0 as the program's shift for correlation sums.
 __global__ void __launch_bounds__(64) k_values(ValuesArgs a) {
-  __shared__ float xl_all[MAX_D * 64];
+  __shared__ float xl_all[MAX_D * 256];
   const int p = blockIdx.x;
   const int lane = threadIdx.x;
   const int64_t i = int64_t(blockIdx.y) * 64 + lane;
@@ -276,8 +322,8 @@ __global__ void __launch_bounds__(64) k_values(ValuesArgs a) {
   const uint32_t vc1 = lane + 64 < L ? code[lane + 64] : 0u;
   const float vv1 = lane + 64 < L ? cval[lane + 64] : 0.0f;
   const int64_t ii = i < a.m ? i : 0;
-  float* xl = xl_all + lane;
-  for (int d = 0; d < a.D; ++d) xl[d * 64] = a.Xt[int64_t(d) * a.Mp + ii];
+  float* xl = xl_all + lane * 4;
+  for (int d = 0; d < a.D; ++d) xl[d * 256] = a.Xt[int64_t(d) * a.Mp + ii];
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_s_waitcnt(0xc07f);
   float top[1];
@@ -327,18 +373,57 @@ __global__ void k_finalize(FinalizeArgs a) {
   a.fitness[p] = F;
 }
 
+__global__ void k_zero_u64(unsigned long long* p, int n) {
+  const int i = threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+// resident workgroups per CU of a class kernel at a given LDS size
+template <int KIND, int CLS, int KV>
+static int resident_blocks(size_t lds) {
+  static size_t cached_lds = size_t(-1);
+  static int cached = 0;
+  if (lds != cached_lds) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_class<KIND, CLS, KV>, 256, lds) != hipSuccess ||
+        nb < 1)
+      nb = 1;
+    cached = nb;
+    cached_lds = lds;
+  }
+  return cached;
+}
+
+static int cu_count() {
+  static int n = 0;
+  if (!n) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) n = 1;
+  }
+  return n;
+}
+
+template <int KIND, int CLS, int KV>
+static hipError_t launch_class(const EvalArgs& a, hipStream_t s) {
+  const size_t lds = size_t(EVAL_WAVES) * a.D * ((class_k(CLS, KV) + 3) / 4) * 256 * sizeof(float);
+  const int grid = resident_blocks<KIND, CLS, KV>(lds) * cu_count();
+  hipLaunchKernelGGL((k_eval_class<KIND, CLS, KV>), dim3(grid), dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
 template <int KIND>
 static hipError_t launch_kind(const EvalArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-  const dim3 grid(uint32_t(a.n_programs) * uint32_t(a.n_chunks));
-  const size_t lds_fast = size_t(EVAL_WAVES) * a.D * 64 * EVAL_K * sizeof(float);
-  if (ev0) (void)hipEventRecord(ev0, s);
-  hipLaunchKernelGGL((k_eval_fast<KIND>), grid, dim3(256), lds_fast, s, a);
-  if (ev1) (void)hipEventRecord(ev1, s);
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, a.work, N_CLASSES);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const size_t lds_deep = size_t(EVAL_WAVES) * a.D * 64 * DEEP_K * sizeof(float);
-  hipLaunchKernelGGL((k_eval_deep<KIND>), dim3(512), dim3(256), lds_deep, s, a);
-  return hipGetLastError();
+  if (ev0) (void)hipEventRecord(ev0, s);
+  e = a.D <= WIDE_TILE_MAX_D ? launch_class<KIND, 0, 0>(a, s) : launch_class<KIND, 0, 1>(a, s);
+  if (ev1) (void)hipEventRecord(ev1, s);
+  if (e != hipSuccess) return e;
+  e = launch_class<KIND, 1, 0>(a, s);
+  if (e != hipSuccess) return e;
+  return launch_class<KIND, 2, 0>(a, s);
 }
 
 hipError_t launch_eval(int kind, const EvalArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {

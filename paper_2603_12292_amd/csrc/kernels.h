@@ -27,8 +27,8 @@ struct PrepareArgs {
   int32_t* scr_need;   // [n_tokens] scratch
   ProgMeta* meta;      // [n_programs]
   int8_t* status_out;  // [n_programs] or null
-  int32_t* deep_count; // programs whose register need exceeds FAST_STACK
-  int32_t* deep_list;  // [n_programs]
+  int32_t* class_count;  // [N_CLASSES] programs per register-need class
+  int32_t* class_list;   // [N_CLASSES][n_programs] program indices per class
 };
 
 struct StageArgs {
@@ -56,9 +56,11 @@ struct EvalArgs {
   int64_t chunk;          // cases per chunk, a multiple of CASES_PER_BLOCK_ITER
   double* part;           // [n_sums][n_chunks][n_programs]
   const double* stats;    // target statistics (correlation fitness)
-  const int32_t* deep_count;
-  const int32_t* deep_list;  // global program indices
-  int32_t prog_begin;        // first program of this launch (slice-local index 0)
+  const int32_t* class_count;       // [N_CLASSES]
+  const int32_t* class_list;        // [N_CLASSES][n_total] global program indices
+  unsigned long long* work;         // [N_CLASSES] work-item counters, zero at launch
+  int32_t n_total;                  // programs in the whole population
+  int32_t prog_begin;               // first program of this launch (slice-local index 0)
 };
 
 struct FinalizeArgs {
@@ -87,10 +89,13 @@ struct ValuesArgs {
 };
 
 constexpr int EVAL_WAVES = 4;
-constexpr int EVAL_K = 4;                                        // cases per lane
-constexpr int CASES_PER_WAVE_ITER = 64 * EVAL_K;                 // 256
-constexpr int CASES_PER_BLOCK_ITER = CASES_PER_WAVE_ITER * EVAL_WAVES;  // 1024
-constexpr int DEEP_K = 2;
+constexpr int CASES_PER_WAVE_ITER = 64 * 8;                      // case padding unit (K <= 8)
+constexpr int CASES_PER_BLOCK_ITER = CASES_PER_WAVE_ITER * EVAL_WAVES;  // chunk granularity
+// Cases per lane of the register-need classes (variant KV selects the
+// narrower tile of class 0, used when the LDS input tile of the wide one
+// would exceed WIDE_TILE_MAX_D variables).
+constexpr int WIDE_TILE_MAX_D = 8;
+__host__ __device__ constexpr int class_k(int c, int kv) { return c == 0 ? (kv == 0 ? 8 : 4) : (c == 1 ? 4 : 2); }
 
 __global__ void k_prepare(PrepareArgs a);
 __global__ void k_stage_cases(StageArgs a);

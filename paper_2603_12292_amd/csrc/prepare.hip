@@ -24,6 +24,7 @@ __global__ void k_prepare(PrepareArgs a) {
   const int32_t cc = a.const_count[p];
   int status = BEAGLE_PROG_OK;
   int need_root = 0;
+  int L_dec = 0;
   if (L <= 0) {
     status = L == 0 ? BEAGLE_PROG_EMPTY : BEAGLE_PROG_BAD_LAYOUT;
   } else if (L > MAX_LEN) {
@@ -93,16 +94,29 @@ __global__ void k_prepare(PrepareArgs a) {
         }
         code[o + size - 1] = op | (arg << 8);
       }
-      // pass 3: handler words at the output positions
+      // pass 3: handler words, fusing "terminal, binary operator" pairs;
+      // decoded words are written back from the start (out <= i always)
       float* cv = a.cval + off;
-      int n = 0, nmax = 0;
+      int n = 0, nmax = 0, out = 0;
       for (int i = 0; i < L; ++i) {
         const uint32_t w = code[i];
-        const uint32_t op = w & 0xFFu, arg = w >> 8;
+        const uint32_t op = w & 0xFFu, arg = (w >> 8) & 0xFFu;
+        const uint32_t wslot = n > 0 ? uint32_t(n - 1) : 0u;
         uint32_t h;
-        if (op == OP_VAR || op == OP_CONST) {
-          h = (op == OP_VAR ? H_VAR : H_CONST) + uint32_t(n);
-          if (op == OP_CONST) cv[i] = a.consts[coff + arg];
+        const bool term = op == OP_VAR || op == OP_CONST;
+        const uint32_t nxt = i + 1 < L ? (code[i + 1] & 0xFFu) : 0xFFu;
+        const bool next_bin = nxt < 4u || (nxt >= 100u && nxt < 106u);
+        if (term && n >= 1 && next_bin) {
+          // the pushed value is the right operand of the next operator and
+          // the current top its left one: top = top op value
+          const uint32_t o = nxt >= 100u ? nxt - 100u : nxt;
+          h = H_FUSED + 6u * (op == OP_CONST ? 1u : 0u) + o;
+          if (op == OP_CONST) cv[out] = a.consts[coff + arg];
+          nmax = n + 1 > nmax ? n + 1 : nmax;
+          ++i;  // the operator is consumed; stack size unchanged
+        } else if (term) {
+          h = op == OP_VAR ? H_VAR : H_CONST;
+          if (op == OP_CONST) cv[out] = a.consts[coff + arg];
           ++n;
         } else if (op >= 100u) {
           h = h_bin(op - 100u, n);
@@ -114,23 +128,31 @@ __global__ void k_prepare(PrepareArgs a) {
           h = H_UN + (op - OP_SIN);
         }
         nmax = n > nmax ? n : nmax;
-        code[i] = h | (arg << 8);
+        // the arg field is a variable index for VAR words and 0 otherwise
+        // (constants come from the side table by position), so the
+        // interpreter may read the input tile at any word's arg
+        const uint32_t varg = op == OP_VAR ? arg : 0u;
+        code[out++] = h | (varg << 8) | (wslot << 16);
       }
       // nmax == need_root by construction; the larger one is kept defensively
       need_root = nmax > need_root ? nmax : need_root;
       if (need_root > MAX_STACK) status = BEAGLE_PROG_TOO_LONG;
+      L_dec = out;
     }
   }
   ProgMeta m;
   m.status = status;
   m.need = need_root;
-  m.len = status == BEAGLE_PROG_OK ? L : 0;
+  m.len = status == BEAGLE_PROG_OK ? L_dec : 0;
   m.shift = 0.0f;
   a.meta[p] = m;
   if (a.status_out) a.status_out[p] = int8_t(status);
-  if (status == BEAGLE_PROG_OK && need_root > FAST_STACK) {
-    const int slot = atomicAdd(a.deep_count, 1);
-    a.deep_list[slot] = p;
+  if (status == BEAGLE_PROG_OK) {
+    // append to the list of its register-need class (list order does not
+    // affect any result: every (program, chunk) partial has its own slot)
+    const int cls = need_class(need_root);
+    const int slot = atomicAdd(a.class_count + cls, 1);
+    a.class_list[int64_t(cls) * a.n_programs + slot] = p;
   }
 }
 

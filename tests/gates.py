@@ -8,9 +8,10 @@ classes.
 Value gate: |F_gpu - F_O64| <= 1e-5 |F_O64| + atol for every program that is
 finite in both and well conditioned: its fitness moves by at most
 1e-6 |F_O64| + atol (a tenth of the gate) when every token is rounded to fp32
-(O32e) and in two runs where every token's result is also perturbed by a
-few ulps (O32p, two seeds) -- a model of an fp32 implementation whose
-operations are accurate to a few ulps, as the GPU's are.  Ill-conditioned
+(O32e) and in two runs where every sin/cos/exp/log result is also perturbed
+by a few ulps (O32p, two seeds) -- a model of an fp32 implementation with
+correctly rounded + - * / sqrt and transcendentals accurate to a few ulps,
+as the GPU's are.  Ill-conditioned
 programs (e.g. sin of exp of a large argument) are counted, not compared.
 atol = 1e-10 * mean(y^2) for MSE, 1e-9 for correlation fitness.
 """

@@ -45,7 +45,8 @@ def test_tiny_population_parity(kind):
     # MSE of programs with exp of large arguments amplifies fp32 rounding
     # (d exp(x) / exp(x) = x dx), so more of them fall outside the
     # well-conditioned set than for correlation fitness
-    n, ill = gates.check(gpu, f64, f32, kind, w.data.y, max_ill_frac=0.15, label=f"tiny kind={kind}",
+    n, ill = gates.check(gpu, f64, f32, kind, w.data.y, max_ill_frac=0.25 if kind == ofit.MSE else 0.15,
+                         label=f"tiny kind={kind}",
                          perturbed=pert)
     print(f"compared {n}, ill-conditioned {ill}")
     assert n > 150
@@ -178,8 +179,8 @@ def test_empty_population():
 
 
 def test_predict_against_o32e():
-    """Per-case outputs.  Programs of + - * / only: bit-identical to O32e
-    (IEEE fp32 with correctly rounded division).  Any program: identical
+    """Per-case outputs.  Programs of + - * / sqrt only: bit-identical to
+    O32e (IEEE fp32 with correctly rounded division and square root).  Any program: identical
     NaN pattern, and within 1e-5 of O64 on every case whose value is stable
     under few-ulp perturbations (O32p, two seeds)."""
     data = wl.make_dataset(13, 600, 3, x_range=(-3.0, 5.0), target_len=8)
@@ -188,7 +189,8 @@ def test_predict_against_o32e():
     arith = []
     for _ in range(32):
         toks, consts = wl.random_program(rng, int(rng.integers(1, 40)), 3)
-        arith.append(([t if (t & 0xFF) >= 9 or (t & 0xFF) < 4 else 2 for t in toks], consts))
+        # transcendental tokens become SQRT (same arity, correctly rounded)
+        arith.append(([t if (t & 0xFF) >= 9 or (t & 0xFF) < 4 else 8 for t in toks], consts))
     ps2 = wl.pack_programs(arith)
     api = _api()
     X = torch.from_numpy(data.X).cuda()

@@ -1,0 +1,117 @@
+"""Generation step and initialisation on the GPU: bit-exact against the oracle."""
+import numpy as np
+import pytest
+
+from oracle import gp
+from paper_2603_12292_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _api():
+    from paper_2603_12292_amd import api
+    return api
+
+
+def _params(api, **kw):
+    p = gp.GenParams(**kw)
+    return p, api.GenParams(**kw)
+
+
+def _slots_to_lists(s):
+    tok = s.tokens.cpu().numpy().view(np.uint16)
+    ln = s.len.cpu().numpy()
+    cst = s.consts.cpu().numpy()
+    cc = s.const_count.cpu().numpy()
+    return tok, ln, cst, cc
+
+
+@pytest.mark.parametrize("D,seed", [(9, 1234), (3, 2**40 + 77), (1, 5)])
+def test_init_bit_exact(D, seed):
+    api = _api()
+    op, ap = _params(api)
+    n = 1000
+    s = api.init_population(n, D, ap, seed, problem=3)
+    torch.cuda.synchronize()
+    tok, ln, cst, cc = _slots_to_lists(s)
+    ref = gp.to_fixed(gp.init_population(n, D, op, seed, problem=3), op.max_len, op.max_consts)
+    assert np.array_equal(ln, ref[1])
+    assert np.array_equal(tok, ref[0])
+    assert np.array_equal(cc, ref[3])
+    assert np.array_equal(cst.view(np.uint32), ref[2].view(np.uint32))
+
+
+def _parents(seed, n, D, lo=1, hi=60):
+    ps = wl.random_population(seed, n, lo, hi, D)
+    rng = np.random.default_rng(seed)
+    fit = rng.standard_normal(n)
+    fit[rng.integers(0, n, size=n // 10)] = np.nan
+    fit[rng.integers(0, n, size=n // 20)] = np.inf
+    fit[rng.integers(0, n, size=n // 10)] = 0.5   # ties
+    return ps, fit
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(p_crossover=0.0, p_mutation=1.0), dict(tournament=7, max_len=40),
+                                dict(p_crossover=0.3, p_mutation=0.3, max_consts=2, const_lo=-1.5, const_hi=2.0)])
+def test_generation_bit_exact(kw):
+    api = _api()
+    op, ap = _params(api, **kw)
+    D = 4
+    ps, fit = _parents(31, 700, D)
+    seed, g = 0x1234_5678_9ABC_DEF0, 17
+    par = api.DevicePrograms.from_programset(ps)
+    f = torch.from_numpy(fit).cuda()
+    s = api.generation(par, f, ap, D, seed, g)
+    torch.cuda.synchronize()
+    tok, ln, cst, cc = _slots_to_lists(s)
+    plist_t = [list(ps.program(p)[0]) for p in range(ps.n)]
+    plist_c = [list(ps.program(p)[1]) for p in range(ps.n)]
+    ref = gp.to_fixed(gp.generation(plist_t, plist_c, fit, D, op, seed, g), op.max_len, op.max_consts)
+    bad = np.nonzero((ln != ref[1]) | np.any(tok != ref[0], axis=1))[0]
+    assert len(bad) == 0, bad[:10]
+    assert np.array_equal(cc, ref[3])
+    assert np.array_equal(cst.view(np.uint32), ref[2].view(np.uint32))
+
+
+def test_generation_loop_reproducible_and_resumable():
+    """Init, then 6 generations of eval + step on the GPU, twice; the second
+    run stops after 3 generations, copies the state to the host and resumes
+    from it: both runs end bit-identical."""
+    api = _api()
+    _, ap = _params(api)
+    D = 3
+    data = wl.make_dataset(41, 4096, D, x_range=(1.0, 5.0), target_len=12)
+    X = torch.from_numpy(data.X).cuda()
+    y = torch.from_numpy(data.y).cuda()
+    seed = 99
+
+    def run(g_from, g_to, state):
+        pop = state
+        for g in range(g_from, g_to + 1):
+            fit = api.evaluate(pop.programs(), X, y, "mse")
+            pop = api.generation(pop.programs(), fit, ap, D, seed, g)
+        return pop
+
+    pop0 = api.init_population(2048, D, ap, seed)
+    a = run(1, 6, pop0)
+    mid = run(1, 3, pop0)
+    host = [t.cpu() for t in (mid.tokens, mid.len, mid.consts, mid.const_count)]
+    resumed = api.Slots(*[t.cuda() for t in host])
+    b = run(4, 6, resumed)
+    for x, z in zip((a.tokens, a.len, a.consts, a.const_count), (b.tokens, b.len, b.consts, b.const_count)):
+        assert torch.equal(x, z)
+    assert torch.all(a.len > 0)
+
+
+def test_generation_argument_errors():
+    api = _api()
+    ps, fit = _parents(3, 10, 2)
+    par = api.DevicePrograms.from_programset(ps)
+    f = torch.from_numpy(fit).cuda()
+    with pytest.raises(api.BeagleError):
+        api.generation(par, f, api.GenParams(tournament=0), 2, 1, 1)
+    with pytest.raises(api.BeagleError):
+        api.generation(par, f, api.GenParams(p_crossover=0.8, p_mutation=0.5), 2, 1, 1)
+    with pytest.raises(api.BeagleError):
+        api.init_population(10, 2, api.GenParams(init_depth_max=7), 1)

@@ -179,3 +179,16 @@ def test_validate_opcode_and_priority():
     assert interp.validate(parse("+ x5"), 0, 2)[0] == interp.ST_UNDERFLOW
     assert interp.validate([9] * 4097, 0, 1)[0] == interp.ST_TOO_LONG
     assert interp.validate(parse("x0 x1 x0 * +"), 0, 2) == (interp.ST_OK, 3)
+
+
+def test_o32p_perturbs_only_transcendentals():
+    rng = np.random.default_rng(3)
+    X = rng.uniform(1, 5, size=(200, 2)).astype(np.float32)
+    toks = parse("x0 x1 / x0 sqrt * x1 -")
+    assert same(interp.run(toks, [], X, "o32p", seed=4), interp.run(toks, [], X, "o32e"))
+    toks = parse("x0 sin x1 exp *")
+    a = interp.run(toks, [], X, "o32p", seed=4)
+    b = interp.run(toks, [], X, "o32e")
+    assert not same(a, b)
+    assert np.all(np.abs(a - b) <= 2 ** -20 * np.abs(b))
+    assert same(a, interp.run(toks, [], X, "o32p", seed=4))
