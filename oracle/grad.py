@@ -18,6 +18,16 @@ the operator by a constant):
   SQRT sign(x) / (2 sqrt|x|) if x != 0, else 0
 A constant slot's gradient is the sum over cases of the adjoints of every
 CONST token that reads it.
+
+Modes (conditioning only; the reference gradient is "o64"):
+  "o32e"  every forward value, every partial derivative and every adjoint
+          product rounded to binary32 (the per-case arithmetic of an fp32
+          adjoint), sums over cases still exact;
+  "o32p"  as o32e, with sin/cos/exp/log results and the derivative values
+          computed from transcendental functions perturbed by a few ulps
+          (seeded), as in oracle.interp.
+A gradient component is stable under these modes when an fp32 adjoint can
+reproduce it; where per-case contributions cancel it is not.
 """
 from __future__ import annotations
 
@@ -30,27 +40,58 @@ from . import interp
 ADD, SUB, MUL, DIV, SIN, COS, EXP, LOG, SQRT, VAR, CONST = range(11)
 
 
+def _fsum(v) -> float:
+    """Exactly rounded sum; plain IEEE sum when a term is not finite."""
+    arr = np.asarray(v, dtype=np.float64)
+    if np.all(np.isfinite(arr)):
+        return math.fsum(arr.tolist())
+    with np.errstate(all="ignore"):
+        return float(np.sum(arr))
+
+
 def _mse64(y_hat, y64):
     d = y_hat - y64
     return math.fsum((d * d).tolist()) / y_hat.shape[0]
 
 
-def mse_and_grad(tokens, consts, X, y):
-    """(F, dF/dconsts float64[len(consts)]) in binary64 throughout."""
+def mse_and_grad(tokens, consts, X, y, mode: str = "o64", seed: int = 0):
+    """(F, dF/dconsts float64[len(consts)]); binary64 throughout for "o64"."""
     X64 = np.asarray(X, dtype=np.float32).astype(np.float64)
     y64 = np.asarray(y, dtype=np.float32).astype(np.float64)
     c64 = np.asarray(consts, dtype=np.float32).astype(np.float64)
-    return mse_and_grad64(tokens, c64, X64, y64)
+    return mse_and_grad64(tokens, c64, X64, y64, mode, seed)
 
 
-def mse_and_grad64(tokens, c64, X64, y64):
-    values, children = interp.run_tape(tokens, c64, X64)
+def _rounder(mode, seed, M):
+    if mode == "o64":
+        return (lambda v: v), (lambda v: v)
+    rng = np.random.default_rng(seed)
+
+    def r32(v):
+        with np.errstate(over="ignore", invalid="ignore"):
+            return np.asarray(v, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+    def r32t(v):  # a transcendental result
+        if mode == "o32p":
+            with np.errstate(all="ignore"):
+                v = v * (1.0 + rng.uniform(-2.0 ** -22, 2.0 ** -22, size=M))
+        return r32(v)
+
+    return r32, r32t
+
+
+def mse_and_grad64(tokens, c64, X64, y64, mode: str = "o64", seed: int = 0):
     M = X64.shape[0]
     L = len(tokens)
+    R, RT = _rounder(mode, seed, M)
+    if mode == "o64":
+        values, children = interp.run_tape(tokens, c64, X64)
+    else:
+        values, children = _tape_rounded(tokens, c64, X64, R, RT)
     y_hat = values[-1]
     F = _mse64(y_hat, y64)
     adj = [None] * L
-    adj[L - 1] = 2.0 * (y_hat - y64) / M
+    adj[L - 1] = R(R(y_hat - y64) * R(2.0 / M)) if mode != "o64" else 2.0 * (y_hat - y64) / M
     g = [[] for _ in range(len(c64))]
     with np.errstate(all="ignore"):
         for t in range(L - 1, -1, -1):
@@ -59,7 +100,7 @@ def mse_and_grad64(tokens, c64, X64, y64):
             if op == VAR:
                 continue
             if op == CONST:
-                g[arg].append(math.fsum(a_t.tolist()))
+                g[arg].append(_fsum(a_t))
                 continue
             kids = children[t]
             if len(kids) == 2:
@@ -70,36 +111,86 @@ def mse_and_grad64(tokens, c64, X64, y64):
                 elif op == SUB:
                     da, db = a_t, -a_t
                 elif op == MUL:
-                    da, db = a_t * b, a_t * a
+                    da, db = R(a_t * b), R(a_t * a)
                 elif op == DIV:
                     nz = b != 0.0
                     bs = np.where(nz, b, 1.0)
-                    da = np.where(nz, a_t / bs, 0.0)
-                    db = np.where(nz, -a_t * a / (bs * bs), 0.0)
+                    if mode == "o64":
+                        da = np.where(nz, a_t / bs, 0.0)
+                        db = np.where(nz, -a_t * a / (bs * bs), 0.0)
+                    else:
+                        r = R(1.0 / bs)
+                        da = np.where(nz, R(a_t * r), 0.0)
+                        db = np.where(nz, R(a_t * R(R(-a * r) * r)), 0.0)
                 else:
                     raise ValueError(op)
                 adj[ia], adj[ib] = da, db
             else:
                 (ix,) = kids
                 x = values[ix]
-                if op == SIN:
-                    dx = a_t * np.cos(x)
-                elif op == COS:
-                    dx = -a_t * np.sin(x)
-                elif op == EXP:
-                    inside = ~((x > 80.0) | (x < -80.0))
-                    dx = np.where(inside, a_t * np.exp(np.where(inside, x, 0.0)), 0.0)
-                elif op == LOG:
-                    nz = x != 0.0
-                    dx = np.where(nz, a_t / np.where(nz, x, 1.0), 0.0)
-                elif op == SQRT:
-                    nz = x != 0.0
-                    dx = np.where(nz, a_t * np.sign(x) / (2.0 * np.sqrt(np.abs(np.where(nz, x, 1.0)))), 0.0)
+                if mode == "o64":
+                    if op == SIN:
+                        dx = a_t * np.cos(x)
+                    elif op == COS:
+                        dx = -a_t * np.sin(x)
+                    elif op == EXP:
+                        inside = ~((x > 80.0) | (x < -80.0))
+                        dx = np.where(inside, a_t * np.exp(np.where(inside, x, 0.0)), 0.0)
+                    elif op == LOG:
+                        nz = x != 0.0
+                        dx = np.where(nz, a_t / np.where(nz, x, 1.0), 0.0)
+                    elif op == SQRT:
+                        nz = x != 0.0
+                        dx = np.where(nz, a_t * np.sign(x) / (2.0 * np.sqrt(np.abs(np.where(nz, x, 1.0)))), 0.0)
+                    else:
+                        raise ValueError(op)
                 else:
-                    raise ValueError(op)
+                    yv = values[t]
+                    if op == SIN:
+                        d = RT(np.cos(x))
+                    elif op == COS:
+                        d = -RT(np.sin(x))
+                    elif op == EXP:
+                        d = np.where((x > 80.0) | (x < -80.0), 0.0, yv)
+                    elif op == LOG:
+                        d = np.where(x != 0.0, R(1.0 / np.where(x != 0.0, x, 1.0)), 0.0)
+                    elif op == SQRT:
+                        d = np.where(x != 0.0, R(np.copysign(0.5, x) / np.where(x != 0.0, yv, 1.0)), 0.0)
+                    else:
+                        raise ValueError(op)
+                    dx = R(a_t * d)
                 adj[ix] = dx
-    grad = np.array([math.fsum(v) for v in g], dtype=np.float64)
+    grad = np.array([_fsum(v) for v in g], dtype=np.float64)
     return F, grad
+
+
+def _tape_rounded(tokens, c64, X64, R, RT):
+    """run_tape with every result rounded to binary32 (RT for sin/cos/exp/log)."""
+    M = X64.shape[0]
+    X32 = R(X64)
+    values = []
+    children = []
+    pos_stack = []
+    for i, t in enumerate(tokens):
+        op, arg = int(t) & 0xFF, int(t) >> 8
+        if op == VAR:
+            values.append(X32[:, arg].copy())
+            children.append(())
+        elif op == CONST:
+            values.append(np.full(M, float(R(np.array([c64[arg]]))[0])))
+            children.append(())
+        elif interp.ARITY[op] == 2:
+            rb = pos_stack.pop()
+            ra = pos_stack.pop()
+            values.append(R(interp.apply_op(op, values[ra], values[rb], None)))
+            children.append((ra, rb))
+        else:
+            rx = pos_stack.pop()
+            v = interp.apply_op(op, None, None, values[rx])
+            values.append(RT(v) if op in (SIN, COS, EXP, LOG) else R(v))
+            children.append((rx,))
+        pos_stack.append(i)
+    return values, children
 
 
 def branch_masks(tokens, c64, X64):

@@ -281,3 +281,22 @@ def generation(parents: DevicePrograms, fitness: torch.Tensor, params: GenParams
                                    generation_index, problem, out.tokens.data_ptr(), out.len.data_ptr(),
                                    out.consts.data_ptr(), out.const_count.data_ptr(), _stream(dev)))
     return out
+
+
+def evaluate_grad(progs: DevicePrograms, X: torch.Tensor, y: torch.Tensor, kind="mse", *,
+                  with_status: bool = False, ctx: Optional[Context] = None):
+    """(fitness float64 [N], dF/dconsts float32 [n_consts]) -- beagle_eval_grad.
+
+    Program p's gradient occupies consts[const_offset[p] : + const_count[p]]
+    of the returned array; the programs' constant ranges must not overlap.
+    """
+    dev = progs.device
+    c = _ctx_for(dev, ctx)
+    ps = progs.struct()
+    ds = _dataset(X, y, dev)
+    fit = torch.empty(progs.n, dtype=torch.float64, device=dev)
+    grad = torch.zeros(progs.consts.numel(), dtype=torch.float32, device=dev)
+    st = torch.empty(progs.n, dtype=torch.int8, device=dev) if with_status else None
+    _check(c.lib.beagle_eval_grad(c.handle, ctypes.byref(ps), ctypes.byref(ds), _kind(kind), fit.data_ptr(),
+                                  grad.data_ptr(), st.data_ptr() if st is not None else None, _stream(dev)))
+    return (fit, grad, st) if with_status else (fit, grad)

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbeagle.so")
-SOURCES = ["api.cpp", "prepare.hip", "eval.hip", "gen.hip"]
+SOURCES = ["api.cpp", "prepare.hip", "eval.hip", "gen.hip", "grad.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

@@ -12,6 +12,7 @@
 #include "../../include/beagle.h"
 #include "beagle_device.h"
 #include "gen.h"
+#include "grad.h"
 #include "kernels.h"
 
 struct beagle_ctx {
@@ -125,24 +126,28 @@ void choose_chunks(int64_t M, int64_t N, int64_t* chunk, int32_t* n_chunks) {
 
 // The pieces of workspace one evaluation uses.
 struct EvalLayout {
-  size_t code, cval, s_stack, s_start, s_need, meta, class_count, class_list, work, Xt, yp, stats, part, total;
+  size_t code, aux, cval, s_stack, s_start, s_need, meta, class_count, class_list, len_list, work, Xt, yp, stats, part,
+      gpart, total;
   int64_t Mp, chunk;
   int32_t n_chunks, slice;
 };
 
-EvalLayout eval_layout(const beagle_programs* P, const beagle_dataset* d, int n_sums, int32_t slice) {
+EvalLayout eval_layout(const beagle_programs* P, const beagle_dataset* d, int n_sums, int32_t slice,
+                       bool with_grad = false) {
   EvalLayout L{};
   Carve c;
   const int64_t nt = std::max<int64_t>(P->n_tokens, 1);
   const int64_t N = std::max<int32_t>(P->n_programs, 1);
   L.code = c.take<uint32_t>(nt);
+  L.aux = c.take<uint32_t>(nt);
   L.cval = c.take<float>(nt);
   L.s_stack = c.take<int32_t>(nt);
   L.s_start = c.take<int32_t>(nt);
   L.s_need = c.take<int32_t>(nt);
   L.meta = c.take<bgl::ProgMeta>(N);
-  L.class_count = c.take<int32_t>(64);
+  L.class_count = c.take<int32_t>(64);  // [0..2] need classes, [8..9] length classes
   L.class_list = c.take<int32_t>(size_t(bgl::N_CLASSES) * N);
+  L.len_list = c.take<int32_t>(size_t(2) * N);
   L.work = c.take<unsigned long long>(bgl::N_CLASSES);
   L.Mp = round_up(d->M, bgl::CASES_PER_WAVE_ITER);
   L.Xt = c.take<float>(size_t(d->D) * L.Mp);
@@ -153,6 +158,7 @@ EvalLayout eval_layout(const beagle_programs* P, const beagle_dataset* d, int n_
   // evaluation sums every program's partials in the same order
   choose_chunks(d->M, N, &L.chunk, &L.n_chunks);
   L.part = c.take<double>(size_t(n_sums) * L.n_chunks * slice);
+  L.gpart = with_grad ? c.take<double>(size_t(L.n_chunks) * std::max<int64_t>(P->n_consts, 1)) : 0;
   L.total = c.used + 256;
   return L;
 }
@@ -165,7 +171,7 @@ __global__ void k_zero_i32(int32_t* p, int n) {
 // Validation + decoding of the programs and staging of the cases (shared by
 // evaluation, prediction and the gradient).
 beagle_status prepare(beagle_ctx* ctx, const beagle_programs* P, const beagle_dataset* d, const EvalLayout& L,
-                      int8_t* status, hipStream_t s) {
+                      int8_t* status, hipStream_t s, int32_t max_words = bgl::MAX_LEN) {
   char* ws = ctx->ws;
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, reinterpret_cast<int32_t*>(ws + L.class_count), 64);
   bgl::PrepareArgs pa;
@@ -180,7 +186,9 @@ beagle_status prepare(beagle_ctx* ctx, const beagle_programs* P, const beagle_da
   pa.n_programs = P->n_programs;
   pa.D = d->D;
   pa.code = reinterpret_cast<uint32_t*>(ws + L.code);
+  pa.aux = reinterpret_cast<uint32_t*>(ws + L.aux);
   pa.cval = reinterpret_cast<float*>(ws + L.cval);
+  pa.max_words = max_words;
   pa.scr_stack = reinterpret_cast<int32_t*>(ws + L.s_stack);
   pa.scr_start = reinterpret_cast<int32_t*>(ws + L.s_start);
   pa.scr_need = reinterpret_cast<int32_t*>(ws + L.s_need);
@@ -188,6 +196,9 @@ beagle_status prepare(beagle_ctx* ctx, const beagle_programs* P, const beagle_da
   pa.status_out = status;
   pa.class_count = reinterpret_cast<int32_t*>(ws + L.class_count);
   pa.class_list = reinterpret_cast<int32_t*>(ws + L.class_list);
+  pa.len_count = reinterpret_cast<int32_t*>(ws + L.class_count) + 8;
+  pa.len_list = reinterpret_cast<int32_t*>(ws + L.len_list);
+  pa.short_words = bgl::GRAD_SHORT_WORDS;
   hipLaunchKernelGGL(bgl::k_prepare, dim3((P->n_programs + 63) / 64), dim3(64), 0, s, pa);
   bgl::StageArgs sa;
   sa.X = d->X;
@@ -518,6 +529,72 @@ beagle_status beagle_generation(beagle_ctx* ctx, const beagle_programs* parents,
                      a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "generation launch");
+  g_error.clear();
+  return BEAGLE_OK;
+}
+
+beagle_status beagle_eval_grad(beagle_ctx* ctx, const beagle_programs* progs, const beagle_dataset* data,
+                               int kind, double* fitness, float* grad_consts, int8_t* status,
+                               beagle_stream stream) {
+  if (!ctx) return fail(BEAGLE_E_INVALID_ARG, "ctx is NULL");
+  if (kind != BEAGLE_FIT_MSE) return fail(BEAGLE_E_UNSUPPORTED, "the gradient supports MSE fitness only");
+  beagle_status st = check_programs(progs);
+  if (st != BEAGLE_OK) return st;
+  st = check_data(data, kind);
+  if (st != BEAGLE_OK) return st;
+  if (progs->n_programs == 0) return BEAGLE_OK;
+  if (!fitness) return fail(BEAGLE_E_INVALID_ARG, "fitness is NULL");
+  if (progs->n_consts > 0 && !grad_consts) return fail(BEAGLE_E_INVALID_ARG, "grad_consts is NULL");
+  DeviceGuard g(ctx->device);
+  if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  EvalLayout L = eval_layout(progs, data, 1, progs->n_programs, true);
+  st = reserve(ctx, L.total);
+  if (st != BEAGLE_OK) return st;
+  st = prepare(ctx, progs, data, L, status, s, bgl::GRAD_LONG_WORDS);
+  if (st != BEAGLE_OK) return st;
+  char* ws = ctx->ws;
+  unsigned long long* work = reinterpret_cast<unsigned long long*>(ws + L.work);
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, reinterpret_cast<int32_t*>(work), 2 * bgl::N_CLASSES);
+  bgl::GradArgs ga;
+  ga.code = reinterpret_cast<const uint32_t*>(ws + L.code);
+  ga.aux = reinterpret_cast<const uint32_t*>(ws + L.aux);
+  ga.cval = reinterpret_cast<const float*>(ws + L.cval);
+  ga.tok_offset = progs->tok_offset;
+  ga.meta = reinterpret_cast<const bgl::ProgMeta*>(ws + L.meta);
+  ga.const_offset = progs->const_offset;
+  ga.const_count = progs->const_count;
+  ga.Xt = reinterpret_cast<const float*>(ws + L.Xt);
+  ga.yp = reinterpret_cast<const float*>(ws + L.yp);
+  ga.M = data->M;
+  ga.Mp = L.Mp;
+  ga.D = data->D;
+  ga.n_programs = progs->n_programs;
+  ga.n_chunks = L.n_chunks;
+  ga.chunk = L.chunk;
+  ga.part = reinterpret_cast<double*>(ws + L.part);
+  ga.gpart = reinterpret_cast<double*>(ws + L.gpart);
+  ga.n_consts = progs->n_consts;
+  ga.list_count = reinterpret_cast<const int32_t*>(ws + L.class_count) + 8;
+  ga.list = reinterpret_cast<const int32_t*>(ws + L.len_list);
+  ga.work = work;
+  hipError_t e = bgl::launch_grad(ga, s);
+  if (e != hipSuccess) return hip_fail(e, "gradient launch");
+  bgl::GradFinalizeArgs fa;
+  fa.meta = ga.meta;
+  fa.part = ga.part;
+  fa.gpart = ga.gpart;
+  fa.const_offset = progs->const_offset;
+  fa.const_count = progs->const_count;
+  fa.M = data->M;
+  fa.n_consts = progs->n_consts;
+  fa.n_programs = progs->n_programs;
+  fa.n_chunks = L.n_chunks;
+  fa.fitness = fitness;
+  fa.grad = grad_consts;
+  hipLaunchKernelGGL(bgl::k_grad_finalize, dim3((progs->n_programs + 255) / 256), dim3(256), 0, s, fa);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "gradient finalize launch");
   g_error.clear();
   return BEAGLE_OK;
 }

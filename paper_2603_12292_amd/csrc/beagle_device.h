@@ -11,9 +11,8 @@
 //
 //     word = handler | (arg << 8) | (wslot << 16)
 //
-// arg is the variable index of VAR and fused-VAR words and 0 in every other
-// word, so it always addresses a valid row of the input tile (the
-// interpreter reads the next word's row one token ahead).
+// arg is the variable index of VAR words, the constant slot of CONST words
+// (their value also sits in a side table by word position) and 0 otherwise.
 //
 // The interpreter keeps the value on top of the stack in `top` and the n-1
 // values below it in stk[0..n-2] (n = stack size before the token).  Every

@@ -21,7 +21,9 @@ struct PrepareArgs {
   int32_t n_programs;
   int32_t D;
   uint32_t* code;      // [n_tokens] decoded words
+  uint32_t* aux;       // [n_tokens] adjoint operands per decoded word
   float* cval;         // [n_tokens] CONST values by output position
+  int32_t max_words;   // decoded words allowed (longer -> BEAGLE_PROG_TOO_LONG)
   int32_t* scr_stack;  // [n_tokens] scratch
   int32_t* scr_start;  // [n_tokens] scratch
   int32_t* scr_need;   // [n_tokens] scratch
@@ -29,6 +31,9 @@ struct PrepareArgs {
   int8_t* status_out;  // [n_programs] or null
   int32_t* class_count;  // [N_CLASSES] programs per register-need class
   int32_t* class_list;   // [N_CLASSES][n_programs] program indices per class
+  int32_t* len_count;    // [2] programs with <= short_words decoded words / more
+  int32_t* len_list;     // [2][n_programs]
+  int32_t short_words;
 };
 
 struct StageArgs {

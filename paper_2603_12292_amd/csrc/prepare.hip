@@ -95,14 +95,20 @@ __global__ void k_prepare(PrepareArgs a) {
         code[o + size - 1] = op | (arg << 8);
       }
       // pass 3: handler words, fusing "terminal, binary operator" pairs;
-      // decoded words are written back from the start (out <= i always)
+      // decoded words are written back from the start (out <= i always).
+      // Alongside, for the adjoint: aux[out] = pa | (rws << 16), pa = the
+      // decoded word that produced the value below the top (binary words),
+      // rws = the adjoint-stack slot the reverse sweep writes (see grad.hip);
+      // `start` is free after pass 2 and holds the producer of each stack slot.
       float* cv = a.cval + off;
+      uint32_t* aux = a.aux + off;
+      int32_t* prod = start;
       int n = 0, nmax = 0, out = 0;
       for (int i = 0; i < L; ++i) {
         const uint32_t w = code[i];
         const uint32_t op = w & 0xFFu, arg = (w >> 8) & 0xFFu;
         const uint32_t wslot = n > 0 ? uint32_t(n - 1) : 0u;
-        uint32_t h;
+        uint32_t h, pa = 0u, rws;
         const bool term = op == OP_VAR || op == OP_CONST;
         const uint32_t nxt = i + 1 < L ? (code[i + 1] & 0xFFu) : 0xFFu;
         const bool next_bin = nxt < 4u || (nxt >= 100u && nxt < 106u);
@@ -113,30 +119,36 @@ __global__ void k_prepare(PrepareArgs a) {
           h = H_FUSED + 6u * (op == OP_CONST ? 1u : 0u) + o;
           if (op == OP_CONST) cv[out] = a.consts[coff + arg];
           nmax = n + 1 > nmax ? n + 1 : nmax;
+          rws = uint32_t(n - 1);
+          prod[n - 1] = out;
           ++i;  // the operator is consumed; stack size unchanged
         } else if (term) {
           h = op == OP_VAR ? H_VAR : H_CONST;
           if (op == OP_CONST) cv[out] = a.consts[coff + arg];
+          rws = uint32_t(n);
+          prod[n] = out;
           ++n;
-        } else if (op >= 100u) {
-          h = h_bin(op - 100u, n);
+        } else if (op >= 100u || op < 4) {
+          h = op >= 100u ? h_bin(op - 100u, n) : h_bin(op, n);  // ADD..DIV: BinIdx == opcode
+          pa = uint32_t(prod[n - 2]);
+          rws = uint32_t(n - 2);
           --n;
-        } else if (op < 4) {
-          h = h_bin(op, n);  // ADD..DIV have BinIdx equal to their opcode
-          --n;
+          prod[n - 1] = out;
         } else {
           h = H_UN + (op - OP_SIN);
+          rws = uint32_t(n - 1);
+          prod[n - 1] = out;
         }
         nmax = n > nmax ? n : nmax;
-        // the arg field is a variable index for VAR words and 0 otherwise
-        // (constants come from the side table by position), so the
-        // interpreter may read the input tile at any word's arg
-        const uint32_t varg = op == OP_VAR ? arg : 0u;
-        code[out++] = h | (varg << 8) | (wslot << 16);
+        // arg: variable index (VAR words), constant slot (CONST words), 0 otherwise
+        const uint32_t warg = term ? arg : 0u;
+        code[out] = h | (warg << 8) | (wslot << 16);
+        aux[out] = pa | (rws << 16);
+        ++out;
       }
       // nmax == need_root by construction; the larger one is kept defensively
       need_root = nmax > need_root ? nmax : need_root;
-      if (need_root > MAX_STACK) status = BEAGLE_PROG_TOO_LONG;
+      if (need_root > MAX_STACK || out > a.max_words) status = BEAGLE_PROG_TOO_LONG;
       L_dec = out;
     }
   }
@@ -153,6 +165,10 @@ __global__ void k_prepare(PrepareArgs a) {
     const int cls = need_class(need_root);
     const int slot = atomicAdd(a.class_count + cls, 1);
     a.class_list[int64_t(cls) * a.n_programs + slot] = p;
+    // and by decoded length (the adjoint keeps short tapes in registers)
+    const int lc = L_dec <= a.short_words ? 0 : 1;
+    const int ls = atomicAdd(a.len_count + lc, 1);
+    a.len_list[int64_t(lc) * a.n_programs + ls] = p;
   }
 }
 

@@ -1,0 +1,194 @@
+"""Adjoint (beagle_eval_grad) against the oracle gradient and finite differences."""
+import math
+
+import numpy as np
+import pytest
+
+import gates
+from oracle import fitness as ofit
+from oracle import grad as og
+from oracle import interp
+from paper_2603_12292_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+GRAD_RTOL = 1e-4
+COND_RTOL = 1e-5
+
+
+def _spread(t, c, data, g64):
+    """Largest move of each gradient component under the O32e and two O32p
+    gradient modes (what an fp32 adjoint can be expected to reproduce)."""
+    spread = np.zeros_like(g64)
+    for mode, seed in (("o32e", 0), ("o32p", 1), ("o32p", 2)):
+        _, gm = og.mse_and_grad(t, c, data.X, data.y, mode, seed)
+        spread = np.maximum(spread, np.where(np.isfinite(gm), np.abs(gm - g64), np.inf))
+    return spread
+
+
+def _stable_components(t, c, data, g64):
+    """Norm-wise stability: components moving by at most COND_RTOL * max|g64|
+    (a tenth of the norm-wise gate)."""
+    scale = float(np.max(np.abs(g64)))
+    return _spread(t, c, data, g64) <= COND_RTOL * scale, scale
+
+
+def _api():
+    from paper_2603_12292_amd import api
+    return api
+
+
+def _grad(ps, data, with_status=False):
+    api = _api()
+    P = api.DevicePrograms.from_programset(ps)
+    X = torch.from_numpy(data.X).cuda()
+    y = torch.from_numpy(data.y).cuda()
+    out = api.evaluate_grad(P, X, y, "mse", with_status=True)
+    torch.cuda.synchronize()
+    f, g, st = out[0].cpu().numpy(), out[1].cpu().numpy(), out[2].cpu().numpy()
+    return f, g, st
+
+
+def _well_conditioned(ps, data, idx):
+    f64, _, f32, pert = gates.references(ps, data.X, data.y, ofit.MSE, subset=idx)
+    at = gates.atol(ofit.MSE, data.y)
+    ok = []
+    for j in range(len(idx)):
+        sp = max([abs(f32[j] - f64[j])] + [abs(p[j] - f64[j]) for p in pert])
+        ok.append(math.isfinite(f64[j]) and sp <= gates.RTOL_COND * abs(f64[j]) + at)
+    return np.array(ok)
+
+
+def test_gradient_matches_oracle():
+    w = wl.config_differentiation(N=160, M=3000)
+    ps, data = w.programs, w.data
+    f, g, st = _grad(ps, data)
+    assert np.all(st == 0)
+    well = _well_conditioned(ps, data, list(range(ps.n)))
+    n_cmp = 0
+    bad = []
+    for p in range(ps.n):
+        if not well[p]:
+            continue
+        t, c = ps.program(p)
+        F, g64 = og.mse_and_grad(t, c, data.X, data.y)
+        if not (math.isfinite(F) and np.all(np.isfinite(g64))):
+            continue
+        o, cc = int(ps.const_offset[p]), int(ps.const_count[p])
+        gg = g[o:o + cc].astype(np.float64)
+        stable, scale = _stable_components(t, c, data, g64)
+        assert abs(f[p] - F) <= 1e-5 * abs(F) + gates.atol(ofit.MSE, data.y)
+        if not np.any(stable):
+            continue
+        err = float(np.max(np.abs(gg - g64)[stable]))
+        if err > GRAD_RTOL * scale + 1e-7:
+            bad.append((p, err / max(scale, 1e-300), gg, g64))
+        n_cmp += 1
+    assert not bad, bad[:5]
+    print(f"compared gradients of {n_cmp} of {ps.n} programs")
+    assert n_cmp > 0.5 * ps.n
+
+
+def test_gradient_against_finite_differences_full_size():
+    """The differentiation workload at full size (N=4096, M=100000); FP64
+    central differences of the oracle on a 64-program subset."""
+    w = wl.config_differentiation()
+    ps, data = w.programs, w.data
+    f, g, st = _grad(ps, data)
+    assert np.all(st == 0)
+    rng = np.random.default_rng(2)
+    sub = sorted(rng.choice(ps.n, size=64, replace=False).tolist())
+    well = _well_conditioned(ps, data, sub)
+    n = 0
+    for j, p in enumerate(sub):
+        if not well[j]:
+            continue
+        t, c = ps.program(p)
+        F, g64 = og.mse_and_grad(t, c, data.X, data.y)
+        if not (math.isfinite(F) and np.all(np.isfinite(g64))):
+            continue
+        # component-wise stability, a tenth of the component-wise FD gate
+        stable = _spread(t, c, data, g64) <= 1e-4 * np.abs(g64)
+        fd1, ok1 = og.central_fd(t, c, data.X, data.y, rel_step=1e-5)
+        fd2, ok2 = og.central_fd(t, c, data.X, data.y, rel_step=1e-6)
+        o = int(ps.const_offset[p])
+        for k in np.nonzero(ok1 & ok2 & stable)[0]:
+            if not (np.isfinite(fd1[k]) and np.isfinite(fd2[k])):
+                continue
+            if abs(fd1[k] - fd2[k]) > 1e-4 * max(abs(fd2[k]), 1e-12):
+                continue  # differences not converged
+            tol = 1e-3 * abs(fd2[k]) + 1e-6 * max(1.0, abs(f[p]))
+            assert abs(float(g[o + k]) - fd2[k]) <= tol, (p, k, g[o + k], fd2[k])
+            n += 1
+    print(f"checked {n} constants against central differences")
+    assert n >= 30
+
+
+def test_forward_equals_plain_evaluation():
+    api = _api()
+    w = wl.config_differentiation(N=512, M=20000)
+    f, g, st = _grad(w.programs, w.data)
+    P = api.DevicePrograms.from_programset(w.programs)
+    X = torch.from_numpy(w.data.X).cuda()
+    y = torch.from_numpy(w.data.y).cuda()
+    f2 = api.evaluate(P, X, y, "mse").cpu().numpy()
+    fin = np.isfinite(f2)
+    assert np.array_equal(np.isnan(f), np.isnan(f2))
+    assert np.all(np.abs(f[fin] - f2[fin]) <= 1e-12 * np.abs(f2[fin]) + 1e-300)
+
+
+def test_long_tapes_many_constants_and_limits():
+    rng = np.random.default_rng(9)
+    data = wl.make_dataset(19, 2500, 3, x_range=(1.0, 3.0), target_len=8)
+    progs = []
+    for L in (70, 150, 255):           # LDS tape (decoded words > 64)
+        t, _ = wl.random_program(rng, L, 3, allow_const=False)
+        progs.append(wl.place_constants(rng, t, 5))
+    for L in (30, 60):                 # more constant slots than lane accumulators
+        t, _ = wl.random_program(rng, L, 3, allow_const=False)
+        progs.append(wl.place_constants(rng, t, 14))
+    t, _ = wl.random_program(rng, 700, 3, allow_const=False)   # > 256 decoded words
+    progs.append(wl.place_constants(rng, t, 3))
+    ps = wl.pack_programs(progs)
+    f, g, st = _grad(ps, data)
+    assert list(st[:5]) == [0] * 5
+    assert st[5] == interp.ST_TOO_LONG and math.isnan(f[5])
+    well = _well_conditioned(ps, data, list(range(5)))
+    for p in range(5):
+        t, c = ps.program(p)
+        F, g64 = og.mse_and_grad(t, c, data.X, data.y)
+        o, cc = int(ps.const_offset[p]), int(ps.const_count[p])
+        if not (math.isfinite(F) and np.all(np.isfinite(g64))):
+            continue
+        if well[p]:
+            assert abs(f[p] - F) <= 1e-5 * abs(F) + gates.atol(ofit.MSE, data.y)
+        stable, scale = _stable_components(t, c, data, g64)
+        err = np.abs(g[o:o + cc] - g64)[stable]
+        assert np.all(err <= GRAD_RTOL * scale + 1e-7), (p, g[o:o + cc], g64, stable)
+
+
+def test_autograd_function_and_adam():
+    from paper_2603_12292_amd import autograd as ag
+    api = _api()
+    w = wl.config_differentiation(N=256, M=5000)
+    P = api.DevicePrograms.from_programset(w.programs)
+    X = torch.from_numpy(w.data.X).cuda()
+    y = torch.from_numpy(w.data.y).cuda()
+    owner = ag.const_owner(P)
+    consts = P.consts.clone().requires_grad_(True)
+    fit = ag.EvalGrad.apply(consts, P, X, y, owner)
+    go = torch.randn_like(fit)
+    fit.backward(go)
+    _, g = api.evaluate_grad(P, X, y)
+    expect = go[owner] * g.double()
+    got = consts.grad.double()
+    fin = torch.isfinite(expect)
+    assert torch.allclose(got[fin], expect[fin], rtol=1e-6, atol=0)
+    res = ag.tune_constants(P, X, y, steps=20, lr=0.05, record=True)
+    before, after = res.fitness_before.cpu().numpy(), res.fitness_after.cpu().numpy()
+    ok = np.isfinite(before) & np.isfinite(after)
+    ratio = after[ok] / np.maximum(before[ok], 1e-300)
+    # gradient steps on each program's own constants: most programs improve
+    assert np.median(ratio) < 1.0
+    assert np.mean(ratio < 1.0) > 0.6

@@ -126,3 +126,28 @@ def test_against_central_differences():
             assert abs(g[j] - fd2[j]) <= tol, (toks, j, g[j], fd1[j], fd2[j])
             n += 1
     assert n > 40
+
+
+def test_fp32_modes_are_close_for_benign_programs():
+    """The fp32-emulating gradient modes differ from binary64 by rounding only."""
+    d = _data(M=300)
+    rng = np.random.default_rng(44)
+    n = 0
+    for _ in range(60):
+        toks, _ = wl.random_program(rng, int(rng.integers(4, 20)), 3, allow_const=False)
+        toks, consts = wl.place_constants(rng, toks, int(rng.integers(1, 4)))
+        F, g = og.mse_and_grad(toks, consts, d.X, d.y)
+        if not (math.isfinite(F) and np.all(np.isfinite(g))) or np.max(np.abs(g)) == 0:
+            continue
+        for mode, seed in (("o32e", 0), ("o32p", 1)):
+            F32, g32 = og.mse_and_grad(toks, consts, d.X, d.y, mode, seed)
+            if np.all(np.isfinite(g32)):
+                # rounding-level agreement for most programs; never wild for all
+                n += np.max(np.abs(g32 - g)) <= 1e-4 * np.max(np.abs(g))
+    assert n >= 60
+    # exactly representable case: c0 * x0 with small integers is exact in fp32
+    X = np.array([[1.0], [2.0], [3.0]], dtype=np.float32)
+    y = np.array([1.0, 5.0, 2.0], dtype=np.float32)
+    F, g = og.mse_and_grad([10, 9, 2], [2.0], X, y)
+    F32, g32 = og.mse_and_grad([10, 9, 2], [2.0], X, y, "o32e")
+    assert F == F32 and g[0] == pytest.approx(g32[0], rel=1e-7)
