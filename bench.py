@@ -66,8 +66,38 @@ def cpu_baseline(w, kind_id, budget_programs: int):
                              w.data.X, w.data.y, kind_id, "o64", subset=sub, processes=cores)
     dt = time.perf_counter() - t0
     return {"value": nodes * w.data.M / dt / 1e9, "unit": "GPop/s", "cores": cores, "kind": "oracle",
-            "sample": f"{len(sub)} of {ps.n} programs (every {step}th), all {w.data.M} cases, "
+            "sample": f"{len(sub)} of {ps.n} programs (every {step}), all {w.data.M} cases, "
                       f"correlation fitness, float64 oracle, {dt:.1f} s wall"}
+
+
+def adjoint_bench(steps: int, warmup: int):
+    """fwd+adjoint GPop/s on the differentiation workload (N=4096, 1..8
+    constants, L~U{8..64}, D=5, M=100000), beside the plain MSE evaluation of
+    the same population; GPop/s counts each program node once per case."""
+    import torch
+    from paper_2603_12292_amd import api
+    from paper_2603_12292_amd import workloads as wl
+    w = wl.config_differentiation()
+    progs = api.DevicePrograms.from_programset(w.programs, "cuda:0")
+    X = torch.from_numpy(w.data.X).cuda()
+    y = torch.from_numpy(w.data.y).cuda()
+    nc = w.programs.node_count() * w.data.M
+
+    def rate(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return nc * steps / (time.perf_counter() - t0) / 1e9
+
+    fwd = rate(lambda: api.evaluate(progs, X, y, "mse"))
+    both = rate(lambda: api.evaluate_grad(progs, X, y, "mse"))
+    return {"workload": "adjoint: N=4096, L~U{8..64}, 1..8 constants, D=5, M=100000, MSE",
+            "fwd_gpops": round(fwd, 2), "fwd_adjoint_gpops": round(both, 2),
+            "adjoint_cost_vs_fwd": round(fwd / both, 3)}
 
 
 def main():
@@ -76,7 +106,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-programs", type=int, default=512)
+    ap.add_argument("--cpu-programs", type=int, default=4096)
+    ap.add_argument("--no-adjoint", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (one process, one device)",
@@ -140,6 +171,8 @@ def main():
                      "kernel_ms": round(k_avg_s * 1e3, 4), "alg_ops_per_launch": alg_ops,
                      "kernel_gpops": round(nodes * M / k_avg_s / 1e9, 2)},
     }
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_bench(args.steps, args.warmup)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, 1, args.cpu_programs)
     print(json.dumps(out), flush=True)
