@@ -130,7 +130,8 @@ void beagle_ctx_destroy(beagle_ctx* ctx);
 
 /* Kernel timing (instrumentation).  While enabled, every beagle_eval call
  * records a pair of HIP events on its stream around its main evaluation
- * kernel (the fast-path interpreter launch).  beagle_ctx_kernel_time waits
+ * kernel (the fast-path interpreter launch), and every beagle_eval_batched
+ * call around its whole graph launch.  beagle_ctx_kernel_time waits
  * for the recorded events and returns the summed elapsed time and the
  * number of launches since timing was last enabled.  Enabling resets. */
 beagle_status beagle_ctx_enable_timing(beagle_ctx* ctx, int enable);
@@ -166,6 +167,47 @@ beagle_status beagle_predict(beagle_ctx* ctx, const beagle_programs* progs, cons
 beagle_status beagle_eval_grad(beagle_ctx* ctx, const beagle_programs* progs, const beagle_dataset* data,
                                int kind, double* fitness, float* grad_consts, int8_t* status,
                                beagle_stream stream);
+
+/* Tile-width policies of the evaluator (beagle_ctx_set_tuning). */
+typedef enum { BEAGLE_TUNE_AUTO = 0, BEAGLE_TUNE_WIDE = 1, BEAGLE_TUNE_NARROW = 2 } beagle_tuning;
+
+/* How many fitness cases each lane carries through the interpreter for the
+ * common programs (stack of at most 4 values): 8 (BEAGLE_TUNE_WIDE, used
+ * only where D <= 8) or 4 (BEAGLE_TUNE_NARROW).  BEAGLE_TUNE_AUTO, the
+ * default, times both the first time an evaluation meets a problem-shape
+ * bucket (fitness kind, D, log2 M, log2 of the mean program length) -- that
+ * call synchronises the device -- and keeps the faster in the context.  When
+ * the environment variable BEAGLE_AUTOTUNE_CACHE names a file, buckets are
+ * read from it when a context is created and every new measurement is
+ * written back to it.  The choice changes no result bit: with either width a
+ * lane adds the same cases in the same order.  Unknown policy:
+ * BEAGLE_E_INVALID_ARG. */
+beagle_status beagle_ctx_set_tuning(beagle_ctx* ctx, int policy);
+
+/* Ragged batching: n_problems independent populations, each on its own
+ * dataset (its own M and D), evaluated by one launch sequence whose work
+ * lists span every problem (the paper batches the population onto the GPU,
+ * section 2.1.2, and runs many benchmark problems, section 2.4).
+ *   progs, data  HOST arrays of n_problems descriptors (device pointers inside)
+ *   fitness      HOST array of n_problems device pointers,
+ *                double[progs[q].n_programs] out
+ *   status       HOST array of n_problems device pointers (int8[n_programs]
+ *                out), or NULL; entries may be NULL
+ * The context captures the launch sequence in a HIP graph the first time it
+ * meets a problem table (every pointer and size above, the tile widths and
+ * the workspace) and replays that graph while the table is unchanged; the
+ * table itself is copied to the device before every launch.  Results are
+ * bit-identical to beagle_eval on each problem alone.  Problems with no
+ * programs are skipped.  The workspace must hold every problem at once
+ * (BEAGLE_E_NOMEM beyond the context cap: no slicing here).  Correlation
+ * fitness needs M >= 2 in every problem.  n_problems <= 65535. */
+beagle_status beagle_eval_batched(beagle_ctx* ctx, const beagle_programs* progs, const beagle_dataset* data,
+                                  int32_t n_problems, int kind, double* const* fitness, int8_t* const* status,
+                                  beagle_stream stream);
+
+/* Graph cache counters of beagle_eval_batched (instrumentation): graphs
+ * captured and graph launches since the context was created. */
+beagle_status beagle_ctx_graph_stats(beagle_ctx* ctx, int64_t* captures, int64_t* replays);
 
 /* Parameters of initialisation and of one generation step. */
 typedef struct {

@@ -24,6 +24,9 @@ E_UNSUPPORTED = -4
 
 FIT_MSE = 0
 FIT_CORR = 1
+TUNE_AUTO = 0
+TUNE_WIDE = 1
+TUNE_NARROW = 2
 
 # per-program status codes
 PROG_STATUS = {0: "ok", 1: "empty", 2: "bad_opcode", 3: "underflow", 4: "bad_final_depth",
@@ -54,7 +57,11 @@ SIGNATURES = [
     ("beagle_ctx_destroy", None, [c_void_p]),
     ("beagle_ctx_enable_timing", c_int, [c_void_p, c_int]),
     ("beagle_ctx_kernel_time", c_int, [c_void_p, POINTER(c_double), POINTER(c_int64)]),
+    ("beagle_ctx_set_tuning", c_int, [c_void_p, c_int]),
+    ("beagle_ctx_graph_stats", c_int, [c_void_p, POINTER(c_int64), POINTER(c_int64)]),
     ("beagle_eval", c_int, [c_void_p, POINTER(Programs), POINTER(Dataset), c_int, c_void_p, c_void_p, c_void_p]),
+    ("beagle_eval_batched", c_int, [c_void_p, POINTER(Programs), POINTER(Dataset), c_int32, c_int,
+                                    POINTER(c_void_p), POINTER(c_void_p), c_void_p]),
     ("beagle_eval_workspace_size", c_int, [POINTER(Programs), POINTER(Dataset), c_int, POINTER(c_size_t)]),
     ("beagle_predict", c_int, [c_void_p, POINTER(Programs), POINTER(Dataset), c_void_p, c_void_p, c_void_p]),
     ("beagle_eval_grad", c_int, [c_void_p, POINTER(Programs), POINTER(Dataset), c_int, c_void_p, c_void_p,
@@ -66,6 +73,7 @@ SIGNATURES = [
 ]
 
 _lib = None
+HEADER = os.path.join(os.path.dirname(HERE), "include", "beagle.h")
 
 
 def load():
@@ -80,7 +88,7 @@ def load():
     for name, res, args in SIGNATURES:
         fn = getattr(lib, name, None)
         if fn is None:
-            continue
+            raise ImportError(f"{LIB_PATH} does not export {name}: rebuild it")
         fn.restype = res
         fn.argtypes = args
     _lib = lib
@@ -90,7 +98,6 @@ def load():
 def declared_symbols():
     """Names of the functions include/beagle.h declares (parsed from the header)."""
     import re
-    hdr = os.path.join(os.path.dirname(HERE), "include", "beagle.h")
-    with open(hdr) as f:
+    with open(HEADER) as f:
         text = f.read()
     return sorted(set(re.findall(r"\b(beagle_[a-z_]+)\s*\(", text)))

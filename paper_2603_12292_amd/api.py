@@ -60,6 +60,19 @@ class Context:
         _check(self.lib.beagle_ctx_kernel_time(self.handle, ctypes.byref(ms), ctypes.byref(n)))
         return float(ms.value), int(n.value)
 
+    def set_tuning(self, policy: str = "auto"):
+        """Tile-width policy: "auto" (measure once per shape bucket), "wide" or "narrow"."""
+        names = {"auto": _lib.TUNE_AUTO, "wide": _lib.TUNE_WIDE, "narrow": _lib.TUNE_NARROW}
+        code = names.get(policy, -1) if isinstance(policy, str) else int(policy)
+        _check(self.lib.beagle_ctx_set_tuning(self.handle, code))
+
+    def graph_stats(self):
+        """(graphs captured, graph launches) of batched evaluation."""
+        a = ctypes.c_int64()
+        b = ctypes.c_int64()
+        _check(self.lib.beagle_ctx_graph_stats(self.handle, ctypes.byref(a), ctypes.byref(b)))
+        return int(a.value), int(b.value)
+
     def close(self):
         if self.handle:
             self.lib.beagle_ctx_destroy(self.handle)
@@ -182,6 +195,39 @@ def evaluate(progs: DevicePrograms, X: torch.Tensor, y: torch.Tensor, kind="mse"
     _check(c.lib.beagle_eval(c.handle, ctypes.byref(ps), ctypes.byref(ds), _kind(kind), fit.data_ptr(),
                              st.data_ptr() if st is not None else None, _stream(dev)))
     return (fit, st) if with_status else fit
+
+
+def evaluate_batched(problems, kind="mse", *, with_status: bool = False, ctx: Optional[Context] = None,
+                     out=None):
+    """Fitness of several independent problems in one batched launch --
+    beagle_eval_batched.  problems: sequence of (DevicePrograms, X, y) on one
+    device.  Returns a list of float64 [N_q] tensors (and of int8 status
+    tensors).  `out`, if given, is a list of preallocated fitness tensors
+    (reusing them lets repeated calls replay the same captured graph)."""
+    problems = list(problems)
+    n = len(problems)
+    if n == 0:
+        return ([], []) if with_status else []
+    dev = problems[0][0].device
+    c = _ctx_for(dev, ctx)
+    P = (_lib.Programs * n)()
+    D = (_lib.Dataset * n)()
+    fits = []
+    sts = []
+    for q, (pr, X, y) in enumerate(problems):
+        if pr.device != dev:
+            raise ValueError("every problem must be on the same device")
+        P[q] = pr.struct()
+        D[q] = _dataset(X, y, dev)
+        f = out[q] if out is not None else torch.empty(pr.n, dtype=torch.float64, device=dev)
+        if f.dtype != torch.float64 or f.numel() != pr.n or f.device != dev or not f.is_contiguous():
+            raise ValueError(f"out[{q}] must be a contiguous float64 tensor of {pr.n} elements on {dev}")
+        fits.append(f)
+        sts.append(torch.empty(pr.n, dtype=torch.int8, device=dev) if with_status else None)
+    fptr = (ctypes.c_void_p * n)(*[f.data_ptr() for f in fits])
+    sptr = (ctypes.c_void_p * n)(*[s_.data_ptr() for s_ in sts]) if with_status else None
+    _check(c.lib.beagle_eval_batched(c.handle, P, D, n, _kind(kind), fptr, sptr, _stream(dev)))
+    return (fits, sts) if with_status else fits
 
 
 def eval_workspace_bytes(progs: DevicePrograms, X: torch.Tensor, y: torch.Tensor, kind="mse") -> int:

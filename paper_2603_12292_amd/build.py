@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbeagle.so")
-SOURCES = ["api.cpp", "prepare.hip", "eval.hip", "gen.hip", "grad.hip"]
+SOURCES = ["api.cpp", "batch.cpp", "tune.cpp", "prepare.hip", "eval.hip", "gen.hip", "grad.hip"]
 ARCH = "gfx950"
 
 FLAGS = [
@@ -51,7 +51,7 @@ def build(verbose: bool = False, out: str = LIB, defines=(), extra=()) -> str:
     variant build (tile parameters) placed elsewhere."""
     build_dir = BUILD if out == LIB else os.path.splitext(out)[0] + "_build"
     os.makedirs(build_dir, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(lambda s: _compile(s, build_dir, defines, extra), SOURCES))
     LIBOUT = out
     tmp = LIBOUT + ".tmp"

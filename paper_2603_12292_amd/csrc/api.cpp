@@ -13,20 +13,13 @@
 #include "beagle_device.h"
 #include "gen.h"
 #include "grad.h"
+#include "host.h"
 #include "kernels.h"
 
-struct beagle_ctx {
-  int device = 0;
-  size_t cap = 0;       // 0 = unlimited
-  char* ws = nullptr;   // device workspace
-  size_t ws_size = 0;
-  bool timing = false;  // record events around the main evaluation kernel
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
-};
+namespace bgl {
+namespace host {
 
-namespace {
-
-thread_local std::string g_error;
+static thread_local std::string g_error;
 
 beagle_status fail(beagle_status s, const std::string& msg) {
   g_error = msg;
@@ -37,30 +30,9 @@ beagle_status hip_fail(hipError_t e, const char* where) {
   return fail(BEAGLE_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
 }
 
-// Makes ctx->device current for the duration of a call.
-struct DeviceGuard {
-  int prev = -1;
-  hipError_t err = hipSuccess;
-  explicit DeviceGuard(int dev) {
-    err = hipGetDevice(&prev);
-    if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
-  }
-  ~DeviceGuard() {
-    int cur = -1;
-    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-  }
-};
+void clear_error() { clear_error(); }
 
-// Bump allocator over the context workspace (256-byte aligned pieces).
-struct Carve {
-  size_t used = 0;
-  template <class T>
-  size_t take(size_t count) {
-    const size_t at = (used + 255) & ~size_t(255);
-    used = at + count * sizeof(T);
-    return at;
-  }
-};
+const char* last_error() { return g_error.c_str(); }
 
 beagle_status reserve(beagle_ctx* ctx, size_t bytes) {
   if (ctx->cap && bytes > ctx->cap)
@@ -70,6 +42,7 @@ beagle_status reserve(beagle_ctx* ctx, size_t bytes) {
   // the old workspace may still be in use by queued work on any stream
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  release_graphs(ctx);  // they point into the old workspace
   if (ctx->ws) (void)hipFree(ctx->ws);
   ctx->ws = nullptr;
   ctx->ws_size = 0;
@@ -124,6 +97,22 @@ void choose_chunks(int64_t M, int64_t N, int64_t* chunk, int32_t* n_chunks) {
   *n_chunks = int32_t((M + ch - 1) / ch);
 }
 
+static __global__ void k_zero_i32(int32_t* p, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+void zero_i32(int32_t* p, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_i32, dim3(uint32_t((n + 255) / 256)), dim3(256), 0, s, p, n);
+}
+
+}  // namespace host
+}  // namespace bgl
+
+namespace {
+
+using namespace bgl::host;
+
 // The pieces of workspace one evaluation uses.
 struct EvalLayout {
   size_t code, aux, cval, s_stack, s_start, s_need, meta, class_count, class_list, len_list, work, Xt, yp, stats, part,
@@ -149,7 +138,7 @@ EvalLayout eval_layout(const beagle_programs* P, const beagle_dataset* d, int n_
   L.class_list = c.take<int32_t>(size_t(bgl::N_CLASSES) * N);
   L.len_list = c.take<int32_t>(size_t(2) * N);
   L.work = c.take<unsigned long long>(bgl::N_CLASSES);
-  L.Mp = round_up(d->M, bgl::CASES_PER_WAVE_ITER);
+  L.Mp = round_up(d->M, bgl::CASES_PER_BLOCK_ITER);
   L.Xt = c.take<float>(size_t(d->D) * L.Mp);
   L.yp = c.take<float>(L.Mp);
   L.stats = c.take<double>(4);
@@ -163,17 +152,12 @@ EvalLayout eval_layout(const beagle_programs* P, const beagle_dataset* d, int n_
   return L;
 }
 
-__global__ void k_zero_i32(int32_t* p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0;
-}
-
 // Validation + decoding of the programs and staging of the cases (shared by
 // evaluation, prediction and the gradient).
 beagle_status prepare(beagle_ctx* ctx, const beagle_programs* P, const beagle_dataset* d, const EvalLayout& L,
                       int8_t* status, hipStream_t s, int32_t max_words = bgl::MAX_LEN) {
   char* ws = ctx->ws;
-  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, reinterpret_cast<int32_t*>(ws + L.class_count), 64);
+  zero_i32(reinterpret_cast<int32_t*>(ws + L.class_count), 64, s);
   bgl::PrepareArgs pa;
   pa.tokens = P->tokens;
   pa.n_tokens = P->n_tokens;
@@ -237,13 +221,24 @@ beagle_status launch_values(beagle_ctx* ctx, const beagle_programs* P, const bea
   return BEAGLE_OK;
 }
 
+// One evaluation slice for the tile-width tuner.
+struct TuneSlice {
+  int kind;
+  bgl::EvalArgs ea;
+};
+
+hipError_t run_slice(void* user, int kv, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  const TuneSlice* t = static_cast<const TuneSlice*>(user);
+  return bgl::launch_eval(t->kind, kv, t->ea, s, ev0, ev1);
+}
+
 }  // namespace
 
 extern "C" {
 
 int beagle_abi_version(void) { return BEAGLE_ABI_VERSION; }
 
-const char* beagle_last_error(void) { return g_error.c_str(); }
+const char* beagle_last_error(void) { return bgl::host::last_error(); }
 
 beagle_status beagle_ctx_create(beagle_ctx** out, int device, size_t max_workspace_bytes) {
   if (!out) return fail(BEAGLE_E_INVALID_ARG, "out is NULL");
@@ -255,8 +250,9 @@ beagle_status beagle_ctx_create(beagle_ctx** out, int device, size_t max_workspa
   beagle_ctx* c = new beagle_ctx;
   c->device = device;
   c->cap = max_workspace_bytes;
+  load_tune_file(c);
   *out = c;
-  g_error.clear();
+  clear_error();
   return BEAGLE_OK;
 }
 
@@ -300,13 +296,20 @@ void beagle_ctx_destroy(beagle_ctx* ctx) {
     DeviceGuard g(ctx->device);
     (void)hipDeviceSynchronize();
     release_events(ctx);
-  }
-  if (ctx->ws) {
-    DeviceGuard g(ctx->device);
-    (void)hipDeviceSynchronize();
-    (void)hipFree(ctx->ws);
+    release_graphs(ctx);
+    if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
+    if (ctx->table_copied) (void)hipEventDestroy(ctx->table_copied);
+    if (ctx->ws) (void)hipFree(ctx->ws);
   }
   delete ctx;
+}
+
+beagle_status beagle_ctx_set_tuning(beagle_ctx* ctx, int policy) {
+  if (!ctx) return fail(BEAGLE_E_INVALID_ARG, "ctx is NULL");
+  if (policy != BEAGLE_TUNE_AUTO && policy != BEAGLE_TUNE_WIDE && policy != BEAGLE_TUNE_NARROW)
+    return fail(BEAGLE_E_INVALID_ARG, "unknown tuning policy");
+  ctx->tuning = policy;
+  return BEAGLE_OK;
 }
 
 beagle_status beagle_eval(beagle_ctx* ctx, const beagle_programs* progs, const beagle_dataset* data, int kind,
@@ -342,8 +345,7 @@ beagle_status beagle_eval(beagle_ctx* ctx, const beagle_programs* progs, const b
     st = launch_values(ctx, progs, data, L, 1, nullptr, 1, s);
     if (st != BEAGLE_OK) return st;
   }
-  for (int32_t p0 = 0; p0 < progs->n_programs; p0 += slice) {
-    const int32_t np = std::min(slice, progs->n_programs - p0);
+  auto slice_args = [&](int32_t p0, int32_t np) {
     bgl::EvalArgs ea;
     ea.code = reinterpret_cast<const uint32_t*>(ws + L.code);
     ea.cval = reinterpret_cast<const float*>(ws + L.cval);
@@ -364,13 +366,25 @@ beagle_status beagle_eval(beagle_ctx* ctx, const beagle_programs* progs, const b
     ea.work = reinterpret_cast<unsigned long long*>(ws + L.work);
     ea.n_total = progs->n_programs;
     ea.prog_begin = p0;
+    return ea;
+  };
+  int kv = 0;
+  {
+    TuneSlice ts{kind, slice_args(0, std::min(slice, progs->n_programs))};
+    st = tile_variant(ctx, kind, data->D, data->M, double(progs->n_tokens) / progs->n_programs, s, run_slice, &ts,
+                      &kv);
+    if (st != BEAGLE_OK) return st;
+  }
+  for (int32_t p0 = 0; p0 < progs->n_programs; p0 += slice) {
+    const int32_t np = std::min(slice, progs->n_programs - p0);
+    const bgl::EvalArgs ea = slice_args(p0, np);
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (ctx->timing) {
       if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
         return fail(BEAGLE_E_HIP, "hipEventCreate");
       ctx->events.emplace_back(ev0, ev1);
     }
-    hipError_t e = bgl::launch_eval(kind, ea, s, ev0, ev1);
+    hipError_t e = bgl::launch_eval(kind, kv, ea, s, ev0, ev1);
     if (e != hipSuccess) return hip_fail(e, "eval launch");
     bgl::FinalizeArgs fa;
     fa.meta = ea.meta;
@@ -385,7 +399,7 @@ beagle_status beagle_eval(beagle_ctx* ctx, const beagle_programs* progs, const b
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "finalize launch");
   }
-  g_error.clear();
+  clear_error();
   return BEAGLE_OK;
 }
 
@@ -422,7 +436,7 @@ beagle_status beagle_predict(beagle_ctx* ctx, const beagle_programs* progs, cons
   if (st != BEAGLE_OK) return st;
   st = launch_values(ctx, progs, data, L, data->M, yhat, 0, s);
   if (st != BEAGLE_OK) return st;
-  g_error.clear();
+  clear_error();
   return BEAGLE_OK;
 }
 
@@ -475,7 +489,7 @@ beagle_status beagle_init_population(beagle_ctx* ctx, const beagle_gen_params* p
                      reinterpret_cast<hipStream_t>(stream), a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "init launch");
-  g_error.clear();
+  clear_error();
   return BEAGLE_OK;
 }
 
@@ -529,7 +543,7 @@ beagle_status beagle_generation(beagle_ctx* ctx, const beagle_programs* parents,
                      a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "generation launch");
-  g_error.clear();
+  clear_error();
   return BEAGLE_OK;
 }
 
@@ -555,7 +569,7 @@ beagle_status beagle_eval_grad(beagle_ctx* ctx, const beagle_programs* progs, co
   if (st != BEAGLE_OK) return st;
   char* ws = ctx->ws;
   unsigned long long* work = reinterpret_cast<unsigned long long*>(ws + L.work);
-  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, reinterpret_cast<int32_t*>(work), 2 * bgl::N_CLASSES);
+  zero_i32(reinterpret_cast<int32_t*>(work), 2 * bgl::N_CLASSES, s);
   bgl::GradArgs ga;
   ga.code = reinterpret_cast<const uint32_t*>(ws + L.code);
   ga.aux = reinterpret_cast<const uint32_t*>(ws + L.aux);
@@ -595,7 +609,7 @@ beagle_status beagle_eval_grad(beagle_ctx* ctx, const beagle_programs* progs, co
   hipLaunchKernelGGL(bgl::k_grad_finalize, dim3((progs->n_programs + 255) / 256), dim3(256), 0, s, fa);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "gradient finalize launch");
-  g_error.clear();
+  clear_error();
   return BEAGLE_OK;
 }
 

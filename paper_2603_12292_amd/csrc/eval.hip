@@ -221,16 +221,24 @@ __device__ __forceinline__ void eval_block(const EvalArgs& a, int p, int c, doub
   constexpr int G = (K + 3) / 4;
   float* xw = xtile + wave * (a.D * G * 256);
   float* xl = xw + lane * 4;
-  for (int64_t base = c0 + int64_t(wave) * (64 * K); base < c1; base += int64_t(EVAL_WAVES) * 64 * K) {
+  // Case order.  A sub-tile is 64 lanes x min(K, 4) cases (case = base +
+  // k * 64 + lane); the block's waves take consecutive sub-tiles, and a lane
+  // with K = 8 holds two sub-tiles EVAL_WAVES sub-tiles apart.  So each lane
+  // adds exactly the cases it would add with K = 4, in the same order: the
+  // tile width of class 0 changes no result bit.
+  constexpr int SUB = K < 4 ? K : 4;
+  constexpr int SPAN = EVAL_WAVES * 64 * SUB;  // cases of one sub-tile row of the block
+  constexpr int NSUB = K / SUB;
+  for (int64_t base = c0 + int64_t(wave) * (64 * SUB); base < c1; base += int64_t(NSUB) * SPAN) {
     float yk[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) yk[k] = a.yp[base + k * 64 + lane];
-    // coalesced global reads (case = base + k*64 + lane), one LDS write per
-    // variable; the wave's tile is private to it, so a wave barrier suffices
+    for (int k = 0; k < K; ++k) yk[k] = a.yp[base + (k / SUB) * SPAN + (k % SUB) * 64 + lane];
+    // coalesced global reads, one LDS write per variable; the wave's tile is
+    // private to it, so a wave barrier suffices
     for (int d = 0; d < a.D; ++d) {
       XRow<K> xv;
 #pragma unroll
-      for (int k = 0; k < K; ++k) xv.v[k] = a.Xt[int64_t(d) * a.Mp + base + k * 64 + lane];
+      for (int k = 0; k < K; ++k) xv.v[k] = a.Xt[int64_t(d) * a.Mp + base + (k / SUB) * SPAN + (k % SUB) * 64 + lane];
       __builtin_amdgcn_wave_barrier();
       store_row<K>(xl, d, xv);
     }
@@ -240,7 +248,7 @@ __device__ __forceinline__ void eval_block(const EvalArgs& a, int p, int c, doub
     interpret<K, S>(vc0, vv0, vc1, vv1, code, cval, L, lane, xl, top);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const bool valid = base + k * 64 + lane < a.M;
+      const bool valid = base + (k / SUB) * SPAN + (k % SUB) * 64 + lane < a.M;
       if constexpr (KIND == BEAGLE_FIT_MSE) {
         const double d = double(top[k]) - double(yk[k]);
         s0 += valid ? d * d : 0.0;
@@ -300,14 +308,70 @@ __global__ void __launch_bounds__(256) k_eval_class(EvalArgs a) {
   }
 }
 
+// One work list of a batched evaluation: the same persistent scheme over the
+// (problem, chunk, program) items of every problem of the table, problem by
+// problem in table order and chunk-major within a problem.
+template <int KIND, int CLS, int KV>
+__global__ void __launch_bounds__(256) k_eval_batch(BatchArgs b) {
+  constexpr int S = class_stack(CLS);
+  constexpr int K = class_k(CLS, KV);
+  constexpr int V = CLS == 0 ? KV : CLS + 1;
+  __shared__ double red[12];
+  __shared__ long long s_item;
+  extern __shared__ float xtile[];
+  const int64_t* off = b.item_off + int64_t(V) * (b.n_problems + 1);
+  const int64_t items = off[b.n_problems];
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (long long)atomicAdd(b.work + V, 1ull);
+    __syncthreads();
+    const uint64_t raw = uint64_t(s_item);
+    __syncthreads();
+    const int64_t it = int64_t((uint64_t(uint32_t(__builtin_amdgcn_readfirstlane(int(raw >> 32)))) << 32) |
+                               uint32_t(__builtin_amdgcn_readfirstlane(int(raw))));
+    if (it >= items) break;  // uniform across the workgroup
+    int lo = 0, hi = b.n_problems;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (off[mid] <= it)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    const BatchProblem& P = b.table[lo];
+    const int32_t count = P.prep.class_count[CLS];
+    const int64_t local = it - off[lo];
+    const int c = int(local / count);
+    const int p = P.prep.class_list[int64_t(CLS) * P.prep.n_programs + local % count];
+    EvalArgs a;
+    a.code = P.prep.code;
+    a.cval = P.prep.cval;
+    a.tok_offset = P.prep.tok_offset;
+    a.meta = P.prep.meta;
+    a.Xt = P.Xt;
+    a.yp = P.yp;
+    a.M = P.M;
+    a.Mp = P.Mp;
+    a.D = P.prep.D;
+    a.n_programs = P.prep.n_programs;
+    a.n_chunks = P.n_chunks;
+    a.chunk = P.chunk;
+    a.part = P.part;
+    a.stats = P.stats;
+    a.class_count = nullptr;
+    a.class_list = nullptr;
+    a.work = nullptr;
+    a.n_total = P.prep.n_programs;
+    a.prog_begin = 0;
+    eval_block<KIND, K, S>(a, p, c, red, xtile);
+  }
+}
+
 // Per-case outputs of every program on cases [0, m): one wave per
 // (program, 64 cases).  In shift mode (m = 1) it stores the output at case
 // 0 as the program's shift for correlation sums.
-__global__ void __launch_bounds__(64) k_values(ValuesArgs a) {
-  __shared__ float xl_all[MAX_D * 256];
-  const int p = blockIdx.x;
+__device__ static void values_program(const ValuesArgs& a, int p, int64_t tile, float* xl_all) {
   const int lane = threadIdx.x;
-  const int64_t i = int64_t(blockIdx.y) * 64 + lane;
+  const int64_t i = tile * 64 + lane;
   const ProgMeta m = a.meta[p];
   if (m.status != BEAGLE_PROG_OK) {
     if (!a.shift_mode && i < a.m) a.out[int64_t(p) * a.m + i] = __int_as_float(0x7FC00000);
@@ -329,16 +393,40 @@ __global__ void __launch_bounds__(64) k_values(ValuesArgs a) {
   float top[1];
   interpret<1, MAX_STACK>(vc0, vv0, vc1, vv1, code, cval, L, lane, xl, top);
   if (a.shift_mode) {
-    if (blockIdx.y == 0 && lane == 0) a.meta[p].shift = top[0];
+    if (tile == 0 && lane == 0) a.meta[p].shift = top[0];
   } else if (i < a.m) {
     a.out[int64_t(p) * a.m + i] = top[0];
   }
 }
 
+__global__ void __launch_bounds__(64) k_values(ValuesArgs a) {
+  __shared__ float xl_all[MAX_D * 256];
+  values_program(a, blockIdx.x, blockIdx.y, xl_all);
+}
+
+// Correlation shifts of every program of the table (one wave per program).
+__global__ void __launch_bounds__(64) k_values_batch(BatchArgs b) {
+  __shared__ float xl_all[MAX_D * 256];
+  const int64_t g = blockIdx.x;
+  const int q = batch_find(b, g, [](const BatchProblem& t) { return t.prog_begin; });
+  const BatchProblem& P = b.table[q];
+  ValuesArgs a;
+  a.code = P.prep.code;
+  a.cval = P.prep.cval;
+  a.tok_offset = P.prep.tok_offset;
+  a.meta = P.prep.meta;
+  a.Xt = P.Xt;
+  a.Mp = P.Mp;
+  a.m = 1;
+  a.D = P.prep.D;
+  a.n_programs = P.prep.n_programs;
+  a.out = nullptr;
+  a.shift_mode = 1;
+  values_program(a, int(g - P.prog_begin), 0, xl_all);
+}
+
 // Fitness of every program from its chunk partials, summed in chunk order.
-__global__ void k_finalize(FinalizeArgs a) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= a.n_programs) return;
+__device__ static void finalize_program(const FinalizeArgs& a, int p) {
   const ProgMeta m = a.meta[p];
   const double nan = __longlong_as_double(0x7FF8000000000000LL);
   double F;
@@ -371,6 +459,45 @@ __global__ void k_finalize(FinalizeArgs a) {
     }
   }
   a.fitness[p] = F;
+}
+
+__global__ void k_finalize(FinalizeArgs a) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < a.n_programs) finalize_program(a, p);
+}
+
+// One thread per program of every problem of the table.
+__global__ void k_finalize_batch(BatchArgs b) {
+  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= b.n_programs) return;
+  const int q = batch_find(b, g, [](const BatchProblem& t) { return t.prog_begin; });
+  const BatchProblem& P = b.table[q];
+  FinalizeArgs a;
+  a.meta = P.prep.meta;
+  a.part = P.part;
+  a.stats = P.stats;
+  a.M = P.M;
+  a.n_programs = P.prep.n_programs;
+  a.n_chunks = P.n_chunks;
+  a.kind = b.kind;
+  a.fitness = P.fitness;
+  finalize_program(a, int(g - P.prog_begin));
+}
+
+// First work item of every problem in each work list (exclusive prefix sums
+// in table order), from the class counts that k_prepare_batch produced.
+__global__ void k_batch_items(BatchArgs b) {
+  const int v = threadIdx.x;
+  if (v >= N_LISTS) return;
+  const int cls = v == 0 ? 0 : v - 1;
+  int64_t* off = b.item_off + int64_t(v) * (b.n_problems + 1);
+  int64_t acc = 0;
+  for (int q = 0; q < b.n_problems; ++q) {
+    off[q] = acc;
+    const BatchProblem& P = b.table[q];
+    if (v >= 2 || P.kv == v) acc += int64_t(P.prep.class_count[cls]) * P.n_chunks;
+  }
+  off[b.n_problems] = acc;
 }
 
 __global__ void k_zero_u64(unsigned long long* p, int n) {
@@ -413,12 +540,12 @@ static hipError_t launch_class(const EvalArgs& a, hipStream_t s) {
 }
 
 template <int KIND>
-static hipError_t launch_kind(const EvalArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+static hipError_t launch_kind(int kv, const EvalArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, a.work, N_CLASSES);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (ev0) (void)hipEventRecord(ev0, s);
-  e = a.D <= WIDE_TILE_MAX_D ? launch_class<KIND, 0, 0>(a, s) : launch_class<KIND, 0, 1>(a, s);
+  e = kv == 0 && a.D <= WIDE_TILE_MAX_D ? launch_class<KIND, 0, 0>(a, s) : launch_class<KIND, 0, 1>(a, s);
   if (ev1) (void)hipEventRecord(ev1, s);
   if (e != hipSuccess) return e;
   e = launch_class<KIND, 1, 0>(a, s);
@@ -426,9 +553,70 @@ static hipError_t launch_kind(const EvalArgs& a, hipStream_t s, hipEvent_t ev0, 
   return launch_class<KIND, 2, 0>(a, s);
 }
 
-hipError_t launch_eval(int kind, const EvalArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-  return kind == BEAGLE_FIT_MSE ? launch_kind<BEAGLE_FIT_MSE>(a, s, ev0, ev1)
-                                : launch_kind<BEAGLE_FIT_CORR>(a, s, ev0, ev1);
+hipError_t launch_eval(int kind, int kv, const EvalArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  return kind == BEAGLE_FIT_MSE ? launch_kind<BEAGLE_FIT_MSE>(kv, a, s, ev0, ev1)
+                                : launch_kind<BEAGLE_FIT_CORR>(kv, a, s, ev0, ev1);
+}
+
+// Persistent grid of a work-list kernel: resident workgroups per CU at the
+// list's LDS tile size, times the CUs (cached per LDS size).
+template <int KIND, int CLS, int KV>
+static int list_grid(int max_d) {
+  const size_t lds = size_t(EVAL_WAVES) * max_d * ((class_k(CLS, KV) + 3) / 4) * 256 * sizeof(float);
+  static size_t cached_lds = size_t(-1);
+  static int cached = 0;
+  if (lds != cached_lds) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_batch<KIND, CLS, KV>, 256, lds) != hipSuccess ||
+        nb < 1)
+      nb = 1;
+    cached = nb * cu_count();
+    cached_lds = lds;
+  }
+  return cached;
+}
+
+template <int KIND, int CLS, int KV>
+static hipError_t launch_list(const BatchArgs& b, int max_d, hipStream_t s) {
+  const size_t lds = size_t(EVAL_WAVES) * max_d * ((class_k(CLS, KV) + 3) / 4) * 256 * sizeof(float);
+  hipLaunchKernelGGL((k_eval_batch<KIND, CLS, KV>), dim3(list_grid<KIND, CLS, KV>(max_d)), dim3(256), lds, s, b);
+  return hipGetLastError();
+}
+
+template <int KIND>
+static void prime_kind(const int* max_d, const int* has) {
+  if (has[0]) (void)list_grid<KIND, 0, 0>(max_d[0]);
+  if (has[1]) (void)list_grid<KIND, 0, 1>(max_d[1]);
+  if (has[2]) (void)list_grid<KIND, 1, 0>(max_d[2]);
+  if (has[3]) (void)list_grid<KIND, 2, 0>(max_d[3]);
+}
+
+void prime_eval_batch(int kind, const int* max_d, const int* has_items) {
+  if (kind == BEAGLE_FIT_MSE)
+    prime_kind<BEAGLE_FIT_MSE>(max_d, has_items);
+  else
+    prime_kind<BEAGLE_FIT_CORR>(max_d, has_items);
+}
+
+template <int KIND>
+static hipError_t launch_batch_kind(const BatchArgs& b, const int* max_d, const int* has, hipStream_t s,
+                                    hipEvent_t ev0, hipEvent_t ev1) {
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, b.work, N_LISTS);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (ev0) (void)hipEventRecord(ev0, s);
+  if (has[0] && (e = launch_list<KIND, 0, 0>(b, max_d[0], s)) != hipSuccess) return e;
+  if (has[1] && (e = launch_list<KIND, 0, 1>(b, max_d[1], s)) != hipSuccess) return e;
+  if (ev1) (void)hipEventRecord(ev1, s);
+  if (has[2] && (e = launch_list<KIND, 1, 0>(b, max_d[2], s)) != hipSuccess) return e;
+  if (has[3] && (e = launch_list<KIND, 2, 0>(b, max_d[3], s)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+hipError_t launch_eval_batch(int kind, const BatchArgs& b, const int* max_d, const int* has_items, hipStream_t s,
+                             hipEvent_t ev0, hipEvent_t ev1) {
+  return kind == BEAGLE_FIT_MSE ? launch_batch_kind<BEAGLE_FIT_MSE>(b, max_d, has_items, s, ev0, ev1)
+                                : launch_batch_kind<BEAGLE_FIT_CORR>(b, max_d, has_items, s, ev0, ev1);
 }
 
 }  // namespace bgl

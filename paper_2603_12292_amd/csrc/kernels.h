@@ -93,9 +93,59 @@ struct ValuesArgs {
   int32_t shift_mode;
 };
 
+// One problem of a batched evaluation: an entry of the device problem table.
+// Every pointer (the caller's arrays and this problem's share of the
+// workspace) is resolved on the host before the table is uploaded.
+struct BatchProblem {
+  PrepareArgs prep;  // programs, decode targets, class lists, status output
+  const float* X;    // [M x D] caller's cases
+  const float* y;    // [M]
+  float* Xt;         // [D x Mp]
+  float* yp;         // [Mp]
+  double* stats;     // [4] target statistics
+  double* part;      // [n_sums][n_chunks][n_programs]
+  double* fitness;   // [n_programs] caller's output
+  int64_t M;
+  int64_t Mp;
+  int64_t chunk;
+  int32_t n_chunks;
+  int32_t kv;          // tile variant of class 0 for this problem
+  int64_t prog_begin;  // first program of this problem in the batch-wide program index
+  int64_t case_begin;  // first padded case of this problem in the batch-wide case index
+};
+
+// Work lists of a batched evaluation: class 0 wide tile, class 0 narrow
+// tile, class 1, class 2.
+constexpr int N_LISTS = 4;
+
+struct BatchArgs {
+  const BatchProblem* table;
+  int32_t n_problems;
+  int32_t kind;
+  int64_t n_programs;          // over the whole table
+  int64_t n_cases;             // padded cases over the whole table
+  int64_t* item_off;           // [N_LISTS][n_problems + 1] first work item of each problem per list
+  unsigned long long* work;    // [N_LISTS] work-item counters, zero at launch
+};
+
+// The problem holding batch-wide index x of a prefix field (prog_begin or
+// case_begin): the last q with field(q) <= x.
+template <class F>
+__device__ __forceinline__ int batch_find(const BatchArgs& b, int64_t x, F field) {
+  int lo = 0, hi = b.n_problems;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (field(b.table[mid]) <= x)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
 constexpr int EVAL_WAVES = 4;
-constexpr int CASES_PER_WAVE_ITER = 64 * 8;                      // case padding unit (K <= 8)
-constexpr int CASES_PER_BLOCK_ITER = CASES_PER_WAVE_ITER * EVAL_WAVES;  // chunk granularity
+constexpr int CASES_PER_WAVE_ITER = 64 * 8;                             // cases of one wave tile (K <= 8)
+constexpr int CASES_PER_BLOCK_ITER = CASES_PER_WAVE_ITER * EVAL_WAVES;  // chunk granularity and case padding
 // Cases per lane of the register-need classes (variant KV selects the
 // narrower tile of class 0, used when the LDS input tile of the wide one
 // would exceed WIDE_TILE_MAX_D variables).
@@ -104,6 +154,12 @@ __host__ __device__ constexpr int class_k(int c, int kv) { return c == 0 ? (kv =
 
 __global__ void k_prepare(PrepareArgs a);
 __global__ void k_stage_cases(StageArgs a);
+__global__ void k_prepare_batch(BatchArgs b);
+__global__ void k_stage_batch(BatchArgs b);
+__global__ void k_target_stats_batch(BatchArgs b);
+__global__ void k_values_batch(BatchArgs b);
+__global__ void k_batch_items(BatchArgs b);
+__global__ void k_finalize_batch(BatchArgs b);
 __global__ void k_target_stats(const float* __restrict__ y, int64_t M, double* __restrict__ stats);
 __global__ void k_finalize(FinalizeArgs a);
 __global__ void k_values(ValuesArgs a);
@@ -111,6 +167,15 @@ __global__ void k_values(ValuesArgs a);
 // host launchers of the templated evaluation kernels (eval.hip)
 // ev0/ev1 (may be null) are recorded on `s` right before and after the
 // fast-path kernel.
-hipError_t launch_eval(int kind, const EvalArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
+// kv selects the tile variant of class 0 (forced to the narrow one above
+// WIDE_TILE_MAX_D variables).
+hipError_t launch_eval(int kind, int kv, const EvalArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
+// The work-list kernels of a batched evaluation; max_d[v] is the largest D
+// among the problems of list v (sizes the LDS tile), lists with
+// has_items[v] == 0 are skipped.
+hipError_t launch_eval_batch(int kind, const BatchArgs& b, const int* max_d, const int* has_items, hipStream_t s,
+                             hipEvent_t ev0, hipEvent_t ev1);
+// Runs the occupancy queries of those launches (before a stream capture).
+void prime_eval_batch(int kind, const int* max_d, const int* has_items);
 
 }  // namespace bgl

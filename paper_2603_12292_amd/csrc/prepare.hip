@@ -15,9 +15,7 @@ namespace bgl {
 //     (opcode, arg) at its output position,
 //  3. forward over the output: track the stack size n before each token and
 //     write the handler word; CONST values go to the side table cval.
-__global__ void k_prepare(PrepareArgs a) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= a.n_programs) return;
+__device__ static void prepare_program(const PrepareArgs& a, int p) {
   const int64_t off = a.tok_offset[p];
   const int32_t L = a.tok_len[p];
   const int64_t coff = a.const_offset[p];
@@ -172,22 +170,54 @@ __global__ void k_prepare(PrepareArgs a) {
   }
 }
 
+__global__ void k_prepare(PrepareArgs a) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < a.n_programs) prepare_program(a, p);
+}
+
+// One thread per program of every problem of the table.
+__global__ void k_prepare_batch(BatchArgs b) {
+  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= b.n_programs) return;
+  const int q = batch_find(b, g, [](const BatchProblem& t) { return t.prog_begin; });
+  prepare_program(b.table[q].prep, int(g - b.table[q].prog_begin));
+}
+
 // X [M x D] row-major -> Xt [D x Mp] (case index fastest), y -> yp [Mp];
 // cases M..Mp-1 repeat case 0 (their outputs are masked out of every sum).
-__global__ void k_stage_cases(StageArgs a) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= a.Mp) return;
+__device__ static void stage_case(const StageArgs& a, int64_t i) {
   const int64_t src = i < a.M ? i : 0;
   for (int d = 0; d < a.D; ++d) a.Xt[int64_t(d) * a.Mp + i] = a.X[src * a.D + d];
   a.yp[i] = a.y[src];
 }
 
+__global__ void k_stage_cases(StageArgs a) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < a.Mp) stage_case(a, i);
+}
+
+// One thread per padded case of every problem of the table.
+__global__ void k_stage_batch(BatchArgs b) {
+  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= b.n_cases) return;
+  const int q = batch_find(b, g, [](const BatchProblem& t) { return t.case_begin; });
+  const BatchProblem& P = b.table[q];
+  StageArgs a;
+  a.X = P.X;
+  a.y = P.y;
+  a.M = P.M;
+  a.Mp = P.Mp;
+  a.D = P.prep.D;
+  a.Xt = P.Xt;
+  a.yp = P.yp;
+  stage_case(a, g - P.case_begin);
+}
+
 // Target statistics for correlation fitness, one workgroup, fixed order:
 //   ybar = y0 + sum(y - y0) / M,  w_i = y_i - ybar (binary64),
 //   stats = {ybar, sum w, sum w^2 - (sum w)^2 / M}.
-__global__ void __launch_bounds__(1024) k_target_stats(const float* __restrict__ y, int64_t M,
-                                                       double* __restrict__ stats) {
-  __shared__ double red[2][1024];
+__device__ static void target_stats_block(const float* __restrict__ y, int64_t M, double* __restrict__ stats,
+                                          double (&red)[2][1024]) {
   const int t = threadIdx.x;
   const double y0 = double(y[0]);
   double s = 0.0;
@@ -221,6 +251,19 @@ __global__ void __launch_bounds__(1024) k_target_stats(const float* __restrict__
     stats[1] = red[0][0];
     stats[2] = red[1][0] - red[0][0] * red[0][0] / double(M);
   }
+}
+
+__global__ void __launch_bounds__(1024) k_target_stats(const float* __restrict__ y, int64_t M,
+                                                       double* __restrict__ stats) {
+  __shared__ double red[2][1024];
+  target_stats_block(y, M, stats, red);
+}
+
+// One workgroup per problem of the table.
+__global__ void __launch_bounds__(1024) k_target_stats_batch(BatchArgs b) {
+  __shared__ double red[2][1024];
+  const BatchProblem& P = b.table[blockIdx.x];
+  target_stats_block(P.y, P.M, P.stats, red);
 }
 
 }  // namespace bgl
