@@ -100,6 +100,92 @@ def adjoint_bench(steps: int, warmup: int):
             "adjoint_cost_vs_fwd": round(fwd / both, 3)}
 
 
+def ragged_bench(steps: int, warmup: int):
+    """The 64-problem ragged workload (1024 programs each, L~U{5..96},
+    D~U{1..9}, M=round(10^U(3,6)), MSE): one batched call (a replayed HIP
+    graph over all problems) against 64 separate beagle_eval calls, both on
+    torch's current stream, inputs resident."""
+    import torch
+    from paper_2603_12292_amd import api
+    from paper_2603_12292_amd import workloads as wl
+    ws = wl.ragged_problems()
+    dev = [(api.DevicePrograms.from_programset(w.programs, "cuda:0"), torch.from_numpy(w.data.X).cuda(),
+            torch.from_numpy(w.data.y).cuda()) for w in ws]
+    out = [torch.empty(p.n, dtype=torch.float64, device="cuda") for p, _, _ in dev]
+    nc = sum(w.programs.node_count() * w.data.M for w in ws)
+    ctx = api.context(0)
+
+    def batched():
+        api.evaluate_batched(dev, "mse", out=out, ctx=ctx)
+
+    def sequential():
+        for p, X, y in dev:
+            api.evaluate(p, X, y, "mse", ctx=ctx)
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    tb = timed(batched)
+    ts = timed(sequential)
+    return {"workload": "ragged: 64 problems x 1024 programs, L~U{5..96}, D~U{1..9}, M=round(10^U(3,6)), MSE",
+            "node_cases": nc, "batched_ms": round(tb * 1e3, 3), "sequential_ms": round(ts * 1e3, 3),
+            "batched_gpops": round(nc / tb / 1e9, 2), "sequential_gpops": round(nc / ts / 1e9, 2),
+            "batched_speedup": round(ts / tb, 3)}
+
+
+def generation_bench(generations: int):
+    """The generation loop: ramped half-and-half N=16384 (depths 2..6, max
+    length 128), D=9, M=10^6, MSE; per generation one evaluation and one
+    selection + variation step (tournament 4, crossover 0.9, mutation 0.1),
+    everything on the GPU.  GPop/s counts the evaluations' node-cases."""
+    import torch
+    from paper_2603_12292_amd import api
+    from paper_2603_12292_amd import workloads as wl
+    data = wl.generation_dataset()
+    X = torch.from_numpy(data.X).cuda()
+    y = torch.from_numpy(data.y).cuda()
+    params = api.GenParams()
+    N, D, seed = 16384, data.D, 2606
+    ctx = api.context(0)
+    pop = api.init_population(N, D, params, seed, ctx=ctx)
+    spare = api.Slots.empty(N, params.max_len, params.max_consts, "cuda")
+    api.evaluate(pop.programs(), X, y, "mse", ctx=ctx)  # tunes the bucket of generation 0
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(generations + 1)]
+    lens = []
+    t0 = time.perf_counter()
+    for g in range(generations + 1):
+        e0, e1, e2 = ev[g]
+        e0.record()
+        fit = api.evaluate(pop.programs(), X, y, "mse", ctx=ctx)
+        e1.record()
+        lens.append(pop.len.to(torch.int64).sum())
+        if g < generations:
+            api.generation(pop.programs(), fit, params, D, seed, g + 1, out=spare, ctx=ctx)
+            pop, spare = spare, pop
+        e2.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = [a.elapsed_time(b) for a, b, _ in ev]
+    gen_ms = [b.elapsed_time(c) for _, b, c in ev[:-1]]
+    tokens = [int(t) for t in torch.stack(lens).cpu()]
+    nc = sum(tokens) * data.M
+    return {"workload": f"generation loop: N={N}, ramped half-and-half depths 2..6, max length 128, D={D}, "
+                        f"M={data.M}, MSE, tournament 4, crossover 0.9, mutation 0.1",
+            "evaluations": generations + 1, "wall_s": round(wall, 3),
+            "eval_ms_mean": round(float(np.mean(ev_ms)), 3), "generation_step_ms_mean": round(float(np.mean(gen_ms)), 4),
+            "eval_gpops": round(nc / (sum(ev_ms) / 1e3) / 1e9, 2), "loop_gpops": round(nc / wall / 1e9, 2),
+            "mean_len_first": round(tokens[0] / N, 2), "mean_len_last": round(tokens[-1] / N, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +194,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-programs", type=int, default=4096)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-ragged", action="store_true")
+    ap.add_argument("--generations", type=int, default=50, help="generation-loop length (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (one process, one device)",
@@ -173,6 +261,10 @@ def main():
     }
     if not args.no_adjoint:
         out["adjoint"] = adjoint_bench(args.steps, args.warmup)
+    if not args.no_ragged:
+        out["ragged"] = ragged_bench(max(1, args.steps // 4), max(1, args.warmup))
+    if args.generations > 0:
+        out["generation_loop"] = generation_bench(args.generations)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, 1, args.cpu_programs)
     print(json.dumps(out), flush=True)

@@ -94,6 +94,7 @@ struct ProgMeta {
   int32_t need;    // register need of the expression tree (max stack size)
   int32_t len;     // decoded instruction words (fused pairs count once)
   float shift;     // correlation fitness: the program's output at case 0
+  uint32_t vmask;  // bit d set: the program reads input variable d (staged only then)
 };
 
 }  // namespace bgl

@@ -17,6 +17,7 @@
 
 #include "beagle_device.h"
 #include "kernels.h"
+#include "trig.h"
 
 namespace bgl {
 
@@ -164,12 +165,10 @@ __device__ __forceinline__ void interpret(uint32_t vc0, float vv0, uint32_t vc1,
         BGL_FUSED(B_RDIV)
 #undef BGL_FUSED
         case H_UN + 0:
-#pragma unroll
-          for (int k = 0; k < K; ++k) top[k] = sinf(top[k]);
+          trig_tile<false, K>(top);
           break;
         case H_UN + 1:
-#pragma unroll
-          for (int k = 0; k < K; ++k) top[k] = cosf(top[k]);
+          trig_tile<true, K>(top);
           break;
         case H_UN + 2:
 #pragma unroll
@@ -213,6 +212,7 @@ __device__ __forceinline__ void eval_block(const EvalArgs& a, int p, int c, doub
   const uint32_t vc1 = lane + 64 < L ? code[lane + 64] : 0u;
   const float vv1 = lane + 64 < L ? cval[lane + 64] : 0.0f;
   const double shift = double(m.shift);
+  const uint32_t vmask = uint32_t(__builtin_amdgcn_readfirstlane(int(m.vmask)));
   const double ybar = KIND == BEAGLE_FIT_CORR ? a.stats[0] : 0.0;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
   const int64_t c0 = int64_t(c) * a.chunk;
@@ -236,6 +236,7 @@ __device__ __forceinline__ void eval_block(const EvalArgs& a, int p, int c, doub
     // coalesced global reads, one LDS write per variable; the wave's tile is
     // private to it, so a wave barrier suffices
     for (int d = 0; d < a.D; ++d) {
+      if (!((vmask >> d) & 1u)) continue;  // a variable the program never reads
       XRow<K> xv;
 #pragma unroll
       for (int k = 0; k < K; ++k) xv.v[k] = a.Xt[int64_t(d) * a.Mp + base + (k / SUB) * SPAN + (k % SUB) * 64 + lane];

@@ -24,6 +24,7 @@
 // partials; a finalize kernel sums the chunks in order.
 #include "beagle_device.h"
 #include "grad.h"
+#include "trig.h"
 
 namespace bgl {
 
@@ -63,10 +64,18 @@ __device__ __forceinline__ void dbinop(float A, float B, float& dA, float& dB) {
   }
 }
 
+// sin (COS = false) or cos of one value per lane, the interpreter's functions
+template <bool COS>
+__device__ __forceinline__ float trig1(float x) {
+  float v[1] = {x};
+  trig_tile<COS, 1>(v);
+  return v[0];
+}
+
 __device__ __forceinline__ float dunary(uint32_t u, float x, float y) {
   switch (u) {
-    case 0: return cosf(x);
-    case 1: return -sinf(x);
+    case 0: return trig1<true>(x);
+    case 1: return -trig1<false>(x);
     case 2: return (x > 80.0f || x < -80.0f) ? 0.0f : y;
     case 3: return x != 0.0f ? 1.0f / x : 0.0f;
     default: return x != 0.0f ? copysignf(0.5f, x) / y : 0.0f;
@@ -187,8 +196,8 @@ __device__ void grad_item(const GradArgs& a, int p, int c, float* lds) {
         BGL_GBIN_ALL(B_RDIV)
 #undef BGL_GBIN
 #undef BGL_GBIN_ALL
-        case H_UN + 0: top = sinf(top); break;
-        case H_UN + 1: top = cosf(top); break;
+        case H_UN + 0: top = trig1<false>(top); break;
+        case H_UN + 1: top = trig1<true>(top); break;
         case H_UN + 2: top = op_exp(top); break;
         case H_UN + 3: top = op_log(top); break;
         case H_UN + 4: top = op_sqrt(top); break;

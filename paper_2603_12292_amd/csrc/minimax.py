@@ -1,0 +1,89 @@
+"""Constants of the library's binary32 sine and cosine (csrc/trig.h).
+
+Run: python -m paper_2603_12292_amd.csrc.minimax  (prints the C++ constants)
+
+1. Bits of 2/pi for the large-argument reduction (Payne and Hanek, "Radian
+   reduction for trigonometric functions", SIGNUM Newsletter 18(1), 1983):
+   pi comes from Machin's formula, pi/4 = 4 atan(1/5) - atan(1/239), in exact
+   integer arithmetic with 320 guard bits, and floor(2^(224+1) / pi) gives
+   bits 1..224 of 2/pi.
+2. pi/2 split into two binary64 numbers (Cody and Waite, "Software Manual for
+   the Elementary Functions", 1980) for the reduction of |x| < 2^30.
+3. Polynomials on |r| <= pi/4 (with a 0.1 % margin): sin r = r + r^3 S(r^2)
+   and cos r = 1 - r^2/2 + r^4 C(r^2), S and C of degree 2, minimising the
+   maximum relative error with Lawson's iteratively reweighted least squares
+   (C. L. Lawson, 1961), then rounded to binary32.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _atan_inv(n: int, one: int) -> int:
+    """atan(1/n) * one, by its alternating series, in integers."""
+    total, term, k, sign = 0, one // n, 1, 1
+    while term:
+        total += sign * (term // k)
+        term //= n * n
+        k += 2
+        sign = -sign
+    return total
+
+
+def pi_fixed(bits: int) -> int:
+    """floor-ish(pi * 2^bits) with `bits` correct bits (guard bits added)."""
+    guard = 64
+    one = 1 << (bits + guard)
+    pi = 4 * (4 * _atan_inv(5, one) - _atan_inv(239, one))
+    return pi >> guard
+
+
+def two_over_pi_words(n_words: int = 7) -> list[int]:
+    """32-bit words holding bits 1 .. 32*n_words of the fraction 2/pi."""
+    nbits = 32 * n_words
+    K = nbits + 320
+    P = pi_fixed(K)                         # pi * 2^K
+    frac = (1 << (nbits + 1 + K)) // P      # floor(2/pi * 2^nbits)
+    return [(frac >> (32 * (n_words - 1 - i))) & 0xFFFFFFFF for i in range(n_words)]
+
+
+def pio2_split() -> tuple[float, float]:
+    P = pi_fixed(200)  # pi * 2^200
+    hi = float(P) / 2.0 ** 201  # nearest binary64 to pi/2 (float() of an int rounds)
+    rest = P - (int(round(hi * 2.0 ** 201)))  # pi/2*2^201 - hi*2^201
+    lo = float(rest) / 2.0 ** 201
+    return hi, lo
+
+
+def _lawson(F, W, xs, deg, iters=400):
+    A = np.stack([xs ** (2 * k) for k in range(deg)], 1)
+    u = np.ones_like(xs) / len(xs)
+    c = None
+    for _ in range(iters):
+        sw = np.sqrt(u) * W
+        c, *_ = np.linalg.lstsq(A * sw[:, None], F * sw, rcond=None)
+        e = np.abs(W * (F - A @ c))
+        u = u * e
+        u /= u.sum()
+    return c
+
+
+def poly_coefficients():
+    xs = np.linspace(1e-4, np.pi / 4 * 1.001, 200001)
+    s = _lawson((np.sin(xs) - xs) / xs ** 3, xs ** 3 / np.sin(xs), xs, 3)
+    c = _lawson((np.cos(xs) - 1 + xs * xs / 2) / xs ** 4, xs ** 4 / np.cos(xs), xs, 3)
+    return [np.float32(v) for v in s], [np.float32(v) for v in c]
+
+
+def main():
+    words = two_over_pi_words()
+    hi, lo = pio2_split()
+    s, c = poly_coefficients()
+    print("two_over_pi bits 1..224:", ", ".join(f"0x{w:08X}u" for w in words))
+    print(f"pio2_hi = {hi.hex()}  pio2_lo = {lo.hex()}  2/pi = {(2 / np.pi).hex()}")
+    print("S =", ", ".join(f"{float(v).hex()}" for v in s), "(", ", ".join(repr(float(v)) for v in s), ")")
+    print("C =", ", ".join(f"{float(v).hex()}" for v in c), "(", ", ".join(repr(float(v)) for v in c), ")")
+
+
+if __name__ == "__main__":
+    main()

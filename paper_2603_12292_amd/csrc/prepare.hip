@@ -23,6 +23,7 @@ __device__ static void prepare_program(const PrepareArgs& a, int p) {
   int status = BEAGLE_PROG_OK;
   int need_root = 0;
   int L_dec = 0;
+  uint32_t vmask = 0;
   if (L <= 0) {
     status = L == 0 ? BEAGLE_PROG_EMPTY : BEAGLE_PROG_BAD_LAYOUT;
   } else if (L > MAX_LEN) {
@@ -42,6 +43,7 @@ __device__ static void prepare_program(const PrepareArgs& a, int p) {
       const uint32_t op = t & 0xFFu, arg = t >> 8;
       if (op >= N_OPCODES) { status = BEAGLE_PROG_BAD_OPCODE; break; }
       if (op == OP_VAR && int(arg) >= a.D) { status = BEAGLE_PROG_BAD_VAR; break; }
+      if (op == OP_VAR) vmask |= 1u << arg;
       if (op == OP_CONST && int(arg) >= cc) { status = BEAGLE_PROG_BAD_CONST; break; }
       const int ar = arity(op);
       if (depth < ar) { status = BEAGLE_PROG_UNDERFLOW; break; }
@@ -155,6 +157,7 @@ __device__ static void prepare_program(const PrepareArgs& a, int p) {
   m.need = need_root;
   m.len = status == BEAGLE_PROG_OK ? L_dec : 0;
   m.shift = 0.0f;
+  m.vmask = status == BEAGLE_PROG_OK ? vmask : 0u;
   a.meta[p] = m;
   if (a.status_out) a.status_out[p] = int8_t(status);
   if (status == BEAGLE_PROG_OK) {

@@ -247,3 +247,33 @@ def test_argument_errors():
         api.evaluate(ps, torch.ones((10, 17), device="cuda"), y)
     with pytest.raises(api.BeagleError):
         api.evaluate(ps, X[:1], y[:1], kind="corr")
+
+
+def test_sin_cos_accuracy():
+    """The interpreter's sine and cosine on arguments spanning the binary32
+    range (both reduction paths, signed zeros, subnormals, +-Inf, NaN):
+    within 2 ulp of the binary64 values, NaN exactly where IEEE gives NaN."""
+    rng = np.random.default_rng(21)
+    parts = [rng.uniform(-1, 1, 20000), rng.uniform(-100, 100, 20000),
+             np.exp(rng.uniform(np.log(1e2), np.log(2.0 ** 30), 20000)),
+             np.exp(rng.uniform(np.log(2.0 ** 30), np.log(3.4e38), 20000)),
+             np.array([0.0, -0.0, 1e-40, -1e-42, 1e-30, np.pi, np.pi / 2, 2.0 ** 30, np.nextafter(2.0 ** 30, 0),
+                       3.4028234663852886e38, np.inf, -np.inf, np.nan, 1e22, 1e20])]
+    x = np.concatenate(parts).astype(np.float32)
+    x = np.concatenate([x, -x[: 60000]]).astype(np.float32)
+    X = torch.from_numpy(x.reshape(-1, 1).copy()).cuda()
+    api = _api()
+    progs = wl.pack_programs([([wl.tok(wl.VAR, 0), wl.tok(wl.SIN)], []), ([wl.tok(wl.VAR, 0), wl.tok(wl.COS)], [])])
+    out = api.predict(_dev(progs), X).cpu().numpy()
+    x64 = x.astype(np.float64)
+    with np.errstate(invalid="ignore"):
+        for row, ref in ((out[0], np.sin(x64)), (out[1], np.cos(x64))):
+            assert np.array_equal(np.isnan(row), np.isnan(ref))
+            ok = ~np.isnan(ref)
+            ulp = np.spacing(np.abs(ref[ok]).astype(np.float32)).astype(np.float64)
+            err = np.abs(row[ok].astype(np.float64) - ref[ok]) / ulp
+            print("max ulp", err.max())
+            assert err.max() <= 2.0
+    # odd and even symmetry, signed zero
+    assert np.signbit(out[0][x == 0]).tolist() == np.signbit(x[x == 0]).tolist()
+    assert np.all(out[1][x == 0] == 1.0)
