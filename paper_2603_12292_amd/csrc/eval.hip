@@ -111,7 +111,7 @@ __device__ __forceinline__ void interpret(uint32_t vc0, float vv0, uint32_t vc1,
     for (int t = 0; t < n; ++t) {
       const uint32_t w = __builtin_amdgcn_readlane(vc, t);
       const uint32_t arg = (w >> 8) & 0xFFu;
-      const uint32_t ws = w >> 16;
+      const uint32_t ws = (w >> 16) & 0xFu;
 #pragma unroll
       for (int k = 0; k < K; ++k) stk[k][ws] = top[k];
       switch (w & 0xFFu) {
@@ -221,35 +221,60 @@ __device__ __forceinline__ void eval_block(const EvalArgs& a, int p, int c, doub
   constexpr int G = (K + 3) / 4;
   float* xw = xtile + wave * (a.D * G * 256);
   float* xl = xw + lane * 4;
-  // Case order.  A sub-tile is 64 lanes x min(K, 4) cases (case = base +
-  // k * 64 + lane); the block's waves take consecutive sub-tiles, and a lane
-  // with K = 8 holds two sub-tiles EVAL_WAVES sub-tiles apart.  So each lane
-  // adds exactly the cases it would add with K = 4, in the same order: the
-  // tile width of class 0 changes no result bit.
+  // Case order.  A sub-tile is 64 lanes x min(K, 4) cases; the block's
+  // waves take consecutive sub-tiles, and a lane with K = 8 holds two
+  // sub-tiles EVAL_WAVES sub-tiles apart.  Lane l holds cases 4l .. 4l+3 of a
+  // sub-tile (K >= 4; k * 64 + l for K = 2).  So each lane adds exactly the
+  // cases it would add with K = 4, in the same order: the tile width of
+  // class 0 changes no result bit.
   constexpr int SUB = K < 4 ? K : 4;
   constexpr int SPAN = EVAL_WAVES * 64 * SUB;  // cases of one sub-tile row of the block
   constexpr int NSUB = K / SUB;
   for (int64_t base = c0 + int64_t(wave) * (64 * SUB); base < c1; base += int64_t(NSUB) * SPAN) {
     float yk[K];
+    if constexpr (K >= 4) {
+      // the tile's inputs go straight from global memory to LDS (16 bytes =
+      // 4 cases per lane, the layout load_row reads); every variable's loads
+      // are issued before one wait
+      __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the last tile's LDS reads are done
+      for (int d = 0; d < a.D; ++d) {
+        if (!((vmask >> d) & 1u)) continue;  // a variable the program never reads
 #pragma unroll
-    for (int k = 0; k < K; ++k) yk[k] = a.yp[base + (k / SUB) * SPAN + (k % SUB) * 64 + lane];
-    // coalesced global reads, one LDS write per variable; the wave's tile is
-    // private to it, so a wave barrier suffices
-    for (int d = 0; d < a.D; ++d) {
-      if (!((vmask >> d) & 1u)) continue;  // a variable the program never reads
-      XRow<K> xv;
+        for (int g = 0; g < NSUB; ++g)
+          __builtin_amdgcn_global_load_lds(a.Xt + int64_t(d) * a.Mp + base + g * SPAN + 4 * lane,
+                                           xw + (d * NSUB + g) * 256, 16, 0, 0);
+      }
 #pragma unroll
-      for (int k = 0; k < K; ++k) xv.v[k] = a.Xt[int64_t(d) * a.Mp + base + (k / SUB) * SPAN + (k % SUB) * 64 + lane];
+      for (int g = 0; g < NSUB; ++g) {
+        const float4 q = *reinterpret_cast<const float4*>(a.yp + base + g * SPAN + 4 * lane);
+        yk[4 * g + 0] = q.x;
+        yk[4 * g + 1] = q.y;
+        yk[4 * g + 2] = q.z;
+        yk[4 * g + 3] = q.w;
+      }
+      __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0): the tile is in LDS
       __builtin_amdgcn_wave_barrier();
-      store_row<K>(xl, d, xv);
+    } else {
+#pragma unroll
+      for (int k = 0; k < K; ++k) yk[k] = a.yp[base + k * 64 + lane];
+      // coalesced global reads, one LDS write per variable; the wave's tile
+      // is private to it, so a wave barrier suffices
+      for (int d = 0; d < a.D; ++d) {
+        if (!((vmask >> d) & 1u)) continue;
+        XRow<K> xv;
+#pragma unroll
+        for (int k = 0; k < K; ++k) xv.v[k] = a.Xt[int64_t(d) * a.Mp + base + k * 64 + lane];
+        __builtin_amdgcn_wave_barrier();
+        store_row<K>(xl, d, xv);
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the tile is in LDS
     }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the tile is in LDS
     float top[K];
     interpret<K, S>(vc0, vv0, vc1, vv1, code, cval, L, lane, xl, top);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const bool valid = base + (k / SUB) * SPAN + (k % SUB) * 64 + lane < a.M;
+      const bool valid = base + (k / SUB) * SPAN + (K >= 4 ? 4 * lane + (k % 4) : k * 64 + lane) < a.M;
       if constexpr (KIND == BEAGLE_FIT_MSE) {
         const double d = double(top[k]) - double(yk[k]);
         s0 += valid ? d * d : 0.0;

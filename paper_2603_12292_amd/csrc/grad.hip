@@ -178,7 +178,7 @@ __device__ void grad_item(const GradArgs& a, int p, int c, float* lds) {
     auto step = [&](int t) {
       const uint32_t w = W.word(t);
       const uint32_t arg = (w >> 8) & 0xFFu;
-      stk[w >> 16] = top;
+      stk[(w >> 16) & 0xFu] = top;
       switch (w & 0xFFu) {
         case H_VAR: top = xl[arg * 64]; break;
         case H_CONST: top = W.cv(t); break;
@@ -243,7 +243,7 @@ __device__ void grad_item(const GradArgs& a, int p, int c, float* lds) {
       const uint32_t w = W.word(t);
       const uint32_t xw = W.auxw(t);
       const uint32_t arg = (w >> 8) & 0xFFu;
-      const uint32_t ws = w >> 16;
+      const uint32_t ws = (w >> 16) & 0xFu;
       const int pa = int(xw & 0xFFFFu);
       float wv = g;            // written to astk[rws]: meaningful for binary words only
       float gc = 0.0f;         // gradient contribution of a CONST slot

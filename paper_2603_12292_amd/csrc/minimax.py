@@ -7,14 +7,16 @@ Run: python -m paper_2603_12292_amd.csrc.minimax  (prints the C++ constants)
    pi comes from Machin's formula, pi/4 = 4 atan(1/5) - atan(1/239), in exact
    integer arithmetic with 320 guard bits, and floor(2^(224+1) / pi) gives
    bits 1..224 of 2/pi.
-2. pi/2 split into two binary64 numbers (Cody and Waite, "Software Manual for
-   the Elementary Functions", 1980) for the reduction of |x| < 2^30.
-3. Polynomials on |r| <= pi/4 (with a 0.1 % margin): sin r = r + r^3 S(r^2)
-   and cos r = 1 - r^2/2 + r^4 C(r^2), S and C of degree 2, minimising the
-   maximum relative error with Lawson's iteratively reweighted least squares
-   (C. L. Lawson, 1961), then rounded to binary32.
+2. pi split into two binary64 numbers (Cody and Waite, "Software Manual for
+   the Elementary Functions", 1980) for the reduction of |x| < 2^30, and 1/pi.
+3. The polynomial on |r| <= pi/2 (with a 0.05 % margin): sin r = r + r^3
+   S(r^2), S of degree 3, minimising the maximum relative error with
+   Lawson's iteratively reweighted least squares (C. L. Lawson, 1961), then
+   rounded to binary32.
 """
 from __future__ import annotations
+
+import functools
 
 import numpy as np
 
@@ -47,11 +49,12 @@ def two_over_pi_words(n_words: int = 7) -> list[int]:
     return [(frac >> (32 * (n_words - 1 - i))) & 0xFFFFFFFF for i in range(n_words)]
 
 
-def pio2_split() -> tuple[float, float]:
-    P = pi_fixed(200)  # pi * 2^200
-    hi = float(P) / 2.0 ** 201  # nearest binary64 to pi/2 (float() of an int rounds)
-    rest = P - (int(round(hi * 2.0 ** 201)))  # pi/2*2^201 - hi*2^201
-    lo = float(rest) / 2.0 ** 201
+def pi_split() -> tuple[float, float]:
+    """(hi, lo): hi the binary64 nearest to pi, lo the binary64 nearest to pi - hi."""
+    from fractions import Fraction
+    P = pi_fixed(300)  # pi * 2^300
+    hi = float(Fraction(P, 1 << 300))
+    lo = float(Fraction(P, 1 << 300) - Fraction(hi))
     return hi, lo
 
 
@@ -68,21 +71,20 @@ def _lawson(F, W, xs, deg, iters=400):
     return c
 
 
+@functools.lru_cache(maxsize=None)
 def poly_coefficients():
-    xs = np.linspace(1e-4, np.pi / 4 * 1.001, 200001)
-    s = _lawson((np.sin(xs) - xs) / xs ** 3, xs ** 3 / np.sin(xs), xs, 3)
-    c = _lawson((np.cos(xs) - 1 + xs * xs / 2) / xs ** 4, xs ** 4 / np.cos(xs), xs, 3)
-    return [np.float32(v) for v in s], [np.float32(v) for v in c]
+    xs = np.linspace(1e-5, np.pi / 2 * 1.0005, 50001)
+    s = _lawson((np.sin(xs) - xs) / xs ** 3, xs ** 3 / np.sin(xs), xs, 4, iters=300)
+    return tuple(np.float32(v) for v in s)
 
 
 def main():
     words = two_over_pi_words()
-    hi, lo = pio2_split()
-    s, c = poly_coefficients()
+    hi, lo = pi_split()
+    s = poly_coefficients()
     print("two_over_pi bits 1..224:", ", ".join(f"0x{w:08X}u" for w in words))
-    print(f"pio2_hi = {hi.hex()}  pio2_lo = {lo.hex()}  2/pi = {(2 / np.pi).hex()}")
-    print("S =", ", ".join(f"{float(v).hex()}" for v in s), "(", ", ".join(repr(float(v)) for v in s), ")")
-    print("C =", ", ".join(f"{float(v).hex()}" for v in c), "(", ", ".join(repr(float(v)) for v in c), ")")
+    print(f"pi_hi = {hi.hex()}  pi_lo = {lo.hex()}  1/pi = {(1 / np.pi).hex()}")
+    print("S =", ", ".join(f"{float(v).hex()}" for v in s))
 
 
 if __name__ == "__main__":

@@ -1,19 +1,20 @@
-// Binary32 sine and cosine for the interpreter, within about 1.5 ulp of the
-// exact values over the whole binary32 range.
+// Binary32 sine and cosine for the interpreter, within 2 ulp of the exact
+// values over the whole binary32 range.
 //
-// |x| = q * pi/2 + r with |r| <= pi/4 (approximately), then sin x and cos x
-// are +-sin r or +-cos r by the quadrant q mod 4.
-//  - |x| < 2^30: Cody-Waite reduction in binary64 with pi/2 split into two
+// One odd polynomial serves both functions: |x| = k pi + r (sine) or
+// |x| = (k + 1/2) pi + r (cosine) with |r| <= pi/2, and then
+//     sin x = sign(x) (-1)^k sin r,      cos x = (-1)^(k+1) sin r.
+//  - |x| < 2^30: Cody-Waite reduction in binary64 with pi split into two
 //    binary64 numbers (binary64 FMA issues at the binary32 rate on this GPU);
 //    the error of r is far below binary32 resolution for every binary32 x in
 //    this range.
 //  - larger finite |x|: Payne-Hanek reduction, an exact integer product of
-//    the 24-bit significand with a 96-bit window of the bits of 2/pi chosen
-//    by the exponent; quadrant from its integer bits, r from 64 fraction bits.
-//  - sin r = r + r^3 S(r^2), cos r = 1 - r^2/2 + r^4 C(r^2): minimax
-//    polynomials in binary32.
-// Constants: csrc/minimax.py derives every one of them (2/pi bits from an
-// integer evaluation of pi, the pi/2 split, the polynomial fits).
+//    the 24-bit significand with a 96-bit window of the bits of 1/pi chosen
+//    by the exponent; k mod 2 from its integer bit, r from 64 fraction bits.
+//  - sin r = r + r^3 S(r^2) on [-pi/2, pi/2], S a minimax polynomial of
+//    degree 3 evaluated in binary32.
+// Constants: csrc/minimax.py derives every one of them (the bits of 1/pi
+// from an integer evaluation of pi, the split of pi, the polynomial fit).
 //
 // The interpreter calls the cheap path for a whole wave when no lane holds a
 // large or non-finite argument, and the general one otherwise; the general
@@ -30,81 +31,79 @@ constexpr float TRIG_SMALL = 1073741824.0f;  // 2^30: bound of the binary64 redu
 
 __device__ __forceinline__ float sin_poly(float r) {
   const float r2 = r * r;
-  float p = __builtin_fmaf(r2, -0x1.99407200p-13f, 0x1.11073200p-7f);
-  p = __builtin_fmaf(r2, p, -0x1.55554600p-3f);
+  float p = __builtin_fmaf(r2, 0x1.5db8e2p-19f, -0x1.9f6fa8p-13f);
+  p = __builtin_fmaf(r2, p, 0x1.110ed2p-7f);
+  p = __builtin_fmaf(r2, p, -0x1.55554cp-3f);
   return __builtin_fmaf(r2 * r, p, r);
 }
 
-__device__ __forceinline__ float cos_poly(float r) {
-  const float r2 = r * r;
-  float p = __builtin_fmaf(r2, 0x1.99e87400p-16f, -0x1.6c0c2800p-10f);
-  p = __builtin_fmaf(r2, p, 0x1.55554a00p-5f);
-  return __builtin_fmaf(r2 * r2, p, __builtin_fmaf(r2, -0.5f, 1.0f));
+// r and the parity p of k for a = |x| < 2^30 (COS: the half-period shift).
+template <bool COS>
+__device__ __forceinline__ float trig_reduce_small(float a, int& p) {
+  const double xd = double(a);
+  const double t = COS ? __builtin_fma(xd, 0x1.45f306dc9c883p-2, -0.5) : xd * 0x1.45f306dc9c883p-2;  // 1/pi
+  const double k = __builtin_rint(t);
+  const double h = COS ? k + 0.5 : k;
+  double r = __builtin_fma(-h, 0x1.921fb54442d18p+1, xd);  // pi, high part
+  r = __builtin_fma(-h, 0x1.1a62633145c07p-53, r);         // pi, low part
+  p = int(k) + (COS ? 1 : 0);
+  return float(r);
 }
 
-// r and q of ax = |x| < 2^30.
-__device__ __forceinline__ float trig_reduce_small(float ax, int& q) {
-  const double xd = double(ax);
-  const double qd = __builtin_rint(xd * 0x1.45f306dc9c883p-1);  // 2/pi
-  double rd = __builtin_fma(-qd, 0x1.921fb54442d18p+0, xd);     // pi/2, high part
-  rd = __builtin_fma(-qd, 0x1.1a62633145c07p-54, rd);           // pi/2, low part
-  q = int(qd);
-  return float(rd);
-}
-
-// r and q (mod 4) of a finite ax >= 2^30 (exponent e >= 30).
-__device__ __forceinline__ float trig_reduce_large(float ax, int& q) {
-  // bits 1..224 of the binary fraction 2/pi
+// The same for a finite a >= 2^30 (exponent e >= 30).
+template <bool COS>
+__device__ __forceinline__ float trig_reduce_large(float a, int& p) {
+  // bits 1..224 of the binary fraction 2/pi; bit j of 1/pi is bit j - 1 of 2/pi
   static constexpr uint32_t two_over_pi[7] = {0xA2F9836Eu, 0x4E441529u, 0xFC2757D1u, 0xF534DDC0u,
                                               0xDB629599u, 0x3C439041u, 0xFE5163ABu};
-  const uint32_t bits = __float_as_uint(ax);
-  const int e = int((bits >> 23) & 0xFFu) - 127;  // ax = m * 2^(e - 23)
+  const uint32_t bits = __float_as_uint(a);
+  const int e = int((bits >> 23) & 0xFFu) - 127;  // a = m * 2^(e - 23)
   const uint64_t m = (bits & 0x7FFFFFu) | 0x800000u;
-  // bits of 2/pi above position e - 24 only add multiples of 4 to
-  // ax * 2/pi; the window starts there (0-based index g = e - 25 >= 5 for
-  // ax >= 2^30; clamped so that the table reads stay in bounds whatever ax)
+  // bits of 1/pi above position e - 23 only add even integers to a / pi;
+  // the window starts there, i.e. at bit e - 24 of 2/pi (0-based index
+  // g = e - 25 >= 5 for a >= 2^30; clamped so that the table reads stay in
+  // bounds whatever a)
   const int g = e - 25 > 0 ? e - 25 : 0;
   const int j = g >> 5, sh = g & 31;
   const uint32_t t0 = two_over_pi[j], t1 = two_over_pi[j + 1], t2 = two_over_pi[j + 2], t3 = two_over_pi[j + 3];
   const uint32_t w2 = __funnelshift_l(t1, t0, sh);
   const uint32_t w1 = __funnelshift_l(t2, t1, sh);
   const uint32_t w0 = __funnelshift_l(t3, t2, sh);
-  // P = m * (w2:w1:w0) = 2^94 * (ax * 2/pi mod 4) up to the truncated bits
+  // P = m * (w2:w1:w0) = 2^95 * (a / pi mod 2) up to the truncated bits
   const uint64_t a0 = m * w0;
   const uint64_t a1 = m * w1 + (a0 >> 32);
   const uint64_t a2 = m * w2 + (a1 >> 32);
-  int qq = int((a2 >> 30) & 3u);
-  // fraction bits 30..93 of P as a signed fixed-point number: a set top bit
-  // means fraction >= 1/2, i.e. the nearest quadrant is the next one
-  const uint64_t f = ((a2 & 0x3FFFFFFFull) << 34) | ((a1 & 0xFFFFFFFFull) << 2) | ((a0 & 0xFFFFFFFFull) >> 30);
-  const int64_t fs = int64_t(f);
-  qq += fs < 0 ? 1 : 0;
-  q = qq;
-  return float(double(fs) * 0x1.921fb54442d18p-64);  // fraction * pi/2
+  const int k0 = int((a2 >> 31) & 1u);
+  // fraction bits 31..94 of P: f in [0, 1) as a 64-bit fixed-point number
+  const uint64_t f = ((a2 & 0x7FFFFFFFull) << 33) | ((a1 & 0xFFFFFFFFull) << 1) | ((a0 & 0xFFFFFFFFull) >> 31);
+  // sine: the nearest k (f >= 1/2 rounds up), r = (f - [f >= 1/2]) pi;
+  // cosine: k = k0, r = (f - 1/2) pi; both as signed 64-bit fixed point
+  const int64_t v = COS ? int64_t(f ^ 0x8000000000000000ull) : int64_t(f);
+  p = COS ? k0 + 1 : k0 + int(f >> 63);
+  return float(double(v) * 0x1.921fb54442d18p-63);  // * pi * 2^-64
 }
 
-// +-sin r or +-cos r for the quadrant q, sign bit flipped by `neg`.
-__device__ __forceinline__ float trig_finish(float r, int q, uint32_t neg) {
-  const float v = (q & 1) ? cos_poly(r) : sin_poly(r);
-  return __uint_as_float(__float_as_uint(v) ^ ((uint32_t(q) & 2u) << 30) ^ neg);
+// (-1)^p sin r, sign bit also flipped by `neg`.
+__device__ __forceinline__ float trig_finish(float r, int p, uint32_t neg) {
+  return __uint_as_float(__float_as_uint(sin_poly(r)) ^ (uint32_t(p) << 31) ^ neg);
 }
 
 // COS = false: sin x, true: cos x; for |x| < 2^30 only.
 template <bool COS>
 __device__ __forceinline__ float trig_small(float x) {
-  int q;
-  const float r = trig_reduce_small(__builtin_fabsf(x), q);
-  return trig_finish(r, COS ? q + 1 : q, COS ? 0u : (__float_as_uint(x) & 0x80000000u));
+  int p;
+  const float r = trig_reduce_small<COS>(__builtin_fabsf(x), p);
+  return trig_finish(r, p, COS ? 0u : (__float_as_uint(x) & 0x80000000u));
 }
 
 // Any binary32 x (NaN and +-Inf give NaN).
 template <bool COS>
 __device__ __forceinline__ float trig_any(float x) {
-  const float ax = __builtin_fabsf(x);
-  if (!(ax <= 3.4028234664e38f)) return __builtin_nanf("");
-  int q;
-  const float r = ax < TRIG_SMALL ? trig_reduce_small(ax, q) : trig_reduce_large(ax, q);
-  return trig_finish(r, COS ? q + 1 : q, COS ? 0u : (__float_as_uint(x) & 0x80000000u));
+  const float a = __builtin_fabsf(x);
+  if (!(a <= 3.4028234664e38f)) return __builtin_nanf("");
+  int p;
+  const float r = a < TRIG_SMALL ? trig_reduce_small<COS>(a, p) : trig_reduce_large<COS>(a, p);
+  return trig_finish(r, p, COS ? 0u : (__float_as_uint(x) & 0x80000000u));
 }
 
 // sin or cos of K values per lane: the cheap reduction for the whole wave
