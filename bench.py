@@ -40,16 +40,17 @@ def function_nodes(ps) -> int:
     return int(np.count_nonzero(ops < 9))
 
 
-def traffic_from_profile():
+def traffic_from_profile(kernel: str):
     """HBM bytes per launch of the interpreter kernel from the committed counter
-    summary, or None when the kernel source changed since it was taken."""
+    summary, or None when the kernel source changed since it was taken or the
+    summary is of another tile-width variant."""
     from paper_2603_12292_amd.profiling import source_hash
     path = os.path.join(ROOT, "profiles", "k_eval_class_corr_plain_mid_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("source_hash") != source_hash():
+    if rec.get("source_hash") != source_hash() or rec.get("kernel") != kernel:
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -232,11 +233,13 @@ def main():
     gpops = nodes * M * args.steps / dt / 1e9
     assert np.isfinite(fit.cpu().numpy()).sum() > 0
 
+    width = ctx.tile_width("corr", w.data.D, M, int(ps.tokens.size), ps.n)
+    kernel = f"k_eval_class<1, 0, {0 if width == 8 else 1}>"
     k_avg_s = k_ms / 1e3 / max(k_n, 1)
     fn = function_nodes(ps)
     alg_ops = fn * M                       # one fp32 op per operator application
     achieved = alg_ops / k_avg_s
-    traffic = traffic_from_profile()
+    traffic = traffic_from_profile(kernel)
     out = {
         "metric": "GPop/s (program-node x fitness-case evals/s), fwd and fwd+adjoint, 1 MI355X",
         "value": round(gpops, 2),
@@ -255,7 +258,8 @@ def main():
                    "programs": ps.n, "fitness_cases": M, "nodes": nodes, "kind": "corr"},
         "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 4), "peak": round(PEAK_LANE_OPS / 1e12, 2),
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_LANE_OPS, 4),
-                     "traffic": traffic, "kernel": "k_eval_class<corr, need<=4, 8 cases/lane>",
+                     "traffic": traffic,
+                     "kernel": f"{kernel}: correlation fitness, register need <= 4, {width} cases per lane",
                      "kernel_ms": round(k_avg_s * 1e3, 4), "alg_ops_per_launch": alg_ops,
                      "kernel_gpops": round(nodes * M / k_avg_s / 1e9, 2)},
     }

@@ -184,6 +184,12 @@ typedef enum { BEAGLE_TUNE_AUTO = 0, BEAGLE_TUNE_WIDE = 1, BEAGLE_TUNE_NARROW = 
  * BEAGLE_E_INVALID_ARG. */
 beagle_status beagle_ctx_set_tuning(beagle_ctx* ctx, int policy);
 
+/* The tile width beagle_eval uses for a problem shape under the current
+ * policy (instrumentation): *cases_per_lane = 8 or 4, or 0 when
+ * BEAGLE_TUNE_AUTO has not measured the bucket yet.  Only sizes are read. */
+beagle_status beagle_ctx_tile_width(beagle_ctx* ctx, int kind, int32_t D, int64_t M, int64_t n_tokens,
+                                    int32_t n_programs, int32_t* cases_per_lane);
+
 /* Ragged batching: n_problems independent populations, each on its own
  * dataset (its own M and D), evaluated by one launch sequence whose work
  * lists span every problem (the paper batches the population onto the GPU,

@@ -66,6 +66,13 @@ class Context:
         code = names.get(policy, -1) if isinstance(policy, str) else int(policy)
         _check(self.lib.beagle_ctx_set_tuning(self.handle, code))
 
+    def tile_width(self, kind, D: int, M: int, n_tokens: int, n_programs: int) -> int:
+        """Cases per lane beagle_eval uses for this shape (0: not measured yet)."""
+        out = ctypes.c_int32()
+        _check(self.lib.beagle_ctx_tile_width(self.handle, _kind(kind), D, M, n_tokens, n_programs,
+                                              ctypes.byref(out)))
+        return int(out.value)
+
     def graph_stats(self):
         """(graphs captured, graph launches) of batched evaluation."""
         a = ctypes.c_int64()

@@ -304,6 +304,18 @@ void beagle_ctx_destroy(beagle_ctx* ctx) {
   delete ctx;
 }
 
+beagle_status beagle_ctx_tile_width(beagle_ctx* ctx, int kind, int32_t D, int64_t M, int64_t n_tokens,
+                                    int32_t n_programs, int32_t* cases_per_lane) {
+  if (!ctx || !cases_per_lane) return fail(BEAGLE_E_INVALID_ARG, "NULL argument");
+  if (kind != BEAGLE_FIT_MSE && kind != BEAGLE_FIT_CORR) return fail(BEAGLE_E_INVALID_ARG, "unknown fitness kind");
+  if (D < 1 || D > BEAGLE_MAX_D || M < 1 || n_programs < 1 || n_tokens < 0)
+    return fail(BEAGLE_E_INVALID_ARG, "bad problem shape");
+  int kv = 0;
+  *cases_per_lane =
+      known_tile_variant(ctx, kind, D, M, double(n_tokens) / n_programs, &kv) ? bgl::class_k(0, kv) : 0;
+  return BEAGLE_OK;
+}
+
 beagle_status beagle_ctx_set_tuning(beagle_ctx* ctx, int policy) {
   if (!ctx) return fail(BEAGLE_E_INVALID_ARG, "ctx is NULL");
   if (policy != BEAGLE_TUNE_AUTO && policy != BEAGLE_TUNE_WIDE && policy != BEAGLE_TUNE_NARROW)

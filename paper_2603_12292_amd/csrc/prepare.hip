@@ -5,9 +5,19 @@
 
 namespace bgl {
 
+// Per-token scratch of one program: an array of T with a stride (LDS
+// arrays are interleaved across the workgroup's threads, so that
+// neighbouring threads hit neighbouring banks).
+template <class T, int STRIDE>
+struct Scratch {
+  T* p;
+  __device__ __forceinline__ int get(int i) const { return int(p[i * STRIDE]); }
+  __device__ __forceinline__ void set(int i, int v) const { p[i * STRIDE] = T(v); }
+};
+
 // One thread per program.  Three passes over the tokens, with per-token
-// scratch in global memory (each program owns tokens[off, off + L) of
-// every scratch array):
+// scratch (`stack`, `start`, `need`, the re-ordered program `ord` and a copy
+// of the tokens `tok`):
 //  1. forward: validate, and for every token record the start of its
 //     subtree and its register need (Strahler number),
 //  2. backward from the root: place every subtree in the output order
@@ -15,7 +25,8 @@ namespace bgl {
 //     (opcode, arg) at its output position,
 //  3. forward over the output: track the stack size n before each token and
 //     write the handler word; CONST values go to the side table cval.
-__device__ static void prepare_program(const PrepareArgs& a, int p) {
+template <class ST, class S, class SO>
+__device__ static void prepare_program(const PrepareArgs& a, int p, ST tok, S stack, S start, S need, SO ord) {
   const int64_t off = a.tok_offset[p];
   const int32_t L = a.tok_len[p];
   const int64_t coff = a.const_offset[p];
@@ -33,13 +44,10 @@ __device__ static void prepare_program(const PrepareArgs& a, int p) {
     status = BEAGLE_PROG_BAD_LAYOUT;
   }
   if (status == BEAGLE_PROG_OK) {
-    const uint16_t* tok = a.tokens + off;
-    int32_t* stack = a.scr_stack + off;   // pass 1: node stack; pass 2: output starts
-    int32_t* start = a.scr_start + off;
-    int32_t* need = a.scr_need + off;
+    // stack: node stack in pass 1, output starts in pass 2
     int depth = 0;
     for (int i = 0; i < L; ++i) {
-      const uint32_t t = tok[i];
+      const uint32_t t = uint32_t(tok.get(i));
       const uint32_t op = t & 0xFFu, arg = t >> 8;
       if (op >= N_OPCODES) { status = BEAGLE_PROG_BAD_OPCODE; break; }
       if (op == OP_VAR && int(arg) >= a.D) { status = BEAGLE_PROG_BAD_VAR; break; }
@@ -48,69 +56,69 @@ __device__ static void prepare_program(const PrepareArgs& a, int p) {
       const int ar = arity(op);
       if (depth < ar) { status = BEAGLE_PROG_UNDERFLOW; break; }
       if (ar == 0) {
-        start[i] = i;
-        need[i] = 1;
+        start.set(i, i);
+        need.set(i, 1);
       } else if (ar == 1) {
-        const int c = stack[depth - 1];
-        start[i] = start[c];
-        need[i] = need[c];
+        const int c = stack.get(depth - 1);
+        start.set(i, start.get(c));
+        need.set(i, need.get(c));
       } else {
-        const int r = stack[depth - 1], l = stack[depth - 2];
-        start[i] = start[l];
-        const int nl = need[l], nr = need[r];
-        need[i] = nl == nr ? nl + 1 : (nl > nr ? nl : nr);
+        const int r = stack.get(depth - 1), l = stack.get(depth - 2);
+        start.set(i, start.get(l));
+        const int nl = need.get(l), nr = need.get(r);
+        need.set(i, nl == nr ? nl + 1 : (nl > nr ? nl : nr));
       }
       depth += 1 - ar;
-      stack[depth - 1] = i;
+      stack.set(depth - 1, i);
     }
     if (status == BEAGLE_PROG_OK && depth != 1) status = BEAGLE_PROG_BAD_FINAL_DEPTH;
     if (status == BEAGLE_PROG_OK) {
-      need_root = need[L - 1];
+      need_root = need.get(L - 1);
       uint32_t* code = a.code + off;
       // pass 2: output start of every subtree, root first
-      int32_t* ostart = stack;
-      ostart[L - 1] = 0;
+      const S ostart = stack;
+      ostart.set(L - 1, 0);
       for (int i = L - 1; i >= 0; --i) {
-        const uint32_t t = tok[i];
+        const uint32_t t = uint32_t(tok.get(i));
         uint32_t op = t & 0xFFu;
         const uint32_t arg = t >> 8;
-        const int o = ostart[i];
-        const int size = i - start[i] + 1;
+        const int o = ostart.get(i);
+        const int size = i - start.get(i) + 1;
         const int ar = arity(op);
         if (ar == 1) {
-          ostart[i - 1] = o;
+          ostart.set(i - 1, o);
         } else if (ar == 2) {
-          const int r = i - 1, l = start[r] - 1;
-          const int size_l = l - start[l] + 1;
-          const int size_r = r - start[r] + 1;
-          if (need[r] > need[l]) {
-            ostart[r] = o;
-            ostart[l] = o + size_r;
+          const int r = i - 1, l = start.get(r) - 1;
+          const int size_l = l - start.get(l) + 1;
+          const int size_r = r - start.get(r) + 1;
+          if (need.get(r) > need.get(l)) {
+            ostart.set(r, o);
+            ostart.set(l, o + size_r);
             op = op == OP_SUB ? 100u + B_RSUB : (op == OP_DIV ? 100u + B_RDIV : op);
           } else {
-            ostart[l] = o;
-            ostart[r] = o + size_l;
+            ostart.set(l, o);
+            ostart.set(r, o + size_l);
           }
         }
-        code[o + size - 1] = op | (arg << 8);
+        ord.set(o + size - 1, int(op | (arg << 8)));
       }
       // pass 3: handler words, fusing "terminal, binary operator" pairs;
-      // decoded words are written back from the start (out <= i always).
+      // decoded words go to `code` (out <= i always, so `ord` may alias it).
       // Alongside, for the adjoint: aux[out] = pa | (rws << 16), pa = the
       // decoded word that produced the value below the top (binary words),
       // rws = the adjoint-stack slot the reverse sweep writes (see grad.hip);
       // `start` is free after pass 2 and holds the producer of each stack slot.
       float* cv = a.cval + off;
       uint32_t* aux = a.aux + off;
-      int32_t* prod = start;
+      const S prod = start;
       int n = 0, nmax = 0, out = 0;
       for (int i = 0; i < L; ++i) {
-        const uint32_t w = code[i];
+        const uint32_t w = uint32_t(ord.get(i));
         const uint32_t op = w & 0xFFu, arg = (w >> 8) & 0xFFu;
         const uint32_t wslot = n > 0 ? uint32_t(n - 1) : 0u;
         uint32_t h, pa = 0u, rws;
         const bool term = op == OP_VAR || op == OP_CONST;
-        const uint32_t nxt = i + 1 < L ? (code[i + 1] & 0xFFu) : 0xFFu;
+        const uint32_t nxt = i + 1 < L ? (uint32_t(ord.get(i + 1)) & 0xFFu) : 0xFFu;
         const bool next_bin = nxt < 4u || (nxt >= 100u && nxt < 106u);
         if (term && n >= 1 && next_bin) {
           // the pushed value is the right operand of the next operator and
@@ -120,24 +128,24 @@ __device__ static void prepare_program(const PrepareArgs& a, int p) {
           if (op == OP_CONST) cv[out] = a.consts[coff + arg];
           nmax = n + 1 > nmax ? n + 1 : nmax;
           rws = uint32_t(n - 1);
-          prod[n - 1] = out;
+          prod.set(n - 1, out);
           ++i;  // the operator is consumed; stack size unchanged
         } else if (term) {
           h = op == OP_VAR ? H_VAR : H_CONST;
           if (op == OP_CONST) cv[out] = a.consts[coff + arg];
           rws = uint32_t(n);
-          prod[n] = out;
+          prod.set(n, out);
           ++n;
         } else if (op >= 100u || op < 4) {
           h = op >= 100u ? h_bin(op - 100u, n) : h_bin(op, n);  // ADD..DIV: BinIdx == opcode
-          pa = uint32_t(prod[n - 2]);
+          pa = uint32_t(prod.get(n - 2));
           rws = uint32_t(n - 2);
           --n;
-          prod[n - 1] = out;
+          prod.set(n - 1, out);
         } else {
           h = H_UN + (op - OP_SIN);
           rws = uint32_t(n - 1);
-          prod[n - 1] = out;
+          prod.set(n - 1, out);
         }
         nmax = n > nmax ? n : nmax;
         // arg: variable index (VAR words), constant slot (CONST words), 0 otherwise
@@ -173,17 +181,62 @@ __device__ static void prepare_program(const PrepareArgs& a, int p) {
   }
 }
 
-__global__ void k_prepare(PrepareArgs a) {
+// Programs of at most PREP_SHORT tokens keep their scratch in LDS (16-bit
+// entries: token indices, needs and tokens all fit), longer ones in the
+// global scratch arrays.
+constexpr int PREP_BLOCK = 64;
+constexpr int PREP_SHORT = 128;
+
+struct PrepLds {
+  uint16_t tok[PREP_SHORT * PREP_BLOCK];
+  uint16_t stack[PREP_SHORT * PREP_BLOCK];
+  uint16_t start[PREP_SHORT * PREP_BLOCK];
+  uint16_t need[PREP_SHORT * PREP_BLOCK];
+  uint16_t ord[PREP_SHORT * PREP_BLOCK];
+};
+
+__device__ static void prepare_one(const PrepareArgs& a, int p, PrepLds& lds) {
+  const int64_t off = a.tok_offset[p];
+  const int32_t L = a.tok_len[p];
+  if (L >= 1 && L <= PREP_SHORT && off >= 0 && off + L <= a.n_tokens) {
+    using SL = Scratch<uint16_t, PREP_BLOCK>;
+    const int t = threadIdx.x;
+    // the tokens first, eight independent loads at a time
+    const uint16_t* src = a.tokens + off;
+    uint16_t* dst = lds.tok + t;
+    int i = 0;
+    for (; i + 8 <= L; i += 8) {
+      uint16_t v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = src[i + j];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) dst[(i + j) * PREP_BLOCK] = v[j];
+    }
+    for (; i < L; ++i) dst[i * PREP_BLOCK] = src[i];
+    prepare_program(a, p, SL{lds.tok + t}, SL{lds.stack + t}, SL{lds.start + t}, SL{lds.need + t},
+                    SL{lds.ord + t});
+  } else {
+    // (an invalid layout is reported before any scratch access)
+    const int64_t o = off >= 0 && off < a.n_tokens ? off : 0;
+    using SG = Scratch<int32_t, 1>;
+    prepare_program(a, p, Scratch<const uint16_t, 1>{a.tokens + o}, SG{a.scr_stack + o}, SG{a.scr_start + o},
+                    SG{a.scr_need + o}, Scratch<uint32_t, 1>{a.code + o});
+  }
+}
+
+__global__ void __launch_bounds__(PREP_BLOCK) k_prepare(PrepareArgs a) {
+  __shared__ PrepLds lds;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < a.n_programs) prepare_program(a, p);
+  if (p < a.n_programs) prepare_one(a, p, lds);
 }
 
 // One thread per program of every problem of the table.
-__global__ void k_prepare_batch(BatchArgs b) {
+__global__ void __launch_bounds__(PREP_BLOCK) k_prepare_batch(BatchArgs b) {
+  __shared__ PrepLds lds;
   const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (g >= b.n_programs) return;
   const int q = batch_find(b, g, [](const BatchProblem& t) { return t.prog_begin; });
-  prepare_program(b.table[q].prep, int(g - b.table[q].prog_begin));
+  prepare_one(b.table[q].prep, int(g - b.table[q].prog_begin), lds);
 }
 
 // X [M x D] row-major -> Xt [D x Mp] (case index fastest), y -> yp [Mp];

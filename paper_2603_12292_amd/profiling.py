@@ -29,8 +29,11 @@ from collections import defaultdict
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 COPY_BYTES = 256 << 20
-KERNEL = "k_eval_class<1, 0, 0>"
-EVAL_SOURCES = ["eval.hip", "beagle_device.h", "kernels.h"]
+# the correlation-fitness interpreter of the common register-need class; its
+# tile-width variant (<1, 0, 0>: 8 cases per lane, <1, 0, 1>: 4) is the one
+# the tuner picked, i.e. the one with the largest total time in the trace
+KERNEL_PREFIX = "k_eval_class<1, 0, "
+EVAL_SOURCES = ["eval.hip", "beagle_device.h", "kernels.h", "trig.h"]
 
 
 def source_hash() -> str:
@@ -73,11 +76,11 @@ def _counter_rows(path):
     return per, names
 
 
-def _counter(path, counter):
+def _counter(path, counter, kernel):
     per, names = _counter_rows(path)
-    evals = [per[d][counter] for d in sorted(per) if KERNEL in names[d]]
+    evals = [per[d][counter] for d in sorted(per) if kernel in names[d]]
     copies = [per[d][counter] for d in sorted(per)
-              if KERNEL not in names[d] and ("copy" in names[d].lower() or "elementwise" in names[d].lower())]
+              if "k_eval" not in names[d] and ("copy" in names[d].lower() or "elementwise" in names[d].lower())]
     return evals, copies
 
 
@@ -85,6 +88,7 @@ def summarize(trace_dir, fetch_csv, write_csv, out_prefix, command):
     stats = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
     lines = []
     kern_ms = None
+    kernel = None
     if stats:
         with open(stats[0]) as f:
             rows = list(csv.DictReader(f))
@@ -94,12 +98,13 @@ def summarize(trace_dir, fetch_csv, write_csv, out_prefix, command):
         for r in rows[:12]:
             lines.append(f"{int(r['Calls']):6d} {float(r['AverageNs']):12.1f} {float(r['TotalDurationNs']):14.1f} "
                          f"{float(r['Percentage']):6.2f}  {r['Name'][:90]}")
-            if KERNEL in r["Name"]:
+            if kernel is None and KERNEL_PREFIX in r["Name"]:
+                kernel = r["Name"][r["Name"].index("k_eval_class"):r["Name"].index(">") + 1]
                 kern_ms = float(r["AverageNs"]) / 1e6
-    rec = {"kernel": KERNEL, "source_hash": source_hash(), "avg_ms": kern_ms}
-    if fetch_csv and write_csv:
-        fe, fc = _counter(fetch_csv, "FETCH_SIZE")
-        we, wc = _counter(write_csv, "WRITE_SIZE")
+    rec = {"kernel": kernel, "source_hash": source_hash(), "avg_ms": kern_ms}
+    if fetch_csv and write_csv and kernel:
+        fe, fc = _counter(fetch_csv, "FETCH_SIZE", kernel)
+        we, wc = _counter(write_csv, "WRITE_SIZE", kernel)
         f_scale = COPY_BYTES / (max(fc) * 1024) if fc else None
         w_scale = COPY_BYTES / (max(wc) * 1024) if wc else None
         fetch = fe[-1] * 1024 * f_scale if fe and f_scale else None
@@ -114,7 +119,7 @@ def summarize(trace_dir, fetch_csv, write_csv, out_prefix, command):
         if fetch is not None and write is not None:
             lines.append(f"  fetch {fetch / 1e6:.3f} MB  write {write / 1e6:.3f} MB  total {(fetch + write) / 1e6:.3f} MB")
     lines.insert(0, f"command: {command}")
-    lines.insert(1, f"kernel {KERNEL}, source hash {rec['source_hash']}")
+    lines.insert(1, f"kernel {kernel}, source hash {rec['source_hash']}")
     with open(out_prefix + ".txt", "w") as f:
         f.write("\n".join(lines) + "\n")
     with open(out_prefix + "_traffic.json", "w") as f:
