@@ -80,12 +80,30 @@ __device__ __forceinline__ int arity(uint32_t op) { return op < 4 ? 2 : (op < 9 
 
 // ---- operator conventions (binary32) -------------------------------------
 __device__ __forceinline__ float op_div(float a, float b) { return b == 0.0f ? 1.0f : a / b; }
+// exp(clamp(x, -80, 80)) = 2^n 2^f with n = rint(x log2 e) and
+// f = x log2 e - n in [-1/2, 1/2], f formed with log2 e split into two
+// binary32 numbers so that its error stays below 2^-25; 2^f from the hardware
+// base-2 exponential, then an exact scaling.  The clamp keeps the result
+// normal (e^80 < 2^116, e^-80 > 2^-116), so no range checks are needed.
+// Comparisons keep NaN as NaN and map +-Inf to the clamp bounds.
 __device__ __forceinline__ float op_exp(float x) {
-  // comparisons keep NaN as NaN and map +-Inf to the clamp bounds
-  float c = x > 80.0f ? 80.0f : (x < -80.0f ? -80.0f : x);
-  return expf(c);
+  const float c = x > 80.0f ? 80.0f : (x < -80.0f ? -80.0f : x);
+  const float n = __builtin_rintf(c * 0x1.715476p+0f);
+  float f = __builtin_fmaf(c, 0x1.715476p+0f, -n);   // log2 e, high part
+  f = __builtin_fmaf(c, 0x1.4ae0c0p-26f, f);        // log2 e, low part
+  return __builtin_amdgcn_ldexpf(__builtin_amdgcn_exp2f(f), int(n));
 }
-__device__ __forceinline__ float op_log(float x) { return x == 0.0f ? 0.0f : logf(fabsf(x)); }
+// log|x| = log2|x| ln 2 (hardware base-2 logarithm; subnormal |x| scaled by
+// 2^32 first, whose log2 is then reduced by 32 exactly), ln 2 split into two
+// binary32 numbers of one sign (so log of +Inf stays +Inf); log of 0 is 0.
+__device__ __forceinline__ float op_log(float x) {
+  const float a = __builtin_fabsf(x);
+  const bool tiny = a < 0x1p-126f;
+  float y = __builtin_amdgcn_logf(tiny ? a * 0x1p32f : a);
+  y = tiny ? y - 32.0f : y;
+  const float r = __builtin_fmaf(y, 0x1.62e42ep-1f, y * 0x1.efa39ep-25f);  // ln 2, high and low parts
+  return x == 0.0f ? 0.0f : r;
+}
 __device__ __forceinline__ float op_sqrt(float x) { return sqrtf(fabsf(x)); }
 
 // Per-program metadata written by the preparation kernel.

@@ -1,4 +1,5 @@
-"""Constants of the library's binary32 sine and cosine (csrc/trig.h).
+"""Constants of the library's binary32 sine, cosine (csrc/trig.h), exponential
+and logarithm (csrc/beagle_device.h).
 
 Run: python -m paper_2603_12292_amd.csrc.minimax  (prints the C++ constants)
 
@@ -13,6 +14,9 @@ Run: python -m paper_2603_12292_amd.csrc.minimax  (prints the C++ constants)
    S(r^2), S of degree 3, minimising the maximum relative error with
    Lawson's iteratively reweighted least squares (C. L. Lawson, 1961), then
    rounded to binary32.
+4. log2(e) and ln(2) each split into a binary32 high part and the binary32
+   nearest to the remainder (Cody and Waite), for the exponential and the
+   logarithm built on the hardware base-2 functions.
 """
 from __future__ import annotations
 
@@ -58,6 +62,24 @@ def pi_split() -> tuple[float, float]:
     return hi, lo
 
 
+def exp_log_splits() -> tuple[float, float, float, float]:
+    """(log2e_hi, log2e_lo, ln2_hi, ln2_lo) as binary32 values (Python floats):
+    hi the largest binary32 not above the constant, lo the binary32 nearest to
+    the (positive) remainder, so that an infinite factor times hi and lo keeps
+    one sign."""
+    from decimal import Decimal, getcontext
+    getcontext().prec = 60
+    ln2 = Decimal(2).ln()
+    out = []
+    for v in (1 / ln2, ln2):
+        hi = np.float32(float(v))
+        if Decimal(float(hi)) > v:
+            hi = np.nextafter(hi, np.float32(0))
+        lo = float(np.float32(float(v - Decimal(float(hi)))))
+        out += [float(hi), lo]
+    return tuple(out)
+
+
 def _lawson(F, W, xs, deg, iters=400):
     A = np.stack([xs ** (2 * k) for k in range(deg)], 1)
     u = np.ones_like(xs) / len(xs)
@@ -85,6 +107,7 @@ def main():
     print("two_over_pi bits 1..224:", ", ".join(f"0x{w:08X}u" for w in words))
     print(f"pi_hi = {hi.hex()}  pi_lo = {lo.hex()}  1/pi = {(1 / np.pi).hex()}")
     print("S =", ", ".join(f"{float(v).hex()}" for v in s))
+    print("log2e hi, lo, ln2 hi, lo =", ", ".join(v.hex() for v in exp_log_splits()))
 
 
 if __name__ == "__main__":

@@ -249,6 +249,46 @@ def test_argument_errors():
         api.evaluate(ps, X[:1], y[:1], kind="corr")
 
 
+def _unary_outputs(op, x):
+    api = _api()
+    X = torch.from_numpy(np.asarray(x, dtype=np.float32).reshape(-1, 1).copy()).cuda()
+    progs = wl.pack_programs([([wl.tok(wl.VAR, 0), wl.tok(op)], [])])
+    return api.predict(_dev(progs), X).cpu().numpy()[0]
+
+
+def _max_ulp(out, ref):
+    assert np.array_equal(np.isnan(out), np.isnan(ref))
+    ok = ~np.isnan(ref)
+    assert np.array_equal(np.isinf(out[ok]), np.isinf(ref[ok]))
+    fin = ok & np.isfinite(ref)
+    ulp = np.spacing(np.abs(ref[fin]).astype(np.float32)).astype(np.float64)
+    return float((np.abs(out[fin].astype(np.float64) - ref[fin]) / ulp).max())
+
+
+def test_exp_log_accuracy():
+    """The interpreter's protected exp and log: within 2 ulp of binary64
+    exp(clamp(x, -80, 80)) and log|x| (log 0 = 0), on arguments spanning the
+    binary32 range, subnormals, values near 1, +-Inf and NaN."""
+    rng = np.random.default_rng(22)
+    special = np.array([0.0, -0.0, 1e-45, -1e-42, 1e-38, 1.0, -1.0, 80.0, -80.0, 80.5, -81.0, 88.0, np.inf,
+                        -np.inf, np.nan, 3.4028234663852886e38], dtype=np.float32)
+    xe = np.concatenate([rng.uniform(-90, 90, 40000), rng.uniform(-1e-3, 1e-3, 10000), special]).astype(np.float32)
+    with np.errstate(all="ignore"):
+        ref = np.exp(np.clip(xe.astype(np.float64), -80.0, 80.0))
+    e = _max_ulp(_unary_outputs(wl.EXP, xe), ref)
+    print("exp max ulp", e)
+    assert e <= 2.0
+    mag = np.exp(rng.uniform(np.log(1e-45), np.log(3e38), 40000))
+    xl = np.concatenate([mag * rng.choice([-1, 1], 40000), rng.uniform(0.9, 1.1, 20000),
+                         1 + rng.uniform(-1e-5, 1e-5, 5000), special]).astype(np.float32)
+    x64 = xl.astype(np.float64)
+    with np.errstate(all="ignore"):
+        ref = np.where(x64 == 0, 0.0, np.log(np.abs(x64)))
+    e = _max_ulp(_unary_outputs(wl.LOG, xl), ref)
+    print("log max ulp", e)
+    assert e <= 2.0
+
+
 def test_sin_cos_accuracy():
     """The interpreter's sine and cosine on arguments spanning the binary32
     range (both reduction paths, signed zeros, subnormals, +-Inf, NaN):

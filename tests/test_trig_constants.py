@@ -1,5 +1,6 @@
-"""The constants of the device sine/cosine (csrc/trig.h) are the ones
-csrc/minimax.py derives, and that derivation is pinned independently."""
+"""The constants of the device sine/cosine (csrc/trig.h), exponential and
+logarithm (csrc/beagle_device.h) are the ones csrc/minimax.py derives, and
+that derivation is pinned independently."""
 import math
 import os
 import re
@@ -59,3 +60,24 @@ def test_header_holds_the_derived_constants():
     body = text[text.index("float sin_poly"):text.index("trig_reduce_small")]
     lits = [float.fromhex(x.rstrip("f")) for x in re.findall(r"-?0x1\.[0-9a-f]+p[-+]?\d+f", body)]
     assert sorted(lits) == sorted(float(c) for c in minimax.poly_coefficients())
+
+
+def _c_hex(v: float) -> str:
+    """binary32 value as the kernels spell it: 0x1.hhhhhhp+e (6 hex digits)."""
+    m, e = v.hex().split("p")
+    sign = "-" if m.startswith("-") else ""
+    m = m.lstrip("-")
+    return f"{sign}{m[:10].ljust(10, '0')}p{e}"
+
+
+def test_exp_log_splits():
+    l2e_hi, l2e_lo, ln2_hi, ln2_lo = minimax.exp_log_splits()
+    for hi, lo, exact in ((l2e_hi, l2e_lo, 1 / math.log(2)), (ln2_hi, ln2_lo, math.log(2))):
+        assert np.float32(hi) == hi and np.float32(lo) == lo
+        # lo is the binary32 nearest to the positive remainder
+        assert abs(hi + lo - exact) <= float(np.spacing(np.float32(lo))) / 2 and lo > 0
+        assert abs(lo) <= np.spacing(np.float32(hi))
+    with open(os.path.join(os.path.dirname(minimax.__file__), "beagle_device.h")) as f:
+        text = f.read()
+    for v in minimax.exp_log_splits():
+        assert _c_hex(v) in text, _c_hex(v)
