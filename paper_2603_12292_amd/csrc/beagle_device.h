@@ -9,7 +9,7 @@
 // reversed operator, so values are unchanged), and writes one 32-bit
 // instruction word per token:
 //
-//     word = handler | (arg << 8) | (wslot << 16)
+//     word = handler | (arg << 8) | (wslot << 16) | (i0 << 24)
 //
 // arg is the variable index of VAR words, the constant slot of CONST words
 // (their value also sits in a side table by word position) and 0 otherwise.
@@ -33,6 +33,19 @@
 //                        (s = 0 VAR, 1 CONST): top = top op value; the
 //                        stack below top is untouched, so the pair costs one
 //                        dispatch and no stack traffic
+//
+// i0 is the handler of the small-stack interpreter (programs of register
+// need <= 4), which keeps no cached top: its handlers are specialised by n
+// as well and rewrite stack slots in place (push writes slot n, a binary
+// operator slot n-2, unary and fused words slot n-1), so no word moves data
+// between registers:
+//
+//     n                   VAR push at n = 0..3
+//     4 + n               CONST push at n
+//     8 + 3*o + (n-2)     binary operator o at n = 2..4
+//     26 + 4*u + (n-1)    unary operator u at n = 1..4
+//     46 + 3*(6*s+o) + (n-1)   fused pair at n = 1..3
+//     255                 (a word of a program that needs a deeper stack)
 //
 // Fused pairs make the decoded program shorter than the token program;
 // ProgMeta::len counts decoded words.  Programs are grouped by register
@@ -71,6 +84,12 @@ constexpr uint32_t H_CONST = 1;
 constexpr uint32_t H_BIN = 2;
 constexpr uint32_t H_UN = 2 + 15 * 6;  // 92
 constexpr uint32_t H_FUSED = H_UN + 5;  // 97
+constexpr uint32_t I0_PUSH_VAR = 0;
+constexpr uint32_t I0_PUSH_CONST = 4;
+constexpr uint32_t I0_BIN = 8;
+constexpr uint32_t I0_UN = 26;
+constexpr uint32_t I0_FUSED = 46;
+constexpr uint32_t I0_NONE = 255;
 constexpr int MAX_LEN = 4096;
 constexpr int MAX_D = 16;
 

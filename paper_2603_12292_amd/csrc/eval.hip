@@ -189,6 +189,111 @@ __device__ __forceinline__ void interpret(uint32_t vc0, float vv0, uint32_t vc1,
   }
 }
 
+// The small-stack interpreter (programs of register need <= 4): no cached
+// top; the handler index i0 (word bits 24..31) names the stack size, so each
+// handler reads and rewrites its slots in place and no word moves values
+// between registers.  st[k][j] is stack slot j of case k; the result is slot 0.
+template <int K>
+__device__ __forceinline__ void interpret_small(uint32_t vc0, float vv0, uint32_t vc1, float vv1,
+                                                const uint32_t* __restrict__ code, const float* __restrict__ cval,
+                                                int L, int lane, const float* xl, float (&res)[K]) {
+  constexpr int S = 4;
+  float st[K][S];
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int j = 0; j < S; ++j) st[k][j] = 0.0f;
+  for (int base = 0; base < L; base += 64) {
+    uint32_t vc;
+    float vv;
+    if (base == 0) {
+      vc = vc0;
+      vv = vv0;
+    } else if (base == 64) {
+      vc = vc1;
+      vv = vv1;
+    } else {
+      const int i = base + lane;
+      vc = i < L ? code[i] : 0u;
+      vv = i < L ? cval[i] : 0.0f;
+    }
+    const int n = __builtin_amdgcn_readfirstlane(L - base < 64 ? L - base : 64);
+    for (int t = 0; t < n; ++t) {
+      const uint32_t w = __builtin_amdgcn_readlane(vc, t);
+      const uint32_t arg = (w >> 8) & 0xFFu;
+      switch (w >> 24) {
+#define BGL_S_PUSH(N)                                                           \
+  case I0_PUSH_VAR + N: {                                                       \
+    const XRow<K> xv = load_row<K>(xl, arg);                                    \
+    _Pragma("unroll") for (int k = 0; k < K; ++k) st[k][N] = xv.v[k];           \
+    break;                                                                      \
+  }                                                                             \
+  case I0_PUSH_CONST + N: {                                                     \
+    const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vv), t)); \
+    _Pragma("unroll") for (int k = 0; k < K; ++k) st[k][N] = v;                 \
+    break;                                                                      \
+  }
+        BGL_S_PUSH(0) BGL_S_PUSH(1) BGL_S_PUSH(2) BGL_S_PUSH(3)
+#undef BGL_S_PUSH
+#define BGL_S_BIN(O, N)                                                         \
+  case I0_BIN + 3 * O + (N - 2):                                                \
+    _Pragma("unroll") for (int k = 0; k < K; ++k) st[k][N - 2] = binop<O>(st[k][N - 2], st[k][N - 1]); \
+    break;
+#define BGL_S_BIN3(O) BGL_S_BIN(O, 2) BGL_S_BIN(O, 3) BGL_S_BIN(O, 4)
+        BGL_S_BIN3(B_ADD) BGL_S_BIN3(B_SUB) BGL_S_BIN3(B_MUL) BGL_S_BIN3(B_DIV) BGL_S_BIN3(B_RSUB) BGL_S_BIN3(B_RDIV)
+#undef BGL_S_BIN3
+#undef BGL_S_BIN
+#define BGL_S_UN(N)                                                             \
+  case I0_UN + 0 * 4 + (N - 1): {                                               \
+    float c[K];                                                                 \
+    _Pragma("unroll") for (int k = 0; k < K; ++k) c[k] = st[k][N - 1];          \
+    trig_tile<false, K>(c);                                                     \
+    _Pragma("unroll") for (int k = 0; k < K; ++k) st[k][N - 1] = c[k];          \
+    break;                                                                      \
+  }                                                                             \
+  case I0_UN + 1 * 4 + (N - 1): {                                               \
+    float c[K];                                                                 \
+    _Pragma("unroll") for (int k = 0; k < K; ++k) c[k] = st[k][N - 1];          \
+    trig_tile<true, K>(c);                                                      \
+    _Pragma("unroll") for (int k = 0; k < K; ++k) st[k][N - 1] = c[k];          \
+    break;                                                                      \
+  }                                                                             \
+  case I0_UN + 2 * 4 + (N - 1):                                                 \
+    _Pragma("unroll") for (int k = 0; k < K; ++k) st[k][N - 1] = op_exp(st[k][N - 1]); \
+    break;                                                                      \
+  case I0_UN + 3 * 4 + (N - 1):                                                 \
+    _Pragma("unroll") for (int k = 0; k < K; ++k) st[k][N - 1] = op_log(st[k][N - 1]); \
+    break;                                                                      \
+  case I0_UN + 4 * 4 + (N - 1):                                                 \
+    _Pragma("unroll") for (int k = 0; k < K; ++k) st[k][N - 1] = op_sqrt(st[k][N - 1]); \
+    break;
+        BGL_S_UN(1) BGL_S_UN(2) BGL_S_UN(3) BGL_S_UN(4)
+#undef BGL_S_UN
+#define BGL_S_FUSED(O, N)                                                       \
+  case I0_FUSED + 3 * O + (N - 1): {                                            \
+    const XRow<K> xv = load_row<K>(xl, arg);                                    \
+    _Pragma("unroll") for (int k = 0; k < K; ++k) st[k][N - 1] = binop<O>(st[k][N - 1], xv.v[k]); \
+    break;                                                                      \
+  }                                                                             \
+  case I0_FUSED + 3 * (6 + O) + (N - 1): {                                      \
+    const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vv), t)); \
+    _Pragma("unroll") for (int k = 0; k < K; ++k) st[k][N - 1] = binop<O>(st[k][N - 1], v); \
+    break;                                                                      \
+  }
+#define BGL_S_FUSED3(O) BGL_S_FUSED(O, 1) BGL_S_FUSED(O, 2) BGL_S_FUSED(O, 3)
+        BGL_S_FUSED3(B_ADD) BGL_S_FUSED3(B_SUB) BGL_S_FUSED3(B_MUL) BGL_S_FUSED3(B_DIV) BGL_S_FUSED3(B_RSUB)
+        BGL_S_FUSED3(B_RDIV)
+#undef BGL_S_FUSED3
+#undef BGL_S_FUSED
+        default:
+          break;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) res[k] = st[k][0];
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
@@ -271,7 +376,10 @@ __device__ __forceinline__ void eval_block(const EvalArgs& a, int p, int c, doub
       __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the tile is in LDS
     }
     float top[K];
-    interpret<K, S>(vc0, vv0, vc1, vv1, code, cval, L, lane, xl, top);
+    if constexpr (S == 4)
+      interpret_small<K>(vc0, vv0, vc1, vv1, code, cval, L, lane, xl, top);
+    else
+      interpret<K, S>(vc0, vv0, vc1, vv1, code, cval, L, lane, xl, top);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const bool valid = base + (k / SUB) * SPAN + (K >= 4 ? 4 * lane + (k % 4) : k * 64 + lane) < a.M;

@@ -116,7 +116,7 @@ __device__ static void prepare_program(const PrepareArgs& a, int p, ST tok, S st
         const uint32_t w = uint32_t(ord.get(i));
         const uint32_t op = w & 0xFFu, arg = (w >> 8) & 0xFFu;
         const uint32_t wslot = n > 0 ? uint32_t(n - 1) : 0u;
-        uint32_t h, pa = 0u, rws;
+        uint32_t h, i0, pa = 0u, rws;
         const bool term = op == OP_VAR || op == OP_CONST;
         const uint32_t nxt = i + 1 < L ? (uint32_t(ord.get(i + 1)) & 0xFFu) : 0xFFu;
         const bool next_bin = nxt < 4u || (nxt >= 100u && nxt < 106u);
@@ -125,6 +125,7 @@ __device__ static void prepare_program(const PrepareArgs& a, int p, ST tok, S st
           // the current top its left one: top = top op value
           const uint32_t o = nxt >= 100u ? nxt - 100u : nxt;
           h = H_FUSED + 6u * (op == OP_CONST ? 1u : 0u) + o;
+          i0 = n <= 3 ? I0_FUSED + 3u * (6u * (op == OP_CONST ? 1u : 0u) + o) + uint32_t(n - 1) : I0_NONE;
           if (op == OP_CONST) cv[out] = a.consts[coff + arg];
           nmax = n + 1 > nmax ? n + 1 : nmax;
           rws = uint32_t(n - 1);
@@ -132,25 +133,28 @@ __device__ static void prepare_program(const PrepareArgs& a, int p, ST tok, S st
           ++i;  // the operator is consumed; stack size unchanged
         } else if (term) {
           h = op == OP_VAR ? H_VAR : H_CONST;
+          i0 = n <= 3 ? (op == OP_VAR ? I0_PUSH_VAR : I0_PUSH_CONST) + uint32_t(n) : I0_NONE;
           if (op == OP_CONST) cv[out] = a.consts[coff + arg];
           rws = uint32_t(n);
           prod.set(n, out);
           ++n;
         } else if (op >= 100u || op < 4) {
           h = op >= 100u ? h_bin(op - 100u, n) : h_bin(op, n);  // ADD..DIV: BinIdx == opcode
+          i0 = n <= 4 ? I0_BIN + 3u * (op >= 100u ? op - 100u : op) + uint32_t(n - 2) : I0_NONE;
           pa = uint32_t(prod.get(n - 2));
           rws = uint32_t(n - 2);
           --n;
           prod.set(n - 1, out);
         } else {
           h = H_UN + (op - OP_SIN);
+          i0 = n <= 4 ? I0_UN + 4u * (op - OP_SIN) + uint32_t(n - 1) : I0_NONE;
           rws = uint32_t(n - 1);
           prod.set(n - 1, out);
         }
         nmax = n > nmax ? n : nmax;
         // arg: variable index (VAR words), constant slot (CONST words), 0 otherwise
         const uint32_t warg = term ? arg : 0u;
-        code[out] = h | (warg << 8) | (wslot << 16);
+        code[out] = h | (warg << 8) | (wslot << 16) | (i0 << 24);
         aux[out] = pa | (rws << 16);
         ++out;
       }
