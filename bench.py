@@ -40,19 +40,20 @@ def function_nodes(ps) -> int:
     return int(np.count_nonzero(ops < 9))
 
 
-def traffic_from_profile(kernel: str):
-    """HBM bytes per launch of the interpreter kernel from the committed counter
-    summary, or None when the kernel source changed since it was taken or the
-    summary is of another tile-width variant."""
+def committed_counters(kernel: str) -> dict:
+    """Counter figures of the interpreter kernel from the committed profile
+    summary (HBM bytes per launch, VALU issue fraction), or {} when the kernel
+    source changed since they were taken or they are of another tile-width
+    variant."""
     from paper_2603_12292_amd.profiling import source_hash
     path = os.path.join(ROOT, "profiles", "k_eval_class_corr_plain_mid_traffic.json")
     if not os.path.exists(path):
-        return None
+        return {}
     with open(path) as f:
         rec = json.load(f)
     if rec.get("source_hash") != source_hash() or rec.get("kernel") != kernel:
-        return None
-    return rec.get("hbm_bytes_per_launch")
+        return {}
+    return rec
 
 
 def cpu_baseline(w, kind_id, budget_programs: int):
@@ -239,7 +240,8 @@ def main():
     fn = function_nodes(ps)
     alg_ops = fn * M                       # one fp32 op per operator application
     achieved = alg_ops / k_avg_s
-    traffic = traffic_from_profile(kernel)
+    counters = committed_counters(kernel)
+    traffic = counters.get("hbm_bytes_per_launch")
     out = {
         "metric": "GPop/s (program-node x fitness-case evals/s), fwd and fwd+adjoint, 1 MI355X",
         "value": round(gpops, 2),
@@ -261,7 +263,9 @@ def main():
                      "traffic": traffic,
                      "kernel": f"{kernel}: correlation fitness, register need <= 4, {width} cases per lane",
                      "kernel_ms": round(k_avg_s * 1e3, 4), "alg_ops_per_launch": alg_ops,
-                     "kernel_gpops": round(nodes * M / k_avg_s / 1e9, 2)},
+                     "kernel_gpops": round(nodes * M / k_avg_s / 1e9, 2),
+                     "valu_issue_frac": (round(counters["valu_issue_frac"], 4)
+                                         if "valu_issue_frac" in counters else None)},
     }
     if not args.no_adjoint:
         out["adjoint"] = adjoint_bench(args.steps, args.warmup)

@@ -5,7 +5,7 @@
       correlation fitness), then a 256 MiB device-to-device copy whose byte
       count is known, used to scale the HBM counters.
 
-  python -m paper_2603_12292_amd.profiling summarize --trace DIR --fetch CSV --write CSV --out PREFIX
+  python -m paper_2603_12292_amd.profiling summarize --trace DIR --fetch CSV --write CSV [--valu CSV] --out PREFIX
       reads the rocprofv3 kernel-trace statistics and the FETCH_SIZE /
       WRITE_SIZE counter CSVs of the run above and writes
       PREFIX.txt (duration and traffic summary) and PREFIX_traffic.json
@@ -14,7 +14,10 @@
 
 FETCH_SIZE and WRITE_SIZE count KiB moved between L2 and memory per
 dispatch; each is scaled by (known bytes / counted bytes) of the calibration
-copy, which reads and writes exactly COPY_BYTES.
+copy, which reads and writes exactly COPY_BYTES.  SQ_INSTS_VALU (wave-level
+VALU instructions per dispatch) times 64 lanes over the traced average
+duration gives the VALU lane-operations issued per second, against the
+chip's 39.3 T lane-operations/s (256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz).
 """
 from __future__ import annotations
 
@@ -29,6 +32,7 @@ from collections import defaultdict
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 COPY_BYTES = 256 << 20
+PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # the correlation-fitness interpreter of the common register-need class; its
 # tile-width variant (<1, 0, 0>: 8 cases per lane, <1, 0, 1>: 4) is the one
 # the tuner picked, i.e. the one with the largest total time in the trace
@@ -84,7 +88,7 @@ def _counter(path, counter, kernel):
     return evals, copies
 
 
-def summarize(trace_dir, fetch_csv, write_csv, out_prefix, command):
+def summarize(trace_dir, fetch_csv, write_csv, out_prefix, command, valu_csv=None):
     stats = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
     lines = []
     kern_ms = None
@@ -118,6 +122,16 @@ def summarize(trace_dir, fetch_csv, write_csv, out_prefix, command):
                      else "HBM traffic: calibration copy not found")
         if fetch is not None and write is not None:
             lines.append(f"  fetch {fetch / 1e6:.3f} MB  write {write / 1e6:.3f} MB  total {(fetch + write) / 1e6:.3f} MB")
+    if valu_csv and kernel and kern_ms:
+        ve, _ = _counter(valu_csv, "SQ_INSTS_VALU", kernel)
+        if ve:
+            lane_ops = ve[-1] * 64
+            rate = lane_ops / (kern_ms * 1e-3)
+            rec.update({"valu_lane_ops_per_launch": lane_ops, "valu_lane_ops_per_s": rate,
+                        "valu_issue_frac": rate / PEAK_LANE_OPS})
+            lines.append("")
+            lines.append(f"VALU issue (SQ_INSTS_VALU x 64 / traced average duration): {lane_ops:.4g} lane-ops per launch, "
+                         f"{rate / 1e12:.2f} T lane-ops/s = {rate / PEAK_LANE_OPS:.3f} of {PEAK_LANE_OPS / 1e12:.1f} T")
     lines.insert(0, f"command: {command}")
     lines.insert(1, f"kernel {kernel}, source hash {rec['source_hash']}")
     with open(out_prefix + ".txt", "w") as f:
@@ -136,13 +150,14 @@ def main():
     s.add_argument("--trace", required=True)
     s.add_argument("--fetch")
     s.add_argument("--write")
+    s.add_argument("--valu")
     s.add_argument("--out", required=True)
     s.add_argument("--command", default="")
     a = ap.parse_args()
     if a.cmd == "run":
         run(a.steps)
     else:
-        summarize(a.trace, a.fetch, a.write, a.out, a.command)
+        summarize(a.trace, a.fetch, a.write, a.out, a.command, a.valu)
 
 
 if __name__ == "__main__":
