@@ -136,8 +136,8 @@ EvalLayout eval_layout(const beagle_programs* P, const beagle_dataset* d, int n_
   L.meta = c.take<bgl::ProgMeta>(N);
   L.class_count = c.take<int32_t>(64);  // [0..2] need classes, [8..9] length classes
   L.class_list = c.take<int32_t>(size_t(bgl::N_CLASSES) * N);
-  L.len_list = c.take<int32_t>(size_t(2) * N);
-  L.work = c.take<unsigned long long>(bgl::N_CLASSES);
+  L.len_list = c.take<int32_t>(size_t(4) * N);
+  L.work = c.take<unsigned long long>(8);  // evaluation: one per class; adjoint: one per list
   L.Mp = round_up(d->M, bgl::CASES_PER_BLOCK_ITER);
   L.Xt = c.take<float>(size_t(d->D) * L.Mp);
   L.yp = c.take<float>(L.Mp);
@@ -581,7 +581,7 @@ beagle_status beagle_eval_grad(beagle_ctx* ctx, const beagle_programs* progs, co
   if (st != BEAGLE_OK) return st;
   char* ws = ctx->ws;
   unsigned long long* work = reinterpret_cast<unsigned long long*>(ws + L.work);
-  zero_i32(reinterpret_cast<int32_t*>(work), 2 * bgl::N_CLASSES, s);
+  zero_i32(reinterpret_cast<int32_t*>(work), 2 * 8, s);
   bgl::GradArgs ga;
   ga.code = reinterpret_cast<const uint32_t*>(ws + L.code);
   ga.aux = reinterpret_cast<const uint32_t*>(ws + L.aux);

@@ -11,6 +11,7 @@ namespace bgl {
 
 constexpr int GRAD_SHORT_WORDS = 64;   // tape in registers up to this many decoded words
 constexpr int GRAD_LONG_WORDS = 256;   // tape in LDS up to this many (longer: TOO_LONG)
+constexpr int GRAD_SMALL_WORDS = 48;   // small-stack adjoint (2 cases per lane) up to this many
 
 struct GradArgs {
   const uint32_t* code;
@@ -30,9 +31,9 @@ struct GradArgs {
   double* part;        // [n_chunks][n_programs] sums of squared errors
   double* gpart;       // [n_chunks][n_consts] gradient partials
   int64_t n_consts;
-  const int32_t* list_count;  // [2]: programs with short / long tapes
-  const int32_t* list;        // [2][n_programs]
-  unsigned long long* work;   // [2] work-item counters, zero at launch
+  const int32_t* list_count;  // [4]: short tape, long tape, small stack <= 48 words, small stack <= 64
+  const int32_t* list;        // [4][n_programs]
+  unsigned long long* work;   // [4] work-item counters, zero at launch
 };
 
 struct GradFinalizeArgs {

@@ -51,14 +51,14 @@ __device__ __forceinline__ void dbinop(float A, float B, float& dA, float& dB) {
   if constexpr (O == B_MUL) { dA = B; dB = A; }
   if constexpr (O == B_DIV) {
     const bool nz = B != 0.0f;
-    const float r = 1.0f / (nz ? B : 1.0f);
+    const float r = __builtin_amdgcn_rcpf(nz ? B : 1.0f);
     dA = nz ? r : 0.0f;
     dB = nz ? -A * r * r : 0.0f;
   }
   if constexpr (O == B_RSUB) { dA = -1.0f; dB = 1.0f; }
   if constexpr (O == B_RDIV) {
     const bool nz = A != 0.0f;
-    const float r = 1.0f / (nz ? A : 1.0f);
+    const float r = __builtin_amdgcn_rcpf(nz ? A : 1.0f);
     dA = nz ? -B * r * r : 0.0f;
     dB = nz ? r : 0.0f;
   }
@@ -77,8 +77,8 @@ __device__ __forceinline__ float dunary(uint32_t u, float x, float y) {
     case 0: return trig1<true>(x);
     case 1: return -trig1<false>(x);
     case 2: return (x > 80.0f || x < -80.0f) ? 0.0f : y;
-    case 3: return x != 0.0f ? 1.0f / x : 0.0f;
-    default: return x != 0.0f ? copysignf(0.5f, x) / y : 0.0f;
+    case 3: return x != 0.0f ? __builtin_amdgcn_rcpf(x) : 0.0f;
+    default: return x != 0.0f ? copysignf(0.5f, x) * __builtin_amdgcn_rcpf(y) : 0.0f;
   }
 }
 
@@ -352,6 +352,337 @@ __global__ void __launch_bounds__(64) k_grad(GradArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// The small-stack adjoint: programs of register need <= 4 with at most
+// GRAD_SMALL_WORDS decoded words (list 2), GK cases per lane.  The forward
+// pass uses the small-stack handlers (word bits 24..31, stack size n known
+// per handler): every stack slot and every adjoint slot is a register named
+// at compile time, and each handler writes the value it produced into the
+// tape itself.  The tape is four register arrays (case 0 / 1, words 0..31 /
+// 32..GRAD_SMALL_WORDS-1; an index can address at most a 32-entry array).  Reverse, for a word at stack size n:
+//   push            slot n's adjoint is the pushed value's (CONST: its slot's
+//                   gradient), and the slot is dropped;
+//   binary          A[n-1] = A[n-2] d/db,  A[n-2] = A[n-2] d/da  with
+//                   a = output of word pa, b = output of word t-1;
+//   unary, fused    A[n-1] scaled by the local derivative (fused CONST words
+//                   also add A[n-1] d/dc to their slot's gradient).
+constexpr int GK = 2;
+// whether the partial derivatives of binary operator o read its operands
+__host__ __device__ constexpr bool uses_operands(uint32_t o) { return o == B_MUL || o == B_DIV || o == B_RDIV; }
+
+template <bool COS>
+__device__ __forceinline__ void trig2(float& a, float& b) {
+  float v[GK] = {a, b};
+  trig_tile<COS, GK>(v);
+  a = v[0];
+  b = v[1];
+}
+
+// one forward word into tape position ti of arrays T0 (case 0) and T1 (case 1)
+template <int NT>
+__device__ __forceinline__ void small_fwd(uint32_t w, float cv, const float* xl, float (&st)[GK][4], float (&T0)[NT],
+                                          float (&T1)[NT], int ti) {
+  const uint32_t arg = (w >> 8) & 0xFFu;
+  const float* xr = xl + arg * (GK * 64);
+#define BGL_PUT(J) \
+  T0[ti] = st[0][J]; \
+  T1[ti] = st[1][J];
+  switch (w >> 24) {
+#define BGL_F_PUSH(N)                    \
+  case I0_PUSH_VAR + N:                  \
+    st[0][N] = xr[0];                    \
+    st[1][N] = xr[64];                   \
+    BGL_PUT(N) break;                    \
+  case I0_PUSH_CONST + N:                \
+    st[0][N] = cv;                       \
+    st[1][N] = cv;                       \
+    BGL_PUT(N) break;
+    BGL_F_PUSH(0) BGL_F_PUSH(1) BGL_F_PUSH(2) BGL_F_PUSH(3)
+#undef BGL_F_PUSH
+#define BGL_F_BIN(O, N)                                   \
+  case I0_BIN + 3 * O + (N - 2):                          \
+    st[0][N - 2] = gbinop<O>(st[0][N - 2], st[0][N - 1]); \
+    st[1][N - 2] = gbinop<O>(st[1][N - 2], st[1][N - 1]); \
+    BGL_PUT(N - 2) break;
+#define BGL_F_BIN3(O) BGL_F_BIN(O, 2) BGL_F_BIN(O, 3) BGL_F_BIN(O, 4)
+    BGL_F_BIN3(B_ADD) BGL_F_BIN3(B_SUB) BGL_F_BIN3(B_MUL) BGL_F_BIN3(B_DIV) BGL_F_BIN3(B_RSUB) BGL_F_BIN3(B_RDIV)
+#undef BGL_F_BIN3
+#undef BGL_F_BIN
+#define BGL_F_UN(N)                                              \
+  case I0_UN + 0 * 4 + (N - 1):                                  \
+    trig2<false>(st[0][N - 1], st[1][N - 1]);                    \
+    BGL_PUT(N - 1) break;                                        \
+  case I0_UN + 1 * 4 + (N - 1):                                  \
+    trig2<true>(st[0][N - 1], st[1][N - 1]);                     \
+    BGL_PUT(N - 1) break;                                        \
+  case I0_UN + 2 * 4 + (N - 1):                                  \
+    st[0][N - 1] = op_exp(st[0][N - 1]);                         \
+    st[1][N - 1] = op_exp(st[1][N - 1]);                         \
+    BGL_PUT(N - 1) break;                                        \
+  case I0_UN + 3 * 4 + (N - 1):                                  \
+    st[0][N - 1] = op_log(st[0][N - 1]);                         \
+    st[1][N - 1] = op_log(st[1][N - 1]);                         \
+    BGL_PUT(N - 1) break;                                        \
+  case I0_UN + 4 * 4 + (N - 1):                                  \
+    st[0][N - 1] = op_sqrt(st[0][N - 1]);                        \
+    st[1][N - 1] = op_sqrt(st[1][N - 1]);                        \
+    BGL_PUT(N - 1) break;
+    BGL_F_UN(1) BGL_F_UN(2) BGL_F_UN(3) BGL_F_UN(4)
+#undef BGL_F_UN
+#define BGL_F_FUSED(O, N)                                 \
+  case I0_FUSED + 3 * O + (N - 1):                        \
+    st[0][N - 1] = gbinop<O>(st[0][N - 1], xr[0]);        \
+    st[1][N - 1] = gbinop<O>(st[1][N - 1], xr[64]);       \
+    BGL_PUT(N - 1) break;                                 \
+  case I0_FUSED + 3 * (6 + O) + (N - 1):                  \
+    st[0][N - 1] = gbinop<O>(st[0][N - 1], cv);           \
+    st[1][N - 1] = gbinop<O>(st[1][N - 1], cv);           \
+    BGL_PUT(N - 1) break;
+#define BGL_F_FUSED3(O) BGL_F_FUSED(O, 1) BGL_F_FUSED(O, 2) BGL_F_FUSED(O, 3)
+    BGL_F_FUSED3(B_ADD) BGL_F_FUSED3(B_SUB) BGL_F_FUSED3(B_MUL) BGL_F_FUSED3(B_DIV) BGL_F_FUSED3(B_RSUB)
+    BGL_F_FUSED3(B_RDIV)
+#undef BGL_F_FUSED3
+#undef BGL_F_FUSED
+    default:
+      break;
+  }
+#undef BGL_PUT
+}
+
+// local derivative of unary operator u for the two cases (x: input, y: output)
+template <int U>
+__device__ __forceinline__ void dunary2(float x0, float x1, float y0, float y1, float& d0, float& d1) {
+  if constexpr (U == 0) {
+    d0 = x0;
+    d1 = x1;
+    trig2<true>(d0, d1);
+  } else if constexpr (U == 1) {
+    d0 = x0;
+    d1 = x1;
+    trig2<false>(d0, d1);
+    d0 = -d0;
+    d1 = -d1;
+  } else {
+    d0 = dunary(uint32_t(U), x0, y0);
+    d1 = dunary(uint32_t(U), x1, y1);
+  }
+}
+
+template <int LANE_SLOTS_>
+__device__ __forceinline__ void add_const_grad(uint32_t arg, float g0, float g1, bool v0, bool v1, double* lg,
+                                               double* wg, int lane) {
+  const double v = (v0 ? double(g0) : 0.0) + (v1 ? double(g1) : 0.0);
+  if (arg < uint32_t(LANE_SLOTS_)) {
+    lg[arg * 64] += v;
+  } else {
+    const double sv = wave_sum_d(v);
+    if (lane == 0) wg[arg] += sv;
+  }
+}
+
+template <int SMALL_HI>  // tape entries of words 32.. per case
+__device__ void grad_small_item(const GradArgs& a, int p, int c, float* lds) {
+  const int lane = threadIdx.x;
+  const ProgMeta m = a.meta[p];
+  const int L = m.len;
+  const int64_t off = a.tok_offset[p];
+  const int64_t coff = a.const_offset[p];
+  const int cc = a.const_count[p];
+  const uint32_t vmask = uint32_t(__builtin_amdgcn_readfirstlane(int(m.vmask)));
+  const uint32_t vc = lane < L ? a.code[off + lane] : 0u;
+  const uint32_t va = lane < L ? a.aux[off + lane] : 0u;
+  const float vv = lane < L ? a.cval[off + lane] : 0.0f;
+  // LDS: input tile [D][GK][64] | lane gradients [8][64] doubles | wave gradients [256] doubles
+  float* xl = lds + lane;
+  double* lg = reinterpret_cast<double*>(lds + a.D * GK * 64) + lane;
+  double* wg = reinterpret_cast<double*>(lds + a.D * GK * 64) + LANE_SLOTS * 64;
+  float t0lo[32], t0hi[SMALL_HI], t1lo[32], t1hi[SMALL_HI];
+  auto tg0 = [&](int t) -> float {
+    const float x = opaque(t0lo[t & 31]);
+    const float y = opaque(t0hi[t & (SMALL_HI - 1)]);
+    return t < 32 ? x : y;
+  };
+  auto tg1 = [&](int t) -> float {
+    const float x = opaque(t1lo[t & 31]);
+    const float y = opaque(t1hi[t & (SMALL_HI - 1)]);
+    return t < 32 ? x : y;
+  };
+  for (int j = 0; j < LANE_SLOTS; ++j) lg[j * 64] = 0.0;
+  for (int j = lane; j < 256; j += 64) wg[j] = 0.0;
+  __builtin_amdgcn_wave_barrier();
+  double s_mse = 0.0;
+  const float inv2m = float(2.0 / double(a.M));
+  const int64_t c0 = int64_t(c) * a.chunk;
+  const int64_t c1 = c0 + a.chunk < a.M ? c0 + a.chunk : a.M;
+  for (int64_t base = c0; base < c1; base += GK * 64) {
+    const int64_t i0 = base + lane, i1 = base + 64 + lane;
+    const bool v0 = i0 < a.M, v1 = i1 < a.M;
+    for (int d = 0; d < a.D; ++d) {
+      if (!((vmask >> d) & 1u)) continue;
+      const float x0 = a.Xt[int64_t(d) * a.Mp + i0];
+      const float x1 = a.Xt[int64_t(d) * a.Mp + i1];
+      xl[(d * GK) * 64] = x0;
+      xl[(d * GK + 1) * 64] = x1;
+    }
+    const float y0 = a.yp[i0], y1 = a.yp[i1];
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the tile is in LDS
+    // ---- forward with tape
+    float st[GK][4];
+#pragma unroll
+    for (int k = 0; k < GK; ++k)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) st[k][j] = 0.0f;
+    const float* xt = lds + lane;
+    const int L0 = L < 32 ? L : 32;
+    for (int t = 0; t < L0; ++t) {
+      const uint32_t w = __builtin_amdgcn_readlane(vc, t);
+      const float cv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vv), t));
+      small_fwd<32>(w, cv, xt, st, t0lo, t1lo, t);
+    }
+    for (int t = 32; t < L; ++t) {
+      const uint32_t w = __builtin_amdgcn_readlane(vc, t);
+      const float cv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vv), t));
+      small_fwd<SMALL_HI>(w, cv, xt, st, t0hi, t1hi, t - 32);
+    }
+    // ---- seed and fitness terms
+    const double e0 = double(st[0][0]) - double(y0), e1 = double(st[1][0]) - double(y1);
+    s_mse += (v0 ? e0 * e0 : 0.0) + (v1 ? e1 * e1 : 0.0);
+    float A[GK][4];
+#pragma unroll
+    for (int k = 0; k < GK; ++k)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) A[k][j] = 0.0f;
+    A[0][0] = v0 ? float(e0) * inv2m : 0.0f;
+    A[1][0] = v1 ? float(e1) * inv2m : 0.0f;
+    // ---- reverse
+    for (int t = L - 1; t >= 0; --t) {
+      const uint32_t w = __builtin_amdgcn_readlane(vc, t);
+      const uint32_t xw = __builtin_amdgcn_readlane(va, t);
+      const float cv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vv), t));
+      const uint32_t arg = (w >> 8) & 0xFFu;
+      const int pa = int(xw & 0xFFFFu);
+      const float* xr = xt + arg * (GK * 64);
+      switch (w >> 24) {
+#define BGL_R_PUSH(N)                                              \
+  case I0_PUSH_VAR + N:                                            \
+    break;                                                         \
+  case I0_PUSH_CONST + N:                                          \
+    add_const_grad<LANE_SLOTS>(arg, A[0][N], A[1][N], v0, v1, lg, wg, lane); \
+    break;
+        BGL_R_PUSH(0) BGL_R_PUSH(1) BGL_R_PUSH(2) BGL_R_PUSH(3)
+#undef BGL_R_PUSH
+#define BGL_R_BIN(O, N)                                           \
+  case I0_BIN + 3 * O + (N - 2): {                                \
+    float dA0, dB0, dA1, dB1;                                     \
+    if constexpr (uses_operands(O)) {                             \
+      dbinop<O>(tg0(pa), tg0(t - 1), dA0, dB0);                   \
+      dbinop<O>(tg1(pa), tg1(t - 1), dA1, dB1);                   \
+    } else {                                                      \
+      dbinop<O>(0.0f, 0.0f, dA0, dB0);                            \
+      dbinop<O>(0.0f, 0.0f, dA1, dB1);                            \
+    }                                                             \
+    A[0][N - 1] = A[0][N - 2] * dB0;                              \
+    A[1][N - 1] = A[1][N - 2] * dB1;                              \
+    A[0][N - 2] = A[0][N - 2] * dA0;                              \
+    A[1][N - 2] = A[1][N - 2] * dA1;                              \
+    break;                                                        \
+  }
+#define BGL_R_BIN3(O) BGL_R_BIN(O, 2) BGL_R_BIN(O, 3) BGL_R_BIN(O, 4)
+        BGL_R_BIN3(B_ADD) BGL_R_BIN3(B_SUB) BGL_R_BIN3(B_MUL) BGL_R_BIN3(B_DIV) BGL_R_BIN3(B_RSUB) BGL_R_BIN3(B_RDIV)
+#undef BGL_R_BIN3
+#undef BGL_R_BIN
+#define BGL_R_UN1(U, N)                                            \
+  case I0_UN + U * 4 + (N - 1): {                                  \
+    float d0, d1;                                                  \
+    if constexpr (U == 2 || U == 4)                                \
+      dunary2<U>(tg0(t - 1), tg1(t - 1), tg0(t), tg1(t), d0, d1);  \
+    else                                                           \
+      dunary2<U>(tg0(t - 1), tg1(t - 1), 0.0f, 0.0f, d0, d1);      \
+    A[0][N - 1] *= d0;                                             \
+    A[1][N - 1] *= d1;                                             \
+    break;                                                         \
+  }
+#define BGL_R_UN(N) BGL_R_UN1(0, N) BGL_R_UN1(1, N) BGL_R_UN1(2, N) BGL_R_UN1(3, N) BGL_R_UN1(4, N)
+        BGL_R_UN(1) BGL_R_UN(2) BGL_R_UN(3) BGL_R_UN(4)
+#undef BGL_R_UN
+#undef BGL_R_UN1
+#define BGL_R_FUSED(O, N)                                          \
+  case I0_FUSED + 3 * O + (N - 1): {                               \
+    float dA0, dB0, dA1, dB1;                                      \
+    if constexpr (uses_operands(O)) {                              \
+      dbinop<O>(tg0(t - 1), xr[0], dA0, dB0);                      \
+      dbinop<O>(tg1(t - 1), xr[64], dA1, dB1);                     \
+    } else {                                                       \
+      dbinop<O>(0.0f, 0.0f, dA0, dB0);                             \
+      dbinop<O>(0.0f, 0.0f, dA1, dB1);                             \
+    }                                                              \
+    A[0][N - 1] *= dA0;                                            \
+    A[1][N - 1] *= dA1;                                            \
+    break;                                                         \
+  }                                                                \
+  case I0_FUSED + 3 * (6 + O) + (N - 1): {                         \
+    float dA0, dB0, dA1, dB1;                                      \
+    if constexpr (uses_operands(O)) {                              \
+      dbinop<O>(tg0(t - 1), cv, dA0, dB0);                         \
+      dbinop<O>(tg1(t - 1), cv, dA1, dB1);                         \
+    } else {                                                       \
+      dbinop<O>(0.0f, 0.0f, dA0, dB0);                             \
+      dbinop<O>(0.0f, 0.0f, dA1, dB1);                             \
+    }                                                              \
+    add_const_grad<LANE_SLOTS>(arg, A[0][N - 1] * dB0, A[1][N - 1] * dB1, v0, v1, lg, wg, lane); \
+    A[0][N - 1] *= dA0;                                            \
+    A[1][N - 1] *= dA1;                                            \
+    break;                                                         \
+  }
+#define BGL_R_FUSED3(O) BGL_R_FUSED(O, 1) BGL_R_FUSED(O, 2) BGL_R_FUSED(O, 3)
+        BGL_R_FUSED3(B_ADD) BGL_R_FUSED3(B_SUB) BGL_R_FUSED3(B_MUL) BGL_R_FUSED3(B_DIV) BGL_R_FUSED3(B_RSUB)
+        BGL_R_FUSED3(B_RDIV)
+#undef BGL_R_FUSED3
+#undef BGL_R_FUSED
+        default:
+          break;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  // ---- reductions (fixed order) and partial outputs
+  s_mse = wave_sum_d(s_mse);
+  if (lane == 0) a.part[int64_t(c) * a.n_programs + p] = s_mse;
+  double* gp = a.gpart + int64_t(c) * a.n_consts + coff;
+  const int nl = cc < LANE_SLOTS ? cc : LANE_SLOTS;
+  for (int j = 0; j < nl; ++j) {
+    const double v = wave_sum_d(lg[j * 64]);
+    if (lane == 0) gp[j] = v;
+  }
+  __builtin_amdgcn_wave_barrier();
+  for (int j = LANE_SLOTS + lane; j < cc; j += 64) gp[j] = wg[j];
+  __builtin_amdgcn_wave_barrier();
+}
+
+// LIST 2: at most GRAD_SMALL_WORDS words (a 16-entry upper tape keeps the
+// kernel within 168 VGPRs: 3 waves per SIMD); LIST 3: at most
+// GRAD_SHORT_WORDS (32-entry upper tape, 2 waves per SIMD).
+template <int LIST>
+__global__ void __launch_bounds__(64) k_grad_small(GradArgs a) {
+  extern __shared__ float lds[];
+  constexpr int HI = LIST == 2 ? GRAD_SMALL_WORDS - 32 : GRAD_SHORT_WORDS - 32;
+  const int32_t count = a.list_count[LIST];
+  const int64_t items = int64_t(count) * a.n_chunks;
+  const int32_t* list = a.list + LIST * int64_t(a.n_programs);
+  for (;;) {
+    unsigned long long it = 0;
+    if (threadIdx.x == 0) it = atomicAdd(a.work + LIST, 1ull);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(it));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(it >> 32));
+    const int64_t item = int64_t((uint64_t(hi) << 32) | lo);
+    if (item >= items) break;
+    const int c = int(item / count);
+    const int p = list[item % count];
+    grad_small_item<HI>(a, p, c, lds);
+  }
+}
+
 __global__ void k_grad_finalize(GradFinalizeArgs a) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= a.n_programs) return;
@@ -393,11 +724,20 @@ size_t grad_lds_bytes(int D, bool long_tape) {
 hipError_t launch_grad(const GradArgs& a, hipStream_t s) {
   const int cus = grad_cu_count();
   const size_t l0 = grad_lds_bytes(a.D, false), l1 = grad_lds_bytes(a.D, true);
-  int nb0 = 0, nb1 = 0;
+  const size_t l2 = size_t(a.D) * GK * 64 * sizeof(float) + (size_t(LANE_SLOTS) * 64 + 256) * sizeof(double);
+  int nb0 = 0, nb1 = 0, nb2 = 0, nb3 = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb0, k_grad<false>, 64, l0) != hipSuccess || nb0 < 1) nb0 = 1;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb1, k_grad<true>, 64, l1) != hipSuccess || nb1 < 1) nb1 = 1;
-  hipLaunchKernelGGL(k_grad<false>, dim3(nb0 * cus), dim3(64), l0, s, a);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb2, k_grad_small<2>, 64, l2) != hipSuccess || nb2 < 1) nb2 = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb3, k_grad_small<3>, 64, l2) != hipSuccess || nb3 < 1) nb3 = 1;
+  hipLaunchKernelGGL(k_grad_small<2>, dim3(nb2 * cus), dim3(64), l2, s, a);
   hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_grad_small<3>, dim3(nb3 * cus), dim3(64), l2, s, a);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_grad<false>, dim3(nb0 * cus), dim3(64), l0, s, a);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_grad<true>, dim3(nb1 * cus), dim3(64), l1, s, a);
   return hipGetLastError();

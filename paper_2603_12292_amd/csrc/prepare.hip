@@ -1,6 +1,7 @@
 // Program preparation (validation, Sethi-Ullman re-serialisation, decoding)
 // and fitness-case staging.
 #include "beagle_device.h"
+#include "grad.h"
 #include "kernels.h"
 
 namespace bgl {
@@ -179,7 +180,9 @@ __device__ static void prepare_program(const PrepareArgs& a, int p, ST tok, S st
     const int slot = atomicAdd(a.class_count + cls, 1);
     a.class_list[int64_t(cls) * a.n_programs + slot] = p;
     // and by decoded length (the adjoint keeps short tapes in registers)
-    const int lc = L_dec <= a.short_words ? 0 : 1;
+    // adjoint lists: 0 short tape, 1 long tape; register need <= 4: 2 at
+    // most GRAD_SMALL_WORDS words, 3 at most short_words
+    const int lc = L_dec > a.short_words ? 1 : (need_root > 4 ? 0 : (L_dec <= GRAD_SMALL_WORDS ? 2 : 3));
     const int ls = atomicAdd(a.len_count + lc, 1);
     a.len_list[int64_t(lc) * a.n_programs + ls] = p;
   }
