@@ -23,8 +23,8 @@ Modes (conditioning only; the reference gradient is "o64"):
   "o32e"  every forward value, every partial derivative and every adjoint
           product rounded to binary32 (the per-case arithmetic of an fp32
           adjoint), sums over cases still exact;
-  "o32p"  as o32e, with sin/cos/exp/log results and the derivative values
-          computed from transcendental functions perturbed by a few ulps
+  "o32p"  as o32e, with sin/cos/exp/log/sqrt results and the derivative
+          values computed from transcendental functions perturbed by a few ulps
           (seeded), as in oracle.interp.
 A gradient component is stable under these modes when an fp32 adjoint can
 reproduce it; where per-case contributions cancel it is not.
@@ -187,7 +187,7 @@ def _tape_rounded(tokens, c64, X64, R, RT):
         else:
             rx = pos_stack.pop()
             v = interp.apply_op(op, None, None, values[rx])
-            values.append(RT(v) if op in (SIN, COS, EXP, LOG) else R(v))
+            values.append(RT(v) if op in (SIN, COS, EXP, LOG, SQRT) else R(v))
             children.append((rx,))
         pos_stack.append(i)
     return values, children

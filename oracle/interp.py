@@ -27,11 +27,11 @@ Modes
          fp32 arithmetic exactly (binary64 has more than 2*24+2 bits, so the
          double rounding is innocuous); for sin, cos, exp, log it is the
          binary64 libm value rounded once.
-  "o32p" o32e with the binary64 result of every sin, cos, exp and log
-         token first scaled by (1 + e), e uniform in [-2^-22, 2^-22] (a few
-         binary32 ulps), drawn from a seeded generator: a model of a binary32
-         implementation whose + - * / sqrt are correctly rounded and whose
-         transcendental functions are accurate to a few ulps.  Used only to
+  "o32p" o32e with the binary64 result of every sin, cos, exp, log and
+         sqrt token first scaled by (1 + e), e uniform in [-2^-22, 2^-22] (a
+         few binary32 ulps), drawn from a seeded generator: a model of a
+         binary32 implementation whose + - * / are correctly rounded and whose
+         other operators are accurate to a few ulps.  Used only to
          decide whether a program's fitness is stable under such differences
          (conditioning), never as a reference value.
 """
@@ -147,7 +147,7 @@ def run(tokens, consts, X, mode: str = "o64", seed: int = 0) -> np.ndarray:
             v = apply_op(op, a, b, None)
         else:
             v = apply_op(op, None, None, stack.pop())
-        if mode == "o32p" and op in (SIN, COS, EXP, LOG):
+        if mode == "o32p" and op in (SIN, COS, EXP, LOG, SQRT):
             with np.errstate(all="ignore"):
                 v = v * (1.0 + rng.uniform(-2.0 ** -22, 2.0 ** -22, size=M))
         if mode != "o64":

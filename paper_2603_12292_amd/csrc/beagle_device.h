@@ -123,7 +123,15 @@ __device__ __forceinline__ float op_log(float x) {
   const float r = __builtin_fmaf(y, 0x1.62e42ep-1f, y * 0x1.efa39ep-25f);  // ln 2, high and low parts
   return x == 0.0f ? 0.0f : r;
 }
-__device__ __forceinline__ float op_sqrt(float x) { return sqrtf(fabsf(x)); }
+// sqrt|x| from the hardware square root, faithful (at most 1 ulp from the
+// correctly rounded result over every binary32 input; inputs below 2^-96 are
+// scaled by 2^32 first and the result by 2^-16)
+__device__ __forceinline__ float op_sqrt(float x) {
+  const float a = __builtin_fabsf(x);
+  const bool tiny = a < 0x1p-96f;
+  const float s = __builtin_amdgcn_sqrtf(tiny ? a * 0x1p32f : a);
+  return tiny ? s * 0x1p-16f : s;
+}
 
 // Per-program metadata written by the preparation kernel.
 struct ProgMeta {

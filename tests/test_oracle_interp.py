@@ -181,11 +181,13 @@ def test_validate_opcode_and_priority():
     assert interp.validate(parse("x0 x1 x0 * +"), 0, 2) == (interp.ST_OK, 3)
 
 
-def test_o32p_perturbs_only_transcendentals():
+def test_o32p_perturbs_only_non_arithmetic_operators():
     rng = np.random.default_rng(3)
     X = rng.uniform(1, 5, size=(200, 2)).astype(np.float32)
-    toks = parse("x0 x1 / x0 sqrt * x1 -")
+    toks = parse("x0 x1 / x0 x1 * * x1 -")
     assert same(interp.run(toks, [], X, "o32p", seed=4), interp.run(toks, [], X, "o32e"))
+    assert not same(interp.run(parse("x0 x1 + sqrt"), [], X, "o32p", seed=4),
+                    interp.run(parse("x0 x1 + sqrt"), [], X, "o32e"))
     toks = parse("x0 sin x1 exp *")
     a = interp.run(toks, [], X, "o32p", seed=4)
     b = interp.run(toks, [], X, "o32e")
