@@ -36,9 +36,18 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+# per-source flags
+SOURCE_FLAGS = {
+    # the adjoint handlers each end in a tape write; sinking those writes into
+    # one shared block turns every stack slot into a phi (register copies on
+    # every word)
+    "grad.hip": ["-mllvm", "-simplifycfg-sink-common=false"],
+}
+
+
 def _compile(src: str, build_dir: str = BUILD, defines=(), extra=()) -> str:
     obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc()] + FLAGS + list(extra) + [f"-D{d}" for d in defines] + \
+    cmd = [hipcc()] + FLAGS + SOURCE_FLAGS.get(src, []) + list(extra) + [f"-D{d}" for d in defines] + \
         ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

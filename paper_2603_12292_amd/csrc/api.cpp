@@ -85,10 +85,10 @@ int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
 // Case chunking of the evaluation grid: about 32K cases per chunk, more
 // chunks when the population alone gives too few workgroups to fill the GPU.
-void choose_chunks(int64_t M, int64_t N, int64_t* chunk, int32_t* n_chunks) {
+void choose_chunks(int64_t M, int64_t N, int64_t* chunk, int32_t* n_chunks, int64_t max_chunk_cases) {
   const int64_t unit = bgl::CASES_PER_BLOCK_ITER;
   const int64_t max_chunks = std::max<int64_t>(1, (M + unit - 1) / unit);
-  int64_t C = std::max<int64_t>(1, (M + 32767) / 32768);
+  int64_t C = std::max<int64_t>(1, (M + max_chunk_cases - 1) / max_chunk_cases);
   const int64_t target_blocks = 4096;
   if (N * C < target_blocks) C = std::max<int64_t>(C, (target_blocks + N - 1) / std::max<int64_t>(N, 1));
   C = std::min(C, max_chunks);
@@ -136,7 +136,7 @@ EvalLayout eval_layout(const beagle_programs* P, const beagle_dataset* d, int n_
   L.meta = c.take<bgl::ProgMeta>(N);
   L.class_count = c.take<int32_t>(64);  // [0..2] need classes, [8..9] length classes
   L.class_list = c.take<int32_t>(size_t(bgl::N_CLASSES) * N);
-  L.len_list = c.take<int32_t>(size_t(4) * N);
+  L.len_list = c.take<int32_t>(size_t(bgl::GRAD_LISTS) * N);
   L.work = c.take<unsigned long long>(8);  // evaluation: one per class; adjoint: one per list
   L.Mp = round_up(d->M, bgl::CASES_PER_BLOCK_ITER);
   L.Xt = c.take<float>(size_t(d->D) * L.Mp);
@@ -145,7 +145,9 @@ EvalLayout eval_layout(const beagle_programs* P, const beagle_dataset* d, int n_
   L.slice = slice;
   // the chunking depends on the whole population only, so that a sliced
   // evaluation sums every program's partials in the same order
-  choose_chunks(d->M, N, &L.chunk, &L.n_chunks);
+  // the adjoint's kernels each walk one list of programs: shorter chunks
+  // keep a short list from leaving most of the chip idle
+  choose_chunks(d->M, N, &L.chunk, &L.n_chunks, with_grad ? bgl::GRAD_CHUNK_CASES : 32768);
   L.part = c.take<double>(size_t(n_sums) * L.n_chunks * slice);
   L.gpart = with_grad ? c.take<double>(size_t(L.n_chunks) * std::max<int64_t>(P->n_consts, 1)) : 0;
   L.total = c.used + 256;

@@ -143,12 +143,12 @@ beagle_status beagle_eval_batched(beagle_ctx* ctx, const beagle_programs* progs,
     o.s_need = c.take<int32_t>(nt);
     o.meta = c.take<bgl::ProgMeta>(N);
     o.class_list = c.take<int32_t>(size_t(bgl::N_CLASSES) * N);
-    o.len_list = c.take<int32_t>(size_t(4) * N);
+    o.len_list = c.take<int32_t>(size_t(bgl::GRAD_LISTS) * N);
     o.Mp = round_up(d.M, bgl::CASES_PER_BLOCK_ITER);
     o.Xt = c.take<float>(size_t(d.D) * o.Mp);
     o.yp = c.take<float>(o.Mp);
     o.stats = c.take<double>(4);
-    choose_chunks(d.M, N, &o.chunk, &o.n_chunks);
+    choose_chunks(d.M, N, &o.chunk, &o.n_chunks, 32768);
     o.part = c.take<double>(size_t(n_sums) * o.n_chunks * N);
   }
   beagle_status st = reserve(ctx, c.used + 256);

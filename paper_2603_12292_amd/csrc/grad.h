@@ -11,7 +11,48 @@ namespace bgl {
 
 constexpr int GRAD_SHORT_WORDS = 64;   // tape in registers up to this many decoded words
 constexpr int GRAD_LONG_WORDS = 256;   // tape in LDS up to this many (longer: TOO_LONG)
-constexpr int GRAD_SMALL_WORDS = 48;   // small-stack adjoint (2 cases per lane) up to this many
+// the derivative-tape adjoint (register need <= 4, 2 cases per lane): tape
+// entries per case of its three kernels (4, 3 and 2 waves per SIMD)
+constexpr int GRAD_DTAPE_SMALL = 32;
+constexpr int GRAD_DTAPE_MID = 48;
+constexpr int GRAD_DTAPE_LARGE = 64;
+// adjoint program lists: 0 short value tape, 1 long value tape, 2..4
+// derivative tape of at most GRAD_DTAPE_SMALL / MID / LARGE entries
+constexpr int GRAD_LISTS = 5;
+// cases per work item of the adjoint (at most; whole evaluation blocks)
+constexpr int64_t GRAD_CHUNK_CASES = 4096;
+
+// Reverse handler of a decoded word in the derivative-tape adjoint (bits
+// 24..31 of the word's aux entry).  n is the stack size before the word in
+// the forward sweep; the offsets below add n (pushes), n - 2 (binary
+// operators) or n - 1 (unary operators and fused words).
+//   NOP        VAR pushes; fused VAR + and -: the adjoint is unchanged
+//   PUSH_CONST the pushed constant's gradient gains the slot's adjoint
+//   BIN_ADD/SUB/RSUB  binary operators with constant partial derivatives
+//   BIN_GEN    binary operators with two tape entries (d/da, d/db)
+//   UN         unary operators: one tape entry (the derivative)
+//   FV_RSUB    fused "x - top": the adjoint changes sign
+//   FV_GEN     fused VAR *, /, reversed /: one entry (d/dtop)
+//   FC_*       fused CONST words: the constant's gradient gains
+//              adjoint * d/dc (ADD/SUB/RSUB: +-1; MUL, DIV: one entry;
+//              RDIV: two entries, d/dtop then d/dc); the adjoint is scaled
+//              by d/dtop (MUL: c; DIV: 1/c, 0 when c == 0)
+constexpr uint32_t R_NOP = 0;
+constexpr uint32_t R_PUSH_CONST = 1;  // + n, n 0..3
+constexpr uint32_t R_BIN_ADD = 5;     // + n - 2, n 2..4
+constexpr uint32_t R_BIN_SUB = 8;
+constexpr uint32_t R_BIN_RSUB = 11;
+constexpr uint32_t R_BIN_GEN = 14;
+constexpr uint32_t R_UN = 17;         // + n - 1, n 1..4
+constexpr uint32_t R_FV_RSUB = 21;    // + n - 1, n 1..3
+constexpr uint32_t R_FV_GEN = 24;
+constexpr uint32_t R_FC_ADD = 27;
+constexpr uint32_t R_FC_SUB = 30;
+constexpr uint32_t R_FC_RSUB = 33;
+constexpr uint32_t R_FC_MUL = 36;
+constexpr uint32_t R_FC_DIV = 39;
+constexpr uint32_t R_FC_RDIV = 42;
+constexpr uint32_t R_NONE = 255;
 
 struct GradArgs {
   const uint32_t* code;
@@ -31,9 +72,9 @@ struct GradArgs {
   double* part;        // [n_chunks][n_programs] sums of squared errors
   double* gpart;       // [n_chunks][n_consts] gradient partials
   int64_t n_consts;
-  const int32_t* list_count;  // [4]: short tape, long tape, small stack <= 48 words, small stack <= 64
-  const int32_t* list;        // [4][n_programs]
-  unsigned long long* work;   // [4] work-item counters, zero at launch
+  const int32_t* list_count;  // [GRAD_LISTS] program counts of the adjoint lists
+  const int32_t* list;        // [GRAD_LISTS][n_programs]
+  unsigned long long* work;   // [GRAD_LISTS] work-item counters, zero at launch
 };
 
 struct GradFinalizeArgs {

@@ -306,7 +306,7 @@ __device__ void grad_item(const GradArgs& a, int p, int c, float* lds) {
 #undef BGL_RFUSED
         default: break;
       }
-      astk[xw >> 16] = wv;
+      astk[(xw >> 16) & 0xFu] = wv;
       if (has_c) {  // wave-uniform
         const double v = valid ? double(gc) : 0.0;
         if (arg < uint32_t(LANE_SLOTS)) {
@@ -353,22 +353,26 @@ __global__ void __launch_bounds__(64) k_grad(GradArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// The small-stack adjoint: programs of register need <= 4 with at most
-// GRAD_SMALL_WORDS decoded words (list 2), GK cases per lane.  The forward
-// pass uses the small-stack handlers (word bits 24..31, stack size n known
-// per handler): every stack slot and every adjoint slot is a register named
-// at compile time, and each handler writes the value it produced into the
-// tape itself.  The tape is four register arrays (case 0 / 1, words 0..31 /
-// 32..GRAD_SMALL_WORDS-1; an index can address at most a 32-entry array).  Reverse, for a word at stack size n:
-//   push            slot n's adjoint is the pushed value's (CONST: its slot's
-//                   gradient), and the slot is dropped;
-//   binary          A[n-1] = A[n-2] d/db,  A[n-2] = A[n-2] d/da  with
-//                   a = output of word pa, b = output of word t-1;
-//   unary, fused    A[n-1] scaled by the local derivative (fused CONST words
-//                   also add A[n-1] d/dc to their slot's gradient).
+// The derivative-tape adjoint: programs of register need <= 4 whose tape
+// fits GRAD_DTAPE_SMALL (list 2) or GRAD_DTAPE_LARGE (list 3) entries per
+// case, GK cases per lane.
+//
+// The forward sweep runs the small-stack handlers (word bits 24..31, stack
+// size n known per handler: every stack slot is a register named at compile
+// time) and each handler stores the local partial derivatives the reverse
+// sweep will need, not its output: binary *, / and reversed / two entries
+// (d/da, d/db), unary operators one (sin x takes cos x from its own
+// reduction), fused VAR *, / one, fused CONST *, / one (d/dc) and reversed /
+// two, every other word none.  Entries are appended in word order, so the
+// reverse sweep, walking the words backwards, takes them from the end with a
+// wave-uniform counter.  The reverse handler of a word (aux bits 24..31) is a
+// linear update of the adjoint stack A:
+//   binary at n    A[n-1] = A[n-2] d/db,  A[n-2] = A[n-2] d/da
+//   unary, fused   A[n-1] scaled by d/dtop
+//   CONST          its slot's gradient gains A (times d/dc when fused)
+// The tape is one register array per case (list 3: two, entries 0..31 and
+// 32..63; an index addresses at most a 32-entry array).
 constexpr int GK = 2;
-// whether the partial derivatives of binary operator o read its operands
-__host__ __device__ constexpr bool uses_operands(uint32_t o) { return o == B_MUL || o == B_DIV || o == B_RDIV; }
 
 template <bool COS>
 __device__ __forceinline__ void trig2(float& a, float& b) {
@@ -378,66 +382,142 @@ __device__ __forceinline__ void trig2(float& a, float& b) {
   b = v[1];
 }
 
-// one forward word into tape position ti of arrays T0 (case 0) and T1 (case 1)
-template <int NT>
-__device__ __forceinline__ void small_fwd(uint32_t w, float cv, const float* xl, float (&st)[GK][4], float (&T0)[NT],
-                                          float (&T1)[NT], int ti) {
-  const uint32_t arg = (w >> 8) & 0xFFu;
-  const float* xr = xl + arg * (GK * 64);
-#define BGL_PUT(J) \
-  T0[ti] = st[0][J]; \
-  T1[ti] = st[1][J];
+// entry e of case k's tape: lo[e] for e < 32, hi[e - 32] above (HI = 0: no
+// upper part)
+template <int HI>
+struct DTape {
+  static constexpr int HS = HI > 0 ? HI : 1;
+};
+
+template <int HI>
+__device__ __forceinline__ void dt_put(float (&lo0)[32], float (&lo1)[32], float (&hi0)[DTape<HI>::HS],
+                                       float (&hi1)[DTape<HI>::HS], int e, float v0, float v1) {
+  if (HI == 0 || e < 32) {
+    lo0[e & 31] = v0;
+    lo1[e & 31] = v1;
+  } else {
+    hi0[(e - 32) & (DTape<HI>::HS - 1)] = v0;
+    hi1[(e - 32) & (DTape<HI>::HS - 1)] = v1;
+  }
+}
+
+template <int HI>
+__device__ __forceinline__ float dt_get(const float (&lo)[32], const float (&hi)[DTape<HI>::HS], int e) {
+  if constexpr (HI == 0) {
+    return lo[e & 31];
+  } else {
+    const float x = opaque(lo[e & 31]);
+    const float y = opaque(hi[(e - 32) & (HI - 1)]);
+    return e < 32 ? x : y;
+  }
+}
+
+// one forward word; e = the next free tape entry
+template <int HI>
+__device__ __forceinline__ void dt_fwd(uint32_t w, float cv, float x0, float x1, float (&st)[GK][4],
+                                       float (&lo0)[32], float (&lo1)[32], float (&hi0)[DTape<HI>::HS],
+                                       float (&hi1)[DTape<HI>::HS], int& e) {
+#define BGL_PUT(V0, V1)                        \
+  dt_put<HI>(lo0, lo1, hi0, hi1, e, V0, V1);   \
+  ++e;
   switch (w >> 24) {
-#define BGL_F_PUSH(N)                    \
-  case I0_PUSH_VAR + N:                  \
-    st[0][N] = xr[0];                    \
-    st[1][N] = xr[64];                   \
-    BGL_PUT(N) break;                    \
-  case I0_PUSH_CONST + N:                \
-    st[0][N] = cv;                       \
-    st[1][N] = cv;                       \
-    BGL_PUT(N) break;
+#define BGL_F_PUSH(N)     \
+  case I0_PUSH_VAR + N:   \
+    st[0][N] = x0;        \
+    st[1][N] = x1;        \
+    break;                \
+  case I0_PUSH_CONST + N: \
+    st[0][N] = cv;        \
+    st[1][N] = cv;        \
+    break;
     BGL_F_PUSH(0) BGL_F_PUSH(1) BGL_F_PUSH(2) BGL_F_PUSH(3)
 #undef BGL_F_PUSH
-#define BGL_F_BIN(O, N)                                   \
-  case I0_BIN + 3 * O + (N - 2):                          \
-    st[0][N - 2] = gbinop<O>(st[0][N - 2], st[0][N - 1]); \
-    st[1][N - 2] = gbinop<O>(st[1][N - 2], st[1][N - 1]); \
-    BGL_PUT(N - 2) break;
+#define BGL_F_BIN(O, N)                                                   \
+  case I0_BIN + 3 * O + (N - 2): {                                        \
+    const float a0 = st[0][N - 2], b0 = st[0][N - 1];                     \
+    const float a1 = st[1][N - 2], b1 = st[1][N - 1];                     \
+    st[0][N - 2] = gbinop<O>(a0, b0);                                     \
+    st[1][N - 2] = gbinop<O>(a1, b1);                                     \
+    if constexpr (O == B_MUL || O == B_DIV || O == B_RDIV) {              \
+      float dA0, dB0, dA1, dB1;                                           \
+      dbinop<O>(a0, b0, dA0, dB0);                                        \
+      dbinop<O>(a1, b1, dA1, dB1);                                        \
+      BGL_PUT(dA0, dA1)                                                   \
+      BGL_PUT(dB0, dB1)                                                   \
+    }                                                                     \
+    break;                                                                \
+  }
 #define BGL_F_BIN3(O) BGL_F_BIN(O, 2) BGL_F_BIN(O, 3) BGL_F_BIN(O, 4)
     BGL_F_BIN3(B_ADD) BGL_F_BIN3(B_SUB) BGL_F_BIN3(B_MUL) BGL_F_BIN3(B_DIV) BGL_F_BIN3(B_RSUB) BGL_F_BIN3(B_RDIV)
 #undef BGL_F_BIN3
 #undef BGL_F_BIN
-#define BGL_F_UN(N)                                              \
-  case I0_UN + 0 * 4 + (N - 1):                                  \
-    trig2<false>(st[0][N - 1], st[1][N - 1]);                    \
-    BGL_PUT(N - 1) break;                                        \
-  case I0_UN + 1 * 4 + (N - 1):                                  \
-    trig2<true>(st[0][N - 1], st[1][N - 1]);                     \
-    BGL_PUT(N - 1) break;                                        \
-  case I0_UN + 2 * 4 + (N - 1):                                  \
-    st[0][N - 1] = op_exp(st[0][N - 1]);                         \
-    st[1][N - 1] = op_exp(st[1][N - 1]);                         \
-    BGL_PUT(N - 1) break;                                        \
-  case I0_UN + 3 * 4 + (N - 1):                                  \
-    st[0][N - 1] = op_log(st[0][N - 1]);                         \
-    st[1][N - 1] = op_log(st[1][N - 1]);                         \
-    BGL_PUT(N - 1) break;                                        \
-  case I0_UN + 4 * 4 + (N - 1):                                  \
-    st[0][N - 1] = op_sqrt(st[0][N - 1]);                        \
-    st[1][N - 1] = op_sqrt(st[1][N - 1]);                        \
-    BGL_PUT(N - 1) break;
+#define BGL_F_UN(N)                                                           \
+  case I0_UN + 0 * 4 + (N - 1): {                                             \
+    float s[GK] = {st[0][N - 1], st[1][N - 1]}, c[GK];                        \
+    sincos_tile<GK>(s, c);                                                    \
+    st[0][N - 1] = s[0];                                                      \
+    st[1][N - 1] = s[1];                                                      \
+    BGL_PUT(c[0], c[1])                                                       \
+    break;                                                                    \
+  }                                                                           \
+  case I0_UN + 1 * 4 + (N - 1): {                                             \
+    float d0 = st[0][N - 1], d1 = st[1][N - 1];                               \
+    trig2<true>(st[0][N - 1], st[1][N - 1]);                                  \
+    trig2<false>(d0, d1);                                                     \
+    BGL_PUT(-d0, -d1)                                                         \
+    break;                                                                    \
+  }                                                                           \
+  case I0_UN + 2 * 4 + (N - 1): {                                             \
+    const float u0 = st[0][N - 1], u1 = st[1][N - 1];                         \
+    st[0][N - 1] = op_exp(u0);                                                \
+    st[1][N - 1] = op_exp(u1);                                                \
+    BGL_PUT(dunary(2u, u0, st[0][N - 1]), dunary(2u, u1, st[1][N - 1]))       \
+    break;                                                                    \
+  }                                                                           \
+  case I0_UN + 3 * 4 + (N - 1): {                                             \
+    const float u0 = st[0][N - 1], u1 = st[1][N - 1];                         \
+    st[0][N - 1] = op_log(u0);                                                \
+    st[1][N - 1] = op_log(u1);                                                \
+    BGL_PUT(dunary(3u, u0, 0.0f), dunary(3u, u1, 0.0f))                       \
+    break;                                                                    \
+  }                                                                           \
+  case I0_UN + 4 * 4 + (N - 1): {                                             \
+    const float u0 = st[0][N - 1], u1 = st[1][N - 1];                         \
+    st[0][N - 1] = op_sqrt(u0);                                               \
+    st[1][N - 1] = op_sqrt(u1);                                               \
+    BGL_PUT(dunary(4u, u0, st[0][N - 1]), dunary(4u, u1, st[1][N - 1]))       \
+    break;                                                                    \
+  }
     BGL_F_UN(1) BGL_F_UN(2) BGL_F_UN(3) BGL_F_UN(4)
 #undef BGL_F_UN
-#define BGL_F_FUSED(O, N)                                 \
-  case I0_FUSED + 3 * O + (N - 1):                        \
-    st[0][N - 1] = gbinop<O>(st[0][N - 1], xr[0]);        \
-    st[1][N - 1] = gbinop<O>(st[1][N - 1], xr[64]);       \
-    BGL_PUT(N - 1) break;                                 \
-  case I0_FUSED + 3 * (6 + O) + (N - 1):                  \
-    st[0][N - 1] = gbinop<O>(st[0][N - 1], cv);           \
-    st[1][N - 1] = gbinop<O>(st[1][N - 1], cv);           \
-    BGL_PUT(N - 1) break;
+#define BGL_F_FUSED(O, N)                                                 \
+  case I0_FUSED + 3 * O + (N - 1): {                                      \
+    const float a0 = st[0][N - 1], a1 = st[1][N - 1];                     \
+    st[0][N - 1] = gbinop<O>(a0, x0);                                     \
+    st[1][N - 1] = gbinop<O>(a1, x1);                                     \
+    if constexpr (O == B_MUL || O == B_DIV || O == B_RDIV) {              \
+      float dA0, dB0, dA1, dB1;                                           \
+      dbinop<O>(a0, x0, dA0, dB0);                                        \
+      dbinop<O>(a1, x1, dA1, dB1);                                        \
+      BGL_PUT(dA0, dA1)                                                   \
+    }                                                                     \
+    break;                                                                \
+  }                                                                       \
+  case I0_FUSED + 3 * (6 + O) + (N - 1): {                                \
+    const float a0 = st[0][N - 1], a1 = st[1][N - 1];                     \
+    st[0][N - 1] = gbinop<O>(a0, cv);                                     \
+    st[1][N - 1] = gbinop<O>(a1, cv);                                     \
+    if constexpr (O == B_MUL || O == B_DIV || O == B_RDIV) {              \
+      float dA0, dB0, dA1, dB1;                                           \
+      dbinop<O>(a0, cv, dA0, dB0);                                        \
+      dbinop<O>(a1, cv, dA1, dB1);                                        \
+      if constexpr (O == B_RDIV) {                                        \
+        BGL_PUT(dA0, dA1)                                                 \
+      }                                                                   \
+      BGL_PUT(dB0, dB1)                                                   \
+    }                                                                     \
+    break;                                                                \
+  }
 #define BGL_F_FUSED3(O) BGL_F_FUSED(O, 1) BGL_F_FUSED(O, 2) BGL_F_FUSED(O, 3)
     BGL_F_FUSED3(B_ADD) BGL_F_FUSED3(B_SUB) BGL_F_FUSED3(B_MUL) BGL_F_FUSED3(B_DIV) BGL_F_FUSED3(B_RSUB)
     BGL_F_FUSED3(B_RDIV)
@@ -449,39 +529,22 @@ __device__ __forceinline__ void small_fwd(uint32_t w, float cv, const float* xl,
 #undef BGL_PUT
 }
 
-// local derivative of unary operator u for the two cases (x: input, y: output)
-template <int U>
-__device__ __forceinline__ void dunary2(float x0, float x1, float y0, float y1, float& d0, float& d1) {
-  if constexpr (U == 0) {
-    d0 = x0;
-    d1 = x1;
-    trig2<true>(d0, d1);
-  } else if constexpr (U == 1) {
-    d0 = x0;
-    d1 = x1;
-    trig2<false>(d0, d1);
-    d0 = -d0;
-    d1 = -d1;
-  } else {
-    d0 = dunary(uint32_t(U), x0, y0);
-    d1 = dunary(uint32_t(U), x1, y1);
-  }
-}
-
 template <int LANE_SLOTS_>
 __device__ __forceinline__ void add_const_grad(uint32_t arg, float g0, float g1, bool v0, bool v1, double* lg,
                                                double* wg, int lane) {
   const double v = (v0 ? double(g0) : 0.0) + (v1 ? double(g1) : 0.0);
   if (arg < uint32_t(LANE_SLOTS_)) {
-    lg[arg * 64] += v;
+    // LDS add without a returned value: nothing waits for it, and the adds
+    // of one lane reach its slot in program order
+    __hip_atomic_fetch_add(lg + arg * 64, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
   } else {
     const double sv = wave_sum_d(v);
     if (lane == 0) wg[arg] += sv;
   }
 }
 
-template <int SMALL_HI>  // tape entries of words 32.. per case
-__device__ void grad_small_item(const GradArgs& a, int p, int c, float* lds) {
+template <int HI>  // upper tape entries per case (0: at most 32 entries)
+__device__ void dtape_item(const GradArgs& a, int p, int c, float* lds) {
   const int lane = threadIdx.x;
   const ProgMeta m = a.meta[p];
   const int L = m.len;
@@ -489,6 +552,11 @@ __device__ void grad_small_item(const GradArgs& a, int p, int c, float* lds) {
   const int64_t coff = a.const_offset[p];
   const int cc = a.const_count[p];
   const uint32_t vmask = uint32_t(__builtin_amdgcn_readfirstlane(int(m.vmask)));
+  const uint32_t dmax = uint32_t(a.D - 1);
+  auto xrow = [dmax](uint32_t word) -> uint32_t {
+    const uint32_t r = (word >> 8) & 0xFFu;
+    return r < dmax ? r : dmax;
+  };
   const uint32_t vc = lane < L ? a.code[off + lane] : 0u;
   const uint32_t va = lane < L ? a.aux[off + lane] : 0u;
   const float vv = lane < L ? a.cval[off + lane] : 0.0f;
@@ -496,17 +564,7 @@ __device__ void grad_small_item(const GradArgs& a, int p, int c, float* lds) {
   float* xl = lds + lane;
   double* lg = reinterpret_cast<double*>(lds + a.D * GK * 64) + lane;
   double* wg = reinterpret_cast<double*>(lds + a.D * GK * 64) + LANE_SLOTS * 64;
-  float t0lo[32], t0hi[SMALL_HI], t1lo[32], t1hi[SMALL_HI];
-  auto tg0 = [&](int t) -> float {
-    const float x = opaque(t0lo[t & 31]);
-    const float y = opaque(t0hi[t & (SMALL_HI - 1)]);
-    return t < 32 ? x : y;
-  };
-  auto tg1 = [&](int t) -> float {
-    const float x = opaque(t1lo[t & 31]);
-    const float y = opaque(t1hi[t & (SMALL_HI - 1)]);
-    return t < 32 ? x : y;
-  };
+  float lo0[32], lo1[32], hi0[DTape<HI>::HS], hi1[DTape<HI>::HS];
   for (int j = 0; j < LANE_SLOTS; ++j) lg[j * 64] = 0.0;
   for (int j = lane; j < 256; j += 64) wg[j] = 0.0;
   __builtin_amdgcn_wave_barrier();
@@ -527,23 +585,27 @@ __device__ void grad_small_item(const GradArgs& a, int p, int c, float* lds) {
     const float y0 = a.yp[i0], y1 = a.yp[i1];
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the tile is in LDS
-    // ---- forward with tape
+    // ---- forward: values on the stack, partial derivatives on the tape
     float st[GK][4];
 #pragma unroll
     for (int k = 0; k < GK; ++k)
 #pragma unroll
       for (int j = 0; j < 4; ++j) st[k][j] = 0.0f;
+    // The input row a word reads is loaded one word ahead, so that the LDS
+    // latency overlaps the previous word; words that read no input load row
+    // min(arg, D - 1), which is in the tile and unused.
     const float* xt = lds + lane;
-    const int L0 = L < 32 ? L : 32;
-    for (int t = 0; t < L0; ++t) {
-      const uint32_t w = __builtin_amdgcn_readlane(vc, t);
+    int e = 0;
+    uint32_t w = __builtin_amdgcn_readlane(vc, 0);
+    float xa0 = xt[xrow(w) * (GK * 64)], xa1 = xt[xrow(w) * (GK * 64) + 64];
+    for (int t = 0; t < L; ++t) {
+      const uint32_t wn = t + 1 < L ? __builtin_amdgcn_readlane(vc, t + 1) : 0u;
+      const float xb0 = xt[xrow(wn) * (GK * 64)], xb1 = xt[xrow(wn) * (GK * 64) + 64];
       const float cv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vv), t));
-      small_fwd<32>(w, cv, xt, st, t0lo, t1lo, t);
-    }
-    for (int t = 32; t < L; ++t) {
-      const uint32_t w = __builtin_amdgcn_readlane(vc, t);
-      const float cv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vv), t));
-      small_fwd<SMALL_HI>(w, cv, xt, st, t0hi, t1hi, t - 32);
+      dt_fwd<HI>(w, cv, xa0, xa1, st, lo0, lo1, hi0, hi1, e);
+      w = wn;
+      xa0 = xb0;
+      xa1 = xb1;
     }
     // ---- seed and fitness terms
     const double e0 = double(st[0][0]) - double(y0), e1 = double(st[1][0]) - double(y1);
@@ -555,91 +617,95 @@ __device__ void grad_small_item(const GradArgs& a, int p, int c, float* lds) {
       for (int j = 0; j < 4; ++j) A[k][j] = 0.0f;
     A[0][0] = v0 ? float(e0) * inv2m : 0.0f;
     A[1][0] = v1 ? float(e1) * inv2m : 0.0f;
-    // ---- reverse
+    // ---- reverse: linear updates of the adjoint stack
+    auto T0 = [&](int i) { return dt_get<HI>(lo0, hi0, i); };
+    auto T1 = [&](int i) { return dt_get<HI>(lo1, hi1, i); };
     for (int t = L - 1; t >= 0; --t) {
-      const uint32_t w = __builtin_amdgcn_readlane(vc, t);
-      const uint32_t xw = __builtin_amdgcn_readlane(va, t);
+      const uint32_t rid = __builtin_amdgcn_readlane(va, t) >> 24;
+      const uint32_t arg = (__builtin_amdgcn_readlane(vc, t) >> 8) & 0xFFu;
       const float cv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vv), t));
-      const uint32_t arg = (w >> 8) & 0xFFu;
-      const int pa = int(xw & 0xFFFFu);
-      const float* xr = xt + arg * (GK * 64);
-      switch (w >> 24) {
-#define BGL_R_PUSH(N)                                              \
-  case I0_PUSH_VAR + N:                                            \
-    break;                                                         \
-  case I0_PUSH_CONST + N:                                          \
-    add_const_grad<LANE_SLOTS>(arg, A[0][N], A[1][N], v0, v1, lg, wg, lane); \
-    break;
+#define BGL_CG(G0, G1) add_const_grad<LANE_SLOTS>(arg, G0, G1, v0, v1, lg, wg, lane);
+      switch (rid) {
+#define BGL_R_PUSH(N)             \
+  case R_PUSH_CONST + N:          \
+    BGL_CG(A[0][N], A[1][N]) break;
         BGL_R_PUSH(0) BGL_R_PUSH(1) BGL_R_PUSH(2) BGL_R_PUSH(3)
 #undef BGL_R_PUSH
-#define BGL_R_BIN(O, N)                                           \
-  case I0_BIN + 3 * O + (N - 2): {                                \
-    float dA0, dB0, dA1, dB1;                                     \
-    if constexpr (uses_operands(O)) {                             \
-      dbinop<O>(tg0(pa), tg0(t - 1), dA0, dB0);                   \
-      dbinop<O>(tg1(pa), tg1(t - 1), dA1, dB1);                   \
-    } else {                                                      \
-      dbinop<O>(0.0f, 0.0f, dA0, dB0);                            \
-      dbinop<O>(0.0f, 0.0f, dA1, dB1);                            \
-    }                                                             \
-    A[0][N - 1] = A[0][N - 2] * dB0;                              \
-    A[1][N - 1] = A[1][N - 2] * dB1;                              \
-    A[0][N - 2] = A[0][N - 2] * dA0;                              \
-    A[1][N - 2] = A[1][N - 2] * dA1;                              \
-    break;                                                        \
-  }
-#define BGL_R_BIN3(O) BGL_R_BIN(O, 2) BGL_R_BIN(O, 3) BGL_R_BIN(O, 4)
-        BGL_R_BIN3(B_ADD) BGL_R_BIN3(B_SUB) BGL_R_BIN3(B_MUL) BGL_R_BIN3(B_DIV) BGL_R_BIN3(B_RSUB) BGL_R_BIN3(B_RDIV)
-#undef BGL_R_BIN3
+#define BGL_R_BIN(N)                              \
+  case R_BIN_ADD + (N - 2):                       \
+    A[0][N - 1] = A[0][N - 2];                    \
+    A[1][N - 1] = A[1][N - 2];                    \
+    break;                                        \
+  case R_BIN_SUB + (N - 2):                       \
+    A[0][N - 1] = -A[0][N - 2];                   \
+    A[1][N - 1] = -A[1][N - 2];                   \
+    break;                                        \
+  case R_BIN_RSUB + (N - 2):                      \
+    A[0][N - 1] = A[0][N - 2];                    \
+    A[1][N - 1] = A[1][N - 2];                    \
+    A[0][N - 2] = -A[0][N - 2];                   \
+    A[1][N - 2] = -A[1][N - 2];                   \
+    break;                                        \
+  case R_BIN_GEN + (N - 2):                       \
+    e -= 2;                                       \
+    A[0][N - 1] = A[0][N - 2] * T0(e + 1);        \
+    A[1][N - 1] = A[1][N - 2] * T1(e + 1);        \
+    A[0][N - 2] *= T0(e);                         \
+    A[1][N - 2] *= T1(e);                         \
+    break;
+        BGL_R_BIN(2) BGL_R_BIN(3) BGL_R_BIN(4)
 #undef BGL_R_BIN
-#define BGL_R_UN1(U, N)                                            \
-  case I0_UN + U * 4 + (N - 1): {                                  \
-    float d0, d1;                                                  \
-    if constexpr (U == 2 || U == 4)                                \
-      dunary2<U>(tg0(t - 1), tg1(t - 1), tg0(t), tg1(t), d0, d1);  \
-    else                                                           \
-      dunary2<U>(tg0(t - 1), tg1(t - 1), 0.0f, 0.0f, d0, d1);      \
-    A[0][N - 1] *= d0;                                             \
-    A[1][N - 1] *= d1;                                             \
-    break;                                                         \
-  }
-#define BGL_R_UN(N) BGL_R_UN1(0, N) BGL_R_UN1(1, N) BGL_R_UN1(2, N) BGL_R_UN1(3, N) BGL_R_UN1(4, N)
+#define BGL_R_UN(N)       \
+  case R_UN + (N - 1):    \
+    e -= 1;               \
+    A[0][N - 1] *= T0(e); \
+    A[1][N - 1] *= T1(e); \
+    break;
         BGL_R_UN(1) BGL_R_UN(2) BGL_R_UN(3) BGL_R_UN(4)
 #undef BGL_R_UN
-#undef BGL_R_UN1
-#define BGL_R_FUSED(O, N)                                          \
-  case I0_FUSED + 3 * O + (N - 1): {                               \
-    float dA0, dB0, dA1, dB1;                                      \
-    if constexpr (uses_operands(O)) {                              \
-      dbinop<O>(tg0(t - 1), xr[0], dA0, dB0);                      \
-      dbinop<O>(tg1(t - 1), xr[64], dA1, dB1);                     \
-    } else {                                                       \
-      dbinop<O>(0.0f, 0.0f, dA0, dB0);                             \
-      dbinop<O>(0.0f, 0.0f, dA1, dB1);                             \
-    }                                                              \
-    A[0][N - 1] *= dA0;                                            \
-    A[1][N - 1] *= dA1;                                            \
+#define BGL_R_FUSED(N)                                             \
+  case R_FV_RSUB + (N - 1):                                        \
+    A[0][N - 1] = -A[0][N - 1];                                    \
+    A[1][N - 1] = -A[1][N - 1];                                    \
+    break;                                                         \
+  case R_FV_GEN + (N - 1):                                         \
+    e -= 1;                                                        \
+    A[0][N - 1] *= T0(e);                                          \
+    A[1][N - 1] *= T1(e);                                          \
+    break;                                                         \
+  case R_FC_ADD + (N - 1):                                         \
+    BGL_CG(A[0][N - 1], A[1][N - 1]) break;                        \
+  case R_FC_SUB + (N - 1):                                         \
+    BGL_CG(-A[0][N - 1], -A[1][N - 1]) break;                      \
+  case R_FC_RSUB + (N - 1):                                        \
+    BGL_CG(A[0][N - 1], A[1][N - 1])                               \
+    A[0][N - 1] = -A[0][N - 1];                                    \
+    A[1][N - 1] = -A[1][N - 1];                                    \
+    break;                                                         \
+  case R_FC_MUL + (N - 1):                                         \
+    e -= 1;                                                        \
+    BGL_CG(A[0][N - 1] * T0(e), A[1][N - 1] * T1(e))               \
+    A[0][N - 1] *= cv;                                             \
+    A[1][N - 1] *= cv;                                             \
+    break;                                                         \
+  case R_FC_DIV + (N - 1): {                                       \
+    e -= 1;                                                        \
+    BGL_CG(A[0][N - 1] * T0(e), A[1][N - 1] * T1(e))               \
+    float dA, dB;                                                  \
+    dbinop<B_DIV>(0.0f, cv, dA, dB);                               \
+    A[0][N - 1] *= dA;                                             \
+    A[1][N - 1] *= dA;                                             \
     break;                                                         \
   }                                                                \
-  case I0_FUSED + 3 * (6 + O) + (N - 1): {                         \
-    float dA0, dB0, dA1, dB1;                                      \
-    if constexpr (uses_operands(O)) {                              \
-      dbinop<O>(tg0(t - 1), cv, dA0, dB0);                         \
-      dbinop<O>(tg1(t - 1), cv, dA1, dB1);                         \
-    } else {                                                       \
-      dbinop<O>(0.0f, 0.0f, dA0, dB0);                             \
-      dbinop<O>(0.0f, 0.0f, dA1, dB1);                             \
-    }                                                              \
-    add_const_grad<LANE_SLOTS>(arg, A[0][N - 1] * dB0, A[1][N - 1] * dB1, v0, v1, lg, wg, lane); \
-    A[0][N - 1] *= dA0;                                            \
-    A[1][N - 1] *= dA1;                                            \
-    break;                                                         \
-  }
-#define BGL_R_FUSED3(O) BGL_R_FUSED(O, 1) BGL_R_FUSED(O, 2) BGL_R_FUSED(O, 3)
-        BGL_R_FUSED3(B_ADD) BGL_R_FUSED3(B_SUB) BGL_R_FUSED3(B_MUL) BGL_R_FUSED3(B_DIV) BGL_R_FUSED3(B_RSUB)
-        BGL_R_FUSED3(B_RDIV)
-#undef BGL_R_FUSED3
+  case R_FC_RDIV + (N - 1):                                        \
+    e -= 2;                                                        \
+    BGL_CG(A[0][N - 1] * T0(e + 1), A[1][N - 1] * T1(e + 1))       \
+    A[0][N - 1] *= T0(e);                                          \
+    A[1][N - 1] *= T1(e);                                          \
+    break;
+        BGL_R_FUSED(1) BGL_R_FUSED(2) BGL_R_FUSED(3)
 #undef BGL_R_FUSED
+#undef BGL_CG
         default:
           break;
       }
@@ -660,13 +726,14 @@ __device__ void grad_small_item(const GradArgs& a, int p, int c, float* lds) {
   __builtin_amdgcn_wave_barrier();
 }
 
-// LIST 2: at most GRAD_SMALL_WORDS words (a 16-entry upper tape keeps the
-// kernel within 168 VGPRs: 3 waves per SIMD); LIST 3: at most
-// GRAD_SHORT_WORDS (32-entry upper tape, 2 waves per SIMD).
+// LIST 2, 3, 4: at most GRAD_DTAPE_SMALL, MID, LARGE entries per case (upper
+// tape 0, 16, 32 entries; 128, <= 168 and <= 256 VGPRs: 4, 3, 2 waves per
+// SIMD).
 template <int LIST>
-__global__ void __launch_bounds__(64) k_grad_small(GradArgs a) {
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LIST == 2 ? 4 : 1)))
+k_grad_dtape(GradArgs a) {
   extern __shared__ float lds[];
-  constexpr int HI = LIST == 2 ? GRAD_SMALL_WORDS - 32 : GRAD_SHORT_WORDS - 32;
+  constexpr int HI = (LIST == 2 ? GRAD_DTAPE_SMALL : LIST == 3 ? GRAD_DTAPE_MID : GRAD_DTAPE_LARGE) - 32;
   const int32_t count = a.list_count[LIST];
   const int64_t items = int64_t(count) * a.n_chunks;
   const int32_t* list = a.list + LIST * int64_t(a.n_programs);
@@ -679,7 +746,7 @@ __global__ void __launch_bounds__(64) k_grad_small(GradArgs a) {
     if (item >= items) break;
     const int c = int(item / count);
     const int p = list[item % count];
-    grad_small_item<HI>(a, p, c, lds);
+    dtape_item<HI>(a, p, c, lds);
   }
 }
 
@@ -725,15 +792,19 @@ hipError_t launch_grad(const GradArgs& a, hipStream_t s) {
   const int cus = grad_cu_count();
   const size_t l0 = grad_lds_bytes(a.D, false), l1 = grad_lds_bytes(a.D, true);
   const size_t l2 = size_t(a.D) * GK * 64 * sizeof(float) + (size_t(LANE_SLOTS) * 64 + 256) * sizeof(double);
-  int nb0 = 0, nb1 = 0, nb2 = 0, nb3 = 0;
+  int nb0 = 0, nb1 = 0, nb2 = 0, nb3 = 0, nb4 = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb0, k_grad<false>, 64, l0) != hipSuccess || nb0 < 1) nb0 = 1;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb1, k_grad<true>, 64, l1) != hipSuccess || nb1 < 1) nb1 = 1;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb2, k_grad_small<2>, 64, l2) != hipSuccess || nb2 < 1) nb2 = 1;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb3, k_grad_small<3>, 64, l2) != hipSuccess || nb3 < 1) nb3 = 1;
-  hipLaunchKernelGGL(k_grad_small<2>, dim3(nb2 * cus), dim3(64), l2, s, a);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb2, k_grad_dtape<2>, 64, l2) != hipSuccess || nb2 < 1) nb2 = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb3, k_grad_dtape<3>, 64, l2) != hipSuccess || nb3 < 1) nb3 = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb4, k_grad_dtape<4>, 64, l2) != hipSuccess || nb4 < 1) nb4 = 1;
+  hipLaunchKernelGGL(k_grad_dtape<2>, dim3(nb2 * cus), dim3(64), l2, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_grad_small<3>, dim3(nb3 * cus), dim3(64), l2, s, a);
+  hipLaunchKernelGGL(k_grad_dtape<3>, dim3(nb3 * cus), dim3(64), l2, s, a);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_grad_dtape<4>, dim3(nb4 * cus), dim3(64), l2, s, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_grad<false>, dim3(nb0 * cus), dim3(64), l0, s, a);

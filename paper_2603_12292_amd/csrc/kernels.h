@@ -31,8 +31,8 @@ struct PrepareArgs {
   int8_t* status_out;  // [n_programs] or null
   int32_t* class_count;  // [N_CLASSES] programs per register-need class
   int32_t* class_list;   // [N_CLASSES][n_programs] program indices per class
-  int32_t* len_count;    // [4] adjoint lists (see k_prepare)
-  int32_t* len_list;     // [4][n_programs]
+  int32_t* len_count;    // [5] adjoint lists (see k_prepare)
+  int32_t* len_list;     // [5][n_programs]
   int32_t short_words;
 };
 

@@ -35,6 +35,7 @@ __device__ static void prepare_program(const PrepareArgs& a, int p, ST tok, S st
   int status = BEAGLE_PROG_OK;
   int need_root = 0;
   int L_dec = 0;
+  int n_ent = 0;  // derivative-tape entries per case (adjoint)
   uint32_t vmask = 0;
   if (L <= 0) {
     status = L == 0 ? BEAGLE_PROG_EMPTY : BEAGLE_PROG_BAD_LAYOUT;
@@ -105,10 +106,12 @@ __device__ static void prepare_program(const PrepareArgs& a, int p, ST tok, S st
       }
       // pass 3: handler words, fusing "terminal, binary operator" pairs;
       // decoded words go to `code` (out <= i always, so `ord` may alias it).
-      // Alongside, for the adjoint: aux[out] = pa | (rws << 16), pa = the
-      // decoded word that produced the value below the top (binary words),
-      // rws = the adjoint-stack slot the reverse sweep writes (see grad.hip);
-      // `start` is free after pass 2 and holds the producer of each stack slot.
+      // Alongside, for the adjoint: aux[out] = pa | (rws << 16) | (rid << 24),
+      // pa = the decoded word that produced the value below the top (binary
+      // words), rws = the adjoint-stack slot the reverse sweep writes, rid =
+      // the word's reverse handler in the derivative-tape adjoint, whose tape
+      // entries per case are counted in n_ent (see grad.hip); `start` is free
+      // after pass 2 and holds the producer of each stack slot.
       float* cv = a.cval + off;
       uint32_t* aux = a.aux + off;
       const S prod = start;
@@ -117,7 +120,7 @@ __device__ static void prepare_program(const PrepareArgs& a, int p, ST tok, S st
         const uint32_t w = uint32_t(ord.get(i));
         const uint32_t op = w & 0xFFu, arg = (w >> 8) & 0xFFu;
         const uint32_t wslot = n > 0 ? uint32_t(n - 1) : 0u;
-        uint32_t h, i0, pa = 0u, rws;
+        uint32_t h, i0, pa = 0u, rws, rid;
         const bool term = op == OP_VAR || op == OP_CONST;
         const uint32_t nxt = i + 1 < L ? (uint32_t(ord.get(i + 1)) & 0xFFu) : 0xFFu;
         const bool next_bin = nxt < 4u || (nxt >= 100u && nxt < 106u);
@@ -130,6 +133,16 @@ __device__ static void prepare_program(const PrepareArgs& a, int p, ST tok, S st
           if (op == OP_CONST) cv[out] = a.consts[coff + arg];
           nmax = n + 1 > nmax ? n + 1 : nmax;
           rws = uint32_t(n - 1);
+          const bool gen = o == B_MUL || o == B_DIV || o == B_RDIV;
+          if (op == OP_VAR) {
+            rid = o == B_RSUB ? R_FV_RSUB : (gen ? R_FV_GEN : R_NOP);
+            n_ent += gen ? 1 : 0;
+          } else {
+            const uint32_t fc[6] = {R_FC_ADD, R_FC_SUB, R_FC_MUL, R_FC_DIV, R_FC_RSUB, R_FC_RDIV};
+            rid = fc[o];
+            n_ent += o == B_RDIV ? 2 : (gen ? 1 : 0);
+          }
+          if (rid != R_NOP) rid = n <= 3 ? rid + uint32_t(n - 1) : R_NONE;
           prod.set(n - 1, out);
           ++i;  // the operator is consumed; stack size unchanged
         } else if (term) {
@@ -137,6 +150,7 @@ __device__ static void prepare_program(const PrepareArgs& a, int p, ST tok, S st
           i0 = n <= 3 ? (op == OP_VAR ? I0_PUSH_VAR : I0_PUSH_CONST) + uint32_t(n) : I0_NONE;
           if (op == OP_CONST) cv[out] = a.consts[coff + arg];
           rws = uint32_t(n);
+          rid = op == OP_VAR ? R_NOP : (n <= 3 ? R_PUSH_CONST + uint32_t(n) : R_NONE);
           prod.set(n, out);
           ++n;
         } else if (op >= 100u || op < 4) {
@@ -144,19 +158,25 @@ __device__ static void prepare_program(const PrepareArgs& a, int p, ST tok, S st
           i0 = n <= 4 ? I0_BIN + 3u * (op >= 100u ? op - 100u : op) + uint32_t(n - 2) : I0_NONE;
           pa = uint32_t(prod.get(n - 2));
           rws = uint32_t(n - 2);
+          const uint32_t bo = op >= 100u ? op - 100u : op;
+          const uint32_t rb[6] = {R_BIN_ADD, R_BIN_SUB, R_BIN_GEN, R_BIN_GEN, R_BIN_RSUB, R_BIN_GEN};
+          rid = n <= 4 ? rb[bo] + uint32_t(n - 2) : R_NONE;
+          n_ent += rb[bo] == R_BIN_GEN ? 2 : 0;
           --n;
           prod.set(n - 1, out);
         } else {
           h = H_UN + (op - OP_SIN);
           i0 = n <= 4 ? I0_UN + 4u * (op - OP_SIN) + uint32_t(n - 1) : I0_NONE;
           rws = uint32_t(n - 1);
+          rid = n <= 4 ? R_UN + uint32_t(n - 1) : R_NONE;
+          n_ent += 1;
           prod.set(n - 1, out);
         }
         nmax = n > nmax ? n : nmax;
         // arg: variable index (VAR words), constant slot (CONST words), 0 otherwise
         const uint32_t warg = term ? arg : 0u;
         code[out] = h | (warg << 8) | (wslot << 16) | (i0 << 24);
-        aux[out] = pa | (rws << 16);
+        aux[out] = pa | (rws << 16) | (rid << 24);
         ++out;
       }
       // nmax == need_root by construction; the larger one is kept defensively
@@ -179,10 +199,16 @@ __device__ static void prepare_program(const PrepareArgs& a, int p, ST tok, S st
     const int cls = need_class(need_root);
     const int slot = atomicAdd(a.class_count + cls, 1);
     a.class_list[int64_t(cls) * a.n_programs + slot] = p;
-    // and by decoded length (the adjoint keeps short tapes in registers)
-    // adjoint lists: 0 short tape, 1 long tape; register need <= 4: 2 at
-    // most GRAD_SMALL_WORDS words, 3 at most short_words
-    const int lc = L_dec > a.short_words ? 1 : (need_root > 4 ? 0 : (L_dec <= GRAD_SMALL_WORDS ? 2 : 3));
+    // and by tape size (the adjoint keeps short tapes in registers)
+    // adjoint lists: 0 short value tape, 1 long value tape; register need
+    // <= 4: 2, 3, 4 at most GRAD_DTAPE_SMALL, MID, LARGE derivative-tape
+    // entries
+    const int lc = L_dec > a.short_words ? 1
+                   : need_root > 4       ? 0
+                   : n_ent <= GRAD_DTAPE_SMALL ? 2
+                   : n_ent <= GRAD_DTAPE_MID   ? 3
+                   : n_ent <= GRAD_DTAPE_LARGE ? 4
+                                               : 0;
     const int ls = atomicAdd(a.len_count + lc, 1);
     a.len_list[int64_t(lc) * a.n_programs + ls] = p;
   }

@@ -37,9 +37,10 @@ __device__ __forceinline__ float sin_poly(float r) {
   return __builtin_fmaf(r2 * r, p, r);
 }
 
-// r and the parity p of k for a = |x| < 2^30 (COS: the half-period shift).
+// r (in binary64) and the parity p of k for a = |x| < 2^30 (COS: the
+// half-period shift).
 template <bool COS>
-__device__ __forceinline__ float trig_reduce_small(float a, int& p) {
+__device__ __forceinline__ double trig_reduce_small_d(float a, int& p) {
   const double xd = double(a);
   const double t = COS ? __builtin_fma(xd, 0x1.45f306dc9c883p-2, -0.5) : xd * 0x1.45f306dc9c883p-2;  // 1/pi
   const double k = __builtin_rint(t);
@@ -47,7 +48,12 @@ __device__ __forceinline__ float trig_reduce_small(float a, int& p) {
   double r = __builtin_fma(-h, 0x1.921fb54442d18p+1, xd);  // pi, high part
   r = __builtin_fma(-h, 0x1.1a62633145c07p-53, r);         // pi, low part
   p = int(k) + (COS ? 1 : 0);
-  return float(r);
+  return r;
+}
+
+template <bool COS>
+__device__ __forceinline__ float trig_reduce_small(float a, int& p) {
+  return float(trig_reduce_small_d<COS>(a, p));
 }
 
 // The same for a finite a >= 2^30 (exponent e >= 30).
@@ -121,6 +127,39 @@ __device__ __forceinline__ void trig_tile(float (&v)[K]) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       v[k] = trig_any<COS>(v[k]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
+// sin x (the interpreter's value, bit for bit) and cos x from one reduction
+// of K values per lane; s holds x on entry.  With x = k pi + r, |r| <= pi/2:
+// cos x = (-1)^k cos r = (-1)^k sin(pi/2 - |r|), the argument formed in
+// binary64 (pi/2 as the halves of the split of pi), so cos x is as accurate
+// as the sine's polynomial allows away from its zeros and within ~1e-8
+// absolute near them.  Large or non-finite arguments of any lane: the
+// general path per case.
+template <int K>
+__device__ __forceinline__ void sincos_tile(float (&s)[K], float (&c)[K]) {
+  bool big = false;
+#pragma unroll
+  for (int k = 0; k < K; ++k) big |= !(__builtin_fabsf(s[k]) < TRIG_SMALL);
+  if (__builtin_amdgcn_ballot_w64(big) == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const float x = s[k];
+      int p;
+      const double r = trig_reduce_small_d<false>(__builtin_fabsf(x), p);
+      s[k] = trig_finish(float(r), p, __float_as_uint(x) & 0x80000000u);
+      const double u = (0x1.921fb54442d18p+0 - __builtin_fabs(r)) + 0x1.1a62633145c07p-54;
+      c[k] = trig_finish(float(u), p, 0u);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const float x = s[k];
+      s[k] = trig_any<false>(x);
+      c[k] = trig_any<true>(x);
       __builtin_amdgcn_sched_barrier(0);
     }
   }

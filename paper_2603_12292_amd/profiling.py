@@ -1,8 +1,9 @@
 """Profiling helpers for the evaluator kernels (run under rocprofv3).
 
-  python -m paper_2603_12292_amd.profiling run [--steps N]
+  python -m paper_2603_12292_amd.profiling run [--steps N] [--adjoint]
       one warm-up and N evaluations of the benchmark workload (plain-mid,
-      correlation fitness), then a 256 MiB device-to-device copy whose byte
+      correlation fitness; --adjoint: fitness and constant gradients of the
+      differentiation workload, MSE), then a 256 MiB device-to-device copy whose byte
       count is known, used to scale the HBM counters.
 
   python -m paper_2603_12292_amd.profiling summarize --trace DIR --fetch CSV --write CSV [--valu CSV] --out PREFIX
@@ -48,18 +49,19 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def run(steps: int):
+def run(steps: int, adjoint: bool = False):
     import torch
     sys.path.insert(0, ROOT)
     from paper_2603_12292_amd import api
     from paper_2603_12292_amd import workloads as wl
-    w = wl.config_mid()
+    w = wl.config_differentiation() if adjoint else wl.config_mid()
     progs = api.DevicePrograms.from_programset(w.programs, "cuda:0")
     X = torch.from_numpy(w.data.X).cuda()
     y = torch.from_numpy(w.data.y).cuda()
-    api.evaluate(progs, X, y, "corr")
+    call = (lambda: api.evaluate_grad(progs, X, y, "mse")) if adjoint else (lambda: api.evaluate(progs, X, y, "corr"))
+    call()
     for _ in range(steps):
-        api.evaluate(progs, X, y, "corr")
+        call()
     torch.cuda.synchronize()
     a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
@@ -146,6 +148,8 @@ def main():
     sub = ap.add_subparsers(dest="cmd", required=True)
     r = sub.add_parser("run")
     r.add_argument("--steps", type=int, default=1)
+    r.add_argument("--adjoint", action="store_true",
+                   help="fitness and constant gradients of the differentiation workload instead")
     s = sub.add_parser("summarize")
     s.add_argument("--trace", required=True)
     s.add_argument("--fetch")
@@ -155,7 +159,7 @@ def main():
     s.add_argument("--command", default="")
     a = ap.parse_args()
     if a.cmd == "run":
-        run(a.steps)
+        run(a.steps, a.adjoint)
     else:
         summarize(a.trace, a.fetch, a.write, a.out, a.command, a.valu)
 

@@ -168,6 +168,35 @@ def test_long_tapes_many_constants_and_limits():
         assert np.all(err <= GRAD_RTOL * scale + 1e-7), (p, g[o:o + cc], g64, stable)
 
 
+def test_tape_size_boundaries():
+    """Unary chains "x0 c0 + u1 u2 ... uk": one tape entry per unary word, so
+    k = 32, 33, 48, 49, 62 put the programs at both sides of each boundary of
+    the derivative-tape kernels (at most 32, 48 and 64 entries per case)."""
+    rng = np.random.default_rng(14)
+    data = wl.make_dataset(23, 3000, 2, x_range=(1.0, 3.0), target_len=8)
+    cycle = [wl.COS, wl.SQRT, wl.SIN, wl.EXP, wl.LOG]   # every unary operator, well conditioned
+    progs = []
+    for k in (32, 33, 48, 49, 62):
+        start = int(rng.integers(len(cycle)))
+        t = [wl.tok(wl.VAR, 0), wl.tok(wl.CONST, 0), wl.tok(wl.ADD)]
+        t += [wl.tok(cycle[(start + i) % len(cycle)]) for i in range(k)]
+        progs.append((t, [float(np.float32(rng.uniform(-1, 1)))]))
+    ps = wl.pack_programs(progs)
+    f, g, st = _grad(ps, data)
+    assert np.all(st == 0)
+    n_cmp = 0
+    for p in range(ps.n):
+        t, c = ps.program(p)
+        F, g64 = og.mse_and_grad(t, c, data.X, data.y)
+        assert math.isfinite(F) and np.all(np.isfinite(g64))
+        assert abs(f[p] - F) <= 1e-5 * abs(F) + gates.atol(ofit.MSE, data.y)
+        stable, scale = _stable_components(t, c, data, g64)
+        err = np.abs(g[p:p + 1] - g64)[stable]
+        assert np.all(err <= GRAD_RTOL * scale + 1e-7), (p, g[p], g64)
+        n_cmp += int(np.any(stable))
+    assert n_cmp == 5
+
+
 def test_autograd_function_and_adam():
     from paper_2603_12292_amd import autograd as ag
     api = _api()

@@ -57,6 +57,8 @@ def test_header_holds_the_derived_constants():
     assert [int(w.strip().rstrip("u"), 16) for w in table.split(",")] == words
     hi, lo = minimax.pi_split()
     assert hi.hex() in text and lo.hex() in text and (1 / math.pi).hex() in text
+    # pi/2 for the cosine of the shared reduction: the exact halves
+    assert (hi / 2).hex() in text and (lo / 2).hex() in text
     body = text[text.index("float sin_poly"):text.index("trig_reduce_small")]
     lits = [float.fromhex(x.rstrip("f")) for x in re.findall(r"-?0x1\.[0-9a-f]+p[-+]?\d+f", body)]
     assert sorted(lits) == sorted(float(c) for c in minimax.poly_coefficients())
