@@ -85,8 +85,7 @@ int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
 // Case chunking of the evaluation grid: about 32K cases per chunk, more
 // chunks when the population alone gives too few workgroups to fill the GPU.
-void choose_chunks(int64_t M, int64_t N, int64_t* chunk, int32_t* n_chunks, int64_t max_chunk_cases) {
-  const int64_t unit = bgl::CASES_PER_BLOCK_ITER;
+void choose_chunks(int64_t M, int64_t N, int64_t* chunk, int32_t* n_chunks, int64_t max_chunk_cases, int64_t unit) {
   const int64_t max_chunks = std::max<int64_t>(1, (M + unit - 1) / unit);
   int64_t C = std::max<int64_t>(1, (M + max_chunk_cases - 1) / max_chunk_cases);
   const int64_t target_blocks = 4096;
@@ -147,7 +146,10 @@ EvalLayout eval_layout(const beagle_programs* P, const beagle_dataset* d, int n_
   // evaluation sums every program's partials in the same order
   // the adjoint's kernels each walk one list of programs: shorter chunks
   // keep a short list from leaving most of the chip idle
-  choose_chunks(d->M, N, &L.chunk, &L.n_chunks, with_grad ? bgl::GRAD_CHUNK_CASES : 32768);
+  if (with_grad)
+    choose_chunks(d->M, N, &L.chunk, &L.n_chunks, bgl::GRAD_CHUNK_CASES, bgl::GRAD_TILE_CASES);
+  else
+    choose_chunks(d->M, N, &L.chunk, &L.n_chunks, 32768, bgl::CASES_PER_BLOCK_ITER);
   L.part = c.take<double>(size_t(n_sums) * L.n_chunks * slice);
   L.gpart = with_grad ? c.take<double>(size_t(L.n_chunks) * std::max<int64_t>(P->n_consts, 1)) : 0;
   L.total = c.used + 256;

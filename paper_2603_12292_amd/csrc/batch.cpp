@@ -148,7 +148,7 @@ beagle_status beagle_eval_batched(beagle_ctx* ctx, const beagle_programs* progs,
     o.Xt = c.take<float>(size_t(d.D) * o.Mp);
     o.yp = c.take<float>(o.Mp);
     o.stats = c.take<double>(4);
-    choose_chunks(d.M, N, &o.chunk, &o.n_chunks, 32768);
+    choose_chunks(d.M, N, &o.chunk, &o.n_chunks, 32768, bgl::CASES_PER_BLOCK_ITER);
     o.part = c.take<double>(size_t(n_sums) * o.n_chunks * N);
   }
   beagle_status st = reserve(ctx, c.used + 256);

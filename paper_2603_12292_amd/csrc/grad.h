@@ -19,8 +19,13 @@ constexpr int GRAD_DTAPE_LARGE = 64;
 // adjoint program lists: 0 short value tape, 1 long value tape, 2..4
 // derivative tape of at most GRAD_DTAPE_SMALL / MID / LARGE entries
 constexpr int GRAD_LISTS = 5;
-// cases per work item of the adjoint (at most; whole evaluation blocks)
-constexpr int64_t GRAD_CHUNK_CASES = 4096;
+// constant slots whose gradients are summed per lane (the derivative-tape
+// kernels take only programs with at most this many slots)
+constexpr int GRAD_LANE_SLOTS = 8;
+// cases per work item of the adjoint (at most), a multiple of the cases one
+// tile of every adjoint kernel covers
+constexpr int64_t GRAD_CHUNK_CASES = 1024;
+constexpr int64_t GRAD_TILE_CASES = 128;
 
 // Reverse handler of a decoded word in the derivative-tape adjoint (bits
 // 24..31 of the word's aux entry).  n is the stack size before the word in
@@ -53,6 +58,13 @@ constexpr uint32_t R_FC_MUL = 36;
 constexpr uint32_t R_FC_DIV = 39;
 constexpr uint32_t R_FC_RDIV = 42;
 constexpr uint32_t R_NONE = 255;
+
+// Forward handlers of the derivative-tape adjoint: the small-stack handler
+// numbers (I0_*) for words that store their entries, and for the words of
+// constant-free subtrees (no entries) of the operators that would store some:
+constexpr uint32_t F_BIN_NT = 82;  // + 3 j + n - 2, j: *, /, reversed /
+constexpr uint32_t F_UN_NT = 91;   // + 4 u + n - 1
+constexpr uint32_t F_FV_NT = 111;  // fused VAR: + 3 j + n - 1
 
 struct GradArgs {
   const uint32_t* code;

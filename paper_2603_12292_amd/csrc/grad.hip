@@ -29,7 +29,7 @@
 namespace bgl {
 
 constexpr int GRAD_S = MAX_STACK;
-constexpr int LANE_SLOTS = 8;  // constant slots accumulated per lane
+constexpr int LANE_SLOTS = GRAD_LANE_SLOTS;  // constant slots accumulated per lane
 
 template <uint32_t O>
 __device__ __forceinline__ float gbinop(float a, float b) {
@@ -370,9 +370,14 @@ __global__ void __launch_bounds__(64) k_grad(GradArgs a) {
 //   binary at n    A[n-1] = A[n-2] d/db,  A[n-2] = A[n-2] d/da
 //   unary, fused   A[n-1] scaled by d/dtop
 //   CONST          its slot's gradient gains A (times d/dc when fused)
+// A subtree without CONST words adds to no gradient: its words store no
+// entries (their own forward handlers), and the reverse sweep follows a
+// per-word "next" index (aux bits 0..7) that skips such a subtree in one
+// step, and skips the words whose reverse update is the identity.
 // The tape is one register array per case (list 3: two, entries 0..31 and
 // 32..63; an index addresses at most a 32-entry array).
 constexpr int GK = 2;
+static_assert(GRAD_TILE_CASES % (GK * 64) == 0, "adjoint chunks hold whole tiles");
 
 template <bool COS>
 __device__ __forceinline__ void trig2(float& a, float& b) {
@@ -412,15 +417,15 @@ __device__ __forceinline__ float dt_get(const float (&lo)[32], const float (&hi)
   }
 }
 
-// one forward word; e = the next free tape entry
+// one forward word (forward handler fid); e = the next free tape entry
 template <int HI>
-__device__ __forceinline__ void dt_fwd(uint32_t w, float cv, float x0, float x1, float (&st)[GK][4],
+__device__ __forceinline__ void dt_fwd(uint32_t fid, float cv, float x0, float x1, float (&st)[GK][4],
                                        float (&lo0)[32], float (&lo1)[32], float (&hi0)[DTape<HI>::HS],
                                        float (&hi1)[DTape<HI>::HS], int& e) {
 #define BGL_PUT(V0, V1)                        \
   dt_put<HI>(lo0, lo1, hi0, hi1, e, V0, V1);   \
   ++e;
-  switch (w >> 24) {
+  switch (fid) {
 #define BGL_F_PUSH(N)     \
   case I0_PUSH_VAR + N:   \
     st[0][N] = x0;        \
@@ -523,24 +528,58 @@ __device__ __forceinline__ void dt_fwd(uint32_t w, float cv, float x0, float x1,
     BGL_F_FUSED3(B_RDIV)
 #undef BGL_F_FUSED3
 #undef BGL_F_FUSED
+    // constant-free words: values only
+#define BGL_N_BIN(J, O, N)                                \
+  case F_BIN_NT + 3 * J + (N - 2):                        \
+    st[0][N - 2] = gbinop<O>(st[0][N - 2], st[0][N - 1]); \
+    st[1][N - 2] = gbinop<O>(st[1][N - 2], st[1][N - 1]); \
+    break;
+#define BGL_N_BIN3(J, O) BGL_N_BIN(J, O, 2) BGL_N_BIN(J, O, 3) BGL_N_BIN(J, O, 4)
+    BGL_N_BIN3(0, B_MUL) BGL_N_BIN3(1, B_DIV) BGL_N_BIN3(2, B_RDIV)
+#undef BGL_N_BIN3
+#undef BGL_N_BIN
+#define BGL_N_UN(N)                                         \
+  case F_UN_NT + 0 * 4 + (N - 1):                           \
+    trig2<false>(st[0][N - 1], st[1][N - 1]);               \
+    break;                                                  \
+  case F_UN_NT + 1 * 4 + (N - 1):                           \
+    trig2<true>(st[0][N - 1], st[1][N - 1]);                \
+    break;                                                  \
+  case F_UN_NT + 2 * 4 + (N - 1):                           \
+    st[0][N - 1] = op_exp(st[0][N - 1]);                    \
+    st[1][N - 1] = op_exp(st[1][N - 1]);                    \
+    break;                                                  \
+  case F_UN_NT + 3 * 4 + (N - 1):                           \
+    st[0][N - 1] = op_log(st[0][N - 1]);                    \
+    st[1][N - 1] = op_log(st[1][N - 1]);                    \
+    break;                                                  \
+  case F_UN_NT + 4 * 4 + (N - 1):                           \
+    st[0][N - 1] = op_sqrt(st[0][N - 1]);                   \
+    st[1][N - 1] = op_sqrt(st[1][N - 1]);                   \
+    break;
+    BGL_N_UN(1) BGL_N_UN(2) BGL_N_UN(3) BGL_N_UN(4)
+#undef BGL_N_UN
+#define BGL_N_FV(J, O, N)                                 \
+  case F_FV_NT + 3 * J + (N - 1):                         \
+    st[0][N - 1] = gbinop<O>(st[0][N - 1], x0);           \
+    st[1][N - 1] = gbinop<O>(st[1][N - 1], x1);           \
+    break;
+#define BGL_N_FV3(J, O) BGL_N_FV(J, O, 1) BGL_N_FV(J, O, 2) BGL_N_FV(J, O, 3)
+    BGL_N_FV3(0, B_MUL) BGL_N_FV3(1, B_DIV) BGL_N_FV3(2, B_RDIV)
+#undef BGL_N_FV3
+#undef BGL_N_FV
     default:
       break;
   }
 #undef BGL_PUT
 }
 
-template <int LANE_SLOTS_>
-__device__ __forceinline__ void add_const_grad(uint32_t arg, float g0, float g1, bool v0, bool v1, double* lg,
-                                               double* wg, int lane) {
+// slot arg (< GRAD_LANE_SLOTS) of the lane's gradient sums gains the two
+// cases' contributions: an LDS add without a returned value, so nothing waits
+// for it, and the adds of one lane reach its slot in program order
+__device__ __forceinline__ void add_const_grad(uint32_t arg, float g0, float g1, bool v0, bool v1, double* lg) {
   const double v = (v0 ? double(g0) : 0.0) + (v1 ? double(g1) : 0.0);
-  if (arg < uint32_t(LANE_SLOTS_)) {
-    // LDS add without a returned value: nothing waits for it, and the adds
-    // of one lane reach its slot in program order
-    __hip_atomic_fetch_add(lg + arg * 64, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-  } else {
-    const double sv = wave_sum_d(v);
-    if (lane == 0) wg[arg] += sv;
-  }
+  __hip_atomic_fetch_add(lg + arg * 64, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 
 template <int HI>  // upper tape entries per case (0: at most 32 entries)
@@ -553,20 +592,19 @@ __device__ void dtape_item(const GradArgs& a, int p, int c, float* lds) {
   const int cc = a.const_count[p];
   const uint32_t vmask = uint32_t(__builtin_amdgcn_readfirstlane(int(m.vmask)));
   const uint32_t dmax = uint32_t(a.D - 1);
-  auto xrow = [dmax](uint32_t word) -> uint32_t {
-    const uint32_t r = (word >> 8) & 0xFFu;
+  // x: the word's aux entry, (next + 1) | fid << 8 | arg << 16 | rid << 24
+  auto xrow = [dmax](uint32_t x) -> uint32_t {
+    const uint32_t r = (x >> 16) & 0xFFu;
     return r < dmax ? r : dmax;
   };
-  const uint32_t vc = lane < L ? a.code[off + lane] : 0u;
   const uint32_t va = lane < L ? a.aux[off + lane] : 0u;
   const float vv = lane < L ? a.cval[off + lane] : 0.0f;
-  // LDS: input tile [D][GK][64] | lane gradients [8][64] doubles | wave gradients [256] doubles
+  // LDS: input tile [D][GK][64] | lane gradients [LANE_SLOTS][64] doubles
+  // (the program has at most LANE_SLOTS constant slots)
   float* xl = lds + lane;
   double* lg = reinterpret_cast<double*>(lds + a.D * GK * 64) + lane;
-  double* wg = reinterpret_cast<double*>(lds + a.D * GK * 64) + LANE_SLOTS * 64;
   float lo0[32], lo1[32], hi0[DTape<HI>::HS], hi1[DTape<HI>::HS];
   for (int j = 0; j < LANE_SLOTS; ++j) lg[j * 64] = 0.0;
-  for (int j = lane; j < 256; j += 64) wg[j] = 0.0;
   __builtin_amdgcn_wave_barrier();
   double s_mse = 0.0;
   const float inv2m = float(2.0 / double(a.M));
@@ -596,13 +634,13 @@ __device__ void dtape_item(const GradArgs& a, int p, int c, float* lds) {
     // min(arg, D - 1), which is in the tile and unused.
     const float* xt = lds + lane;
     int e = 0;
-    uint32_t w = __builtin_amdgcn_readlane(vc, 0);
+    uint32_t w = __builtin_amdgcn_readlane(va, 0);
     float xa0 = xt[xrow(w) * (GK * 64)], xa1 = xt[xrow(w) * (GK * 64) + 64];
     for (int t = 0; t < L; ++t) {
-      const uint32_t wn = t + 1 < L ? __builtin_amdgcn_readlane(vc, t + 1) : 0u;
+      const uint32_t wn = t + 1 < L ? __builtin_amdgcn_readlane(va, t + 1) : 0u;
       const float xb0 = xt[xrow(wn) * (GK * 64)], xb1 = xt[xrow(wn) * (GK * 64) + 64];
       const float cv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vv), t));
-      dt_fwd<HI>(w, cv, xa0, xa1, st, lo0, lo1, hi0, hi1, e);
+      dt_fwd<HI>((w >> 8) & 0xFFu, cv, xa0, xa1, st, lo0, lo1, hi0, hi1, e);
       w = wn;
       xa0 = xb0;
       xa1 = xb1;
@@ -617,14 +655,17 @@ __device__ void dtape_item(const GradArgs& a, int p, int c, float* lds) {
       for (int j = 0; j < 4; ++j) A[k][j] = 0.0f;
     A[0][0] = v0 ? float(e0) * inv2m : 0.0f;
     A[1][0] = v1 ? float(e1) * inv2m : 0.0f;
-    // ---- reverse: linear updates of the adjoint stack
+    // ---- reverse: linear updates of the adjoint stack, visiting only the
+    // words that are neither constant-free nor NOP (the root always)
     auto T0 = [&](int i) { return dt_get<HI>(lo0, hi0, i); };
     auto T1 = [&](int i) { return dt_get<HI>(lo1, hi1, i); };
-    for (int t = L - 1; t >= 0; --t) {
-      const uint32_t rid = __builtin_amdgcn_readlane(va, t) >> 24;
-      const uint32_t arg = (__builtin_amdgcn_readlane(vc, t) >> 8) & 0xFFu;
+    for (int t = L - 1; t >= 0;) {
+      const uint32_t x = __builtin_amdgcn_readlane(va, t);
+      const uint32_t rid = x >> 24;
+      const uint32_t arg = (x >> 16) & 0xFFu;
       const float cv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vv), t));
-#define BGL_CG(G0, G1) add_const_grad<LANE_SLOTS>(arg, G0, G1, v0, v1, lg, wg, lane);
+      t = int(x & 0xFFu) - 1;
+#define BGL_CG(G0, G1) add_const_grad(arg, G0, G1, v0, v1, lg);
       switch (rid) {
 #define BGL_R_PUSH(N)             \
   case R_PUSH_CONST + N:          \
@@ -716,13 +757,10 @@ __device__ void dtape_item(const GradArgs& a, int p, int c, float* lds) {
   s_mse = wave_sum_d(s_mse);
   if (lane == 0) a.part[int64_t(c) * a.n_programs + p] = s_mse;
   double* gp = a.gpart + int64_t(c) * a.n_consts + coff;
-  const int nl = cc < LANE_SLOTS ? cc : LANE_SLOTS;
-  for (int j = 0; j < nl; ++j) {
+  for (int j = 0; j < cc; ++j) {
     const double v = wave_sum_d(lg[j * 64]);
     if (lane == 0) gp[j] = v;
   }
-  __builtin_amdgcn_wave_barrier();
-  for (int j = LANE_SLOTS + lane; j < cc; j += 64) gp[j] = wg[j];
   __builtin_amdgcn_wave_barrier();
 }
 
@@ -791,7 +829,7 @@ size_t grad_lds_bytes(int D, bool long_tape) {
 hipError_t launch_grad(const GradArgs& a, hipStream_t s) {
   const int cus = grad_cu_count();
   const size_t l0 = grad_lds_bytes(a.D, false), l1 = grad_lds_bytes(a.D, true);
-  const size_t l2 = size_t(a.D) * GK * 64 * sizeof(float) + (size_t(LANE_SLOTS) * 64 + 256) * sizeof(double);
+  const size_t l2 = size_t(a.D) * GK * 64 * sizeof(float) + size_t(LANE_SLOTS) * 64 * sizeof(double);
   int nb0 = 0, nb1 = 0, nb2 = 0, nb3 = 0, nb4 = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb0, k_grad<false>, 64, l0) != hipSuccess || nb0 < 1) nb0 = 1;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb1, k_grad<true>, 64, l1) != hipSuccess || nb1 < 1) nb1 = 1;

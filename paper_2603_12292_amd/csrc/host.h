@@ -90,8 +90,9 @@ beagle_status check_programs(const beagle_programs* p);
 beagle_status check_data(const beagle_dataset* d, int kind);
 int64_t round_up(int64_t v, int64_t m);
 // Case chunks of one call: at most max_chunk_cases cases each (rounded up to
-// whole blocks), more when the population alone gives too few work items.
-void choose_chunks(int64_t M, int64_t N, int64_t* chunk, int32_t* n_chunks, int64_t max_chunk_cases);
+// a multiple of unit, the cases one kernel iteration covers), more when the
+// population alone gives too few work items.
+void choose_chunks(int64_t M, int64_t N, int64_t* chunk, int32_t* n_chunks, int64_t max_chunk_cases, int64_t unit);
 void zero_i32(int32_t* p, int64_t n, hipStream_t s);
 
 // Tile variant of class 0 for a problem (0 wide, 1 narrow).  Under

@@ -26,6 +26,53 @@ struct Scratch {
 //     (opcode, arg) at its output position,
 //  3. forward over the output: track the stack size n before each token and
 //     write the handler word; CONST values go to the side table cval.
+// The forward handler of a word that stores no tape entries (a constant-free
+// subtree's word) in the derivative-tape adjoint's numbering.
+__device__ static uint32_t fwd_notape(uint32_t i0) {
+  auto gen = [](uint32_t o) -> int { return o == B_MUL ? 0 : o == B_DIV ? 1 : o == B_RDIV ? 2 : -1; };
+  if (i0 >= I0_UN && i0 < I0_FUSED) return F_UN_NT + (i0 - I0_UN);
+  if (i0 >= I0_BIN && i0 < I0_UN) {
+    const uint32_t q = i0 - I0_BIN;
+    const int j = gen(q / 3u);
+    return j >= 0 ? F_BIN_NT + 3u * uint32_t(j) + q % 3u : i0;
+  }
+  if (i0 >= I0_FUSED && i0 < I0_FUSED + 18u) {  // fused VAR words
+    const uint32_t q = i0 - I0_FUSED;
+    const int j = gen(q / 3u);
+    return j >= 0 ? F_FV_NT + 3u * uint32_t(j) + q % 3u : i0;
+  }
+  return i0;
+}
+
+// Rewrites aux of a program of the derivative-tape adjoint (at most 64
+// words; none of the value-tape kernels reads it) as
+//   (next + 1) | (fid << 8) | (arg << 16) | (rid << 24):
+// fid its forward handler (fwd_notape for constant-free words), arg its
+// variable or constant slot, next the word the reverse sweep visits after
+// it: the reverse sweep visits only words that are not constant-free and not
+// NOP, and steps over a constant-free subtree in one jump.  wfirst holds,
+// per word, the first word of its subtree (bit 15: constant-free); vis is
+// scratch (the word to visit when the sweep arrives at word u, plus one).
+template <class S>
+__device__ static void dtape_words(const uint32_t* code, uint32_t* aux, int L, S vis, S wfirst) {
+  for (int u = 0; u < L; ++u) {
+    const int fw = wfirst.get(u);
+    const bool wcf = (fw & 0x8000) != 0;
+    const int sk = wcf ? (fw & 0x7FFF) - 1 : u - 1;
+    const bool real = !wcf && (aux[u] >> 24) != R_NOP;
+    vis.set(u, real ? u + 1 : (sk >= 0 ? vis.get(sk) : 0));
+  }
+  for (int u = 0; u < L; ++u) {
+    const uint32_t c = code[u];
+    const int fw = wfirst.get(u);
+    const bool wcf = (fw & 0x8000) != 0;
+    const int sk = wcf ? (fw & 0x7FFF) - 1 : u - 1;
+    const uint32_t next1 = sk >= 0 ? uint32_t(vis.get(sk)) : 0u;
+    const uint32_t fid = wcf ? fwd_notape(c >> 24) : (c >> 24);
+    aux[u] = next1 | (fid << 8) | (((c >> 8) & 0xFFu) << 16) | (aux[u] & 0xFF000000u);
+  }
+}
+
 template <class ST, class S, class SO>
 __device__ static void prepare_program(const PrepareArgs& a, int p, ST tok, S stack, S start, S need, SO ord) {
   const int64_t off = a.tok_offset[p];
@@ -110,17 +157,27 @@ __device__ static void prepare_program(const PrepareArgs& a, int p, ST tok, S st
       // pa = the decoded word that produced the value below the top (binary
       // words), rws = the adjoint-stack slot the reverse sweep writes, rid =
       // the word's reverse handler in the derivative-tape adjoint, whose tape
-      // entries per case are counted in n_ent (see grad.hip); `start` is free
-      // after pass 2 and holds the producer of each stack slot.
+      // entries per case are counted in n_ent (see grad.hip).  A word whose
+      // subtree holds no CONST ("constant-free") needs no adjoint: it has no
+      // entries and its rid is NOP.  `start` is free after pass 2 and holds
+      // the producer of each stack slot, `need` the first decoded word of
+      // each slot's subtree, `stack` per word the first word of its subtree
+      // with bit 15 set when constant-free; cfm bit j: slot j constant-free.
       float* cv = a.cval + off;
       uint32_t* aux = a.aux + off;
       const S prod = start;
+      const S pfirst = need;
+      const S wfirst = stack;
+      uint32_t cfm = 0u;
       int n = 0, nmax = 0, out = 0;
       for (int i = 0; i < L; ++i) {
         const uint32_t w = uint32_t(ord.get(i));
         const uint32_t op = w & 0xFFu, arg = (w >> 8) & 0xFFu;
         const uint32_t wslot = n > 0 ? uint32_t(n - 1) : 0u;
         uint32_t h, i0, pa = 0u, rws, rid;
+        bool wcf;   // constant-free subtree
+        int wfst;   // first word of the subtree
+        int ent;    // derivative-tape entries when not constant-free
         const bool term = op == OP_VAR || op == OP_CONST;
         const uint32_t nxt = i + 1 < L ? (uint32_t(ord.get(i + 1)) & 0xFFu) : 0xFFu;
         const bool next_bin = nxt < 4u || (nxt >= 100u && nxt < 106u);
@@ -136,13 +193,16 @@ __device__ static void prepare_program(const PrepareArgs& a, int p, ST tok, S st
           const bool gen = o == B_MUL || o == B_DIV || o == B_RDIV;
           if (op == OP_VAR) {
             rid = o == B_RSUB ? R_FV_RSUB : (gen ? R_FV_GEN : R_NOP);
-            n_ent += gen ? 1 : 0;
+            ent = gen ? 1 : 0;
           } else {
             const uint32_t fc[6] = {R_FC_ADD, R_FC_SUB, R_FC_MUL, R_FC_DIV, R_FC_RSUB, R_FC_RDIV};
             rid = fc[o];
-            n_ent += o == B_RDIV ? 2 : (gen ? 1 : 0);
+            ent = o == B_RDIV ? 2 : (gen ? 1 : 0);
           }
           if (rid != R_NOP) rid = n <= 3 ? rid + uint32_t(n - 1) : R_NONE;
+          wcf = op == OP_VAR && ((cfm >> (n - 1)) & 1u);
+          wfst = pfirst.get(n - 1);
+          cfm = wcf ? (cfm | (1u << (n - 1))) : (cfm & ~(1u << (n - 1)));
           prod.set(n - 1, out);
           ++i;  // the operator is consumed; stack size unchanged
         } else if (term) {
@@ -151,6 +211,11 @@ __device__ static void prepare_program(const PrepareArgs& a, int p, ST tok, S st
           if (op == OP_CONST) cv[out] = a.consts[coff + arg];
           rws = uint32_t(n);
           rid = op == OP_VAR ? R_NOP : (n <= 3 ? R_PUSH_CONST + uint32_t(n) : R_NONE);
+          ent = 0;
+          wcf = op == OP_VAR;
+          wfst = out;
+          if (n < 32) cfm = wcf ? (cfm | (1u << n)) : (cfm & ~(1u << n));
+          if (n < MAX_STACK) pfirst.set(n, out);
           prod.set(n, out);
           ++n;
         } else if (op >= 100u || op < 4) {
@@ -161,7 +226,10 @@ __device__ static void prepare_program(const PrepareArgs& a, int p, ST tok, S st
           const uint32_t bo = op >= 100u ? op - 100u : op;
           const uint32_t rb[6] = {R_BIN_ADD, R_BIN_SUB, R_BIN_GEN, R_BIN_GEN, R_BIN_RSUB, R_BIN_GEN};
           rid = n <= 4 ? rb[bo] + uint32_t(n - 2) : R_NONE;
-          n_ent += rb[bo] == R_BIN_GEN ? 2 : 0;
+          ent = rb[bo] == R_BIN_GEN ? 2 : 0;
+          wcf = ((cfm >> (n - 2)) & 1u) && ((cfm >> (n - 1)) & 1u);
+          wfst = pfirst.get(n - 2);
+          cfm = wcf ? (cfm | (1u << (n - 2))) : (cfm & ~(1u << (n - 2)));
           --n;
           prod.set(n - 1, out);
         } else {
@@ -169,13 +237,20 @@ __device__ static void prepare_program(const PrepareArgs& a, int p, ST tok, S st
           i0 = n <= 4 ? I0_UN + 4u * (op - OP_SIN) + uint32_t(n - 1) : I0_NONE;
           rws = uint32_t(n - 1);
           rid = n <= 4 ? R_UN + uint32_t(n - 1) : R_NONE;
-          n_ent += 1;
+          ent = 1;
+          wcf = (cfm >> (n - 1)) & 1u;
+          wfst = pfirst.get(n - 1);
           prod.set(n - 1, out);
         }
         nmax = n > nmax ? n : nmax;
         // arg: variable index (VAR words), constant slot (CONST words), 0 otherwise
         const uint32_t warg = term ? arg : 0u;
         code[out] = h | (warg << 8) | (wslot << 16) | (i0 << 24);
+        if (wcf)
+          rid = R_NOP;
+        else
+          n_ent += ent;
+        wfirst.set(out, wfst | (wcf ? 0x8000 : 0));
         aux[out] = pa | (rws << 16) | (rid << 24);
         ++out;
       }
@@ -201,14 +276,15 @@ __device__ static void prepare_program(const PrepareArgs& a, int p, ST tok, S st
     a.class_list[int64_t(cls) * a.n_programs + slot] = p;
     // and by tape size (the adjoint keeps short tapes in registers)
     // adjoint lists: 0 short value tape, 1 long value tape; register need
-    // <= 4: 2, 3, 4 at most GRAD_DTAPE_SMALL, MID, LARGE derivative-tape
-    // entries
-    const int lc = L_dec > a.short_words ? 1
-                   : need_root > 4       ? 0
+    // <= 4 and at most GRAD_LANE_SLOTS constant slots: 2, 3, 4 at most
+    // GRAD_DTAPE_SMALL, MID, LARGE derivative-tape entries
+    const int lc = L_dec > a.short_words                     ? 1
+                   : need_root > 4 || cc > GRAD_LANE_SLOTS    ? 0
                    : n_ent <= GRAD_DTAPE_SMALL ? 2
                    : n_ent <= GRAD_DTAPE_MID   ? 3
                    : n_ent <= GRAD_DTAPE_LARGE ? 4
                                                : 0;
+    if (lc >= 2) dtape_words(a.code + off, a.aux + off, L_dec, need, stack);
     const int ls = atomicAdd(a.len_count + lc, 1);
     a.len_list[int64_t(lc) * a.n_programs + ls] = p;
   }

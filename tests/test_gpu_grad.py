@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 import gates
+import progtext
 from oracle import fitness as ofit
 from oracle import grad as og
 from oracle import interp
@@ -195,6 +196,39 @@ def test_tape_size_boundaries():
         assert np.all(err <= GRAD_RTOL * scale + 1e-7), (p, g[p], g64)
         n_cmp += int(np.any(stable))
     assert n_cmp == 5
+
+
+def test_constant_free_subtrees():
+    """Subtrees without constants store no tape entries and the reverse sweep
+    steps over them: constant-free root (unused slot: zero gradient),
+    constant-free left / right operands, nested and fused forms."""
+    data = wl.make_dataset(29, 2000, 2, x_range=(1.0, 3.0), target_len=8)
+    texts = [
+        ("x0 x1 * sin x0 cos +", 1),
+        ("x0 x1 * sin c0 x0 * +", 1),
+        ("c0 x0 x1 / sqrt x1 exp * -", 1),
+        ("x0 sin x1 cos * c0 c1 + /", 2),
+        ("x0 c0 + x1 x0 * x1 sin / *", 1),
+        ("x1 x0 x1 * x0 / - c0 * x0 x1 + sin x0 * log c1 * +", 2),
+        ("x0 x1 - x0 * x1 x0 / + c0 /", 1),
+        ("c0 x0 x1 * x1 x0 - / sin *", 1),
+    ]
+    progs = [(progtext.parse(t), [0.7, -1.3][:k]) for t, k in texts]
+    ps = wl.pack_programs(progs)
+    f, g, st = _grad(ps, data)
+    assert np.all(st == 0)
+    for p in range(ps.n):
+        t, c = ps.program(p)
+        F, g64 = og.mse_and_grad(t, c, data.X, data.y)
+        o, cc = int(ps.const_offset[p]), int(ps.const_count[p])
+        assert abs(f[p] - F) <= 1e-5 * abs(F) + gates.atol(ofit.MSE, data.y), texts[p]
+        if p == 0:
+            assert g[o] == 0.0 and g64[0] == 0.0
+            continue
+        stable, scale = _stable_components(t, c, data, g64)
+        assert np.any(stable), texts[p]
+        err = np.abs(g[o:o + cc] - g64)[stable]
+        assert np.all(err <= GRAD_RTOL * scale + 1e-7), (texts[p], g[o:o + cc], g64)
 
 
 def test_autograd_function_and_adam():
