@@ -11,10 +11,10 @@ namespace bgl {
 
 constexpr int GRAD_SHORT_WORDS = 64;   // tape in registers up to this many decoded words
 constexpr int GRAD_LONG_WORDS = 256;   // tape in LDS up to this many (longer: TOO_LONG)
-// the derivative-tape adjoint (register need <= 4, 2 cases per lane): tape
-// entries per case of its three kernels (4, 3 and 2 waves per SIMD)
-constexpr int GRAD_DTAPE_SMALL = 32;
-constexpr int GRAD_DTAPE_MID = 48;
+// the derivative-tape adjoint (register need <= 4): tape entries per case of
+// its three kernels (4, 2 and 2 cases per lane)
+constexpr int GRAD_DTAPE_SMALL = 16;
+constexpr int GRAD_DTAPE_MID = 32;
 constexpr int GRAD_DTAPE_LARGE = 64;
 // adjoint program lists: 0 short value tape, 1 long value tape, 2..4
 // derivative tape of at most GRAD_DTAPE_SMALL / MID / LARGE entries
@@ -25,7 +25,7 @@ constexpr int GRAD_LANE_SLOTS = 8;
 // cases per work item of the adjoint (at most), a multiple of the cases one
 // tile of every adjoint kernel covers
 constexpr int64_t GRAD_CHUNK_CASES = 1024;
-constexpr int64_t GRAD_TILE_CASES = 128;
+constexpr int64_t GRAD_TILE_CASES = 256;
 
 // Reverse handler of a decoded word in the derivative-tape adjoint (bits
 // 24..31 of the word's aux entry).  n is the stack size before the word in

@@ -353,20 +353,21 @@ __global__ void __launch_bounds__(64) k_grad(GradArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// The derivative-tape adjoint: programs of register need <= 4 whose tape
-// fits GRAD_DTAPE_SMALL (list 2) or GRAD_DTAPE_LARGE (list 3) entries per
-// case, GK cases per lane.
+// The derivative-tape adjoint: programs of register need <= 4 and at most
+// GRAD_LANE_SLOTS constant slots whose tape fits GRAD_DTAPE_SMALL (list 2, 4
+// cases per lane), GRAD_DTAPE_MID (list 3, 2 cases per lane) or
+// GRAD_DTAPE_LARGE (list 4, 2 cases per lane) entries per case.
 //
-// The forward sweep runs the small-stack handlers (word bits 24..31, stack
-// size n known per handler: every stack slot is a register named at compile
-// time) and each handler stores the local partial derivatives the reverse
-// sweep will need, not its output: binary *, / and reversed / two entries
-// (d/da, d/db), unary operators one (sin x takes cos x from its own
-// reduction), fused VAR *, / one, fused CONST *, / one (d/dc) and reversed /
-// two, every other word none.  Entries are appended in word order, so the
-// reverse sweep, walking the words backwards, takes them from the end with a
-// wave-uniform counter.  The reverse handler of a word (aux bits 24..31) is a
-// linear update of the adjoint stack A:
+// The forward sweep runs the small-stack handlers (stack size n known per
+// handler: every stack slot is a register named at compile time) and each
+// handler stores the local partial derivatives the reverse sweep will need,
+// not its output: binary *, / and reversed / two entries (d/da, d/db), unary
+// operators one (sin x takes cos x from its own reduction), fused VAR *, /
+// one, fused CONST *, / one (d/dc) and reversed / two, every other word none.
+// Entries are appended in word order, so the reverse sweep, walking the
+// words backwards, takes them from the end with a wave-uniform counter.  The
+// reverse handler of a word (aux bits 24..31) is a linear update of the
+// adjoint stack A:
 //   binary at n    A[n-1] = A[n-2] d/db,  A[n-2] = A[n-2] d/da
 //   unary, fused   A[n-1] scaled by d/dtop
 //   CONST          its slot's gradient gains A (times d/dc when fused)
@@ -374,154 +375,182 @@ __global__ void __launch_bounds__(64) k_grad(GradArgs a) {
 // entries (their own forward handlers), and the reverse sweep follows a
 // per-word "next" index (aux bits 0..7) that skips such a subtree in one
 // step, and skips the words whose reverse update is the identity.
-// The tape is one register array per case (list 3: two, entries 0..31 and
-// 32..63; an index addresses at most a 32-entry array).
-constexpr int GK = 2;
-static_assert(GRAD_TILE_CASES % (GK * 64) == 0, "adjoint chunks hold whole tiles");
+// The tape is one register array per case (list 4: two, entries 0..31 and
+// 32..63), each array a separate variable so that it stays in registers.
+static_assert(GRAD_TILE_CASES % (4 * 64) == 0 && GRAD_TILE_CASES % (2 * 64) == 0,
+              "adjoint chunks hold whole tiles");
 
-template <bool COS>
-__device__ __forceinline__ void trig2(float& a, float& b) {
-  float v[GK] = {a, b};
-  trig_tile<COS, GK>(v);
-  a = v[0];
-  b = v[1];
-}
-
-// entry e of case k's tape: lo[e] for e < 32, hi[e - 32] above (HI = 0: no
-// upper part)
-template <int HI>
-struct DTape {
-  static constexpr int HS = HI > 0 ? HI : 1;
+// The tape of 2 cases per lane: entry e of case k in lk[e] (e < 32) or
+// hk[e - 32] (H > 0).
+template <int H>
+struct Tape2 {
+  static constexpr int HS = H > 0 ? H : 1;
+  float (&l0)[32];
+  float (&l1)[32];
+  float (&h0)[HS];
+  float (&h1)[HS];
+  __device__ __forceinline__ void put(int e, const float (&v)[2]) {
+    if (H == 0 || e < 32) {
+      l0[e & 31] = v[0];
+      l1[e & 31] = v[1];
+    } else {
+      h0[(e - 32) & (HS - 1)] = v[0];
+      h1[(e - 32) & (HS - 1)] = v[1];
+    }
+  }
+  __device__ __forceinline__ void get(int e, float (&v)[2]) const {
+    if constexpr (H == 0) {
+      v[0] = l0[e & 31];
+      v[1] = l1[e & 31];
+    } else {
+      // both halves read and one selected (no branch on the entry index)
+      const float x0 = opaque(l0[e & 31]), y0 = opaque(h0[(e - 32) & (HS - 1)]);
+      const float x1 = opaque(l1[e & 31]), y1 = opaque(h1[(e - 32) & (HS - 1)]);
+      v[0] = e < 32 ? x0 : y0;
+      v[1] = e < 32 ? x1 : y1;
+    }
+  }
 };
 
-template <int HI>
-__device__ __forceinline__ void dt_put(float (&lo0)[32], float (&lo1)[32], float (&hi0)[DTape<HI>::HS],
-                                       float (&hi1)[DTape<HI>::HS], int e, float v0, float v1) {
-  if (HI == 0 || e < 32) {
-    lo0[e & 31] = v0;
-    lo1[e & 31] = v1;
-  } else {
-    hi0[(e - 32) & (DTape<HI>::HS - 1)] = v0;
-    hi1[(e - 32) & (DTape<HI>::HS - 1)] = v1;
+// The tape of 4 cases per lane, N entries per case.
+template <int N>
+struct Tape4 {
+  float (&t0)[N];
+  float (&t1)[N];
+  float (&t2)[N];
+  float (&t3)[N];
+  __device__ __forceinline__ void put(int e, const float (&v)[4]) {
+    t0[e & (N - 1)] = v[0];
+    t1[e & (N - 1)] = v[1];
+    t2[e & (N - 1)] = v[2];
+    t3[e & (N - 1)] = v[3];
   }
-}
-
-template <int HI>
-__device__ __forceinline__ float dt_get(const float (&lo)[32], const float (&hi)[DTape<HI>::HS], int e) {
-  if constexpr (HI == 0) {
-    return lo[e & 31];
-  } else {
-    const float x = opaque(lo[e & 31]);
-    const float y = opaque(hi[(e - 32) & (HI - 1)]);
-    return e < 32 ? x : y;
+  __device__ __forceinline__ void get(int e, float (&v)[4]) const {
+    v[0] = t0[e & (N - 1)];
+    v[1] = t1[e & (N - 1)];
+    v[2] = t2[e & (N - 1)];
+    v[3] = t3[e & (N - 1)];
   }
-}
+};
 
-// one forward word (forward handler fid); e = the next free tape entry
-template <int HI>
-__device__ __forceinline__ void dt_fwd(uint32_t fid, float cv, float x0, float x1, float (&st)[GK][4],
-                                       float (&lo0)[32], float (&lo1)[32], float (&hi0)[DTape<HI>::HS],
-                                       float (&hi1)[DTape<HI>::HS], int& e) {
-#define BGL_PUT(V0, V1)                        \
-  dt_put<HI>(lo0, lo1, hi0, hi1, e, V0, V1);   \
+#define BGL_K(G) _Pragma("unroll") for (int k = 0; k < (G); ++k)
+
+// one forward word (forward handler fid) for G cases; e = the next free tape
+// entry
+template <int G, class TP>
+__device__ __forceinline__ void dt_fwd(uint32_t fid, float cv, const float (&x)[G], float (&st)[G][4], TP& tp,
+                                       int& e) {
+#define BGL_PUT(D) \
+  tp.put(e, D);    \
   ++e;
   switch (fid) {
-#define BGL_F_PUSH(N)     \
-  case I0_PUSH_VAR + N:   \
-    st[0][N] = x0;        \
-    st[1][N] = x1;        \
-    break;                \
-  case I0_PUSH_CONST + N: \
-    st[0][N] = cv;        \
-    st[1][N] = cv;        \
+#define BGL_F_PUSH(N)                    \
+  case I0_PUSH_VAR + N:                  \
+    BGL_K(G) st[k][N] = x[k];            \
+    break;                               \
+  case I0_PUSH_CONST + N:                \
+    BGL_K(G) st[k][N] = cv;              \
     break;
     BGL_F_PUSH(0) BGL_F_PUSH(1) BGL_F_PUSH(2) BGL_F_PUSH(3)
 #undef BGL_F_PUSH
-#define BGL_F_BIN(O, N)                                                   \
-  case I0_BIN + 3 * O + (N - 2): {                                        \
-    const float a0 = st[0][N - 2], b0 = st[0][N - 1];                     \
-    const float a1 = st[1][N - 2], b1 = st[1][N - 1];                     \
-    st[0][N - 2] = gbinop<O>(a0, b0);                                     \
-    st[1][N - 2] = gbinop<O>(a1, b1);                                     \
-    if constexpr (O == B_MUL || O == B_DIV || O == B_RDIV) {              \
-      float dA0, dB0, dA1, dB1;                                           \
-      dbinop<O>(a0, b0, dA0, dB0);                                        \
-      dbinop<O>(a1, b1, dA1, dB1);                                        \
-      BGL_PUT(dA0, dA1)                                                   \
-      BGL_PUT(dB0, dB1)                                                   \
-    }                                                                     \
-    break;                                                                \
+#define BGL_F_BIN(O, N)                                       \
+  case I0_BIN + 3 * O + (N - 2): {                            \
+    float dA[G], dB[G];                                       \
+    BGL_K(G) {                                                \
+      const float a = st[k][N - 2], b = st[k][N - 1];         \
+      st[k][N - 2] = gbinop<O>(a, b);                         \
+      dbinop<O>(a, b, dA[k], dB[k]);                          \
+    }                                                         \
+    if constexpr (O == B_MUL || O == B_DIV || O == B_RDIV) {  \
+      BGL_PUT(dA)                                             \
+      BGL_PUT(dB)                                             \
+    }                                                         \
+    break;                                                    \
   }
 #define BGL_F_BIN3(O) BGL_F_BIN(O, 2) BGL_F_BIN(O, 3) BGL_F_BIN(O, 4)
     BGL_F_BIN3(B_ADD) BGL_F_BIN3(B_SUB) BGL_F_BIN3(B_MUL) BGL_F_BIN3(B_DIV) BGL_F_BIN3(B_RSUB) BGL_F_BIN3(B_RDIV)
 #undef BGL_F_BIN3
 #undef BGL_F_BIN
-#define BGL_F_UN(N)                                                           \
-  case I0_UN + 0 * 4 + (N - 1): {                                             \
-    float s[GK] = {st[0][N - 1], st[1][N - 1]}, c[GK];                        \
-    sincos_tile<GK>(s, c);                                                    \
-    st[0][N - 1] = s[0];                                                      \
-    st[1][N - 1] = s[1];                                                      \
-    BGL_PUT(c[0], c[1])                                                       \
-    break;                                                                    \
-  }                                                                           \
-  case I0_UN + 1 * 4 + (N - 1): {                                             \
-    float d0 = st[0][N - 1], d1 = st[1][N - 1];                               \
-    trig2<true>(st[0][N - 1], st[1][N - 1]);                                  \
-    trig2<false>(d0, d1);                                                     \
-    BGL_PUT(-d0, -d1)                                                         \
-    break;                                                                    \
-  }                                                                           \
-  case I0_UN + 2 * 4 + (N - 1): {                                             \
-    const float u0 = st[0][N - 1], u1 = st[1][N - 1];                         \
-    st[0][N - 1] = op_exp(u0);                                                \
-    st[1][N - 1] = op_exp(u1);                                                \
-    BGL_PUT(dunary(2u, u0, st[0][N - 1]), dunary(2u, u1, st[1][N - 1]))       \
-    break;                                                                    \
-  }                                                                           \
-  case I0_UN + 3 * 4 + (N - 1): {                                             \
-    const float u0 = st[0][N - 1], u1 = st[1][N - 1];                         \
-    st[0][N - 1] = op_log(u0);                                                \
-    st[1][N - 1] = op_log(u1);                                                \
-    BGL_PUT(dunary(3u, u0, 0.0f), dunary(3u, u1, 0.0f))                       \
-    break;                                                                    \
-  }                                                                           \
-  case I0_UN + 4 * 4 + (N - 1): {                                             \
-    const float u0 = st[0][N - 1], u1 = st[1][N - 1];                         \
-    st[0][N - 1] = op_sqrt(u0);                                               \
-    st[1][N - 1] = op_sqrt(u1);                                               \
-    BGL_PUT(dunary(4u, u0, st[0][N - 1]), dunary(4u, u1, st[1][N - 1]))       \
-    break;                                                                    \
+#define BGL_F_UN(N)                                            \
+  case I0_UN + 0 * 4 + (N - 1): {                              \
+    float s[G], c[G];                                          \
+    BGL_K(G) s[k] = st[k][N - 1];                              \
+    sincos_tile<G>(s, c);                                      \
+    BGL_K(G) st[k][N - 1] = s[k];                              \
+    BGL_PUT(c)                                                 \
+    break;                                                     \
+  }                                                            \
+  case I0_UN + 1 * 4 + (N - 1): {                              \
+    float v[G], d[G];                                          \
+    BGL_K(G) v[k] = d[k] = st[k][N - 1];                       \
+    trig_tile<true, G>(v);                                     \
+    trig_tile<false, G>(d);                                    \
+    BGL_K(G) {                                                 \
+      st[k][N - 1] = v[k];                                     \
+      d[k] = -d[k];                                            \
+    }                                                          \
+    BGL_PUT(d)                                                 \
+    break;                                                     \
+  }                                                            \
+  case I0_UN + 2 * 4 + (N - 1): {                              \
+    float d[G];                                                \
+    BGL_K(G) {                                                 \
+      const float u = st[k][N - 1];                            \
+      st[k][N - 1] = op_exp(u);                                \
+      d[k] = dunary(2u, u, st[k][N - 1]);                      \
+    }                                                          \
+    BGL_PUT(d)                                                 \
+    break;                                                     \
+  }                                                            \
+  case I0_UN + 3 * 4 + (N - 1): {                              \
+    float d[G];                                                \
+    BGL_K(G) {                                                 \
+      const float u = st[k][N - 1];                            \
+      st[k][N - 1] = op_log(u);                                \
+      d[k] = dunary(3u, u, 0.0f);                              \
+    }                                                          \
+    BGL_PUT(d)                                                 \
+    break;                                                     \
+  }                                                            \
+  case I0_UN + 4 * 4 + (N - 1): {                              \
+    float d[G];                                                \
+    BGL_K(G) {                                                 \
+      const float u = st[k][N - 1];                            \
+      st[k][N - 1] = op_sqrt(u);                               \
+      d[k] = dunary(4u, u, st[k][N - 1]);                      \
+    }                                                          \
+    BGL_PUT(d)                                                 \
+    break;                                                     \
   }
     BGL_F_UN(1) BGL_F_UN(2) BGL_F_UN(3) BGL_F_UN(4)
 #undef BGL_F_UN
-#define BGL_F_FUSED(O, N)                                                 \
-  case I0_FUSED + 3 * O + (N - 1): {                                      \
-    const float a0 = st[0][N - 1], a1 = st[1][N - 1];                     \
-    st[0][N - 1] = gbinop<O>(a0, x0);                                     \
-    st[1][N - 1] = gbinop<O>(a1, x1);                                     \
-    if constexpr (O == B_MUL || O == B_DIV || O == B_RDIV) {              \
-      float dA0, dB0, dA1, dB1;                                           \
-      dbinop<O>(a0, x0, dA0, dB0);                                        \
-      dbinop<O>(a1, x1, dA1, dB1);                                        \
-      BGL_PUT(dA0, dA1)                                                   \
-    }                                                                     \
-    break;                                                                \
-  }                                                                       \
-  case I0_FUSED + 3 * (6 + O) + (N - 1): {                                \
-    const float a0 = st[0][N - 1], a1 = st[1][N - 1];                     \
-    st[0][N - 1] = gbinop<O>(a0, cv);                                     \
-    st[1][N - 1] = gbinop<O>(a1, cv);                                     \
-    if constexpr (O == B_MUL || O == B_DIV || O == B_RDIV) {              \
-      float dA0, dB0, dA1, dB1;                                           \
-      dbinop<O>(a0, cv, dA0, dB0);                                        \
-      dbinop<O>(a1, cv, dA1, dB1);                                        \
-      if constexpr (O == B_RDIV) {                                        \
-        BGL_PUT(dA0, dA1)                                                 \
-      }                                                                   \
-      BGL_PUT(dB0, dB1)                                                   \
-    }                                                                     \
-    break;                                                                \
+#define BGL_F_FUSED(O, N)                                     \
+  case I0_FUSED + 3 * O + (N - 1): {                          \
+    float dA[G], dB[G];                                       \
+    BGL_K(G) {                                                \
+      const float a = st[k][N - 1];                           \
+      st[k][N - 1] = gbinop<O>(a, x[k]);                      \
+      dbinop<O>(a, x[k], dA[k], dB[k]);                       \
+    }                                                         \
+    if constexpr (O == B_MUL || O == B_DIV || O == B_RDIV) {  \
+      BGL_PUT(dA)                                             \
+    }                                                         \
+    break;                                                    \
+  }                                                           \
+  case I0_FUSED + 3 * (6 + O) + (N - 1): {                    \
+    float dA[G], dB[G];                                       \
+    BGL_K(G) {                                                \
+      const float a = st[k][N - 1];                           \
+      st[k][N - 1] = gbinop<O>(a, cv);                        \
+      dbinop<O>(a, cv, dA[k], dB[k]);                         \
+    }                                                         \
+    if constexpr (O == B_RDIV) {                              \
+      BGL_PUT(dA)                                             \
+    }                                                         \
+    if constexpr (O == B_MUL || O == B_DIV || O == B_RDIV) {  \
+      BGL_PUT(dB)                                             \
+    }                                                         \
+    break;                                                    \
   }
 #define BGL_F_FUSED3(O) BGL_F_FUSED(O, 1) BGL_F_FUSED(O, 2) BGL_F_FUSED(O, 3)
     BGL_F_FUSED3(B_ADD) BGL_F_FUSED3(B_SUB) BGL_F_FUSED3(B_MUL) BGL_F_FUSED3(B_DIV) BGL_F_FUSED3(B_RSUB)
@@ -529,40 +558,43 @@ __device__ __forceinline__ void dt_fwd(uint32_t fid, float cv, float x0, float x
 #undef BGL_F_FUSED3
 #undef BGL_F_FUSED
     // constant-free words: values only
-#define BGL_N_BIN(J, O, N)                                \
-  case F_BIN_NT + 3 * J + (N - 2):                        \
-    st[0][N - 2] = gbinop<O>(st[0][N - 2], st[0][N - 1]); \
-    st[1][N - 2] = gbinop<O>(st[1][N - 2], st[1][N - 1]); \
+#define BGL_N_BIN(J, O, N)                                         \
+  case F_BIN_NT + 3 * J + (N - 2):                                 \
+    BGL_K(G) st[k][N - 2] = gbinop<O>(st[k][N - 2], st[k][N - 1]); \
     break;
 #define BGL_N_BIN3(J, O) BGL_N_BIN(J, O, 2) BGL_N_BIN(J, O, 3) BGL_N_BIN(J, O, 4)
     BGL_N_BIN3(0, B_MUL) BGL_N_BIN3(1, B_DIV) BGL_N_BIN3(2, B_RDIV)
 #undef BGL_N_BIN3
 #undef BGL_N_BIN
-#define BGL_N_UN(N)                                         \
-  case F_UN_NT + 0 * 4 + (N - 1):                           \
-    trig2<false>(st[0][N - 1], st[1][N - 1]);               \
-    break;                                                  \
-  case F_UN_NT + 1 * 4 + (N - 1):                           \
-    trig2<true>(st[0][N - 1], st[1][N - 1]);                \
-    break;                                                  \
-  case F_UN_NT + 2 * 4 + (N - 1):                           \
-    st[0][N - 1] = op_exp(st[0][N - 1]);                    \
-    st[1][N - 1] = op_exp(st[1][N - 1]);                    \
-    break;                                                  \
-  case F_UN_NT + 3 * 4 + (N - 1):                           \
-    st[0][N - 1] = op_log(st[0][N - 1]);                    \
-    st[1][N - 1] = op_log(st[1][N - 1]);                    \
-    break;                                                  \
-  case F_UN_NT + 4 * 4 + (N - 1):                           \
-    st[0][N - 1] = op_sqrt(st[0][N - 1]);                   \
-    st[1][N - 1] = op_sqrt(st[1][N - 1]);                   \
+#define BGL_N_UN(N)                                  \
+  case F_UN_NT + 0 * 4 + (N - 1): {                  \
+    float v[G];                                      \
+    BGL_K(G) v[k] = st[k][N - 1];                    \
+    trig_tile<false, G>(v);                          \
+    BGL_K(G) st[k][N - 1] = v[k];                    \
+    break;                                           \
+  }                                                  \
+  case F_UN_NT + 1 * 4 + (N - 1): {                  \
+    float v[G];                                      \
+    BGL_K(G) v[k] = st[k][N - 1];                    \
+    trig_tile<true, G>(v);                           \
+    BGL_K(G) st[k][N - 1] = v[k];                    \
+    break;                                           \
+  }                                                  \
+  case F_UN_NT + 2 * 4 + (N - 1):                    \
+    BGL_K(G) st[k][N - 1] = op_exp(st[k][N - 1]);    \
+    break;                                           \
+  case F_UN_NT + 3 * 4 + (N - 1):                    \
+    BGL_K(G) st[k][N - 1] = op_log(st[k][N - 1]);    \
+    break;                                           \
+  case F_UN_NT + 4 * 4 + (N - 1):                    \
+    BGL_K(G) st[k][N - 1] = op_sqrt(st[k][N - 1]);   \
     break;
     BGL_N_UN(1) BGL_N_UN(2) BGL_N_UN(3) BGL_N_UN(4)
 #undef BGL_N_UN
 #define BGL_N_FV(J, O, N)                                 \
   case F_FV_NT + 3 * J + (N - 1):                         \
-    st[0][N - 1] = gbinop<O>(st[0][N - 1], x0);           \
-    st[1][N - 1] = gbinop<O>(st[1][N - 1], x1);           \
+    BGL_K(G) st[k][N - 1] = gbinop<O>(st[k][N - 1], x[k]); \
     break;
 #define BGL_N_FV3(J, O) BGL_N_FV(J, O, 1) BGL_N_FV(J, O, 2) BGL_N_FV(J, O, 3)
     BGL_N_FV3(0, B_MUL) BGL_N_FV3(1, B_DIV) BGL_N_FV3(2, B_RDIV)
@@ -574,16 +606,22 @@ __device__ __forceinline__ void dt_fwd(uint32_t fid, float cv, float x0, float x
 #undef BGL_PUT
 }
 
-// slot arg (< GRAD_LANE_SLOTS) of the lane's gradient sums gains the two
-// cases' contributions: an LDS add without a returned value, so nothing waits
-// for it, and the adds of one lane reach its slot in program order
-__device__ __forceinline__ void add_const_grad(uint32_t arg, float g0, float g1, bool v0, bool v1, double* lg) {
-  const double v = (v0 ? double(g0) : 0.0) + (v1 ? double(g1) : 0.0);
+// slot arg (< GRAD_LANE_SLOTS) of the lane's gradient sums gains the cases'
+// contributions g[k] (valid cases only): an LDS add without a returned value,
+// so nothing waits for it, and the adds of one lane reach its slot in
+// program order
+template <int G>
+__device__ __forceinline__ void add_const_grad(uint32_t arg, const float (&g)[G], const bool (&valid)[G],
+                                               double* lg) {
+  double v = 0.0;
+  BGL_K(G) v += valid[k] ? double(g[k]) : 0.0;
   __hip_atomic_fetch_add(lg + arg * 64, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 
-template <int HI>  // upper tape entries per case (0: at most 32 entries)
-__device__ void dtape_item(const GradArgs& a, int p, int c, float* lds) {
+// one program on one chunk of cases, G cases per lane (case base + 64 k +
+// lane of each tile of 64 G cases)
+template <int G, class TP>
+__device__ __forceinline__ void dtape_item(const GradArgs& a, int p, int c, float* lds, TP tp) {
   const int lane = threadIdx.x;
   const ProgMeta m = a.meta[p];
   const int L = m.len;
@@ -599,154 +637,163 @@ __device__ void dtape_item(const GradArgs& a, int p, int c, float* lds) {
   };
   const uint32_t va = lane < L ? a.aux[off + lane] : 0u;
   const float vv = lane < L ? a.cval[off + lane] : 0.0f;
-  // LDS: input tile [D][GK][64] | lane gradients [LANE_SLOTS][64] doubles
+  // LDS: input tile [D][G][64] | lane gradients [LANE_SLOTS][64] doubles
   // (the program has at most LANE_SLOTS constant slots)
   float* xl = lds + lane;
-  double* lg = reinterpret_cast<double*>(lds + a.D * GK * 64) + lane;
-  float lo0[32], lo1[32], hi0[DTape<HI>::HS], hi1[DTape<HI>::HS];
+  double* lg = reinterpret_cast<double*>(lds + a.D * G * 64) + lane;
   for (int j = 0; j < LANE_SLOTS; ++j) lg[j * 64] = 0.0;
   __builtin_amdgcn_wave_barrier();
   double s_mse = 0.0;
   const float inv2m = float(2.0 / double(a.M));
   const int64_t c0 = int64_t(c) * a.chunk;
   const int64_t c1 = c0 + a.chunk < a.M ? c0 + a.chunk : a.M;
-  for (int64_t base = c0; base < c1; base += GK * 64) {
-    const int64_t i0 = base + lane, i1 = base + 64 + lane;
-    const bool v0 = i0 < a.M, v1 = i1 < a.M;
+  for (int64_t base = c0; base < c1; base += G * 64) {
+    bool valid[G];
+    float yv[G];
+    BGL_K(G) valid[k] = base + 64 * k + lane < a.M;
     for (int d = 0; d < a.D; ++d) {
       if (!((vmask >> d) & 1u)) continue;
-      const float x0 = a.Xt[int64_t(d) * a.Mp + i0];
-      const float x1 = a.Xt[int64_t(d) * a.Mp + i1];
-      xl[(d * GK) * 64] = x0;
-      xl[(d * GK + 1) * 64] = x1;
+      float xv[G];
+      BGL_K(G) xv[k] = a.Xt[int64_t(d) * a.Mp + base + 64 * k + lane];
+      BGL_K(G) xl[(d * G + k) * 64] = xv[k];
     }
-    const float y0 = a.yp[i0], y1 = a.yp[i1];
+    BGL_K(G) yv[k] = a.yp[base + 64 * k + lane];
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the tile is in LDS
     // ---- forward: values on the stack, partial derivatives on the tape
-    float st[GK][4];
-#pragma unroll
-    for (int k = 0; k < GK; ++k)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) st[k][j] = 0.0f;
+    float st[G][4];
+    BGL_K(G) for (int j = 0; j < 4; ++j) st[k][j] = 0.0f;
     // The input row a word reads is loaded one word ahead, so that the LDS
     // latency overlaps the previous word; words that read no input load row
     // min(arg, D - 1), which is in the tile and unused.
     const float* xt = lds + lane;
     int e = 0;
     uint32_t w = __builtin_amdgcn_readlane(va, 0);
-    float xa0 = xt[xrow(w) * (GK * 64)], xa1 = xt[xrow(w) * (GK * 64) + 64];
+    float xa[G];
+    BGL_K(G) xa[k] = xt[xrow(w) * (G * 64) + 64 * k];
     for (int t = 0; t < L; ++t) {
       const uint32_t wn = t + 1 < L ? __builtin_amdgcn_readlane(va, t + 1) : 0u;
-      const float xb0 = xt[xrow(wn) * (GK * 64)], xb1 = xt[xrow(wn) * (GK * 64) + 64];
+      float xb[G];
+      BGL_K(G) xb[k] = xt[xrow(wn) * (G * 64) + 64 * k];
       const float cv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vv), t));
-      dt_fwd<HI>((w >> 8) & 0xFFu, cv, xa0, xa1, st, lo0, lo1, hi0, hi1, e);
+      dt_fwd<G>((w >> 8) & 0xFFu, cv, xa, st, tp, e);
       w = wn;
-      xa0 = xb0;
-      xa1 = xb1;
+      BGL_K(G) xa[k] = xb[k];
     }
     // ---- seed and fitness terms
-    const double e0 = double(st[0][0]) - double(y0), e1 = double(st[1][0]) - double(y1);
-    s_mse += (v0 ? e0 * e0 : 0.0) + (v1 ? e1 * e1 : 0.0);
-    float A[GK][4];
-#pragma unroll
-    for (int k = 0; k < GK; ++k)
-#pragma unroll
+    float A[G][4];
+    BGL_K(G) {
+      const double ek = double(st[k][0]) - double(yv[k]);
+      s_mse += valid[k] ? ek * ek : 0.0;
       for (int j = 0; j < 4; ++j) A[k][j] = 0.0f;
-    A[0][0] = v0 ? float(e0) * inv2m : 0.0f;
-    A[1][0] = v1 ? float(e1) * inv2m : 0.0f;
+      A[k][0] = valid[k] ? float(ek) * inv2m : 0.0f;
+    }
     // ---- reverse: linear updates of the adjoint stack, visiting only the
     // words that are neither constant-free nor NOP (the root always)
-    auto T0 = [&](int i) { return dt_get<HI>(lo0, hi0, i); };
-    auto T1 = [&](int i) { return dt_get<HI>(lo1, hi1, i); };
     for (int t = L - 1; t >= 0;) {
       const uint32_t x = __builtin_amdgcn_readlane(va, t);
       const uint32_t rid = x >> 24;
       const uint32_t arg = (x >> 16) & 0xFFu;
       const float cv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vv), t));
       t = int(x & 0xFFu) - 1;
-#define BGL_CG(G0, G1) add_const_grad(arg, G0, G1, v0, v1, lg);
+      float g[G], d0[G], d1[G];
       switch (rid) {
-#define BGL_R_PUSH(N)             \
-  case R_PUSH_CONST + N:          \
-    BGL_CG(A[0][N], A[1][N]) break;
+#define BGL_R_PUSH(N)                             \
+  case R_PUSH_CONST + N:                          \
+    BGL_K(G) g[k] = A[k][N];                      \
+    add_const_grad<G>(arg, g, valid, lg);         \
+    break;
         BGL_R_PUSH(0) BGL_R_PUSH(1) BGL_R_PUSH(2) BGL_R_PUSH(3)
 #undef BGL_R_PUSH
-#define BGL_R_BIN(N)                              \
-  case R_BIN_ADD + (N - 2):                       \
-    A[0][N - 1] = A[0][N - 2];                    \
-    A[1][N - 1] = A[1][N - 2];                    \
-    break;                                        \
-  case R_BIN_SUB + (N - 2):                       \
-    A[0][N - 1] = -A[0][N - 2];                   \
-    A[1][N - 1] = -A[1][N - 2];                   \
-    break;                                        \
-  case R_BIN_RSUB + (N - 2):                      \
-    A[0][N - 1] = A[0][N - 2];                    \
-    A[1][N - 1] = A[1][N - 2];                    \
-    A[0][N - 2] = -A[0][N - 2];                   \
-    A[1][N - 2] = -A[1][N - 2];                   \
-    break;                                        \
-  case R_BIN_GEN + (N - 2):                       \
-    e -= 2;                                       \
-    A[0][N - 1] = A[0][N - 2] * T0(e + 1);        \
-    A[1][N - 1] = A[1][N - 2] * T1(e + 1);        \
-    A[0][N - 2] *= T0(e);                         \
-    A[1][N - 2] *= T1(e);                         \
+#define BGL_R_BIN(N)                                    \
+  case R_BIN_ADD + (N - 2):                             \
+    BGL_K(G) A[k][N - 1] = A[k][N - 2];                 \
+    break;                                              \
+  case R_BIN_SUB + (N - 2):                             \
+    BGL_K(G) A[k][N - 1] = -A[k][N - 2];                \
+    break;                                              \
+  case R_BIN_RSUB + (N - 2):                            \
+    BGL_K(G) {                                          \
+      A[k][N - 1] = A[k][N - 2];                        \
+      A[k][N - 2] = -A[k][N - 2];                       \
+    }                                                   \
+    break;                                              \
+  case R_BIN_GEN + (N - 2):                             \
+    e -= 2;                                             \
+    tp.get(e, d0);                                      \
+    tp.get(e + 1, d1);                                  \
+    BGL_K(G) {                                          \
+      A[k][N - 1] = A[k][N - 2] * d1[k];                \
+      A[k][N - 2] *= d0[k];                             \
+    }                                                   \
     break;
         BGL_R_BIN(2) BGL_R_BIN(3) BGL_R_BIN(4)
 #undef BGL_R_BIN
-#define BGL_R_UN(N)       \
-  case R_UN + (N - 1):    \
-    e -= 1;               \
-    A[0][N - 1] *= T0(e); \
-    A[1][N - 1] *= T1(e); \
+#define BGL_R_UN(N)                       \
+  case R_UN + (N - 1):                    \
+    e -= 1;                               \
+    tp.get(e, d0);                        \
+    BGL_K(G) A[k][N - 1] *= d0[k];        \
     break;
         BGL_R_UN(1) BGL_R_UN(2) BGL_R_UN(3) BGL_R_UN(4)
 #undef BGL_R_UN
 #define BGL_R_FUSED(N)                                             \
   case R_FV_RSUB + (N - 1):                                        \
-    A[0][N - 1] = -A[0][N - 1];                                    \
-    A[1][N - 1] = -A[1][N - 1];                                    \
+    BGL_K(G) A[k][N - 1] = -A[k][N - 1];                           \
     break;                                                         \
   case R_FV_GEN + (N - 1):                                         \
     e -= 1;                                                        \
-    A[0][N - 1] *= T0(e);                                          \
-    A[1][N - 1] *= T1(e);                                          \
+    tp.get(e, d0);                                                 \
+    BGL_K(G) A[k][N - 1] *= d0[k];                                 \
     break;                                                         \
   case R_FC_ADD + (N - 1):                                         \
-    BGL_CG(A[0][N - 1], A[1][N - 1]) break;                        \
+    BGL_K(G) g[k] = A[k][N - 1];                                   \
+    add_const_grad<G>(arg, g, valid, lg);                          \
+    break;                                                         \
   case R_FC_SUB + (N - 1):                                         \
-    BGL_CG(-A[0][N - 1], -A[1][N - 1]) break;                      \
+    BGL_K(G) g[k] = -A[k][N - 1];                                  \
+    add_const_grad<G>(arg, g, valid, lg);                          \
+    break;                                                         \
   case R_FC_RSUB + (N - 1):                                        \
-    BGL_CG(A[0][N - 1], A[1][N - 1])                               \
-    A[0][N - 1] = -A[0][N - 1];                                    \
-    A[1][N - 1] = -A[1][N - 1];                                    \
+    BGL_K(G) {                                                     \
+      g[k] = A[k][N - 1];                                          \
+      A[k][N - 1] = -A[k][N - 1];                                  \
+    }                                                              \
+    add_const_grad<G>(arg, g, valid, lg);                          \
     break;                                                         \
   case R_FC_MUL + (N - 1):                                         \
     e -= 1;                                                        \
-    BGL_CG(A[0][N - 1] * T0(e), A[1][N - 1] * T1(e))               \
-    A[0][N - 1] *= cv;                                             \
-    A[1][N - 1] *= cv;                                             \
+    tp.get(e, d0);                                                 \
+    BGL_K(G) {                                                     \
+      g[k] = A[k][N - 1] * d0[k];                                  \
+      A[k][N - 1] *= cv;                                           \
+    }                                                              \
+    add_const_grad<G>(arg, g, valid, lg);                          \
     break;                                                         \
   case R_FC_DIV + (N - 1): {                                       \
     e -= 1;                                                        \
-    BGL_CG(A[0][N - 1] * T0(e), A[1][N - 1] * T1(e))               \
+    tp.get(e, d0);                                                 \
     float dA, dB;                                                  \
     dbinop<B_DIV>(0.0f, cv, dA, dB);                               \
-    A[0][N - 1] *= dA;                                             \
-    A[1][N - 1] *= dA;                                             \
+    BGL_K(G) {                                                     \
+      g[k] = A[k][N - 1] * d0[k];                                  \
+      A[k][N - 1] *= dA;                                           \
+    }                                                              \
+    add_const_grad<G>(arg, g, valid, lg);                          \
     break;                                                         \
   }                                                                \
   case R_FC_RDIV + (N - 1):                                        \
     e -= 2;                                                        \
-    BGL_CG(A[0][N - 1] * T0(e + 1), A[1][N - 1] * T1(e + 1))       \
-    A[0][N - 1] *= T0(e);                                          \
-    A[1][N - 1] *= T1(e);                                          \
+    tp.get(e, d0);                                                 \
+    tp.get(e + 1, d1);                                             \
+    BGL_K(G) {                                                     \
+      g[k] = A[k][N - 1] * d1[k];                                  \
+      A[k][N - 1] *= d0[k];                                        \
+    }                                                              \
+    add_const_grad<G>(arg, g, valid, lg);                          \
     break;
         BGL_R_FUSED(1) BGL_R_FUSED(2) BGL_R_FUSED(3)
 #undef BGL_R_FUSED
-#undef BGL_CG
         default:
           break;
       }
@@ -764,14 +811,28 @@ __device__ void dtape_item(const GradArgs& a, int p, int c, float* lds) {
   __builtin_amdgcn_wave_barrier();
 }
 
-// LIST 2, 3, 4: at most GRAD_DTAPE_SMALL, MID, LARGE entries per case (upper
-// tape 0, 16, 32 entries; 128, <= 168 and <= 256 VGPRs: 4, 3, 2 waves per
-// SIMD).
+// cases per lane of list 2, 3, 4
+__host__ __device__ constexpr int dtape_cases(int list) { return list == 2 ? 4 : 2; }
+
 template <int LIST>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LIST == 2 ? 4 : 1)))
-k_grad_dtape(GradArgs a) {
+__device__ __forceinline__ void dtape_list_item(const GradArgs& a, int p, int c, float* lds) {
+  if constexpr (LIST == 2) {
+    constexpr int N = GRAD_DTAPE_SMALL;
+    float t0[N], t1[N], t2[N], t3[N];
+    dtape_item<4>(a, p, c, lds, Tape4<N>{t0, t1, t2, t3});
+  } else {
+    constexpr int H = (LIST == 3 ? GRAD_DTAPE_MID : GRAD_DTAPE_LARGE) - 32;
+    constexpr int HS = H > 0 ? H : 1;
+    float l0[32], l1[32], h0[HS], h1[HS];
+    dtape_item<2>(a, p, c, lds, Tape2<H>{l0, l1, h0, h1});
+  }
+}
+
+// LIST 2, 3, 4: at most GRAD_DTAPE_SMALL (4 cases per lane), MID, LARGE
+// entries per case (2 cases per lane, upper tape 0 or 32 entries).
+template <int LIST>
+__global__ void __launch_bounds__(64) k_grad_dtape(GradArgs a) {
   extern __shared__ float lds[];
-  constexpr int HI = (LIST == 2 ? GRAD_DTAPE_SMALL : LIST == 3 ? GRAD_DTAPE_MID : GRAD_DTAPE_LARGE) - 32;
   const int32_t count = a.list_count[LIST];
   const int64_t items = int64_t(count) * a.n_chunks;
   const int32_t* list = a.list + LIST * int64_t(a.n_programs);
@@ -784,9 +845,10 @@ k_grad_dtape(GradArgs a) {
     if (item >= items) break;
     const int c = int(item / count);
     const int p = list[item % count];
-    dtape_item<HI>(a, p, c, lds);
+    dtape_list_item<LIST>(a, p, c, lds);
   }
 }
+#undef BGL_K
 
 __global__ void k_grad_finalize(GradFinalizeArgs a) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -829,20 +891,21 @@ size_t grad_lds_bytes(int D, bool long_tape) {
 hipError_t launch_grad(const GradArgs& a, hipStream_t s) {
   const int cus = grad_cu_count();
   const size_t l0 = grad_lds_bytes(a.D, false), l1 = grad_lds_bytes(a.D, true);
-  const size_t l2 = size_t(a.D) * GK * 64 * sizeof(float) + size_t(LANE_SLOTS) * 64 * sizeof(double);
+  const size_t l2 = size_t(a.D) * dtape_cases(2) * 64 * sizeof(float) + size_t(LANE_SLOTS) * 64 * sizeof(double);
+  const size_t l3 = size_t(a.D) * dtape_cases(3) * 64 * sizeof(float) + size_t(LANE_SLOTS) * 64 * sizeof(double);
   int nb0 = 0, nb1 = 0, nb2 = 0, nb3 = 0, nb4 = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb0, k_grad<false>, 64, l0) != hipSuccess || nb0 < 1) nb0 = 1;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb1, k_grad<true>, 64, l1) != hipSuccess || nb1 < 1) nb1 = 1;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb2, k_grad_dtape<2>, 64, l2) != hipSuccess || nb2 < 1) nb2 = 1;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb3, k_grad_dtape<3>, 64, l2) != hipSuccess || nb3 < 1) nb3 = 1;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb4, k_grad_dtape<4>, 64, l2) != hipSuccess || nb4 < 1) nb4 = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb3, k_grad_dtape<3>, 64, l3) != hipSuccess || nb3 < 1) nb3 = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb4, k_grad_dtape<4>, 64, l3) != hipSuccess || nb4 < 1) nb4 = 1;
   hipLaunchKernelGGL(k_grad_dtape<2>, dim3(nb2 * cus), dim3(64), l2, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_grad_dtape<3>, dim3(nb3 * cus), dim3(64), l2, s, a);
+  hipLaunchKernelGGL(k_grad_dtape<3>, dim3(nb3 * cus), dim3(64), l3, s, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_grad_dtape<4>, dim3(nb4 * cus), dim3(64), l2, s, a);
+  hipLaunchKernelGGL(k_grad_dtape<4>, dim3(nb4 * cus), dim3(64), l3, s, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_grad<false>, dim3(nb0 * cus), dim3(64), l0, s, a);
