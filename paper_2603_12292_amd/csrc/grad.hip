@@ -639,7 +639,6 @@ __device__ __forceinline__ void dtape_item(const GradArgs& a, int p, int c, floa
   const float vv = lane < L ? a.cval[off + lane] : 0.0f;
   // LDS: input tile [D][G][64] | lane gradients [LANE_SLOTS][64] doubles
   // (the program has at most LANE_SLOTS constant slots)
-  float* xl = lds + lane;
   double* lg = reinterpret_cast<double*>(lds + a.D * G * 64) + lane;
   for (int j = 0; j < LANE_SLOTS; ++j) lg[j * 64] = 0.0;
   __builtin_amdgcn_wave_barrier();
@@ -651,20 +650,23 @@ __device__ __forceinline__ void dtape_item(const GradArgs& a, int p, int c, floa
     bool valid[G];
     float yv[G];
     BGL_K(G) valid[k] = base + 64 * k + lane < a.M;
+    // the tile's inputs go straight from global memory to LDS (64 cases per
+    // instruction), every variable's loads issued before one wait
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the last tile's LDS reads are done
     for (int d = 0; d < a.D; ++d) {
       if (!((vmask >> d) & 1u)) continue;
-      float xv[G];
-      BGL_K(G) xv[k] = a.Xt[int64_t(d) * a.Mp + base + 64 * k + lane];
-      BGL_K(G) xl[(d * G + k) * 64] = xv[k];
+      BGL_K(G) __builtin_amdgcn_global_load_lds(a.Xt + int64_t(d) * a.Mp + base + 64 * k + lane,
+                                                lds + (d * G + k) * 64, 4, 0, 0);
     }
     BGL_K(G) yv[k] = a.yp[base + 64 * k + lane];
+    __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0): the tile is in LDS
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the tile is in LDS
     // ---- forward: values on the stack, partial derivatives on the tape
     float st[G][4];
     BGL_K(G) for (int j = 0; j < 4; ++j) st[k][j] = 0.0f;
-    // The input row a word reads is loaded one word ahead, so that the LDS
-    // latency overlaps the previous word; words that read no input load row
+    // The input row a word reads is loaded at the end of the previous word,
+    // into the registers the handler reads (no copies), so that the LDS
+    // latency overlaps the dispatch; words that read no input load row
     // min(arg, D - 1), which is in the tile and unused.
     const float* xt = lds + lane;
     int e = 0;
@@ -672,13 +674,10 @@ __device__ __forceinline__ void dtape_item(const GradArgs& a, int p, int c, floa
     float xa[G];
     BGL_K(G) xa[k] = xt[xrow(w) * (G * 64) + 64 * k];
     for (int t = 0; t < L; ++t) {
-      const uint32_t wn = t + 1 < L ? __builtin_amdgcn_readlane(va, t + 1) : 0u;
-      float xb[G];
-      BGL_K(G) xb[k] = xt[xrow(wn) * (G * 64) + 64 * k];
       const float cv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vv), t));
       dt_fwd<G>((w >> 8) & 0xFFu, cv, xa, st, tp, e);
-      w = wn;
-      BGL_K(G) xa[k] = xb[k];
+      w = t + 1 < L ? __builtin_amdgcn_readlane(va, t + 1) : 0u;
+      BGL_K(G) xa[k] = xt[xrow(w) * (G * 64) + 64 * k];
     }
     // ---- seed and fitness terms
     float A[G][4];
