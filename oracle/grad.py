@@ -1,11 +1,20 @@
-"""Gradient of the MSE fitness with respect to program constants -- test infrastructure.
+"""Gradient of the fitness with respect to program constants -- test infrastructure.
 
 The paper evolves structure and constants together and has no gradient step;
 the library adds a reverse-mode adjoint over the postfix tape so a program's
 ephemeral constants can be tuned by gradient descent.  This module is the
 float64 reference for it.
 
-For F = (1/M) sum_i (y_hat_i - y_i)^2 the seed is dF/dy_hat_i = 2 (y_hat_i - y_i) / M.
+Seeds dF/dy_hat_i:
+  MSE   F = (1/M) sum_i (y_hat_i - y_i)^2:  2 (y_hat_i - y_i) / M.
+  CORR  F = 1 - r^2 with r Pearson's coefficient (Eq. 1) of y_hat and y,
+        from the centred sums Sxx, Syy, Sxy (u_i = y_hat_i - mean y_hat,
+        w_i = y_i - mean y):
+            dr/dy_hat_i = w_i / sqrt(Sxx Syy) - r u_i / Sxx,
+            dF/dy_hat_i = -2 r dr/dy_hat_i.
+        Readings: the derivative is that of 1 - r^2 also where F is clamped
+        to [0, 1] (rounding only); Sxx == 0 (F = 1 by convention): 0; a NaN
+        fitness gives NaN seeds.
 Adjoints flow from each token to its operands (reverse token order) with
 these partial derivatives, matching the operator conventions of
 ``oracle.interp`` (derivative taken as 0 where a protected branch replaces
@@ -35,6 +44,7 @@ import math
 
 import numpy as np
 
+from . import fitness as ofit
 from . import interp
 
 ADD, SUB, MUL, DIV, SIN, COS, EXP, LOG, SQRT, VAR, CONST = range(11)
@@ -80,7 +90,38 @@ def _rounder(mode, seed, M):
     return r32, r32t
 
 
+def corr_and_grad(tokens, consts, X, y, mode: str = "o64", seed: int = 0):
+    """(1 - r^2, dF/dconsts float64[len(consts)]); binary64 throughout for "o64"."""
+    X64 = np.asarray(X, dtype=np.float32).astype(np.float64)
+    y64 = np.asarray(y, dtype=np.float32).astype(np.float64)
+    c64 = np.asarray(consts, dtype=np.float32).astype(np.float64)
+    return fitness_and_grad64(CORR_KIND, tokens, c64, X64, y64, mode, seed)
+
+
+MSE_KIND, CORR_KIND = 0, 1
+
+
+def _corr_seed(y_hat, y64):
+    """(F, dF/dy_hat) of F = 1 - r^2, binary64, with the readings above."""
+    F = ofit.corr_fitness(y_hat, y64)
+    M = y_hat.shape[0]
+    if not math.isfinite(F):
+        return F, np.full(M, math.nan)
+    sxx, syy, sxy = ofit.pearson_sums(y_hat, y64)
+    if sxx == 0.0:
+        return F, np.zeros(M)
+    r = sxy / math.sqrt(sxx * syy)
+    u = y_hat - math.fsum(y_hat.tolist()) / M
+    w = y64 - math.fsum(y64.tolist()) / M
+    return F, -2.0 * r * (w / math.sqrt(sxx * syy) - r * u / sxx)
+
+
 def mse_and_grad64(tokens, c64, X64, y64, mode: str = "o64", seed: int = 0):
+    return fitness_and_grad64(MSE_KIND, tokens, c64, X64, y64, mode, seed)
+
+
+def fitness_and_grad64(kind, tokens, c64, X64, y64, mode: str = "o64", seed: int = 0):
+    """(F, gradient): the fitness kind's seed, then the reverse sweep."""
     M = X64.shape[0]
     L = len(tokens)
     R, RT = _rounder(mode, seed, M)
@@ -89,9 +130,14 @@ def mse_and_grad64(tokens, c64, X64, y64, mode: str = "o64", seed: int = 0):
     else:
         values, children = _tape_rounded(tokens, c64, X64, R, RT)
     y_hat = values[-1]
-    F = _mse64(y_hat, y64)
     adj = [None] * L
-    adj[L - 1] = R(R(y_hat - y64) * R(2.0 / M)) if mode != "o64" else 2.0 * (y_hat - y64) / M
+    if kind == MSE_KIND:
+        F = _mse64(y_hat, y64)
+        adj[L - 1] = R(R(y_hat - y64) * R(2.0 / M)) if mode != "o64" else 2.0 * (y_hat - y64) / M
+    else:
+        with np.errstate(all="ignore"):
+            F, sd = _corr_seed(y_hat, y64)
+        adj[L - 1] = R(sd)
     g = [[] for _ in range(len(c64))]
     with np.errstate(all="ignore"):
         for t in range(L - 1, -1, -1):
@@ -210,8 +256,8 @@ def branch_masks(tokens, c64, X64):
     return masks
 
 
-def central_fd(tokens, consts, X, y, rel_step: float = 1e-5):
-    """Central finite differences of the binary64 MSE, and which slots are admissible.
+def central_fd(tokens, consts, X, y, rel_step: float = 1e-5, kind: int = MSE_KIND):
+    """Central finite differences of the binary64 fitness, and which slots are admissible.
 
     Step h_j = rel_step * max(1, |c_j|).  A slot is inadmissible when the +-h
     perturbation flips any protected-branch decision in any case.
@@ -232,7 +278,8 @@ def central_fd(tokens, consts, X, y, rel_step: float = 1e-5):
             for m0, m1 in zip(base, branch_masks(tokens, cc, X64)):
                 if np.any(m0 != m1):
                     ok[j] = False
-        fp = _mse64(interp.run_tape(tokens, cp, X64)[0][-1], y64)
-        fm = _mse64(interp.run_tape(tokens, cm, X64)[0][-1], y64)
+        fit = _mse64 if kind == MSE_KIND else ofit.corr_fitness
+        fp = fit(interp.run_tape(tokens, cp, X64)[0][-1], y64)
+        fm = fit(interp.run_tape(tokens, cm, X64)[0][-1], y64)
         fd[j] = (fp - fm) / (cp[j] - cm[j])
     return fd, ok

@@ -6,6 +6,7 @@ import pytest
 import torch
 
 from oracle import grad as og
+from oracle import interp
 from paper_2603_12292_amd import workloads as wl
 from progtext import parse
 
@@ -38,8 +39,9 @@ def test_closed_forms():
     assert g[1] == 0.0
 
 
-def _torch_graph(tokens, c, X, y):
-    """The same program built directly as a torch float64 graph (CPU)."""
+def _torch_graph(tokens, c, X, y, corr=False):
+    """The same program built directly as a torch float64 graph (CPU); the
+    MSE, or 1 - r^2 from the centred sums."""
     Xt = torch.tensor(X.astype(np.float64))
     st = []
     for t in tokens:
@@ -76,6 +78,11 @@ def _torch_graph(tokens, c, X, y):
                 st.append(torch.where(z, torch.zeros_like(x), torch.sqrt(torch.abs(torch.where(z, torch.ones_like(x), x)))))
     (yh,) = st
     yt = torch.tensor(y.astype(np.float64))
+    if corr:
+        u = yh - yh.mean()
+        w = yt - yt.mean()
+        r = (u * w).sum() / torch.sqrt((u * u).sum() * (w * w).sum())
+        return 1.0 - r * r
     return torch.mean((yh - yt) ** 2)
 
 
@@ -151,3 +158,94 @@ def test_fp32_modes_are_close_for_benign_programs():
     F, g = og.mse_and_grad([10, 9, 2], [2.0], X, y)
     F32, g32 = og.mse_and_grad([10, 9, 2], [2.0], X, y, "o32e")
     assert F == F32 and g[0] == pytest.approx(g32[0], rel=1e-7)
+
+
+# ---- correlation fitness 1 - r^2
+
+
+def test_corr_affine_invariance():
+    """1 - r^2 does not change under y_hat -> a y_hat + b (a > 0), so the
+    constants of "P c0 * c1 +" have zero gradient; P's own constants do not."""
+    d = _data(M=300)
+    rng = np.random.default_rng(51)
+    n = 0
+    for _ in range(40):
+        toks, _ = wl.random_program(rng, int(rng.integers(3, 16)), 3, allow_const=False)
+        toks, consts = wl.place_constants(rng, toks, 1)
+        t2 = list(toks) + parse("c1 * c2 +")
+        c2 = list(consts) + [np.float32(1.7), np.float32(-0.4)]
+        F, g = og.corr_and_grad(t2, c2, d.X, d.y)
+        F0, g0 = og.corr_and_grad(toks, consts, d.X, d.y)
+        if not (math.isfinite(F) and F < 1.0 and np.all(np.isfinite(g))):
+            continue
+        assert F == pytest.approx(F0, rel=1e-9, abs=1e-12)
+        scale = max(abs(g0[0]), 1e-6)
+        assert abs(g[1]) <= 1e-9 * scale + 1e-13 and abs(g[2]) <= 1e-9 * scale + 1e-13, (toks, g)
+        # the inner constant's gradient scales by 1 (r is unchanged)
+        assert g[0] == pytest.approx(g0[0], rel=1e-6, abs=1e-12)
+        n += 1
+    assert n > 15
+
+
+def test_corr_against_torch_autograd_float64():
+    d = _data(M=300)
+    rng = np.random.default_rng(52)
+    n = 0
+    for _ in range(150):
+        toks, _ = wl.random_program(rng, int(rng.integers(4, 30)), 3, allow_const=False)
+        toks, consts = wl.place_constants(rng, toks, int(rng.integers(1, 5)))
+        F, g = og.corr_and_grad(toks, consts, d.X, d.y)
+        if not math.isfinite(F) or not np.all(np.isfinite(g)) or F >= 1.0 or F <= 0.0:
+            continue
+        # the seeds sum to zero only up to rounding, so a constant term of
+        # huge magnitude (e^(c e^c)) leaves noise of its size in its slots'
+        # (exactly zero) gradients, differently in each summation order:
+        # compared on outputs of moderate magnitude
+        y_hat = interp.run(toks, consts, d.X, "o64")
+        if not np.max(np.abs(y_hat)) < 1e4:
+            continue
+        c = torch.tensor(np.asarray(consts, dtype=np.float32).astype(np.float64), requires_grad=True)
+        Ft = _torch_graph(toks, c, d.X, d.y, corr=True)
+        Ft.backward()
+        gt = c.grad.numpy()
+        assert F == pytest.approx(Ft.item(), rel=1e-9, abs=1e-12)
+        scale = max(1e-300, float(np.max(np.abs(gt))))
+        # absolute floor: constants that only shift or scale the output have
+        # an exactly zero gradient, computed by both sides as rounding noise
+        assert np.all(np.abs(g - gt) <= 1e-7 * scale + 1e-14), (toks, g, gt)
+        n += 1
+    assert n > 50
+
+
+def test_corr_against_central_differences():
+    d = _data(M=300)
+    rng = np.random.default_rng(53)
+    n = 0
+    for _ in range(100):
+        toks, _ = wl.random_program(rng, int(rng.integers(4, 20)), 3, allow_const=False)
+        toks, consts = wl.place_constants(rng, toks, int(rng.integers(1, 4)))
+        F, g = og.corr_and_grad(toks, consts, d.X, d.y)
+        if not math.isfinite(F) or not np.all(np.isfinite(g)):
+            continue
+        fd1, ok1 = og.central_fd(toks, consts, d.X, d.y, rel_step=1e-5, kind=og.CORR_KIND)
+        fd2, ok2 = og.central_fd(toks, consts, d.X, d.y, rel_step=1e-6, kind=og.CORR_KIND)
+        for j in np.nonzero(ok1 & ok2)[0]:
+            if abs(fd1[j] - fd2[j]) > 1e-4 * max(abs(fd2[j]), 1e-12):
+                continue
+            h = 1e-6 * max(1.0, abs(float(consts[j])))
+            tol = 1e-5 * max(abs(g[j]), abs(fd2[j])) + 1e-15 / h + 1e-12
+            assert abs(g[j] - fd2[j]) <= tol, (toks, j, g[j], fd1[j], fd2[j])
+            n += 1
+    assert n > 30
+
+
+def test_corr_degenerate_cases():
+    d = _data(M=200)
+    # constant output: Sxx == 0, F = 1, zero gradient
+    F, g = og.corr_and_grad(parse("c0 sin c1 *"), [np.float32(0.3), np.float32(2.0)], d.X, d.y)
+    assert F == 1.0 and np.all(g == 0.0)
+    # a NaN output in one case: F is NaN and so is every used slot's gradient
+    X = d.X.copy()
+    X[7, 0] = np.float32(np.inf)
+    F, g = og.corr_and_grad(parse("x0 x0 - c0 *"), [np.float32(1.5)], X, d.y)
+    assert math.isnan(F) and math.isnan(g[0])
