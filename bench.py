@@ -74,8 +74,10 @@ def cpu_baseline(w, kind_id, budget_programs: int):
 
 def adjoint_bench(steps: int, warmup: int):
     """fwd+adjoint GPop/s on the differentiation workload (N=4096, 1..8
-    constants, L~U{8..64}, D=5, M=100000), beside the plain MSE evaluation of
-    the same population; GPop/s counts each program node once per case."""
+    constants, L~U{8..64}, D=5, M=100000), beside the plain evaluation of
+    the same population, for the MSE and the correlation fitness (whose
+    adjoint runs the evaluation first for its seeds); GPop/s counts each
+    program node once per case."""
     import torch
     from paper_2603_12292_amd import api
     from paper_2603_12292_amd import workloads as wl
@@ -97,9 +99,12 @@ def adjoint_bench(steps: int, warmup: int):
 
     fwd = rate(lambda: api.evaluate(progs, X, y, "mse"))
     both = rate(lambda: api.evaluate_grad(progs, X, y, "mse"))
-    return {"workload": "adjoint: N=4096, L~U{8..64}, 1..8 constants, D=5, M=100000, MSE",
+    fwd_c = rate(lambda: api.evaluate(progs, X, y, "corr"))
+    both_c = rate(lambda: api.evaluate_grad(progs, X, y, "corr"))
+    return {"workload": "adjoint: N=4096, L~U{8..64}, 1..8 constants, D=5, M=100000, MSE (and 1 - r^2)",
             "fwd_gpops": round(fwd, 2), "fwd_adjoint_gpops": round(both, 2),
-            "adjoint_cost_vs_fwd": round(fwd / both, 3)}
+            "adjoint_cost_vs_fwd": round(fwd / both, 3),
+            "corr_fwd_gpops": round(fwd_c, 2), "corr_fwd_adjoint_gpops": round(both_c, 2)}
 
 
 def ragged_bench(steps: int, warmup: int):

@@ -156,14 +156,21 @@ beagle_status beagle_eval_workspace_size(const beagle_programs* progs, const bea
 beagle_status beagle_predict(beagle_ctx* ctx, const beagle_programs* progs, const beagle_dataset* data,
                              float* yhat, int8_t* status, beagle_stream stream);
 
-/* MSE fitness and its gradient with respect to every program's constants
- * (not in the paper: reverse-mode differentiation over the postfix tape so a
+/* Fitness and its gradient with respect to every program's constants (not
+ * in the paper: reverse-mode differentiation over the postfix tape so a
  * program's ephemeral constants can be tuned by gradient steps).
+ *   kind         BEAGLE_FIT_MSE, or BEAGLE_FIT_CORR: the gradient of
+ *                1 - r^2 (r of Eq. 1), unclamped where the fitness is
+ *                clamped to [0, 1], zero for a constant output (fitness 1),
+ *                NaN for a NaN fitness; the fitness is the one beagle_eval
+ *                gives (same kernels)
+ *   fitness      double[n_programs] out, device
  *   grad_consts  float[n_consts] out, device, same layout as consts; slots
  *                outside every program's range are left untouched
+ *   status       int8[n_programs] out, device, may be NULL
  * Derivatives are taken as 0 where a protected branch replaces the
  * operator by a constant (DIV by 0, EXP outside [-80, 80], LOG of 0, SQRT of
- * 0).  Only BEAGLE_FIT_MSE is supported (BEAGLE_E_UNSUPPORTED otherwise). */
+ * 0).  Programs of more than 256 decoded words get status TOO_LONG. */
 beagle_status beagle_eval_grad(beagle_ctx* ctx, const beagle_programs* progs, const beagle_dataset* data,
                                int kind, double* fitness, float* grad_consts, int8_t* status,
                                beagle_stream stream);

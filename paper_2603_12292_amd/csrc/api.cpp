@@ -115,9 +115,9 @@ using namespace bgl::host;
 // The pieces of workspace one evaluation uses.
 struct EvalLayout {
   size_t code, aux, cval, s_stack, s_start, s_need, meta, class_count, class_list, len_list, work, Xt, yp, stats, part,
-      gpart, total;
-  int64_t Mp, chunk;
-  int32_t n_chunks, slice;
+      gpart, coef, total;
+  int64_t Mp, chunk, gchunk;      // case chunks of the evaluation and of the adjoint
+  int32_t n_chunks, gn_chunks, slice;
 };
 
 EvalLayout eval_layout(const beagle_programs* P, const beagle_dataset* d, int n_sums, int32_t slice,
@@ -144,14 +144,15 @@ EvalLayout eval_layout(const beagle_programs* P, const beagle_dataset* d, int n_
   L.slice = slice;
   // the chunking depends on the whole population only, so that a sliced
   // evaluation sums every program's partials in the same order
+  choose_chunks(d->M, N, &L.chunk, &L.n_chunks, 32768, bgl::CASES_PER_BLOCK_ITER);
   // the adjoint's kernels each walk one list of programs: shorter chunks
   // keep a short list from leaving most of the chip idle
-  if (with_grad)
-    choose_chunks(d->M, N, &L.chunk, &L.n_chunks, bgl::GRAD_CHUNK_CASES, bgl::GRAD_TILE_CASES);
-  else
-    choose_chunks(d->M, N, &L.chunk, &L.n_chunks, 32768, bgl::CASES_PER_BLOCK_ITER);
-  L.part = c.take<double>(size_t(n_sums) * L.n_chunks * slice);
-  L.gpart = with_grad ? c.take<double>(size_t(L.n_chunks) * std::max<int64_t>(P->n_consts, 1)) : 0;
+  L.gchunk = 0;
+  L.gn_chunks = 0;
+  if (with_grad) choose_chunks(d->M, N, &L.gchunk, &L.gn_chunks, bgl::GRAD_CHUNK_CASES, bgl::GRAD_TILE_CASES);
+  L.part = c.take<double>(std::max<size_t>(size_t(n_sums) * L.n_chunks * slice, size_t(L.gn_chunks) * N));
+  L.gpart = with_grad ? c.take<double>(size_t(L.gn_chunks) * std::max<int64_t>(P->n_consts, 1)) : 0;
+  L.coef = with_grad ? c.take<double>(size_t(3) * N) : 0;
   L.total = c.used + 256;
   return L;
 }
@@ -411,6 +412,7 @@ beagle_status beagle_eval(beagle_ctx* ctx, const beagle_programs* progs, const b
     fa.n_chunks = L.n_chunks;
     fa.kind = kind;
     fa.fitness = fitness + p0;
+    fa.coef = nullptr;
     hipLaunchKernelGGL(bgl::k_finalize, dim3((np + 255) / 256), dim3(256), 0, s, fa);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "finalize launch");
@@ -563,11 +565,72 @@ beagle_status beagle_generation(beagle_ctx* ctx, const beagle_programs* parents,
   return BEAGLE_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// The correlation evaluation of the whole population (target statistics,
+// shifts, interpreter, finalize) writing the fitness and the seed
+// coefficients of the correlation adjoint.
+beagle_status corr_pass(beagle_ctx* ctx, const beagle_programs* progs, const beagle_dataset* data,
+                        const EvalLayout& L, double* fitness, hipStream_t s) {
+  char* ws = ctx->ws;
+  hipLaunchKernelGGL(bgl::k_target_stats, dim3(1), dim3(1024), 0, s, data->y, data->M,
+                     reinterpret_cast<double*>(ws + L.stats));
+  beagle_status st = launch_values(ctx, progs, data, L, 1, nullptr, 1, s);
+  if (st != BEAGLE_OK) return st;
+  bgl::EvalArgs ea;
+  ea.code = reinterpret_cast<const uint32_t*>(ws + L.code);
+  ea.cval = reinterpret_cast<const float*>(ws + L.cval);
+  ea.tok_offset = progs->tok_offset;
+  ea.meta = reinterpret_cast<const bgl::ProgMeta*>(ws + L.meta);
+  ea.Xt = reinterpret_cast<const float*>(ws + L.Xt);
+  ea.yp = reinterpret_cast<const float*>(ws + L.yp);
+  ea.M = data->M;
+  ea.Mp = L.Mp;
+  ea.D = data->D;
+  ea.n_programs = progs->n_programs;
+  ea.n_chunks = L.n_chunks;
+  ea.chunk = L.chunk;
+  ea.part = reinterpret_cast<double*>(ws + L.part);
+  ea.stats = reinterpret_cast<const double*>(ws + L.stats);
+  ea.class_count = reinterpret_cast<const int32_t*>(ws + L.class_count);
+  ea.class_list = reinterpret_cast<const int32_t*>(ws + L.class_list);
+  ea.work = reinterpret_cast<unsigned long long*>(ws + L.work);
+  ea.n_total = progs->n_programs;
+  ea.prog_begin = 0;
+  int kv = 0;
+  TuneSlice ts{BEAGLE_FIT_CORR, ea};
+  st = tile_variant(ctx, BEAGLE_FIT_CORR, data->D, data->M, double(progs->n_tokens) / progs->n_programs, s,
+                    run_slice, &ts, &kv);
+  if (st != BEAGLE_OK) return st;
+  hipError_t e = bgl::launch_eval(BEAGLE_FIT_CORR, kv, ea, s, nullptr, nullptr);
+  if (e != hipSuccess) return hip_fail(e, "eval launch");
+  bgl::FinalizeArgs fa;
+  fa.meta = ea.meta;
+  fa.part = ea.part;
+  fa.stats = ea.stats;
+  fa.M = data->M;
+  fa.n_programs = progs->n_programs;
+  fa.n_chunks = L.n_chunks;
+  fa.kind = BEAGLE_FIT_CORR;
+  fa.fitness = fitness;
+  fa.coef = reinterpret_cast<double*>(ws + L.coef);
+  hipLaunchKernelGGL(bgl::k_finalize, dim3((progs->n_programs + 255) / 256), dim3(256), 0, s, fa);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "finalize launch");
+  return BEAGLE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 beagle_status beagle_eval_grad(beagle_ctx* ctx, const beagle_programs* progs, const beagle_dataset* data,
                                int kind, double* fitness, float* grad_consts, int8_t* status,
                                beagle_stream stream) {
   if (!ctx) return fail(BEAGLE_E_INVALID_ARG, "ctx is NULL");
-  if (kind != BEAGLE_FIT_MSE) return fail(BEAGLE_E_UNSUPPORTED, "the gradient supports MSE fitness only");
+  if (kind != BEAGLE_FIT_MSE && kind != BEAGLE_FIT_CORR) return fail(BEAGLE_E_INVALID_ARG, "unknown fitness kind");
   beagle_status st = check_programs(progs);
   if (st != BEAGLE_OK) return st;
   st = check_data(data, kind);
@@ -578,12 +641,19 @@ beagle_status beagle_eval_grad(beagle_ctx* ctx, const beagle_programs* progs, co
   DeviceGuard g(ctx->device);
   if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  EvalLayout L = eval_layout(progs, data, 1, progs->n_programs, true);
+  const bool corr = kind == BEAGLE_FIT_CORR;
+  EvalLayout L = eval_layout(progs, data, corr ? 3 : 1, progs->n_programs, true);
   st = reserve(ctx, L.total);
   if (st != BEAGLE_OK) return st;
   st = prepare(ctx, progs, data, L, status, s, bgl::GRAD_LONG_WORDS);
   if (st != BEAGLE_OK) return st;
   char* ws = ctx->ws;
+  if (corr) {
+    // first pass: the correlation fitness and every program's seed
+    // coefficients, by the evaluator (its own chunking)
+    st = corr_pass(ctx, progs, data, L, fitness, s);
+    if (st != BEAGLE_OK) return st;
+  }
   unsigned long long* work = reinterpret_cast<unsigned long long*>(ws + L.work);
   zero_i32(reinterpret_cast<int32_t*>(work), 2 * 8, s);
   bgl::GradArgs ga;
@@ -600,11 +670,14 @@ beagle_status beagle_eval_grad(beagle_ctx* ctx, const beagle_programs* progs, co
   ga.Mp = L.Mp;
   ga.D = data->D;
   ga.n_programs = progs->n_programs;
-  ga.n_chunks = L.n_chunks;
-  ga.chunk = L.chunk;
+  ga.n_chunks = L.gn_chunks;
+  ga.chunk = L.gchunk;
   ga.part = reinterpret_cast<double*>(ws + L.part);
   ga.gpart = reinterpret_cast<double*>(ws + L.gpart);
   ga.n_consts = progs->n_consts;
+  ga.kind = kind;
+  ga.coef = reinterpret_cast<const double*>(ws + L.coef);
+  ga.stats = reinterpret_cast<const double*>(ws + L.stats);
   ga.list_count = reinterpret_cast<const int32_t*>(ws + L.class_count) + 8;
   ga.list = reinterpret_cast<const int32_t*>(ws + L.len_list);
   ga.work = work;
@@ -619,7 +692,8 @@ beagle_status beagle_eval_grad(beagle_ctx* ctx, const beagle_programs* progs, co
   fa.M = data->M;
   fa.n_consts = progs->n_consts;
   fa.n_programs = progs->n_programs;
-  fa.n_chunks = L.n_chunks;
+  fa.n_chunks = L.gn_chunks;
+  fa.kind = kind;
   fa.fitness = fitness;
   fa.grad = grad_consts;
   hipLaunchKernelGGL(bgl::k_grad_finalize, dim3((progs->n_programs + 255) / 256), dim3(256), 0, s, fa);

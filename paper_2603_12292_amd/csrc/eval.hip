@@ -576,6 +576,12 @@ __device__ static void finalize_program(const FinalizeArgs& a, int p) {
       for (int c = 0; c < a.n_chunks; ++c) s[j] += a.part[(int64_t(j) * a.n_chunks + c) * a.n_programs + p];
     const double Md = double(a.M);
     const double syy = a.stats[2], sw = a.stats[1];
+    // gradient seed (1 - r^2 differentiated, unclamped; zero for a constant
+    // output, NaN for a NaN fitness): with u = yhat - shift and w = y - ybar,
+    // Sxx = sum u^2 - (sum u)^2 / M, Sxy = sum u w - sum u sum w / M, so
+    // dSxx/dyhat_i = 2 (yhat_i - mu), dSxy/dyhat_i = w_i - mean w and
+    // dF/dyhat_i = -2 r (dSxy/dyhat_i / sqrt(Sxx Syy) - r (yhat_i - mu) / Sxx)
+    double alpha = nan, beta = nan, mu = nan;
     if (!isfinite(s[0]) || !isfinite(s[1]) || !isfinite(s[2])) {
       F = nan;
     } else if (!(syy > 0.0)) {
@@ -583,13 +589,23 @@ __device__ static void finalize_program(const FinalizeArgs& a, int p) {
     } else {
       const double sxx = s[1] - s[0] * s[0] / Md;
       const double sxy = s[2] - s[0] * sw / Md;
+      mu = double(m.shift) + s[0] / Md;
       if (!(sxx > 0.0)) {
         F = 1.0;
+        alpha = beta = 0.0;
       } else {
-        const double r = sxy / sqrt(sxx * syy);
+        const double q = sqrt(sxx * syy);
+        const double r = sxy / q;
         F = 1.0 - r * r;
         F = F < 0.0 ? 0.0 : (F > 1.0 ? 1.0 : F);
+        alpha = -2.0 * r / q;
+        beta = 2.0 * r * r / sxx;
       }
+    }
+    if (a.coef) {
+      a.coef[3 * int64_t(p)] = alpha;
+      a.coef[3 * int64_t(p) + 1] = beta;
+      a.coef[3 * int64_t(p) + 2] = mu;
     }
   }
   a.fitness[p] = F;
@@ -615,6 +631,7 @@ __global__ void k_finalize_batch(BatchArgs b) {
   a.n_chunks = P.n_chunks;
   a.kind = b.kind;
   a.fitness = P.fitness;
+  a.coef = nullptr;
   finalize_program(a, int(g - P.prog_begin));
 }
 

@@ -84,6 +84,9 @@ struct GradArgs {
   double* part;        // [n_chunks][n_programs] sums of squared errors
   double* gpart;       // [n_chunks][n_consts] gradient partials
   int64_t n_consts;
+  int32_t kind;               // BEAGLE_FIT_MSE or BEAGLE_FIT_CORR
+  const double* coef;         // CORR: per program (alpha, beta, mu) of the seed
+  const double* stats;        // CORR: target statistics (mean, sum of w = y - mean, Syy)
   const int32_t* list_count;  // [GRAD_LISTS] program counts of the adjoint lists
   const int32_t* list;        // [GRAD_LISTS][n_programs]
   unsigned long long* work;   // [GRAD_LISTS] work-item counters, zero at launch
@@ -99,6 +102,7 @@ struct GradFinalizeArgs {
   int64_t n_consts;
   int32_t n_programs;
   int32_t n_chunks;
+  int32_t kind;     // CORR: the fitness comes from the evaluation pass
   double* fitness;
   float* grad;
 };

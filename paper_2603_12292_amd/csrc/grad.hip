@@ -8,7 +8,8 @@
 //           output is stored in a tape (a register array indexed by the
 //           wave-uniform word position for programs of <= 64 decoded words,
 //           a per-wave LDS array for <= 256);
-//  seed     g = dF/dyhat = 2 (yhat - y) / M for the case (0 for padding);
+//  seed     g = dF/dyhat for the case (0 for padding): MSE 2 (yhat - y) / M,
+//           CORR from the program's coefficients (see Seed);
 //  reverse  the words run backwards with an adjoint stack that mirrors the
 //           forward stack (adjoint of stack position j in astk[j], the top
 //           cached in g).  A binary word at forward stack size n reads its
@@ -95,6 +96,37 @@ __device__ __forceinline__ double wave_sum_d(double v) {
   return v;
 }
 
+// dF/dyhat of one case: MSE 2 (yhat - y) / M (the binary64 difference
+// rounded, then scaled); CORR alpha (y - ycen) + beta (yhat - mu) in
+// binary64 with the program's coefficients from the evaluation pass
+// (ycen = mean y + mean of y - mean y).
+struct Seed {
+  bool corr;
+  float inv2m;
+  double alpha, beta, mu, ycen;
+  __device__ __forceinline__ Seed(const GradArgs& a, int p) {
+    corr = a.kind == BEAGLE_FIT_CORR;
+    inv2m = float(2.0 / double(a.M));
+    alpha = beta = mu = ycen = 0.0;
+    if (corr) {
+      alpha = uniform(a.coef[3 * int64_t(p)]);
+      beta = uniform(a.coef[3 * int64_t(p) + 1]);
+      mu = uniform(a.coef[3 * int64_t(p) + 2]);
+      ycen = uniform(a.stats[0] + a.stats[1] / double(a.M));
+    }
+  }
+  // a wave-uniform value held in scalar registers
+  __device__ static __forceinline__ double uniform(double v) {
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+  }
+  __device__ __forceinline__ float operator()(float yhat, float y) const {
+    if (corr) return float(alpha * (double(y) - ycen) + beta * (double(yhat) - mu));
+    return float(double(yhat) - double(y)) * inv2m;
+  }
+};
+
 // Decoded words of one program: broadcast from VGPRs (short) or read with
 // uniform loads (long).
 template <bool LONG>
@@ -161,7 +193,7 @@ __device__ void grad_item(const GradArgs& a, int p, int c, float* lds) {
   for (int j = lane; j < 256; j += 64) wg[j] = 0.0;
   __builtin_amdgcn_wave_barrier();
   double s_mse = 0.0;
-  const float inv2m = float(2.0 / double(a.M));
+  const Seed seed(a, p);
   const int64_t c0 = int64_t(c) * a.chunk;
   const int64_t c1 = c0 + a.chunk < a.M ? c0 + a.chunk : a.M;
   for (int64_t base = c0; base < c1; base += 64) {
@@ -234,7 +266,7 @@ __device__ void grad_item(const GradArgs& a, int p, int c, float* lds) {
     // ---- seed and fitness term
     const double dd = double(top) - double(yk);
     s_mse += valid ? dd * dd : 0.0;
-    float g = valid ? float(dd) * inv2m : 0.0f;
+    float g = valid ? seed(top, yk) : 0.0f;
     // ---- reverse
     float astk[GRAD_S];
 #pragma unroll
@@ -643,7 +675,7 @@ __device__ __forceinline__ void dtape_item(const GradArgs& a, int p, int c, floa
   for (int j = 0; j < LANE_SLOTS; ++j) lg[j * 64] = 0.0;
   __builtin_amdgcn_wave_barrier();
   double s_mse = 0.0;
-  const float inv2m = float(2.0 / double(a.M));
+  const Seed seed(a, p);
   const int64_t c0 = int64_t(c) * a.chunk;
   const int64_t c1 = c0 + a.chunk < a.M ? c0 + a.chunk : a.M;
   for (int64_t base = c0; base < c1; base += G * 64) {
@@ -685,7 +717,7 @@ __device__ __forceinline__ void dtape_item(const GradArgs& a, int p, int c, floa
       const double ek = double(st[k][0]) - double(yv[k]);
       s_mse += valid[k] ? ek * ek : 0.0;
       for (int j = 0; j < 4; ++j) A[k][j] = 0.0f;
-      A[k][0] = valid[k] ? float(ek) * inv2m : 0.0f;
+      A[k][0] = valid[k] ? seed(st[k][0], yv[k]) : 0.0f;
     }
     // ---- reverse: linear updates of the adjoint stack, visiting only the
     // words that are neither constant-free nor NOP (the root always)
@@ -857,13 +889,15 @@ __global__ void k_grad_finalize(GradFinalizeArgs a) {
   const int64_t coff = a.const_offset[p];
   const int cc = a.const_count[p];
   if (m.status != BEAGLE_PROG_OK) {
-    a.fitness[p] = nan;
+    if (a.kind == BEAGLE_FIT_MSE) a.fitness[p] = nan;
     for (int j = 0; j < cc; ++j) a.grad[coff + j] = __int_as_float(0x7FC00000);
     return;
   }
-  double s = 0.0;
-  for (int c = 0; c < a.n_chunks; ++c) s += a.part[int64_t(c) * a.n_programs + p];
-  a.fitness[p] = s / double(a.M);
+  if (a.kind == BEAGLE_FIT_MSE) {
+    double s = 0.0;
+    for (int c = 0; c < a.n_chunks; ++c) s += a.part[int64_t(c) * a.n_programs + p];
+    a.fitness[p] = s / double(a.M);
+  }
   for (int j = 0; j < cc; ++j) {
     double g = 0.0;
     for (int c = 0; c < a.n_chunks; ++c) g += a.gpart[int64_t(c) * a.n_consts + coff + j];

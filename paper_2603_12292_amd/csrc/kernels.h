@@ -77,6 +77,9 @@ struct FinalizeArgs {
   int32_t n_chunks;
   int32_t kind;
   double* fitness;
+  // correlation fitness only, or null: per program (alpha, beta, mu) of the
+  // gradient seed dF/dyhat_i = alpha (w_i - mean w) + beta (yhat_i - mu)
+  double* coef;
 };
 
 struct ValuesArgs {

@@ -18,21 +18,22 @@ GRAD_RTOL = 1e-4
 COND_RTOL = 1e-5
 
 
-def _spread(t, c, data, g64):
+def _spread(t, c, data, g64, kind=ofit.MSE):
     """Largest move of each gradient component under the O32e and two O32p
     gradient modes (what an fp32 adjoint can be expected to reproduce)."""
     spread = np.zeros_like(g64)
+    fn = og.mse_and_grad if kind == ofit.MSE else og.corr_and_grad
     for mode, seed in (("o32e", 0), ("o32p", 1), ("o32p", 2)):
-        _, gm = og.mse_and_grad(t, c, data.X, data.y, mode, seed)
+        _, gm = fn(t, c, data.X, data.y, mode, seed)
         spread = np.maximum(spread, np.where(np.isfinite(gm), np.abs(gm - g64), np.inf))
     return spread
 
 
-def _stable_components(t, c, data, g64):
+def _stable_components(t, c, data, g64, kind=ofit.MSE):
     """Norm-wise stability: components moving by at most COND_RTOL * max|g64|
     (a tenth of the norm-wise gate)."""
     scale = float(np.max(np.abs(g64)))
-    return _spread(t, c, data, g64) <= COND_RTOL * scale, scale
+    return _spread(t, c, data, g64, kind) <= COND_RTOL * scale, scale
 
 
 def _api():
@@ -40,20 +41,20 @@ def _api():
     return api
 
 
-def _grad(ps, data, with_status=False):
+def _grad(ps, data, with_status=False, kind="mse"):
     api = _api()
     P = api.DevicePrograms.from_programset(ps)
     X = torch.from_numpy(data.X).cuda()
     y = torch.from_numpy(data.y).cuda()
-    out = api.evaluate_grad(P, X, y, "mse", with_status=True)
+    out = api.evaluate_grad(P, X, y, kind, with_status=True)
     torch.cuda.synchronize()
     f, g, st = out[0].cpu().numpy(), out[1].cpu().numpy(), out[2].cpu().numpy()
     return f, g, st
 
 
-def _well_conditioned(ps, data, idx):
-    f64, _, f32, pert = gates.references(ps, data.X, data.y, ofit.MSE, subset=idx)
-    at = gates.atol(ofit.MSE, data.y)
+def _well_conditioned(ps, data, idx, kind=ofit.MSE):
+    f64, _, f32, pert = gates.references(ps, data.X, data.y, kind, subset=idx)
+    at = gates.atol(kind, data.y)
     ok = []
     for j in range(len(idx)):
         sp = max([abs(f32[j] - f64[j])] + [abs(p[j] - f64[j]) for p in pert])
@@ -229,6 +230,59 @@ def test_constant_free_subtrees():
         assert np.any(stable), texts[p]
         err = np.abs(g[o:o + cc] - g64)[stable]
         assert np.all(err <= GRAD_RTOL * scale + 1e-7), (texts[p], g[o:o + cc], g64)
+
+
+def test_corr_gradient_matches_oracle():
+    """The adjoint of 1 - r^2 against the oracle on well-conditioned
+    programs and stable components; the fitness is beagle_eval's, bit for
+    bit."""
+    api = _api()
+    w = wl.config_differentiation(N=160, M=3000)
+    ps, data = w.programs, w.data
+    f, g, st = _grad(ps, data, kind="corr")
+    assert np.all(st == 0)
+    P = api.DevicePrograms.from_programset(ps)
+    f_eval = api.evaluate(P, torch.from_numpy(data.X).cuda(), torch.from_numpy(data.y).cuda(), "corr").cpu().numpy()
+    assert np.array_equal(f, f_eval, equal_nan=True)
+    well = _well_conditioned(ps, data, list(range(ps.n)), ofit.CORR)
+    n_cmp = 0
+    bad = []
+    for p in range(ps.n):
+        if not well[p]:
+            continue
+        t, c = ps.program(p)
+        F, g64 = og.corr_and_grad(t, c, data.X, data.y)
+        if not (math.isfinite(F) and np.all(np.isfinite(g64))) or F >= 1.0:
+            continue
+        o, cc = int(ps.const_offset[p]), int(ps.const_count[p])
+        gg = g[o:o + cc].astype(np.float64)
+        stable, scale = _stable_components(t, c, data, g64, ofit.CORR)
+        if not np.any(stable) or scale == 0.0:
+            continue
+        err = float(np.max(np.abs(gg - g64)[stable]))
+        if err > GRAD_RTOL * scale + 1e-7:
+            bad.append((p, err / max(scale, 1e-300), gg, g64))
+        n_cmp += 1
+    assert not bad, bad[:5]
+    print(f"compared correlation gradients of {n_cmp} of {ps.n} programs")
+    assert n_cmp > 0.4 * ps.n
+
+
+def test_corr_gradient_affine_invariance_and_degenerate():
+    """Outer scale and shift constants get a zero gradient (up to rounding);
+    a constant output gets zero; a NaN fitness (an fp32 overflow: e^80 e^80
+    is +Inf, classified NaN as O32e does) NaN gradients."""
+    data = wl.make_dataset(37, 4000, 2, x_range=(1.0, 3.0), target_len=8)
+    texts = [("x0 sin x1 * c0 * c1 +", [1.5, -0.25]),
+             ("c0 sin c1 *", [0.3, 2.0]),
+             ("x0 exp exp exp x1 exp exp exp * c0 *", [1.0])]
+    ps = wl.pack_programs([(progtext.parse(t), c) for t, c in texts])
+    f, g, st = _grad(ps, data, kind="corr")
+    F0, g0 = og.corr_and_grad(progtext.parse("x0 sin x1 *"), [], data.X, data.y)
+    assert abs(f[0] - F0) <= 1e-5 * abs(F0) + 1e-9
+    assert np.all(np.abs(g[0:2]) <= 1e-5), g[0:2]
+    assert f[1] == 1.0 and np.all(g[2:4] == 0.0)
+    assert math.isnan(f[2]) and math.isnan(g[4])
 
 
 def test_autograd_function_and_adam():
