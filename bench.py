@@ -101,10 +101,24 @@ def adjoint_bench(steps: int, warmup: int):
     both = rate(lambda: api.evaluate_grad(progs, X, y, "mse"))
     fwd_c = rate(lambda: api.evaluate(progs, X, y, "corr"))
     both_c = rate(lambda: api.evaluate_grad(progs, X, y, "corr"))
+    # 20 Adam steps on every program's constants, end to end (adjoint,
+    # optimizer update, final evaluation)
+    from paper_2603_12292_amd import autograd as ag
+    ag.tune_constants(progs, X, y, steps=2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = ag.tune_constants(progs, X, y, steps=20, lr=0.05)
+    torch.cuda.synchronize()
+    adam_s = time.perf_counter() - t0
+    ok = torch.isfinite(res.fitness_before) & torch.isfinite(res.fitness_after)
+    improved = float((res.fitness_after[ok] < res.fitness_before[ok]).double().mean().item())
     return {"workload": "adjoint: N=4096, L~U{8..64}, 1..8 constants, D=5, M=100000, MSE (and 1 - r^2)",
             "fwd_gpops": round(fwd, 2), "fwd_adjoint_gpops": round(both, 2),
             "adjoint_cost_vs_fwd": round(fwd / both, 3),
-            "corr_fwd_gpops": round(fwd_c, 2), "corr_fwd_adjoint_gpops": round(both_c, 2)}
+            "corr_fwd_gpops": round(fwd_c, 2), "corr_fwd_adjoint_gpops": round(both_c, 2),
+            "adam_20_steps_ms": round(adam_s * 1e3, 2),
+            "adam_gpops": round(nc * 21 / adam_s / 1e9, 2),
+            "adam_programs_improved": round(improved, 3)}
 
 
 def ragged_bench(steps: int, warmup: int):

@@ -1,7 +1,8 @@
 """Constant tuning by gradient steps on top of the adjoint (beagle_eval_grad).
 
 EvalGrad is a torch.autograd.Function whose input is the flat constant
-tensor of a population and whose output is every program's MSE fitness;
+tensor of a population and whose output is every program's fitness (MSE or
+the correlation fitness 1 - r^2);
 its forward runs the adjoint kernel once and keeps dF_p/dconsts, its backward
 scales that saved gradient by the incoming gradient of the owning program
 (no second kernel launch).  tune_constants runs Adam on the constants with
@@ -34,13 +35,13 @@ def const_owner(progs: api.DevicePrograms) -> torch.Tensor:
 
 
 class EvalGrad(torch.autograd.Function):
-    """fitness[N] = MSE of every program as a function of the flat constants."""
+    """fitness[N] of every program (kind "mse" or "corr") as a function of the flat constants."""
 
     @staticmethod
     def forward(fctx, consts: torch.Tensor, progs: api.DevicePrograms, X: torch.Tensor, y: torch.Tensor,
-                owner: torch.Tensor):
+                owner: torch.Tensor, kind: str = "mse"):
         p = dataclasses.replace(progs, consts=consts.detach().contiguous())
-        fit, grad = api.evaluate_grad(p, X, y, "mse")
+        fit, grad = api.evaluate_grad(p, X, y, kind)
         fctx.save_for_backward(grad, owner)
         return fit
 
@@ -49,7 +50,7 @@ class EvalGrad(torch.autograd.Function):
         grad, owner = fctx.saved_tensors
         scale = torch.where(owner >= 0, grad_out[owner.clamp(min=0)], torch.zeros((), dtype=grad_out.dtype,
                                                                                    device=grad_out.device))
-        return (scale * grad.to(grad_out.dtype)).to(grad.dtype), None, None, None, None
+        return (scale * grad.to(grad_out.dtype)).to(grad.dtype), None, None, None, None, None
 
 
 @dataclasses.dataclass
@@ -62,8 +63,9 @@ class TuneResult:
 
 def tune_constants(progs: api.DevicePrograms, X: torch.Tensor, y: torch.Tensor, steps: int = 20,
                    lr: float = 0.05, betas=(0.9, 0.999), eps: float = 1e-8,
-                   record: bool = False) -> TuneResult:
-    """Adam on the constants of every program; returns the tuned constants."""
+                   record: bool = False, kind: str = "mse") -> TuneResult:
+    """Adam on the constants of every program (fitness kind "mse" or
+    "corr"); returns the tuned constants."""
     owner = const_owner(progs)
     consts = progs.consts.detach().clone().requires_grad_(True)
     opt = torch.optim.Adam([consts], lr=lr, betas=betas, eps=eps)
@@ -71,7 +73,7 @@ def tune_constants(progs: api.DevicePrograms, X: torch.Tensor, y: torch.Tensor, 
     before = None
     for _ in range(steps):
         opt.zero_grad(set_to_none=False)
-        fit = EvalGrad.apply(consts, progs, X, y, owner)
+        fit = EvalGrad.apply(consts, progs, X, y, owner, kind)
         if before is None:
             before = fit.detach().clone()
         ok = torch.isfinite(fit)
@@ -81,5 +83,5 @@ def tune_constants(progs: api.DevicePrograms, X: torch.Tensor, y: torch.Tensor, 
         opt.step()
         if record:
             history.append(float(loss.detach()))
-    final = api.evaluate(dataclasses.replace(progs, consts=consts.detach().contiguous()), X, y, "mse")
+    final = api.evaluate(dataclasses.replace(progs, consts=consts.detach().contiguous()), X, y, kind)
     return TuneResult(consts.detach(), before, final, history)

@@ -309,3 +309,9 @@ def test_autograd_function_and_adam():
     # gradient steps on each program's own constants: most programs improve
     assert np.median(ratio) < 1.0
     assert np.mean(ratio < 1.0) > 0.6
+    # under the correlation fitness 1 - r^2 as well
+    res = ag.tune_constants(P, X, y, steps=20, lr=0.05, kind="corr")
+    before, after = res.fitness_before.cpu().numpy(), res.fitness_after.cpu().numpy()
+    ok = np.isfinite(before) & np.isfinite(after) & (before < 1.0)
+    assert np.mean(after[ok] <= before[ok] + 1e-12) > 0.6
+    assert np.median(after[ok] - before[ok]) <= 0.0
