@@ -121,6 +121,34 @@ def adjoint_bench(steps: int, warmup: int):
             "adam_programs_improved": round(improved, 3)}
 
 
+def scores_bench(steps: int, warmup: int):
+    """The paper's scores (Eq. 3 summed over cases, Eq. 2) on the plain-mid
+    population with targets undefined on a quarter of the domain (same
+    shape: D=5, M=100000); GPop/s as for the main metric."""
+    import torch
+    from paper_2603_12292_amd import api
+    from paper_2603_12292_amd import workloads as wl
+    w = wl.config_mid()
+    data = wl.invalid_target_dataset(2609, 100_000, 5)
+    progs = api.DevicePrograms.from_programset(w.programs, "cuda:0")
+    X = torch.from_numpy(data.X).cuda()
+    y = torch.from_numpy(data.y).cuda()
+    nc = w.programs.node_count() * data.M
+
+    def rate(kind):
+        for _ in range(warmup):
+            api.evaluate_score(progs, X, y, kind, 1000.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            api.evaluate_score(progs, X, y, kind, 1000.0)
+        torch.cuda.synchronize()
+        return nc * steps / (time.perf_counter() - t0) / 1e9
+
+    return {"workload": "scores: plain-mid programs, y = log(x0 - 2)(1 + x1/4) (NaN on x0 < 2), M=100000, S=1000",
+            "point_gpops": round(rate("point"), 2), "r4_gpops": round(rate("r4"), 2)}
+
+
 def ragged_bench(steps: int, warmup: int):
     """The 64-problem ragged workload (1024 programs each, L~U{5..96},
     D~U{1..9}, M=round(10^U(3,6)), MSE): one batched call (a replayed HIP
@@ -216,6 +244,7 @@ def main():
     ap.add_argument("--cpu-programs", type=int, default=4096)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-ragged", action="store_true")
+    ap.add_argument("--no-scores", action="store_true", help="skip the paper's Eq. 2 / Eq. 3 score rates")
     ap.add_argument("--generations", type=int, default=50, help="generation-loop length (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -288,6 +317,8 @@ def main():
     }
     if not args.no_adjoint:
         out["adjoint"] = adjoint_bench(args.steps, args.warmup)
+    if not args.no_scores:
+        out["scores"] = scores_bench(args.steps, args.warmup)
     if not args.no_ragged:
         out["ragged"] = ragged_bench(max(1, args.steps // 4), max(1, args.warmup))
     if args.generations > 0:

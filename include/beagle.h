@@ -69,8 +69,15 @@ typedef enum {
  * 1 - r^2 with r Pearson's correlation (Eq. 1), its sums accumulated in
  * binary64 and clamped to [0, 1].  Classification: MSE is NaN if any yhat is
  * NaN, else +Inf if any yhat is +-Inf; CORR is NaN if any yhat is not
- * finite, 1 if every yhat is equal, NaN if every y is equal. */
-typedef enum { BEAGLE_FIT_MSE = 0, BEAGLE_FIT_CORR = 1 } beagle_fitness_kind;
+ * finite, 1 if every yhat is equal, NaN if every y is equal.
+ * POINT and R4 are the paper's own scores (higher is better; see
+ * beagle_eval_score): POINT the sum over cases of Eq. 3, R4 Eq. 2. */
+typedef enum {
+  BEAGLE_FIT_MSE = 0,
+  BEAGLE_FIT_CORR = 1,
+  BEAGLE_FIT_POINT = 2,
+  BEAGLE_FIT_R4 = 3
+} beagle_fitness_kind;
 
 /* Per-program status codes written to the optional status[] outputs.  A
  * program with a non-zero status gets fitness NaN.  Tokens are checked in
@@ -145,8 +152,28 @@ beagle_status beagle_ctx_kernel_time(beagle_ctx* ctx, double* total_ms, int64_t*
 beagle_status beagle_eval(beagle_ctx* ctx, const beagle_programs* progs, const beagle_dataset* data,
                           int kind, double* fitness, int8_t* status, beagle_stream stream);
 
-/* Workspace bytes beagle_eval needs for this population and dataset in one
- * pass (before any capping); only the sizes in `progs` and `data` are read. */
+/* The paper's scores (section 2.1.5), which pair invalid values (NaN, +Inf,
+ * -Inf) of the output and of the target instead of discarding them; higher
+ * is better.  S = max_score (finite, > 0).
+ *   BEAGLE_FIT_POINT  sum over cases of Eq. 3: both valid: S if both are 0,
+ *                     else round(S min/max - [yhat y < 0] S/11) with
+ *                     min/max of |yhat|, |y| in binary64, S/11 real-valued
+ *                     and round() half to even; both invalid: S; one
+ *                     invalid: -S
+ *   BEAGLE_FIT_R4     Eq. 2: S r^4 (M - c1 - c2) - S (c1 - c2), c1 the cases
+ *                     with exactly one invalid value, c2 those with two, r
+ *                     Pearson's r (Eq. 1) over the cases where both are
+ *                     valid (0 with fewer than two such cases or zero
+ *                     variance), its sums in binary64
+ *   score   double[n_programs] out, device (NaN for an invalid program)
+ *   status  int8[n_programs] out, device, may be NULL
+ * y may hold invalid values.  Needs M >= 1, 1 <= D <= BEAGLE_MAX_D. */
+beagle_status beagle_eval_score(beagle_ctx* ctx, const beagle_programs* progs, const beagle_dataset* data,
+                                int kind, double max_score, double* score, int8_t* status, beagle_stream stream);
+
+/* Workspace bytes beagle_eval (beagle_eval_score for its kinds) needs for
+ * this population and dataset in one pass (before any capping); only the
+ * sizes in `progs` and `data` are read. */
 beagle_status beagle_eval_workspace_size(const beagle_programs* progs, const beagle_dataset* data, int kind,
                                          size_t* bytes);
 

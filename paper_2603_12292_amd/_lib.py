@@ -24,6 +24,8 @@ E_UNSUPPORTED = -4
 
 FIT_MSE = 0
 FIT_CORR = 1
+FIT_POINT = 2
+FIT_R4 = 3
 TUNE_AUTO = 0
 TUNE_WIDE = 1
 TUNE_NARROW = 2
@@ -64,6 +66,8 @@ SIGNATURES = [
     ("beagle_eval_batched", c_int, [c_void_p, POINTER(Programs), POINTER(Dataset), c_int32, c_int,
                                     POINTER(c_void_p), POINTER(c_void_p), c_void_p]),
     ("beagle_eval_workspace_size", c_int, [POINTER(Programs), POINTER(Dataset), c_int, POINTER(c_size_t)]),
+    ("beagle_eval_score", c_int, [c_void_p, POINTER(Programs), POINTER(Dataset), c_int, c_double, c_void_p,
+                                  c_void_p, c_void_p]),
     ("beagle_predict", c_int, [c_void_p, POINTER(Programs), POINTER(Dataset), c_void_p, c_void_p, c_void_p]),
     ("beagle_eval_grad", c_int, [c_void_p, POINTER(Programs), POINTER(Dataset), c_int, c_void_p, c_void_p,
                                  c_void_p, c_void_p]),

@@ -15,7 +15,7 @@ import torch
 
 from . import _lib
 
-_FIT_NAMES = {"mse": _lib.FIT_MSE, "corr": _lib.FIT_CORR}
+_FIT_NAMES = {"mse": _lib.FIT_MSE, "corr": _lib.FIT_CORR, "point": _lib.FIT_POINT, "r4": _lib.FIT_R4}
 
 
 def _kind(kind) -> int:
@@ -334,6 +334,21 @@ def generation(parents: DevicePrograms, fitness: torch.Tensor, params: GenParams
                                    generation_index, problem, out.tokens.data_ptr(), out.len.data_ptr(),
                                    out.consts.data_ptr(), out.const_count.data_ptr(), _stream(dev)))
     return out
+
+
+def evaluate_score(progs: DevicePrograms, X: torch.Tensor, y: torch.Tensor, kind="point", max_score: float = 1000.0,
+                   *, with_status: bool = False, ctx: Optional[Context] = None):
+    """float64 [N] scores (higher is better) -- beagle_eval_score: "point" the
+    sum over cases of the paper's Eq. 3, "r4" its Eq. 2; y may hold NaN/Inf."""
+    dev = progs.device
+    c = _ctx_for(dev, ctx)
+    ps = progs.struct()
+    ds = _dataset(X, y, dev)
+    out = torch.empty(progs.n, dtype=torch.float64, device=dev)
+    st = torch.empty(progs.n, dtype=torch.int8, device=dev) if with_status else None
+    _check(c.lib.beagle_eval_score(c.handle, ctypes.byref(ps), ctypes.byref(ds), _kind(kind), float(max_score),
+                                   out.data_ptr(), st.data_ptr() if st is not None else None, _stream(dev)))
+    return (out, st) if with_status else out
 
 
 def evaluate_grad(progs: DevicePrograms, X: torch.Tensor, y: torch.Tensor, kind="mse", *,

@@ -329,10 +329,14 @@ beagle_status beagle_ctx_set_tuning(beagle_ctx* ctx, int policy) {
   return BEAGLE_OK;
 }
 
-beagle_status beagle_eval(beagle_ctx* ctx, const beagle_programs* progs, const beagle_dataset* data, int kind,
-                          double* fitness, int8_t* status, beagle_stream stream) {
-  if (!ctx) return fail(BEAGLE_E_INVALID_ARG, "ctx is NULL");
-  if (kind != BEAGLE_FIT_MSE && kind != BEAGLE_FIT_CORR) return fail(BEAGLE_E_INVALID_ARG, "unknown fitness kind");
+}  // extern "C"
+
+namespace {
+
+// Whole-population evaluation of any fitness kind (smax: the maximum score of
+// the paper's scores).
+beagle_status evaluate(beagle_ctx* ctx, const beagle_programs* progs, const beagle_dataset* data, int kind,
+                       double smax, double* fitness, int8_t* status, beagle_stream stream) {
   beagle_status st = check_programs(progs);
   if (st != BEAGLE_OK) return st;
   st = check_data(data, kind);
@@ -342,7 +346,7 @@ beagle_status beagle_eval(beagle_ctx* ctx, const beagle_programs* progs, const b
   DeviceGuard g(ctx->device);
   if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const int n_sums = kind == BEAGLE_FIT_MSE ? 1 : 3;
+  const int n_sums = bgl::kind_sums(kind);
   // largest program slice whose partials fit the cap (the whole population
   // when there is no cap)
   int32_t slice = progs->n_programs;
@@ -356,7 +360,7 @@ beagle_status beagle_eval(beagle_ctx* ctx, const beagle_programs* progs, const b
   st = prepare(ctx, progs, data, L, status, s);
   if (st != BEAGLE_OK) return st;
   char* ws = ctx->ws;
-  if (kind == BEAGLE_FIT_CORR) {
+  if (kind == BEAGLE_FIT_CORR || kind == BEAGLE_FIT_R4) {
     hipLaunchKernelGGL(bgl::k_target_stats, dim3(1), dim3(1024), 0, s, data->y, data->M,
                        reinterpret_cast<double*>(ws + L.stats));
     st = launch_values(ctx, progs, data, L, 1, nullptr, 1, s);
@@ -383,6 +387,7 @@ beagle_status beagle_eval(beagle_ctx* ctx, const beagle_programs* progs, const b
     ea.work = reinterpret_cast<unsigned long long*>(ws + L.work);
     ea.n_total = progs->n_programs;
     ea.prog_begin = p0;
+    ea.smax = smax;
     return ea;
   };
   int kv = 0;
@@ -413,6 +418,7 @@ beagle_status beagle_eval(beagle_ctx* ctx, const beagle_programs* progs, const b
     fa.kind = kind;
     fa.fitness = fitness + p0;
     fa.coef = nullptr;
+    fa.smax = smax;
     hipLaunchKernelGGL(bgl::k_finalize, dim3((np + 255) / 256), dim3(256), 0, s, fa);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "finalize launch");
@@ -421,15 +427,37 @@ beagle_status beagle_eval(beagle_ctx* ctx, const beagle_programs* progs, const b
   return BEAGLE_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+beagle_status beagle_eval(beagle_ctx* ctx, const beagle_programs* progs, const beagle_dataset* data, int kind,
+                          double* fitness, int8_t* status, beagle_stream stream) {
+  if (!ctx) return fail(BEAGLE_E_INVALID_ARG, "ctx is NULL");
+  if (kind != BEAGLE_FIT_MSE && kind != BEAGLE_FIT_CORR)
+    return fail(BEAGLE_E_INVALID_ARG, "unknown fitness kind (the paper's scores: beagle_eval_score)");
+  return evaluate(ctx, progs, data, kind, 0.0, fitness, status, stream);
+}
+
+beagle_status beagle_eval_score(beagle_ctx* ctx, const beagle_programs* progs, const beagle_dataset* data, int kind,
+                                double max_score, double* score, int8_t* status, beagle_stream stream) {
+  if (!ctx) return fail(BEAGLE_E_INVALID_ARG, "ctx is NULL");
+  if (kind != BEAGLE_FIT_POINT && kind != BEAGLE_FIT_R4)
+    return fail(BEAGLE_E_INVALID_ARG, "beagle_eval_score takes BEAGLE_FIT_POINT or BEAGLE_FIT_R4");
+  if (!(max_score > 0.0) || !std::isfinite(max_score))
+    return fail(BEAGLE_E_INVALID_ARG, "max_score must be finite and > 0");
+  return evaluate(ctx, progs, data, kind, max_score, score, status, stream);
+}
+
 beagle_status beagle_eval_workspace_size(const beagle_programs* progs, const beagle_dataset* data, int kind,
                                          size_t* bytes) {
   if (!bytes) return fail(BEAGLE_E_INVALID_ARG, "bytes is NULL");
-  if (kind != BEAGLE_FIT_MSE && kind != BEAGLE_FIT_CORR) return fail(BEAGLE_E_INVALID_ARG, "unknown fitness kind");
+  if (kind < BEAGLE_FIT_MSE || kind > BEAGLE_FIT_R4) return fail(BEAGLE_E_INVALID_ARG, "unknown fitness kind");
   beagle_status st = check_programs(progs);
   if (st != BEAGLE_OK) return st;
   st = check_data(data, kind);
   if (st != BEAGLE_OK) return st;
-  *bytes = eval_layout(progs, data, kind == BEAGLE_FIT_MSE ? 1 : 3, std::max(progs->n_programs, 1)).total;
+  *bytes = eval_layout(progs, data, bgl::kind_sums(kind), std::max(progs->n_programs, 1)).total;
   return BEAGLE_OK;
 }
 

@@ -300,10 +300,28 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Eq. 3 for one case (the paper's point-to-point score, see beagle.h): the
+// products and differences rounded separately (no contraction), so that the
+// rounding decision is the one a plain binary64 evaluation takes.
+__device__ __forceinline__ double point_case(float yh, float y, double smax, double s11) {
+  const bool vh = isfinite(yh), vy = isfinite(y);
+  if (!(vh && vy)) return vh == vy ? smax : -smax;
+  const double a = fabs(double(yh)), b = fabs(double(y));
+  const double hi = a > b ? a : b, lo = a > b ? b : a;
+  if (hi == 0.0) return smax;
+  double t = __dmul_rn(smax, lo / hi);
+  if ((yh < 0.0f && y > 0.0f) || (yh > 0.0f && y < 0.0f)) t = __dsub_rn(t, s11);
+  return __builtin_rint(t);
+}
+
 // One workgroup: program p on case chunk c.  Writes the chunk's partial sums
-//   MSE : part[0][c][p] = sum (yhat - y)^2
-//   CORR: part[j][c][p] = sum u, sum u^2, sum u*w   (u = yhat - shift_p,
-//         w = y - ybar), all in binary64.
+//   MSE  : part[0][c][p] = sum (yhat - y)^2
+//   CORR : part[j][c][p] = sum u, sum u^2, sum u*w   (u = yhat - shift_p,
+//          w = y - ybar), all in binary64
+//   POINT: part[0][c][p] = sum of the Eq. 3 case scores (integers, exact)
+//   R4   : part[j][c][p] = c1, c2 (cases with one / two invalid values), and
+//          over the cases where both are valid sum u, sum u^2, sum u*w,
+//          sum w, sum w^2.
 template <int KIND, int K, int S>
 __device__ __forceinline__ void eval_block(const EvalArgs& a, int p, int c, double* red, float* xtile) {
   const ProgMeta m = a.meta[p];
@@ -318,8 +336,10 @@ __device__ __forceinline__ void eval_block(const EvalArgs& a, int p, int c, doub
   const float vv1 = lane + 64 < L ? cval[lane + 64] : 0.0f;
   const double shift = double(m.shift);
   const uint32_t vmask = uint32_t(__builtin_amdgcn_readfirstlane(int(m.vmask)));
-  const double ybar = KIND == BEAGLE_FIT_CORR ? a.stats[0] : 0.0;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  const double ybar = KIND == BEAGLE_FIT_CORR || KIND == BEAGLE_FIT_R4 ? a.stats[0] : 0.0;
+  const double smax = a.smax, s11 = a.smax / 11.0;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
+  uint32_t n1 = 0u, n2 = 0u;
   const int64_t c0 = int64_t(c) * a.chunk;
   const int64_t c1 = c0 + a.chunk < a.M ? c0 + a.chunk : a.M;
   // this wave's input tile (layout: load_row); G * 256 floats per variable
@@ -386,30 +406,64 @@ __device__ __forceinline__ void eval_block(const EvalArgs& a, int p, int c, doub
       if constexpr (KIND == BEAGLE_FIT_MSE) {
         const double d = double(top[k]) - double(yk[k]);
         s0 += valid ? d * d : 0.0;
-      } else {
+      } else if constexpr (KIND == BEAGLE_FIT_CORR) {
         const double u = valid ? double(top[k]) - shift : 0.0;
         const double w = valid ? double(yk[k]) - ybar : 0.0;
         s0 += u;
         s1 += u * u;
         s2 += u * w;
+      } else if constexpr (KIND == BEAGLE_FIT_POINT) {
+        s0 += valid ? point_case(top[k], yk[k], smax, s11) : 0.0;
+      } else {
+        const bool vh = isfinite(top[k]), vy = isfinite(yk[k]);
+        const bool both = valid && vh && vy;
+        n1 += valid && vh != vy ? 1u : 0u;
+        n2 += valid && !vh && !vy ? 1u : 0u;
+        const double u = both ? double(top[k]) - shift : 0.0;
+        const double w = both ? double(yk[k]) - ybar : 0.0;
+        s0 += u;
+        s1 += u * u;
+        s2 += u * w;
+        s3 += w;
+        s4 += w * w;
       }
     }
   }
-  constexpr int NS = KIND == BEAGLE_FIT_MSE ? 1 : 3;
-  s0 = wave_sum(s0);
-  if constexpr (NS == 3) {
-    s1 = wave_sum(s1);
+  constexpr int NS = kind_sums(KIND);
+  if constexpr (KIND == BEAGLE_FIT_R4) {
+    // counts first: c1, c2, then the five sums
+    const double c1d = wave_sum(double(n1)), c2d = wave_sum(double(n2));
+    s4 = wave_sum(s4);
+    s3 = wave_sum(s3);
     s2 = wave_sum(s2);
-  }
-  if (lane == 0) {
-    red[wave * 3 + 0] = s0;
-    red[wave * 3 + 1] = s1;
-    red[wave * 3 + 2] = s2;
+    s1 = wave_sum(s1);
+    s0 = wave_sum(s0);
+    if (lane == 0) {
+      double* r = red + wave * MAX_SUMS;
+      r[0] = c1d;
+      r[1] = c2d;
+      r[2] = s0;
+      r[3] = s1;
+      r[4] = s2;
+      r[5] = s3;
+      r[6] = s4;
+    }
+  } else {
+    s0 = wave_sum(s0);
+    if constexpr (NS == 3) {
+      s1 = wave_sum(s1);
+      s2 = wave_sum(s2);
+    }
+    if (lane == 0) {
+      red[wave * MAX_SUMS + 0] = s0;
+      red[wave * MAX_SUMS + 1] = s1;
+      red[wave * MAX_SUMS + 2] = s2;
+    }
   }
   __syncthreads();
   if (threadIdx.x < NS) {
     const int j = threadIdx.x;
-    const double t = ((red[j] + red[3 + j]) + red[6 + j]) + red[9 + j];
+    const double t = ((red[j] + red[MAX_SUMS + j]) + red[2 * MAX_SUMS + j]) + red[3 * MAX_SUMS + j];
     a.part[(int64_t(j) * a.n_chunks + c) * a.n_programs + p] = t;
   }
   __syncthreads();
@@ -423,7 +477,7 @@ template <int KIND, int CLS, int KV>
 __global__ void __launch_bounds__(256) k_eval_class(EvalArgs a) {
   constexpr int S = class_stack(CLS);
   constexpr int K = class_k(CLS, KV);
-  __shared__ double red[12];
+  __shared__ double red[EVAL_WAVES * MAX_SUMS];
   __shared__ long long s_item;
   extern __shared__ float xtile[];
   const int32_t count = a.class_count[CLS];
@@ -450,7 +504,7 @@ __global__ void __launch_bounds__(256) k_eval_batch(BatchArgs b) {
   constexpr int S = class_stack(CLS);
   constexpr int K = class_k(CLS, KV);
   constexpr int V = CLS == 0 ? KV : CLS + 1;
-  __shared__ double red[12];
+  __shared__ double red[EVAL_WAVES * MAX_SUMS];
   __shared__ long long s_item;
   extern __shared__ float xtile[];
   const int64_t* off = b.item_off + int64_t(V) * (b.n_problems + 1);
@@ -527,7 +581,9 @@ __device__ static void values_program(const ValuesArgs& a, int p, int64_t tile, 
   float top[1];
   interpret<1, MAX_STACK>(vc0, vv0, vc1, vv1, code, cval, L, lane, xl, top);
   if (a.shift_mode) {
-    if (tile == 0 && lane == 0) a.meta[p].shift = top[0];
+    // a finite shift (a non-finite output at case 0 is either the whole
+    // fitness, NaN, or an invalid pair of the paper's scores)
+    if (tile == 0 && lane == 0) a.meta[p].shift = isfinite(top[0]) ? top[0] : 0.0f;
   } else if (i < a.m) {
     a.out[int64_t(p) * a.m + i] = top[0];
   }
@@ -570,6 +626,26 @@ __device__ static void finalize_program(const FinalizeArgs& a, int p) {
     double s = 0.0;
     for (int c = 0; c < a.n_chunks; ++c) s += a.part[int64_t(c) * a.n_programs + p];
     F = s / double(a.M);
+  } else if (a.kind == BEAGLE_FIT_POINT) {
+    double s = 0.0;
+    for (int c = 0; c < a.n_chunks; ++c) s += a.part[int64_t(c) * a.n_programs + p];
+    F = s;
+  } else if (a.kind == BEAGLE_FIT_R4) {
+    double s[7];
+    for (int j = 0; j < 7; ++j) {
+      s[j] = 0.0;
+      for (int c = 0; c < a.n_chunks; ++c) s[j] += a.part[(int64_t(j) * a.n_chunks + c) * a.n_programs + p];
+    }
+    const double c1 = s[0], c2 = s[1], n = double(a.M) - c1 - c2;
+    double r = 0.0;
+    if (n >= 2.0) {
+      const double sxx = s[3] - s[2] * s[2] / n;
+      const double syy = s[6] - s[5] * s[5] / n;
+      const double sxy = s[4] - s[2] * s[5] / n;
+      if (sxx > 0.0 && syy > 0.0) r = sxy / sqrt(sxx * syy);
+    }
+    const double r2 = r * r;
+    F = a.smax * (r2 * r2) * n - a.smax * (c1 - c2);
   } else {
     double s[3] = {0.0, 0.0, 0.0};
     for (int j = 0; j < 3; ++j)
@@ -705,8 +781,16 @@ static hipError_t launch_kind(int kv, const EvalArgs& a, hipStream_t s, hipEvent
 }
 
 hipError_t launch_eval(int kind, int kv, const EvalArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-  return kind == BEAGLE_FIT_MSE ? launch_kind<BEAGLE_FIT_MSE>(kv, a, s, ev0, ev1)
-                                : launch_kind<BEAGLE_FIT_CORR>(kv, a, s, ev0, ev1);
+  switch (kind) {
+    case BEAGLE_FIT_MSE:
+      return launch_kind<BEAGLE_FIT_MSE>(kv, a, s, ev0, ev1);
+    case BEAGLE_FIT_CORR:
+      return launch_kind<BEAGLE_FIT_CORR>(kv, a, s, ev0, ev1);
+    case BEAGLE_FIT_POINT:
+      return launch_kind<BEAGLE_FIT_POINT>(kv, a, s, ev0, ev1);
+    default:
+      return launch_kind<BEAGLE_FIT_R4>(kv, a, s, ev0, ev1);
+  }
 }
 
 // Persistent grid of a work-list kernel: resident workgroups per CU at the

@@ -46,6 +46,13 @@ struct StageArgs {
   float* yp;  // [Mp]
 };
 
+// Partial sums per (chunk, program) of each fitness kind (the evaluator's
+// epilogue: MSE 1, CORR 3, the paper's POINT score 1, its R4 score 7).
+__host__ __device__ constexpr int kind_sums(int kind) {
+  return kind == BEAGLE_FIT_MSE ? 1 : kind == BEAGLE_FIT_CORR ? 3 : kind == BEAGLE_FIT_POINT ? 1 : 7;
+}
+constexpr int MAX_SUMS = 8;
+
 struct EvalArgs {
   const uint32_t* code;
   const float* cval;
@@ -66,6 +73,7 @@ struct EvalArgs {
   unsigned long long* work;         // [N_CLASSES] work-item counters, zero at launch
   int32_t n_total;                  // programs in the whole population
   int32_t prog_begin;               // first program of this launch (slice-local index 0)
+  double smax = 0.0;                // the paper's scores: maximum score S
 };
 
 struct FinalizeArgs {
@@ -79,7 +87,8 @@ struct FinalizeArgs {
   double* fitness;
   // correlation fitness only, or null: per program (alpha, beta, mu) of the
   // gradient seed dF/dyhat_i = alpha (w_i - mean w) + beta (yhat_i - mu)
-  double* coef;
+  double* coef = nullptr;
+  double smax = 0.0;  // the paper's scores: maximum score S
 };
 
 struct ValuesArgs {

@@ -378,26 +378,38 @@ __global__ void k_stage_batch(BatchArgs b) {
   stage_case(a, g - P.case_begin);
 }
 
-// Target statistics for correlation fitness, one workgroup, fixed order:
-//   ybar = y0 + sum(y - y0) / M,  w_i = y_i - ybar (binary64),
-//   stats = {ybar, sum w, sum w^2 - (sum w)^2 / M}.
+// Target statistics for the correlation fitness and the paper's r^4 score,
+// one workgroup, fixed order, over the valid (finite) targets only (every
+// target of a correlation fitness is valid): with n of them,
+//   ybar = y0 + sum(y - y0) / n  (y0 = y[0], or 0 when y[0] is invalid),
+//   w_i = y_i - ybar (binary64), stats = {ybar, sum w, sum w^2 - (sum w)^2 / n}.
 __device__ static void target_stats_block(const float* __restrict__ y, int64_t M, double* __restrict__ stats,
                                           double (&red)[2][1024]) {
   const int t = threadIdx.x;
-  const double y0 = double(y[0]);
-  double s = 0.0;
-  for (int64_t i = t; i < M; i += 1024) s += double(y[i]) - y0;
+  const double y0 = isfinite(y[0]) ? double(y[0]) : 0.0;
+  double s = 0.0, cnt = 0.0;
+  for (int64_t i = t; i < M; i += 1024) {
+    const bool ok = isfinite(y[i]);
+    s += ok ? double(y[i]) - y0 : 0.0;
+    cnt += ok ? 1.0 : 0.0;
+  }
   red[0][t] = s;
+  red[1][t] = cnt;
   __syncthreads();
   for (int w = 512; w > 0; w >>= 1) {
-    if (t < w) red[0][t] += red[0][t + w];
+    if (t < w) {
+      red[0][t] += red[0][t + w];
+      red[1][t] += red[1][t + w];
+    }
     __syncthreads();
   }
-  const double ybar = y0 + red[0][0] / double(M);
+  const double n = red[1][0];
+  const double ybar = n > 0.0 ? y0 + red[0][0] / n : y0;
   __syncthreads();
   double s1 = 0.0, s2 = 0.0;
   for (int64_t i = t; i < M; i += 1024) {
-    const double w = double(y[i]) - ybar;
+    const bool ok = isfinite(y[i]);
+    const double w = ok ? double(y[i]) - ybar : 0.0;
     s1 += w;
     s2 += w * w;
   }
@@ -414,7 +426,7 @@ __device__ static void target_stats_block(const float* __restrict__ y, int64_t M
   if (t == 0) {
     stats[0] = ybar;
     stats[1] = red[0][0];
-    stats[2] = red[1][0] - red[0][0] * red[0][0] / double(M);
+    stats[2] = red[1][0] - red[0][0] * red[0][0] / (n > 0.0 ? n : 1.0);
   }
 }
 

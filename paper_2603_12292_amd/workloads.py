@@ -306,6 +306,19 @@ class Workload:
     data: Dataset
 
 
+def invalid_target_dataset(seed: int, M: int, D: int, *, x_range=(1.0, 5.0)) -> Dataset:
+    """Targets undefined on part of the domain, as the paper's scores are
+    built for: y = log(x0 - 2) * (1 + x1 / 4) evaluated in binary64 without
+    protection (NaN where x0 < 2), rounded to binary32; X ~ U(x_range)."""
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(x_range[0], x_range[1], size=(M, D)).astype(np.float32)
+    X64 = X.astype(np.float64)
+    x1 = X64[:, 1] if D > 1 else X64[:, 0]
+    with np.errstate(invalid="ignore", divide="ignore"):
+        y = (np.log(X64[:, 0] - 2.0) * (1.0 + x1 / 4.0)).astype(np.float32)
+    return Dataset(X, y, [], [])
+
+
 def config_tiny(seed: int = 2604) -> Workload:
     """N=256, L~U{3..32}, D=3, M=1000, X~U(1,5), 10-token target + 1% noise."""
     progs = random_population(seed, 256, 3, 32, 3)
