@@ -73,8 +73,14 @@ __device__ static void dtape_words(const uint32_t* code, uint32_t* aux, int L, S
   }
 }
 
+// The lists a valid program joins: its register-need class and its adjoint
+// list (-1: an invalid program joins none).
+struct ListIds {
+  int cls = -1, lc = -1;
+};
+
 template <class ST, class S, class SO>
-__device__ static void prepare_program(const PrepareArgs& a, int p, ST tok, S stack, S start, S need, SO ord) {
+__device__ static ListIds prepare_program(const PrepareArgs& a, int p, ST tok, S stack, S start, S need, SO ord) {
   const int64_t off = a.tok_offset[p];
   const int32_t L = a.tok_len[p];
   const int64_t coff = a.const_offset[p];
@@ -268,12 +274,11 @@ __device__ static void prepare_program(const PrepareArgs& a, int p, ST tok, S st
   m.vmask = status == BEAGLE_PROG_OK ? vmask : 0u;
   a.meta[p] = m;
   if (a.status_out) a.status_out[p] = int8_t(status);
+  ListIds ids;
   if (status == BEAGLE_PROG_OK) {
-    // append to the list of its register-need class (list order does not
-    // affect any result: every (program, chunk) partial has its own slot)
-    const int cls = need_class(need_root);
-    const int slot = atomicAdd(a.class_count + cls, 1);
-    a.class_list[int64_t(cls) * a.n_programs + slot] = p;
+    // the list of its register-need class (list order does not affect any
+    // result: every (program, chunk) partial has its own slot)
+    ids.cls = need_class(need_root);
     // and by tape size (the adjoint keeps short tapes in registers)
     // adjoint lists: 0 short value tape, 1 long value tape; register need
     // <= 4 and at most GRAD_LANE_SLOTS constant slots: 2, 3, 4 at most
@@ -285,9 +290,38 @@ __device__ static void prepare_program(const PrepareArgs& a, int p, ST tok, S st
                    : n_ent <= GRAD_DTAPE_LARGE ? 4
                                                : 0;
     if (lc >= 2) dtape_words(a.code + off, a.aux + off, L_dec, need, stack);
-    const int ls = atomicAdd(a.len_count + lc, 1);
-    a.len_list[int64_t(lc) * a.n_programs + ls] = p;
+    ids.lc = lc;
   }
+  return ids;
+}
+
+// Appends every active lane's program p to list `which` (< NL) of
+// count/list (lists `stride` apart), one atomic per list and wave: the lanes
+// of one list take consecutive slots in lane order.  Every lane of the wave
+// calls it.
+template <int NL>
+__device__ static void wave_append(int which, int p, int32_t* count, int32_t* list, int64_t stride) {
+  const int lane = threadIdx.x & 63;
+  for (int l = 0; l < NL; ++l) {
+    const uint64_t m = __ballot(which == l);
+    if (m == 0) continue;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    const int rank = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
+    int base = 0;
+    if (lane == leader) base = atomicAdd(count + l, __popcll(m));
+    base = __shfl(base, leader, 64);
+    if (which == l) list[int64_t(l) * stride + base + rank] = p;
+  }
+}
+
+// One program's list appends with one atomic each (the batched kernel:
+// neighbouring lanes belong to different problems).
+__device__ static void append_one(const PrepareArgs& a, int p, ListIds ids) {
+  if (ids.cls < 0) return;
+  const int slot = atomicAdd(a.class_count + ids.cls, 1);
+  a.class_list[int64_t(ids.cls) * a.n_programs + slot] = p;
+  const int ls = atomicAdd(a.len_count + ids.lc, 1);
+  a.len_list[int64_t(ids.lc) * a.n_programs + ls] = p;
 }
 
 // Programs of at most PREP_SHORT tokens keep their scratch in LDS (16-bit
@@ -304,7 +338,7 @@ struct PrepLds {
   uint16_t ord[PREP_SHORT * PREP_BLOCK];
 };
 
-__device__ static void prepare_one(const PrepareArgs& a, int p, PrepLds& lds) {
+__device__ static ListIds prepare_one(const PrepareArgs& a, int p, PrepLds& lds) {
   const int64_t off = a.tok_offset[p];
   const int32_t L = a.tok_len[p];
   if (L >= 1 && L <= PREP_SHORT && off >= 0 && off + L <= a.n_tokens) {
@@ -322,13 +356,13 @@ __device__ static void prepare_one(const PrepareArgs& a, int p, PrepLds& lds) {
       for (int j = 0; j < 8; ++j) dst[(i + j) * PREP_BLOCK] = v[j];
     }
     for (; i < L; ++i) dst[i * PREP_BLOCK] = src[i];
-    prepare_program(a, p, SL{lds.tok + t}, SL{lds.stack + t}, SL{lds.start + t}, SL{lds.need + t},
-                    SL{lds.ord + t});
+    return prepare_program(a, p, SL{lds.tok + t}, SL{lds.stack + t}, SL{lds.start + t}, SL{lds.need + t},
+                           SL{lds.ord + t});
   } else {
     // (an invalid layout is reported before any scratch access)
     const int64_t o = off >= 0 && off < a.n_tokens ? off : 0;
     using SG = Scratch<int32_t, 1>;
-    prepare_program(a, p, Scratch<const uint16_t, 1>{a.tokens + o}, SG{a.scr_stack + o}, SG{a.scr_start + o},
+    return prepare_program(a, p, Scratch<const uint16_t, 1>{a.tokens + o}, SG{a.scr_stack + o}, SG{a.scr_start + o},
                     SG{a.scr_need + o}, Scratch<uint32_t, 1>{a.code + o});
   }
 }
@@ -336,7 +370,12 @@ __device__ static void prepare_one(const PrepareArgs& a, int p, PrepLds& lds) {
 __global__ void __launch_bounds__(PREP_BLOCK) k_prepare(PrepareArgs a) {
   __shared__ PrepLds lds;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < a.n_programs) prepare_one(a, p, lds);
+  ListIds ids;
+  if (p < a.n_programs) ids = prepare_one(a, p, lds);
+  // list appends aggregated per wave (per-program atomics on a handful of
+  // counters serialise when the population is large)
+  wave_append<N_CLASSES>(ids.cls, p, a.class_count, a.class_list, a.n_programs);
+  wave_append<GRAD_LISTS>(ids.lc, p, a.len_count, a.len_list, a.n_programs);
 }
 
 // One thread per program of every problem of the table.
@@ -345,7 +384,9 @@ __global__ void __launch_bounds__(PREP_BLOCK) k_prepare_batch(BatchArgs b) {
   const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (g >= b.n_programs) return;
   const int q = batch_find(b, g, [](const BatchProblem& t) { return t.prog_begin; });
-  prepare_one(b.table[q].prep, int(g - b.table[q].prog_begin), lds);
+  const PrepareArgs& a = b.table[q].prep;
+  const int p = int(g - b.table[q].prog_begin);
+  append_one(a, p, prepare_one(a, p, lds));
 }
 
 // X [M x D] row-major -> Xt [D x Mp] (case index fastest), y -> yp [Mp];
