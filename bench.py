@@ -59,7 +59,8 @@ def committed_counters(kernel: str) -> dict:
 def cpu_baseline(w, kind_id, budget_programs: int):
     from oracle import population as opop
     ps = w.programs
-    cores = min(16, len(os.sched_getaffinity(0)))
+    # the pool's processes (one when the GPU runtime already runs: no fork then)
+    cores = 1 if opop._gpu_runtime_started() else min(16, len(os.sched_getaffinity(0)))
     step = max(1, ps.n // budget_programs)
     sub = list(range(0, ps.n, step))[:budget_programs]
     nodes = int(ps.tok_len[sub].astype(np.int64).sum())
@@ -258,6 +259,9 @@ def main():
 
     w = wl.config_mid()
     ps = w.programs
+    # the CPU oracle first: its worker processes are forked before this
+    # process starts the GPU runtime (forking after that is not safe)
+    cpu = cpu_baseline(w, 1, args.cpu_programs) if not args.no_cpu_baseline else None
     dev = torch.device("cuda:0")
     progs = api.DevicePrograms.from_programset(ps, dev)
     X = torch.from_numpy(w.data.X).to(dev)
@@ -323,8 +327,8 @@ def main():
         out["ragged"] = ragged_bench(max(1, args.steps // 4), max(1, args.warmup))
     if args.generations > 0:
         out["generation_loop"] = generation_bench(args.generations)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, 1, args.cpu_programs)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import math
 import os
+import sys
 from typing import Optional
 
 import numpy as np
@@ -44,6 +45,17 @@ def _worker(args):
     return lo, out, sts
 
 
+def _gpu_runtime_started() -> bool:
+    """Whether this process has initialised a GPU runtime (through torch):
+    its threads make fork() unsafe (a forked child can block forever on a
+    lock one of them held), so the pool is not used then."""
+    torch = sys.modules.get("torch")
+    try:
+        return bool(torch is not None and torch.cuda.is_initialized())
+    except Exception:
+        return True
+
+
 def evaluate_population(tokens, tok_offset, tok_len, consts, const_offset, const_count,
                         X, y, kind: int, mode: str = "o64", processes: Optional[int] = None,
                         subset=None, seed: int = 0):
@@ -61,6 +73,8 @@ def evaluate_population(tokens, tok_offset, tok_len, consts, const_offset, const
         const_offset = np.asarray(const_offset)[idx]
         const_count = np.asarray(const_count)[idx]
     N = len(tok_len)
+    if processes and processes > 1 and _gpu_runtime_started():
+        processes = None  # forking is unsafe once the GPU runtime runs threads
     if not processes or processes <= 1 or N < 2:
         _, f, s = _worker((tokens, consts, tok_offset, tok_len, const_offset, const_count,
                            X, y, kind, mode, 0, N, seed))

@@ -314,6 +314,60 @@ __device__ __forceinline__ double point_case(float yh, float y, double smax, dou
   return __builtin_rint(t);
 }
 
+// Per-lane accumulators of one fitness kind over the cases a lane adds, and
+// their wave sums in partial order (see eval_block).
+template <int KIND>
+struct Acc {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
+  uint32_t n1 = 0u, n2 = 0u;
+  __device__ __forceinline__ void add(float yh, float yt, bool valid, double shift, double ybar, double smax,
+                                      double s11) {
+    if constexpr (KIND == BEAGLE_FIT_MSE) {
+      const double d = double(yh) - double(yt);
+      s0 += valid ? d * d : 0.0;
+    } else if constexpr (KIND == BEAGLE_FIT_CORR) {
+      const double u = valid ? double(yh) - shift : 0.0;
+      const double w = valid ? double(yt) - ybar : 0.0;
+      s0 += u;
+      s1 += u * u;
+      s2 += u * w;
+    } else if constexpr (KIND == BEAGLE_FIT_POINT) {
+      s0 += valid ? point_case(yh, yt, smax, s11) : 0.0;
+    } else {
+      const bool vh = isfinite(yh), vy = isfinite(yt);
+      const bool both = valid && vh && vy;
+      n1 += valid && vh != vy ? 1u : 0u;
+      n2 += valid && !vh && !vy ? 1u : 0u;
+      const double u = both ? double(yh) - shift : 0.0;
+      const double w = both ? double(yt) - ybar : 0.0;
+      s0 += u;
+      s1 += u * u;
+      s2 += u * w;
+      s3 += w;
+      s4 += w * w;
+    }
+  }
+  // the wave's sums in partial order: MSE, POINT {s0}; CORR {s0, s1, s2};
+  // R4 {c1, c2, s0, s1, s2, s3, s4}
+  __device__ __forceinline__ void wave_sums(double (&v)[MAX_SUMS]) const {
+    if constexpr (KIND == BEAGLE_FIT_R4) {
+      v[0] = wave_sum(double(n1));
+      v[1] = wave_sum(double(n2));
+      v[2] = wave_sum(s0);
+      v[3] = wave_sum(s1);
+      v[4] = wave_sum(s2);
+      v[5] = wave_sum(s3);
+      v[6] = wave_sum(s4);
+    } else {
+      v[0] = wave_sum(s0);
+      if constexpr (KIND == BEAGLE_FIT_CORR) {
+        v[1] = wave_sum(s1);
+        v[2] = wave_sum(s2);
+      }
+    }
+  }
+};
+
 // One workgroup: program p on case chunk c.  Writes the chunk's partial sums
 //   MSE  : part[0][c][p] = sum (yhat - y)^2
 //   CORR : part[j][c][p] = sum u, sum u^2, sum u*w   (u = yhat - shift_p,
@@ -338,8 +392,7 @@ __device__ __forceinline__ void eval_block(const EvalArgs& a, int p, int c, doub
   const uint32_t vmask = uint32_t(__builtin_amdgcn_readfirstlane(int(m.vmask)));
   const double ybar = KIND == BEAGLE_FIT_CORR || KIND == BEAGLE_FIT_R4 ? a.stats[0] : 0.0;
   const double smax = a.smax, s11 = a.smax / 11.0;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
-  uint32_t n1 = 0u, n2 = 0u;
+  Acc<KIND> acc;
   const int64_t c0 = int64_t(c) * a.chunk;
   const int64_t c1 = c0 + a.chunk < a.M ? c0 + a.chunk : a.M;
   // this wave's input tile (layout: load_row); G * 256 floats per variable
@@ -403,62 +456,15 @@ __device__ __forceinline__ void eval_block(const EvalArgs& a, int p, int c, doub
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const bool valid = base + (k / SUB) * SPAN + (K >= 4 ? 4 * lane + (k % 4) : k * 64 + lane) < a.M;
-      if constexpr (KIND == BEAGLE_FIT_MSE) {
-        const double d = double(top[k]) - double(yk[k]);
-        s0 += valid ? d * d : 0.0;
-      } else if constexpr (KIND == BEAGLE_FIT_CORR) {
-        const double u = valid ? double(top[k]) - shift : 0.0;
-        const double w = valid ? double(yk[k]) - ybar : 0.0;
-        s0 += u;
-        s1 += u * u;
-        s2 += u * w;
-      } else if constexpr (KIND == BEAGLE_FIT_POINT) {
-        s0 += valid ? point_case(top[k], yk[k], smax, s11) : 0.0;
-      } else {
-        const bool vh = isfinite(top[k]), vy = isfinite(yk[k]);
-        const bool both = valid && vh && vy;
-        n1 += valid && vh != vy ? 1u : 0u;
-        n2 += valid && !vh && !vy ? 1u : 0u;
-        const double u = both ? double(top[k]) - shift : 0.0;
-        const double w = both ? double(yk[k]) - ybar : 0.0;
-        s0 += u;
-        s1 += u * u;
-        s2 += u * w;
-        s3 += w;
-        s4 += w * w;
-      }
+      acc.add(top[k], yk[k], valid, shift, ybar, smax, s11);
     }
   }
   constexpr int NS = kind_sums(KIND);
-  if constexpr (KIND == BEAGLE_FIT_R4) {
-    // counts first: c1, c2, then the five sums
-    const double c1d = wave_sum(double(n1)), c2d = wave_sum(double(n2));
-    s4 = wave_sum(s4);
-    s3 = wave_sum(s3);
-    s2 = wave_sum(s2);
-    s1 = wave_sum(s1);
-    s0 = wave_sum(s0);
-    if (lane == 0) {
-      double* r = red + wave * MAX_SUMS;
-      r[0] = c1d;
-      r[1] = c2d;
-      r[2] = s0;
-      r[3] = s1;
-      r[4] = s2;
-      r[5] = s3;
-      r[6] = s4;
-    }
-  } else {
-    s0 = wave_sum(s0);
-    if constexpr (NS == 3) {
-      s1 = wave_sum(s1);
-      s2 = wave_sum(s2);
-    }
-    if (lane == 0) {
-      red[wave * MAX_SUMS + 0] = s0;
-      red[wave * MAX_SUMS + 1] = s1;
-      red[wave * MAX_SUMS + 2] = s2;
-    }
+  double v[MAX_SUMS];
+  acc.wave_sums(v);
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < NS; ++j) red[wave * MAX_SUMS + j] = v[j];
   }
   __syncthreads();
   if (threadIdx.x < NS) {
@@ -493,6 +499,90 @@ __global__ void __launch_bounds__(256) k_eval_class(EvalArgs a) {
     const int p = list[it % count] - a.prog_begin;
     if (p < 0 || p >= a.n_programs) continue;  // a program of another slice
     eval_block<KIND, K, S>(a, p, c, red, xtile);
+  }
+}
+
+// Small case sets (one chunk of at most RESIDENT_MAX_BYTES of inputs): every
+// workgroup copies the whole input set into LDS once, laid out per pass of
+// 64 K cases as the block kernel lays out a tile ([pass][variable][64 K]),
+// and each wave then takes whole programs of register-need class 0 from the
+// list and runs every pass, so that nothing is staged per program, no case
+// is padding beyond the last pass and no workgroup barrier is taken per
+// program.  A lane adds its cases in the order it would with either tile
+// width, so the width changes no result bit here either.
+template <int KIND, int K>
+__device__ __forceinline__ void eval_wave_resident(const EvalArgs& a, int p, const float* xres, int passes) {
+  constexpr int K64 = K * 64;
+  const ProgMeta m = a.meta[p];
+  const int lane = threadIdx.x & 63;
+  const int64_t off = a.tok_offset[p];
+  const uint32_t* code = a.code + off;
+  const float* cval = a.cval + off;
+  const int L = m.len;
+  const uint32_t vc0 = lane < L ? code[lane] : 0u;
+  const float vv0 = lane < L ? cval[lane] : 0.0f;
+  const uint32_t vc1 = lane + 64 < L ? code[lane + 64] : 0u;
+  const float vv1 = lane + 64 < L ? cval[lane + 64] : 0.0f;
+  const double shift = double(m.shift);
+  const double ybar = KIND == BEAGLE_FIT_CORR || KIND == BEAGLE_FIT_R4 ? a.stats[0] : 0.0;
+  const double smax = a.smax, s11 = a.smax / 11.0;
+  Acc<KIND> acc;
+  for (int ps = 0; ps < passes; ++ps) {
+    const int64_t base = int64_t(ps) * K64;
+    float yk[K];
+#pragma unroll
+    for (int g = 0; g < K / 4; ++g) {
+      const float4 q = *reinterpret_cast<const float4*>(a.yp + base + g * 256 + 4 * lane);
+      yk[4 * g + 0] = q.x;
+      yk[4 * g + 1] = q.y;
+      yk[4 * g + 2] = q.z;
+      yk[4 * g + 3] = q.w;
+    }
+    float top[K];
+    interpret_small<K>(vc0, vv0, vc1, vv1, code, cval, L, lane, xres + ps * (a.D * K64) + 4 * lane, top);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const bool valid = base + (k / 4) * 256 + 4 * lane + (k % 4) < a.M;
+      acc.add(top[k], yk[k], valid, shift, ybar, smax, s11);
+    }
+  }
+  double v[MAX_SUMS];
+  acc.wave_sums(v);
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < kind_sums(KIND); ++j) a.part[int64_t(j) * a.n_programs + p] = v[j];
+  }
+}
+
+template <int KIND, int K>
+__global__ void __launch_bounds__(256) k_eval_resident(EvalArgs a) {
+  constexpr int K64 = K * 64;
+  extern __shared__ float xres[];
+  const int passes = int((a.M + K64 - 1) / K64);
+  const int per_pass = a.D * K64;
+  for (int i = threadIdx.x; i < passes * per_pass; i += blockDim.x) {
+    const int ps = i / per_pass, r = i - ps * per_pass, d = r / K64, j = r - d * K64;
+    xres[i] = a.Xt[int64_t(d) * a.Mp + int64_t(ps) * K64 + j];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  // The wave's loop must stay free of divergent branches: a lane-0-only
+  // branch around the atomic lets the compiler restructure the loop so that
+  // after the first program only lane 0 goes back to the atomic while the
+  // other lanes re-run the old item forever.  So every lane takes part in
+  // the atomic (lane 0 adds 1, the others 0: one atomic after the wave
+  // reduction), the item is read from lane 0 explicitly, the count is a
+  // scalar and no early continue splits the body.
+  const int32_t count = __builtin_amdgcn_readfirstlane(a.class_count[0]);
+  const int32_t* list = a.class_list;
+  for (;;) {
+    const unsigned long long it = atomicAdd(a.work, lane == 0 ? 1ull : 0ull);
+    const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(it), 0);
+    const uint32_t hi = __builtin_amdgcn_readlane(uint32_t(it >> 32), 0);
+    const int64_t item = int64_t((uint64_t(hi) << 32) | lo);
+    if (item >= count) break;
+    const int p = __builtin_amdgcn_readfirstlane(list[item] - a.prog_begin);
+    if (p >= 0 && p < a.n_programs) eval_wave_resident<KIND, K>(a, p, xres, passes);  // else another slice's
   }
 }
 
@@ -766,13 +856,42 @@ static hipError_t launch_class(const EvalArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// inputs bytes of the resident kernel (0: not eligible): one chunk, enough
+// programs to give every SIMD several waves, inputs within RESIDENT_MAX_BYTES
+static size_t resident_bytes(const EvalArgs& a, int K) {
+  if (a.n_chunks != 1 || a.n_total < RESIDENT_MIN_PROGRAMS) return 0;
+  const int64_t k64 = 64 * K;
+  const size_t b = size_t((a.M + k64 - 1) / k64) * size_t(a.D) * size_t(k64) * sizeof(float);
+  return b <= RESIDENT_MAX_BYTES ? b : 0;
+}
+
+template <int KIND, int K>
+static hipError_t launch_resident(const EvalArgs& a, size_t lds, hipStream_t s) {
+  static size_t cached_lds = size_t(-1);
+  static int cached = 0;
+  if (lds != cached_lds) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_resident<KIND, K>, 256, lds) != hipSuccess || nb < 1)
+      nb = 1;
+    cached = nb;
+    cached_lds = lds;
+  }
+  hipLaunchKernelGGL((k_eval_resident<KIND, K>), dim3(cached * cu_count()), dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
 template <int KIND>
 static hipError_t launch_kind(int kv, const EvalArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, a.work, N_CLASSES);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (ev0) (void)hipEventRecord(ev0, s);
-  e = kv == 0 && a.D <= WIDE_TILE_MAX_D ? launch_class<KIND, 0, 0>(a, s) : launch_class<KIND, 0, 1>(a, s);
+  const bool wide = kv == 0 && a.D <= WIDE_TILE_MAX_D;
+  const size_t rb = resident_bytes(a, wide ? 8 : 4);
+  if (rb)
+    e = wide ? launch_resident<KIND, 8>(a, rb, s) : launch_resident<KIND, 4>(a, rb, s);
+  else
+    e = wide ? launch_class<KIND, 0, 0>(a, s) : launch_class<KIND, 0, 1>(a, s);
   if (ev1) (void)hipEventRecord(ev1, s);
   if (e != hipSuccess) return e;
   e = launch_class<KIND, 1, 0>(a, s);

@@ -372,10 +372,11 @@ __global__ void __launch_bounds__(64) k_grad(GradArgs a) {
   const int64_t items = int64_t(count) * a.n_chunks;
   const int32_t* list = a.list + (LONG ? int64_t(a.n_programs) : 0);
   for (;;) {
-    unsigned long long it = 0;
-    if (threadIdx.x == 0) it = atomicAdd(a.work + (LONG ? 1 : 0), 1ull);
-    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(it));
-    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(it >> 32));
+    // every lane takes part (lane 0 adds 1): no divergent branch in the
+    // persistent loop, the item read from lane 0 explicitly
+    const unsigned long long it = atomicAdd(a.work + (LONG ? 1 : 0), threadIdx.x == 0 ? 1ull : 0ull);
+    const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(it), 0);
+    const uint32_t hi = __builtin_amdgcn_readlane(uint32_t(it >> 32), 0);
     const int64_t item = int64_t((uint64_t(hi) << 32) | lo);
     if (item >= items) break;
     const int c = int(item / count);
@@ -868,10 +869,11 @@ __global__ void __launch_bounds__(64) k_grad_dtape(GradArgs a) {
   const int64_t items = int64_t(count) * a.n_chunks;
   const int32_t* list = a.list + LIST * int64_t(a.n_programs);
   for (;;) {
-    unsigned long long it = 0;
-    if (threadIdx.x == 0) it = atomicAdd(a.work + LIST, 1ull);
-    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(it));
-    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(it >> 32));
+    // every lane takes part (lane 0 adds 1): no divergent branch in the
+    // persistent loop, the item read from lane 0 explicitly
+    const unsigned long long it = atomicAdd(a.work + LIST, threadIdx.x == 0 ? 1ull : 0ull);
+    const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(it), 0);
+    const uint32_t hi = __builtin_amdgcn_readlane(uint32_t(it >> 32), 0);
     const int64_t item = int64_t((uint64_t(hi) << 32) | lo);
     if (item >= items) break;
     const int c = int(item / count);

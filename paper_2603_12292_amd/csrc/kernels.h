@@ -162,6 +162,10 @@ constexpr int CASES_PER_BLOCK_ITER = CASES_PER_WAVE_ITER * EVAL_WAVES;  // chunk
 // narrower tile of class 0, used when the LDS input tile of the wide one
 // would exceed WIDE_TILE_MAX_D variables).
 constexpr int WIDE_TILE_MAX_D = 8;
+// The resident-inputs evaluator (small case sets): inputs of at most this
+// many bytes per workgroup, populations of at least this many programs.
+constexpr size_t RESIDENT_MAX_BYTES = 64 * 1024;
+constexpr int32_t RESIDENT_MIN_PROGRAMS = 4096;
 __host__ __device__ constexpr int class_k(int c, int kv) { return c == 0 ? (kv == 0 ? 8 : 4) : (c == 1 ? 4 : 2); }
 
 __global__ void k_prepare(PrepareArgs a);

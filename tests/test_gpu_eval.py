@@ -339,3 +339,60 @@ def test_sin_cos_accuracy():
     # odd and even symmetry, signed zero
     assert np.signbit(out[0][x == 0]).tolist() == np.signbit(x[x == 0]).tolist()
     assert np.all(out[1][x == 0] == 1.0)
+
+
+@pytest.mark.parametrize("M", [512, 1000, 64])
+def test_resident_small_case_sets(M):
+    """Large populations on small case sets (the paper's regime: 512 or 1024
+    cases per generation) take the resident-inputs kernel: oracle gates on a
+    sample for MSE and 1 - r^2, and every program of every kind (with the
+    paper's scores) within rounding of the same programs evaluated as
+    populations below the resident threshold (the block kernel)."""
+    from oracle import scores as sc
+    api = _api()
+    N = 8192
+    ps = wl.random_population(90 + M, N, 3, 48, 5)
+    data = wl.make_dataset(91, M, 5, x_range=(1.0, 10.0), target_len=12)
+    X, y = _xy(data)
+    P = _dev(ps)
+    sub = list(range(0, N, 97))
+    for kind, name in ((ofit.MSE, "mse"), (ofit.CORR, "corr")):
+        print(f"resident M={M} N={N} {name}: GPU evaluation", flush=True)
+        gpu, st = _run(ps, data, kind)
+        assert np.all(st == 0)
+        print(f"resident M={M} {name}: oracle references", flush=True)
+        f64, _, f32, pert = gates.references(ps, data.X, data.y, kind, subset=sub)
+        # programs of up to 48 tokens: about 40 % of them are ill-conditioned
+        # under MSE (exp of large arguments), fewer under 1 - r^2
+        n, _ = gates.check(gpu[sub], f64, f32, kind, data.y, max_ill_frac=0.5 if kind == ofit.MSE else 0.25,
+                           label=f"resident {name} M={M}", perturbed=pert)
+        assert n > 0.4 * len(sub)
+    bad_y = wl.invalid_target_dataset(92, M, 5, x_range=(1.0, 10.0))
+    for name, yy in (("mse", y), ("corr", y), ("point", torch.from_numpy(bad_y.y).cuda()),
+                     ("r4", torch.from_numpy(bad_y.y).cuda())):
+        Xk = X if name in ("mse", "corr") else torch.from_numpy(bad_y.X).cuda()
+        run = (lambda pp: api.evaluate(pp, Xk, yy, name)) if name in ("mse", "corr") else \
+            (lambda pp: api.evaluate_score(pp, Xk, yy, name, 1000.0))
+        print(f"resident M={M} {name}: whole population and slices", flush=True)
+        whole = run(P).cpu().numpy()
+        parts = []
+        for p0 in range(0, N, 2048):
+            sl = ps.subset(list(range(p0, p0 + 2048)))
+            parts.append(run(_dev(sl)).cpu().numpy())
+        part = np.concatenate(parts)
+        assert np.array_equal(np.isnan(whole), np.isnan(part)), name
+        ok = np.isfinite(part)
+        if name == "point":
+            assert np.array_equal(whole[ok], part[ok])
+        else:
+            scale = np.maximum(np.abs(part[ok]), 1.0 if name == "r4" else 1e-300)
+            assert np.all(np.abs(whole[ok] - part[ok]) <= 1e-9 * scale + 1e-12), name
+        # the paper's point score of a sample against the oracle (bit-exact
+        # wherever the oracle's evaluation modes agree on every case)
+        if name == "point":
+            for p in sub[:20]:
+                t, c = ps.program(p)
+                outs = [interp.run(t, c, bad_y.X, m, s) for m, s in (("o64", 0), ("o32e", 0), ("o32p", 1))]
+                scores = {sc.point_score(o, bad_y.y, 1000.0) for o in outs}
+                if len(scores) == 1:
+                    assert whole[p] == scores.pop(), p
