@@ -45,6 +45,26 @@ Constants: a child's constant table is rebuilt in token order (CONST token
 k reads slot k) with the value of the slot it read in its parent; CONST
 tokens beyond max_consts become VAR 0.
 
+Microcosm selection (section 2.1.6 of the paper: a sorted random sample of
+100 individuals stands in for the ranking of the whole population, and its
+percentiles drive one pass of selection that keeps the population at a
+target size).  The paper gives no formulas; reading:
+  * the sample: draw j of the stream with counter (MICRO_INDEX, generation,
+    block, MICRO_TAG | problem) picks individual below(u, N), j = 0 .. s-1
+    (with replacement);
+  * order: lower fitness first, NaN worse than everything; the sample is
+    sorted by (fitness, draw position) and its entry at position
+    k = ceil(keep * s) - 1 (clamped to [0, s - 1]) is the threshold tau;
+  * survivors: every individual whose fitness is not NaN and <= tau (every
+    non-NaN one when tau is NaN), in index order -- one pass; when none
+    survives, every individual does;
+  * children (any number, so that the population can follow a size
+    schedule): child c draws as in the generation step, but parents A and B
+    are survivors[below(u_1, S)] and survivors[below(u_{t+1}, S)] (draws
+    2..t and t+2..2t are not read), S the number of survivors.  With
+    p_crossover = 0 and p_mutation = 1 every child is a point mutant of a
+    survivor: the paper's mutation-only variation.
+
 Ramped half-and-half: individual c gets depth d = dmin + (c mod n) with
 n = dmax - dmin + 1, and uses the full method when (c div n) is even, grow
 otherwise.  Nodes are generated in pre-order: full draws a function
@@ -69,6 +89,8 @@ BINARY = (ADD, SUB, MUL, DIV)
 UNARY = (SIN, COS, EXP, LOG, SQRT)
 FUNCTIONS = BINARY + UNARY
 INIT_TAG = 0x80000000
+MICRO_TAG = 0x40000000
+MICRO_INDEX = 0xFFFFFFFF
 
 
 def arity(op: int) -> int:
@@ -160,15 +182,44 @@ def _with_values(tokens, consts):
     return out
 
 
+def _sort_key(f: float):
+    return (1, 0.0) if math.isnan(f) else (0, f)
+
+
+def microcosm_threshold(fitness, sample: int, keep: float, seed: int, generation: int, problem: int = 0):
+    """tau of the microcosm (NaN when the sample's entry at the keep
+    quantile is NaN)."""
+    fitness = np.asarray(fitness, dtype=np.float64)
+    N = len(fitness)
+    s = Stream(seed, MICRO_INDEX, generation, MICRO_TAG | problem)
+    drawn = [(float(fitness[below(s.draw(j), N)]), j) for j in range(sample)]
+    drawn.sort(key=lambda e: (_sort_key(e[0]), e[1]))
+    k = min(sample - 1, max(0, math.ceil(float(np.float32(keep)) * sample) - 1))
+    return drawn[k][0]
+
+
+def survivors(fitness, tau: float) -> List[int]:
+    """Indices that survive the threshold, in index order (all when none)."""
+    fitness = np.asarray(fitness, dtype=np.float64)
+    out = [i for i, f in enumerate(fitness.tolist())
+           if not math.isnan(f) and (math.isnan(tau) or f <= tau)]
+    return out if out else list(range(len(fitness)))
+
+
 def make_child(c: int, parents_tok, parents_const, fitness: np.ndarray, D: int,
-               params: GenParams, seed: int, generation: int, problem: int = 0):
-    """(tokens, consts) of child c for one generation step."""
+               params: GenParams, seed: int, generation: int, problem: int = 0, surv=None):
+    """(tokens, consts) of child c for one generation step (tournaments, or
+    a uniform draw over `surv` for microcosm selection)."""
     N = len(parents_tok)
     t = params.tournament
     s = Stream(seed, c, generation, problem)
     choice = unit(s.draw(0))
-    ia = tournament(fitness, [below(s.draw(1 + k), N) for k in range(t)])
-    ib = tournament(fitness, [below(s.draw(1 + t + k), N) for k in range(t)])
+    if surv is None:
+        ia = tournament(fitness, [below(s.draw(1 + k), N) for k in range(t)])
+        ib = tournament(fitness, [below(s.draw(1 + t + k), N) for k in range(t)])
+    else:
+        ia = surv[below(s.draw(1), len(surv))]
+        ib = surv[below(s.draw(1 + t), len(surv))]
     A, Ac = parents_tok[ia], parents_const[ia]
     B, Bc = parents_tok[ib], parents_const[ib]
     LA, LB = len(A), len(B)
@@ -220,6 +271,17 @@ def generation(parents_tok, parents_const, fitness, D: int, params: GenParams,
     fitness = np.asarray(fitness, dtype=np.float64)
     return [make_child(c, parents_tok, parents_const, fitness, D, params, seed,
                        generation_index, problem) for c in range(len(parents_tok))]
+
+
+def generation_microcosm(parents_tok, parents_const, fitness, D: int, params: GenParams, seed: int,
+                         generation_index: int, n_children: int, sample: int = 100, keep: float = 0.5,
+                         problem: int = 0):
+    """Children (tokens, consts) of slots 0 .. n_children - 1 under microcosm selection."""
+    fitness = np.asarray(fitness, dtype=np.float64)
+    tau = microcosm_threshold(fitness, sample, keep, seed, generation_index, problem)
+    surv = survivors(fitness, tau)
+    return [make_child(c, parents_tok, parents_const, fitness, D, params, seed, generation_index, problem, surv)
+            for c in range(n_children)]
 
 
 def init_individual(c: int, D: int, params: GenParams, seed: int, problem: int = 0):

@@ -192,3 +192,74 @@ def test_const_value_mapping():
     assert gp.const_value(u, -5.0, 5.0) == 0.0
     v = gp.const_value(0xFFFFFFFF, -5.0, 5.0)
     assert v == float(np.float32(-5.0 + 10.0 * (1 - 2.0 ** -24)))
+
+
+# ---- microcosm selection
+
+
+def test_microcosm_fraction_matches_order_statistics():
+    """tau is the k-th smallest (1-based k = ceil(keep s)) of s uniform draws,
+    so for continuous fitness the surviving fraction F(tau) has expectation
+    k / (s + 1) (the k-th order statistic of s uniforms)."""
+    rng = np.random.default_rng(11)
+    f = rng.normal(size=20000)
+    for keep, s in ((0.5, 100), (0.25, 100), (1.0, 100), (0.5, 20)):
+        k = min(s, max(1, math.ceil(np.float32(keep) * s)))
+        fr = [len(gp.survivors(f, gp.microcosm_threshold(f, s, keep, 1000 + g, g))) / len(f) for g in range(300)]
+        # standard error of the mean of a Beta(k, s - k + 1) variable over 300 draws
+        var = k * (s - k + 1) / ((s + 1) ** 2 * (s + 2))
+        assert abs(np.mean(fr) - k / (s + 1)) < 4 * math.sqrt(var / 300) + 2 / len(f), (keep, s, np.mean(fr))
+
+
+def test_microcosm_degenerate_and_ties():
+    nan = float("nan")
+    f = np.full(50, nan)
+    assert gp.survivors(f, gp.microcosm_threshold(f, 100, 0.5, 1, 1)) == list(range(50))
+    f = np.full(50, 2.5)
+    assert gp.microcosm_threshold(f, 100, 0.5, 1, 1) == 2.5
+    assert gp.survivors(f, 2.5) == list(range(50))
+    # NaN individuals never survive a finite threshold; a NaN threshold
+    # keeps every finite individual
+    f = np.array([1.0, nan, 3.0, 0.5, nan])
+    assert gp.survivors(f, 1.0) == [0, 3]
+    assert gp.survivors(f, nan) == [0, 2, 3]
+    # the threshold is the sample's entry at the keep position: keep = 1
+    # gives the worst drawn individual, a tiny keep the best
+    rng = np.random.default_rng(3)
+    f = rng.normal(size=400)
+    from oracle.philox import Stream, below
+    st = Stream(9, gp.MICRO_INDEX, 4, gp.MICRO_TAG)
+    drawn = [float(f[below(st.draw(j), 400)]) for j in range(100)]
+    assert gp.microcosm_threshold(f, 100, 1.0, 9, 4) == max(drawn)
+    assert gp.microcosm_threshold(f, 100, 0.001, 9, 4) == min(drawn)
+
+
+def test_microcosm_mutation_only_children():
+    """p_crossover = 0, p_mutation = 1: every child is its drawn survivor
+    with at most one token changed (same arity), for any child count."""
+    rng = np.random.default_rng(21)
+    D = 3
+    parents = []
+    for _ in range(64):
+        toks, consts = wl.random_program(rng, int(rng.integers(3, 30)), D)
+        parents.append((toks, consts))
+    fit = rng.normal(size=64)
+    params = gp.GenParams(p_crossover=0.0, p_mutation=1.0)
+    ptok = [p[0] for p in parents]
+    pcst = [p[1] for p in parents]
+    for n_children in (17, 64, 150):
+        kids = gp.generation_microcosm(ptok, pcst, fit, D, params, 5, 3, n_children)
+        assert len(kids) == n_children
+        tau = gp.microcosm_threshold(fit, 100, 0.5, 5, 3)
+        surv = gp.survivors(fit, tau)
+        for c, (kt, _) in enumerate(kids):
+            from oracle.philox import Stream, below
+            s = Stream(5, c, 3, 0)
+            a = surv[below(s.draw(1), len(surv))]
+            pt = ptok[a]
+            assert len(kt) == len(pt)
+            diff = [i for i in range(len(pt)) if (kt[i] & 0xFF) != (pt[i] & 0xFF) or
+                    ((kt[i] & 0xFF) == gp.VAR and kt[i] != pt[i])]
+            assert len(diff) <= 1
+            for i in diff:
+                assert gp.arity(kt[i] & 0xFF) == gp.arity(pt[i] & 0xFF)
