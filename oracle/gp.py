@@ -36,9 +36,14 @@ Subtree crossover: the subtree of postfix token i is the contiguous run
 Child = A[:sA] + B[sB:iB+1] + A[iA+1:]; a child longer than max_len is
 replaced by a copy of A.
 
+Operator sets: op_set 0 uses the nine operators ADD SUB MUL DIV SIN COS EXP
+LOG SQRT; op_set 1 the paper's sixteen (its parameter table, section
+2.1.7): those nine and SQUARE RECIP TAN ASIN ACOS ATAN TANH, in this order.
+
 Point mutation: the token at the drawn position is replaced by a token of the
 same arity, drawn uniformly: binary from (ADD, SUB, MUL, DIV), unary from
-(SIN, COS, EXP, LOG, SQRT), terminal from (x_0 .. x_{D-1}, CONST).  A new
+the set's unary operators in the order above, terminal from (x_0 .. x_{D-1},
+CONST).  A new
 CONST gets the value fp32(lo + (hi - lo) * unit) computed in binary64.
 
 Constants: a child's constant table is rebuilt in token order (CONST token
@@ -68,8 +73,9 @@ target size).  The paper gives no formulas; reading:
 Ramped half-and-half: individual c gets depth d = dmin + (c mod n) with
 n = dmax - dmin + 1, and uses the full method when (c div n) is even, grow
 otherwise.  Nodes are generated in pre-order: full draws a function
-(uniform over the 9 operators) above depth d, grow draws uniformly over the
-9 operators and D+1 terminal symbols, and level d always draws a terminal
+(uniform over the set's F operators, in the order above) above depth d,
+grow draws uniformly over the F operators and D+1 terminal symbols, and
+level d always draws a terminal
 (uniform over D+1 symbols).  A CONST symbol draws its value from the next
 word while fewer than max_consts constants exist, else it becomes VAR 0.  The
 tree is written in postfix, left operand first.
@@ -85,9 +91,19 @@ import numpy as np
 from .philox import Stream, below, unit
 
 ADD, SUB, MUL, DIV, SIN, COS, EXP, LOG, SQRT, VAR, CONST = range(11)
+SQUARE, RECIP, TAN, ASIN, ACOS, ATAN, TANH = range(11, 18)
 BINARY = (ADD, SUB, MUL, DIV)
 UNARY = (SIN, COS, EXP, LOG, SQRT)
+UNARY_EXT = UNARY + (SQUARE, RECIP, TAN, ASIN, ACOS, ATAN, TANH)
 FUNCTIONS = BINARY + UNARY
+
+
+def unary_set(params) -> tuple:
+    return UNARY_EXT if params.op_set == 1 else UNARY
+
+
+def function_set(params) -> tuple:
+    return BINARY + unary_set(params)
 INIT_TAG = 0x80000000
 MICRO_TAG = 0x40000000
 MICRO_INDEX = 0xFFFFFFFF
@@ -96,7 +112,7 @@ MICRO_INDEX = 0xFFFFFFFF
 def arity(op: int) -> int:
     if op in BINARY:
         return 2
-    if op in UNARY:
+    if op in UNARY_EXT:
         return 1
     return 0
 
@@ -112,6 +128,7 @@ class GenParams:
     const_hi: float = 5.0
     init_depth_min: int = 2
     init_depth_max: int = 6
+    op_set: int = 0
 
 
 def const_value(u: int, lo: float, hi: float) -> float:
@@ -248,7 +265,8 @@ def make_child(c: int, parents_tok, parents_const, fitness: np.ndarray, D: int,
         if a == 2:
             pieces[mpos] = (BINARY[below(msym_u, 4)], 0.0)
         elif a == 1:
-            pieces[mpos] = (UNARY[below(msym_u, 5)], 0.0)
+            un = unary_set(params)
+            pieces[mpos] = (un[below(msym_u, len(un))], 0.0)
         else:
             sym = below(msym_u, D + 1)
             if sym < D:
@@ -308,18 +326,20 @@ def init_individual(c: int, D: int, params: GenParams, seed: int, problem: int =
         else:
             toks.append(VAR)
 
+    funcs = function_set(params)
+
     def node(level):
         if level == depth:
             terminal(below(draw(), D + 1))
             return
         if full:
-            op = FUNCTIONS[below(draw(), len(FUNCTIONS))]
+            op = funcs[below(draw(), len(funcs))]
         else:
-            sym = below(draw(), len(FUNCTIONS) + D + 1)
-            if sym >= len(FUNCTIONS):
-                terminal(sym - len(FUNCTIONS))
+            sym = below(draw(), len(funcs) + D + 1)
+            if sym >= len(funcs):
+                terminal(sym - len(funcs))
                 return
-            op = FUNCTIONS[sym]
+            op = funcs[sym]
         for _ in range(arity(op)):
             node(level + 1)
         toks.append(op)

@@ -25,6 +25,10 @@ the operator by a constant):
   EXP exp x inside [-80, 80], else 0
   LOG 1/x if x != 0, else 0
   SQRT sign(x) / (2 sqrt|x|) if x != 0, else 0
+  SQUARE 2x      RECIP -1/x^2      TAN 1 + tan^2 x
+  ASIN 1/sqrt(1 - x^2)   ACOS -1/sqrt(1 - x^2)   (NaN outside [-1, 1])
+  ATAN 1/(1 + x^2)       TANH sech^2 x = 4e / (1 + e)^2, e = exp(-2|x|)
+                         (1 - tanh^2 x cancels where tanh saturates)
 A constant slot's gradient is the sum over cases of the adjoints of every
 CONST token that reads it.
 
@@ -32,9 +36,15 @@ Modes (conditioning only; the reference gradient is "o64"):
   "o32e"  every forward value, every partial derivative and every adjoint
           product rounded to binary32 (the per-case arithmetic of an fp32
           adjoint), sums over cases still exact;
-  "o32p"  as o32e, with sin/cos/exp/log/sqrt results and the derivative
-          values computed from transcendental functions perturbed by a few ulps
-          (seeded), as in oracle.interp.
+  "o32p"  as o32e, with the results of the approximate operators
+          (oracle.interp.APPROXIMATE) and the derivative values computed from
+          transcendental functions perturbed by a few ulps (seeded), as in
+          oracle.interp.
+In the fp32 modes the further operators' derivatives are formed from the
+rounded values the way an fp32 adjoint forms them: SQUARE 2x, RECIP -(y y),
+TAN 1 + y y, ASIN and ACOS +-1/sqrt((1 - x)(1 + x)) (approximate),
+ATAN 1/(1 + x x), TANH 4e / ((1 + e)(1 + e)) with e = exp(max(-2|x|, -80))
+(approximate), with y the operator's value.
 A gradient component is stable under these modes when an fp32 adjoint can
 reproduce it; where per-case contributions cancel it is not.
 """
@@ -48,6 +58,7 @@ from . import fitness as ofit
 from . import interp
 
 ADD, SUB, MUL, DIV, SIN, COS, EXP, LOG, SQRT, VAR, CONST = range(11)
+SQUARE, RECIP, TAN, ASIN, ACOS, ATAN, TANH = range(11, 18)
 
 
 def _fsum(v) -> float:
@@ -188,6 +199,21 @@ def fitness_and_grad64(kind, tokens, c64, X64, y64, mode: str = "o64", seed: int
                     elif op == SQRT:
                         nz = x != 0.0
                         dx = np.where(nz, a_t * np.sign(x) / (2.0 * np.sqrt(np.abs(np.where(nz, x, 1.0)))), 0.0)
+                    elif op == SQUARE:
+                        dx = a_t * (2.0 * x)
+                    elif op == RECIP:
+                        dx = -a_t / (x * x)
+                    elif op == TAN:
+                        t_x = np.tan(x)
+                        dx = a_t * (1.0 + t_x * t_x)
+                    elif op in (ASIN, ACOS):
+                        d = 1.0 / np.sqrt(1.0 - x * x)
+                        dx = a_t * (d if op == ASIN else -d)
+                    elif op == ATAN:
+                        dx = a_t / (1.0 + x * x)
+                    elif op == TANH:
+                        e = np.exp(-2.0 * np.abs(x))
+                        dx = a_t * (4.0 * e / ((1.0 + e) * (1.0 + e)))
                     else:
                         raise ValueError(op)
                 else:
@@ -202,6 +228,21 @@ def fitness_and_grad64(kind, tokens, c64, X64, y64, mode: str = "o64", seed: int
                         d = np.where(x != 0.0, R(1.0 / np.where(x != 0.0, x, 1.0)), 0.0)
                     elif op == SQRT:
                         d = np.where(x != 0.0, R(np.copysign(0.5, x) / np.where(x != 0.0, yv, 1.0)), 0.0)
+                    elif op == SQUARE:
+                        d = R(2.0 * x)
+                    elif op == RECIP:
+                        d = R(-(yv * yv))
+                    elif op == TAN:
+                        d = R(1.0 + R(yv * yv))
+                    elif op in (ASIN, ACOS):
+                        d = RT(1.0 / np.sqrt(R(R(1.0 - x) * R(1.0 + x))))
+                        d = d if op == ASIN else -d
+                    elif op == ATAN:
+                        d = R(1.0 / R(1.0 + R(x * x)))
+                    elif op == TANH:
+                        e = RT(np.exp(np.maximum(R(-2.0 * np.abs(x)), -80.0)))
+                        ep = R(1.0 + e)
+                        d = R(R(4.0 * e) / R(ep * ep))
                     else:
                         raise ValueError(op)
                     dx = R(a_t * d)
@@ -233,7 +274,7 @@ def _tape_rounded(tokens, c64, X64, R, RT):
         else:
             rx = pos_stack.pop()
             v = interp.apply_op(op, None, None, values[rx])
-            values.append(RT(v) if op in (SIN, COS, EXP, LOG, SQRT) else R(v))
+            values.append(RT(v) if op in interp.APPROXIMATE else R(v))
             children.append((rx,))
         pos_stack.append(i)
     return values, children

@@ -8,7 +8,9 @@ element per fitness case.
 
 Token format: uint16 ``opcode | (arg << 8)``.
 Opcodes: 0 ADD 1 SUB 2 MUL 3 DIV 4 SIN 5 COS 6 EXP 7 LOG 8 SQRT
-9 VAR (arg = input variable) 10 CONST (arg = constant slot).
+9 VAR (arg = input variable) 10 CONST (arg = constant slot), and the rest
+of the paper's operator table (its parameter table, section 2.1.7):
+11 SQUARE 12 RECIP 13 TAN 14 ASIN 15 ACOS 16 ATAN 17 TANH (unary).
 For a binary operator the top of the stack is the right operand b and the
 entry below it the left operand a; the result is ``a op b``.
 
@@ -19,6 +21,12 @@ operators; the library fixes these protected forms):
   EXP   exp(min(max(x, -80), 80)) written with comparisons, so NaN -> NaN
   LOG   x == 0 ? 0 : log|x|
   SQRT  sqrt|x|
+The seven further operators keep the paper's unprotected semantics (invalid
+values flow on and are scored as such, section 2.1.5):
+  SQUARE x * x        RECIP 1 / x (+-Inf at +-0)
+  TAN   tan x (+-Inf -> NaN)
+  ASIN, ACOS  NaN outside [-1, 1]
+  ATAN  atan x        TANH tanh x
 
 Modes
   "o64"  every operation in IEEE binary64 on the fp32 inputs widened exactly
@@ -27,8 +35,8 @@ Modes
          fp32 arithmetic exactly (binary64 has more than 2*24+2 bits, so the
          double rounding is innocuous); for sin, cos, exp, log it is the
          binary64 libm value rounded once.
-  "o32p" o32e with the binary64 result of every sin, cos, exp, log and
-         sqrt token first scaled by (1 + e), e uniform in [-2^-22, 2^-22] (a
+  "o32p" o32e with the binary64 result of every sin, cos, exp, log,
+         sqrt, tan, asin, acos, atan and tanh token first scaled by (1 + e), e uniform in [-2^-22, 2^-22] (a
          few binary32 ulps), drawn from a seeded generator: a model of a
          binary32 implementation whose + - * / are correctly rounded and whose
          other operators are accurate to a few ulps.  Used only to
@@ -40,8 +48,13 @@ from __future__ import annotations
 import numpy as np
 
 ADD, SUB, MUL, DIV, SIN, COS, EXP, LOG, SQRT, VAR, CONST = range(11)
-N_OPCODES = 11
+SQUARE, RECIP, TAN, ASIN, ACOS, ATAN, TANH = range(11, 18)
+N_OPCODES = 18
+EXTENDED = (SQUARE, RECIP, TAN, ASIN, ACOS, ATAN, TANH)
 ARITY = {ADD: 2, SUB: 2, MUL: 2, DIV: 2, SIN: 1, COS: 1, EXP: 1, LOG: 1, SQRT: 1, VAR: 0, CONST: 0}
+ARITY.update({op: 1 for op in EXTENDED})
+# results of these operators come from approximate (few-ulp) device functions
+APPROXIMATE = (SIN, COS, EXP, LOG, SQRT, TAN, ASIN, ACOS, ATAN, TANH)
 
 # per-program status codes
 ST_OK = 0
@@ -117,6 +130,20 @@ def apply_op(op: int, a, b, x):
             return np.where(x == 0.0, 0.0, np.log(np.where(x == 0.0, 1.0, np.abs(x))))
         if op == SQRT:
             return np.sqrt(np.abs(x))
+        if op == SQUARE:
+            return x * x
+        if op == RECIP:
+            return 1.0 / x
+        if op == TAN:
+            return np.tan(x)
+        if op == ASIN:
+            return np.arcsin(x)
+        if op == ACOS:
+            return np.arccos(x)
+        if op == ATAN:
+            return np.arctan(x)
+        if op == TANH:
+            return np.tanh(x)
     raise ValueError(f"not an operator: {op}")
 
 
@@ -147,7 +174,7 @@ def run(tokens, consts, X, mode: str = "o64", seed: int = 0) -> np.ndarray:
             v = apply_op(op, a, b, None)
         else:
             v = apply_op(op, None, None, stack.pop())
-        if mode == "o32p" and op in (SIN, COS, EXP, LOG, SQRT):
+        if mode == "o32p" and op in APPROXIMATE:
             with np.errstate(all="ignore"):
                 v = v * (1.0 + rng.uniform(-2.0 ** -22, 2.0 ** -22, size=M))
         if mode != "o64":

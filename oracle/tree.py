@@ -8,7 +8,9 @@ instead of whole vectors), so agreement between the two pins operand order,
 arity handling and the operator conventions.  The elementary functions sin,
 cos, exp and log are taken from numpy (called on one-element arrays, which
 numpy evaluates exactly as it does inside longer arrays) so that the two
-evaluators can be compared bit for bit.
+evaluators can be compared bit for bit; so are tan, asin, acos, atan and
+tanh, with their domain rules (NaN outside [-1, 1] for asin and acos, NaN
+for tan of +-Inf) and 1/x at +-0 (+-Inf) written out here.
 """
 from __future__ import annotations
 
@@ -16,7 +18,9 @@ import math
 
 import numpy as np
 
-_NAMES = {0: "+", 1: "-", 2: "*", 3: "/", 4: "sin", 5: "cos", 6: "exp", 7: "log", 8: "sqrt"}
+_NAMES = {0: "+", 1: "-", 2: "*", 3: "/", 4: "sin", 5: "cos", 6: "exp", 7: "log", 8: "sqrt",
+          11: "sq", 12: "inv", 13: "tan", 14: "asin", 15: "acos", 16: "atan", 17: "tanh"}
+_UNARY = (4, 5, 6, 7, 8, 11, 12, 13, 14, 15, 16, 17)
 
 
 class Node:
@@ -41,7 +45,7 @@ def parse(tokens) -> Node:
             right = st.pop()
             left = st.pop()
             st.append(Node(_NAMES[op], 0, [left, right]))
-        elif op in (4, 5, 6, 7, 8):
+        elif op in _UNARY:
             st.append(Node(_NAMES[op], 0, [st.pop()]))
         else:
             raise ValueError(op)
@@ -114,6 +118,22 @@ def _scalar(kind, vals):
         return _np1(np.log, abs(x))
     if kind == "sqrt":
         return math.sqrt(abs(x))
+    if kind == "sq":
+        return x * x
+    if kind == "inv":
+        if x == 0.0:
+            return math.copysign(math.inf, x)
+        return 1.0 / x
+    if kind == "tan":
+        return math.nan if math.isinf(x) else _np1(np.tan, x)
+    if kind in ("asin", "acos"):
+        if not abs(x) <= 1.0:
+            return math.nan
+        return _np1(np.arcsin if kind == "asin" else np.arccos, x)
+    if kind == "atan":
+        return _np1(np.arctan, x)
+    if kind == "tanh":
+        return _np1(np.tanh, x)
     raise ValueError(kind)
 
 

@@ -1,7 +1,8 @@
 """Readable program notation for tests: 'x0 x1 + c0 *' -> uint16 token list."""
 import numpy as np
 
-_OPS = {"+": 0, "-": 1, "*": 2, "/": 3, "sin": 4, "cos": 5, "exp": 6, "log": 7, "sqrt": 8}
+_OPS = {"+": 0, "-": 1, "*": 2, "/": 3, "sin": 4, "cos": 5, "exp": 6, "log": 7, "sqrt": 8,
+        "sq": 11, "inv": 12, "tan": 13, "asin": 14, "acos": 15, "atan": 16, "tanh": 17}
 _NAMES = {v: k for k, v in _OPS.items()}
 
 

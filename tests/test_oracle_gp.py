@@ -263,3 +263,31 @@ def test_microcosm_mutation_only_children():
             assert len(diff) <= 1
             for i in diff:
                 assert gp.arity(kt[i] & 0xFF) == gp.arity(pt[i] & 0xFF)
+
+
+
+def test_operator_set_one_draws_every_operator():
+    """op_set 1 (the paper's sixteen): initialisation and mutation reach the
+    seven further unary operators, uniformly among the unary ones."""
+    params = gp.GenParams(op_set=1, p_crossover=0.0, p_mutation=1.0)
+    pop = gp.init_population(3000, 2, params, seed=5)
+    seen = {int(t) & 0xFF for toks, _ in pop for t in toks}
+    assert set(range(11, 18)) <= seen and seen <= set(range(18))
+    ptok = [t for t, _ in pop]
+    pcst = [c for _, c in pop]
+    fit = np.zeros(len(pop))
+    kids = gp.generation(ptok, pcst, fit, 2, params, 5, 1)
+    counts = np.zeros(18)
+    for (kt, _), c in zip(kids, range(len(kids))):
+        s = Stream(5, c, 1, 0)
+        t = params.tournament
+        a = gp.tournament(fit, [below(s.draw(1 + k), len(pop)) for k in range(t)])
+        pt = ptok[a]
+        mpos = below(s.draw(2 * params.tournament + 3), len(pt))
+        if gp.arity(int(pt[mpos]) & 0xFF) == 1:
+            counts[int(kt[mpos]) & 0xFF] += 1
+    un = counts[list(gp.UNARY_EXT)]
+    assert un.sum() > 600 and un.min() > 0.5 * un.sum() / 12
+    # op_set 0 never produces them
+    pop0 = gp.init_population(500, 2, gp.GenParams(), seed=5)
+    assert all((int(t) & 0xFF) < 11 for toks, _ in pop0 for t in toks)

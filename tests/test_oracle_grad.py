@@ -73,9 +73,13 @@ def _torch_graph(tokens, c, X, y, corr=False):
             elif op == 7:
                 z = x == 0
                 st.append(torch.where(z, torch.zeros_like(x), torch.log(torch.abs(torch.where(z, torch.ones_like(x), x)))))
-            else:
+            elif op == 8:
                 z = x == 0
                 st.append(torch.where(z, torch.zeros_like(x), torch.sqrt(torch.abs(torch.where(z, torch.ones_like(x), x)))))
+            else:
+                f = {11: torch.square, 12: torch.reciprocal, 13: torch.tan, 14: torch.asin, 15: torch.acos,
+                     16: torch.atan, 17: torch.tanh}[op]
+                st.append(f(x))
     (yh,) = st
     yt = torch.tensor(y.astype(np.float64))
     if corr:
@@ -249,3 +253,78 @@ def test_corr_degenerate_cases():
     X[7, 0] = np.float32(np.inf)
     F, g = og.corr_and_grad(parse("x0 x0 - c0 *"), [np.float32(1.5)], X, d.y)
     assert math.isnan(F) and math.isnan(g[0])
+
+
+_EXT = (4, 5, 6, 7, 8) + tuple(range(11, 18))
+
+
+def test_tanh_derivative_where_tanh_saturates():
+    """d tanh(c) / dc = sech^2 c keeps full relative accuracy at c = 20,
+    where 1 - tanh^2 c has none."""
+    d = _data()
+    y = d.y.astype(np.float64)
+    M = len(y)
+    F, g = og.mse_and_grad(parse("c0 tanh"), [np.float32(20.0)], d.X, d.y)
+    sech2 = 1.0 / math.cosh(20.0) ** 2
+    assert g[0] == pytest.approx(2.0 / M * math.fsum((math.tanh(20.0) - y).tolist()) * sech2, rel=1e-12)
+
+
+def test_extended_closed_forms():
+    """The paper's further operators: dF/dc of f(c x0) against hand-derived
+    derivatives (x0 in [1, 5], c small enough that asin/acos stay defined)."""
+    d = _data()
+    x = d.X[:, 0].astype(np.float64)
+    y = d.y.astype(np.float64)
+    M = len(y)
+    c = np.float32(0.125)
+    cf = float(c)
+    u = cf * x
+    cases = {"sq": (u * u, 2 * u), "inv": (1 / u, -1 / (u * u)), "tan": (np.tan(u), 1 + np.tan(u) ** 2),
+             "asin": (np.arcsin(u), 1 / np.sqrt(1 - u * u)), "acos": (np.arccos(u), -1 / np.sqrt(1 - u * u)),
+             "atan": (np.arctan(u), 1 / (1 + u * u)), "tanh": (np.tanh(u), 1 - np.tanh(u) ** 2)}
+    for name, (val, dval) in cases.items():
+        F, g = og.mse_and_grad(parse(f"c0 x0 * {name}"), [c], d.X, d.y)
+        assert F == pytest.approx(math.fsum(((val - y) ** 2).tolist()) / M, rel=1e-12), name
+        assert g[0] == pytest.approx(2.0 / M * math.fsum(((val - y) * dval * x).tolist()), rel=1e-10), name
+
+
+@pytest.mark.parametrize("kind", [og.MSE_KIND, og.CORR_KIND])
+def test_extended_against_torch_autograd_float64(kind):
+    """Random programs over all twelve unary operators against torch's own
+    derivatives of tan, asin, acos, atan, tanh, square and reciprocal."""
+    d = _data(M=300)
+    rng = np.random.default_rng(47 + kind)
+    n = 0
+    for _ in range(200):
+        toks, _ = wl.random_program(rng, int(rng.integers(4, 24)), 3, allow_const=False, unary=_EXT)
+        if not any((t & 0xFF) >= 11 for t in toks):
+            continue
+        toks, consts = wl.place_constants(rng, toks, int(rng.integers(1, 4)), const_lo=-1.0, const_hi=1.0)
+        if not any((t & 0xFF) == 9 for t in toks):
+            continue  # a constant output: 1 - r^2 is 1 by convention, gradient 0
+        X64 = d.X.astype(np.float64)
+        F, g = og.fitness_and_grad64(kind, toks, np.asarray(consts, dtype=np.float32).astype(np.float64), X64,
+                                     d.y.astype(np.float64))
+        if not math.isfinite(F) or not np.all(np.isfinite(g)):
+            continue
+        # as for the base operators: 1 - r^2 compared on outputs of moderate
+        # magnitude, with an absolute floor for exactly-zero gradients that
+        # both sides compute as rounding noise
+        if kind == og.CORR_KIND and not np.max(np.abs(interp.run(toks, consts, d.X, "o64"))) < 1e4:
+            continue
+        c = torch.tensor(np.asarray(consts, dtype=np.float32).astype(np.float64), requires_grad=True)
+        Ft = _torch_graph(toks, c, d.X, d.y, corr=kind == og.CORR_KIND)
+        if not torch.isfinite(Ft):
+            continue
+        Ft.backward()
+        gt = c.grad.numpy()
+        if not np.all(np.isfinite(gt)):
+            continue
+        assert F == pytest.approx(Ft.item(), rel=1e-9, abs=1e-12)
+        scale = max(1e-300, float(np.max(np.abs(gt))))
+        # torch differentiates tanh as 1 - tanh^2, which keeps only noise of
+        # about 1e-16 where tanh saturates (the oracle uses sech^2): floor
+        floor = 1e-12 * max(1.0, abs(F))
+        assert np.all(np.abs(g - gt) <= 1e-7 * scale + floor), (toks, g, gt)
+        n += 1
+    assert n > 25

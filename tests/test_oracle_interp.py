@@ -172,7 +172,8 @@ def test_validate(prog, cc, D, status):
 
 
 def test_validate_opcode_and_priority():
-    assert interp.validate([11], 0, 1)[0] == interp.ST_BAD_OPCODE
+    assert interp.validate([18], 0, 1)[0] == interp.ST_BAD_OPCODE
+    assert interp.validate([9, 17], 0, 1) == (interp.ST_OK, 1)  # TANH: the last opcode
     assert interp.validate([9, 0xFF], 0, 1)[0] == interp.ST_BAD_OPCODE
     # first faulty token decides: bad var before a later underflow
     assert interp.validate(parse("x5 +"), 0, 2)[0] == interp.ST_BAD_VAR
@@ -194,3 +195,67 @@ def test_o32p_perturbs_only_non_arithmetic_operators():
     assert not same(a, b)
     assert np.all(np.abs(a - b) <= 2 ** -20 * np.abs(b))
     assert same(a, interp.run(toks, [], X, "o32p", seed=4))
+
+
+
+# ---- the paper's further operators (SQUARE RECIP TAN ASIN ACOS ATAN TANH)
+
+def test_extended_special_values():
+    X = np.array([[3.0], [0.0], [-0.0], [2.0], [-1.0], [1.0], [np.inf], [np.nan]], dtype=np.float32)
+    r = {name: interp.run(parse(f"x0 {name}"), [], X) for name in ("sq", "inv", "tan", "asin", "acos", "atan", "tanh")}
+    assert r["sq"][0] == 9.0 and r["inv"][0] == 1.0 / 3.0
+    assert r["inv"][1] == math.inf and r["inv"][2] == -math.inf          # 1/x at +-0
+    assert math.isnan(r["asin"][3]) and math.isnan(r["acos"][3])         # outside [-1, 1]
+    assert r["acos"][4] == math.pi and r["asin"][5] == math.pi / 2 and r["acos"][5] == 0.0
+    assert math.isnan(r["tan"][6]) and r["atan"][6] == math.pi / 2 and r["tanh"][6] == 1.0
+    assert all(math.isnan(v[7]) for v in r.values())
+    assert r["tanh"][1] == 0.0 and r["atan"][1] == 0.0 and r["tan"][1] == 0.0
+
+
+def test_extended_identities():
+    """Inverse pairs and the defining formulas of the further operators,
+    each written as a program over the base operators where one exists."""
+    rng = np.random.default_rng(7)
+    X = np.stack([rng.uniform(-0.99, 0.99, 500), rng.uniform(-1.5, 1.5, 500)], axis=1).astype(np.float32)
+    x = X[:, 0].astype(np.float64)
+    t = X[:, 1].astype(np.float64)
+    run = lambda prog, c=(): interp.run(parse(prog), list(c), X)
+    assert np.allclose(run("x0 asin sin"), x, rtol=0, atol=1e-15)
+    assert np.allclose(run("x0 acos cos"), x, rtol=0, atol=1e-15)
+    assert np.allclose(run("x0 asin x0 acos +"), np.full(500, math.pi / 2), rtol=0, atol=1e-15)
+    assert np.allclose(run("x1 atan tan"), t, rtol=0, atol=1e-15)
+    # tan = sin / cos, square = x * x exactly, 1 / (1 / x) = x
+    assert np.allclose(run("x1 tan"), run("x1 sin x1 cos /"), rtol=1e-15, atol=0)
+    assert np.array_equal(run("x1 sq"), run("x1 x1 *"))
+    assert np.allclose(run("x1 inv inv"), t, rtol=2e-16, atol=0)
+    # tanh x = (e^2x - 1) / (e^2x + 1)
+    assert np.allclose(run("x1 tanh"), run("x1 x1 + exp c0 - x1 x1 + exp c0 + /", [1.0]), rtol=1e-15, atol=1e-16)
+
+
+def test_extended_against_tree_evaluator():
+    """Random programs over all twelve unary operators, both modes, bit for
+    bit against the tree evaluator (including NaN and Inf outputs)."""
+    from paper_2603_12292_amd.workloads import random_program
+    rng = np.random.default_rng(54321)
+    X = np.concatenate([rng.uniform(-3, 3, size=(14, 3)), [[0.0, -0.0, 1.0], [np.inf, 0.5, -1.0]]]).astype(np.float32)
+    un = (4, 5, 6, 7, 8) + tuple(range(11, 18))
+    n_ext = 0
+    for _ in range(1500):
+        toks, consts = random_program(rng, int(rng.integers(1, 30)), 3, unary=un)
+        n_ext += any((t & 0xFF) >= 11 for t in toks)
+        for mode, r32 in (("o64", False), ("o32e", True)):
+            a = interp.run(toks, consts, X, mode)
+            b = tree.run(toks, consts, X, round32=r32)
+            assert same(a, b), (show(toks), mode)
+    assert n_ext > 800
+
+
+def test_extended_o32e_exact_operators():
+    """SQUARE and RECIP rounded once equal IEEE binary32 x * x and 1 / x."""
+    rng = np.random.default_rng(9)
+    x = np.concatenate([rng.standard_normal(2000) * 10.0 ** rng.integers(-20, 20, 2000),
+                        [0.0, -0.0, 1e-45, 3e38]]).astype(np.float32)
+    X = x[:, None]
+    with np.errstate(all="ignore"):
+        assert same(interp.run(parse("x0 sq"), [], X, "o32e"), (x * x).astype(np.float64))
+        assert same(interp.run(parse("x0 inv"), [], X, "o32e"), (np.float32(1.0) / x).astype(np.float64))
