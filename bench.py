@@ -150,6 +150,114 @@ def scores_bench(steps: int, warmup: int):
             "point_gpops": round(rate("point"), 2), "r4_gpops": round(rate("r4"), 2)}
 
 
+def paper_shape_bench(steps: int, warmup: int):
+    """The paper's regime: 2^20 programs (plain-mid x256, L~U{5..64}) on
+    512 cases, per whole-population evaluation (decode, staging,
+    interpreter, reductions) for the MSE, 1 - r^2 and the paper's two
+    scores; GPop/s as for the main metric."""
+    import torch
+    from paper_2603_12292_amd import api
+    from paper_2603_12292_amd import workloads as wl
+    w = wl.config_paper_shape()
+    progs = api.DevicePrograms.from_programset(w.programs, "cuda:0")
+    X = torch.from_numpy(w.data.X).cuda()
+    y = torch.from_numpy(w.data.y).cuda()
+    nc = w.programs.node_count() * w.data.M
+    out = {"workload": w.name}
+    for kind in ("mse", "corr", "point", "r4"):
+        def call():
+            if kind in ("mse", "corr"):
+                api.evaluate(progs, X, y, kind)
+            else:
+                api.evaluate_score(progs, X, y, kind, 1000.0)
+        for _ in range(max(1, warmup)):
+            call()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n = max(1, steps // 2)
+        for _ in range(n):
+            call()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / n
+        out[f"{kind}_ms"] = round(dt * 1e3, 3)
+        out[f"{kind}_gpops"] = round(nc / dt / 1e9, 2)
+    return out
+
+
+# The paper's population schedule under correlation fitness (its parameter
+# table): 5M individuals before generation 5, 3M before 10, 1M before 15,
+# 500k before 20, 250k from then on.
+PAPER_CORR_SCHEDULE = ((5, 5_000_000), (10, 3_000_000), (15, 1_000_000), (20, 500_000), (None, 250_000))
+
+
+def paper_pop_size(g: int) -> int:
+    for end, n in PAPER_CORR_SCHEDULE:
+        if end is None or g < end:
+            return n
+    raise AssertionError
+
+
+def paper_loop_bench(generations: int):
+    """The paper's evolutionary loop at its own sizes: ramped half-and-half
+    initial population (depths 2..6, max length 64), correlation fitness
+    (1 - r^2) on 512 cases (D = 5), microcosm selection (sample 100, keep
+    0.5) and mutation-only variation, the population following the paper's
+    correlation schedule; everything on the GPU, one stream.  Reports the
+    time per generation (evaluation, selection + variation) at each
+    population size."""
+    import torch
+    from paper_2603_12292_amd import api
+    from paper_2603_12292_amd import workloads as wl
+    data = wl.config_paper_shape().data
+    X = torch.from_numpy(data.X).cuda()
+    y = torch.from_numpy(data.y).cuda()
+    params = api.GenParams(tournament=1, p_crossover=0.0, p_mutation=1.0, max_len=64, max_consts=8,
+                           init_depth_min=2, init_depth_max=5)
+    D, seed = data.D, 2612
+    ctx = api.context(0)
+    pop = api.init_population(paper_pop_size(0), D, params, seed, ctx=ctx)
+    # warm-up: tunes the evaluator buckets and grows the workspace once
+    api.evaluate(pop.programs(), X, y, "corr", ctx=ctx)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(generations)]
+    lens = []
+    t0 = time.perf_counter()
+    for g in range(generations):
+        e0, e1, e2 = ev[g]
+        e0.record()
+        fit = api.evaluate(pop.programs(), X, y, "corr", ctx=ctx)
+        e1.record()
+        lens.append(pop.len.to(torch.int64).sum())
+        pop = api.generation_microcosm(pop.programs(), fit, params, D, seed, g + 1, paper_pop_size(g + 1),
+                                       sample=100, keep=0.5, ctx=ctx)
+        e2.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tokens = [int(t) for t in torch.stack(lens).cpu()]
+    phases = {}
+    for g in range(generations):
+        n = paper_pop_size(g)
+        e0, e1, e2 = ev[g]
+        ph = phases.setdefault(n, {"generations": 0, "eval_ms": 0.0, "select_vary_ms": 0.0, "node_cases": 0})
+        ph["generations"] += 1
+        ph["eval_ms"] += e0.elapsed_time(e1)
+        ph["select_vary_ms"] += e1.elapsed_time(e2)
+        ph["node_cases"] += tokens[g] * data.M
+    rows = []
+    for n, ph in phases.items():
+        k = ph["generations"]
+        rows.append({"population": n, "generations": k, "eval_ms": round(ph["eval_ms"] / k, 3),
+                     "select_vary_ms": round(ph["select_vary_ms"] / k, 3),
+                     "generation_ms": round((ph["eval_ms"] + ph["select_vary_ms"]) / k, 3),
+                     "eval_gpops": round(ph["node_cases"] / (ph["eval_ms"] / 1e3) / 1e9, 2)})
+    return {"workload": f"paper loop: correlation fitness, M={data.M}, D={D}, ramped half-and-half depths 2..5 "
+                        f"(max length 64), microcosm selection (sample 100, keep 0.5), mutation only, population "
+                        f"5M/3M/1M/500k/250k at generations 0/5/10/15/20",
+            "generations": generations, "wall_s": round(wall, 3), "phases": rows,
+            "mean_len_first": round(tokens[0] / paper_pop_size(0), 2),
+            "mean_len_last": round(tokens[-1] / paper_pop_size(generations - 1), 2)}
+
+
 def ragged_bench(steps: int, warmup: int):
     """The 64-problem ragged workload (1024 programs each, L~U{5..96},
     D~U{1..9}, M=round(10^U(3,6)), MSE): one batched call (a replayed HIP
@@ -246,7 +354,10 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-ragged", action="store_true")
     ap.add_argument("--no-scores", action="store_true", help="skip the paper's Eq. 2 / Eq. 3 score rates")
+    ap.add_argument("--no-paper-shape", action="store_true", help="skip the 2^20-program x 512-case rates")
     ap.add_argument("--generations", type=int, default=50, help="generation-loop length (0 = skip)")
+    ap.add_argument("--paper-loop", type=int, default=25,
+                    help="generations of the paper's own loop at its population schedule (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (one process, one device)",
@@ -323,10 +434,14 @@ def main():
         out["adjoint"] = adjoint_bench(args.steps, args.warmup)
     if not args.no_scores:
         out["scores"] = scores_bench(args.steps, args.warmup)
+    if not args.no_paper_shape:
+        out["paper_shape"] = paper_shape_bench(args.steps, args.warmup)
     if not args.no_ragged:
         out["ragged"] = ragged_bench(max(1, args.steps // 4), max(1, args.warmup))
     if args.generations > 0:
         out["generation_loop"] = generation_bench(args.generations)
+    if args.paper_loop > 0:
+        out["paper_loop"] = paper_loop_bench(args.paper_loop)
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

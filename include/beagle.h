@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define BEAGLE_ABI_VERSION 1
+#define BEAGLE_ABI_VERSION 2
 
 typedef struct beagle_ctx beagle_ctx;
 typedef void* beagle_stream; /* hipStream_t */
@@ -126,7 +126,8 @@ typedef struct {
 
 int beagle_abi_version(void);
 
-/* Message describing the last failure on the calling host thread ("" if none). */
+/* Message describing the last failure on the calling host thread; "" if
+ * none, and after a call that launched its work successfully. */
 const char* beagle_last_error(void);
 
 /* Create a context on HIP device `device`.  max_workspace_bytes caps the
@@ -237,7 +238,10 @@ beagle_status beagle_ctx_tile_width(beagle_ctx* ctx, int kind, int32_t D, int64_
  * meets a problem table (every pointer and size above, the tile widths and
  * the workspace) and replays that graph while the table is unchanged; the
  * table itself is copied to the device before every launch.  Results are
- * bit-identical to beagle_eval on each problem alone.  Problems with no
+ * bit-identical to beagle_eval on each problem alone, except on problems
+ * that beagle_eval gives to its resident-inputs kernel (at least 4096
+ * programs on a case set whose inputs fit 64 KB in one chunk): there the
+ * partial sums are added in another order (same accuracy).  Problems with no
  * programs are skipped.  The workspace must hold every problem at once
  * (BEAGLE_E_NOMEM beyond the context cap: no slicing here).  Correlation
  * fitness needs M >= 2 in every problem.  n_problems <= 65535. */
@@ -260,6 +264,13 @@ typedef struct {
   float const_hi;
   int32_t init_depth_min; /* ramped half-and-half depths, 2^(max+1)-1 <= max_len */
   int32_t init_depth_max;
+  int32_t op_set;         /* operators drawn by initialisation and mutation:
+                             0 = + - * / sin cos exp log sqrt;
+                             1 = those and the rest of the paper's table
+                             (parameter table, section 2.1.7): x^2, 1/x, tan,
+                             asin, acos, atan, tanh.  Function draws are
+                             uniform over the set in the order + - * /, then
+                             the unary operators in opcode order            */
 } beagle_gen_params;
 
 /* Ramped half-and-half initial population of n programs over D variables
@@ -288,6 +299,39 @@ beagle_status beagle_generation(beagle_ctx* ctx, const beagle_programs* parents,
                                 const beagle_gen_params* params, int32_t D, uint64_t seed, uint64_t generation,
                                 uint32_t problem, uint16_t* child_tokens, int32_t* child_len,
                                 float* child_consts, int32_t* child_const_count, beagle_stream stream);
+
+/* One generation under microcosm selection (the paper's Monte-Carlo
+ * population control, section 2.1.6): a random sample of `sample`
+ * individuals, sorted by fitness, stands in for the ranking of the whole
+ * population; its entry at position ceil(keep * sample) - 1 (keep in
+ * (0, 1], the product in binary64) is the threshold tau, and one pass over
+ * the population keeps every individual whose fitness is not NaN and
+ * <= tau (every non-NaN one when tau is NaN; every individual when none
+ * survives).  Then n_children child slots (any count, so that the
+ * population can follow a size schedule) are filled as in
+ * beagle_generation, except that parents A and B are survivors drawn
+ * uniformly: survivor[below(draw 1, S)] and survivor[below(draw t+1, S)],
+ * S the survivor count, survivors in index order.  With p_crossover = 0
+ * and p_mutation = 1 every child is a point mutant of a survivor.
+ *   sample      1 .. 1024 individuals, drawn with replacement: draw j of the
+ *               Philox4x32-10 stream with key = seed and counter
+ *               (0xFFFFFFFF, generation, j / 4, 0x40000000 | problem),
+ *               word j % 4, picks individual below(u, n_programs)
+ *   order       lower fitness first, NaN last, ties by draw position
+ *   problem     < 2^30
+ *   threshold   DEVICE double[1] out (tau), or NULL
+ *   n_survivors DEVICE int32[1] out (survivors; 0 means none survived and
+ *               every parent was eligible), or NULL
+ * Children are bit-exact functions of (parents, fitness, params, D, sample,
+ * keep, seed, generation, problem).  The survivor list lives in the context
+ * workspace (4 bytes per parent): calls on one context must be ordered, as
+ * for the evaluations.  n_children may be 0 (selection only). */
+beagle_status beagle_generation_microcosm(beagle_ctx* ctx, const beagle_programs* parents, const double* fitness,
+                                          const beagle_gen_params* params, int32_t D, int32_t sample, float keep,
+                                          uint64_t seed, uint64_t generation, uint32_t problem, int32_t n_children,
+                                          uint16_t* child_tokens, int32_t* child_len, float* child_consts,
+                                          int32_t* child_const_count, double* threshold, int32_t* n_survivors,
+                                          beagle_stream stream);
 
 #ifdef __cplusplus
 }

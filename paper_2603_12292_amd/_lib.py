@@ -48,7 +48,7 @@ class Dataset(ctypes.Structure):
 class GenParams(ctypes.Structure):
     _fields_ = [("tournament", c_int32), ("p_crossover", c_float), ("p_mutation", c_float),
                 ("max_len", c_int32), ("max_consts", c_int32), ("const_lo", c_float), ("const_hi", c_float),
-                ("init_depth_min", c_int32), ("init_depth_max", c_int32)]
+                ("init_depth_min", c_int32), ("init_depth_max", c_int32), ("op_set", c_int32)]
 
 
 # (name, restype, argtypes) of every exported entry point
@@ -75,6 +75,9 @@ SIGNATURES = [
                                        c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     ("beagle_generation", c_int, [c_void_p, POINTER(Programs), c_void_p, POINTER(GenParams), c_int32, c_uint64,
                                   c_uint64, c_uint32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    ("beagle_generation_microcosm", c_int, [c_void_p, POINTER(Programs), c_void_p, POINTER(GenParams), c_int32,
+                                            c_int32, c_float, c_uint64, c_uint64, c_uint32, c_int32, c_void_p,
+                                            c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
 ]
 
 _lib = None

@@ -273,10 +273,11 @@ class GenParams:
     const_hi: float = 5.0
     init_depth_min: int = 2
     init_depth_max: int = 6
+    op_set: int = 0  # 0: + - * / sin cos exp log sqrt; 1: and x^2 1/x tan asin acos atan tanh
 
     def struct(self) -> _lib.GenParams:
         return _lib.GenParams(self.tournament, self.p_crossover, self.p_mutation, self.max_len, self.max_consts,
-                              self.const_lo, self.const_hi, self.init_depth_min, self.init_depth_max)
+                              self.const_lo, self.const_hi, self.init_depth_min, self.init_depth_max, self.op_set)
 
 
 @dataclasses.dataclass
@@ -334,6 +335,32 @@ def generation(parents: DevicePrograms, fitness: torch.Tensor, params: GenParams
                                    generation_index, problem, out.tokens.data_ptr(), out.len.data_ptr(),
                                    out.consts.data_ptr(), out.const_count.data_ptr(), _stream(dev)))
     return out
+
+
+def generation_microcosm(parents: DevicePrograms, fitness: torch.Tensor, params: GenParams, D: int, seed: int,
+                         generation_index: int, n_children: int, *, sample: int = 100, keep: float = 0.5,
+                         problem: int = 0, out: Optional[Slots] = None, with_selection: bool = False,
+                         ctx: Optional[Context] = None):
+    """One generation under microcosm selection -- beagle_generation_microcosm.
+    Returns the child slots, and with `with_selection` also the threshold
+    (float64 [1]) and the survivor count (int32 [1]) as device tensors."""
+    dev = parents.device
+    c = _ctx_for(dev, ctx)
+    if fitness.dtype != torch.float64 or fitness.device != dev or fitness.numel() != parents.n:
+        raise ValueError("fitness must be float64 [N] on the parents' device")
+    if out is None:
+        out = Slots.empty(n_children, params.max_len, params.max_consts, dev)
+    if out.n != n_children:
+        raise ValueError("out must hold n_children slots")
+    tau = torch.empty(1, dtype=torch.float64, device=dev)
+    ns = torch.empty(1, dtype=torch.int32, device=dev)
+    ps = parents.struct()
+    p = params.struct()
+    _check(c.lib.beagle_generation_microcosm(c.handle, ctypes.byref(ps), fitness.data_ptr(), ctypes.byref(p), D,
+                                             sample, keep, seed, generation_index, problem, n_children,
+                                             out.tokens.data_ptr(), out.len.data_ptr(), out.consts.data_ptr(),
+                                             out.const_count.data_ptr(), tau.data_ptr(), ns.data_ptr(), _stream(dev)))
+    return (out, tau, ns) if with_selection else out
 
 
 def evaluate_score(progs: DevicePrograms, X: torch.Tensor, y: torch.Tensor, kind="point", max_score: float = 1000.0,

@@ -30,7 +30,7 @@ beagle_status hip_fail(hipError_t e, const char* where) {
   return fail(BEAGLE_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
 }
 
-void clear_error() { clear_error(); }
+void clear_error() { g_error.clear(); }
 
 const char* last_error() { return g_error.c_str(); }
 
@@ -495,8 +495,12 @@ static beagle_status check_gen_params(const beagle_gen_params* p, int32_t D) {
   if (p->max_len < 1 || p->max_len > BEAGLE_MAX_LEN) return fail(BEAGLE_E_UNSUPPORTED, "max_len must be in [1, 4096]");
   if (p->max_consts < 0 || p->max_consts > 255) return fail(BEAGLE_E_UNSUPPORTED, "max_consts must be in [0, 255]");
   if (!(p->const_lo <= p->const_hi)) return fail(BEAGLE_E_INVALID_ARG, "const_lo > const_hi");
+  if (p->op_set != 0 && p->op_set != 1) return fail(BEAGLE_E_INVALID_ARG, "op_set must be 0 or 1");
   return BEAGLE_OK;
 }
+
+// unary operators of an operator set (see beagle_gen_params::op_set)
+static int32_t n_unary_of(const beagle_gen_params* p) { return p->op_set == 1 ? 12 : 5; }
 
 beagle_status beagle_init_population(beagle_ctx* ctx, const beagle_gen_params* params, int32_t n, int32_t D,
                                      uint64_t seed, uint32_t problem, uint16_t* tokens, int32_t* len,
@@ -525,6 +529,7 @@ beagle_status beagle_init_population(beagle_ctx* ctx, const beagle_gen_params* p
   a.max_consts = params->max_consts;
   a.const_lo = params->const_lo;
   a.const_hi = params->const_hi;
+  a.n_unary = n_unary_of(params);
   a.seed = seed;
   a.tag = 0x80000000u | problem;
   a.tokens = tokens;
@@ -567,6 +572,9 @@ beagle_status beagle_generation(beagle_ctx* ctx, const beagle_programs* parents,
   a.const_count = parents->const_count;
   a.fitness = fitness;
   a.n = n;
+  a.n_parents = n;
+  a.surv = nullptr;
+  a.n_surv = nullptr;
   a.D = D;
   a.tournament = params->tournament;
   // operator thresholds in binary32: p_crossover and p_crossover + p_mutation
@@ -578,6 +586,7 @@ beagle_status beagle_generation(beagle_ctx* ctx, const beagle_programs* parents,
   a.max_consts = params->max_consts;
   a.const_lo = params->const_lo;
   a.const_hi = params->const_hi;
+  a.n_unary = n_unary_of(params);
   a.seed = seed;
   a.generation = uint32_t(generation);
   a.tag = problem;
@@ -589,6 +598,102 @@ beagle_status beagle_generation(beagle_ctx* ctx, const beagle_programs* parents,
                      a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "generation launch");
+  clear_error();
+  return BEAGLE_OK;
+}
+
+beagle_status beagle_generation_microcosm(beagle_ctx* ctx, const beagle_programs* parents, const double* fitness,
+                                          const beagle_gen_params* params, int32_t D, int32_t sample, float keep,
+                                          uint64_t seed, uint64_t generation, uint32_t problem, int32_t n_children,
+                                          uint16_t* child_tokens, int32_t* child_len, float* child_consts,
+                                          int32_t* child_const_count, double* threshold, int32_t* n_survivors,
+                                          beagle_stream stream) {
+  if (!ctx) return fail(BEAGLE_E_INVALID_ARG, "ctx is NULL");
+  beagle_status st = check_programs(parents);
+  if (st != BEAGLE_OK) return st;
+  st = check_gen_params(params, D);
+  if (st != BEAGLE_OK) return st;
+  if (problem & 0xC0000000u) return fail(BEAGLE_E_INVALID_ARG, "problem id must be < 2^30");
+  if (sample < 1 || sample > bgl::MICRO_MAX_SAMPLE)
+    return fail(BEAGLE_E_INVALID_ARG, "sample must be in 1.." + std::to_string(bgl::MICRO_MAX_SAMPLE));
+  if (!(keep > 0.0f && keep <= 1.0f)) return fail(BEAGLE_E_INVALID_ARG, "keep must be in (0, 1]");
+  if (n_children < 0) return fail(BEAGLE_E_INVALID_ARG, "n_children < 0");
+  const int32_t n = parents->n_programs;
+  if (n == 0 && n_children > 0) return fail(BEAGLE_E_INVALID_ARG, "children need at least one parent");
+  if (n == 0) return BEAGLE_OK;
+  if (!fitness) return fail(BEAGLE_E_INVALID_ARG, "fitness is NULL");
+  if (n_children > 0 && (!child_tokens || !child_len || !child_const_count || (params->max_consts > 0 && !child_consts)))
+    return fail(BEAGLE_E_INVALID_ARG, "an output pointer is NULL");
+  DeviceGuard g(ctx->device);
+  if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+  const int32_t n_blocks = int32_t((int64_t(n) + bgl::MICRO_BLOCK - 1) / bgl::MICRO_BLOCK);
+  Carve cv;
+  const size_t o_tau = cv.take<double>(1);
+  const size_t o_ns = cv.take<int32_t>(1);
+  const size_t o_off = cv.take<int32_t>(size_t(n_blocks));
+  const size_t o_surv = cv.take<int32_t>(size_t(n));
+  st = reserve(ctx, cv.used);
+  if (st != BEAGLE_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  bgl::MicroArgs m;
+  m.fitness = fitness;
+  m.n = n;
+  m.sample = sample;
+  // threshold position ceil(keep * sample) - 1 in the sorted sample (the
+  // product in binary64, clamped to the sample)
+  const double kq = std::ceil(double(keep) * double(sample)) - 1.0;
+  m.k = int32_t(std::min(double(sample - 1), std::max(0.0, kq)));
+  m.seed = seed;
+  m.generation = uint32_t(generation);
+  m.tag = bgl::MICRO_TAG | problem;
+  m.n_blocks = n_blocks;
+  m.tau = threshold ? threshold : reinterpret_cast<double*>(ctx->ws + o_tau);
+  m.n_surv = n_survivors ? n_survivors : reinterpret_cast<int32_t*>(ctx->ws + o_ns);
+  m.block_off = reinterpret_cast<int32_t*>(ctx->ws + o_off);
+  m.surv = reinterpret_cast<int32_t*>(ctx->ws + o_surv);
+  hipLaunchKernelGGL(bgl::k_micro_threshold, dim3(1), dim3(bgl::MICRO_MAX_SAMPLE), 0, s, m);
+  hipLaunchKernelGGL(bgl::k_micro_count, dim3(n_blocks), dim3(bgl::MICRO_BLOCK), 0, s, m);
+  hipLaunchKernelGGL(bgl::k_micro_scan, dim3(1), dim3(1024), 0, s, m);
+  hipLaunchKernelGGL(bgl::k_micro_scatter, dim3(n_blocks), dim3(bgl::MICRO_BLOCK), 0, s, m);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "microcosm selection launch");
+  if (n_children > 0) {
+    bgl::GenStepArgs a;
+    a.tokens = parents->tokens;
+    a.n_tokens = parents->n_tokens;
+    a.tok_offset = parents->tok_offset;
+    a.tok_len = parents->tok_len;
+    a.consts = parents->consts;
+    a.n_consts = parents->n_consts;
+    a.const_offset = parents->const_offset;
+    a.const_count = parents->const_count;
+    a.fitness = fitness;
+    a.n = n_children;
+    a.n_parents = n;
+    a.surv = m.surv;
+    a.n_surv = m.n_surv;
+    a.D = D;
+    a.tournament = params->tournament;
+    const float pc = params->p_crossover;
+    volatile float sum = pc + params->p_mutation;
+    a.t_cross = pc;
+    a.t_mut = sum;
+    a.max_len = params->max_len;
+    a.max_consts = params->max_consts;
+    a.const_lo = params->const_lo;
+    a.const_hi = params->const_hi;
+    a.n_unary = n_unary_of(params);
+    a.seed = seed;
+    a.generation = uint32_t(generation);
+    a.tag = problem;
+    a.child_tokens = child_tokens;
+    a.child_len = child_len;
+    a.child_consts = child_consts;
+    a.child_const_count = child_const_count;
+    hipLaunchKernelGGL(bgl::k_generation, dim3((n_children + 63) / 64), dim3(64), 0, s, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "generation launch");
+  }
   clear_error();
   return BEAGLE_OK;
 }

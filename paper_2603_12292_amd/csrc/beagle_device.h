@@ -28,8 +28,9 @@
 //                        ADD, SUB, MUL, DIV, RSUB (b - a), RDIV (b / a);
 //                        its left operand is stk[n-2], a register named at
 //                        compile time
-//     92 + u             unary operator u in SIN, COS, EXP, LOG, SQRT
-//     97 + 6*s + o       fused "push a terminal, then binary operator o"
+//     92 + u             unary operator u in SIN, COS, EXP, LOG, SQRT,
+//                        SQUARE, RECIP, TAN, ASIN, ACOS, ATAN, TANH
+//     104 + 6*s + o      fused "push a terminal, then binary operator o"
 //                        (s = 0 VAR, 1 CONST): top = top op value; the
 //                        stack below top is untouched, so the pair costs one
 //                        dispatch and no stack traffic
@@ -43,14 +44,18 @@
 //     n                   VAR push at n = 0..3
 //     4 + n               CONST push at n
 //     8 + 3*o + (n-2)     binary operator o at n = 2..4
-//     26 + 4*u + (n-1)    unary operator u at n = 1..4
+//     26 + 4*u + (n-1)    unary operator u (the first five) at n = 1..4
 //     46 + 3*(6*s+o) + (n-1)   fused pair at n = 1..3
-//     255                 (a word of a program that needs a deeper stack)
+//     255                 (a word of a program that needs a deeper stack or
+//                         uses one of the seven further operators)
 //
 // Fused pairs make the decoded program shorter than the token program;
 // ProgMeta::len counts decoded words.  Programs are grouped by register
 // need into classes of 4, 8 and 16 stack slots, each run by a kernel
-// instantiated for that stack size.
+// instantiated for that stack size.  A program that uses any of the seven
+// further operators of the paper's table (SQUARE .. TANH) runs in class 1 at
+// least: the small-stack kernels, the hot path of the nine-operator
+// programs, carry no code for them.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -70,8 +75,23 @@ enum Opcode : uint32_t {
   OP_SQRT = 8,
   OP_VAR = 9,
   OP_CONST = 10,
-  N_OPCODES = 11
+  // the rest of the paper's operator table (unary, unprotected)
+  OP_SQUARE = 11,
+  OP_RECIP = 12,
+  OP_TAN = 13,
+  OP_ASIN = 14,
+  OP_ACOS = 15,
+  OP_ATAN = 16,
+  OP_TANH = 17,
+  N_OPCODES = 18
 };
+
+constexpr uint32_t N_UNARY = 12;  // SIN..SQRT, SQUARE..TANH
+constexpr uint32_t U_FIRST_EXT = 5;  // unary index of SQUARE
+
+// unary index u of a unary opcode (0..4: SIN..SQRT, 5..11: SQUARE..TANH)
+__host__ __device__ constexpr uint32_t unary_index(uint32_t op) { return op <= OP_SQRT ? op - OP_SIN : op - 6u; }
+__host__ __device__ constexpr bool is_extended(uint32_t op) { return op >= OP_SQUARE && op < N_OPCODES; }
 
 enum BinIdx : uint32_t { B_ADD = 0, B_SUB = 1, B_MUL = 2, B_DIV = 3, B_RSUB = 4, B_RDIV = 5 };
 
@@ -82,8 +102,8 @@ __host__ __device__ constexpr int need_class(int need) { return need <= 4 ? 0 : 
 constexpr uint32_t H_VAR = 0;
 constexpr uint32_t H_CONST = 1;
 constexpr uint32_t H_BIN = 2;
-constexpr uint32_t H_UN = 2 + 15 * 6;  // 92
-constexpr uint32_t H_FUSED = H_UN + 5;  // 97
+constexpr uint32_t H_UN = 2 + 15 * 6;         // 92
+constexpr uint32_t H_FUSED = H_UN + N_UNARY;  // 104
 constexpr uint32_t I0_PUSH_VAR = 0;
 constexpr uint32_t I0_PUSH_CONST = 4;
 constexpr uint32_t I0_BIN = 8;
@@ -95,7 +115,7 @@ constexpr int MAX_D = 16;
 
 __host__ __device__ constexpr uint32_t h_bin(uint32_t o, int n) { return H_BIN + 15u * o + uint32_t(n - 2); }
 
-__device__ __forceinline__ int arity(uint32_t op) { return op < 4 ? 2 : (op < 9 ? 1 : 0); }
+__device__ __forceinline__ int arity(uint32_t op) { return op < 4 ? 2 : (op < 9 || (op > OP_CONST && op < N_OPCODES) ? 1 : 0); }
 
 // ---- operator conventions (binary32) -------------------------------------
 __device__ __forceinline__ float op_div(float a, float b) { return b == 0.0f ? 1.0f : a / b; }
@@ -131,6 +151,22 @@ __device__ __forceinline__ float op_sqrt(float x) {
   const bool tiny = a < 0x1p-96f;
   const float s = __builtin_amdgcn_sqrtf(tiny ? a * 0x1p32f : a);
   return tiny ? s * 0x1p-16f : s;
+}
+
+// The seven further operators (unary index U_FIRST_EXT + j), IEEE semantics:
+// x * x; 1 / x (correctly rounded, +-Inf at +-0); tan, asin, acos, atan and
+// tanh from the device math library (a few ulp; NaN outside the domain of
+// asin and acos and for tan of +-Inf).
+template <uint32_t U>
+__device__ __forceinline__ float op_ext(float x) {
+  if constexpr (U == 5) return x * x;
+  if constexpr (U == 6) return 1.0f / x;
+  if constexpr (U == 7) return tanf(x);
+  if constexpr (U == 8) return asinf(x);
+  if constexpr (U == 9) return acosf(x);
+  if constexpr (U == 10) return atanf(x);
+  if constexpr (U == 11) return tanhf(x);
+  return 0.0f;
 }
 
 // Per-program metadata written by the preparation kernel.

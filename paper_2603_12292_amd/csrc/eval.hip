@@ -182,6 +182,12 @@ __device__ __forceinline__ void interpret(uint32_t vc0, float vv0, uint32_t vc1,
 #pragma unroll
           for (int k = 0; k < K; ++k) top[k] = op_sqrt(top[k]);
           break;
+#define BGL_EXT(U)                                                             \
+  case H_UN + U:                                                               \
+    _Pragma("unroll") for (int k = 0; k < K; ++k) top[k] = op_ext<U>(top[k]);  \
+    break;
+        BGL_EXT(5) BGL_EXT(6) BGL_EXT(7) BGL_EXT(8) BGL_EXT(9) BGL_EXT(10) BGL_EXT(11)
+#undef BGL_EXT
         default:
           break;
       }
@@ -573,16 +579,21 @@ __global__ void __launch_bounds__(256) k_eval_resident(EvalArgs a) {
   // the atomic (lane 0 adds 1, the others 0: one atomic after the wave
   // reduction), the item is read from lane 0 explicitly, the count is a
   // scalar and no early continue splits the body.
+  // Each atomic claims RESIDENT_BATCH consecutive programs (one
+  // same-address atomic per program would serialise at the counter).
   const int32_t count = __builtin_amdgcn_readfirstlane(a.class_count[0]);
   const int32_t* list = a.class_list;
   for (;;) {
-    const unsigned long long it = atomicAdd(a.work, lane == 0 ? 1ull : 0ull);
+    const unsigned long long it = atomicAdd(a.work, lane == 0 ? (unsigned long long)RESIDENT_BATCH : 0ull);
     const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(it), 0);
     const uint32_t hi = __builtin_amdgcn_readlane(uint32_t(it >> 32), 0);
-    const int64_t item = int64_t((uint64_t(hi) << 32) | lo);
-    if (item >= count) break;
-    const int p = __builtin_amdgcn_readfirstlane(list[item] - a.prog_begin);
-    if (p >= 0 && p < a.n_programs) eval_wave_resident<KIND, K>(a, p, xres, passes);  // else another slice's
+    const int64_t first = int64_t((uint64_t(hi) << 32) | lo);
+    if (first >= count) break;
+    const int64_t end = first + RESIDENT_BATCH < count ? first + RESIDENT_BATCH : count;
+    for (int64_t item = first; item < end; ++item) {
+      const int p = __builtin_amdgcn_readfirstlane(list[item] - a.prog_begin);
+      if (p >= 0 && p < a.n_programs) eval_wave_resident<KIND, K>(a, p, xres, passes);  // else another slice's
+    }
   }
 }
 
@@ -856,13 +867,19 @@ static hipError_t launch_class(const EvalArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// inputs bytes of the resident kernel (0: not eligible): one chunk, enough
-// programs to give every SIMD several waves, inputs within RESIDENT_MAX_BYTES
+// input bytes of the resident kernel with K cases per lane (the case set
+// padded to whole passes of 64 K cases)
 static size_t resident_bytes(const EvalArgs& a, int K) {
-  if (a.n_chunks != 1 || a.n_total < RESIDENT_MIN_PROGRAMS) return 0;
   const int64_t k64 = 64 * K;
-  const size_t b = size_t((a.M + k64 - 1) / k64) * size_t(a.D) * size_t(k64) * sizeof(float);
-  return b <= RESIDENT_MAX_BYTES ? b : 0;
+  return size_t((a.M + k64 - 1) / k64) * size_t(a.D) * size_t(k64) * sizeof(float);
+}
+
+// The resident kernel takes the call when there is one chunk, enough programs
+// to give every SIMD several waves, and inputs within RESIDENT_MAX_BYTES at
+// the wider tile's padding: the choice never depends on the tile width, so
+// the tuner's pick cannot switch kernels (and summation orders).
+static bool resident_eligible(const EvalArgs& a) {
+  return a.n_chunks == 1 && a.n_total >= RESIDENT_MIN_PROGRAMS && resident_bytes(a, 8) <= RESIDENT_MAX_BYTES;
 }
 
 template <int KIND, int K>
@@ -887,9 +904,8 @@ static hipError_t launch_kind(int kv, const EvalArgs& a, hipStream_t s, hipEvent
   if (e != hipSuccess) return e;
   if (ev0) (void)hipEventRecord(ev0, s);
   const bool wide = kv == 0 && a.D <= WIDE_TILE_MAX_D;
-  const size_t rb = resident_bytes(a, wide ? 8 : 4);
-  if (rb)
-    e = wide ? launch_resident<KIND, 8>(a, rb, s) : launch_resident<KIND, 4>(a, rb, s);
+  if (resident_eligible(a))
+    e = wide ? launch_resident<KIND, 8>(a, resident_bytes(a, 8), s) : launch_resident<KIND, 4>(a, resident_bytes(a, 4), s);
   else
     e = wide ? launch_class<KIND, 0, 0>(a, s) : launch_class<KIND, 0, 1>(a, s);
   if (ev1) (void)hipEventRecord(ev1, s);

@@ -71,6 +71,9 @@ __device__ __noinline__ float const_value(uint32_t u, float lo, float hi) {
   return float(double(lo) + prod);
 }
 
+// opcode of unary index u (0..4: SIN..SQRT, 5..11: SQUARE..TANH)
+__device__ __forceinline__ uint32_t unary_opcode(uint32_t u) { return u < 5u ? OP_SIN + u : OP_SQUARE + (u - 5u); }
+
 __device__ __forceinline__ int subtree_start(const uint16_t* tok, int i) {
   int need = 1;
   for (int j = i; j >= 0; --j) {
@@ -137,9 +140,18 @@ __global__ void k_generation(GenStepArgs a) {
   const int t = a.tournament;
   Stream s(a.seed, uint32_t(c), a.generation, a.tag);
   const double choice = unit01(s.draw(0));
-  const uint32_t N = uint32_t(a.n);
-  const int ia = tournament(s, 1, t, a.fitness, N);
-  const int ib = tournament(s, 1 + t, t, a.fitness, N);
+  const uint32_t N = uint32_t(a.n_parents);
+  int ia, ib;
+  if (a.surv) {
+    const int S = *a.n_surv;
+    const uint32_t ua = below(s.draw(1), uint32_t(S > 0 ? S : N));
+    const uint32_t ub = below(s.draw(1 + t), uint32_t(S > 0 ? S : N));
+    ia = S > 0 ? a.surv[ua] : int(ua);
+    ib = S > 0 ? a.surv[ub] : int(ub);
+  } else {
+    ia = tournament(s, 1, t, a.fitness, N);
+    ib = tournament(s, 1 + t, t, a.fitness, N);
+  }
   const int64_t oa = a.tok_offset[ia], ob = a.tok_offset[ib];
   const int64_t coa = a.const_offset[ia], cob = a.const_offset[ib];
   const int LA = a.tok_len[ia], LB = a.tok_len[ib];
@@ -185,7 +197,7 @@ __global__ void k_generation(GenStepArgs a) {
     if (ar == 2) {
       repl = below(msym, 4);  // ADD, SUB, MUL, DIV
     } else if (ar == 1) {
-      repl = OP_SIN + below(msym, 5);
+      repl = unary_opcode(below(msym, uint32_t(a.n_unary)));
     } else {
       const uint32_t sym = below(msym, uint32_t(a.D + 1));
       if (int(sym) < a.D) {
@@ -213,6 +225,100 @@ __global__ void k_generation(GenStepArgs a) {
   a.child_const_count[c] = w.ncst;
 }
 
+// ---- microcosm selection ----------------------------------------------------
+// A random sample of the population, ranked in one workgroup, gives the
+// fitness threshold at the keep quantile; every individual at least that
+// good survives, compacted in index order (per-block counts, one scan, a
+// scatter), and the children draw their parents uniformly from the
+// survivors.  Sort order of the sample: lower fitness first, NaN last, ties
+// by draw position; survival: fitness not NaN and <= tau (every non-NaN
+// individual when tau is NaN).
+
+__device__ __forceinline__ bool survives(double f, double tau) { return !isnan(f) && (isnan(tau) || f <= tau); }
+
+// blockDim.x == MICRO_MAX_SAMPLE, one workgroup
+__global__ void __launch_bounds__(MICRO_MAX_SAMPLE) k_micro_threshold(MicroArgs a) {
+  __shared__ double f[MICRO_MAX_SAMPLE];
+  const int j = threadIdx.x;
+  if (j < a.sample) {
+    Stream s(a.seed, MICRO_INDEX, a.generation, a.tag);
+    f[j] = a.fitness[below(s.draw(j), uint32_t(a.n))];
+  }
+  __syncthreads();
+  if (j >= a.sample) return;
+  const double fj = f[j];
+  const bool nj = isnan(fj);
+  int rank = 0;
+  for (int i = 0; i < a.sample; ++i) {
+    const double fi = f[i];
+    const bool ni = isnan(fi);
+    const bool less = ni != nj ? nj : (!ni && fi != fj ? fi < fj : i < j);
+    rank += less ? 1 : 0;
+  }
+  if (rank == a.k) *a.tau = fj;  // ranks are a permutation: exactly one writer
+}
+
+// survivors of block b (MICRO_BLOCK consecutive individuals), MICRO_BLOCK threads
+__global__ void __launch_bounds__(MICRO_BLOCK) k_micro_count(MicroArgs a) {
+  __shared__ int wave_n[MICRO_BLOCK / 64];
+  const int64_t i = int64_t(blockIdx.x) * MICRO_BLOCK + threadIdx.x;
+  const double tau = *a.tau;
+  const bool keep = i < a.n && survives(a.fitness[i], tau);
+  const int n = __popcll(__builtin_amdgcn_ballot_w64(keep));
+  if ((threadIdx.x & 63) == 0) wave_n[threadIdx.x >> 6] = n;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < MICRO_BLOCK / 64; ++w) t += wave_n[w];
+    a.block_off[blockIdx.x] = t;
+  }
+}
+
+// exclusive prefix sums of the block counts in place, and the total; one
+// workgroup of 1024 threads walking the counts 1024 at a time
+__global__ void __launch_bounds__(1024) k_micro_scan(MicroArgs a) {
+  __shared__ int wave_tot[16];
+  __shared__ int carry_s;
+  if (threadIdx.x == 0) carry_s = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int base = 0; base < a.n_blocks; base += 1024) {
+    const int b = base + int(threadIdx.x);
+    const int v = b < a.n_blocks ? a.block_off[b] : 0;
+    // inclusive scan inside the wave
+    int x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int y = __shfl_up(x, d, 64);
+      if (lane >= d) x += y;
+    }
+    if (lane == 63) wave_tot[w] = x;
+    __syncthreads();
+    const int carry = carry_s;
+    int before = 0;
+    for (int q = 0; q < w; ++q) before += wave_tot[q];
+    if (b < a.n_blocks) a.block_off[b] = carry + before + x - v;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry_s = carry + before + x;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *a.n_surv = carry_s;
+}
+
+__global__ void __launch_bounds__(MICRO_BLOCK) k_micro_scatter(MicroArgs a) {
+  __shared__ int wave_n[MICRO_BLOCK / 64];
+  const int64_t i = int64_t(blockIdx.x) * MICRO_BLOCK + threadIdx.x;
+  const double tau = *a.tau;
+  const bool keep = i < a.n && survives(a.fitness[i], tau);
+  const uint64_t m = __builtin_amdgcn_ballot_w64(keep);
+  if ((threadIdx.x & 63) == 0) wave_n[threadIdx.x >> 6] = __popcll(m);
+  __syncthreads();
+  int at = a.block_off[blockIdx.x];
+  for (int w = 0; w < int(threadIdx.x >> 6); ++w) at += wave_n[w];
+  at += __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
+  if (keep) a.surv[at] = int32_t(i);
+}
+
 __global__ void k_init_population(InitArgs a) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= a.n) return;
@@ -231,7 +337,7 @@ __global__ void k_init_population(InitArgs a) {
   Frame fr[MAX_INIT_DEPTH + 1];
   int sp = 0;
   int level = 0;
-  const uint32_t n_fun = 9;
+  const uint32_t n_fun = 4u + uint32_t(a.n_unary);
   for (;;) {
     bool term;
     uint32_t sym;
@@ -247,9 +353,9 @@ __global__ void k_init_population(InitArgs a) {
       sym = term ? v - n_fun : v;
     }
     if (!term) {
-      // functions in the order ADD SUB MUL DIV SIN COS EXP LOG SQRT = opcodes 0..8
-      fr[sp].op = uint8_t(sym);
-      fr[sp].left = uint8_t(arity(sym));
+      // functions in the order ADD SUB MUL DIV, then the unary ones
+      fr[sp].op = uint8_t(sym < 4u ? sym : unary_opcode(sym - 4u));
+      fr[sp].left = uint8_t(arity(fr[sp].op));
       fr[sp].level = uint8_t(level);
       ++sp;
       ++level;

@@ -26,6 +26,8 @@ constexpr int GRAD_LANE_SLOTS = 8;
 // tile of every adjoint kernel covers
 constexpr int64_t GRAD_CHUNK_CASES = 1024;
 constexpr int64_t GRAD_TILE_CASES = 256;
+// work items a wave claims per atomic in the adjoint kernels
+constexpr int GRAD_BATCH = 4;
 
 // Reverse handler of a decoded word in the derivative-tape adjoint (bits
 // 24..31 of the word's aux entry).  n is the stack size before the word in

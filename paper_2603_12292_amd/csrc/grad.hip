@@ -73,13 +73,27 @@ __device__ __forceinline__ float trig1(float x) {
   return v[0];
 }
 
+// d/dx of unary operator u at operand x with value y
 __device__ __forceinline__ float dunary(uint32_t u, float x, float y) {
   switch (u) {
     case 0: return trig1<true>(x);
     case 1: return -trig1<false>(x);
     case 2: return (x > 80.0f || x < -80.0f) ? 0.0f : y;
     case 3: return x != 0.0f ? __builtin_amdgcn_rcpf(x) : 0.0f;
-    default: return x != 0.0f ? copysignf(0.5f, x) * __builtin_amdgcn_rcpf(y) : 0.0f;
+    case 4: return x != 0.0f ? copysignf(0.5f, x) * __builtin_amdgcn_rcpf(y) : 0.0f;
+    case 5: return 2.0f * x;
+    case 6: return -(y * y);
+    case 7: return 1.0f + y * y;
+    case 8: return rsqrtf((1.0f - x) * (1.0f + x));
+    case 9: return -rsqrtf((1.0f - x) * (1.0f + x));
+    case 10: return 1.0f / (1.0f + x * x);
+    default: {
+      // tanh: sech^2 x = 4e / (1 + e)^2 with e = exp(-2|x|) (1 - y^2 cancels
+      // where tanh saturates)
+      const float e = op_exp(-2.0f * __builtin_fabsf(x));
+      const float ep = 1.0f + e;
+      return (4.0f * e) / (ep * ep);
+    }
   }
 }
 
@@ -233,6 +247,13 @@ __device__ void grad_item(const GradArgs& a, int p, int c, float* lds) {
         case H_UN + 2: top = op_exp(top); break;
         case H_UN + 3: top = op_log(top); break;
         case H_UN + 4: top = op_sqrt(top); break;
+        case H_UN + 5: top = op_ext<5>(top); break;
+        case H_UN + 6: top = op_ext<6>(top); break;
+        case H_UN + 7: top = op_ext<7>(top); break;
+        case H_UN + 8: top = op_ext<8>(top); break;
+        case H_UN + 9: top = op_ext<9>(top); break;
+        case H_UN + 10: top = op_ext<10>(top); break;
+        case H_UN + 11: top = op_ext<11>(top); break;
 #define BGL_GFUSED(O)                                                     \
   case H_FUSED + O: top = gbinop<O>(top, xl[arg * 64]); break;            \
   case H_FUSED + 6 + O: top = gbinop<O>(top, W.cv(t)); break;
@@ -312,6 +333,13 @@ __device__ void grad_item(const GradArgs& a, int p, int c, float* lds) {
         case H_UN + 2:
         case H_UN + 3:
         case H_UN + 4:
+        case H_UN + 5:
+        case H_UN + 6:
+        case H_UN + 7:
+        case H_UN + 8:
+        case H_UN + 9:
+        case H_UN + 10:
+        case H_UN + 11:
           g = g * dunary((w & 0xFFu) - H_UN, tget(t - 1), tget(t));
           break;
 #define BGL_RFUSED(O)                                   \
@@ -372,16 +400,23 @@ __global__ void __launch_bounds__(64) k_grad(GradArgs a) {
   const int64_t items = int64_t(count) * a.n_chunks;
   const int32_t* list = a.list + (LONG ? int64_t(a.n_programs) : 0);
   for (;;) {
-    // every lane takes part (lane 0 adds 1): no divergent branch in the
-    // persistent loop, the item read from lane 0 explicitly
-    const unsigned long long it = atomicAdd(a.work + (LONG ? 1 : 0), threadIdx.x == 0 ? 1ull : 0ull);
+    // as in k_grad_dtape: every lane in the atomic, a batch per atomic
+    const unsigned long long it =
+        atomicAdd(a.work + (LONG ? 1 : 0), threadIdx.x == 0 ? (unsigned long long)GRAD_BATCH : 0ull);
     const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(it), 0);
     const uint32_t hi = __builtin_amdgcn_readlane(uint32_t(it >> 32), 0);
-    const int64_t item = int64_t((uint64_t(hi) << 32) | lo);
-    if (item >= items) break;
-    const int c = int(item / count);
-    const int p = list[item % count];
-    grad_item<LONG>(a, p, c, lds);
+    const int64_t first = int64_t((uint64_t(hi) << 32) | lo);
+    if (first >= items) break;
+    const int n = int(first + GRAD_BATCH < items ? GRAD_BATCH : items - first);
+    int c = int(first / count), i = int(first - int64_t(c) * count);
+    for (int k = 0; k < n; ++k) {
+      const int p = __builtin_amdgcn_readfirstlane(list[i]);
+      grad_item<LONG>(a, p, c, lds);
+      if (++i == count) {
+        i = 0;
+        ++c;
+      }
+    }
   }
 }
 
@@ -863,22 +898,32 @@ __device__ __forceinline__ void dtape_list_item(const GradArgs& a, int p, int c,
 // LIST 2, 3, 4: at most GRAD_DTAPE_SMALL (4 cases per lane), MID, LARGE
 // entries per case (2 cases per lane, upper tape 0 or 32 entries).
 template <int LIST>
-__global__ void __launch_bounds__(64) k_grad_dtape(GradArgs a) {
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LIST == 3 ? 4 : 1))) k_grad_dtape(GradArgs a) {
   extern __shared__ float lds[];
   const int32_t count = a.list_count[LIST];
   const int64_t items = int64_t(count) * a.n_chunks;
   const int32_t* list = a.list + LIST * int64_t(a.n_programs);
   for (;;) {
-    // every lane takes part (lane 0 adds 1): no divergent branch in the
-    // persistent loop, the item read from lane 0 explicitly
-    const unsigned long long it = atomicAdd(a.work + LIST, threadIdx.x == 0 ? 1ull : 0ull);
+    // every lane takes part (lane 0 adds GRAD_BATCH): no divergent branch in
+    // the persistent loop, the first item read from lane 0 explicitly; a
+    // batch of items per atomic (one same-address atomic per item would
+    // serialise at the counter)
+    const unsigned long long it = atomicAdd(a.work + LIST, threadIdx.x == 0 ? (unsigned long long)GRAD_BATCH : 0ull);
     const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(it), 0);
     const uint32_t hi = __builtin_amdgcn_readlane(uint32_t(it >> 32), 0);
-    const int64_t item = int64_t((uint64_t(hi) << 32) | lo);
-    if (item >= items) break;
-    const int c = int(item / count);
-    const int p = list[item % count];
-    dtape_list_item<LIST>(a, p, c, lds);
+    const int64_t first = int64_t((uint64_t(hi) << 32) | lo);
+    if (first >= items) break;
+    const int n = int(first + GRAD_BATCH < items ? GRAD_BATCH : items - first);
+    // item = c * count + i, stepped without a division per item
+    int c = int(first / count), i = int(first - int64_t(c) * count);
+    for (int k = 0; k < n; ++k) {
+      const int p = __builtin_amdgcn_readfirstlane(list[i]);
+      dtape_list_item<LIST>(a, p, c, lds);
+      if (++i == count) {
+        i = 0;
+        ++c;
+      }
+    }
   }
 }
 #undef BGL_K

@@ -166,6 +166,7 @@ constexpr int WIDE_TILE_MAX_D = 8;
 // many bytes per workgroup, populations of at least this many programs.
 constexpr size_t RESIDENT_MAX_BYTES = 64 * 1024;
 constexpr int32_t RESIDENT_MIN_PROGRAMS = 4096;
+constexpr int RESIDENT_BATCH = 16;  // programs a wave claims per atomic
 __host__ __device__ constexpr int class_k(int c, int kv) { return c == 0 ? (kv == 0 ? 8 : 4) : (c == 1 ? 4 : 2); }
 
 __global__ void k_prepare(PrepareArgs a);

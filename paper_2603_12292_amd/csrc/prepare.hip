@@ -90,6 +90,7 @@ __device__ static ListIds prepare_program(const PrepareArgs& a, int p, ST tok, S
   int L_dec = 0;
   int n_ent = 0;  // derivative-tape entries per case (adjoint)
   uint32_t vmask = 0;
+  bool ext = false;  // uses one of the further operators (SQUARE .. TANH)
   if (L <= 0) {
     status = L == 0 ? BEAGLE_PROG_EMPTY : BEAGLE_PROG_BAD_LAYOUT;
   } else if (L > MAX_LEN) {
@@ -107,6 +108,7 @@ __device__ static ListIds prepare_program(const PrepareArgs& a, int p, ST tok, S
       if (op >= N_OPCODES) { status = BEAGLE_PROG_BAD_OPCODE; break; }
       if (op == OP_VAR && int(arg) >= a.D) { status = BEAGLE_PROG_BAD_VAR; break; }
       if (op == OP_VAR) vmask |= 1u << arg;
+      ext |= is_extended(op);
       if (op == OP_CONST && int(arg) >= cc) { status = BEAGLE_PROG_BAD_CONST; break; }
       const int ar = arity(op);
       if (depth < ar) { status = BEAGLE_PROG_UNDERFLOW; break; }
@@ -239,8 +241,9 @@ __device__ static ListIds prepare_program(const PrepareArgs& a, int p, ST tok, S
           --n;
           prod.set(n - 1, out);
         } else {
-          h = H_UN + (op - OP_SIN);
-          i0 = n <= 4 ? I0_UN + 4u * (op - OP_SIN) + uint32_t(n - 1) : I0_NONE;
+          const uint32_t u = unary_index(op);
+          h = H_UN + u;
+          i0 = n <= 4 && u < U_FIRST_EXT ? I0_UN + 4u * u + uint32_t(n - 1) : I0_NONE;
           rws = uint32_t(n - 1);
           rid = n <= 4 ? R_UN + uint32_t(n - 1) : R_NONE;
           ent = 1;
@@ -279,12 +282,14 @@ __device__ static ListIds prepare_program(const PrepareArgs& a, int p, ST tok, S
     // the list of its register-need class (list order does not affect any
     // result: every (program, chunk) partial has its own slot)
     ids.cls = need_class(need_root);
+    // the further operators are compiled into the general-stack kernels only
+    if (ext && ids.cls == 0) ids.cls = 1;
     // and by tape size (the adjoint keeps short tapes in registers)
     // adjoint lists: 0 short value tape, 1 long value tape; register need
     // <= 4 and at most GRAD_LANE_SLOTS constant slots: 2, 3, 4 at most
     // GRAD_DTAPE_SMALL, MID, LARGE derivative-tape entries
-    const int lc = L_dec > a.short_words                     ? 1
-                   : need_root > 4 || cc > GRAD_LANE_SLOTS    ? 0
+    const int lc = L_dec > a.short_words                          ? 1
+                   : need_root > 4 || cc > GRAD_LANE_SLOTS || ext  ? 0
                    : n_ent <= GRAD_DTAPE_SMALL ? 2
                    : n_ent <= GRAD_DTAPE_MID   ? 3
                    : n_ent <= GRAD_DTAPE_LARGE ? 4

@@ -30,7 +30,11 @@ import numpy as np
 ADD, SUB, MUL, DIV, SIN, COS, EXP, LOG, SQRT, VAR, CONST = range(11)
 BINARY_OPS = (ADD, SUB, MUL, DIV)
 UNARY_OPS = (SIN, COS, EXP, LOG, SQRT)
-OP_NAMES = ("add", "sub", "mul", "div", "sin", "cos", "exp", "log", "sqrt", "var", "const")
+# the rest of the paper's operator table (unary)
+SQUARE, RECIP, TAN, ASIN, ACOS, ATAN, TANH = range(11, 18)
+EXTENDED_OPS = (SQUARE, RECIP, TAN, ASIN, ACOS, ATAN, TANH)
+OP_NAMES = ("add", "sub", "mul", "div", "sin", "cos", "exp", "log", "sqrt", "var", "const",
+            "square", "recip", "tan", "asin", "acos", "atan", "tanh")
 
 
 def tok(op: int, arg: int = 0) -> int:
@@ -40,7 +44,7 @@ def tok(op: int, arg: int = 0) -> int:
 def arity_of(op: int) -> int:
     if op in BINARY_OPS:
         return 2
-    if op in UNARY_OPS:
+    if op in UNARY_OPS or op in EXTENDED_OPS:
         return 1
     return 0
 
@@ -97,16 +101,18 @@ def pack_programs(progs: Sequence[Tuple[Sequence[int], Sequence[float]]]) -> Pro
 # --- random programs of an exact length ---------------------------------------
 def random_program(rng: np.random.Generator, length: int, D: int, *, max_consts: int = 8,
                    const_lo: float = -5.0, const_hi: float = 5.0,
-                   allow_const: bool = True) -> Tuple[List[int], List[float]]:
+                   allow_const: bool = True, unary=None) -> Tuple[List[int], List[float]]:
     """One valid postfix program of exactly ``length`` tokens.
 
     Left to right, each token is drawn uniformly among the symbols that still
     let the program close to a single value in the tokens that remain: the
-    four binary operators (need two values on the stack), the five unary ones
-    (need one) and the D+1 terminal symbols x_0..x_{D-1}, CONST (allowed while
+    four binary operators (need two values on the stack), the unary ones
+    (need one; the five of the base set, or the opcodes in ``unary``) and
+    the D+1 terminal symbols x_0..x_{D-1}, CONST (allowed while
     depth + 1 <= tokens remaining).  CONST draws beyond ``max_consts`` become
     x_0.  Constants are U(const_lo, const_hi) rounded to fp32.
     """
+    unary_ops = UNARY_OPS if unary is None else tuple(unary)
     if length < 1:
         raise ValueError("length must be >= 1")
     toks: List[int] = []
@@ -122,7 +128,7 @@ def random_program(rng: np.random.Generator, length: int, D: int, *, max_consts:
         if depth + 1 - 1 <= r:
             ok += [(0, s) for s in range(n_term_syms)]
         if depth >= 1 and depth - 1 <= r:
-            ok += [(1, op) for op in UNARY_OPS]
+            ok += [(1, op) for op in unary_ops]
         if depth >= 2 and depth - 2 <= r:
             ok += [(2, op) for op in BINARY_OPS]
         kind, sym = ok[int(rng.integers(len(ok)))]
@@ -161,11 +167,12 @@ def place_constants(rng: np.random.Generator, toks: List[int], k: int, *,
 
 def random_population(seed: int, N: int, len_lo: int, len_hi: int, D: int, *,
                       max_consts: int = 8, const_range: Tuple[float, float] = (-5.0, 5.0),
-                      consts_per_program: Optional[Tuple[int, int]] = None) -> ProgramSet:
+                      consts_per_program: Optional[Tuple[int, int]] = None, unary=None) -> ProgramSet:
     """N programs, lengths uniform on {len_lo..len_hi}.
 
     With ``consts_per_program=(a, b)`` each program first gets a variables-only
-    skeleton, then k ~ U{a..b} of its terminals become constants.
+    skeleton, then k ~ U{a..b} of its terminals become constants.  ``unary``:
+    the unary opcodes to draw from (default: the five of the base set).
     """
     rng = np.random.default_rng(np.random.SeedSequence([seed, 0x5052]))
     progs = []
@@ -173,9 +180,9 @@ def random_population(seed: int, N: int, len_lo: int, len_hi: int, D: int, *,
     for _ in range(N):
         L = int(rng.integers(len_lo, len_hi + 1))
         if consts_per_program is None:
-            progs.append(random_program(rng, L, D, max_consts=max_consts, const_lo=lo, const_hi=hi))
+            progs.append(random_program(rng, L, D, max_consts=max_consts, const_lo=lo, const_hi=hi, unary=unary))
         else:
-            t, _ = random_program(rng, L, D, allow_const=False)
+            t, _ = random_program(rng, L, D, allow_const=False, unary=unary)
             k = int(rng.integers(consts_per_program[0], consts_per_program[1] + 1))
             progs.append(place_constants(rng, t, k, const_lo=lo, const_hi=hi))
     return pack_programs(progs)
@@ -304,6 +311,32 @@ class Workload:
     name: str
     programs: ProgramSet
     data: Dataset
+
+
+def replicate(ps: "ProgramSet", times: int) -> "ProgramSet":
+    """The population repeated `times` times, every copy with its own token
+    and constant storage (program p of copy r is program r * n + p)."""
+    n_tok = int(ps.tokens.shape[0])
+    n_const = int(ps.consts.shape[0])
+    reps = np.arange(times, dtype=np.int64)
+    return ProgramSet(
+        tokens=np.tile(ps.tokens, times),
+        tok_offset=(ps.tok_offset[None, :] + reps[:, None] * n_tok).reshape(-1).astype(np.int64),
+        tok_len=np.tile(ps.tok_len, times),
+        consts=np.tile(ps.consts, times),
+        const_offset=(ps.const_offset[None, :] + reps[:, None] * n_const).reshape(-1).astype(np.int64),
+        const_count=np.tile(ps.const_count, times),
+    )
+
+
+def config_paper_shape(seed: int = 2611, *, copies: int = 256, M: int = 512) -> Workload:
+    """The paper's regime (about 10^6 individuals, 512 fitness cases per
+    generation): the plain-mid population (N = 4096, L ~ U{5..64}, D = 5)
+    replicated to 2^20 programs, on 512 cases drawn like plain-mid's."""
+    base = config_mid()
+    data = make_dataset(seed, M, 5, x_range=(1.0, 10.0), target_len=20)
+    return Workload(f"paper-shape: N={base.programs.n * copies} (plain-mid x{copies}), L~U{{5..64}}, D=5, M={M}",
+                    replicate(base.programs, copies), data)
 
 
 def invalid_target_dataset(seed: int, M: int, D: int, *, x_range=(1.0, 5.0)) -> Dataset:

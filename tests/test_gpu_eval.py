@@ -121,7 +121,7 @@ def test_special_programs():
 
 def test_invalid_programs_status_and_nan():
     data = wl.make_dataset(6, 500, 2, x_range=(1.0, 5.0), target_len=6)
-    progs = [("x0 +", []), ("x0 x1", []), ("x5", []), ("c3", [1.0]), ([11], []), ([], []),
+    progs = [("x0 +", []), ("x0 x1", []), ("x5", []), ("c3", [1.0]), ([18], []), ([], []),
              ("x0 x1 +", []), ([9] * 4097, [])]
     ps = wl.pack_programs([(parse(p) if isinstance(p, str) else p, c) for p, c in progs])
     f, st = _run(ps, data, ofit.MSE)
@@ -396,3 +396,38 @@ def test_resident_small_case_sets(M):
                 scores = {sc.point_score(o, bad_y.y, 1000.0) for o in outs}
                 if len(scores) == 1:
                     assert whole[p] == scores.pop(), p
+
+
+def test_success_clears_last_error():
+    """A call that launches its work successfully leaves beagle_last_error()
+    empty; a rejected call sets it."""
+    import ctypes
+    from paper_2603_12292_amd import _lib
+    lib = _lib.load()
+    w = wl.config_tiny()
+    P = _lib.Programs(0x1000, 70, 0x2000, 0x3000, 0x4000, 20, 0x5000, 0x6000, 10)
+    Dd = _lib.Dataset(0x7000, 0x8000, 1000, 3)
+    assert lib.beagle_eval(None, ctypes.byref(P), ctypes.byref(Dd), _lib.FIT_MSE, None, None, None) == _lib.E_INVALID_ARG
+    assert lib.beagle_last_error() != b""
+    _run(w.programs, w.data, ofit.MSE)
+    assert lib.beagle_last_error() == b""
+
+
+@pytest.mark.parametrize("M", [5000, 5300])
+def test_resident_tile_width_changes_no_bit(M):
+    """Populations on the resident-inputs kernel's side of its threshold
+    (M = 5000, D = 3) and just past it for the wide tile's padding
+    (M = 5300): 8 and 4 cases per lane give the same fitness bits."""
+    api = _api()
+    ps = wl.random_population(95, 4096, 3, 40, 3)
+    data = wl.make_dataset(96, M, 3, x_range=(1.0, 5.0), target_len=10)
+    X, y = _xy(data)
+    P = _dev(ps)
+    ctx = api.Context(0)
+    for kind in ("mse", "corr"):
+        ctx.set_tuning("wide")
+        a = api.evaluate(P, X, y, kind, ctx=ctx).cpu().numpy()
+        ctx.set_tuning("narrow")
+        b = api.evaluate(P, X, y, kind, ctx=ctx).cpu().numpy()
+        assert np.array_equal(a.view(np.uint64), b.view(np.uint64)), (kind, M)
+    ctx.close()

@@ -115,3 +115,99 @@ def test_generation_argument_errors():
         api.generation(par, f, api.GenParams(p_crossover=0.8, p_mutation=0.5), 2, 1, 1)
     with pytest.raises(api.BeagleError):
         api.init_population(10, 2, api.GenParams(init_depth_max=7), 1)
+
+
+# ---- microcosm selection
+
+
+def _micro_case(n, seed, nan_frac=0.1, ties=True):
+    rng = np.random.default_rng(seed)
+    fit = rng.standard_normal(n)
+    fit[rng.integers(0, n, size=int(n * nan_frac))] = np.nan
+    fit[rng.integers(0, n, size=n // 20)] = np.inf
+    if ties:
+        fit[rng.integers(0, n, size=n // 10)] = 0.25
+    return fit
+
+
+@pytest.mark.parametrize("n,sample,keep,seed,g", [
+    (1, 100, 0.5, 1, 1), (63, 100, 0.5, 2, 3), (256, 7, 0.3, 3, 1), (1000, 100, 0.5, 4, 2),
+    (70_001, 100, 0.5, 2**40 + 5, 9), (70_001, 1024, 0.05, 6, 11), (300_000, 100, 1.0, 7, 4),
+    (300_000, 1, 0.5, 8, 5)])
+def test_microcosm_selection_bit_exact(n, sample, keep, seed, g):
+    """Threshold (bit for bit) and survivor count against the oracle; sizes
+    with a ragged last compaction block and more than one scan chunk."""
+    api = _api()
+    fit = _micro_case(n, seed)
+    # selection only reads the fitness: parents are n copies of "x0"
+    par = api.DevicePrograms.from_fixed(torch.full((n, 1), gp.VAR, dtype=torch.int16, device="cuda"),
+                                        torch.ones(n, dtype=torch.int32, device="cuda"),
+                                        torch.zeros((n, 1), dtype=torch.float32, device="cuda"),
+                                        torch.zeros(n, dtype=torch.int32, device="cuda"))
+    f = torch.from_numpy(fit).cuda()
+    _, tau, ns = api.generation_microcosm(par, f, api.GenParams(), 2, seed, g, 0, sample=sample, keep=keep,
+                                          with_selection=True)
+    torch.cuda.synchronize()
+    ref_tau = gp.microcosm_threshold(fit, sample, keep, seed, g)
+    t = tau.cpu().numpy()
+    assert t.view(np.uint64)[0] == np.array([ref_tau]).view(np.uint64)[0], (t[0], ref_tau)
+    keep_mask = ~np.isnan(fit) & (np.isnan(ref_tau) | (fit <= ref_tau))
+    assert int(ns.cpu()[0]) == int(keep_mask.sum()) > 0
+    assert gp.survivors(fit, ref_tau) == np.nonzero(keep_mask)[0].tolist()
+
+
+@pytest.mark.parametrize("kw,n_children", [(dict(p_crossover=0.0, p_mutation=1.0), 1500),
+                                           (dict(), 700), (dict(tournament=3, max_consts=2), 333)])
+def test_microcosm_children_bit_exact(kw, n_children):
+    """Children drawn from the survivors, bit-exact against the oracle, for
+    child counts above, equal to and below the parent count."""
+    api = _api()
+    op, ap = _params(api, **kw)
+    D = 4
+    ps, fit = _parents(41, 700, D)
+    seed, g = 0x0BAD_5EED_0000_0001, 6
+    par = api.DevicePrograms.from_programset(ps)
+    f = torch.from_numpy(fit).cuda()
+    s, tau, ns = api.generation_microcosm(par, f, ap, D, seed, g, n_children, sample=100, keep=0.4,
+                                          with_selection=True)
+    torch.cuda.synchronize()
+    tok, ln, cst, cc = _slots_to_lists(s)
+    plist_t = [list(ps.program(p)[0]) for p in range(ps.n)]
+    plist_c = [list(ps.program(p)[1]) for p in range(ps.n)]
+    kids = gp.generation_microcosm(plist_t, plist_c, fit, D, op, seed, g, n_children, sample=100, keep=0.4)
+    ref = gp.to_fixed(kids, op.max_len, op.max_consts)
+    bad = np.nonzero((ln != ref[1]) | np.any(tok != ref[0], axis=1))[0]
+    assert len(bad) == 0, bad[:10]
+    assert np.array_equal(cc, ref[3])
+    assert np.array_equal(cst.view(np.uint32), ref[2].view(np.uint32))
+    assert 0 < int(ns.cpu()[0]) < 700
+
+
+def test_microcosm_no_survivor_uses_every_parent():
+    """All-NaN fitness: no survivor (count 0), children drawn from every parent."""
+    api = _api()
+    op, ap = _params(api, p_crossover=0.0, p_mutation=1.0)
+    D = 3
+    ps, _ = _parents(5, 300, D)
+    fit = np.full(300, np.nan)
+    par = api.DevicePrograms.from_programset(ps)
+    s, tau, ns = api.generation_microcosm(par, torch.from_numpy(fit).cuda(), ap, D, 77, 2, 256,
+                                          with_selection=True)
+    torch.cuda.synchronize()
+    assert int(ns.cpu()[0]) == 0 and np.isnan(tau.cpu().numpy()[0])
+    tok, ln, _, _ = _slots_to_lists(s)
+    plist_t = [list(ps.program(p)[0]) for p in range(ps.n)]
+    plist_c = [list(ps.program(p)[1]) for p in range(ps.n)]
+    ref = gp.to_fixed(gp.generation_microcosm(plist_t, plist_c, fit, D, op, 77, 2, 256), op.max_len, op.max_consts)
+    assert np.array_equal(ln, ref[1]) and np.array_equal(tok, ref[0])
+
+
+def test_microcosm_argument_errors():
+    api = _api()
+    ps, fit = _parents(3, 10, 2)
+    par = api.DevicePrograms.from_programset(ps)
+    f = torch.from_numpy(fit).cuda()
+    for kw in (dict(sample=0), dict(sample=1025), dict(keep=0.0), dict(keep=1.5), dict(keep=float("nan")),
+               dict(problem=2**30)):
+        with pytest.raises(api.BeagleError):
+            api.generation_microcosm(par, f, api.GenParams(), 2, 1, 1, 5, **kw)
