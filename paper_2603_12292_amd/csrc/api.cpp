@@ -160,7 +160,7 @@ EvalLayout eval_layout(const beagle_programs* P, const beagle_dataset* d, int n_
 // Validation + decoding of the programs and staging of the cases (shared by
 // evaluation, prediction and the gradient).
 beagle_status prepare(beagle_ctx* ctx, const beagle_programs* P, const beagle_dataset* d, const EvalLayout& L,
-                      int8_t* status, hipStream_t s, int32_t max_words = bgl::MAX_LEN) {
+                      int8_t* status, hipStream_t s, int32_t max_words = bgl::MAX_LEN, bool adjoint = false) {
   char* ws = ctx->ws;
   zero_i32(reinterpret_cast<int32_t*>(ws + L.class_count), 64, s);
   bgl::PrepareArgs pa;
@@ -188,7 +188,14 @@ beagle_status prepare(beagle_ctx* ctx, const beagle_programs* P, const beagle_da
   pa.len_count = reinterpret_cast<int32_t*>(ws + L.class_count) + 8;
   pa.len_list = reinterpret_cast<int32_t*>(ws + L.len_list);
   pa.short_words = bgl::GRAD_SHORT_WORDS;
-  hipLaunchKernelGGL(bgl::k_prepare, dim3((P->n_programs + 63) / 64), dim3(64), 0, s, pa);
+  pa.adjoint = adjoint ? 1 : 0;
+  // the narrow-scratch decoder when programs are short on average (both
+  // variants write the same words; a longer program takes the global scratch)
+  const bool narrow = P->n_tokens <= 40 * int64_t(P->n_programs);
+  if (narrow)
+    hipLaunchKernelGGL(bgl::k_prepare<true>, dim3((P->n_programs + 63) / 64), dim3(64), 0, s, pa);
+  else
+    hipLaunchKernelGGL(bgl::k_prepare<false>, dim3((P->n_programs + 63) / 64), dim3(64), 0, s, pa);
   bgl::StageArgs sa;
   sa.X = d->X;
   sa.y = d->y;
@@ -221,6 +228,35 @@ beagle_status launch_values(beagle_ctx* ctx, const beagle_programs* P, const bea
   const int64_t tiles = (m + 63) / 64;
   if (tiles > 65535) return fail(BEAGLE_E_UNSUPPORTED, "predict: M > 4194240");
   hipLaunchKernelGGL(bgl::k_values, dim3(P->n_programs, uint32_t(tiles)), dim3(64), 0, s, va);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "values launch");
+  return BEAGLE_OK;
+}
+
+// The correlation shifts before an evaluation (correlation fitness and the
+// Eq. 2 score).  When the shape takes the resident-inputs kernel, class 0's
+// shifts come from that kernel's first pass (*in_kernel = true) and only the
+// class-1 and class-2 programs run the shift pass here.
+beagle_status launch_shifts(beagle_ctx* ctx, const beagle_programs* P, const beagle_dataset* d, const EvalLayout& L,
+                            hipStream_t s, bool* in_kernel) {
+  *in_kernel = bgl::resident_eligible(d->M, d->D, L.n_chunks, P->n_programs);
+  if (!*in_kernel) return launch_values(ctx, P, d, L, 1, nullptr, 1, s);
+  bgl::ValuesArgs va;
+  char* ws = ctx->ws;
+  va.code = reinterpret_cast<const uint32_t*>(ws + L.code);
+  va.cval = reinterpret_cast<const float*>(ws + L.cval);
+  va.tok_offset = P->tok_offset;
+  va.meta = reinterpret_cast<bgl::ProgMeta*>(ws + L.meta);
+  va.Xt = reinterpret_cast<const float*>(ws + L.Xt);
+  va.Mp = L.Mp;
+  va.m = 1;
+  va.D = d->D;
+  va.n_programs = P->n_programs;
+  va.out = nullptr;
+  va.shift_mode = 1;
+  hipLaunchKernelGGL(bgl::k_values_deep, dim3(2048), dim3(64), 0, s, va,
+                     reinterpret_cast<const int32_t*>(ws + L.class_count),
+                     reinterpret_cast<const int32_t*>(ws + L.class_list), P->n_programs);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "values launch");
   return BEAGLE_OK;
@@ -360,10 +396,11 @@ beagle_status evaluate(beagle_ctx* ctx, const beagle_programs* progs, const beag
   st = prepare(ctx, progs, data, L, status, s);
   if (st != BEAGLE_OK) return st;
   char* ws = ctx->ws;
+  bool shift_in_kernel = false;
   if (kind == BEAGLE_FIT_CORR || kind == BEAGLE_FIT_R4) {
     hipLaunchKernelGGL(bgl::k_target_stats, dim3(1), dim3(1024), 0, s, data->y, data->M,
                        reinterpret_cast<double*>(ws + L.stats));
-    st = launch_values(ctx, progs, data, L, 1, nullptr, 1, s);
+    st = launch_shifts(ctx, progs, data, L, s, &shift_in_kernel);
     if (st != BEAGLE_OK) return st;
   }
   auto slice_args = [&](int32_t p0, int32_t np) {
@@ -388,6 +425,7 @@ beagle_status evaluate(beagle_ctx* ctx, const beagle_programs* progs, const beag
     ea.n_total = progs->n_programs;
     ea.prog_begin = p0;
     ea.smax = smax;
+    ea.meta_shift = shift_in_kernel ? reinterpret_cast<bgl::ProgMeta*>(ws + L.meta) + p0 : nullptr;
     return ea;
   };
   int kv = 0;
@@ -710,7 +748,8 @@ beagle_status corr_pass(beagle_ctx* ctx, const beagle_programs* progs, const bea
   char* ws = ctx->ws;
   hipLaunchKernelGGL(bgl::k_target_stats, dim3(1), dim3(1024), 0, s, data->y, data->M,
                      reinterpret_cast<double*>(ws + L.stats));
-  beagle_status st = launch_values(ctx, progs, data, L, 1, nullptr, 1, s);
+  bool shift_in_kernel = false;
+  beagle_status st = launch_shifts(ctx, progs, data, L, s, &shift_in_kernel);
   if (st != BEAGLE_OK) return st;
   bgl::EvalArgs ea;
   ea.code = reinterpret_cast<const uint32_t*>(ws + L.code);
@@ -732,6 +771,7 @@ beagle_status corr_pass(beagle_ctx* ctx, const beagle_programs* progs, const bea
   ea.work = reinterpret_cast<unsigned long long*>(ws + L.work);
   ea.n_total = progs->n_programs;
   ea.prog_begin = 0;
+  ea.meta_shift = shift_in_kernel ? reinterpret_cast<bgl::ProgMeta*>(ws + L.meta) : nullptr;
   int kv = 0;
   TuneSlice ts{BEAGLE_FIT_CORR, ea};
   st = tile_variant(ctx, BEAGLE_FIT_CORR, data->D, data->M, double(progs->n_tokens) / progs->n_programs, s,
@@ -778,7 +818,7 @@ beagle_status beagle_eval_grad(beagle_ctx* ctx, const beagle_programs* progs, co
   EvalLayout L = eval_layout(progs, data, corr ? 3 : 1, progs->n_programs, true);
   st = reserve(ctx, L.total);
   if (st != BEAGLE_OK) return st;
-  st = prepare(ctx, progs, data, L, status, s, bgl::GRAD_LONG_WORDS);
+  st = prepare(ctx, progs, data, L, status, s, bgl::GRAD_LONG_WORDS, true);
   if (st != BEAGLE_OK) return st;
   char* ws = ctx->ws;
   if (corr) {

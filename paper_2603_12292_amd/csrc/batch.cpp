@@ -198,6 +198,7 @@ beagle_status beagle_eval_batched(beagle_ctx* ctx, const beagle_programs* progs,
     pa.len_count = counts + int64_t(64) * i + 8;
     pa.len_list = reinterpret_cast<int32_t*>(ws + o.len_list);
     pa.short_words = bgl::GRAD_SHORT_WORDS;
+    pa.adjoint = 0;
     t.X = d.X;
     t.y = d.y;
     t.Xt = reinterpret_cast<float*>(ws + o.Xt);

@@ -529,8 +529,9 @@ __device__ __forceinline__ void eval_wave_resident(const EvalArgs& a, int p, con
   const float vv0 = lane < L ? cval[lane] : 0.0f;
   const uint32_t vc1 = lane + 64 < L ? code[lane + 64] : 0u;
   const float vv1 = lane + 64 < L ? cval[lane + 64] : 0.0f;
-  const double shift = double(m.shift);
-  const double ybar = KIND == BEAGLE_FIT_CORR || KIND == BEAGLE_FIT_R4 ? a.stats[0] : 0.0;
+  constexpr bool SHIFTED = KIND == BEAGLE_FIT_CORR || KIND == BEAGLE_FIT_R4;
+  double shift = double(m.shift);
+  const double ybar = SHIFTED ? a.stats[0] : 0.0;
   const double smax = a.smax, s11 = a.smax / 11.0;
   Acc<KIND> acc;
   for (int ps = 0; ps < passes; ++ps) {
@@ -546,6 +547,14 @@ __device__ __forceinline__ void eval_wave_resident(const EvalArgs& a, int p, con
     }
     float top[K];
     interpret_small<K>(vc0, vv0, vc1, vv1, code, cval, L, lane, xres + ps * (a.D * K64) + 4 * lane, top);
+    if (SHIFTED && ps == 0 && a.meta_shift) {
+      // the shift is the output at case 0 (lane 0, first case) when finite:
+      // the value the shift pass computes, from the same arithmetic
+      const float y0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(top[0]), 0));
+      const float sh = isfinite(y0) ? y0 : 0.0f;
+      if (lane == 0) a.meta_shift[p].shift = sh;
+      shift = double(sh);
+    }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const bool valid = base + (k / 4) * 256 + 4 * lane + (k % 4) < a.M;
@@ -693,6 +702,20 @@ __device__ static void values_program(const ValuesArgs& a, int p, int64_t tile, 
 __global__ void __launch_bounds__(64) k_values(ValuesArgs a) {
   __shared__ float xl_all[MAX_D * 256];
   values_program(a, blockIdx.x, blockIdx.y, xl_all);
+}
+
+// Correlation shifts of the class-1 and class-2 programs only (the
+// resident-inputs kernel computes class 0's): a fixed grid striding over the
+// two lists, no counters.
+__global__ void __launch_bounds__(64) k_values_deep(ValuesArgs a, const int32_t* class_count,
+                                                    const int32_t* class_list, int32_t stride) {
+  __shared__ float xl_all[MAX_D * 256];
+  const int32_t c1 = class_count[1], c2 = class_count[2];
+  for (int32_t item = blockIdx.x; item < c1 + c2; item += gridDim.x) {
+    const int32_t p = item < c1 ? class_list[stride + item] : class_list[2 * int64_t(stride) + (item - c1)];
+    values_program(a, p, 0, xl_all);
+    __builtin_amdgcn_wave_barrier();
+  }
 }
 
 // Correlation shifts of every program of the table (one wave per program).
@@ -878,9 +901,12 @@ static size_t resident_bytes(const EvalArgs& a, int K) {
 // to give every SIMD several waves, and inputs within RESIDENT_MAX_BYTES at
 // the wider tile's padding: the choice never depends on the tile width, so
 // the tuner's pick cannot switch kernels (and summation orders).
-static bool resident_eligible(const EvalArgs& a) {
-  return a.n_chunks == 1 && a.n_total >= RESIDENT_MIN_PROGRAMS && resident_bytes(a, 8) <= RESIDENT_MAX_BYTES;
+bool resident_eligible(int64_t M, int32_t D, int32_t n_chunks, int32_t n_total) {
+  const size_t b8 = size_t((M + 511) / 512) * size_t(D) * 512u * sizeof(float);
+  return n_chunks == 1 && n_total >= RESIDENT_MIN_PROGRAMS && b8 <= RESIDENT_MAX_BYTES;
 }
+
+static bool resident_eligible(const EvalArgs& a) { return resident_eligible(a.M, a.D, a.n_chunks, a.n_total); }
 
 template <int KIND, int K>
 static hipError_t launch_resident(const EvalArgs& a, size_t lds, hipStream_t s) {

@@ -34,6 +34,9 @@ struct PrepareArgs {
   int32_t* len_count;    // [5] adjoint lists (see k_prepare)
   int32_t* len_list;     // [5][n_programs]
   int32_t short_words;
+  // nonzero: also write the adjoint's per-word operands (aux) and its
+  // program lists (an evaluation without gradients needs neither)
+  int32_t adjoint;
 };
 
 struct StageArgs {
@@ -74,6 +77,10 @@ struct EvalArgs {
   int32_t n_total;                  // programs in the whole population
   int32_t prog_begin;               // first program of this launch (slice-local index 0)
   double smax = 0.0;                // the paper's scores: maximum score S
+  // correlation and Eq. 2: when set, the resident-inputs kernel takes each
+  // class-0 program's shift from its own first pass and stores it here (the
+  // same array as meta); the shift pass then covers classes 1 and 2 only
+  ProgMeta* meta_shift = nullptr;
 };
 
 struct FinalizeArgs {
@@ -169,6 +176,9 @@ constexpr int32_t RESIDENT_MIN_PROGRAMS = 4096;
 constexpr int RESIDENT_BATCH = 16;  // programs a wave claims per atomic
 __host__ __device__ constexpr int class_k(int c, int kv) { return c == 0 ? (kv == 0 ? 8 : 4) : (c == 1 ? 4 : 2); }
 
+// NARROW: scratch for programs of at most 64 tokens in LDS (longer ones use
+// the global scratch), for populations of short programs
+template <bool NARROW>
 __global__ void k_prepare(PrepareArgs a);
 __global__ void k_stage_cases(StageArgs a);
 __global__ void k_prepare_batch(BatchArgs b);
@@ -180,6 +190,12 @@ __global__ void k_finalize_batch(BatchArgs b);
 __global__ void k_target_stats(const float* __restrict__ y, int64_t M, double* __restrict__ stats);
 __global__ void k_finalize(FinalizeArgs a);
 __global__ void k_values(ValuesArgs a);
+// correlation shifts of the programs of register-need classes 1 and 2 (a
+// persistent grid walking their class lists)
+__global__ void k_values_deep(ValuesArgs a, const int32_t* class_count, const int32_t* class_list, int32_t stride);
+// whether an evaluation of this shape takes the resident-inputs kernel for
+// class 0 (one chunk, enough programs, inputs within RESIDENT_MAX_BYTES)
+bool resident_eligible(int64_t M, int32_t D, int32_t n_chunks, int32_t n_total);
 
 // host launchers of the templated evaluation kernels (eval.hip)
 // ev0/ev1 (may be null) are recorded on `s` right before and after the

@@ -1,5 +1,7 @@
 // Program preparation (validation, Sethi-Ullman re-serialisation, decoding)
 // and fitness-case staging.
+#include <type_traits>
+
 #include "beagle_device.h"
 #include "grad.h"
 #include "kernels.h"
@@ -260,7 +262,7 @@ __device__ static ListIds prepare_program(const PrepareArgs& a, int p, ST tok, S
         else
           n_ent += ent;
         wfirst.set(out, wfst | (wcf ? 0x8000 : 0));
-        aux[out] = pa | (rws << 16) | (rid << 24);
+        if (a.adjoint) aux[out] = pa | (rws << 16) | (rid << 24);
         ++out;
       }
       // nmax == need_root by construction; the larger one is kept defensively
@@ -294,7 +296,7 @@ __device__ static ListIds prepare_program(const PrepareArgs& a, int p, ST tok, S
                    : n_ent <= GRAD_DTAPE_MID   ? 3
                    : n_ent <= GRAD_DTAPE_LARGE ? 4
                                                : 0;
-    if (lc >= 2) dtape_words(a.code + off, a.aux + off, L_dec, need, stack);
+    if (a.adjoint && lc >= 2) dtape_words(a.code + off, a.aux + off, L_dec, need, stack);
     ids.lc = lc;
   }
   return ids;
@@ -325,6 +327,7 @@ __device__ static void append_one(const PrepareArgs& a, int p, ListIds ids) {
   if (ids.cls < 0) return;
   const int slot = atomicAdd(a.class_count + ids.cls, 1);
   a.class_list[int64_t(ids.cls) * a.n_programs + slot] = p;
+  if (!a.adjoint) return;
   const int ls = atomicAdd(a.len_count + ids.lc, 1);
   a.len_list[int64_t(ids.lc) * a.n_programs + ls] = p;
 }
@@ -336,6 +339,8 @@ constexpr int PREP_BLOCK = 64;
 constexpr int PREP_SHORT = 128;
 
 struct PrepLds {
+  static constexpr int SHORT = PREP_SHORT;
+  using Index = Scratch<uint16_t, PREP_BLOCK>;
   uint16_t tok[PREP_SHORT * PREP_BLOCK];
   uint16_t stack[PREP_SHORT * PREP_BLOCK];
   uint16_t start[PREP_SHORT * PREP_BLOCK];
@@ -343,11 +348,40 @@ struct PrepLds {
   uint16_t ord[PREP_SHORT * PREP_BLOCK];
 };
 
-__device__ static ListIds prepare_one(const PrepareArgs& a, int p, PrepLds& lds) {
+// 8-bit index scratch for programs of at most PREP_NARROW tokens: every value
+// the passes store is an index or count below 128, or such an index with the
+// constant-free flag (bit 15), which is kept in bit 7 here.
+template <int STRIDE>
+struct Scratch8 {
+  uint8_t* p;
+  __device__ __forceinline__ int get(int i) const {
+    const int b = p[i * STRIDE];
+    return (b & 0x7F) | ((b & 0x80) << 8);
+  }
+  __device__ __forceinline__ void set(int i, int v) const { p[i * STRIDE] = uint8_t((v & 0x7F) | ((v >> 8) & 0x80)); }
+};
+
+// The scratch of populations of short programs: 28 KB per workgroup instead
+// of 80 KB, so five workgroups share a compute unit instead of two (the
+// passes are latency-bound; longer programs take the global scratch).
+constexpr int PREP_NARROW = 64;
+struct PrepLdsNarrow {
+  static constexpr int SHORT = PREP_NARROW;
+  using Index = Scratch8<PREP_BLOCK>;
+  uint16_t tok[PREP_NARROW * PREP_BLOCK];
+  uint8_t stack[PREP_NARROW * PREP_BLOCK];
+  uint8_t start[PREP_NARROW * PREP_BLOCK];
+  uint8_t need[PREP_NARROW * PREP_BLOCK];
+  uint16_t ord[PREP_NARROW * PREP_BLOCK];
+};
+
+template <class LDS>
+__device__ static ListIds prepare_one(const PrepareArgs& a, int p, LDS& lds) {
   const int64_t off = a.tok_offset[p];
   const int32_t L = a.tok_len[p];
-  if (L >= 1 && L <= PREP_SHORT && off >= 0 && off + L <= a.n_tokens) {
+  if (L >= 1 && L <= LDS::SHORT && off >= 0 && off + L <= a.n_tokens) {
     using SL = Scratch<uint16_t, PREP_BLOCK>;
+    using SI = typename LDS::Index;
     const int t = threadIdx.x;
     // the tokens first, eight independent loads at a time
     const uint16_t* src = a.tokens + off;
@@ -361,7 +395,7 @@ __device__ static ListIds prepare_one(const PrepareArgs& a, int p, PrepLds& lds)
       for (int j = 0; j < 8; ++j) dst[(i + j) * PREP_BLOCK] = v[j];
     }
     for (; i < L; ++i) dst[i * PREP_BLOCK] = src[i];
-    return prepare_program(a, p, SL{lds.tok + t}, SL{lds.stack + t}, SL{lds.start + t}, SL{lds.need + t},
+    return prepare_program(a, p, SL{lds.tok + t}, SI{lds.stack + t}, SI{lds.start + t}, SI{lds.need + t},
                            SL{lds.ord + t});
   } else {
     // (an invalid layout is reported before any scratch access)
@@ -372,15 +406,16 @@ __device__ static ListIds prepare_one(const PrepareArgs& a, int p, PrepLds& lds)
   }
 }
 
+template <bool NARROW>
 __global__ void __launch_bounds__(PREP_BLOCK) k_prepare(PrepareArgs a) {
-  __shared__ PrepLds lds;
+  __shared__ typename std::conditional<NARROW, PrepLdsNarrow, PrepLds>::type lds;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   ListIds ids;
   if (p < a.n_programs) ids = prepare_one(a, p, lds);
   // list appends aggregated per wave (per-program atomics on a handful of
   // counters serialise when the population is large)
   wave_append<N_CLASSES>(ids.cls, p, a.class_count, a.class_list, a.n_programs);
-  wave_append<GRAD_LISTS>(ids.lc, p, a.len_count, a.len_list, a.n_programs);
+  if (a.adjoint) wave_append<GRAD_LISTS>(ids.lc, p, a.len_count, a.len_list, a.n_programs);
 }
 
 // One thread per program of every problem of the table.
@@ -393,6 +428,9 @@ __global__ void __launch_bounds__(PREP_BLOCK) k_prepare_batch(BatchArgs b) {
   const int p = int(g - b.table[q].prog_begin);
   append_one(a, p, prepare_one(a, p, lds));
 }
+
+template __global__ void k_prepare<false>(PrepareArgs);
+template __global__ void k_prepare<true>(PrepareArgs);
 
 // X [M x D] row-major -> Xt [D x Mp] (case index fastest), y -> yp [Mp];
 // cases M..Mp-1 repeat case 0 (their outputs are masked out of every sum).

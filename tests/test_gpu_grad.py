@@ -315,3 +315,33 @@ def test_autograd_function_and_adam():
     ok = np.isfinite(before) & np.isfinite(after) & (before < 1.0)
     assert np.mean(after[ok] <= before[ok] + 1e-12) > 0.6
     assert np.median(after[ok] - before[ok]) <= 0.0
+
+
+def test_decoder_variants_agree():
+    """The narrow-scratch decoder (populations of short programs) and the
+    wide one write the same words: the same 300 programs, alone (mean length
+    ~33: narrow) and followed by 60 programs of 200 tokens (mean > 40: wide),
+    give bit-identical fitness, status and constant gradients (M = 3000: one
+    chunk, no resident kernel, so no program's result depends on the
+    others)."""
+    api = _api()
+    rng = np.random.default_rng(77)
+    progs = []
+    for _ in range(300):
+        t, _ = wl.random_program(rng, int(rng.integers(3, 65)), 3, allow_const=False)
+        progs.append(wl.place_constants(rng, t, int(rng.integers(0, 5))))
+    longs = [wl.random_program(rng, 200, 3) for _ in range(60)]
+    data = wl.make_dataset(78, 3000, 3, x_range=(1.0, 5.0), target_len=8)
+    X = torch.from_numpy(data.X).cuda()
+    y = torch.from_numpy(data.y).cuda()
+    short = wl.pack_programs(progs)
+    both = wl.pack_programs(progs + longs)
+    assert short.tokens.size <= 40 * short.n and both.tokens.size > 40 * both.n
+    for kind in ("mse", "corr"):
+        f1, g1, s1 = api.evaluate_grad(api.DevicePrograms.from_programset(short), X, y, kind, with_status=True)
+        f2, g2, s2 = api.evaluate_grad(api.DevicePrograms.from_programset(both), X, y, kind, with_status=True)
+        torch.cuda.synchronize()
+        n_c = int(short.consts.size)
+        assert np.array_equal(s1.cpu().numpy(), s2.cpu().numpy()[:300])
+        assert np.array_equal(f1.cpu().numpy().view(np.uint64), f2.cpu().numpy()[:300].view(np.uint64)), kind
+        assert np.array_equal(g1.cpu().numpy().view(np.uint32), g2.cpu().numpy()[:n_c].view(np.uint32)), kind
