@@ -71,6 +71,19 @@ __device__ __noinline__ float const_value(uint32_t u, float lo, float hi) {
   return float(double(lo) + prod);
 }
 
+// Zeroes elements [from, to) of a child slot: element stores up to the first
+// 16-byte boundary, then 16-byte stores, then the tail (one thread writes a
+// whole slot, so element-wide stores would each touch another cache line
+// across the wave).
+template <class T>
+__device__ __forceinline__ void zero_fill(T* base, int from, int to) {
+  constexpr int PER = 16 / int(sizeof(T));
+  int i = from;
+  while (i < to && (reinterpret_cast<uintptr_t>(base + i) & 15u) != 0) base[i++] = T(0);
+  for (; i + PER <= to; i += PER) *reinterpret_cast<uint4*>(base + i) = make_uint4(0u, 0u, 0u, 0u);
+  for (; i < to; ++i) base[i] = T(0);
+}
+
 // opcode of unary index u (0..4: SIN..SQRT, 5..11: SQUARE..TANH)
 __device__ __forceinline__ uint32_t unary_opcode(uint32_t u) { return u < 5u ? OP_SIN + u : OP_SQUARE + (u - 5u); }
 
@@ -219,8 +232,8 @@ __global__ void k_generation(GenStepArgs a) {
   } else {
     w.copy(A, Ac, ca, 0, LA);
   }
-  for (int i = w.len; i < a.max_len; ++i) out[i] = 0;
-  for (int i = w.ncst; i < a.max_consts; ++i) outc[i] = 0.0f;
+  zero_fill(out, w.len, a.max_len);
+  zero_fill(outc, w.ncst, a.max_consts);
   a.child_len[c] = w.len;
   a.child_const_count[c] = w.ncst;
 }
@@ -378,8 +391,8 @@ __global__ void k_init_population(InitArgs a) {
     if (sp == 0) break;
     level = fr[sp - 1].level + 1;
   }
-  for (int i = len; i < a.max_len; ++i) out[i] = 0;
-  for (int i = ncst; i < a.max_consts; ++i) outc[i] = 0.0f;
+  zero_fill(out, len, a.max_len);
+  zero_fill(outc, ncst, a.max_consts);
   a.len[c] = len;
   a.const_count[c] = ncst;
 }
