@@ -82,6 +82,8 @@ SIGNATURES = [
 
 _lib = None
 HEADER = os.path.join(os.path.dirname(HERE), "include", "beagle.h")
+# the layout of the structures above (beagle_gen_params grew op_set in 2)
+ABI_VERSION = 2
 
 
 def load():
@@ -99,6 +101,9 @@ def load():
             raise ImportError(f"{LIB_PATH} does not export {name}: rebuild it")
         fn.restype = res
         fn.argtypes = args
+    if lib.beagle_abi_version() != ABI_VERSION:
+        raise ImportError(f"{LIB_PATH} has ABI version {lib.beagle_abi_version()}, these bindings {ABI_VERSION}: "
+                          "rebuild it")
     _lib = lib
     return lib
 

@@ -34,7 +34,7 @@ def test_binding_covers_the_header():
 def test_abi_version_matches_header(lib):
     with open(_lib.HEADER) as f:
         m = re.search(r"#define BEAGLE_ABI_VERSION (\d+)", f.read())
-    assert lib.beagle_abi_version() == int(m.group(1))
+    assert lib.beagle_abi_version() == int(m.group(1)) == _lib.ABI_VERSION
 
 
 def test_constants_match_header():
