@@ -869,7 +869,7 @@ beagle_status beagle_eval_grad(beagle_ctx* ctx, const beagle_programs* progs, co
   fa.kind = kind;
   fa.fitness = fitness;
   fa.grad = grad_consts;
-  hipLaunchKernelGGL(bgl::k_grad_finalize, dim3((progs->n_programs + 255) / 256), dim3(256), 0, s, fa);
+  hipLaunchKernelGGL(bgl::k_grad_finalize, dim3(progs->n_programs), dim3(64), 0, s, fa);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "gradient finalize launch");
   clear_error();

@@ -928,25 +928,30 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LIST ==
 }
 #undef BGL_K
 
-__global__ void k_grad_finalize(GradFinalizeArgs a) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= a.n_programs) return;
+// One wave per program: lane 0 sums the fitness partials, lane j the
+// gradient partials of constant slot j (and j + 64, ...), each over the
+// chunks in chunk order.
+__global__ void __launch_bounds__(64) k_grad_finalize(GradFinalizeArgs a) {
+  const int p = blockIdx.x;
+  const int lane = threadIdx.x;
   const ProgMeta m = a.meta[p];
   const double nan = __longlong_as_double(0x7FF8000000000000LL);
   const int64_t coff = a.const_offset[p];
   const int cc = a.const_count[p];
   if (m.status != BEAGLE_PROG_OK) {
-    if (a.kind == BEAGLE_FIT_MSE) a.fitness[p] = nan;
-    for (int j = 0; j < cc; ++j) a.grad[coff + j] = __int_as_float(0x7FC00000);
+    if (a.kind == BEAGLE_FIT_MSE && lane == 0) a.fitness[p] = nan;
+    for (int j = lane; j < cc; j += 64) a.grad[coff + j] = __int_as_float(0x7FC00000);
     return;
   }
-  if (a.kind == BEAGLE_FIT_MSE) {
+  if (a.kind == BEAGLE_FIT_MSE && lane == 0) {
     double s = 0.0;
+#pragma unroll 8
     for (int c = 0; c < a.n_chunks; ++c) s += a.part[int64_t(c) * a.n_programs + p];
     a.fitness[p] = s / double(a.M);
   }
-  for (int j = 0; j < cc; ++j) {
+  for (int j = lane; j < cc; j += 64) {
     double g = 0.0;
+#pragma unroll 8
     for (int c = 0; c < a.n_chunks; ++c) g += a.gpart[int64_t(c) * a.n_consts + coff + j];
     a.grad[coff + j] = float(g);
   }
