@@ -368,7 +368,7 @@ def main():
                     help="generations of the paper's own loop at its population schedule (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (one process, one device)",
+        print("bench.py measures one GPU: the library has no multi-GPU path (one process, one device)",
               file=sys.stderr)
         sys.exit(2)
 

@@ -2,8 +2,8 @@
 
 Classification gate: the GPU fitness class (finite / +inf / nan) equals the
 class the fp32-emulating oracle (O32e) gives; an fp32 evaluation can
-overflow where binary64 does not, so the binary64 oracle is not the judge of
-classes.
+overflow where binary64 does not, so the classes come from O32e, not from
+the binary64 oracle.
 
 Value gate: |F_gpu - F_O64| <= 1e-5 |F_O64| + atol for every program that is
 finite in both and well conditioned: its fitness moves by at most
