@@ -114,7 +114,8 @@ using namespace bgl::host;
 
 // The pieces of workspace one evaluation uses.
 struct EvalLayout {
-  size_t code, aux, cval, s_stack, s_start, s_need, meta, class_count, class_list, len_list, work, Xt, yp, stats, part,
+  size_t code, aux, cval, s_stack, s_start, s_need, meta, class_count, class_list, len_list, long_list, work, Xt, yp,
+      stats, part,
       gpart, coef, total;
   int64_t Mp, chunk, gchunk;      // case chunks of the evaluation and of the adjoint
   int32_t n_chunks, gn_chunks, slice;
@@ -136,6 +137,7 @@ EvalLayout eval_layout(const beagle_programs* P, const beagle_dataset* d, int n_
   L.class_count = c.take<int32_t>(64);  // [0..2] need classes, [8..9] length classes
   L.class_list = c.take<int32_t>(size_t(bgl::N_CLASSES) * N);
   L.len_list = c.take<int32_t>(size_t(bgl::GRAD_LISTS) * N);
+  L.long_list = c.take<int32_t>(size_t(N));
   L.work = c.take<unsigned long long>(8);  // evaluation: one per class; adjoint: one per list
   L.Mp = round_up(d->M, bgl::CASES_PER_BLOCK_ITER);
   L.Xt = c.take<float>(size_t(d->D) * L.Mp);
@@ -189,13 +191,11 @@ beagle_status prepare(beagle_ctx* ctx, const beagle_programs* P, const beagle_da
   pa.len_list = reinterpret_cast<int32_t*>(ws + L.len_list);
   pa.short_words = bgl::GRAD_SHORT_WORDS;
   pa.adjoint = adjoint ? 1 : 0;
-  // the narrow-scratch decoder when programs are short on average (both
-  // variants write the same words; a longer program takes the global scratch)
-  const bool narrow = P->n_tokens <= 40 * int64_t(P->n_programs);
-  if (narrow)
-    hipLaunchKernelGGL(bgl::k_prepare<true>, dim3((P->n_programs + 63) / 64), dim3(64), 0, s, pa);
-  else
-    hipLaunchKernelGGL(bgl::k_prepare<false>, dim3((P->n_programs + 63) / 64), dim3(64), 0, s, pa);
+  pa.long_count = reinterpret_cast<int32_t*>(ws + L.class_count) + 16;
+  pa.long_list = reinterpret_cast<int32_t*>(ws + L.long_list);
+  // programs of at most 64 tokens, then the ones longer than that
+  hipLaunchKernelGGL(bgl::k_prepare, dim3((P->n_programs + 63) / 64), dim3(64), 0, s, pa);
+  hipLaunchKernelGGL(bgl::k_prepare_long, dim3(512), dim3(64), 0, s, pa);
   bgl::StageArgs sa;
   sa.X = d->X;
   sa.y = d->y;

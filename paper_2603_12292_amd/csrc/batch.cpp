@@ -199,6 +199,8 @@ beagle_status beagle_eval_batched(beagle_ctx* ctx, const beagle_programs* progs,
     pa.len_list = reinterpret_cast<int32_t*>(ws + o.len_list);
     pa.short_words = bgl::GRAD_SHORT_WORDS;
     pa.adjoint = 0;
+    pa.long_count = nullptr;  // k_prepare_batch decodes every program itself
+    pa.long_list = nullptr;
     t.X = d.X;
     t.y = d.y;
     t.Xt = reinterpret_cast<float*>(ws + o.Xt);

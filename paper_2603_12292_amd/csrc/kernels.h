@@ -37,6 +37,9 @@ struct PrepareArgs {
   // nonzero: also write the adjoint's per-word operands (aux) and its
   // program lists (an evaluation without gradients needs neither)
   int32_t adjoint;
+  // programs k_prepare leaves to k_prepare_long (count zero at launch)
+  int32_t* long_count;
+  int32_t* long_list;  // [n_programs]
 };
 
 struct StageArgs {
@@ -176,10 +179,10 @@ constexpr int32_t RESIDENT_MIN_PROGRAMS = 4096;
 constexpr int RESIDENT_BATCH = 16;  // programs a wave claims per atomic
 __host__ __device__ constexpr int class_k(int c, int kv) { return c == 0 ? (kv == 0 ? 8 : 4) : (c == 1 ? 4 : 2); }
 
-// NARROW: scratch for programs of at most 64 tokens in LDS (longer ones use
-// the global scratch), for populations of short programs
-template <bool NARROW>
+// decoding: programs of at most 64 tokens in k_prepare (narrow LDS
+// scratch), the longer ones it lists in k_prepare_long
 __global__ void k_prepare(PrepareArgs a);
+__global__ void k_prepare_long(PrepareArgs a);
 __global__ void k_stage_cases(StageArgs a);
 __global__ void k_prepare_batch(BatchArgs b);
 __global__ void k_stage_batch(BatchArgs b);

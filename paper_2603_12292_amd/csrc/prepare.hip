@@ -361,9 +361,9 @@ struct Scratch8 {
   __device__ __forceinline__ void set(int i, int v) const { p[i * STRIDE] = uint8_t((v & 0x7F) | ((v >> 8) & 0x80)); }
 };
 
-// The scratch of populations of short programs: 28 KB per workgroup instead
-// of 80 KB, so five workgroups share a compute unit instead of two (the
-// passes are latency-bound; longer programs take the global scratch).
+// The scratch of the first decoding pass: 28 KB per workgroup instead of
+// 80 KB, so five workgroups share a compute unit instead of two (the passes
+// are latency-bound); longer programs go to k_prepare_long.
 constexpr int PREP_NARROW = 64;
 struct PrepLdsNarrow {
   static constexpr int SHORT = PREP_NARROW;
@@ -406,16 +406,42 @@ __device__ static ListIds prepare_one(const PrepareArgs& a, int p, LDS& lds) {
   }
 }
 
-template <bool NARROW>
+// One thread per program, with the narrow LDS scratch; a program longer than
+// PREP_NARROW tokens is not decoded here but appended to the long list for
+// k_prepare_long (list order does not affect any result).
 __global__ void __launch_bounds__(PREP_BLOCK) k_prepare(PrepareArgs a) {
-  __shared__ typename std::conditional<NARROW, PrepLdsNarrow, PrepLds>::type lds;
+  __shared__ PrepLdsNarrow lds;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   ListIds ids;
-  if (p < a.n_programs) ids = prepare_one(a, p, lds);
+  bool defer = false;
+  if (p < a.n_programs) {
+    defer = a.tok_len[p] > PREP_NARROW;
+    if (!defer) ids = prepare_one(a, p, lds);
+  }
   // list appends aggregated per wave (per-program atomics on a handful of
   // counters serialise when the population is large)
+  wave_append<1>(defer ? 0 : -1, p, a.long_count, a.long_list, 0);
   wave_append<N_CLASSES>(ids.cls, p, a.class_count, a.class_list, a.n_programs);
   if (a.adjoint) wave_append<GRAD_LISTS>(ids.lc, p, a.len_count, a.len_list, a.n_programs);
+}
+
+// The programs k_prepare deferred: a fixed grid striding over the long list
+// with the wide LDS scratch (programs above PREP_SHORT tokens use the global
+// scratch).  Exits at once when the list is empty.
+__global__ void __launch_bounds__(PREP_BLOCK) k_prepare_long(PrepareArgs a) {
+  __shared__ PrepLds lds;
+  const int32_t n = *a.long_count;
+  for (int32_t base = blockIdx.x * PREP_BLOCK; base < n; base += gridDim.x * PREP_BLOCK) {
+    const int32_t item = base + int32_t(threadIdx.x);
+    ListIds ids;
+    int p = 0;
+    if (item < n) {
+      p = a.long_list[item];
+      ids = prepare_one(a, p, lds);
+    }
+    wave_append<N_CLASSES>(ids.cls, p, a.class_count, a.class_list, a.n_programs);
+    if (a.adjoint) wave_append<GRAD_LISTS>(ids.lc, p, a.len_count, a.len_list, a.n_programs);
+  }
 }
 
 // One thread per program of every problem of the table.
@@ -428,9 +454,6 @@ __global__ void __launch_bounds__(PREP_BLOCK) k_prepare_batch(BatchArgs b) {
   const int p = int(g - b.table[q].prog_begin);
   append_one(a, p, prepare_one(a, p, lds));
 }
-
-template __global__ void k_prepare<false>(PrepareArgs);
-template __global__ void k_prepare<true>(PrepareArgs);
 
 // X [M x D] row-major -> Xt [D x Mp] (case index fastest), y -> yp [Mp];
 // cases M..Mp-1 repeat case 0 (their outputs are masked out of every sum).

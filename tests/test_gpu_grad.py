@@ -317,31 +317,37 @@ def test_autograd_function_and_adam():
     assert np.median(after[ok] - before[ok]) <= 0.0
 
 
-def test_decoder_variants_agree():
-    """The narrow-scratch decoder (populations of short programs) and the
-    wide one write the same words: the same 300 programs, alone (mean length
-    ~33: narrow) and followed by 60 programs of 200 tokens (mean > 40: wide),
-    give bit-identical fitness, status and constant gradients (M = 3000: one
-    chunk, no resident kernel, so no program's result depends on the
-    others)."""
+def test_decoder_passes_agree():
+    """Programs of at most 64 tokens are decoded by the first pass (narrow
+    LDS scratch), longer ones by the second (wide LDS scratch up to 128
+    tokens, global scratch beyond).  The same 390 programs mixing all three
+    lengths, grouped by length and shuffled, give bit-identical fitness,
+    status and constant gradients per program (same population size, hence
+    the same case chunks; each program's result is independent of its
+    position and of the list order of both passes)."""
     api = _api()
     rng = np.random.default_rng(77)
-    progs = []
-    for _ in range(300):
-        t, _ = wl.random_program(rng, int(rng.integers(3, 65)), 3, allow_const=False)
-        progs.append(wl.place_constants(rng, t, int(rng.integers(0, 5))))
-    longs = [wl.random_program(rng, 200, 3) for _ in range(60)]
+    flat = []
+    for lo, hi, n in ((3, 64, 300), (65, 128, 60), (129, 300, 30)):
+        for _ in range(n):
+            t, _ = wl.random_program(rng, int(rng.integers(lo, hi + 1)), 3, allow_const=False)
+            flat.append(wl.place_constants(rng, t, int(rng.integers(0, 5))))
+    order = rng.permutation(len(flat))
+    grouped = wl.pack_programs(flat)
+    mixed = wl.pack_programs([flat[i] for i in order])
     data = wl.make_dataset(78, 3000, 3, x_range=(1.0, 5.0), target_len=8)
     X = torch.from_numpy(data.X).cuda()
     y = torch.from_numpy(data.y).cuda()
-    short = wl.pack_programs(progs)
-    both = wl.pack_programs(progs + longs)
-    assert short.tokens.size <= 40 * short.n and both.tokens.size > 40 * both.n
     for kind in ("mse", "corr"):
-        f1, g1, s1 = api.evaluate_grad(api.DevicePrograms.from_programset(short), X, y, kind, with_status=True)
-        f2, g2, s2 = api.evaluate_grad(api.DevicePrograms.from_programset(both), X, y, kind, with_status=True)
-        torch.cuda.synchronize()
-        n_c = int(short.consts.size)
-        assert np.array_equal(s1.cpu().numpy(), s2.cpu().numpy()[:300])
-        assert np.array_equal(f1.cpu().numpy().view(np.uint64), f2.cpu().numpy()[:300].view(np.uint64)), kind
-        assert np.array_equal(g1.cpu().numpy().view(np.uint32), g2.cpu().numpy()[:n_c].view(np.uint32)), kind
+        out = []
+        for ps in (grouped, mixed):
+            f, g, st = api.evaluate_grad(api.DevicePrograms.from_programset(ps), X, y, kind, with_status=True)
+            out.append((f.cpu().numpy(), g.cpu().numpy(), st.cpu().numpy()))
+        (f1, g1, s1), (fm, gm, sm) = out
+        assert (s1 == 0).sum() > 350
+        for k, i in enumerate(order):
+            assert fm[k].view(np.uint64) == f1[i].view(np.uint64), (kind, k, i)
+            assert sm[k] == s1[i]
+            o, cc = int(mixed.const_offset[k]), int(mixed.const_count[k])
+            o1 = int(grouped.const_offset[i])
+            assert np.array_equal(gm[o:o + cc].view(np.uint32), g1[o1:o1 + cc].view(np.uint32)), (kind, k, i)
