@@ -169,6 +169,34 @@ __device__ __forceinline__ float op_ext(float x) {
   return 0.0f;
 }
 
+// One DPP move of a binary64 value (both halves, the same lane pattern);
+// lanes whose source is outside the row, and rows outside ROW_MASK, get 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_move(double v) {
+  const uint64_t b = uint64_t(__double_as_longlong(v));
+  const uint32_t lo = uint32_t(__builtin_amdgcn_update_dpp(0, int(uint32_t(b)), CTRL, ROW_MASK, 0xF, true));
+  const uint32_t hi = uint32_t(__builtin_amdgcn_update_dpp(0, int(uint32_t(b >> 32)), CTRL, ROW_MASK, 0xF, true));
+  return __longlong_as_double((long long)((uint64_t(hi) << 32) | lo));
+}
+
+// Sum of a binary64 value over the 64 lanes, returned in every lane (all
+// lanes active).  Row shifts by 1, 2, 4 and 8 leave each row's sum in its
+// lane 15; broadcasting lane 15 into rows 1 and 3, then lane 31 into rows 2
+// and 3, leaves the total in lane 63.  All register-to-register (the
+// butterfly of lane shuffles it replaces went through the LDS crossbar).
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_move<0x111, 0xF>(v);  // row_shr:1
+  v += dpp_move<0x112, 0xF>(v);  // row_shr:2
+  v += dpp_move<0x114, 0xF>(v);  // row_shr:4
+  v += dpp_move<0x118, 0xF>(v);  // row_shr:8
+  v += dpp_move<0x142, 0xA>(v);  // row_bcast:15
+  v += dpp_move<0x143, 0xC>(v);  // row_bcast:31
+  const uint64_t b = uint64_t(__double_as_longlong(v));
+  const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(b), 63);
+  const uint32_t hi = __builtin_amdgcn_readlane(uint32_t(b >> 32), 63);
+  return __longlong_as_double((long long)((uint64_t(hi) << 32) | lo));
+}
+
 // Per-program metadata written by the preparation kernel.
 struct ProgMeta {
   int32_t status;  // BEAGLE_PROG_* code

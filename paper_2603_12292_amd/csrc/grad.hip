@@ -104,11 +104,7 @@ __device__ __forceinline__ float opaque(float x) {
   return x;
 }
 
-__device__ __forceinline__ double wave_sum_d(double v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-  return v;
-}
+__device__ __forceinline__ double wave_sum_d(double v) { return wave_sum(v); }
 
 // dF/dyhat of one case: MSE 2 (yhat - y) / M (the binary64 difference
 // rounded, then scaled); CORR alpha (y - ycen) + beta (yhat - mu) in
