@@ -197,9 +197,10 @@ def paper_pop_size(g: int) -> int:
     raise AssertionError
 
 
-def paper_loop_bench(generations: int):
+def paper_loop_bench(generations: int, op_set: int = 0):
     """The paper's evolutionary loop at its own sizes: ramped half-and-half
-    initial population (depths 2..6, max length 64), correlation fitness
+    initial population (depths 2..5, max length 64) over the 9 base
+    operators (op_set 0) or the paper's 16 (op_set 1), correlation fitness
     (1 - r^2) on 512 cases (D = 5), microcosm selection (sample 100, keep
     0.5) and mutation-only variation, the population following the paper's
     correlation schedule; everything on the GPU, one stream.  Reports the
@@ -212,7 +213,7 @@ def paper_loop_bench(generations: int):
     X = torch.from_numpy(data.X).cuda()
     y = torch.from_numpy(data.y).cuda()
     params = api.GenParams(tournament=1, p_crossover=0.0, p_mutation=1.0, max_len=64, max_consts=8,
-                           init_depth_min=2, init_depth_max=5)
+                           init_depth_min=2, init_depth_max=5, op_set=op_set)
     D, seed = data.D, 2612
     ctx = api.context(0)
     init = api.init_population(paper_pop_size(0), D, params, seed, ctx=ctx)
@@ -258,9 +259,10 @@ def paper_loop_bench(generations: int):
                      "select_vary_ms": round(ph["select_vary_ms"] / k, 3),
                      "generation_ms": round((ph["eval_ms"] + ph["select_vary_ms"]) / k, 3),
                      "eval_gpops": round(ph["node_cases"] / (ph["eval_ms"] / 1e3) / 1e9, 2)})
+    ops = "the paper's 16 operators" if op_set == 1 else "the 9 base operators"
     return {"workload": f"paper loop: correlation fitness, M={data.M}, D={D}, ramped half-and-half depths 2..5 "
-                        f"(max length 64), microcosm selection (sample 100, keep 0.5), mutation only, population "
-                        f"5M/3M/1M/500k/250k at generations 0/5/10/15/20",
+                        f"(max length 64), {ops}, microcosm selection (sample 100, keep 0.5), mutation only, "
+                        f"population 5M/3M/1M/500k/250k at generations 0/5/10/15/20",
             "generations": generations, "wall_s": round(wall, 3), "phases": rows,
             "mean_len_first": round(tokens[0] / paper_pop_size(0), 2),
             "mean_len_last": round(tokens[-1] / paper_pop_size(generations - 1), 2)}
@@ -450,6 +452,7 @@ def main():
         out["generation_loop"] = generation_bench(args.generations)
     if args.paper_loop > 0:
         out["paper_loop"] = paper_loop_bench(args.paper_loop)
+        out["paper_loop_16_ops"] = paper_loop_bench(args.paper_loop, op_set=1)
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

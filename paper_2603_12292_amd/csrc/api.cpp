@@ -234,9 +234,9 @@ beagle_status launch_values(beagle_ctx* ctx, const beagle_programs* P, const bea
 }
 
 // The correlation shifts before an evaluation (correlation fitness and the
-// Eq. 2 score).  When the shape takes the resident-inputs kernel, class 0's
-// shifts come from that kernel's first pass (*in_kernel = true) and only the
-// class-1 and class-2 programs run the shift pass here.
+// Eq. 2 score).  When the shape takes the resident-inputs kernels, the
+// shifts of classes 0 and 1 come from those kernels' first pass
+// (*in_kernel = true) and only the class-2 programs run the shift pass here.
 beagle_status launch_shifts(beagle_ctx* ctx, const beagle_programs* P, const beagle_dataset* d, const EvalLayout& L,
                             hipStream_t s, bool* in_kernel) {
   *in_kernel = bgl::resident_eligible(d->M, d->D, L.n_chunks, P->n_programs);

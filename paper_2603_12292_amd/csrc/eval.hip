@@ -515,7 +515,7 @@ k_eval_class(EvalArgs a) {
 // is padding beyond the last pass and no workgroup barrier is taken per
 // program.  A lane adds its cases in the order it would with either tile
 // width, so the width changes no result bit here either.
-template <int KIND, int K>
+template <int KIND, int K, int CLS>
 __device__ __forceinline__ void eval_wave_resident(const EvalArgs& a, int p, const float* xres, int passes) {
   constexpr int K64 = K * 64;
   const ProgMeta m = a.meta[p];
@@ -545,7 +545,10 @@ __device__ __forceinline__ void eval_wave_resident(const EvalArgs& a, int p, con
       yk[4 * g + 3] = q.w;
     }
     float top[K];
-    interpret_small<K>(vc0, vv0, vc1, vv1, code, cval, L, lane, xres + ps * (a.D * K64) + 4 * lane, top);
+    if constexpr (CLS == 0)
+      interpret_small<K>(vc0, vv0, vc1, vv1, code, cval, L, lane, xres + ps * (a.D * K64) + 4 * lane, top);
+    else
+      interpret<K, class_stack(CLS)>(vc0, vv0, vc1, vv1, code, cval, L, lane, xres + ps * (a.D * K64) + 4 * lane, top);
     if (SHIFTED && ps == 0 && a.meta_shift) {
       // the shift is the output at case 0 (lane 0, first case) when finite:
       // the value the shift pass computes, from the same arithmetic
@@ -568,10 +571,17 @@ __device__ __forceinline__ void eval_wave_resident(const EvalArgs& a, int p, con
   }
 }
 
-template <int KIND, int K>
+template <int KIND, int K, int CLS>
 __global__ void __launch_bounds__(256) k_eval_resident(EvalArgs a) {
   constexpr int K64 = K * 64;
   extern __shared__ float xres[];
+  // A list of at most four programs per wave is walked statically (wave w
+  // takes programs w, w + W, ...: no atomics); a longer one through the
+  // shared counter, RESIDENT_BATCH programs per claim.  Workgroups whose
+  // waves would find nothing leave before staging the inputs.
+  const int32_t n_list = a.class_count[CLS];
+  const int32_t n_waves = int32_t(gridDim.x) * 4;
+  if (int64_t(blockIdx.x) * 4 >= n_list) return;
   const int passes = int((a.M + K64 - 1) / K64);
   const int per_pass = a.D * K64;
   for (int i = threadIdx.x; i < passes * per_pass; i += blockDim.x) {
@@ -589,10 +599,18 @@ __global__ void __launch_bounds__(256) k_eval_resident(EvalArgs a) {
   // scalar and no early continue splits the body.
   // Each atomic claims RESIDENT_BATCH consecutive programs (one
   // same-address atomic per program would serialise at the counter).
-  const int32_t count = __builtin_amdgcn_readfirstlane(a.class_count[0]);
-  const int32_t* list = a.class_list;
+  const int32_t count = __builtin_amdgcn_readfirstlane(a.class_count[CLS]);
+  const int32_t* list = a.class_list + int64_t(CLS) * a.n_total;
+  if (count <= 4 * n_waves) {
+    const int32_t wave_id = __builtin_amdgcn_readfirstlane(int32_t(blockIdx.x) * 4 + int32_t(threadIdx.x >> 6));
+    for (int32_t item = wave_id; item < count; item += n_waves) {
+      const int p = __builtin_amdgcn_readfirstlane(list[item] - a.prog_begin);
+      if (p >= 0 && p < a.n_programs) eval_wave_resident<KIND, K, CLS>(a, p, xres, passes);  // else another slice's
+    }
+    return;
+  }
   for (;;) {
-    const unsigned long long it = atomicAdd(a.work, lane == 0 ? (unsigned long long)RESIDENT_BATCH : 0ull);
+    const unsigned long long it = atomicAdd(a.work + CLS, lane == 0 ? (unsigned long long)RESIDENT_BATCH : 0ull);
     const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(it), 0);
     const uint32_t hi = __builtin_amdgcn_readlane(uint32_t(it >> 32), 0);
     const int64_t first = int64_t((uint64_t(hi) << 32) | lo);
@@ -600,7 +618,7 @@ __global__ void __launch_bounds__(256) k_eval_resident(EvalArgs a) {
     const int64_t end = first + RESIDENT_BATCH < count ? first + RESIDENT_BATCH : count;
     for (int64_t item = first; item < end; ++item) {
       const int p = __builtin_amdgcn_readfirstlane(list[item] - a.prog_begin);
-      if (p >= 0 && p < a.n_programs) eval_wave_resident<KIND, K>(a, p, xres, passes);  // else another slice's
+      if (p >= 0 && p < a.n_programs) eval_wave_resident<KIND, K, CLS>(a, p, xres, passes);  // else another slice's
     }
   }
 }
@@ -703,16 +721,15 @@ __global__ void __launch_bounds__(64) k_values(ValuesArgs a) {
   values_program(a, blockIdx.x, blockIdx.y, xl_all);
 }
 
-// Correlation shifts of the class-1 and class-2 programs only (the
-// resident-inputs kernel computes class 0's): a fixed grid striding over the
-// two lists, no counters.
+// Correlation shifts of the class-2 programs only (the resident-inputs
+// kernels compute those of classes 0 and 1): a fixed grid striding over the
+// list, no counters.
 __global__ void __launch_bounds__(64) k_values_deep(ValuesArgs a, const int32_t* class_count,
                                                     const int32_t* class_list, int32_t stride) {
   __shared__ float xl_all[MAX_D * 256];
-  const int32_t c1 = class_count[1], c2 = class_count[2];
-  for (int32_t item = blockIdx.x; item < c1 + c2; item += gridDim.x) {
-    const int32_t p = item < c1 ? class_list[stride + item] : class_list[2 * int64_t(stride) + (item - c1)];
-    values_program(a, p, 0, xl_all);
+  const int32_t c2 = class_count[2];
+  for (int32_t item = blockIdx.x; item < c2; item += gridDim.x) {
+    values_program(a, class_list[2 * int64_t(stride) + item], 0, xl_all);
     __builtin_amdgcn_wave_barrier();
   }
 }
@@ -907,18 +924,19 @@ bool resident_eligible(int64_t M, int32_t D, int32_t n_chunks, int32_t n_total) 
 
 static bool resident_eligible(const EvalArgs& a) { return resident_eligible(a.M, a.D, a.n_chunks, a.n_total); }
 
-template <int KIND, int K>
+template <int KIND, int K, int CLS>
 static hipError_t launch_resident(const EvalArgs& a, size_t lds, hipStream_t s) {
   static size_t cached_lds = size_t(-1);
   static int cached = 0;
   if (lds != cached_lds) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_resident<KIND, K>, 256, lds) != hipSuccess || nb < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_resident<KIND, K, CLS>, 256, lds) != hipSuccess ||
+        nb < 1)
       nb = 1;
     cached = nb;
     cached_lds = lds;
   }
-  hipLaunchKernelGGL((k_eval_resident<KIND, K>), dim3(cached * cu_count()), dim3(256), lds, s, a);
+  hipLaunchKernelGGL((k_eval_resident<KIND, K, CLS>), dim3(cached * cu_count()), dim3(256), lds, s, a);
   return hipGetLastError();
 }
 
@@ -929,13 +947,17 @@ static hipError_t launch_kind(int kv, const EvalArgs& a, hipStream_t s, hipEvent
   if (e != hipSuccess) return e;
   if (ev0) (void)hipEventRecord(ev0, s);
   const bool wide = kv == 0 && a.D <= WIDE_TILE_MAX_D;
-  if (resident_eligible(a))
-    e = wide ? launch_resident<KIND, 8>(a, resident_bytes(a, 8), s) : launch_resident<KIND, 4>(a, resident_bytes(a, 4), s);
+  const bool resident = resident_eligible(a);
+  if (resident)
+    e = wide ? launch_resident<KIND, 8, 0>(a, resident_bytes(a, 8), s)
+             : launch_resident<KIND, 4, 0>(a, resident_bytes(a, 4), s);
   else
     e = wide ? launch_class<KIND, 0, 0>(a, s) : launch_class<KIND, 0, 1>(a, s);
   if (ev1) (void)hipEventRecord(ev1, s);
   if (e != hipSuccess) return e;
-  e = launch_class<KIND, 1, 0>(a, s);
+  // class 1 (register need 5..8, and every program with one of the further
+  // operators) resident too when the shape allows, 4 cases per lane
+  e = resident ? launch_resident<KIND, 4, 1>(a, resident_bytes(a, 4), s) : launch_class<KIND, 1, 0>(a, s);
   if (e != hipSuccess) return e;
   return launch_class<KIND, 2, 0>(a, s);
 }

@@ -80,9 +80,9 @@ struct EvalArgs {
   int32_t n_total;                  // programs in the whole population
   int32_t prog_begin;               // first program of this launch (slice-local index 0)
   double smax = 0.0;                // the paper's scores: maximum score S
-  // correlation and Eq. 2: when set, the resident-inputs kernel takes each
-  // class-0 program's shift from its own first pass and stores it here (the
-  // same array as meta); the shift pass then covers classes 1 and 2 only
+  // correlation and Eq. 2: when set, the resident-inputs kernels take each
+  // class-0 and class-1 program's shift from their own first pass and store
+  // it here (the same array as meta); the shift pass then covers class 2 only
   ProgMeta* meta_shift = nullptr;
 };
 
@@ -193,8 +193,8 @@ __global__ void k_finalize_batch(BatchArgs b);
 __global__ void k_target_stats(const float* __restrict__ y, int64_t M, double* __restrict__ stats);
 __global__ void k_finalize(FinalizeArgs a);
 __global__ void k_values(ValuesArgs a);
-// correlation shifts of the programs of register-need classes 1 and 2 (a
-// persistent grid walking their class lists)
+// correlation shifts of the programs of register-need class 2 (a persistent
+// grid walking its class list)
 __global__ void k_values_deep(ValuesArgs a, const int32_t* class_count, const int32_t* class_list, int32_t stride);
 // whether an evaluation of this shape takes the resident-inputs kernel for
 // class 0 (one chunk, enough programs, inputs within RESIDENT_MAX_BYTES)

@@ -173,3 +173,36 @@ def test_init_and_generation_bit_exact():
     assert np.array_equal(kids.len.cpu().numpy(), r[1])
     assert np.array_equal(kids.tokens.cpu().numpy().view(np.uint16), r[0])
     assert np.array_equal(kids.consts.cpu().numpy().view(np.uint32), r[2].view(np.uint32))
+
+
+@pytest.mark.parametrize("kind", [ofit.MSE, ofit.CORR])
+def test_resident_class1_small_case_set(kind):
+    """The paper's regime with its full operator table: 6000 programs using
+    the further operators (register-need class 1 at least) on 512 cases take
+    the resident-inputs kernels; the same programs in slices of 2000 (below
+    the resident threshold: the block kernels) give the same classification
+    and values within summation-order rounding, and a sample passes the
+    oracle gate."""
+    api = _api()
+    name = "mse" if kind == ofit.MSE else "corr"
+    ps = _population(1301 + kind, 6000, 3, 30, 3, const_range=(-1.5, 1.5))
+    data = wl.make_dataset(1302, 512, 3, x_range=(-1.2, 1.2), target_len=8)
+    X = torch.from_numpy(data.X).cuda()
+    y = torch.from_numpy(data.y).cuda()
+    whole, st = api.evaluate(api.DevicePrograms.from_programset(ps), X, y, name, with_status=True)
+    whole = whole.cpu().numpy()
+    assert np.all(st.cpu().numpy() == 0)
+    parts = [api.evaluate(api.DevicePrograms.from_programset(ps.subset(list(range(p0, p0 + 2000)))), X, y, name)
+             .cpu().numpy() for p0 in range(0, 6000, 2000)]
+    part = np.concatenate(parts)
+    assert [ofit.classify(v) for v in whole] == [ofit.classify(v) for v in part]
+    ok = np.isfinite(part)
+    assert ok.sum() > 1000
+    scale = np.maximum(np.abs(part[ok]), 1e-300)
+    assert np.all(np.abs(whole[ok] - part[ok]) <= 1e-9 * scale + 1e-12)
+    sub = list(range(0, 6000, 37))
+    f64, _, f32, pert = gates.references(ps, data.X, data.y, kind, subset=sub)
+    keep = [j for j in range(len(sub)) if _class_stable(f32, [f64] + pert, j)]
+    n, _ = gates.check(whole[sub][keep], f64[keep], f32[keep], kind, data.y, max_ill_frac=0.4,
+                       label=f"resident class 1 {name}", perturbed=[p[keep] for p in pert])
+    assert n > 20
