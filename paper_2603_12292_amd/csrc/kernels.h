@@ -172,11 +172,12 @@ constexpr int CASES_PER_BLOCK_ITER = CASES_PER_WAVE_ITER * EVAL_WAVES;  // chunk
 // narrower tile of class 0, used when the LDS input tile of the wide one
 // would exceed WIDE_TILE_MAX_D variables).
 constexpr int WIDE_TILE_MAX_D = 8;
-// The resident-inputs evaluator (small case sets): inputs of at most this
-// many bytes per workgroup, populations of at least this many programs.
+// The resident-inputs evaluator (small case sets, register-need classes 0
+// and 1): inputs of at most this many bytes per workgroup, populations of at
+// least this many programs.
 constexpr size_t RESIDENT_MAX_BYTES = 64 * 1024;
 constexpr int32_t RESIDENT_MIN_PROGRAMS = 4096;
-constexpr int RESIDENT_BATCH = 16;  // programs a wave claims per atomic
+constexpr int RESIDENT_BATCH = 16;  // programs a wave claims per atomic (long lists)
 __host__ __device__ constexpr int class_k(int c, int kv) { return c == 0 ? (kv == 0 ? 8 : 4) : (c == 1 ? 4 : 2); }
 
 // decoding: programs of at most 64 tokens in k_prepare (narrow LDS
@@ -196,8 +197,9 @@ __global__ void k_values(ValuesArgs a);
 // correlation shifts of the programs of register-need class 2 (a persistent
 // grid walking its class list)
 __global__ void k_values_deep(ValuesArgs a, const int32_t* class_count, const int32_t* class_list, int32_t stride);
-// whether an evaluation of this shape takes the resident-inputs kernel for
-// class 0 (one chunk, enough programs, inputs within RESIDENT_MAX_BYTES)
+// whether an evaluation of this shape takes the resident-inputs kernels for
+// classes 0 and 1 (one chunk, enough programs, inputs within
+// RESIDENT_MAX_BYTES)
 bool resident_eligible(int64_t M, int32_t D, int32_t n_chunks, int32_t n_total);
 
 // host launchers of the templated evaluation kernels (eval.hip)

@@ -332,9 +332,10 @@ __device__ static void append_one(const PrepareArgs& a, int p, ListIds ids) {
   a.len_list[int64_t(ids.lc) * a.n_programs + ls] = p;
 }
 
-// Programs of at most PREP_SHORT tokens keep their scratch in LDS (16-bit
-// entries: token indices, needs and tokens all fit), longer ones in the
-// global scratch arrays.
+// The second decoding pass (k_prepare_long, and the batched kernel): programs
+// of at most PREP_SHORT tokens keep their scratch in LDS (16-bit entries:
+// token indices, needs and tokens all fit), longer ones in the global scratch
+// arrays.  The first pass uses the narrow scratch below.
 constexpr int PREP_BLOCK = 64;
 constexpr int PREP_SHORT = 128;
 
