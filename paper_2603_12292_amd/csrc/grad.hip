@@ -894,7 +894,7 @@ __device__ __forceinline__ void dtape_list_item(const GradArgs& a, int p, int c,
 // LIST 2, 3, 4: at most GRAD_DTAPE_SMALL (4 cases per lane), MID, LARGE
 // entries per case (2 cases per lane, upper tape 0 or 32 entries).
 template <int LIST>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LIST == 3 ? 4 : 1))) k_grad_dtape(GradArgs a) {
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LIST == 3 || LIST == 2 ? 4 : 1))) k_grad_dtape(GradArgs a) {
   extern __shared__ float lds[];
   const int32_t count = a.list_count[LIST];
   const int64_t items = int64_t(count) * a.n_chunks;
