@@ -15,6 +15,7 @@ from typing import Optional
 
 import numpy as np
 
+from . import bound as obound
 from . import fitness as fit
 from . import interp
 
@@ -34,14 +35,27 @@ def evaluate_one(tokens, consts, X, y, kind: int, mode: str = "o64", seed: int =
     return fit.fitness(kind, yh, y), st
 
 
+def bound_one(tokens, consts, X, y, kind: int, div_eps=None):
+    """(first-order fitness bound of oracle.bound, status) of one program;
+    NaN for an invalid program."""
+    st, _ = interp.validate(tokens, len(consts), X.shape[1])
+    if st != interp.ST_OK:
+        return math.nan, st
+    return obound.fitness_bound(tokens, consts, X, y, kind, div_eps=div_eps), st
+
+
 def _worker(args):
-    tokens, consts, tok_offset, tok_len, const_offset, const_count, X, y, kind, mode, lo, hi, seed = args
+    tokens, consts, tok_offset, tok_len, const_offset, const_count, X, y, kind, mode, lo, hi, seed, div_eps = args
     out = np.empty(hi - lo)
     sts = np.empty(hi - lo, dtype=np.int8)
     for i, p in enumerate(range(lo, hi)):
         o, l = int(tok_offset[p]), int(tok_len[p])
         co, cc = int(const_offset[p]), int(const_count[p])
-        out[i], sts[i] = evaluate_one(tokens[o:o + l], consts[co:co + cc], X, y, kind, mode, seed * 1_000_003 + p)
+        if mode == "bound":
+            out[i], sts[i] = bound_one(tokens[o:o + l], consts[co:co + cc], X, y, kind, div_eps)
+        else:
+            out[i], sts[i] = evaluate_one(tokens[o:o + l], consts[co:co + cc], X, y, kind, mode,
+                                          seed * 1_000_003 + p)
     return lo, out, sts
 
 
@@ -58,11 +72,13 @@ def _gpu_runtime_started() -> bool:
 
 def evaluate_population(tokens, tok_offset, tok_len, consts, const_offset, const_count,
                         X, y, kind: int, mode: str = "o64", processes: Optional[int] = None,
-                        subset=None, seed: int = 0):
+                        subset=None, seed: int = 0, div_eps=None):
     """fitness float64[N] (or [len(subset)]) and status int8[...].
 
     ``subset`` restricts the evaluation to the listed program indices (in
-    that order).
+    that order).  mode "bound" returns oracle.bound's first-order fitness
+    bound per program instead (``div_eps``: the relative error bound of a
+    division that is not correctly rounded, None for a correctly rounded one).
     """
     X = np.asarray(X, dtype=np.float32)
     y = np.asarray(y, dtype=np.float32)
@@ -77,14 +93,14 @@ def evaluate_population(tokens, tok_offset, tok_len, consts, const_offset, const
         processes = None  # forking is unsafe once the GPU runtime runs threads
     if not processes or processes <= 1 or N < 2:
         _, f, s = _worker((tokens, consts, tok_offset, tok_len, const_offset, const_count,
-                           X, y, kind, mode, 0, N, seed))
+                           X, y, kind, mode, 0, N, seed, div_eps))
         return f, s
     import multiprocessing as mp
     chunks = []
     step = max(1, math.ceil(N / (processes * 4)))
     for lo in range(0, N, step):
         chunks.append((tokens, consts, tok_offset, tok_len, const_offset, const_count,
-                       X, y, kind, mode, lo, min(N, lo + step), seed))
+                       X, y, kind, mode, lo, min(N, lo + step), seed, div_eps))
     f = np.empty(N)
     s = np.empty(N, dtype=np.int8)
     env_before = os.environ.get("OMP_NUM_THREADS")

@@ -24,29 +24,30 @@ _UNARY = (4, 5, 6, 7, 8, 11, 12, 13, 14, 15, 16, 17)
 
 
 class Node:
-    __slots__ = ("kind", "arg", "kids")
+    __slots__ = ("kind", "arg", "kids", "pos")
 
-    def __init__(self, kind, arg, kids):
+    def __init__(self, kind, arg, kids, pos=-1):
         self.kind = kind
         self.arg = arg
         self.kids = kids
+        self.pos = pos  # index of the node's token in the postfix program
 
 
 def parse(tokens) -> Node:
     """Postfix tokens -> expression tree (raises on malformed programs)."""
     st = []
-    for t in tokens:
+    for i, t in enumerate(tokens):
         op, arg = int(t) & 0xFF, int(t) >> 8
         if op == 9:
-            st.append(Node("var", arg, []))
+            st.append(Node("var", arg, [], i))
         elif op == 10:
-            st.append(Node("const", arg, []))
+            st.append(Node("const", arg, [], i))
         elif op in (0, 1, 2, 3):
             right = st.pop()
             left = st.pop()
-            st.append(Node(_NAMES[op], 0, [left, right]))
+            st.append(Node(_NAMES[op], 0, [left, right], i))
         elif op in _UNARY:
-            st.append(Node(_NAMES[op], 0, [st.pop()]))
+            st.append(Node(_NAMES[op], 0, [st.pop()], i))
         else:
             raise ValueError(op)
     if len(st) != 1:
@@ -137,18 +138,25 @@ def _scalar(kind, vals):
     raise ValueError(kind)
 
 
-def evaluate(node: Node, xrow, consts, round32: bool = False) -> float:
-    """Value of the tree for one fitness case (a row of X)."""
+def evaluate(node: Node, xrow, consts, round32: bool = False, perturb=None, row: int = 0) -> float:
+    """Value of the tree for one fitness case (a row of X).
+
+    ``perturb(pos, row, v)``, when given, replaces the result v of every
+    operator node (token index pos) before its parent uses it: a way to
+    impose chosen errors on chosen operations, case by case.
+    """
     if node.kind == "var":
         return float(xrow[node.arg])
     if node.kind == "const":
         return float(consts[node.arg])
-    v = _scalar(node.kind, [evaluate(k, xrow, consts, round32) for k in node.kids])
+    v = _scalar(node.kind, [evaluate(k, xrow, consts, round32, perturb, row) for k in node.kids])
+    if perturb is not None:
+        v = perturb(node.pos, row, v)
     return _r32(v) if round32 else v
 
 
-def run(tokens, consts, X, round32: bool = False) -> np.ndarray:
+def run(tokens, consts, X, round32: bool = False, perturb=None) -> np.ndarray:
     root = parse(tokens)
     c = [float(np.float32(v)) for v in consts]
     Xf = np.asarray(X, dtype=np.float32)
-    return np.array([evaluate(root, [float(v) for v in row], c, round32) for row in Xf])
+    return np.array([evaluate(root, [float(v) for v in row], c, round32, perturb, i) for i, row in enumerate(Xf)])
