@@ -8,9 +8,13 @@ fitness the library computes.  The point-to-point fitness here is the mean
 squared error.
 
 Conventions where the paper is silent (it pairs invalid values instead):
-  MSE   any NaN y_hat -> NaN; else any +-Inf y_hat -> +Inf;
-        else (1/M) * sum (y_hat - y)^2
-  CORR  any non-finite y_hat -> NaN; two-pass centred sums
+  MSE   the case terms d_i = y_hat_i - y_i in IEEE binary64: any NaN d_i
+        (a NaN output or target, or an infinite output equal to an infinite
+        target) -> NaN; else any +-Inf d_i -> +Inf; else
+        (1/M) * sum d_i^2.  For finite targets: any NaN y_hat -> NaN, else
+        any +-Inf y_hat -> +Inf.
+  CORR  any non-finite y_hat or y -> NaN (Eq. 1's sums are undefined; the
+        section 2.1.5 datasets may hold invalid targets); two-pass centred sums
         Sxx = sum (y_hat - mean y_hat)^2, Syy = sum (y - mean y)^2,
         Sxy = sum (y_hat - mean y_hat)(y - mean y);
         Sxx == 0 -> r := 0 (F = 1); Syy == 0 -> NaN;
@@ -30,11 +34,12 @@ CORR = 1
 def mse(y_hat, y) -> float:
     yh = np.asarray(y_hat, dtype=np.float64)
     yt = np.asarray(y, dtype=np.float32).astype(np.float64)
-    if np.any(np.isnan(yh)):
+    with np.errstate(invalid="ignore"):
+        d = yh - yt
+    if np.any(np.isnan(d)):
         return math.nan
-    if np.any(np.isinf(yh)):
+    if np.any(np.isinf(d)):
         return math.inf
-    d = yh - yt
     return math.fsum((d * d).tolist()) / yh.shape[0]
 
 
@@ -61,7 +66,7 @@ def pearson_r(y_hat, y) -> float:
 def corr_fitness(y_hat, y) -> float:
     """1 - r^2 with the degenerate-case conventions above."""
     yh = np.asarray(y_hat, dtype=np.float64)
-    if not np.all(np.isfinite(yh)):
+    if not np.all(np.isfinite(yh)) or not np.all(np.isfinite(np.asarray(y, dtype=np.float64))):
         return math.nan
     sxx, syy, sxy = pearson_sums(yh, y)
     if syy == 0.0:

@@ -27,6 +27,29 @@ def test_mse_classification():
     assert math.isfinite(fit.mse([big, -big, big, -big], -y))
 
 
+def test_non_finite_targets():
+    """Targets holding invalid values (section 2.1.5 expects such datasets):
+    MSE follows IEEE arithmetic of its case terms, 1 - r^2 is undefined."""
+    yh = np.array([1.0, 2.0, 3.0, 4.0])
+    nan_y = np.array([1, np.nan, 3, 4], dtype=np.float32)
+    inf_y = np.array([1, np.inf, 3, 4], dtype=np.float32)
+    assert math.isnan(fit.mse(yh, nan_y))
+    assert fit.mse(yh, inf_y) == math.inf
+    # an infinite output meeting the same infinite target: inf - inf is NaN
+    assert math.isnan(fit.mse([1.0, np.inf, 3.0, 4.0], inf_y))
+    assert fit.mse([1.0, -np.inf, 3.0, 4.0], inf_y) == math.inf
+    # NaN anywhere beats +Inf elsewhere
+    assert math.isnan(fit.mse([np.inf, 2.0, 3.0, 4.0], nan_y))
+    # 1 - r^2 is NaN, never a perfect 0, for a NaN or infinite target
+    rng = np.random.default_rng(6)
+    a = rng.standard_normal(50)
+    for bad in (np.nan, np.inf, -np.inf):
+        y = rng.standard_normal(50).astype(np.float32)
+        y[7] = bad
+        assert math.isnan(fit.corr_fitness(a, y))
+        assert math.isnan(fit.fitness(fit.CORR, a, y))
+
+
 def test_pearson_matches_library_routines():
     rng = np.random.default_rng(4)
     for _ in range(20):
