@@ -97,18 +97,20 @@ def test_batched_oracle_parity(kind):
     probs = _small_problems(9, kind)
     dev = [_problem(ps, d) for ps, d in probs]
     fits = [f.cpu().numpy() for f in api.evaluate_batched(dev, KINDS[kind])]
-    compared = ill = 0
+    compared = ill = checked = finite = 0
     for q, ((ps, data), gpu) in enumerate(zip(probs, fits)):
         sub = list(range(0, ps.n, max(1, ps.n // 12)))
-        f64, s64, f32, pert = gates.references(ps, data.X, data.y, kind, subset=sub, processes=4)
-        # a dozen programs per problem is too few to bound the ill-conditioned
-        # share per problem; it is bounded over the whole batch below
-        n, n_ill = gates.check(gpu[sub], f64, f32, kind, data.y, max_ill_frac=1.0, label=f"batch q={q}",
-                               perturbed=pert)
-        compared += n
-        ill += n_ill
-    print(f"compared {compared}, ill-conditioned {ill}")
-    assert compared > 50
+        r = gates.references(ps, data.X, data.y, kind, subset=sub, processes=4)
+        # a dozen programs per problem is too few to bound the shares per
+        # problem; they are bounded over the whole batch below
+        s = gates.check(gpu[sub], r, kind, data.y, max_ill_frac=1.0, max_unchecked_frac=1.0, label=f"batch q={q}",
+                        min_value=0)
+        compared += s.n_value
+        ill += s.n_ill
+        checked += s.n_checked
+        finite += s.n_finite
+    print(f"value-gated {compared}, ill-conditioned {ill}, under a value gate {checked} of {finite} finite")
+    assert compared > 50 and checked >= 0.9 * finite
     # programs up to 80 tokens often hold exp of large arguments, whose
     # relative condition number is |x|: with MSE (which keeps the magnitude
     # of yhat) about half of them move by more than 1e-6 under fp32 rounding
@@ -201,13 +203,15 @@ def test_ragged_workload_full_size(kind):
     for q, (p, X, y) in enumerate(dev):
         one = api.evaluate(p, X, y, KINDS[kind]).cpu().numpy()
         assert np.array_equal(_bits(one), _bits(fits[q])), q
-    compared = 0
+    compared = checked = finite = 0
     for q in range(0, 64, 8):
         w = ws[q]
-        sub = [3, 517]
-        f64, _, f32, pert = gates.references(w.programs, w.data.X, w.data.y, kind, subset=sub, processes=2)
-        n, _ = gates.check(fits[q][sub], f64, f32, kind, w.data.y, max_ill_frac=1.0, label=f"ragged q={q}",
-                           perturbed=pert)
-        compared += n
-    print(f"compared {compared}")
-    assert compared >= 8
+        sub = [3, 517, 1001]
+        r = gates.references(w.programs, w.data.X, w.data.y, kind, subset=sub, processes=2)
+        s = gates.check(fits[q][sub], r, kind, w.data.y, max_ill_frac=1.0, max_unchecked_frac=1.0,
+                        label=f"ragged q={q}", min_value=0)
+        compared += s.n_value
+        checked += s.n_checked
+        finite += s.n_finite
+    print(f"value-gated {compared}, under a value gate {checked} of {finite} finite")
+    assert compared >= 12 and checked >= 18

@@ -53,12 +53,12 @@ def _grad(ps, data, with_status=False, kind="mse"):
 
 
 def _well_conditioned(ps, data, idx, kind=ofit.MSE):
-    f64, _, f32, pert = gates.references(ps, data.X, data.y, kind, subset=idx)
+    r = gates.references(ps, data.X, data.y, kind, subset=idx)
     at = gates.atol(kind, data.y)
     ok = []
     for j in range(len(idx)):
-        sp = max([abs(f32[j] - f64[j])] + [abs(p[j] - f64[j]) for p in pert])
-        ok.append(math.isfinite(f64[j]) and sp <= gates.RTOL_COND * abs(f64[j]) + at)
+        sp = max([abs(r.f32[j] - r.f64[j])] + [abs(p[j] - r.f64[j]) for p in r.pert])
+        ok.append(math.isfinite(r.f64[j]) and sp <= gates.RTOL_COND * abs(r.f64[j]) + at)
     return np.array(ok)
 
 
