@@ -15,6 +15,8 @@ tree        an independent recursive tree evaluator (scalar Python math),
             used to pin the stack interpreter by brute force
 fitness     MSE and correlation fitness 1 - r^2 (Eq. 1), float64 sums
 population  whole-population evaluation -> fitness[N]
+bound       bound on the fitness change of a binary32 evaluation (running
+            error bound per case, combined through the MSE and Eq. 1's r)
 grad        reverse-mode gradient of MSE w.r.t. program constants, and
             central finite differences
 philox      Philox4x32-10 counter-based generator (Salmon et al., SC'11)

@@ -1,70 +1,73 @@
-"""First-order bound on the fitness change of a binary32 evaluation -- test infrastructure.
+"""Bound on the fitness change of a binary32 evaluation -- test infrastructure.
 
 Why it exists.  The parity claim of the library is a binary32 evaluation per
 case (paper, section 2.1.2: every genome is run on every fitness case) whose
 + - * / are correctly rounded and whose other operators are accurate to a
 few ulps.  Such an evaluation reproduces the fp32-emulating oracle (mode
-"o32e" of ``oracle.interp``) token by token except that each token's result
-may carry a small relative error of its own.  How far that moves a program's
-fitness depends on the program: sin of a large argument or exp of a large
-argument amplifies it enormously.  This module computes, for one program, a
-bound B on that movement, so that every program can be value-checked
-against the oracle, the ill-conditioned ones included, with an envelope
-that follows from the stated operator accuracies rather than from a
-tolerance chosen by hand.
+"o32e" of ``oracle.interp``) token by token, except that each token's result
+may carry a small error of its own, which later tokens carry on.  How far
+that moves a program's fitness depends on the program: sin or exp of a
+large argument, or a division by a value near zero, amplify it enormously.
+This module computes, for one program, a bound B on that movement, so that
+every program can be value-checked against the oracle, the ill-conditioned
+ones included, with an envelope that follows from the stated operator
+accuracies rather than from a tolerance chosen by hand.
 
-Model.  Token t on case i has the value v[t,i] along a base trajectory (the
-o32e values by default).  The evaluation under test computes
-v[t,i] (1 + d[t,i]) instead, |d[t,i]| <= eps[t], and everything downstream
-takes the perturbed value.  To first order the fitness then moves by
+Model.  Token t on case i has the value v[t,i] along the base trajectory
+(the o32e values by default).  The evaluation under test computes
+v'[t,i] = f_t(operands') (1 + e) + (tiny), |e| <= eps[t]: the exact operator
+on its own (perturbed) operands, then its own error.
 
-    dF = sum over t, i of  A[t,i] v[t,i] d[t,i],
-
-where A[t,i] = dF / dv[t,i] is token t's adjoint on case i: the derivative
-of the fitness with respect to that token's output through everything that
-consumes it (reverse mode over the postfix tape; Linnainmaa, BIT 16 (1976),
-introduced reverse accumulation exactly for this estimate of accumulated
-rounding error).  Hence
-
-    |dF| <= B = sum over t, i of  |A[t,i]| (|v[t,i]| eps[t] + tiny[t]),
-
-with tiny[t] = 2^-149 (the absolute error of a binary32 subnormal result)
-where eps[t] > 0.
+Per-case bound (a running error bound, forward over the postfix tape; the
+interval arithmetic of the operators' ranges, in binary64): d[t,i] >=
+|v'[t,i] - v[t,i]| follows from the operands' bounds by the operator's
+modulus of continuity,
+  ADD, SUB   da + db
+  MUL        |b| da + |a| db + da db
+  DIV        (|b| da + |a| db) / (|b| (|b| - db))        needs db < |b|
+  SIN, COS   min(|cos x| dx + dx^2/2, 2) (|sin x| for COS; Taylor's bound)
+  EXP        exp(clamp(x + dx)) - exp(clamp(x - dx)) at most, one-sided
+  LOG        log(|x| / (|x| - dx))                       needs dx < |x|
+  SQRT       the larger of sqrt(|x| + dx) - sqrt|x| and sqrt|x| - sqrt(max(|x| - dx, 0))
+  SQUARE     2 |x| dx + dx^2
+  RECIP      dx / (|x| (|x| - dx))                       needs dx < |x|
+  TAN        dx (1 + max tan^2 at x -+ dx)               needs no pole within dx
+  ASIN, ACOS dx / sqrt(1 - (|x| + dx)^2)                 needs |x| + dx < 1
+  ATAN, TANH min(dx, pi), min(dx, 2) (1-Lipschitz)
+plus the token's own error eps[t] (|v| + d) + 2^-149 (subnormal spacing)
+where eps[t] > 0.  A protected operator at its branch point with an exact
+operand (DIV with b == 0 and db == 0, LOG with x == 0 and dx == 0) stays on
+its branch (bound 0 from there); where a "needs" condition fails, the case
+is unbounded (+inf) and so is the program's B ("vacuous": no bound exists).
 
 eps per token (``token_eps``), for a binary32 evaluation against o32e:
   * VAR, CONST: 0 (the same binary32 inputs).
   * SIN COS EXP LOG and the five further library functions: their stated
     accuracy plus o32e's own half ulp, as a relative bound (``EPS_APPROX``).
-  * SQRT: faithful (within 1 ulp of the exact value, o32e within 1/2):
-    1.5 ulp < 2^-22.
-  * ADD SUB MUL DIV SQUARE RECIP (correctly rounded): 0 when every input is
-    bit-identical to o32e, i.e. when no token below it carries an error
-    ("untainted"); otherwise the two roundings of slightly different exact
-    values can differ by up to 1 ulp: 2^-23.  ``div_eps`` overrides DIV for
-    an implementation whose division is not correctly rounded.
-A constant output under 1 - r^2 is a branch point too (F = 1 by
-convention, any variation gives some r): B is 0 when every token carrying
-error has one value on all cases, +inf otherwise.
-The protected operators have branch points (DIV with b == 0, LOG with
-x == 0, SQRT at 0 with its unbounded derivative).  A tainted input lying
-exactly on such a point may move off it, and the fitness jumps: no
-first-order bound exists, and B is +inf ("vacuous").  An untainted input at
-such a point stays there; its branch's derivative is then irrelevant and
-taken as 0.  Where a partial derivative or a product is not finite, B is
-+inf as well.
+  * SQRT: faithful (within 1 ulp of the exact value, o32e within 1/2): 2^-22.
+  * ADD SUB MUL DIV SQUARE RECIP (correctly rounded): on a case where both
+    operands are exact (bound 0), the same rounding of the same value: 0;
+    otherwise the two roundings can differ by up to 1 ulp: 2^-23.
+    ``div_eps`` sets DIV's for an implementation whose division is not
+    correctly rounded.
 
-Seeds dF/dyhat_i (binary64, at the base trajectory's yhat):
-  MSE   2 (yhat_i - y_i) / M
-  CORR  -2 r (w_i / sqrt(Sxx Syy) - r u_i / Sxx) with the centred sums of
-        Eq. 1 (u = yhat - mean yhat, w = y - mean y); 0 when Sxx == 0 (F is
-        then 1 by convention).
-Partial derivatives: those of the operator conventions in ``oracle.interp``,
-evaluated in binary64 at the base values:
-  ADD (1, 1)  SUB (1, -1)  MUL (b, a)  DIV (1/b, -a/b^2)
-  SIN cos x  COS -sin x  EXP e^x inside [-80, 80], 0 outside
-  LOG 1/x  SQRT sign(x) / (2 sqrt|x|)  SQUARE 2x  RECIP -1/x^2
-  TAN 1 + tan^2 x  ASIN 1/sqrt(1 - x^2)  ACOS -1/sqrt(1 - x^2)
-  ATAN 1/(1 + x^2)  TANH 4e/(1 + e)^2 with e = exp(-2|x|)
+Fitness bound from the per-case output bounds b[i] (exact, not linearised):
+  MSE   |(d + h)^2 - d^2| <= 2 |d| b + b^2 per case, d = yhat - y:
+        B = sum_i (2 |d_i| b_i + b_i^2) / M.
+  CORR  with s = sqrt(Sxx), g = ||b||_2 and B1 = sum_i |dr/dyhat_i| b_i
+        (dr/dyhat_i = w_i / sqrt(Sxx Syy) - r u_i / Sxx, the centred sums of
+        Eq. 1), the perturbed r differs from r by at most
+            Br = (s B1 + |r| g^2 / (2 (s - g))) / (s - g)      (needs g < s)
+        (the centred output u moves by a vector of norm <= g; the norm of
+        u is convex with curvature <= 1/(s - g) on that ball), and
+        F = 1 - r^2 by at most B = min(Br (2|r| + Br), 1).  A constant
+        output (F = 1 by convention): B = 0 when every token carrying error
+        has one value on all cases (the outputs stay equal), else +inf.
+B is first-order tight: as the errors shrink it approaches the largest
+first-order change, sum |dF/dv[t,i]| |v[t,i]| eps[t] over the worst signs
+(``adjoints`` gives those derivatives by reverse mode -- Linnainmaa, BIT 16
+(1976), introduced reverse accumulation for this estimate of accumulated
+rounding error -- and the tests impose exactly those errors).
 """
 from __future__ import annotations
 
@@ -86,7 +89,7 @@ TINY = 2.0 ** -149        # the absolute spacing of binary32 subnormals
 EPS_APPROX = {SIN: 4 * ULP, COS: 4 * ULP, EXP: 4 * ULP, LOG: 4 * ULP,
               TAN: 8 * ULP, ASIN: 8 * ULP, ACOS: 8 * ULP, ATAN: 8 * ULP, TANH: 8 * ULP}
 EPS_SQRT = 2 * ULP        # faithful square root: 1.5 ulp from o32e's correctly rounded one
-EPS_ROUNDED = ULP         # a correctly rounded operator on tainted inputs
+EPS_ROUNDED = ULP         # a correctly rounded operator on inexact operands
 
 
 def _round32(v):
@@ -129,28 +132,155 @@ def tape(tokens, consts, X, base: str = "o32e"):
     return values, children
 
 
-def token_eps(tokens, children, div_eps=None, eps_scale: float = 1.0):
-    """(eps[t], tainted[t]) for every token (see the module header);
-    ``eps_scale`` multiplies every eps (small scales keep a perturbation
+def token_eps(tokens, div_eps=None, eps_scale: float = 1.0):
+    """(eps[t], always[t]): each token's relative error budget and whether it
+    applies on every case (approximate operators, and DIV when div_eps is
+    given) or only where an operand is inexact (correctly rounded ones).
+    ``eps_scale`` multiplies every budget (small scales keep a perturbation
     test in the first-order regime)."""
-    eps = [0.0] * len(tokens)
-    tainted = [False] * len(tokens)
-    for t, tk in enumerate(tokens):
+    eps, always = [], []
+    for tk in tokens:
         op = int(tk) & 0xFF
-        below = any(tainted[c] for c in children[t])
         if op in (VAR, CONST):
-            e = 0.0
+            e, a = 0.0, False
         elif op in EPS_APPROX:
-            e = EPS_APPROX[op]
+            e, a = EPS_APPROX[op], True
         elif op == SQRT:
-            e = EPS_SQRT
+            e, a = EPS_SQRT, True
         elif op == DIV and div_eps is not None:
-            e = max(div_eps, EPS_ROUNDED if below else 0.0)
+            e, a = div_eps, True
         else:
-            e = EPS_ROUNDED if below else 0.0
-        eps[t] = e * eps_scale
-        tainted[t] = below or e > 0.0
-    return eps, tainted
+            e, a = EPS_ROUNDED, False
+        eps.append(e * eps_scale)
+        always.append(a)
+    return eps, always
+
+
+def case_bounds(tokens, consts, X, base: str = "o32e", div_eps=None, eps_scale: float = 1.0):
+    """(values, children, d, rel) of one valid program: d[t] the per-case
+    bound on |v'[t] - v[t]| (forward running bound, see the module header),
+    rel[t] the per-case relative error budget of token t's own result (0
+    where none applies)."""
+    values, children = tape(tokens, consts, X, base)
+    eps, always = token_eps(tokens, div_eps, eps_scale)
+    L = len(tokens)
+    M = values[0].shape[0]
+    d = [None] * L
+    rel = [None] * L
+    with np.errstate(all="ignore"):
+        for t in range(L):
+            op = int(tokens[t]) & 0xFF
+            kids = children[t]
+            v = values[t]
+            if not kids:
+                d[t] = np.zeros(M)
+                rel[t] = np.zeros(M)
+                continue
+            if len(kids) == 2:
+                a, b = values[kids[0]], values[kids[1]]
+                da, db = d[kids[0]], d[kids[1]]
+                if op in (ADD, SUB):
+                    p = da + db
+                elif op == MUL:
+                    p = np.abs(b) * da + np.abs(a) * db + da * db
+                elif op == DIV:
+                    ab = np.abs(b)
+                    p = np.where(db < ab, (ab * da + np.abs(a) * db) / (ab * (ab - db)), np.inf)
+                    p = np.where(b == 0.0, np.where(db == 0.0, 0.0, np.inf), p)
+                else:
+                    raise ValueError(op)
+                exact = (da == 0.0) & (db == 0.0)
+            else:
+                x = values[kids[0]]
+                dx = d[kids[0]]
+                ax = np.abs(x)
+                if op == SIN:
+                    p = np.minimum(np.abs(np.cos(x)) * dx + 0.5 * dx * dx, 2.0)
+                elif op == COS:
+                    p = np.minimum(np.abs(np.sin(x)) * dx + 0.5 * dx * dx, 2.0)
+                elif op == EXP:
+                    e0 = np.exp(np.clip(x, -80.0, 80.0))
+                    p = np.maximum(np.exp(np.clip(x + dx, -80.0, 80.0)) - e0,
+                                   e0 - np.exp(np.clip(x - dx, -80.0, 80.0)))
+                elif op == LOG:
+                    p = np.where(dx < ax, np.log(ax / (ax - dx)), np.inf)
+                    p = np.where(x == 0.0, np.where(dx == 0.0, 0.0, np.inf), p)
+                elif op == SQRT:
+                    p = np.maximum(np.sqrt(ax + dx) - np.sqrt(ax), np.sqrt(ax) - np.sqrt(np.maximum(ax - dx, 0.0)))
+                elif op == SQUARE:
+                    p = 2.0 * ax * dx + dx * dx
+                elif op == RECIP:
+                    p = np.where(dx < ax, dx / (ax * (ax - dx)), np.inf)
+                elif op == TAN:
+                    lo, hi = x - dx, x + dx
+                    pole = np.floor(hi / np.pi - 0.5) != np.floor(lo / np.pi - 0.5)
+                    p = np.where(pole, np.inf, dx * (1.0 + np.maximum(np.tan(lo) ** 2, np.tan(hi) ** 2)))
+                elif op in (ASIN, ACOS):
+                    m = ax + dx
+                    p = np.where(m < 1.0, dx / np.sqrt(1.0 - m * m), np.inf)
+                elif op == ATAN:
+                    p = np.minimum(dx, np.pi)
+                elif op == TANH:
+                    p = np.minimum(dx, 2.0)
+                else:
+                    raise ValueError(op)
+                exact = dx == 0.0
+            p = np.where(np.isnan(p), np.inf, p)
+            r = np.full(M, eps[t]) if always[t] else np.where(exact, 0.0, eps[t])
+            rel[t] = r
+            d[t] = p + np.where(r > 0.0, r * (np.abs(v) + p) + TINY, 0.0)
+    return values, children, d, rel
+
+
+def mse_bound(y_hat, y, b) -> float:
+    """Largest change of the MSE when every output moves by at most b[i]."""
+    yh = np.asarray(y_hat, dtype=np.float64)
+    y64 = np.asarray(y, dtype=np.float32).astype(np.float64)
+    if not np.all(np.isfinite(b)):
+        return math.inf
+    with np.errstate(all="ignore"):
+        B = float(np.sum(2.0 * np.abs(yh - y64) * b + b * b)) / yh.shape[0]
+    return B if math.isfinite(B) else math.inf
+
+
+def corr_bound(y_hat, y, b) -> float:
+    """Largest change of 1 - r^2 (non-constant outputs) when every output
+    moves by at most b[i] (see the module header)."""
+    yh = np.asarray(y_hat, dtype=np.float64)
+    y64 = np.asarray(y, dtype=np.float32).astype(np.float64)
+    if not np.all(np.isfinite(b)):
+        return math.inf
+    M = yh.shape[0]
+    sxx, syy, sxy = ofit.pearson_sums(yh, y64)
+    s = math.sqrt(sxx)
+    r = sxy / math.sqrt(sxx * syy)
+    u = yh - math.fsum(yh.tolist()) / M
+    w = y64 - math.fsum(y64.tolist()) / M
+    B1 = float(np.sum(np.abs(w / math.sqrt(sxx * syy) - r * u / sxx) * b))
+    g = float(np.sqrt(np.sum(b * b)))
+    if not g < s:
+        return math.inf
+    Br = (s * B1 + abs(r) * g * g / (2.0 * (s - g))) / (s - g)
+    B = min(Br * (2.0 * abs(r) + Br), 1.0)
+    return B if math.isfinite(B) else math.inf
+
+
+def fitness_bound(tokens, consts, X, y, kind: int, base: str = "o32e", div_eps=None,
+                  eps_scale: float = 1.0) -> float:
+    """B of one valid program (see the module header): +inf when no bound
+    exists, NaN when the base fitness is not finite."""
+    values, children, d, _ = case_bounds(tokens, consts, X, base, div_eps, eps_scale)
+    yh = values[-1]
+    F = ofit.fitness(kind, yh, y)
+    if not math.isfinite(F):
+        return math.nan
+    if kind == ofit.MSE:
+        return mse_bound(yh, y, d[-1])
+    if np.all(yh == yh[0]):
+        # a constant output: F = 1 by convention, any variation gives some r
+        varying = any(np.any(d[t] > 0.0) and not np.all(values[t] == values[t][0]) for t in range(len(tokens)))
+        return math.inf if varying else 0.0
+    return corr_bound(yh, y, d[-1])
 
 
 def seed(kind: int, y_hat, y):
@@ -172,9 +302,11 @@ def seed(kind: int, y_hat, y):
     return F, -2.0 * r * (w / math.sqrt(sxx * syy) - r * u / sxx)
 
 
-def adjoints(tokens, values, children, seed_vec, tainted):
-    """Per-token adjoint vectors A[t] = dF/dv[t] (reverse sweep, binary64);
-    None when a tainted input sits on a protected operator's branch point."""
+def adjoints(tokens, values, children, seed_vec):
+    """Per-token adjoint vectors A[t] = dF/dv[t] (reverse sweep, binary64,
+    the partial derivatives of the operator conventions; 0 at a protected
+    operator's branch point): the first-order effect of an error on token
+    t's result, whose signs give the worst-case errors."""
     L = len(tokens)
     adj = [None] * L
     adj[L - 1] = seed_vec
@@ -185,8 +317,6 @@ def adjoints(tokens, values, children, seed_vec, tainted):
             kids = children[t]
             if not kids:
                 continue
-            if a_t is None:
-                a_t = np.zeros_like(seed_vec)
             if len(kids) == 2:
                 ia, ib = kids
                 a, b = values[ia], values[ib]
@@ -198,83 +328,43 @@ def adjoints(tokens, values, children, seed_vec, tainted):
                     da, db = a_t * b, a_t * a
                 elif op == DIV:
                     on = b == 0.0
-                    if np.any(on & (a_t != 0.0)) and tainted[ib]:
-                        return None
                     bs = np.where(on, 1.0, b)
                     da = np.where(on, 0.0, a_t / bs)
                     db = np.where(on, 0.0, -a_t * a / (bs * bs))
                 else:
                     raise ValueError(op)
-                adj[ia] = da if adj[ia] is None else adj[ia] + da
-                adj[ib] = db if adj[ib] is None else adj[ib] + db
+                adj[ia], adj[ib] = da, db
             else:
                 (ix,) = kids
                 x = values[ix]
                 if op == SIN:
-                    d = np.cos(x)
+                    dfx = np.cos(x)
                 elif op == COS:
-                    d = -np.sin(x)
+                    dfx = -np.sin(x)
                 elif op == EXP:
                     inside = ~((x > 80.0) | (x < -80.0))
-                    d = np.where(inside, np.exp(np.where(inside, x, 0.0)), 0.0)
+                    dfx = np.where(inside, np.exp(np.where(inside, x, 0.0)), 0.0)
                 elif op in (LOG, SQRT):
                     on = x == 0.0
-                    if np.any(on & (a_t != 0.0)) and tainted[ix]:
-                        return None
                     xs = np.where(on, 1.0, x)
-                    d = 1.0 / xs if op == LOG else np.sign(xs) / (2.0 * np.sqrt(np.abs(xs)))
-                    d = np.where(on, 0.0, d)
+                    dfx = 1.0 / xs if op == LOG else np.sign(xs) / (2.0 * np.sqrt(np.abs(xs)))
+                    dfx = np.where(on, 0.0, dfx)
                 elif op == SQUARE:
-                    d = 2.0 * x
+                    dfx = 2.0 * x
                 elif op == RECIP:
-                    d = -1.0 / (x * x)
+                    dfx = -1.0 / (x * x)
                 elif op == TAN:
                     tx = np.tan(x)
-                    d = 1.0 + tx * tx
+                    dfx = 1.0 + tx * tx
                 elif op in (ASIN, ACOS):
-                    d = 1.0 / np.sqrt(1.0 - x * x)
-                    d = d if op == ASIN else -d
+                    dfx = 1.0 / np.sqrt(1.0 - x * x)
+                    dfx = dfx if op == ASIN else -dfx
                 elif op == ATAN:
-                    d = 1.0 / (1.0 + x * x)
+                    dfx = 1.0 / (1.0 + x * x)
                 elif op == TANH:
                     e = np.exp(-2.0 * np.abs(x))
-                    d = 4.0 * e / ((1.0 + e) * (1.0 + e))
+                    dfx = 4.0 * e / ((1.0 + e) * (1.0 + e))
                 else:
                     raise ValueError(op)
-                dx = np.where(a_t == 0.0, 0.0, a_t * d)
-                adj[ix] = dx if adj[ix] is None else adj[ix] + dx
+                adj[ix] = np.where(a_t == 0.0, 0.0, a_t * dfx)
     return adj
-
-
-def fitness_bound(tokens, consts, X, y, kind: int, base: str = "o32e", div_eps=None,
-                  eps_scale: float = 1.0) -> float:
-    """B of one valid program (see the module header): +inf when no
-    first-order bound exists, NaN when the base fitness is not finite."""
-    values, children = tape(tokens, consts, X, base)
-    F, sv = seed(kind, values[-1], y)
-    if sv is None:
-        return math.nan
-    eps, tainted = token_eps(tokens, children, div_eps, eps_scale)
-    if kind == ofit.CORR and np.all(values[-1] == values[-1][0]):
-        # a constant output: F = 1 by convention, and any case-to-case
-        # variation, however small, gives some r.  The output stays constant
-        # when every token that carries error has one value on all cases
-        # (the same operation on the same operands); otherwise F is not
-        # determined at all.
-        varying = any(tainted[t] and not np.all(values[t] == values[t][0]) for t in range(len(tokens)))
-        return math.inf if varying else 0.0
-    adj = adjoints(tokens, values, children, sv, tainted)
-    if adj is None:
-        return math.inf
-    terms = []
-    with np.errstate(all="ignore"):
-        for t in range(len(tokens)):
-            if eps[t] == 0.0 or adj[t] is None:
-                continue
-            a = np.abs(adj[t])
-            c = np.where(a == 0.0, 0.0, a * (np.abs(values[t]) * eps[t] + TINY))
-            if not np.all(np.isfinite(c)):
-                return math.inf
-            terms.append(float(np.sum(c)))  # non-negative terms: pairwise sum suffices for a bound
-    B = math.fsum(terms)
-    return B if math.isfinite(B) else math.inf
