@@ -8,16 +8,24 @@ overflow where binary64 does not, so the classes come from O32e, not from
 the binary64 oracle.
 
 Envelope gate (every program finite on both sides): |F_gpu - F_O32e| <=
-2 B + 1e-8 |F_O32e| + atol, with B the first-order bound of oracle.bound:
-how far the fitness can move when every approximate operator's result
-carries its stated error (sin, cos, exp, log within 2 ulp, sqrt faithful,
-the library's tan, asin, acos, atan, tanh within 4 ulp) and every correctly
-rounded operator downstream of one re-rounds.  The factor 2 covers the
-second-order terms; 1e-8 |F| the binary64 summation order.  Programs whose
-bound is infinite (a value carrying error lies exactly on a protected
-operator's branch point, or F is the convention for a constant output) are
-counted as "vacuous"; those among them that the value gate does not cover
-either are counted as unchecked and bounded in number.
+B (1 + 1e-6) + 1e-8 |F_O32e| + atol, with B the bound of oracle.bound: how
+far the fitness can move when every approximate operator's result carries
+its stated error (sin, cos, exp, log within 2 ulp, sqrt faithful, the
+library's tan, asin, acos, atan, tanh within 4 ulp) and every correctly
+rounded operator with an inexact operand re-rounds (a running error bound
+per case, combined exactly through the MSE and through r of Eq. 1);
+1e-8 |F| covers the binary64 summation order.  Programs whose bound is
+infinite (on some case a value may reach a pole or a branch point of an
+operator within its error, or F is the convention for a constant output)
+are counted as "vacuous"; those among them that the value gate does not
+cover either are counted as unchecked and bounded in number.
+
+Output gate (the programs neither gate below or above covers: ill
+conditioned with a vacuous bound): the GPU's own per-case outputs (from
+beagle_predict, the same interpreter code) on every case whose per-case
+bound is finite lie within it of O32e's, and the GPU fitness equals the
+oracle's fitness of those outputs (binary64 summation order aside) -- the
+reduction checked exactly, the interpreter everywhere a bound exists.
 
 Value gate (the claim: within 1e-5 of the binary64 oracle):
 |F_gpu - F_O64| <= 1e-5 |F_O64| + atol for every program that is finite in
@@ -35,6 +43,7 @@ from typing import List, NamedTuple
 
 import numpy as np
 
+from oracle import bound as obound
 from oracle import fitness as ofit
 from oracle import population as opop
 
@@ -87,6 +96,7 @@ class Stats(NamedTuple):
     n_finite: int    # programs finite in the fp32-emulating oracle
     n_unchecked: int  # finite programs under neither value gate (ill conditioned and vacuous)
     max_gate: float  # largest |F_gpu - F_O64| / (1e-5 |F_O64| + atol) over the value-gated programs
+    unchecked: tuple = ()  # indices of the unchecked programs (for the output gate)
 
     @property
     def n_checked(self) -> int:
@@ -104,6 +114,7 @@ def check(gpu, refs: Refs, kind, y, max_ill_frac=0.05, label="", max_unchecked_f
     bad_cls = [i for i in range(len(gpu)) if cls_gpu[i] != cls_32[i]]
     assert not bad_cls, (label, "classification", [(i, gpu[i], f32e[i], f64[i]) for i in bad_cls[:10]])
     n_val = n_ill = n_env = n_vac = n_unc = 0
+    unc = []
     max_gate = 0.0
     bad_val, bad_env = [], []
     for i in range(len(gpu)):
@@ -114,13 +125,15 @@ def check(gpu, refs: Refs, kind, y, max_ill_frac=0.05, label="", max_unchecked_f
             n_vac += 1
         else:
             n_env += 1
-            lim = 2.0 * bound[i] + ENV_RTOL * abs(f32e[i]) + at
+            lim = bound[i] * (1.0 + 1e-6) + ENV_RTOL * abs(f32e[i]) + at
             if not abs(gpu[i] - f32e[i]) <= lim:
                 bad_env.append((i, gpu[i], f32e[i], bound[i]))
         if not math.isfinite(f64[i]) or not all(math.isfinite(p[i]) for p in pert) or \
                 max([abs(f32e[i] - f64[i])] + [abs(p[i] - f64[i]) for p in pert]) > RTOL_COND * abs(f64[i]) + at:
             n_ill += 1
-            n_unc += vacuous
+            if vacuous:
+                n_unc += 1
+                unc.append(i)
             continue
         n_val += 1
         err = abs(gpu[i] - f64[i])
@@ -133,4 +146,45 @@ def check(gpu, refs: Refs, kind, y, max_ill_frac=0.05, label="", max_unchecked_f
     assert n_ill <= max_ill_frac * max(finite, 1) + 2, (label, "too many ill-conditioned", n_ill, finite)
     assert n_unc <= max_unchecked_frac * max(finite, 1) + 2, (label, "too many programs unchecked", n_unc, finite)
     assert n_val >= min_value, (label, "no program value-checked", n_val, finite)
-    return Stats(n_val, n_ill, n_env, n_vac, finite, n_unc, max_gate)
+    return Stats(n_val, n_ill, n_env, n_vac, finite, n_unc, max_gate, tuple(unc))
+
+
+def check_outputs(programs, X, y, kind, outs, fitness, label=""):
+    """The output gate for a list of (tokens, consts) programs with the GPU's
+    per-case outputs outs[k] (binary32) and fitness[k]; returns (cases
+    checked, cases without a bound)."""
+    at = atol(kind, y)
+    n_ok = n_free = 0
+    for k, (toks, consts) in enumerate(programs):
+        values, _, d, _ = obound.case_bounds(toks, consts, X)
+        y32, b = values[-1], d[-1]
+        out = np.asarray(outs[k], dtype=np.float64)
+        fin = np.isfinite(b)
+        bad = np.flatnonzero(fin & ~(np.abs(out - y32) <= b * (1.0 + 1e-6)))
+        assert bad.size == 0, (label, "output", k, [(int(i), out[i], y32[i], b[i]) for i in bad[:5]])
+        n_ok += int(fin.sum())
+        n_free += int((~fin).sum())
+        f_own = ofit.fitness(kind, out, y)
+        assert ofit.classify(f_own) == ofit.classify(fitness[k]), (label, "output fitness class", k)
+        if math.isfinite(f_own):
+            assert abs(fitness[k] - f_own) <= ENV_RTOL * abs(f_own) + at, (label, "output fitness", k,
+                                                                             fitness[k], f_own)
+    return n_ok, n_free
+
+
+def output_gate(ps, X, y, kind, gpu_cmp, stats: Stats, idx=None, label=""):
+    """Runs the output gate on the GPU for the programs `stats` left
+    unchecked: gpu_cmp is the fitness array given to check(), idx the
+    program index (in ps) of each of its positions (None: the same).
+    Returns (programs, cases checked, cases without a bound)."""
+    if not stats.unchecked:
+        return 0, 0, 0
+    import torch
+    from paper_2603_12292_amd import api
+    prog = [int(idx[i]) if idx is not None else int(i) for i in stats.unchecked]
+    sub = ps.subset(prog)
+    outs = api.predict(api.DevicePrograms.from_programset(sub), torch.from_numpy(np.ascontiguousarray(X)).cuda())
+    outs = outs.cpu().numpy()
+    ok, free = check_outputs([ps.program(p) for p in prog], X, y, kind, outs,
+                             [float(gpu_cmp[i]) for i in stats.unchecked], label=label)
+    return len(prog), ok, free

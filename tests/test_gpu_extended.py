@@ -94,7 +94,7 @@ def test_population_fitness(kind):
     s = gates.check(gpu[keep], r.take(keep), kind, data.y, max_ill_frac=0.35, max_unchecked_frac=0.1,
                     label=f"extended kind={kind}")
     # about two programs in three are NaN (asin, acos, 1/x) or unstable
-    print(s)
+    print(s, "output gate:", gates.output_gate(ps, data.X, data.y, kind, gpu[keep], s, idx=keep, label="ext"))
     assert s.n_value > 0.18 * ps.n and s.n_checked >= 0.9 * s.n_finite
 
 
@@ -205,5 +205,6 @@ def test_resident_class1_small_case_set(kind):
     keep = [j for j in range(len(sub)) if _class_stable(r.f32, [r.f64] + r.pert, j)]
     s = gates.check(whole[sub][keep], r.take(keep), kind, data.y, max_ill_frac=0.4, max_unchecked_frac=0.1,
                     label=f"resident class 1 {name}")
-    print(s)
+    print(s, "output gate:", gates.output_gate(ps, data.X, data.y, kind, whole[sub][keep], s,
+                                               idx=[sub[j] for j in keep], label="ext resident"))
     assert s.n_value > 20 and s.n_checked >= 0.9 * s.n_finite
