@@ -178,6 +178,28 @@ beagle_status beagle_eval_score(beagle_ctx* ctx, const beagle_programs* progs, c
 beagle_status beagle_eval_workspace_size(const beagle_programs* progs, const beagle_dataset* data, int kind,
                                          size_t* bytes);
 
+/* beagle_eval without a context, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same kernels and results (bit for bit) as
+ * beagle_eval, on the calling thread's current device, with every piece of
+ * workspace taken from one static device array of
+ * BEAGLE_STATIC_SCRATCH_BYTES per device, part of the library's code object
+ * (each device the library runs on holds it until the process ends).  The
+ * call allocates and frees nothing, creates no events and does not tune:
+ * 4 cases per lane (beagle_eval's tile width changes no result bit).  The
+ * caller owns progs, data, fitness and status as for beagle_eval.
+ *   kind    BEAGLE_FIT_MSE or BEAGLE_FIT_CORR
+ * A population whose workspace exceeds the array is evaluated in program
+ * slices (as under a context's workspace cap, identical results); when even
+ * one program's share does not fit, BEAGLE_E_NOMEM and nothing is launched.
+ * Every call on a device shares that device's array and leaves its
+ * contents behind: calls that overlap in time on one device (two streams,
+ * two threads) race and give undefined results; calls on one stream are
+ * ordered and safe. */
+#define BEAGLE_STATIC_SCRATCH_BYTES (32u << 20)
+beagle_status beagle_eval_static(const beagle_programs* progs, const beagle_dataset* data, int kind,
+                                 double* fitness, int8_t* status, beagle_stream stream);
+
 /* Per-case outputs yhat[p * M + i] (binary32) of every program: a debugging
  * and testing aid for small populations (n_programs * M <= 2^31).  Invalid
  * programs give NaN rows. */

@@ -63,6 +63,7 @@ SIGNATURES = [
     ("beagle_ctx_graph_stats", c_int, [c_void_p, POINTER(c_int64), POINTER(c_int64)]),
     ("beagle_ctx_tile_width", c_int, [c_void_p, c_int, c_int32, c_int64, c_int64, c_int32, POINTER(c_int32)]),
     ("beagle_eval", c_int, [c_void_p, POINTER(Programs), POINTER(Dataset), c_int, c_void_p, c_void_p, c_void_p]),
+    ("beagle_eval_static", c_int, [POINTER(Programs), POINTER(Dataset), c_int, c_void_p, c_void_p, c_void_p]),
     ("beagle_eval_batched", c_int, [c_void_p, POINTER(Programs), POINTER(Dataset), c_int32, c_int,
                                     POINTER(c_void_p), POINTER(c_void_p), c_void_p]),
     ("beagle_eval_workspace_size", c_int, [POINTER(Programs), POINTER(Dataset), c_int, POINTER(c_size_t)]),

@@ -204,6 +204,23 @@ def evaluate(progs: DevicePrograms, X: torch.Tensor, y: torch.Tensor, kind="mse"
     return (fit, st) if with_status else fit
 
 
+def evaluate_static(progs: DevicePrograms, X: torch.Tensor, y: torch.Tensor, kind="mse", *,
+                    fitness: Optional[torch.Tensor] = None, status: Optional[torch.Tensor] = None):
+    """beagle_eval_static: the evaluation without a context or any device
+    allocation by the library (workspace in its static per-device array);
+    pass preallocated `fitness` (float64 [N]) and `status` (int8 [N]) to keep
+    the call allocation-free on the Python side too."""
+    dev = progs.device
+    lib = _lib.load()
+    ps = progs.struct()
+    ds = _dataset(X, y, dev)
+    fit = fitness if fitness is not None else torch.empty(progs.n, dtype=torch.float64, device=dev)
+    with torch.cuda.device(dev):
+        _check(lib.beagle_eval_static(ctypes.byref(ps), ctypes.byref(ds), _kind(kind), fit.data_ptr(),
+                                      status.data_ptr() if status is not None else None, _stream(dev)))
+    return fit
+
+
 def evaluate_batched(problems, kind="mse", *, with_status: bool = False, ctx: Optional[Context] = None,
                      out=None):
     """Fitness of several independent problems in one batched launch --

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -161,9 +162,8 @@ EvalLayout eval_layout(const beagle_programs* P, const beagle_dataset* d, int n_
 
 // Validation + decoding of the programs and staging of the cases (shared by
 // evaluation, prediction and the gradient).
-beagle_status prepare(beagle_ctx* ctx, const beagle_programs* P, const beagle_dataset* d, const EvalLayout& L,
+beagle_status prepare(char* ws, const beagle_programs* P, const beagle_dataset* d, const EvalLayout& L,
                       int8_t* status, hipStream_t s, int32_t max_words = bgl::MAX_LEN, bool adjoint = false) {
-  char* ws = ctx->ws;
   zero_i32(reinterpret_cast<int32_t*>(ws + L.class_count), 64, s);
   bgl::PrepareArgs pa;
   pa.tokens = P->tokens;
@@ -210,10 +210,9 @@ beagle_status prepare(beagle_ctx* ctx, const beagle_programs* P, const beagle_da
   return BEAGLE_OK;
 }
 
-beagle_status launch_values(beagle_ctx* ctx, const beagle_programs* P, const beagle_dataset* d,
+beagle_status launch_values(char* ws, const beagle_programs* P, const beagle_dataset* d,
                             const EvalLayout& L, int64_t m, float* out, int shift_mode, hipStream_t s) {
   bgl::ValuesArgs va;
-  char* ws = ctx->ws;
   va.code = reinterpret_cast<const uint32_t*>(ws + L.code);
   va.cval = reinterpret_cast<const float*>(ws + L.cval);
   va.tok_offset = P->tok_offset;
@@ -237,12 +236,11 @@ beagle_status launch_values(beagle_ctx* ctx, const beagle_programs* P, const bea
 // Eq. 2 score).  When the shape takes the resident-inputs kernels, the
 // shifts of classes 0 and 1 come from those kernels' first pass
 // (*in_kernel = true) and only the class-2 programs run the shift pass here.
-beagle_status launch_shifts(beagle_ctx* ctx, const beagle_programs* P, const beagle_dataset* d, const EvalLayout& L,
+beagle_status launch_shifts(char* ws, const beagle_programs* P, const beagle_dataset* d, const EvalLayout& L,
                             hipStream_t s, bool* in_kernel) {
   *in_kernel = bgl::resident_eligible(d->M, d->D, L.n_chunks, P->n_programs);
-  if (!*in_kernel) return launch_values(ctx, P, d, L, 1, nullptr, 1, s);
+  if (!*in_kernel) return launch_values(ws, P, d, L, 1, nullptr, 1, s);
   bgl::ValuesArgs va;
-  char* ws = ctx->ws;
   va.code = reinterpret_cast<const uint32_t*>(ws + L.code);
   va.cval = reinterpret_cast<const float*>(ws + L.cval);
   va.tok_offset = P->tok_offset;
@@ -369,38 +367,37 @@ beagle_status beagle_ctx_set_tuning(beagle_ctx* ctx, int policy) {
 
 namespace {
 
-// Whole-population evaluation of any fitness kind (smax: the maximum score of
-// the paper's scores).
-beagle_status evaluate(beagle_ctx* ctx, const beagle_programs* progs, const beagle_dataset* data, int kind,
-                       double smax, double* fitness, int8_t* status, beagle_stream stream) {
-  beagle_status st = check_programs(progs);
-  if (st != BEAGLE_OK) return st;
-  st = check_data(data, kind);
-  if (st != BEAGLE_OK) return st;
-  if (progs->n_programs == 0) return BEAGLE_OK;
-  if (!fitness) return fail(BEAGLE_E_INVALID_ARG, "fitness is NULL");
-  DeviceGuard g(ctx->device);
-  if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+// Layout of a whole-population evaluation within `cap` bytes of workspace
+// (0: unlimited): the largest program slice whose partials fit.
+EvalLayout capped_layout(const beagle_programs* progs, const beagle_dataset* data, int kind, size_t cap,
+                         int32_t* slice_out) {
   const int n_sums = bgl::kind_sums(kind);
-  // largest program slice whose partials fit the cap (the whole population
-  // when there is no cap)
   int32_t slice = progs->n_programs;
   EvalLayout L = eval_layout(progs, data, n_sums, slice);
-  while (ctx->cap && L.total > ctx->cap && slice > 1) {
+  while (cap && L.total > cap && slice > 1) {
     slice = (slice + 1) / 2;
     L = eval_layout(progs, data, n_sums, slice);
   }
-  st = reserve(ctx, L.total);
+  *slice_out = slice;
+  return L;
+}
+
+// The launches of one whole-population evaluation of any fitness kind
+// (smax: the maximum score of the paper's scores) in workspace ws, laid out
+// by L with `slice` programs per interpreter launch.  With a context, the
+// tile width comes from its tuner and its timing events bracket each
+// interpreter launch; without one, 4 cases per lane (the width changes no
+// result bit) and nothing is created.
+beagle_status evaluate_in(char* ws, const EvalLayout& L, int32_t slice, beagle_ctx* ctx,
+                          const beagle_programs* progs, const beagle_dataset* data, int kind, double smax,
+                          double* fitness, int8_t* status, hipStream_t s) {
+  beagle_status st = prepare(ws, progs, data, L, status, s);
   if (st != BEAGLE_OK) return st;
-  st = prepare(ctx, progs, data, L, status, s);
-  if (st != BEAGLE_OK) return st;
-  char* ws = ctx->ws;
   bool shift_in_kernel = false;
   if (kind == BEAGLE_FIT_CORR || kind == BEAGLE_FIT_R4) {
     hipLaunchKernelGGL(bgl::k_target_stats, dim3(1), dim3(1024), 0, s, data->y, data->M,
                        reinterpret_cast<double*>(ws + L.stats));
-    st = launch_shifts(ctx, progs, data, L, s, &shift_in_kernel);
+    st = launch_shifts(ws, progs, data, L, s, &shift_in_kernel);
     if (st != BEAGLE_OK) return st;
   }
   auto slice_args = [&](int32_t p0, int32_t np) {
@@ -428,8 +425,8 @@ beagle_status evaluate(beagle_ctx* ctx, const beagle_programs* progs, const beag
     ea.meta_shift = shift_in_kernel ? reinterpret_cast<bgl::ProgMeta*>(ws + L.meta) + p0 : nullptr;
     return ea;
   };
-  int kv = 0;
-  {
+  int kv = 1;
+  if (ctx) {
     TuneSlice ts{kind, slice_args(0, std::min(slice, progs->n_programs))};
     st = tile_variant(ctx, kind, data->D, data->M, double(progs->n_tokens) / progs->n_programs, s, run_slice, &ts,
                       &kv);
@@ -439,7 +436,7 @@ beagle_status evaluate(beagle_ctx* ctx, const beagle_programs* progs, const beag
     const int32_t np = std::min(slice, progs->n_programs - p0);
     const bgl::EvalArgs ea = slice_args(p0, np);
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    if (ctx->timing) {
+    if (ctx && ctx->timing) {
       if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
         return fail(BEAGLE_E_HIP, "hipEventCreate");
       ctx->events.emplace_back(ev0, ev1);
@@ -461,11 +458,87 @@ beagle_status evaluate(beagle_ctx* ctx, const beagle_programs* progs, const beag
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "finalize launch");
   }
+  return BEAGLE_OK;
+}
+
+// Whole-population evaluation in a context's workspace.
+beagle_status evaluate(beagle_ctx* ctx, const beagle_programs* progs, const beagle_dataset* data, int kind,
+                       double smax, double* fitness, int8_t* status, beagle_stream stream) {
+  beagle_status st = check_programs(progs);
+  if (st != BEAGLE_OK) return st;
+  st = check_data(data, kind);
+  if (st != BEAGLE_OK) return st;
+  if (progs->n_programs == 0) return BEAGLE_OK;
+  if (!fitness) return fail(BEAGLE_E_INVALID_ARG, "fitness is NULL");
+  DeviceGuard g(ctx->device);
+  if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int32_t slice = 0;
+  const EvalLayout L = capped_layout(progs, data, kind, ctx->cap, &slice);
+  st = reserve(ctx, L.total);
+  if (st != BEAGLE_OK) return st;
+  st = evaluate_in(ctx->ws, L, slice, ctx, progs, data, kind, smax, fitness, status, s);
+  if (st != BEAGLE_OK) return st;
   clear_error();
   return BEAGLE_OK;
 }
 
+// Workspace of beagle_eval_static: one array per device, in the library's
+// code object, never allocated or freed by a call.  In host code `scratch`
+// names a host-side stand-in; its device address on each device comes from
+// hipGetSymbolAddress with that device current (scratch_on).
+static __device__ __align__(256) char scratch[BEAGLE_STATIC_SCRATCH_BYTES];
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static char* g_scratch[MAX_DEVICES] = {};
+
+beagle_status scratch_on(int dev, char** out) {
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(BEAGLE_E_UNSUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch[dev] = static_cast<char*>(ptr);
+  }
+  *out = g_scratch[dev];
+  return BEAGLE_OK;
+}
+
 }  // namespace
+
+extern "C" {
+
+beagle_status beagle_eval_static(const beagle_programs* progs, const beagle_dataset* data, int kind, double* fitness,
+                                 int8_t* status, beagle_stream stream) {
+  if (kind != BEAGLE_FIT_MSE && kind != BEAGLE_FIT_CORR)
+    return fail(BEAGLE_E_INVALID_ARG, "unknown fitness kind (MSE or CORR)");
+  beagle_status st = check_programs(progs);
+  if (st != BEAGLE_OK) return st;
+  st = check_data(data, kind);
+  if (st != BEAGLE_OK) return st;
+  if (progs->n_programs == 0) return BEAGLE_OK;
+  if (!fitness) return fail(BEAGLE_E_INVALID_ARG, "fitness is NULL");
+  int32_t slice = 0;
+  const EvalLayout L = capped_layout(progs, data, kind, BEAGLE_STATIC_SCRATCH_BYTES, &slice);
+  if (L.total > BEAGLE_STATIC_SCRATCH_BYTES)
+    return fail(BEAGLE_E_NOMEM, "beagle_eval_static: the evaluation needs " + std::to_string(L.total) +
+                                    " bytes of scratch, the static array holds " +
+                                    std::to_string(size_t(BEAGLE_STATIC_SCRATCH_BYTES)));
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  char* ws = nullptr;
+  st = scratch_on(dev, &ws);
+  if (st != BEAGLE_OK) return st;
+  st = evaluate_in(ws, L, slice, nullptr, progs, data, kind, 0.0, fitness, status,
+                   reinterpret_cast<hipStream_t>(stream));
+  if (st != BEAGLE_OK) return st;
+  clear_error();
+  return BEAGLE_OK;
+}
+
+}  // extern "C"
 
 extern "C" {
 
@@ -516,9 +589,9 @@ beagle_status beagle_predict(beagle_ctx* ctx, const beagle_programs* progs, cons
   EvalLayout L = eval_layout(progs, data, 1, 1);
   st = reserve(ctx, L.total);
   if (st != BEAGLE_OK) return st;
-  st = prepare(ctx, progs, data, L, status, s);
+  st = prepare(ctx->ws, progs, data, L, status, s);
   if (st != BEAGLE_OK) return st;
-  st = launch_values(ctx, progs, data, L, data->M, yhat, 0, s);
+  st = launch_values(ctx->ws, progs, data, L, data->M, yhat, 0, s);
   if (st != BEAGLE_OK) return st;
   clear_error();
   return BEAGLE_OK;
@@ -749,7 +822,7 @@ beagle_status corr_pass(beagle_ctx* ctx, const beagle_programs* progs, const bea
   hipLaunchKernelGGL(bgl::k_target_stats, dim3(1), dim3(1024), 0, s, data->y, data->M,
                      reinterpret_cast<double*>(ws + L.stats));
   bool shift_in_kernel = false;
-  beagle_status st = launch_shifts(ctx, progs, data, L, s, &shift_in_kernel);
+  beagle_status st = launch_shifts(ws, progs, data, L, s, &shift_in_kernel);
   if (st != BEAGLE_OK) return st;
   bgl::EvalArgs ea;
   ea.code = reinterpret_cast<const uint32_t*>(ws + L.code);
@@ -818,7 +891,7 @@ beagle_status beagle_eval_grad(beagle_ctx* ctx, const beagle_programs* progs, co
   EvalLayout L = eval_layout(progs, data, corr ? 3 : 1, progs->n_programs, true);
   st = reserve(ctx, L.total);
   if (st != BEAGLE_OK) return st;
-  st = prepare(ctx, progs, data, L, status, s, bgl::GRAD_LONG_WORDS, true);
+  st = prepare(ctx->ws, progs, data, L, status, s, bgl::GRAD_LONG_WORDS, true);
   if (st != BEAGLE_OK) return st;
   char* ws = ctx->ws;
   if (corr) {
