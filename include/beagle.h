@@ -67,9 +67,11 @@ typedef enum {
 
 /* Fitness kinds (section 2.1.5).  MSE = (1/M) sum (yhat - y)^2.  CORR =
  * 1 - r^2 with r Pearson's correlation (Eq. 1), its sums accumulated in
- * binary64 and clamped to [0, 1].  Classification: MSE is NaN if any yhat is
- * NaN, else +Inf if any yhat is +-Inf; CORR is NaN if any yhat is not
- * finite, 1 if every yhat is equal, NaN if every y is equal.
+ * binary64 and clamped to [0, 1].  Classification: MSE follows IEEE
+ * arithmetic of its case terms yhat - y: NaN if any is NaN (a NaN output or
+ * target, or an infinite output meeting the same infinite target), else
+ * +Inf if any is infinite; CORR is NaN if any yhat or y is not finite, 1 if
+ * every yhat is equal, NaN if every y is equal.
  * POINT and R4 are the paper's own scores (higher is better; see
  * beagle_eval_score): POINT the sum over cases of Eq. 3, R4 Eq. 2. */
 typedef enum {
