@@ -28,23 +28,28 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# fp32 VALU issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = one
-# non-packed fp32 lane operation per lane per clock (the 157.3 TFLOP/s figure
-# counts a packed two-wide FMA as 4 flops; a stack interpreter issues neither).
+# MI355X's published fp32 vector peak (256 CUs x 256 flop/clock x 2.4 GHz;
+# it counts a packed two-wide FMA as four flops): the roofline denominator.
+PEAK_FP32 = 157.3e12
+# its non-packed fp32 lane-operation issue rate, 256 CUs x 4 SIMDs x 16
+# lanes x 2.4 GHz: the denominator of the issue fraction measured by counters
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 HBM_PEAK = 8.0e12
+# binary64 operations of the fitness epilogue per program and case
+# (MSE: difference, square-add, mask; 1 - r^2: u, w, three sums)
+EPILOGUE_OPS = {"mse": 3, "corr": 5}
 
 
 def function_nodes(ps) -> int:
     ops = ps.tokens & 0xFF
-    return int(np.count_nonzero(ops < 9))
+    return int(np.count_nonzero((ops < 9) | (ops > 10)))
 
 
 def committed_counters(kernel: str) -> dict:
     """Counter figures of the interpreter kernel from the committed profile
-    summary (HBM bytes per launch, VALU issue fraction), or {} when the kernel
-    source changed since they were taken or they are of another tile-width
-    variant."""
+    summary (HBM bytes per launch, VALU and SALU instructions), or {} when
+    the kernel source changed since they were taken or they are of another
+    tile-width variant."""
     from paper_2603_12292_amd.profiling import source_hash
     path = os.path.join(ROOT, "profiles", "k_eval_class_corr_plain_mid_traffic.json")
     if not os.path.exists(path):
@@ -56,21 +61,136 @@ def committed_counters(kernel: str) -> dict:
     return rec
 
 
-def cpu_baseline(w, kind_id, budget_programs: int):
+def job_cores() -> int:
+    """Host cores this job may use: its affinity mask, limited by the thread
+    allotment it runs under (OMP_NUM_THREADS, which a shared GPU machine sets to
+    the job's CPU share)."""
+    n = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return n
+
+
+def _pool_map(fn, items, cores):
+    """fn over items in a process pool (fork: called before this process
+    starts the GPU runtime), results in order."""
+    if cores <= 1:
+        return [fn(x) for x in items]
+    import multiprocessing as mp
+    before = os.environ.get("OMP_NUM_THREADS")
+    os.environ["OMP_NUM_THREADS"] = "1"
+    try:
+        with mp.get_context("fork").Pool(cores) as pool:
+            return pool.map(fn, items, chunksize=1)
+    finally:
+        if before is None:
+            os.environ.pop("OMP_NUM_THREADS", None)
+        else:
+            os.environ["OMP_NUM_THREADS"] = before
+
+
+def _oracle_eval(ps, data, kind_id, cores, subset=None):
+    """(seconds, fitness[...], node-cases) of the binary64 oracle."""
     from oracle import population as opop
-    ps = w.programs
-    # the pool's processes (one when the GPU runtime already runs: no fork then)
-    cores = 1 if opop._gpu_runtime_started() else min(16, len(os.sched_getaffinity(0)))
-    step = max(1, ps.n // budget_programs)
-    sub = list(range(0, ps.n, step))[:budget_programs]
-    nodes = int(ps.tok_len[sub].astype(np.int64).sum())
+    idx = list(range(ps.n)) if subset is None else list(subset)
+    nodes = int(ps.tok_len[idx].astype(np.int64).sum())
     t0 = time.perf_counter()
-    opop.evaluate_population(ps.tokens, ps.tok_offset, ps.tok_len, ps.consts, ps.const_offset, ps.const_count,
-                             w.data.X, w.data.y, kind_id, "o64", subset=sub, processes=cores)
-    dt = time.perf_counter() - t0
-    return {"value": nodes * w.data.M / dt / 1e9, "unit": "GPop/s", "cores": cores, "kind": "oracle",
-            "sample": f"{len(sub)} of {ps.n} programs (every {step}), all {w.data.M} cases, "
-                      f"correlation fitness, float64 oracle, {dt:.1f} s wall"}
+    f, _ = opop.evaluate_population(ps.tokens, ps.tok_offset, ps.tok_len, ps.consts, ps.const_offset,
+                                    ps.const_count, data.X, data.y, kind_id, "o64", subset=idx, processes=cores)
+    return time.perf_counter() - t0, f, nodes * data.M
+
+
+def _grad_one(args):
+    from oracle import grad as og
+    toks, consts, X, y = args
+    return og.mse_and_grad(toks, consts, X, y)
+
+
+def cpu_baselines(w, cores, ragged):
+    """The binary64 CPU oracle, timed on this host before the GPU runtime
+    starts: the benchmark workload in full (the contract's cpu_baseline,
+    also kept for the parity statistics), and the other workloads on the
+    bounded samples stated in each entry."""
+    from paper_2603_12292_amd import workloads as wl
+    dt, f64, nc = _oracle_eval(w.programs, w.data, 1, cores)
+    main = {"value": nc / dt / 1e9, "unit": "GPop/s", "cores": cores, "kind": "oracle",
+            "sample": f"{w.programs.n} of {w.programs.n} programs, all {w.data.M} cases, correlation fitness, "
+                      f"float64 oracle, {dt:.1f} s wall"}
+    other = {}
+    tiny = wl.config_tiny()
+    for kid, name in ((0, "mse"), (1, "corr")):
+        d, _, n = _oracle_eval(tiny.programs, tiny.data, kid, cores)
+        other[f"plain_tiny_{name}"] = {"value": round(n / d / 1e9, 4), "unit": "GPop/s", "cores": cores,
+                                       "sample": f"all 256 programs x 1000 cases, {d:.2f} s"}
+    d, _, n = _oracle_eval(w.programs, w.data, 0, cores, subset=range(0, w.programs.n, 8))
+    other["plain_mid_mse"] = {"value": round(n / d / 1e9, 4), "unit": "GPop/s", "cores": cores,
+                              "sample": f"SUBSET: 512 of 4096 programs (every 8th), all 100000 cases, {d:.2f} s"}
+    # generation loop: one generation's evaluation on a program sample,
+    # scaled to the population, plus the oracle's whole variation step
+    from oracle import gp
+    gd = wl.generation_dataset()
+    params = gp.GenParams()
+    pop = gp.init_population(16384, gd.D, params, 2606)
+    ps0 = wl.pack_programs(pop)
+    sub = list(range(0, 16384, 256))
+    d_e, f_e, n_e = _oracle_eval(ps0, gd, 0, cores, subset=sub)
+    fit = np.arange(16384, dtype=np.float64) * 1e-3   # any ordering: the step's cost
+    fit[sub] = f_e
+    t0 = time.perf_counter()
+    gp.generation([t for t, _ in pop], [c for _, c in pop], fit, gd.D, params, 2606, 1)
+    d_v = time.perf_counter() - t0
+    eval_s = d_e * 16384 / len(sub)
+    other["generation_loop"] = {
+        "eval_gpops": round(n_e / d_e / 1e9, 4), "unit": "GPop/s", "cores": cores,
+        "s_per_generation": round(eval_s + d_v, 2), "s_51_evaluations_50_steps": round(51 * eval_s + 50 * d_v, 1),
+        "sample": f"EXTRAPOLATED: generation 0 evaluated on 64 of 16384 programs (every 256th) x 10^6 cases "
+                  f"({d_e:.2f} s) scaled to the population, one whole variation step (16384 children, one core, "
+                  f"{d_v:.2f} s); the loop's 51 evaluations and 50 steps scaled from these"}
+    # ragged batching: every 8th problem, every 32nd program of it
+    nc_all = sum(q.programs.node_count() * q.data.M for q in ragged)
+    tot_s = tot_n = 0
+    for q in ragged[::8]:
+        d, _, n = _oracle_eval(q.programs, q.data, 0, cores, subset=range(0, q.programs.n, 32))
+        tot_s += d
+        tot_n += n
+    other["ragged"] = {"value": round(tot_n / tot_s / 1e9, 4), "unit": "GPop/s", "cores": cores,
+                       "s_whole_workload": round(tot_s * nc_all / tot_n, 1),
+                       "sample": f"SUBSET: 8 of 64 problems (every 8th) x 32 of 1024 programs (every 32nd), "
+                                 f"{tot_n:.3g} of {nc_all:.3g} node-cases ({tot_s:.1f} s); the whole-workload "
+                                 f"time scaled by node-cases"}
+    # differentiation: forward and forward + gradient on 64 programs
+    dw = wl.config_differentiation()
+    sub = list(range(0, dw.programs.n, 64))
+    d_f, _, n_f = _oracle_eval(dw.programs, dw.data, 0, cores, subset=sub)
+    args = []
+    for p in sub:
+        t, c = dw.programs.program(p)
+        args.append((t, c, dw.data.X, dw.data.y))
+    t0 = time.perf_counter()
+    _pool_map(_grad_one, args, cores)
+    d_g = time.perf_counter() - t0
+    other["differentiation"] = {"fwd_gpops": round(n_f / d_f / 1e9, 4),
+                                "fwd_adjoint_gpops": round(n_f / d_g / 1e9, 4), "unit": "GPop/s", "cores": cores,
+                                "sample": f"SUBSET: 64 of 4096 programs (every 64th) x 100000 cases, MSE: forward "
+                                          f"{d_f:.2f} s, fitness and constant gradients {d_g:.2f} s"}
+    return main, other, f64
+
+
+def parity_stats(gpu, f64_fresh, w, kind_id):
+    """Gate statistics of the GPU fitness of every program of the benchmark
+    workload against the oracle's stored values (tests/golden), after
+    checking that the oracle run above reproduces the stored binary64 ones."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import gates
+    import golden_mid
+    refs = golden_mid.load(w)[kind_id]
+    same = None if f64_fresh is None else bool(np.array_equal(f64_fresh, refs.f64, equal_nan=True))
+    s = gates.check(gpu, refs, kind_id, w.data.y, max_ill_frac=1.0, max_unchecked_frac=1.0, min_value=0)
+    return {"programs": int(len(gpu)), "finite": s.n_finite, "value_gate_1e-5": s.n_value,
+            "ill_conditioned": s.n_ill, "envelope_gate": s.n_env, "bound_vacuous": s.n_vacuous,
+            "unchecked": s.n_unchecked, "max_err_over_gate": round(float(s.max_gate), 4),
+            "all_gates_pass": True, "oracle_rerun_matches_stored": same}
 
 
 def adjoint_bench(steps: int, warmup: int):
@@ -268,15 +388,13 @@ def paper_loop_bench(generations: int, op_set: int = 0):
             "mean_len_last": round(tokens[-1] / paper_pop_size(generations - 1), 2)}
 
 
-def ragged_bench(steps: int, warmup: int):
+def ragged_bench(ws, steps: int, warmup: int):
     """The 64-problem ragged workload (1024 programs each, L~U{5..96},
     D~U{1..9}, M=round(10^U(3,6)), MSE): one batched call (a replayed HIP
     graph over all problems) against 64 separate beagle_eval calls, both on
     torch's current stream, inputs resident."""
     import torch
     from paper_2603_12292_amd import api
-    from paper_2603_12292_amd import workloads as wl
-    ws = wl.ragged_problems()
     dev = [(api.DevicePrograms.from_programset(w.programs, "cuda:0"), torch.from_numpy(w.data.X).cuda(),
             torch.from_numpy(w.data.y).cuda()) for w in ws]
     out = [torch.empty(p.n, dtype=torch.float64, device="cuda") for p, _, _ in dev]
@@ -354,13 +472,30 @@ def generation_bench(generations: int):
             "mean_len_first": round(tokens[0] / N, 2), "mean_len_last": round(tokens[-1] / N, 2)}
 
 
+def plain_rate(w, kind, steps, warmup, ctx):
+    """GPop/s of whole beagle_eval calls on one workload (inputs resident)."""
+    import torch
+    from paper_2603_12292_amd import api
+    progs = api.DevicePrograms.from_programset(w.programs, "cuda:0")
+    X = torch.from_numpy(w.data.X).cuda()
+    y = torch.from_numpy(w.data.y).cuda()
+    for _ in range(max(1, warmup)):
+        api.evaluate(progs, X, y, kind, ctx=ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fit = api.evaluate(progs, X, y, kind, ctx=ctx)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    return w.programs.node_count() * w.data.M / dt / 1e9, dt, fit.cpu().numpy()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-programs", type=int, default=4096)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-ragged", action="store_true")
     ap.add_argument("--no-scores", action="store_true", help="skip the paper's Eq. 2 / Eq. 3 score rates")
@@ -374,15 +509,17 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import torch
-    from paper_2603_12292_amd import api
     from paper_2603_12292_amd import workloads as wl
 
     w = wl.config_mid()
     ps = w.programs
+    ragged = wl.ragged_problems() if not (args.no_ragged and args.no_cpu_baseline) else None
     # the CPU oracle first: its worker processes are forked before this
     # process starts the GPU runtime (forking after that is not safe)
-    cpu = cpu_baseline(w, 1, args.cpu_programs) if not args.no_cpu_baseline else None
+    cpu = cpu_baselines(w, job_cores(), ragged) if not args.no_cpu_baseline else None
+
+    import torch
+    from paper_2603_12292_amd import api
     dev = torch.device("cuda:0")
     progs = api.DevicePrograms.from_programset(ps, dev)
     X = torch.from_numpy(w.data.X).to(dev)
@@ -405,16 +542,24 @@ def main():
     ctx.enable_timing(False)
     dt = t1 - t0
     gpops = nodes * M * args.steps / dt / 1e9
-    assert np.isfinite(fit.cpu().numpy()).sum() > 0
+    fit = fit.cpu().numpy()
+    assert np.isfinite(fit).sum() > 0
 
     width = ctx.tile_width("corr", w.data.D, M, int(ps.tokens.size), ps.n)
     kernel = f"k_eval_class<1, 0, {0 if width == 8 else 1}>"
     k_avg_s = k_ms / 1e3 / max(k_n, 1)
     fn = function_nodes(ps)
-    alg_ops = fn * M                       # one fp32 op per operator application
+    # algorithmic work of one launch: one operation per operator application
+    # (binary or unary; terminals move data) plus the binary64 epilogue per
+    # program and case
+    alg_ops = fn * M + EPILOGUE_OPS["corr"] * ps.n * M
     achieved = alg_ops / k_avg_s
     counters = committed_counters(kernel)
     traffic = counters.get("hbm_bytes_per_launch")
+    node_cases = nodes * M
+    valu = counters.get("valu_insts_per_launch")
+    salu = counters.get("salu_insts_per_launch")
+    wave_tiles = -(-M // (64 * width))           # passes of one wave over the cases of a program
     out = {
         "metric": "GPop/s (program-node x fitness-case evals/s), fwd and fwd+adjoint, 1 MI355X",
         "value": round(gpops, 2),
@@ -431,15 +576,31 @@ def main():
         "config": {"workload": "plain-mid: N=4096 programs, L~U{5..64}, D=5, M=100000, X~U(1,10), "
                                "20-token target, correlation fitness 1-r^2",
                    "programs": ps.n, "fitness_cases": M, "nodes": nodes, "kind": "corr"},
-        "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 4), "peak": round(PEAK_LANE_OPS / 1e12, 2),
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_LANE_OPS, 4),
+        "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 4), "peak": round(PEAK_FP32 / 1e12, 1),
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32, 4),
                      "traffic": traffic,
                      "kernel": f"{kernel}: correlation fitness, register need <= 4, {width} cases per lane",
                      "kernel_ms": round(k_avg_s * 1e3, 4), "alg_ops_per_launch": alg_ops,
-                     "kernel_gpops": round(nodes * M / k_avg_s / 1e9, 2),
+                     "kernel_gpops": round(node_cases / k_avg_s / 1e9, 2),
                      "valu_issue_frac": (round(counters["valu_issue_frac"], 4)
-                                         if "valu_issue_frac" in counters else None)},
+                                         if "valu_issue_frac" in counters else None),
+                     "valu_issue_peak_lane_ops": round(PEAK_LANE_OPS / 1e12, 2),
+                     "valu_lane_ops_per_node_case": round(valu * 64 / node_cases, 3) if valu else None,
+                     "salu_insts_per_node_per_wave": (round(salu / (nodes * wave_tiles), 2) if salu else None)},
     }
+    if cpu is not None:
+        main_cpu, other_cpu, f64 = cpu
+        out["parity"] = parity_stats(fit, f64, w, 1)
+    mid_mse, _, fit_mse = plain_rate(w, "mse", args.steps, args.warmup, ctx)
+    out["plain_mid_mse"] = {"workload": "plain-mid, MSE", "gpops": round(mid_mse, 2)}
+    if cpu is not None:
+        out["plain_mid_mse"]["parity"] = parity_stats(fit_mse, None, w, 0)
+    tiny = wl.config_tiny()
+    out["plain_tiny"] = {"workload": tiny.name}
+    for kind in ("mse", "corr"):
+        g, d, _ = plain_rate(tiny, kind, args.steps, args.warmup, ctx)
+        out["plain_tiny"][f"{kind}_gpops"] = round(g, 3)
+        out["plain_tiny"][f"{kind}_us"] = round(d * 1e6, 1)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_bench(args.steps, args.warmup)
     if not args.no_scores:
@@ -447,14 +608,15 @@ def main():
     if not args.no_paper_shape:
         out["paper_shape"] = paper_shape_bench(args.steps, args.warmup)
     if not args.no_ragged:
-        out["ragged"] = ragged_bench(max(1, args.steps // 4), max(1, args.warmup))
+        out["ragged"] = ragged_bench(ragged, max(1, args.steps // 4), max(1, args.warmup))
     if args.generations > 0:
         out["generation_loop"] = generation_bench(args.generations)
     if args.paper_loop > 0:
         out["paper_loop"] = paper_loop_bench(args.paper_loop)
         out["paper_loop_16_ops"] = paper_loop_bench(args.paper_loop, op_set=1)
     if cpu is not None:
-        out["cpu_baseline"] = cpu
+        out["cpu_baseline"] = main_cpu
+        out["cpu_baselines_other"] = other_cpu
     print(json.dumps(out), flush=True)
 
 

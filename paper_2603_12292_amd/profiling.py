@@ -13,6 +13,15 @@
       (HBM bytes per launch of the interpreter kernel, with the hash of the
       kernel sources the counters were taken on).
 
+  python -m paper_2603_12292_amd.profiling ops
+      one evaluation per single-operator program shape (see OP_SHAPES), each
+      a population of 1024 identical programs on 2^17 cases, MSE, 4 cases
+      per lane: run under rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_SALU.
+
+  python -m paper_2603_12292_amd.profiling summarize-ops --pmc CSV --out PREFIX
+      per-operator VALU lane-operations and SALU instructions per node-case
+      from that run (PREFIX.txt).
+
 FETCH_SIZE and WRITE_SIZE count KiB moved between L2 and memory per
 dispatch; each is scaled by (known bytes / counted bytes) of the calibration
 copy, which reads and writes exactly COPY_BYTES.  SQ_INSTS_VALU (wave-level
@@ -71,10 +80,105 @@ def run(steps: int, adjoint: bool = False):
     print(f"profiled {steps} evaluation(s) of {w.name} and a {COPY_BYTES} byte copy", flush=True)
 
 
+# Single-operator program shapes (D = 1, x0 in [1, 2]).  Every shape's cost
+# above the one-token program "x0" is divided by its count of the measured
+# unit: a unary operator; a "push x0, binary operator" pair whose right
+# operand is a square root (its cost subtracted; the pair is not fused); a
+# fused word "binary operator with a variable or constant operand" (two
+# nodes, one decoded word).
+OPS_N = 1024
+OPS_M = 1 << 17
+UNARY_NAMES = ("sin", "cos", "exp", "log", "sqrt")
+BINARY_NAMES = ("+", "-", "*", "/")
+
+
+def op_shapes():
+    """[(name, tokens, consts, units, subtract)]; subtract: (shape, count)
+    whose per-unit cost is removed first, or None."""
+    from paper_2603_12292_amd import workloads as wl
+    V, C = wl.tok(wl.VAR, 0), wl.tok(wl.CONST, 0)
+    un = dict(zip(UNARY_NAMES, (wl.SIN, wl.COS, wl.EXP, wl.LOG, wl.SQRT)))
+    bi = dict(zip(BINARY_NAMES, (wl.ADD, wl.SUB, wl.MUL, wl.DIV)))
+    out = [("x0 (base)", [V], [], 0, None)]
+    for n, op in un.items():
+        out.append((n, [V] + [wl.tok(op)] * 63, [], 63, None))
+    for n, op in bi.items():
+        # x0 (x0 sqrt b)^21: 21 pushes, 21 square roots, 21 unfused binaries
+        out.append((f"push+{n}", [V] + [V, wl.tok(wl.SQRT), wl.tok(op)] * 21, [], 21, ("sqrt", 21)))
+        out.append((f"fused x0 {n}", [V] + [V, wl.tok(op)] * 31, [], 31, None))
+        out.append((f"fused c0 {n}", [V] + [C, wl.tok(op)] * 31, [0.75], 31, None))
+    return out
+
+
+def run_ops():
+    import numpy as np
+    import torch
+    sys.path.insert(0, ROOT)
+    from paper_2603_12292_amd import api
+    from paper_2603_12292_amd import workloads as wl
+    rng = np.random.default_rng(5)
+    X = torch.from_numpy(rng.uniform(1.0, 2.0, (OPS_M, 1)).astype(np.float32)).cuda()
+    y = torch.from_numpy(rng.uniform(0.0, 1.0, OPS_M).astype(np.float32)).cuda()
+    ctx = api.Context(0)
+    ctx.set_tuning("narrow")
+    for name, toks, consts, _, _ in op_shapes():
+        ps = wl.pack_programs([(toks, consts)] * OPS_N)
+        api.evaluate(api.DevicePrograms.from_programset(ps, "cuda:0"), X, y, "mse", ctx=ctx)
+        torch.cuda.synchronize()
+        print(f"evaluated shape {name!r}", flush=True)
+    ctx.close()
+
+
+def summarize_ops(pmc_csv, out_prefix, command):
+    per, names = _counter_rows(pmc_csv)
+    # each evaluation launches one interpreter kernel per register-need
+    # class; every shape here is class 0 at 4 cases per lane
+    evals = [d for d in sorted(per) if "k_eval_class<0, 0, 1>" in names[d]]
+    shapes = op_shapes()
+    assert len(evals) == len(shapes), (len(evals), len(shapes))
+    row = {s[0]: per[d] for s, d in zip(shapes, evals)}
+    base = row["x0 (base)"]
+    cases = OPS_N * OPS_M
+    res = {}
+    for name, toks, _, units, sub in shapes:
+        if units == 0:
+            continue
+        v = (row[name]["SQ_INSTS_VALU"] - base["SQ_INSTS_VALU"]) * 64 / cases
+        sa = (row[name]["SQ_INSTS_SALU"] - base["SQ_INSTS_SALU"]) * 64 / cases
+        if sub:
+            v -= res[sub[0]][0] * sub[1]
+            sa -= res[sub[0]][1] * sub[1]
+        res[name] = (v / units, sa / units)
+    lines = [f"command: {command}",
+             f"kernel k_eval_class<0, 0, 1> (MSE, register need <= 4, 4 cases per lane), source hash {source_hash()}",
+             f"{OPS_N} identical programs per shape, D = 1, M = {OPS_M}, x0 ~ U(1, 2); cost above the program x0",
+             "per unit and case: SQ_INSTS_VALU x 64 (VALU lane-operations) and SQ_INSTS_SALU x 64 (scalar",
+             "instructions per 64 cases).  Units: a unary operator; push+b = pushing x0 and an unfused binary b",
+             "(right operand a square root, its cost subtracted); fused = one decoded word, two nodes.",
+             "",
+             f"{'unit':<14} {'VALU lane-ops':>14} {'SALU x64':>10}"]
+    for name, (v, sa) in res.items():
+        lines.append(f"{name:<14} {v:14.2f} {sa:10.2f}")
+    with open(out_prefix + ".txt", "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def _counter_csv(path):
+    """The counter CSV of a rocprofv3 run: `path` itself, or the one file
+    named *counter_collection.csv below it."""
+    if os.path.isdir(path):
+        found = glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True)
+        if len(found) != 1:
+            raise FileNotFoundError(f"expected one counter_collection.csv below {path}, found {found}")
+        return found[0]
+    return path
+
+
 def _counter_rows(path):
     per = defaultdict(dict)
     names = {}
-    with open(path) as f:
+    with open(_counter_csv(path)) as f:
         for r in csv.DictReader(f):
             d = int(r["Dispatch_Id"])
             per[d][r["Counter_Name"]] = float(r["Counter_Value"])
@@ -126,14 +230,18 @@ def summarize(trace_dir, fetch_csv, write_csv, out_prefix, command, valu_csv=Non
             lines.append(f"  fetch {fetch / 1e6:.3f} MB  write {write / 1e6:.3f} MB  total {(fetch + write) / 1e6:.3f} MB")
     if valu_csv and kernel and kern_ms:
         ve, _ = _counter(valu_csv, "SQ_INSTS_VALU", kernel)
+        se, _ = _counter(valu_csv, "SQ_INSTS_SALU", kernel)
         if ve:
             lane_ops = ve[-1] * 64
             rate = lane_ops / (kern_ms * 1e-3)
-            rec.update({"valu_lane_ops_per_launch": lane_ops, "valu_lane_ops_per_s": rate,
-                        "valu_issue_frac": rate / PEAK_LANE_OPS})
+            rec.update({"valu_insts_per_launch": ve[-1], "valu_lane_ops_per_launch": lane_ops,
+                        "valu_lane_ops_per_s": rate, "valu_issue_frac": rate / PEAK_LANE_OPS})
             lines.append("")
             lines.append(f"VALU issue (SQ_INSTS_VALU x 64 / traced average duration): {lane_ops:.4g} lane-ops per launch, "
                          f"{rate / 1e12:.2f} T lane-ops/s = {rate / PEAK_LANE_OPS:.3f} of {PEAK_LANE_OPS / 1e12:.1f} T")
+        if se:
+            rec["salu_insts_per_launch"] = se[-1]
+            lines.append(f"SALU instructions per launch (SQ_INSTS_SALU): {se[-1]:.4g}")
     lines.insert(0, f"command: {command}")
     lines.insert(1, f"kernel {kernel}, source hash {rec['source_hash']}")
     with open(out_prefix + ".txt", "w") as f:
@@ -157,9 +265,18 @@ def main():
     s.add_argument("--valu")
     s.add_argument("--out", required=True)
     s.add_argument("--command", default="")
+    sub.add_parser("ops")
+    so = sub.add_parser("summarize-ops")
+    so.add_argument("--pmc", required=True)
+    so.add_argument("--out", required=True)
+    so.add_argument("--command", default="")
     a = ap.parse_args()
     if a.cmd == "run":
         run(a.steps, a.adjoint)
+    elif a.cmd == "ops":
+        run_ops()
+    elif a.cmd == "summarize-ops":
+        summarize_ops(a.pmc, a.out, a.command)
     else:
         summarize(a.trace, a.fetch, a.write, a.out, a.command, a.valu)
 
