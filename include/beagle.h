@@ -94,7 +94,8 @@ enum {
   BEAGLE_PROG_BAD_VAR = 5,         /* VAR arg >= D                              */
   BEAGLE_PROG_BAD_CONST = 6,       /* CONST arg >= const_count                  */
   BEAGLE_PROG_TOO_LONG = 7,        /* tok_len > BEAGLE_MAX_LEN                  */
-  BEAGLE_PROG_BAD_LAYOUT = 8       /* offsets/lengths outside the given arrays  */
+  BEAGLE_PROG_BAD_LAYOUT = 8       /* offsets/lengths outside the given arrays,
+                                      or a range overlapping another program's */
 };
 
 #define BEAGLE_MAX_LEN 4096 /* tokens per program                               */
@@ -105,7 +106,12 @@ enum {
  * and its constant table is
  *   consts[const_offset[p] .. const_offset[p] + const_count[p]).
  * n_tokens and n_consts are the lengths of tokens[] and consts[]; ranges
- * outside them give BEAGLE_PROG_BAD_LAYOUT. */
+ * outside them give BEAGLE_PROG_BAD_LAYOUT.  Each program is decoded into
+ * workspace at its own token offset, so the token ranges of different
+ * programs must not overlap (for beagle_eval_grad, whose gradient has the
+ * constants' layout, neither may the constant ranges): a program whose
+ * range overlaps a lower-indexed program's gets BEAGLE_PROG_BAD_LAYOUT and
+ * NaN, the others are unaffected.  Ranges may come in any order. */
 typedef struct {
   const uint16_t* tokens;
   int64_t n_tokens;
@@ -202,9 +208,10 @@ beagle_status beagle_eval_workspace_size(const beagle_programs* progs, const bea
 beagle_status beagle_eval_static(const beagle_programs* progs, const beagle_dataset* data, int kind,
                                  double* fitness, int8_t* status, beagle_stream stream);
 
-/* Per-case outputs yhat[p * M + i] (binary32) of every program: a debugging
- * and testing aid for small populations (n_programs * M <= 2^31).  Invalid
- * programs give NaN rows. */
+/* Per-case outputs yhat[p * M + i] (binary32) of every program -- the
+ * model outputs each fitness of section 2.1.5 compares with the targets,
+ * from the same interpreter code: a debugging and testing aid for small
+ * populations (n_programs * M <= 2^31).  Invalid programs give NaN rows. */
 beagle_status beagle_predict(beagle_ctx* ctx, const beagle_programs* progs, const beagle_dataset* data,
                              float* yhat, int8_t* status, beagle_stream stream);
 
@@ -297,7 +304,10 @@ typedef struct {
                              the unary operators in opcode order            */
 } beagle_gen_params;
 
-/* Ramped half-and-half initial population of n programs over D variables
+/* The initial population of the evolutionary loop (sections 1 and 2.1.2:
+ * initialise, then evaluate, select and vary each generation), by ramped
+ * half-and-half (the paper does not name its initialisation):
+ * n programs over D variables
  * into fixed-capacity slots: tokens[c * max_len ...] (zero padded),
  * len[c], consts[c * max_consts ...] (zero padded), const_count[c].
  * Random draws come from Philox4x32-10 keyed by `seed` (see
@@ -307,7 +317,9 @@ beagle_status beagle_init_population(beagle_ctx* ctx, const beagle_gen_params* p
                                      uint64_t seed, uint32_t problem, uint16_t* tokens, int32_t* len,
                                      float* consts, int32_t* const_count, beagle_stream stream);
 
-/* One generation: for every child slot c in [0, n_programs), size-t
+/* One generation of the loop of sections 1 and 2.1.2 (select, then vary
+ * the genomes; mutation as the random correction of section 2.1.4,
+ * crossover beside it): for every child slot c in [0, n_programs), size-t
  * tournament selection on `fitness` (lower is better, NaN worst, ties to
  * the lower index), then subtree crossover, point mutation or a copy, into
  * fixed-capacity child slots laid out as for beagle_init_population.

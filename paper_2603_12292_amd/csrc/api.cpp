@@ -115,9 +115,8 @@ using namespace bgl::host;
 
 // The pieces of workspace one evaluation uses.
 struct EvalLayout {
-  size_t code, aux, cval, s_stack, s_start, s_need, meta, class_count, class_list, len_list, long_list, work, Xt, yp,
-      stats, part,
-      gpart, coef, total;
+  size_t code, aux, cval, s_stack, s_start, s_need, owner, cowner, meta, class_count, class_list, len_list, long_list,
+      work, Xt, yp, stats, part, gpart, coef, total;
   int64_t Mp, chunk, gchunk;      // case chunks of the evaluation and of the adjoint
   int32_t n_chunks, gn_chunks, slice;
 };
@@ -134,8 +133,10 @@ EvalLayout eval_layout(const beagle_programs* P, const beagle_dataset* d, int n_
   L.s_stack = c.take<int32_t>(nt);
   L.s_start = c.take<int32_t>(nt);
   L.s_need = c.take<int32_t>(nt);
+  L.owner = c.take<int32_t>(nt);
+  L.cowner = with_grad ? c.take<int32_t>(std::max<int64_t>(P->n_consts, 1)) : 0;
   L.meta = c.take<bgl::ProgMeta>(N);
-  L.class_count = c.take<int32_t>(64);  // [0..2] need classes, [8..9] length classes
+  L.class_count = c.take<int32_t>(64);  // [0..2] need classes, [8..9] length classes, [32..33] layout flags
   L.class_list = c.take<int32_t>(size_t(bgl::N_CLASSES) * N);
   L.len_list = c.take<int32_t>(size_t(bgl::GRAD_LISTS) * N);
   L.long_list = c.take<int32_t>(size_t(N));
@@ -193,7 +194,16 @@ beagle_status prepare(char* ws, const beagle_programs* P, const beagle_dataset* 
   pa.adjoint = adjoint ? 1 : 0;
   pa.long_count = reinterpret_cast<int32_t*>(ws + L.class_count) + 16;
   pa.long_list = reinterpret_cast<int32_t*>(ws + L.long_list);
-  // programs of at most 64 tokens, then the ones longer than that
+  pa.layout = reinterpret_cast<int32_t*>(ws + L.class_count) + 32;
+  pa.owner = reinterpret_cast<int32_t*>(ws + L.owner);
+  pa.cowner = adjoint ? reinterpret_cast<int32_t*>(ws + L.cowner) : nullptr;
+  // disjoint ranges (the fill and mark passes return at once when the
+  // ranges are sorted and disjoint), then programs of at most 64 tokens,
+  // then the ones longer than that
+  const uint32_t pgrid = uint32_t((P->n_programs + 255) / 256);
+  hipLaunchKernelGGL(bgl::k_layout_check, dim3(pgrid), dim3(256), 0, s, pa);
+  hipLaunchKernelGGL(bgl::k_layout_fill, dim3(1024), dim3(256), 0, s, pa);
+  hipLaunchKernelGGL(bgl::k_layout_mark, dim3(std::min<uint32_t>(pgrid, 1024)), dim3(256), 0, s, pa);
   hipLaunchKernelGGL(bgl::k_prepare, dim3((P->n_programs + 63) / 64), dim3(64), 0, s, pa);
   hipLaunchKernelGGL(bgl::k_prepare_long, dim3(512), dim3(64), 0, s, pa);
   bgl::StageArgs sa;

@@ -56,6 +56,10 @@ struct Batch {
 // Enqueues the whole batched evaluation on `s` (the capture stream).
 hipError_t enqueue(const Batch& b, int32_t* counts, hipStream_t s) {
   zero_i32(counts, int64_t(64) * b.n, s);
+  const uint32_t pgrid = uint32_t((b.n_programs + 255) / 256);
+  hipLaunchKernelGGL(bgl::k_layout_check_batch, dim3(pgrid), dim3(256), 0, s, b.args);
+  hipLaunchKernelGGL(bgl::k_layout_fill_batch, dim3(64, uint32_t(b.n)), dim3(256), 0, s, b.args);
+  hipLaunchKernelGGL(bgl::k_layout_mark_batch, dim3(std::min<uint32_t>(pgrid, 1024)), dim3(256), 0, s, b.args);
   hipLaunchKernelGGL(bgl::k_prepare_batch, dim3(uint32_t((b.n_programs + 63) / 64)), dim3(64), 0, s, b.args);
   hipLaunchKernelGGL(bgl::k_stage_batch, dim3(uint32_t((b.n_cases + 255) / 256)), dim3(256), 0, s, b.args);
   if (b.args.kind == BEAGLE_FIT_CORR) {
@@ -124,7 +128,7 @@ beagle_status beagle_eval_batched(beagle_ctx* ctx, const beagle_programs* progs,
   const size_t at_work = c.take<unsigned long long>(bgl::N_LISTS);
   const size_t at_counts = c.take<int32_t>(size_t(64) * n);
   struct Off {
-    size_t code, aux, cval, s_stack, s_start, s_need, meta, class_list, len_list, Xt, yp, stats, part;
+    size_t code, aux, cval, s_stack, s_start, s_need, owner, meta, class_list, len_list, Xt, yp, stats, part;
     int64_t Mp, chunk;
     int32_t n_chunks;
   };
@@ -141,6 +145,7 @@ beagle_status beagle_eval_batched(beagle_ctx* ctx, const beagle_programs* progs,
     o.s_stack = c.take<int32_t>(nt);
     o.s_start = c.take<int32_t>(nt);
     o.s_need = c.take<int32_t>(nt);
+    o.owner = c.take<int32_t>(nt);
     o.meta = c.take<bgl::ProgMeta>(N);
     o.class_list = c.take<int32_t>(size_t(bgl::N_CLASSES) * N);
     o.len_list = c.take<int32_t>(size_t(bgl::GRAD_LISTS) * N);
@@ -201,6 +206,9 @@ beagle_status beagle_eval_batched(beagle_ctx* ctx, const beagle_programs* progs,
     pa.adjoint = 0;
     pa.long_count = nullptr;  // k_prepare_batch decodes every program itself
     pa.long_list = nullptr;
+    pa.layout = counts + int64_t(64) * i + 32;
+    pa.owner = reinterpret_cast<int32_t*>(ws + o.owner);
+    pa.cowner = nullptr;
     t.X = d.X;
     t.y = d.y;
     t.Xt = reinterpret_cast<float*>(ws + o.Xt);

@@ -40,6 +40,17 @@ struct PrepareArgs {
   // programs k_prepare leaves to k_prepare_long (count zero at launch)
   int32_t* long_count;
   int32_t* long_list;  // [n_programs]
+  // Disjoint ranges: every program is decoded in place of its tokens, so the
+  // token ranges of different programs (and, for the adjoint, whose gradient
+  // output has the constants' layout, the constant ranges) must not overlap.
+  // layout[0], layout[1] (zero at launch): set by k_layout_check when the
+  // token / constant ranges are not sorted and disjoint by program index;
+  // then owner / cowner hold, per token / constant slot, the lowest index of
+  // a program whose range covers it, and a program finding another index in
+  // its range gets BEAGLE_PROG_BAD_LAYOUT.
+  int32_t* layout;
+  int32_t* owner;   // [n_tokens]
+  int32_t* cowner;  // [n_consts] (adjoint only)
 };
 
 struct StageArgs {
@@ -182,6 +193,15 @@ __host__ __device__ constexpr int class_k(int c, int kv) { return c == 0 ? (kv =
 
 // decoding: programs of at most 64 tokens in k_prepare (narrow LDS
 // scratch), the longer ones it lists in k_prepare_long
+// the disjoint-ranges check before decoding (see PrepareArgs::layout):
+// neighbour comparison, then (only when that found unsorted or overlapping
+// ranges) the owner arrays filled and marked
+__global__ void k_layout_check(PrepareArgs a);
+__global__ void k_layout_fill(PrepareArgs a);
+__global__ void k_layout_mark(PrepareArgs a);
+__global__ void k_layout_check_batch(BatchArgs b);
+__global__ void k_layout_fill_batch(BatchArgs b);
+__global__ void k_layout_mark_batch(BatchArgs b);
 __global__ void k_prepare(PrepareArgs a);
 __global__ void k_prepare_long(PrepareArgs a);
 __global__ void k_stage_cases(StageArgs a);

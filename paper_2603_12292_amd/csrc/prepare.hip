@@ -81,6 +81,21 @@ struct ListIds {
   int cls = -1, lc = -1;
 };
 
+// Whether program p holds its token range (and, for the adjoint, its
+// constant range) alone: always when the ranges are sorted and disjoint,
+// else when every slot of its ranges carries its own index as the lowest
+// covering one (see PrepareArgs::layout).
+__device__ static bool owns_ranges(const PrepareArgs& a, int p, int64_t off, int32_t L, int64_t coff, int32_t cc) {
+  if (!a.layout) return true;
+  if (a.layout[0])
+    for (int32_t i = 0; i < L; ++i)
+      if (a.owner[off + i] != p) return false;
+  if (a.adjoint && a.layout[1])
+    for (int32_t j = 0; j < cc; ++j)
+      if (a.cowner[coff + j] != p) return false;
+  return true;
+}
+
 template <class ST, class S, class SO>
 __device__ static ListIds prepare_program(const PrepareArgs& a, int p, ST tok, S stack, S start, S need, SO ord) {
   const int64_t off = a.tok_offset[p];
@@ -100,6 +115,8 @@ __device__ static ListIds prepare_program(const PrepareArgs& a, int p, ST tok, S
   } else if (off < 0 || off + L > a.n_tokens || cc < 0 ||
              (cc > 0 && (coff < 0 || coff + cc > a.n_consts))) {
     status = BEAGLE_PROG_BAD_LAYOUT;
+  } else if (!owns_ranges(a, p, off, L, coff, cc)) {
+    status = BEAGLE_PROG_BAD_LAYOUT;  // overlaps a lower-indexed program's range
   }
   if (status == BEAGLE_PROG_OK) {
     // stack: node stack in pass 1, output starts in pass 2
@@ -442,6 +459,92 @@ __global__ void __launch_bounds__(PREP_BLOCK) k_prepare_long(PrepareArgs a) {
     }
     wave_append<N_CLASSES>(ids.cls, p, a.class_count, a.class_list, a.n_programs);
     if (a.adjoint) wave_append<GRAD_LISTS>(ids.lc, p, a.len_count, a.len_list, a.n_programs);
+  }
+}
+
+// ---- disjoint-ranges check -------------------------------------------------
+// Token range of program p when it lies within the token array (else
+// false: the program is rejected by the layout checks of the decoder).
+__device__ static bool tok_range(const PrepareArgs& a, int p, int64_t& off, int32_t& L) {
+  off = a.tok_offset[p];
+  L = a.tok_len[p];
+  return L >= 0 && L <= MAX_LEN && off >= 0 && off + L <= a.n_tokens;
+}
+
+__device__ static bool const_range(const PrepareArgs& a, int p, int64_t& off, int32_t& n) {
+  off = a.const_offset[p];
+  n = a.const_count[p];
+  return n >= 0 && (n == 0 || (off >= 0 && off + n <= a.n_consts));
+}
+
+// Program p against program p + 1: ranges out of order, overlapping, or out
+// of bounds (conservatively) set the flag.
+__device__ static void layout_pair(const PrepareArgs& a, int p) {
+  if (p + 1 >= a.n_programs) return;
+  int64_t o0, o1;
+  int32_t n0, n1;
+  const bool v0 = tok_range(a, p, o0, n0), v1 = tok_range(a, p + 1, o1, n1);
+  if (!(v0 && v1 && o0 + n0 <= o1)) atomicOr(a.layout, 1);
+  if (a.adjoint) {
+    const bool c0 = const_range(a, p, o0, n0), c1 = const_range(a, p + 1, o1, n1);
+    if (!(c0 && c1 && (n0 == 0 || n1 == 0 || o0 + n0 <= o1))) atomicOr(a.layout + 1, 1);
+  }
+}
+
+// grid-stride fill of the owner arrays with the largest index (only after a
+// flagged layout)
+__device__ static void layout_fill(const PrepareArgs& a, int64_t i0, int64_t stride) {
+  if (a.layout[0])
+    for (int64_t i = i0; i < a.n_tokens; i += stride) a.owner[i] = 0x7FFFFFFF;
+  if (a.adjoint && a.layout[1])
+    for (int64_t i = i0; i < a.n_consts; i += stride) a.cowner[i] = 0x7FFFFFFF;
+}
+
+// program p marks its ranges with its index (the lowest index wins)
+__device__ static void layout_mark(const PrepareArgs& a, int p) {
+  int64_t off;
+  int32_t n;
+  if (a.layout[0] && tok_range(a, p, off, n))
+    for (int32_t i = 0; i < n; ++i) atomicMin(a.owner + off + i, p);
+  if (a.adjoint && a.layout[1] && const_range(a, p, off, n))
+    for (int32_t i = 0; i < n; ++i) atomicMin(a.cowner + off + i, p);
+}
+
+__global__ void k_layout_check(PrepareArgs a) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p < a.n_programs) layout_pair(a, int(p));
+}
+
+__global__ void k_layout_fill(PrepareArgs a) {
+  layout_fill(a, int64_t(blockIdx.x) * blockDim.x + threadIdx.x, int64_t(gridDim.x) * blockDim.x);
+}
+
+__global__ void k_layout_mark(PrepareArgs a) {
+  if (!a.layout[0] && !(a.adjoint && a.layout[1])) return;
+  for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < a.n_programs;
+       p += int64_t(gridDim.x) * blockDim.x)
+    layout_mark(a, int(p));
+}
+
+__global__ void k_layout_check_batch(BatchArgs b) {
+  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= b.n_programs) return;
+  const int q = batch_find(b, g, [](const BatchProblem& t) { return t.prog_begin; });
+  layout_pair(b.table[q].prep, int(g - b.table[q].prog_begin));
+}
+
+// blockIdx.y: the problem
+__global__ void k_layout_fill_batch(BatchArgs b) {
+  layout_fill(b.table[blockIdx.y].prep, int64_t(blockIdx.x) * blockDim.x + threadIdx.x,
+              int64_t(gridDim.x) * blockDim.x);
+}
+
+__global__ void k_layout_mark_batch(BatchArgs b) {
+  for (int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < b.n_programs;
+       g += int64_t(gridDim.x) * blockDim.x) {
+    const int q = batch_find(b, g, [](const BatchProblem& t) { return t.prog_begin; });
+    const PrepareArgs& a = b.table[q].prep;
+    if (a.layout[0] || (a.adjoint && a.layout[1])) layout_mark(a, int(g - b.table[q].prog_begin));
   }
 }
 

@@ -159,6 +159,45 @@ def test_non_finite_targets():
                 assert not np.any(np.isfinite(gpu))
 
 
+def test_overlapping_token_ranges():
+    """Each program is decoded in place of its tokens, so token ranges must
+    not overlap: a program whose range overlaps a lower-indexed program's
+    gets BEAGLE_PROG_BAD_LAYOUT (8) and NaN, the others evaluate as in a
+    disjoint layout -- also when the ranges are out of order."""
+    api = _api()
+    data = wl.make_dataset(41, 3000, 2, x_range=(1.0, 5.0), target_len=8)
+    X, y = _xy(data)
+    t0 = parse("x0 c0 * c1 + x1 sin *")
+    t1 = parse("x1 c0 / x0 exp -")
+    toks = np.array(t0 + t1, dtype=np.uint16)
+    L0, L1 = len(t0), len(t1)
+    consts = np.array([1.5, -0.5, 2.25, 3.0, 7.0, 0.125], dtype=np.float32)
+    ref = {}
+    for kind in ("mse", "corr"):
+        # disjoint, sorted: programs (t0, c[0:2]), (t1, c[2:3]), (t0 again in a copy)
+        P = api.DevicePrograms.from_arrays(np.concatenate([toks, toks[:L0]]), [0, L0, L0 + L1], [L0, L1, L0],
+                                           consts, [0, 2, 4], [2, 1, 2])
+        f, st = api.evaluate(P, X, y, kind, with_status=True)
+        ref[kind] = f.cpu().numpy()
+        assert np.all(st.cpu().numpy() == 0)
+        # the third program shares the first one's tokens with other constants
+        Q = api.DevicePrograms.from_arrays(toks, [0, L0, 0], [L0, L1, L0], consts, [0, 2, 4], [2, 1, 2])
+        f, st = api.evaluate(Q, X, y, kind, with_status=True)
+        f, st = f.cpu().numpy(), st.cpu().numpy()
+        assert list(st) == [0, 0, 8] and math.isnan(f[2]), (kind, st, f)
+        assert np.array_equal(f[:2].view(np.uint64), ref[kind][:2].view(np.uint64))
+        # disjoint but out of order: identical results
+        R = api.DevicePrograms.from_arrays(np.concatenate([toks[:L0], toks[L0:], toks[:L0]][::-1]),
+                                           [L1 + L0, L0, 0], [L0, L1, L0], consts, [0, 2, 4], [2, 1, 2])
+        f, st = api.evaluate(R, X, y, kind, with_status=True)
+        assert np.all(st.cpu().numpy() == 0)
+        assert np.array_equal(f.cpu().numpy().view(np.uint64), ref[kind].view(np.uint64))
+    # the oracle for the first two programs
+    for k, (t, c) in enumerate(((t0, consts[0:2]), (t1, consts[2:3]))):
+        f32, _ = gates.oracle(wl.pack_programs([(t, c)]), data.X, data.y, ofit.CORR, "o64")
+        assert abs(ref["corr"][k] - f32[0]) <= 1e-5 * abs(f32[0]) + 1e-9
+
+
 def test_invalid_programs_status_and_nan():
     data = wl.make_dataset(6, 500, 2, x_range=(1.0, 5.0), target_len=6)
     progs = [("x0 +", []), ("x0 x1", []), ("x5", []), ("c3", [1.0]), ([18], []), ([], []),

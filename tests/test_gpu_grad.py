@@ -351,3 +351,29 @@ def test_decoder_passes_agree():
             o, cc = int(mixed.const_offset[k]), int(mixed.const_count[k])
             o1 = int(grouped.const_offset[i])
             assert np.array_equal(gm[o:o + cc].view(np.uint32), g1[o1:o1 + cc].view(np.uint32)), (kind, k, i)
+
+
+def test_overlapping_constant_ranges():
+    """The gradient has the constants' layout, so for beagle_eval_grad the
+    constant ranges must not overlap either: a program whose constant range
+    overlaps a lower-indexed program's gets BEAGLE_PROG_BAD_LAYOUT (8), NaN
+    fitness, and leaves the shared gradient slots to the first."""
+    api = _api()
+    data = wl.make_dataset(43, 2000, 2, x_range=(1.0, 5.0), target_len=8)
+    X = torch.from_numpy(data.X).cuda()
+    y = torch.from_numpy(data.y).cuda()
+    t0 = progtext.parse("x0 c0 * c1 +")
+    t1 = progtext.parse("x1 c0 * x0 +")
+    toks = np.array(t0 + t1, dtype=np.uint16)
+    consts = np.array([1.5, -0.5], dtype=np.float32)
+    P = api.DevicePrograms.from_arrays(toks, [0, len(t0)], [len(t0), len(t1)], consts, [0, 0], [2, 1])
+    f, g, st = api.evaluate_grad(P, X, y, "mse", with_status=True)
+    f, g, st = f.cpu().numpy(), g.cpu().numpy(), st.cpu().numpy()
+    assert list(st) == [0, 8] and math.isnan(f[1]) and math.isfinite(f[0])
+    F, gref = og.mse_and_grad(t0, consts, data.X, data.y)
+    assert np.allclose(g, gref, rtol=1e-4, atol=1e-7), (g, gref)
+    # the same constants as separate ranges: both valid
+    Q = api.DevicePrograms.from_arrays(toks, [0, len(t0)], [len(t0), len(t1)], np.concatenate([consts, consts[:1]]),
+                                       [0, 2], [2, 1])
+    _, _, st = api.evaluate_grad(Q, X, y, "mse", with_status=True)
+    assert np.all(st.cpu().numpy() == 0)
