@@ -118,7 +118,53 @@ __host__ __device__ constexpr uint32_t h_bin(uint32_t o, int n) { return H_BIN +
 __device__ __forceinline__ int arity(uint32_t op) { return op < 4 ? 2 : (op < 9 || (op > OP_CONST && op < N_OPCODES) ? 1 : 0); }
 
 // ---- operator conventions (binary32) -------------------------------------
-__device__ __forceinline__ float op_div(float a, float b) { return b == 0.0f ? 1.0f : a / b; }
+// The protected quotient b == 0 ? 1 : a / b, correctly rounded.
+__device__ __forceinline__ float op_div_cr(float a, float b) { return b == 0.0f ? 1.0f : a / b; }
+
+// binary32 classes (the mask of v_cmp_class_f32): +-normal numbers
+constexpr int CLASS_NORMAL = (1 << 3) | (1 << 8);
+// +-0 and +-subnormal numbers
+constexpr int CLASS_ZERO_SUB = (1 << 4) | (1 << 5) | (1 << 6) | (1 << 7);
+
+// The protected quotient of K pairs per lane.  Each case first takes the
+// faithful quotient q = q0 + (a - b q0) r with r the hardware reciprocal of
+// b and q0 = a r (the residual by one FMA; at most 1 ulp from a / b -- the
+// reciprocal's error enters only squared); when that q is not a normal
+// number (a zero divisor, a zero, subnormal, infinite or NaN quotient, or a
+// reciprocal out of range), or when |a| < 2^-100 (below about 2^-102 the
+// residual underflows and is no longer exact), the case takes the correctly
+// rounded protected quotient instead.  The choice depends on the case alone, so every grouping
+// of cases into waves gives the same values; the correctly rounded path runs
+// only when some lane of the wave needs it.
+template <int K>
+__device__ __forceinline__ void div_tile(const float (&a)[K], const float (&b)[K], float (&q)[K]) {
+  uint64_t any = 0;
+  bool bad[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const float r = __builtin_amdgcn_rcpf(b[k]);
+    const float q0 = a[k] * r;
+    q[k] = __builtin_fmaf(__builtin_fmaf(-b[k], q0, a[k]), r, q0);
+    // not normal: |q| outside [2^-126, FLT_MAX] (zeros, subnormals, infinities)
+    // or NaN, as one median and one comparison (NaN compares unequal)
+    const float aq = __builtin_fabsf(q[k]);
+    const bool odd = __builtin_amdgcn_fmed3f(aq, 0x1p-126f, 0x1.fffffep127f) != aq;
+    const bool tiny = __builtin_fabsf(a[k]) < 0x1p-100f;
+    bad[k] = odd || tiny;
+    any |= __builtin_amdgcn_ballot_w64(odd) | __builtin_amdgcn_ballot_w64(tiny);
+  }
+  if (any) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) q[k] = bad[k] ? op_div_cr(a[k], b[k]) : q[k];
+  }
+}
+
+__device__ __forceinline__ float op_div(float a, float b) {
+  const float av[1] = {a}, bv[1] = {b};
+  float q[1];
+  div_tile<1>(av, bv, q);
+  return q[0];
+}
 // exp(clamp(x, -80, 80)) = 2^n 2^f with n = rint(x log2 e) and
 // f = x log2 e - n in [-1/2, 1/2], f formed with log2 e split into two
 // binary32 numbers so that its error stays below 2^-25; 2^f from the hardware
@@ -151,6 +197,61 @@ __device__ __forceinline__ float op_sqrt(float x) {
   const bool tiny = a < 0x1p-96f;
   const float s = __builtin_amdgcn_sqrtf(tiny ? a * 0x1p32f : a);
   return tiny ? s * 0x1p-16f : s;
+}
+
+// Whether any of the K values of any lane satisfies `cond`: one compare
+// per value into a wave mask, the masks OR-ed in scalar registers.
+template <int K, class F>
+__device__ __forceinline__ bool wave_any(F cond) {
+  uint64_t m = 0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) m |= __builtin_amdgcn_ballot_w64(cond(k));
+  return m != 0;
+}
+
+// The same three operators on K values per lane: where no lane holds an
+// argument that needs the range handling above (exp: |x| > 80 or NaN; log:
+// a zero or subnormal argument; sqrt: |x| < 2^-96), the wave runs the same
+// arithmetic without it -- bit-identical results, fewer instructions.
+template <int K>
+__device__ __forceinline__ void exp_tile(float (&v)[K]) {
+  if (!wave_any<K>([&](int k) { return !(__builtin_fabsf(v[k]) <= 80.0f); })) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const float n = __builtin_rintf(v[k] * 0x1.715476p+0f);
+      float f = __builtin_fmaf(v[k], 0x1.715476p+0f, -n);
+      f = __builtin_fmaf(v[k], 0x1.4ae0c0p-26f, f);
+      v[k] = __builtin_amdgcn_ldexpf(__builtin_amdgcn_exp2f(f), int(n));
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = op_exp(v[k]);
+  }
+}
+
+template <int K>
+__device__ __forceinline__ void log_tile(float (&v)[K]) {
+  if (!wave_any<K>([&](int k) { return __builtin_amdgcn_classf(v[k], CLASS_ZERO_SUB); })) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const float y = __builtin_amdgcn_logf(__builtin_fabsf(v[k]));
+      v[k] = __builtin_fmaf(y, 0x1.62e42ep-1f, y * 0x1.efa39ep-25f);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = op_log(v[k]);
+  }
+}
+
+template <int K>
+__device__ __forceinline__ void sqrt_tile(float (&v)[K]) {
+  if (!wave_any<K>([&](int k) { return __builtin_fabsf(v[k]) < 0x1p-96f; })) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = __builtin_amdgcn_sqrtf(__builtin_fabsf(v[k]));
+  } else {
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = op_sqrt(v[k]);
+  }
 }
 
 // The seven further operators (unary index U_FIRST_EXT + j), IEEE semantics:

@@ -32,6 +32,20 @@ __device__ __forceinline__ float binop(float a, float b) {
   return 0.0f;
 }
 
+// r[k] = a[k] op b[k] on the K cases of a lane; the protected division
+// (and its reversed form) through div_tile, one check per wave
+template <uint32_t O, int K>
+__device__ __forceinline__ void binop_tile(const float (&a)[K], const float (&b)[K], float (&r)[K]) {
+  if constexpr (O == B_DIV) {
+    div_tile<K>(a, b, r);
+  } else if constexpr (O == B_RDIV) {
+    div_tile<K>(b, a, r);
+  } else {
+#pragma unroll
+    for (int k = 0; k < K; ++k) r[k] = binop<O>(a[k], b[k]);
+  }
+}
+
 // The wave's input tile in LDS: variable d of case k (k-th of this lane's K
 // cases) lives at  ((d * G + k / 4) * 64 + lane) * 4 + k % 4  floats, G =
 // ceil(K / 4): every 16-byte access of a wave is contiguous across lanes
@@ -130,8 +144,12 @@ __device__ __forceinline__ void interpret(uint32_t vc0, float vv0, uint32_t vc1,
 #define BGL_BIN(O, N)                                                          \
   case H_BIN + 15 * O + (N - 2):                                               \
     if constexpr (N <= S) {                                                    \
-      _Pragma("unroll") for (int k = 0; k < K; ++k) top[k] =                   \
-          binop<O>(stk[k][N <= S ? N - 2 : 0], top[k]);                        \
+      float a_[K], t_[K];                                                      \
+      _Pragma("unroll") for (int k = 0; k < K; ++k) {                          \
+        a_[k] = stk[k][N <= S ? N - 2 : 0];                                    \
+        t_[k] = top[k];                                                        \
+      }                                                                        \
+      binop_tile<O, K>(a_, t_, top);                                           \
     }                                                                          \
     break;
 #define BGL_BIN_ALL(O)                                                          \
@@ -149,12 +167,19 @@ __device__ __forceinline__ void interpret(uint32_t vc0, float vv0, uint32_t vc1,
 #define BGL_FUSED(O)                                                           \
   case H_FUSED + O: {                                                          \
     const XRow<K> xv = load_row<K>(xl, arg);                                   \
-    _Pragma("unroll") for (int k = 0; k < K; ++k) top[k] = binop<O>(top[k], xv.v[k]); \
+    float t_[K];                                                               \
+    _Pragma("unroll") for (int k = 0; k < K; ++k) t_[k] = top[k];              \
+    binop_tile<O, K>(t_, xv.v, top);                                           \
     break;                                                                     \
   }                                                                            \
   case H_FUSED + 6 + O: {                                                      \
     const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vv), t)); \
-    _Pragma("unroll") for (int k = 0; k < K; ++k) top[k] = binop<O>(top[k], v); \
+    float t_[K], c_[K];                                                        \
+    _Pragma("unroll") for (int k = 0; k < K; ++k) {                            \
+      t_[k] = top[k];                                                          \
+      c_[k] = v;                                                               \
+    }                                                                          \
+    binop_tile<O, K>(t_, c_, top);                                             \
     break;                                                                     \
   }
         BGL_FUSED(B_ADD)
@@ -171,16 +196,13 @@ __device__ __forceinline__ void interpret(uint32_t vc0, float vv0, uint32_t vc1,
           trig_tile<true, K>(top);
           break;
         case H_UN + 2:
-#pragma unroll
-          for (int k = 0; k < K; ++k) top[k] = op_exp(top[k]);
+          exp_tile<K>(top);
           break;
         case H_UN + 3:
-#pragma unroll
-          for (int k = 0; k < K; ++k) top[k] = op_log(top[k]);
+          log_tile<K>(top);
           break;
         case H_UN + 4:
-#pragma unroll
-          for (int k = 0; k < K; ++k) top[k] = op_sqrt(top[k]);
+          sqrt_tile<K>(top);
           break;
 #define BGL_EXT(U)                                                             \
   case H_UN + U:                                                               \
@@ -242,9 +264,16 @@ __device__ __forceinline__ void interpret_small(uint32_t vc0, float vv0, uint32_
         BGL_S_PUSH(0) BGL_S_PUSH(1) BGL_S_PUSH(2) BGL_S_PUSH(3)
 #undef BGL_S_PUSH
 #define BGL_S_BIN(O, N)                                                         \
-  case I0_BIN + 3 * O + (N - 2):                                                \
-    _Pragma("unroll") for (int k = 0; k < K; ++k) st[k][N - 2] = binop<O>(st[k][N - 2], st[k][N - 1]); \
-    break;
+  case I0_BIN + 3 * O + (N - 2): {                                              \
+    float a_[K], b_[K], r_[K];                                                  \
+    _Pragma("unroll") for (int k = 0; k < K; ++k) {                             \
+      a_[k] = st[k][N - 2];                                                     \
+      b_[k] = st[k][N - 1];                                                     \
+    }                                                                           \
+    binop_tile<O, K>(a_, b_, r_);                                               \
+    _Pragma("unroll") for (int k = 0; k < K; ++k) st[k][N - 2] = r_[k];         \
+    break;                                                                      \
+  }
 #define BGL_S_BIN3(O) BGL_S_BIN(O, 2) BGL_S_BIN(O, 3) BGL_S_BIN(O, 4)
         BGL_S_BIN3(B_ADD) BGL_S_BIN3(B_SUB) BGL_S_BIN3(B_MUL) BGL_S_BIN3(B_DIV) BGL_S_BIN3(B_RSUB) BGL_S_BIN3(B_RDIV)
 #undef BGL_S_BIN3
@@ -264,26 +293,47 @@ __device__ __forceinline__ void interpret_small(uint32_t vc0, float vv0, uint32_
     _Pragma("unroll") for (int k = 0; k < K; ++k) st[k][N - 1] = c[k];          \
     break;                                                                      \
   }                                                                             \
-  case I0_UN + 2 * 4 + (N - 1):                                                 \
-    _Pragma("unroll") for (int k = 0; k < K; ++k) st[k][N - 1] = op_exp(st[k][N - 1]); \
+  case I0_UN + 2 * 4 + (N - 1): {                                               \
+    float c[K];                                                                 \
+    _Pragma("unroll") for (int k = 0; k < K; ++k) c[k] = st[k][N - 1];          \
+    exp_tile<K>(c);                                                             \
+    _Pragma("unroll") for (int k = 0; k < K; ++k) st[k][N - 1] = c[k];          \
     break;                                                                      \
-  case I0_UN + 3 * 4 + (N - 1):                                                 \
-    _Pragma("unroll") for (int k = 0; k < K; ++k) st[k][N - 1] = op_log(st[k][N - 1]); \
+  }                                                                             \
+  case I0_UN + 3 * 4 + (N - 1): {                                               \
+    float c[K];                                                                 \
+    _Pragma("unroll") for (int k = 0; k < K; ++k) c[k] = st[k][N - 1];          \
+    log_tile<K>(c);                                                             \
+    _Pragma("unroll") for (int k = 0; k < K; ++k) st[k][N - 1] = c[k];          \
     break;                                                                      \
-  case I0_UN + 4 * 4 + (N - 1):                                                 \
-    _Pragma("unroll") for (int k = 0; k < K; ++k) st[k][N - 1] = op_sqrt(st[k][N - 1]); \
-    break;
+  }                                                                             \
+  case I0_UN + 4 * 4 + (N - 1): {                                               \
+    float c[K];                                                                 \
+    _Pragma("unroll") for (int k = 0; k < K; ++k) c[k] = st[k][N - 1];          \
+    sqrt_tile<K>(c);                                                            \
+    _Pragma("unroll") for (int k = 0; k < K; ++k) st[k][N - 1] = c[k];          \
+    break;                                                                      \
+  }
         BGL_S_UN(1) BGL_S_UN(2) BGL_S_UN(3) BGL_S_UN(4)
 #undef BGL_S_UN
 #define BGL_S_FUSED(O, N)                                                       \
   case I0_FUSED + 3 * O + (N - 1): {                                            \
     const XRow<K> xv = load_row<K>(xl, arg);                                    \
-    _Pragma("unroll") for (int k = 0; k < K; ++k) st[k][N - 1] = binop<O>(st[k][N - 1], xv.v[k]); \
+    float a_[K], r_[K];                                                         \
+    _Pragma("unroll") for (int k = 0; k < K; ++k) a_[k] = st[k][N - 1];         \
+    binop_tile<O, K>(a_, xv.v, r_);                                             \
+    _Pragma("unroll") for (int k = 0; k < K; ++k) st[k][N - 1] = r_[k];         \
     break;                                                                      \
   }                                                                             \
   case I0_FUSED + 3 * (6 + O) + (N - 1): {                                      \
     const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vv), t)); \
-    _Pragma("unroll") for (int k = 0; k < K; ++k) st[k][N - 1] = binop<O>(st[k][N - 1], v); \
+    float a_[K], c_[K], r_[K];                                                  \
+    _Pragma("unroll") for (int k = 0; k < K; ++k) {                             \
+      a_[k] = st[k][N - 1];                                                     \
+      c_[k] = v;                                                                \
+    }                                                                           \
+    binop_tile<O, K>(a_, c_, r_);                                               \
+    _Pragma("unroll") for (int k = 0; k < K; ++k) st[k][N - 1] = r_[k];         \
     break;                                                                      \
   }
 #define BGL_S_FUSED3(O) BGL_S_FUSED(O, 1) BGL_S_FUSED(O, 2) BGL_S_FUSED(O, 3)
@@ -322,15 +372,17 @@ struct Acc {
   uint32_t n1 = 0u, n2 = 0u;
   __device__ __forceinline__ void add(float yh, float yt, bool valid, double shift, double ybar, double smax,
                                       double s11) {
+    // masks act on the terms' inputs and every product is an explicit FMA,
+    // so a case adds the same bits whether its tile is masked or not
     if constexpr (KIND == BEAGLE_FIT_MSE) {
-      const double d = double(yh) - double(yt);
-      s0 += valid ? d * d : 0.0;
+      const double d = valid ? double(yh) - double(yt) : 0.0;
+      s0 = __builtin_fma(d, d, s0);
     } else if constexpr (KIND == BEAGLE_FIT_CORR) {
       const double u = valid ? double(yh) - shift : 0.0;
       const double w = valid ? double(yt) - ybar : 0.0;
       s0 += u;
-      s1 += u * u;
-      s2 += u * w;
+      s1 = __builtin_fma(u, u, s1);
+      s2 = __builtin_fma(u, w, s2);
     } else if constexpr (KIND == BEAGLE_FIT_POINT) {
       s0 += valid ? point_case(yh, yt, smax, s11) : 0.0;
     } else {
@@ -341,10 +393,10 @@ struct Acc {
       const double u = both ? double(yh) - shift : 0.0;
       const double w = both ? double(yt) - ybar : 0.0;
       s0 += u;
-      s1 += u * u;
-      s2 += u * w;
+      s1 = __builtin_fma(u, u, s1);
+      s2 = __builtin_fma(u, w, s2);
       s3 += w;
-      s4 += w * w;
+      s4 = __builtin_fma(w, w, s4);
     }
   }
   // the wave's sums in partial order: MSE, POINT {s0}; CORR {s0, s1, s2};
@@ -453,10 +505,17 @@ __device__ __forceinline__ void eval_block(const EvalArgs& a, int p, int c, doub
       interpret_small<K>(vc0, vv0, vc1, vv1, code, cval, L, lane, xl, top);
     else
       interpret<K, S>(vc0, vv0, vc1, vv1, code, cval, L, lane, xl, top);
+    // a tile wholly inside the case set (every tile but the last) adds
+    // without per-case validity masks
+    if (base + int64_t(NSUB - 1) * SPAN + 64 * SUB <= a.M) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const bool valid = base + (k / SUB) * SPAN + (K >= 4 ? 4 * lane + (k % 4) : k * 64 + lane) < a.M;
-      acc.add(top[k], yk[k], valid, shift, ybar, smax, s11);
+      for (int k = 0; k < K; ++k) acc.add(top[k], yk[k], true, shift, ybar, smax, s11);
+    } else {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const bool valid = base + (k / SUB) * SPAN + (K >= 4 ? 4 * lane + (k % 4) : k * 64 + lane) < a.M;
+        acc.add(top[k], yk[k], valid, shift, ybar, smax, s11);
+      }
     }
   }
   constexpr int NS = kind_sums(KIND);
@@ -557,10 +616,15 @@ __device__ __forceinline__ void eval_wave_resident(const EvalArgs& a, int p, con
       if (lane == 0) a.meta_shift[p].shift = sh;
       shift = double(sh);
     }
+    if (base + K64 <= a.M) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const bool valid = base + (k / 4) * 256 + 4 * lane + (k % 4) < a.M;
-      acc.add(top[k], yk[k], valid, shift, ybar, smax, s11);
+      for (int k = 0; k < K; ++k) acc.add(top[k], yk[k], true, shift, ybar, smax, s11);
+    } else {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const bool valid = base + (k / 4) * 256 + 4 * lane + (k % 4) < a.M;
+        acc.add(top[k], yk[k], valid, shift, ybar, smax, s11);
+      }
     }
   }
   double v[MAX_SUMS];

@@ -2,12 +2,15 @@
 // values over the whole binary32 range.
 //
 // One odd polynomial serves both functions: |x| = k pi + r (sine) or
-// |x| = (k + 1/2) pi + r (cosine) with |r| <= pi/2, and then
-//     sin x = sign(x) (-1)^k sin r,      cos x = (-1)^(k+1) sin r.
+// |x| = (j + 1/2) pi + r (cosine) with |r| <= pi/2, and then
+//     sin x = sign(x) (-1)^k sin r,      cos x = (-1)^(j+1) sin r.
 //  - |x| < 2^30: Cody-Waite reduction in binary64 with pi split into two
 //    binary64 numbers (binary64 FMA issues at the binary32 rate on this GPU);
 //    the error of r is far below binary32 resolution for every binary32 x in
-//    this range.
+//    this range.  The integer k comes from one FMA whose addend 1.5 * 2^52
+//    makes the sum's unit in the last place 1: the sum is that constant plus
+//    the nearest integer, and its low word holds k's parity; for the
+//    cosine j = k - 1 with k the integer nearest to |x| / pi + 1/2.
 //  - larger finite |x|: Payne-Hanek reduction, an exact integer product of
 //    the 24-bit significand with a 96-bit window of the bits of 1/pi chosen
 //    by the exponent; k mod 2 from its integer bit, r from 64 fraction bits.
@@ -37,17 +40,20 @@ __device__ __forceinline__ float sin_poly(float r) {
   return __builtin_fmaf(r2 * r, p, r);
 }
 
-// r (in binary64) and the parity p of k for a = |x| < 2^30 (COS: the
-// half-period shift).
+constexpr double TRIG_ROUND = 0x1.8p52;  // 1.5 * 2^52
+
+// r (in binary64) for a = |x| < 2^30, and in bit 0 of p the parity of k
+// (sine: a = k pi + r) or of j + 1 = k (cosine: a = (j + 1/2) pi + r).
 template <bool COS>
 __device__ __forceinline__ double trig_reduce_small_d(float a, int& p) {
   const double xd = double(a);
-  const double t = COS ? __builtin_fma(xd, 0x1.45f306dc9c883p-2, -0.5) : xd * 0x1.45f306dc9c883p-2;  // 1/pi
-  const double k = __builtin_rint(t);
-  const double h = COS ? k + 0.5 : k;
+  // 1/pi; t = TRIG_ROUND + k
+  const double t = COS ? __builtin_fma(xd, 0x1.45f306dc9c883p-2, 0.5) + TRIG_ROUND
+                       : __builtin_fma(xd, 0x1.45f306dc9c883p-2, TRIG_ROUND);
+  const double h = COS ? (t - TRIG_ROUND) - 0.5 : t - TRIG_ROUND;
   double r = __builtin_fma(-h, 0x1.921fb54442d18p+1, xd);  // pi, high part
   r = __builtin_fma(-h, 0x1.1a62633145c07p-53, r);         // pi, low part
-  p = int(k) + (COS ? 1 : 0);
+  p = int(uint32_t(uint64_t(__builtin_bit_cast(uint64_t, t))));
   return r;
 }
 
@@ -102,13 +108,15 @@ __device__ __forceinline__ float trig_small(float x) {
   return trig_finish(r, p, COS ? 0u : (__float_as_uint(x) & 0x80000000u));
 }
 
-// Any binary32 x (NaN and +-Inf give NaN).
+// Any binary32 x (NaN and +-Inf give NaN); the same value as trig_small
+// where both apply.
 template <bool COS>
 __device__ __forceinline__ float trig_any(float x) {
   const float a = __builtin_fabsf(x);
   if (!(a <= 3.4028234664e38f)) return __builtin_nanf("");
+  if (a < TRIG_SMALL) return trig_small<COS>(x);
   int p;
-  const float r = a < TRIG_SMALL ? trig_reduce_small<COS>(a, p) : trig_reduce_large<COS>(a, p);
+  const float r = trig_reduce_large<COS>(a, p);
   return trig_finish(r, p, COS ? 0u : (__float_as_uint(x) & 0x80000000u));
 }
 
@@ -117,10 +125,10 @@ __device__ __forceinline__ float trig_any(float x) {
 // through the general path.
 template <bool COS, int K>
 __device__ __forceinline__ void trig_tile(float (&v)[K]) {
-  bool big = false;
+  uint64_t big = 0;
 #pragma unroll
-  for (int k = 0; k < K; ++k) big |= !(__builtin_fabsf(v[k]) < TRIG_SMALL);
-  if (__builtin_amdgcn_ballot_w64(big) == 0) {
+  for (int k = 0; k < K; ++k) big |= __builtin_amdgcn_ballot_w64(!(__builtin_fabsf(v[k]) < TRIG_SMALL));
+  if (big == 0) {
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = trig_small<COS>(v[k]);
   } else {
@@ -141,10 +149,10 @@ __device__ __forceinline__ void trig_tile(float (&v)[K]) {
 // general path per case.
 template <int K>
 __device__ __forceinline__ void sincos_tile(float (&s)[K], float (&c)[K]) {
-  bool big = false;
+  uint64_t big = 0;
 #pragma unroll
-  for (int k = 0; k < K; ++k) big |= !(__builtin_fabsf(s[k]) < TRIG_SMALL);
-  if (__builtin_amdgcn_ballot_w64(big) == 0) {
+  for (int k = 0; k < K; ++k) big |= __builtin_amdgcn_ballot_w64(!(__builtin_fabsf(s[k]) < TRIG_SMALL));
+  if (big == 0) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const float x = s[k];

@@ -50,8 +50,10 @@ from oracle import population as opop
 RTOL = 1e-5
 RTOL_COND = 1e-6
 ENV_RTOL = 1e-8
-# relative error bound of the library's division (None: correctly rounded)
-DIV_EPS = None
+# relative error bound of the library's division against the correctly
+# rounded quotient of o32e: faithful (within 1 ulp of the exact quotient),
+# o32e within 1/2: 1.5 ulp < 2^-22
+DIV_EPS = 2.0 ** -22
 
 
 def atol(kind, y):
@@ -156,7 +158,7 @@ def check_outputs(programs, X, y, kind, outs, fitness, label=""):
     at = atol(kind, y)
     n_ok = n_free = 0
     for k, (toks, consts) in enumerate(programs):
-        values, _, d, _ = obound.case_bounds(toks, consts, X)
+        values, _, d, _ = obound.case_bounds(toks, consts, X, div_eps=DIV_EPS)
         y32, b = values[-1], d[-1]
         out = np.asarray(outs[k], dtype=np.float64)
         fin = np.isfinite(b)

@@ -10,7 +10,8 @@ and the whole population takes minutes of CPU time).
 
 Columns per line: program, kind (0 MSE, 1 CORR), status, F_O64, F_O32e,
 F_O32p (seed 1), F_O32p (seed 2), B (oracle.bound's bound on the fitness
-change of a binary32 evaluation), floats written with repr (exact round trip).
+change of a binary32 evaluation with the library's operator accuracies,
+gates.DIV_EPS for its division), floats written with repr (exact round trip).
 
     python tests/golden/make_mid_fitness.py [--processes P]
 """
@@ -24,6 +25,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 sys.path.insert(0, os.path.dirname(HERE))
 
+import gates  # noqa: E402
 import golden_mid  # noqa: E402
 from oracle import population as opop  # noqa: E402
 from paper_2603_12292_amd import workloads as wl  # noqa: E402
@@ -42,7 +44,7 @@ def main():
         for mode, seed in (("o64", 0), ("o32e", 0), ("o32p", 1), ("o32p", 2), ("bound", 0)):
             f, st = opop.evaluate_population(ps.tokens, ps.tok_offset, ps.tok_len, ps.consts, ps.const_offset,
                                              ps.const_count, w.data.X, w.data.y, kind, mode,
-                                             processes=a.processes, seed=seed)
+                                             processes=a.processes, seed=seed, div_eps=gates.DIV_EPS)
             cols.append(f)
             if mode == "o64":
                 status = st

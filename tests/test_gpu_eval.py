@@ -321,25 +321,29 @@ def test_empty_population():
 
 
 def test_predict_against_o32e():
-    """Per-case outputs.  Programs of + - * / only: bit-identical to O32e
-    (IEEE fp32 with correctly rounded division).  Any program: identical NaN
-    pattern, and within 1e-5 of O64 on every case whose value is stable under
-    few-ulp perturbations (O32p, two seeds)."""
+    """Per-case outputs.  Programs of + - * only: bit-identical to O32e (IEEE
+    fp32).  Programs of + - * / and any program: the NaN pattern of O32e,
+    and every case whose running error bound (oracle.bound, with the
+    library's faithful division) is finite within it of O32e; within 1e-5
+    of O64 on every case stable under few-ulp perturbations (O32p, two
+    seeds)."""
+    from oracle import bound as ob
     data = wl.make_dataset(13, 600, 3, x_range=(-3.0, 5.0), target_len=8)
     ps = wl.random_population(14, 64, 1, 40, 3)
     rng = np.random.default_rng(5)
-    arith = []
+    arith, quot = [], []
     for _ in range(32):
         toks, consts = wl.random_program(rng, int(rng.integers(1, 40)), 3)
         # every unary token u becomes "x0 +" (top + x0): still a valid program
         out = []
         for t in toks:
             out += [t] if (t & 0xFF) >= 9 or (t & 0xFF) < 4 else [wl.tok(wl.VAR, 0), wl.tok(wl.ADD)]
-        arith.append((out, consts))
-    ps2 = wl.pack_programs(arith)
+        quot.append((out, consts))
+        arith.append(([wl.tok(wl.MUL) if (t & 0xFF) == wl.DIV else t for t in out], consts))
     api = _api()
     X = torch.from_numpy(data.X).cuda()
-    for pset, exact in ((ps, False), (ps2, True)):
+    n_bounded = 0
+    for pset, exact in ((ps, False), (wl.pack_programs(quot), False), (wl.pack_programs(arith), True)):
         out, st = api.predict(_dev(pset), X, with_status=True)
         out = out.cpu().numpy().astype(np.float64)
         assert np.all(st.cpu().numpy() == 0)
@@ -350,13 +354,50 @@ def test_predict_against_o32e():
                 assert np.array_equal(out[p].view(np.uint64), y32.view(np.uint64)) or \
                     np.array_equal(out[p], y32, equal_nan=True), p
                 continue
-            y64 = interp.run(t, c, data.X, "o64")
             assert np.array_equal(np.isnan(out[p]), np.isnan(y32)), p
+            b = ob.case_bounds(t, c, data.X, div_eps=gates.DIV_EPS)[2][-1]
+            fin = np.isfinite(b)
+            assert np.all(np.abs(out[p][fin] - y32[fin]) <= b[fin] * (1 + 1e-6)), p
+            n_bounded += int(fin.sum())
+            y64 = interp.run(t, c, data.X, "o64")
             spread = np.abs(y32 - y64)
             for s in (1, 2):
                 spread = np.maximum(spread, np.abs(interp.run(t, c, data.X, "o32p", seed=s) - y64))
             well = np.isfinite(y64) & (spread <= 1e-6 * np.abs(y64))
             assert np.all(np.abs(out[p][well] - y64[well]) <= 1e-5 * np.abs(y64[well])), p
+    assert n_bounded > 0.9 * 96 * 600
+
+
+def test_division_accuracy():
+    """The interpreter's protected division: within 1 ulp of the correctly
+    rounded binary32 quotient for every normal quotient (reciprocal, product
+    and one residual correction), and equal to it wherever the quotient is
+    zero, subnormal, infinite or NaN or the dividend is below 2^-100 in
+    magnitude (where the residual would underflow); 1 for a zero divisor.  Operands span
+    the binary32 range, with subnormals, signed zeros, +-Inf and NaN."""
+    rng = np.random.default_rng(24)
+    n = 300000
+    mag = lambda m: np.exp(rng.uniform(np.log(1e-45), np.log(3.4e38), m)) * rng.choice([-1, 1], m)
+    special = np.array([0.0, -0.0, 1e-45, -1e-40, 1e-38, 1.0, -1.0, 3.4e38, -3.4e38, np.inf, -np.inf, np.nan,
+                        2.0 ** 126, 2.0 ** 127, 2.0 ** -126, 2.0 ** -127], dtype=np.float32)
+    a = np.concatenate([mag(n), rng.uniform(-10, 10, n), np.repeat(special, len(special))]).astype(np.float32)
+    b = np.concatenate([mag(n), rng.uniform(-10, 10, n), np.tile(special, len(special))]).astype(np.float32)
+    X = torch.from_numpy(np.stack([a, b], axis=1).copy()).cuda()
+    api = _api()
+    progs = wl.pack_programs([([wl.tok(wl.VAR, 0), wl.tok(wl.VAR, 1), wl.tok(wl.DIV)], []),
+                              ([wl.tok(wl.VAR, 1), wl.tok(wl.VAR, 0), wl.tok(wl.DIV)], [])])
+    out = api.predict(_dev(progs), X).cpu().numpy()
+    for row, (num, den) in zip(out, ((a, b), (b, a))):
+        with np.errstate(all="ignore"):
+            ref = np.where(den == 0, np.float32(1.0), num / den).astype(np.float32)
+        normal = np.isfinite(ref) & (np.abs(ref) >= np.float32(2.0 ** -126)) & ~(np.abs(num) < np.float32(2.0 ** -100))
+        same = ~normal
+        assert np.array_equal(row[same].view(np.uint32), ref[same].view(np.uint32)) or \
+            np.array_equal(row[same], ref[same], equal_nan=True)
+        assert np.array_equal(np.isnan(row[same]), np.isnan(ref[same]))
+        d = np.abs(row[normal].view(np.int32).astype(np.int64) - ref[normal].view(np.int32).astype(np.int64))
+        print(f"normal quotients {int(normal.sum())}: max {int(d.max())} ulp, {int((d > 0).sum())} not correctly rounded")
+        assert d.max() <= 1
 
 
 def test_determinism():
