@@ -234,6 +234,18 @@ beagle_status beagle_eval_grad(beagle_ctx* ctx, const beagle_programs* progs, co
                                int kind, double* fitness, float* grad_consts, int8_t* status,
                                beagle_stream stream);
 
+/* Decoders of the programs of at most 64 tokens (beagle_ctx_set_decoder). */
+typedef enum { BEAGLE_DECODE_WAVE = 0, BEAGLE_DECODE_THREAD = 1 } beagle_decoder;
+
+/* Which kernel validates and decodes (section 2.1.4's reverse-Polish
+ * genomes into the interpreter's words) the programs of at most 64 tokens
+ * in every later call of this context: BEAGLE_DECODE_WAVE (the default),
+ * one wave per program with a token per lane, or BEAGLE_DECODE_THREAD, one
+ * thread per program.  Both give the same statuses and bit-identical
+ * results; the choice exists for testing and comparison.  Longer programs
+ * always take the thread decoder.  Unknown decoder: BEAGLE_E_INVALID_ARG. */
+beagle_status beagle_ctx_set_decoder(beagle_ctx* ctx, int decoder);
+
 /* Tile-width policies of the evaluator (beagle_ctx_set_tuning). */
 typedef enum { BEAGLE_TUNE_AUTO = 0, BEAGLE_TUNE_WIDE = 1, BEAGLE_TUNE_NARROW = 2 } beagle_tuning;
 

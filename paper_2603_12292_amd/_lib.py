@@ -26,6 +26,8 @@ FIT_MSE = 0
 FIT_CORR = 1
 FIT_POINT = 2
 FIT_R4 = 3
+DECODE_WAVE = 0
+DECODE_THREAD = 1
 TUNE_AUTO = 0
 TUNE_WIDE = 1
 TUNE_NARROW = 2
@@ -60,6 +62,7 @@ SIGNATURES = [
     ("beagle_ctx_enable_timing", c_int, [c_void_p, c_int]),
     ("beagle_ctx_kernel_time", c_int, [c_void_p, POINTER(c_double), POINTER(c_int64)]),
     ("beagle_ctx_set_tuning", c_int, [c_void_p, c_int]),
+    ("beagle_ctx_set_decoder", c_int, [c_void_p, c_int]),
     ("beagle_ctx_graph_stats", c_int, [c_void_p, POINTER(c_int64), POINTER(c_int64)]),
     ("beagle_ctx_tile_width", c_int, [c_void_p, c_int, c_int32, c_int64, c_int64, c_int32, POINTER(c_int32)]),
     ("beagle_eval", c_int, [c_void_p, POINTER(Programs), POINTER(Dataset), c_int, c_void_p, c_void_p, c_void_p]),

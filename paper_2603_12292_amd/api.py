@@ -66,6 +66,13 @@ class Context:
         code = names.get(policy, -1) if isinstance(policy, str) else int(policy)
         _check(self.lib.beagle_ctx_set_tuning(self.handle, code))
 
+    def set_decoder(self, decoder: str = "wave"):
+        """Decoder of the programs of at most 64 tokens: "wave" (one wave per
+        program, the default) or "thread" (one thread per program)."""
+        names = {"wave": _lib.DECODE_WAVE, "thread": _lib.DECODE_THREAD}
+        code = names.get(decoder, -1) if isinstance(decoder, str) else int(decoder)
+        _check(self.lib.beagle_ctx_set_decoder(self.handle, code))
+
     def tile_width(self, kind, D: int, M: int, n_tokens: int, n_programs: int) -> int:
         """Cases per lane beagle_eval uses for this shape (0: not measured yet)."""
         out = ctypes.c_int32()

@@ -164,7 +164,8 @@ EvalLayout eval_layout(const beagle_programs* P, const beagle_dataset* d, int n_
 // Validation + decoding of the programs and staging of the cases (shared by
 // evaluation, prediction and the gradient).
 beagle_status prepare(char* ws, const beagle_programs* P, const beagle_dataset* d, const EvalLayout& L,
-                      int8_t* status, hipStream_t s, int32_t max_words = bgl::MAX_LEN, bool adjoint = false) {
+                      int8_t* status, hipStream_t s, int decoder, int32_t max_words = bgl::MAX_LEN,
+                      bool adjoint = false) {
   zero_i32(reinterpret_cast<int32_t*>(ws + L.class_count), 64, s);
   bgl::PrepareArgs pa;
   pa.tokens = P->tokens;
@@ -204,7 +205,11 @@ beagle_status prepare(char* ws, const beagle_programs* P, const beagle_dataset* 
   hipLaunchKernelGGL(bgl::k_layout_check, dim3(pgrid), dim3(256), 0, s, pa);
   hipLaunchKernelGGL(bgl::k_layout_fill, dim3(1024), dim3(256), 0, s, pa);
   hipLaunchKernelGGL(bgl::k_layout_mark, dim3(std::min<uint32_t>(pgrid, 1024)), dim3(256), 0, s, pa);
-  hipLaunchKernelGGL(bgl::k_prepare, dim3((P->n_programs + 63) / 64), dim3(64), 0, s, pa);
+  if (decoder == BEAGLE_DECODE_THREAD)
+    hipLaunchKernelGGL(bgl::k_prepare, dim3((P->n_programs + 63) / 64), dim3(64), 0, s, pa);
+  else
+    hipLaunchKernelGGL(adjoint ? bgl::k_prepare_wave<true> : bgl::k_prepare_wave<false>,
+                       dim3((P->n_programs + 255) / 256), dim3(256), 0, s, pa);
   hipLaunchKernelGGL(bgl::k_prepare_long, dim3(512), dim3(64), 0, s, pa);
   bgl::StageArgs sa;
   sa.X = d->X;
@@ -365,6 +370,14 @@ beagle_status beagle_ctx_tile_width(beagle_ctx* ctx, int kind, int32_t D, int64_
   return BEAGLE_OK;
 }
 
+beagle_status beagle_ctx_set_decoder(beagle_ctx* ctx, int decoder) {
+  if (!ctx) return fail(BEAGLE_E_INVALID_ARG, "ctx is NULL");
+  if (decoder != BEAGLE_DECODE_WAVE && decoder != BEAGLE_DECODE_THREAD)
+    return fail(BEAGLE_E_INVALID_ARG, "unknown decoder");
+  ctx->decoder = decoder;
+  return BEAGLE_OK;
+}
+
 beagle_status beagle_ctx_set_tuning(beagle_ctx* ctx, int policy) {
   if (!ctx) return fail(BEAGLE_E_INVALID_ARG, "ctx is NULL");
   if (policy != BEAGLE_TUNE_AUTO && policy != BEAGLE_TUNE_WIDE && policy != BEAGLE_TUNE_NARROW)
@@ -401,7 +414,7 @@ EvalLayout capped_layout(const beagle_programs* progs, const beagle_dataset* dat
 beagle_status evaluate_in(char* ws, const EvalLayout& L, int32_t slice, beagle_ctx* ctx,
                           const beagle_programs* progs, const beagle_dataset* data, int kind, double smax,
                           double* fitness, int8_t* status, hipStream_t s) {
-  beagle_status st = prepare(ws, progs, data, L, status, s);
+  beagle_status st = prepare(ws, progs, data, L, status, s, ctx ? ctx->decoder : BEAGLE_DECODE_WAVE);
   if (st != BEAGLE_OK) return st;
   bool shift_in_kernel = false;
   if (kind == BEAGLE_FIT_CORR || kind == BEAGLE_FIT_R4) {
@@ -599,7 +612,7 @@ beagle_status beagle_predict(beagle_ctx* ctx, const beagle_programs* progs, cons
   EvalLayout L = eval_layout(progs, data, 1, 1);
   st = reserve(ctx, L.total);
   if (st != BEAGLE_OK) return st;
-  st = prepare(ctx->ws, progs, data, L, status, s);
+  st = prepare(ctx->ws, progs, data, L, status, s, ctx->decoder);
   if (st != BEAGLE_OK) return st;
   st = launch_values(ctx->ws, progs, data, L, data->M, yhat, 0, s);
   if (st != BEAGLE_OK) return st;
@@ -901,7 +914,7 @@ beagle_status beagle_eval_grad(beagle_ctx* ctx, const beagle_programs* progs, co
   EvalLayout L = eval_layout(progs, data, corr ? 3 : 1, progs->n_programs, true);
   st = reserve(ctx, L.total);
   if (st != BEAGLE_OK) return st;
-  st = prepare(ctx->ws, progs, data, L, status, s, bgl::GRAD_LONG_WORDS, true);
+  st = prepare(ctx->ws, progs, data, L, status, s, ctx->decoder, bgl::GRAD_LONG_WORDS, true);
   if (st != BEAGLE_OK) return st;
   char* ws = ctx->ws;
   if (corr) {

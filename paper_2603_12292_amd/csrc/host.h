@@ -39,6 +39,7 @@ struct beagle_ctx {
   bool timing = false;  // record events around the main evaluation kernel
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   int tuning = BEAGLE_TUNE_AUTO;
+  int decoder = BEAGLE_DECODE_WAVE;  // decoder of programs of at most 64 tokens
   std::map<bgl::host::TuneKey, int> tuned;  // bucket -> tile variant (0 wide, 1 narrow)
   std::string tune_file;                    // BEAGLE_AUTOTUNE_CACHE at creation ("" = none)
   // batched evaluation

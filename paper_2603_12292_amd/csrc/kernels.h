@@ -191,8 +191,9 @@ constexpr int32_t RESIDENT_MIN_PROGRAMS = 4096;
 constexpr int RESIDENT_BATCH = 16;  // programs a wave claims per atomic (long lists)
 __host__ __device__ constexpr int class_k(int c, int kv) { return c == 0 ? (kv == 0 ? 8 : 4) : (c == 1 ? 4 : 2); }
 
-// decoding: programs of at most 64 tokens in k_prepare (narrow LDS
-// scratch), the longer ones it lists in k_prepare_long
+// decoding: programs of at most 64 tokens in k_prepare_wave (a wave per
+// program) or k_prepare (a thread per program, narrow LDS scratch), the
+// longer ones they list for k_prepare_long
 // the disjoint-ranges check before decoding (see PrepareArgs::layout):
 // neighbour comparison, then (only when that found unsorted or overlapping
 // ranges) the owner arrays filled and marked
@@ -203,6 +204,9 @@ __global__ void k_layout_check_batch(BatchArgs b);
 __global__ void k_layout_fill_batch(BatchArgs b);
 __global__ void k_layout_mark_batch(BatchArgs b);
 __global__ void k_prepare(PrepareArgs a);
+// ADJ: also the adjoint's per-word operands and lists (PrepareArgs::adjoint)
+template <bool ADJ>
+__global__ void k_prepare_wave(PrepareArgs a);
 __global__ void k_prepare_long(PrepareArgs a);
 __global__ void k_stage_cases(StageArgs a);
 __global__ void k_prepare_batch(BatchArgs b);

@@ -462,6 +462,406 @@ __global__ void __launch_bounds__(PREP_BLOCK) k_prepare_long(PrepareArgs a) {
   }
 }
 
+// ---- wave-per-program decoding ---------------------------------------------
+// The same decoding (statuses, words, side tables, metadata, list
+// membership -- bit for bit) for a program of at most 64 tokens, with the
+// program's tokens spread over one wave's lanes (lane i holds token i) and
+// every sequential pass replaced by prefix sums and pointer chasing across
+// lanes, so a program costs a few hundred wave instructions whatever its
+// shape and no lane waits on another program's length.
+//  - depth after each token: a prefix sum of (1 - arity); the first faulty
+//    token (in token order) decides the status, as in the serial passes;
+//  - subtree start s_i of each token: one past the last earlier position
+//    whose depth is below token i's (found by a binary descent over the
+//    minima of power-of-two windows);
+//  - register need: repeated bottom-up relaxation (one round per tree
+//    level);
+//  - output position: each child learns from its parent (through LDS)
+//    whether it is placed second and behind how many tokens; the offsets
+//    are summed to the root by pointer jumping;
+//  - words: the re-ordered tokens are gathered through LDS; stack sizes,
+//    fused pairs and word indices are prefix sums; a word's producer and
+//    first word, and whether its subtree is constant-free, are read at its
+//    subtree's bounds.
+namespace wdec {
+
+__device__ __forceinline__ int lane_id() { return int(threadIdx.x & 63u); }
+// v of lane src (0 <= src < 64 where the result is used)
+__device__ __forceinline__ int from(int v, int src) { return __builtin_amdgcn_ds_bpermute(src << 2, v); }
+// v of the lane CTRL names (a DPP row shift or broadcast), 0 where that
+// lane is outside the row or the row is outside ROW_MASK
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int dpp(int v) { return __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xF, true); }
+// Inclusive prefix sum over the 64 lanes (all active), register to
+// register: row shifts by 1, 2, 4, 8 give each row of 16 its own prefix
+// sums, then lane 15's total is added into rows 1 and 3 and lane 31's into
+// rows 2 and 3.
+__device__ __forceinline__ int scan_add(int v) {
+  v += dpp<0x111, 0xF>(v);
+  v += dpp<0x112, 0xF>(v);
+  v += dpp<0x114, 0xF>(v);
+  v += dpp<0x118, 0xF>(v);
+  v += dpp<0x142, 0xA>(v);
+  v += dpp<0x143, 0xC>(v);
+  return v;
+}
+// Maximum / bitwise OR over the 64 lanes of non-negative values, the same
+// pattern (zero never changes a result), read from lane 63 (uniform).
+__device__ __forceinline__ int wave_max(int v) {
+  v = max(v, dpp<0x111, 0xF>(v));
+  v = max(v, dpp<0x112, 0xF>(v));
+  v = max(v, dpp<0x114, 0xF>(v));
+  v = max(v, dpp<0x118, 0xF>(v));
+  v = max(v, dpp<0x142, 0xA>(v));
+  v = max(v, dpp<0x143, 0xC>(v));
+  return __builtin_amdgcn_readlane(v, 63);
+}
+__device__ __forceinline__ uint32_t wave_or(uint32_t u) {
+  int v = int(u);
+  v |= dpp<0x111, 0xF>(v);
+  v |= dpp<0x112, 0xF>(v);
+  v |= dpp<0x114, 0xF>(v);
+  v |= dpp<0x118, 0xF>(v);
+  v |= dpp<0x142, 0xA>(v);
+  v |= dpp<0x143, 0xC>(v);
+  return uint32_t(__builtin_amdgcn_readlane(v, 63));
+}
+__device__ __forceinline__ int first_lane(uint64_t m) { return __ffsll((unsigned long long)m) - 1; }
+// selections whose operands are evaluated first (a conditional expression
+// with computed operands can become a lane-divergent branch)
+template <class T>
+__device__ __forceinline__ T sel(bool c, T a, T b) { return c ? a : b; }
+template <class T>
+__device__ __forceinline__ T pick4(int k, T a, T b, T c, T d) { return sel(k == 0, a, sel(k == 1, b, sel(k == 2, c, d))); }
+__device__ __forceinline__ int lane_value(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+
+}  // namespace wdec
+
+// Per-wave LDS of the wave decoder.
+struct WaveDecLds {
+  uint32_t a[64];
+  uint32_t b[64];
+};
+
+// Decodes program p (at most 64 tokens, its header fields given, uniform)
+// with the calling wave; `tok` is the lane's token (lane < L, when the
+// token range lies within the array; 0 otherwise).  Returns its lists
+// (wave-uniform).
+template <bool ADJ>
+__device__ static ListIds decode_wave(const PrepareArgs& a, int p, int64_t off, int32_t L, int64_t coff, int32_t cc,
+                                      uint32_t tok, WaveDecLds& sh) {
+  using namespace wdec;
+  const int lane = lane_id();
+  int status = BEAGLE_PROG_OK;
+  int need_root = 0, L_dec = 0;
+  uint32_t vmask = 0;
+  bool ext = false;
+  if (L <= 0) {
+    status = L == 0 ? BEAGLE_PROG_EMPTY : BEAGLE_PROG_BAD_LAYOUT;
+  } else if (off < 0 || off + L > a.n_tokens || cc < 0 || (cc > 0 && (coff < 0 || coff + cc > a.n_consts))) {
+    status = BEAGLE_PROG_BAD_LAYOUT;
+  } else if (a.layout) {
+    // ranges not sorted and disjoint: every slot must carry p as its owner
+    bool mine = true;
+    if (a.layout[0]) mine = __builtin_amdgcn_ballot_w64(lane < L && a.owner[off + lane] != p) == 0;
+    if (ADJ && mine && a.layout[1])
+      for (int32_t j0 = 0; j0 < cc && mine; j0 += 64)
+        mine = __builtin_amdgcn_ballot_w64(j0 + lane < cc && a.cowner[coff + j0 + lane] != p) == 0;
+    if (!mine) status = BEAGLE_PROG_BAD_LAYOUT;
+  }
+  if (status == BEAGLE_PROG_OK) {
+    const bool act = lane < L;
+    const uint32_t t = act ? tok : 0u;
+    const uint32_t op = t & 0xFFu, arg = t >> 8;
+    const bool opok = op < N_OPCODES;
+    // arity per opcode, 2 bits each (ADD..DIV 2, SIN..SQRT 1, VAR, CONST 0,
+    // SQUARE..TANH 1)
+    constexpr uint64_t ARITY = 0x5554155AAull;
+    const int ar = opok ? int((ARITY >> (2u * op)) & 3u) : 0;
+    // depth after each token
+    const int d = scan_add(act ? 1 - ar : 0);
+    // depth before < arity: underflow
+    const int err = !opok                              ? BEAGLE_PROG_BAD_OPCODE
+                    : (op == OP_VAR) & (int(arg) >= a.D)  ? BEAGLE_PROG_BAD_VAR
+                    : (op == OP_CONST) & (int(arg) >= cc) ? BEAGLE_PROG_BAD_CONST
+                    : d < 1                             ? BEAGLE_PROG_UNDERFLOW
+                                                        : 0;
+    const uint64_t em = __builtin_amdgcn_ballot_w64(act & (err != 0));
+    if (em) status = lane_value(err, first_lane(em));
+    else if (lane_value(d, L - 1) != 1) status = BEAGLE_PROG_BAD_FINAL_DEPTH;
+    if (status == BEAGLE_PROG_OK) {
+      vmask = wave_or(act & (op == OP_VAR) ? 1u << arg : 0u);
+      ext = __builtin_amdgcn_ballot_w64(act & (op - uint32_t(OP_SQUARE) < uint32_t(N_OPCODES - OP_SQUARE))) != 0;
+      // ---- subtree starts: s = 1 + the last j < lane with d_j < d (d_{-1} = 0)
+      int mn[6];
+      mn[0] = d;
+#pragma unroll
+      for (int k = 1; k < 6; ++k) {
+        const int w = 1 << (k - 1);
+        const int u = from(mn[k - 1], lane - w);
+        mn[k] = sel((lane >= w) & (u < mn[k - 1]), u, mn[k - 1]);  // min over [lane - 2^k + 1, lane]
+      }
+      int q = lane - 1;
+#pragma unroll
+      for (int k = 5; k >= 0; --k) {
+        const int v = from(mn[k], q > 0 ? q : 0);
+        q -= sel((q - (1 << k) + 1 >= 0) & (v >= d), 1 << k, 0);
+      }
+      const int st = q + 1;
+      // ---- register need, bottom-up: leaves 1; unary: the child's;
+      // binary: the larger child's, plus one when both are equal
+      const int s_prev = from(st, lane > 0 ? lane - 1 : 0);  // start of the right operand
+      const int lch = s_prev - 1;                              // left child (binary)
+      int need = ar == 0 ? 1 : 0;
+      int nr = 0, nl = 0;
+      for (;;) {
+        nr = from(need, lane > 0 ? lane - 1 : 0);
+        nl = from(need, lch > 0 ? lch : 0);
+        const int nb2 = sel((nl > 0) & (nr > 0), sel(nl == nr, nl + 1, max(nl, nr)), 0);
+        need = sel(ar == 1, nr, sel(ar == 2, nb2, need));
+        if (__builtin_amdgcn_ballot_w64(act & (need == 0)) == 0) break;
+      }
+      need_root = lane_value(need, L - 1);
+      // ---- output order: parents tell children their offset within the
+      // parent's output range; the root's range starts at 0
+      const bool swap = (ar == 2) & (nr > nl);
+      const int size_r = lane - s_prev;  // binary: the right operand's size
+      const int st_l = from(st, lch > 0 ? lch : 0);
+      const int size_l = lch - st_l + 1;
+      if (act && ar >= 1) sh.a[lane - 1] = uint32_t(lane) | (uint32_t(ar == 2 && !swap ? size_l : 0) << 8);
+      if (act && ar == 2) sh.a[lch] = uint32_t(lane) | (uint32_t(swap ? size_r : 0) << 8);
+      if (lane == L - 1) sh.a[lane] = uint32_t(lane);
+      __builtin_amdgcn_wave_barrier();
+      int pk = act ? int(sh.a[lane]) : lane;  // parent | offset << 8
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int r = 0; r < 6; ++r) {
+        const int v = from(pk, pk & 0xFF);
+        pk = (pk & ~0xFF) + v;  // offsets add up, the parent pointer jumps
+      }
+      const int ostart = pk >> 8;
+      const int oend = ostart + (lane - st);
+      const uint32_t op2 = sel(swap & (op == OP_SUB), 100u + B_RSUB, sel(swap & (op == OP_DIV), 100u + B_RDIV, op));
+      if (act) sh.b[oend] = op2 | (arg << 8) | (uint32_t(ostart) << 16);
+      __builtin_amdgcn_wave_barrier();
+      const uint32_t e = act ? sh.b[lane] : 0xFFu;
+      __builtin_amdgcn_wave_barrier();
+      // ---- words, in output order (lane o holds output token o)
+      const uint32_t o_op = e & 0xFFu, o_arg = (e >> 8) & 0xFFu;
+      const int o_st = int(e >> 16);  // start of its subtree
+      const bool o_bin = (o_op < 4u) | (o_op - 100u < 6u);
+      const bool o_term = o_op - uint32_t(OP_VAR) < 2u;  // VAR or CONST
+      const int o_delta = sel(act, sel(o_bin, -1, sel(o_term, 1, 0)), 0);
+      const int n_after = scan_add(o_delta);
+      const int n = n_after - o_delta;  // stack size before the token
+      const int nmax = wave_max(act ? n_after : 0);
+      const uint32_t nxt = uint32_t(from(int(o_op), lane < 63 ? lane + 1 : 63));
+      const bool nxt_bin = (lane + 1 < L) & ((nxt < 4u) | (nxt - 100u < 6u));
+      const bool fused = act & o_term & (n >= 1) & nxt_bin;
+      const bool absorbed = (lane > 0) & (((__builtin_amdgcn_ballot_w64(fused) << 1) >> lane) & 1u);
+      const bool ws = act & !absorbed;
+      const uint64_t wm = __builtin_amdgcn_ballot_w64(ws);
+      const int E = int(__builtin_amdgcn_mbcnt_hi(uint32_t(wm >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(wm), 0u)));
+      const int widx = ws ? E : E - 1;  // word of each token (a fused pair's operator: the pair's word)
+      L_dec = __popcll(wm);
+      // the word's handler and small-stack handler: fused pair, terminal
+      // push, binary operator, unary operator (all four computed, one
+      // selection each: no branch per kind)
+      const uint32_t un = uint32_t(n);
+      const uint32_t ob = nxt >= 100u ? nxt - 100u : nxt;     // the fused pair's operator
+      const uint32_t bo = o_op >= 100u ? o_op - 100u : o_op;  // a binary word's operator
+      const bool isc = o_op == OP_CONST, isv = o_op == OP_VAR;
+      const uint32_t u = unary_index(o_op);
+      const uint32_t isc1 = isc ? 1u : 0u;
+      const int kind = fused ? 0 : o_term ? 1 : o_bin ? 2 : 3;
+      const uint32_t h = pick4(kind, H_FUSED + 6u * isc1 + ob, isv ? H_VAR : H_CONST, H_BIN + 15u * bo + (un - 2u),
+                               H_UN + u);
+      const uint32_t i0_f = I0_FUSED + 3u * (6u * isc1 + ob) + (un - 1u);
+      const uint32_t i0_t = (isv ? I0_PUSH_VAR : I0_PUSH_CONST) + un;
+      const uint32_t i0_b = I0_BIN + 3u * bo + (un - 2u);
+      const uint32_t i0_u = I0_UN + 4u * u + (un - 1u);
+      const uint32_t i0 = pick4(kind, sel(n <= 3, i0_f, I0_NONE), sel(n <= 3, i0_t, I0_NONE), sel(n <= 4, i0_b, I0_NONE),
+                                sel((n <= 4) & (u < U_FIRST_EXT), i0_u, I0_NONE));
+      const uint32_t wslot = n > 0 ? un - 1u : 0u;
+      const uint32_t warg = o_term ? o_arg : 0u;
+      const uint32_t word = h | (warg << 8) | (wslot << 16) | (i0 << 24);
+      need_root = nmax > need_root ? nmax : need_root;
+      if (need_root > MAX_STACK || L_dec > a.max_words) status = BEAGLE_PROG_TOO_LONG;
+      if (ws) {
+        a.code[off + widx] = word;
+        if (isc) a.cval[off + widx] = a.consts[coff + o_arg];
+      }
+      int lc_short = -1;
+      if constexpr (ADJ) {
+        const int cst = scan_add(act & isc ? 1 : 0);  // CONST tokens up to here
+        // the token whose subtree the word produces, and that subtree's start
+        // (every cross-lane read runs on all lanes: inside a lane-dependent
+        // branch its source lane may be inactive)
+        const int last = sel(fused, lane + 1, lane);
+        const int st_next = from(o_st, lane < 63 ? lane + 1 : 63);
+        const int last_st = sel(fused, st_next, o_st);
+        const int c_hi = from(cst, last < 64 ? last : 63);
+        const int c_lo = from(cst, last_st > 0 ? last_st - 1 : 0);
+        const bool sub_cf = c_hi - (last_st > 0 ? c_lo : 0) == 0;  // no CONST in the subtree
+        const int wfst = from(widx, last_st);
+        // binary words: the producer of the left operand ends just before the
+        // right operand's subtree
+        const int r_st = from(o_st, lane > 0 ? lane - 1 : 0);
+        const int pa_w = from(widx, r_st > 0 ? r_st - 1 : 0);
+        // per operator (B_ADD .. B_RDIV, 8 bits each): reverse handler and
+        // derivative-tape entries of fused VAR words, fused CONST words and
+        // binary words
+        constexpr uint64_t RID_FV = uint64_t(R_FV_GEN) << 40 | uint64_t(R_FV_RSUB) << 32 | uint64_t(R_FV_GEN) << 24 |
+                                    uint64_t(R_FV_GEN) << 16 | uint64_t(R_NOP) << 8 | uint64_t(R_NOP);
+        constexpr uint64_t RID_FC = uint64_t(R_FC_RDIV) << 40 | uint64_t(R_FC_RSUB) << 32 | uint64_t(R_FC_DIV) << 24 |
+                                    uint64_t(R_FC_MUL) << 16 | uint64_t(R_FC_SUB) << 8 | uint64_t(R_FC_ADD);
+        constexpr uint64_t RID_BIN = uint64_t(R_BIN_GEN) << 40 | uint64_t(R_BIN_RSUB) << 32 |
+                                     uint64_t(R_BIN_GEN) << 24 | uint64_t(R_BIN_GEN) << 16 |
+                                     uint64_t(R_BIN_SUB) << 8 | uint64_t(R_BIN_ADD);
+        constexpr uint32_t ENT_FV = 0x101100u, ENT_FC = 0x201100u, ENT_BIN = 0x202200u;  // 4 bits each
+        const uint32_t rid_f = uint32_t(((isc ? RID_FC : RID_FV) >> (8u * ob)) & 0xFFu);
+        const uint32_t rid_b = uint32_t((RID_BIN >> (8u * bo)) & 0xFFu);
+        const int ent_f = int(((isc ? ENT_FC : ENT_FV) >> (4u * ob)) & 0xFu);
+        const int ent_b = int((ENT_BIN >> (4u * bo)) & 0xFu);
+        // the slot the reverse sweep writes, also the offset of the handler
+        const uint32_t rws = pick4(kind, un - 1u, un, un - 2u, un - 1u);
+        const uint32_t rid0 = pick4(kind, rid_f, isv ? R_NOP : R_PUSH_CONST, rid_b, R_UN);
+        const int rlim = kind <= 1 ? 3 : 4;
+        const int ent = pick4(kind, ent_f, 0, ent_b, 1);
+        const bool wcf = pick4<bool>(kind, (!isc) & sub_cf, isv, sub_cf, sub_cf);
+        const uint32_t pa = sel(kind == 2, uint32_t(pa_w), 0u);
+        const uint32_t rid = sel(wcf | (rid0 == R_NOP), R_NOP, sel(n <= rlim, rid0 + rws, R_NONE));
+        const int n_ent = lane_value(scan_add(ws & !wcf ? ent : 0), 63);
+        lc_short = L_dec > a.short_words ? 1
+                   : need_root > 4 || cc > GRAD_LANE_SLOTS || ext ? 0
+                   : n_ent <= GRAD_DTAPE_SMALL ? 2 : n_ent <= GRAD_DTAPE_MID ? 3
+                   : n_ent <= GRAD_DTAPE_LARGE ? 4 : 0;
+        const bool dtape = status == BEAGLE_PROG_OK && lc_short >= 2;
+        if (ws && !dtape) a.aux[off + widx] = pa | (rws << 16) | (rid << 24);
+        // ---- the derivative-tape adjoint's words (see dtape_words)
+        if (dtape) {
+          // per word u (lane u): first word of its subtree with the
+          // constant-free flag, its reverse handler, its code word
+          if (ws) {
+            sh.a[widx] = uint32_t(wfst) | (wcf ? 0x8000u : 0u) | (rid << 16);
+            sh.b[widx] = word;
+          }
+          __builtin_amdgcn_wave_barrier();
+          const bool wact = lane < L_dec;
+          const uint32_t fw = wact ? sh.a[lane] : 0u;
+          const uint32_t c = wact ? sh.b[lane] : 0u;
+          __builtin_amdgcn_wave_barrier();
+          const bool ucf = (fw & 0x8000u) != 0;
+          const uint32_t urid = (fw >> 16) & 0xFFu;
+          const int sk = ucf ? int(fw & 0x7FFFu) - 1 : lane - 1;
+          const bool real = (!ucf) & (urid != R_NOP);
+          // vis(u) = u + 1 if real, vis(sk) if sk >= 0, else 0: pointer
+          // jumping over the skip links (state: the value | 0x100 once known,
+          // else the link)
+          int stv = sel(real, (lane + 1) | 0x100, sel(sk < 0, 0x100, sk));
+#pragma unroll
+          for (int r = 0; r < 6; ++r) {
+            const int v = from(stv, stv & 0xFF);
+            stv = sel((stv & 0x100) != 0, stv, v);
+          }
+          const int vis = stv & 0xFF;
+          const int next1 = from(vis, sk > 0 ? sk : 0);
+          const uint32_t fid = ucf ? fwd_notape(c >> 24) : (c >> 24);
+          if (wact)
+            a.aux[off + lane] = uint32_t(sk >= 0 ? next1 : 0) | (fid << 8) | (((c >> 8) & 0xFFu) << 16) | (urid << 24);
+        }
+      }
+      L_dec = status == BEAGLE_PROG_OK ? L_dec : 0;
+      ListIds ids;
+      if (status == BEAGLE_PROG_OK) {
+        ids.cls = need_class(need_root);
+        if (ext && ids.cls == 0) ids.cls = 1;
+        ids.lc = lc_short;
+      }
+      if (lane == 0) {
+        ProgMeta m;
+        m.status = status;
+        m.need = need_root;
+        m.len = L_dec;
+        m.shift = 0.0f;
+        m.vmask = status == BEAGLE_PROG_OK ? vmask : 0u;
+        a.meta[p] = m;
+        if (a.status_out) a.status_out[p] = int8_t(status);
+      }
+      return ids;
+    }
+  }
+  if (lane == 0) {
+    ProgMeta m;
+    m.status = status;
+    m.need = 0;
+    m.len = 0;
+    m.shift = 0.0f;
+    m.vmask = 0u;
+    a.meta[p] = m;
+    if (a.status_out) a.status_out[p] = int8_t(status);
+  }
+  return ListIds{};
+}
+
+// Four waves per workgroup, 64 consecutive programs per wave decoded one at
+// a time; a program longer than 64 tokens is appended to the long list for
+// k_prepare_long.  List appends as in k_prepare (one atomic per list and
+// wave).
+// The program headers of a wave's 64 programs are loaded once (lane j:
+// program j), and each program's tokens are loaded while the previous
+// program is decoded.
+__device__ __forceinline__ int64_t lane64(int64_t v, int j) {
+  const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(uint64_t(v)), j);
+  const uint32_t hi = __builtin_amdgcn_readlane(uint32_t(uint64_t(v) >> 32), j);
+  return int64_t((uint64_t(hi) << 32) | lo);
+}
+
+template <bool ADJ>
+__global__ void __launch_bounds__(256) k_prepare_wave(PrepareArgs a) {
+  __shared__ WaveDecLds lds[4];
+  const int lane = int(threadIdx.x & 63u), w = int(threadIdx.x >> 6);
+  const int64_t base = (int64_t(blockIdx.x) * 4 + w) * 64;
+  const int64_t pl = base + lane;
+  const bool have = pl < a.n_programs;
+  const int32_t hL = have ? a.tok_len[pl] : 0;
+  const int64_t hoff = have ? a.tok_offset[pl] : 0;
+  const int64_t hcoff = have ? a.const_offset[pl] : 0;
+  const int32_t hcc = have ? a.const_count[pl] : 0;
+  const int nb = base < a.n_programs ? int(a.n_programs - base < 64 ? a.n_programs - base : 64) : 0;
+  // the lane's token of program j, where program j is decoded here and its
+  // token range lies within the array (else 0: the decoder reports it)
+  auto fetch = [&](int j) -> uint32_t {
+    const int32_t L = __builtin_amdgcn_readlane(hL, j);
+    const int64_t off = lane64(hoff, j);
+    const bool ok = L >= 1 && L <= PREP_NARROW && off >= 0 && off + L <= a.n_tokens && lane < L;
+    return ok ? uint32_t(a.tokens[off + lane]) : 0u;
+  };
+  int cls = -1, lc = -1;
+  bool defer = false;
+  uint32_t t_next = nb > 0 ? fetch(0) : 0u;
+  for (int j = 0; j < nb; ++j) {
+    const uint32_t t = t_next;
+    if (j + 1 < nb) t_next = fetch(j + 1);
+    const int32_t L = __builtin_amdgcn_readlane(hL, j);
+    if (L > PREP_NARROW) {
+      defer |= lane == j;
+      continue;
+    }
+    const ListIds ids = decode_wave<ADJ>(a, int(base + j), lane64(hoff, j), L, lane64(hcoff, j),
+                                    __builtin_amdgcn_readlane(hcc, j), t, lds[w]);
+    cls = wdec::sel(lane == j, ids.cls, cls);
+    lc = wdec::sel(lane == j, ids.lc, lc);
+  }
+  const int p = int(base + lane);
+  wave_append<1>(defer ? 0 : -1, p, a.long_count, a.long_list, 0);
+  wave_append<N_CLASSES>(cls, p, a.class_count, a.class_list, a.n_programs);
+  if (ADJ) wave_append<GRAD_LISTS>(lc, p, a.len_count, a.len_list, a.n_programs);
+}
+
+template __global__ void k_prepare_wave<false>(PrepareArgs a);
+template __global__ void k_prepare_wave<true>(PrepareArgs a);
+
 // ---- disjoint-ranges check -------------------------------------------------
 // Token range of program p when it lies within the token array (else
 // false: the program is rejected by the layout checks of the decoder).
