@@ -388,6 +388,60 @@ def paper_loop_bench(generations: int, op_set: int = 0):
             "mean_len_last": round(tokens[-1] / paper_pop_size(generations - 1), 2)}
 
 
+def selection_bench(populations=(1_000_000, 5_000_000), reps: int = 20):
+    """The context of the paper's section 2.1.6 (microcosm selection against
+    a full ranking): per population size, the microcosm selection pass
+    (threshold from a 100-draw sample, survivor list; beagle_generation_
+    microcosm without children) against a full ranking of the same float64
+    fitness on the GPU (torch.sort, a device radix sort, then the better
+    half's indices as the survivor list), both timed with events, fitness
+    resident (uniform values with 1 % NaN)."""
+    import torch
+    from paper_2603_12292_amd import api
+    ctx = api.context(0)
+    params = api.GenParams(tournament=1, p_crossover=0.0, p_mutation=1.0, max_len=64, max_consts=8,
+                           init_depth_min=2, init_depth_max=5)
+    rows = []
+    for n in populations:
+        g = torch.Generator(device="cuda").manual_seed(7)
+        fit = torch.rand(n, dtype=torch.float64, device="cuda", generator=g)
+        fit[torch.rand(n, device="cuda", generator=g) < 0.01] = float("nan")
+        # parents are not read without children: a one-token program per slot
+        toks = torch.full((n,), 9, dtype=torch.int16, device="cuda")
+        progs = api.DevicePrograms(toks, torch.arange(n, dtype=torch.int64, device="cuda"),
+                                   torch.ones(n, dtype=torch.int32, device="cuda"),
+                                   torch.zeros(1, dtype=torch.float32, device="cuda"),
+                                   torch.zeros(n, dtype=torch.int64, device="cuda"),
+                                   torch.zeros(n, dtype=torch.int32, device="cuda"))
+
+        def micro(i):
+            return api.generation_microcosm(progs, fit, params, 1, 11, i, 0, sample=100, keep=0.5,
+                                            with_selection=True, ctx=ctx)
+
+        def ranking(i):
+            order = torch.sort(fit).indices   # ascending, NaN last
+            return order[: n // 2]
+
+        out = {}
+        for name, fn in (("microcosm_select_ms", micro), ("full_ranking_ms", ranking)):
+            for i in range(3):
+                fn(i)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for i in range(reps):
+                fn(i)
+            e1.record()
+            torch.cuda.synchronize()
+            out[name] = round(e0.elapsed_time(e1) / reps, 4)
+        _, _, ns = micro(0)
+        out.update({"population": n, "microcosm_survivors": int(ns.item()),
+                    "ranking_over_microcosm": round(out["full_ranking_ms"] / out["microcosm_select_ms"], 1)})
+        rows.append(out)
+    return {"workload": "selection on float64 fitness (uniform, 1 % NaN): microcosm (sample 100, keep 0.5) "
+                        "against a full device sort keeping the better half", "rows": rows}
+
+
 def ragged_bench(ws, steps: int, warmup: int):
     """The 64-problem ragged workload (1024 programs each, L~U{5..96},
     D~U{1..9}, M=round(10^U(3,6)), MSE): one batched call (a replayed HIP
@@ -496,6 +550,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--main-only", action="store_true",
+                    help="only the main line (every other line and the CPU baseline skipped): the run whose "
+                         "kernel trace gives the interpreter's average launch duration")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-ragged", action="store_true")
     ap.add_argument("--no-scores", action="store_true", help="skip the paper's Eq. 2 / Eq. 3 score rates")
@@ -513,6 +570,8 @@ def main():
 
     w = wl.config_mid()
     ps = w.programs
+    if args.main_only:
+        args.no_cpu_baseline = True
     ragged = wl.ragged_problems() if not (args.no_ragged and args.no_cpu_baseline) else None
     # the CPU oracle first: its worker processes are forked before this
     # process starts the GPU runtime (forking after that is not safe)
@@ -591,6 +650,9 @@ def main():
     if cpu is not None:
         main_cpu, other_cpu, f64 = cpu
         out["parity"] = parity_stats(fit, f64, w, 1)
+    if args.main_only:
+        print(json.dumps(out), flush=True)
+        return
     mid_mse, _, fit_mse = plain_rate(w, "mse", args.steps, args.warmup, ctx)
     out["plain_mid_mse"] = {"workload": "plain-mid, MSE", "gpops": round(mid_mse, 2)}
     if cpu is not None:
@@ -614,6 +676,7 @@ def main():
     if args.paper_loop > 0:
         out["paper_loop"] = paper_loop_bench(args.paper_loop)
         out["paper_loop_16_ops"] = paper_loop_bench(args.paper_loop, op_set=1)
+        out["selection"] = selection_bench()
     if cpu is not None:
         out["cpu_baseline"] = main_cpu
         out["cpu_baselines_other"] = other_cpu

@@ -18,6 +18,14 @@
       a population of 1024 identical programs on 2^17 cases, MSE, 4 cases
       per lane: run under rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_SALU.
 
+  python -m paper_2603_12292_amd.profiling paper [--steps N] [--kind mse]
+      one warm-up and N evaluations of the paper-regime population (2^20
+      programs on 512 cases).
+
+  python -m paper_2603_12292_amd.profiling summarize-kernels --trace DIR --pmc DIR... --kernels a,b --out PREFIX
+      per named kernel: kernel-trace duration and the mean per dispatch of
+      every counter of the given counter runs (PREFIX.txt, PREFIX.json).
+
   python -m paper_2603_12292_amd.profiling summarize-ops --pmc CSV --out PREFIX
       per-operator VALU lane-operations and SALU instructions per node-case
       from that run (PREFIX.txt).
@@ -251,6 +259,69 @@ def summarize(trace_dir, fetch_csv, write_csv, out_prefix, command, valu_csv=Non
     print("\n".join(lines))
 
 
+def run_paper(steps: int, kind: str = "mse"):
+    """The paper-regime evaluation: 2^20 programs (plain-mid replicated 256
+    times) on 512 cases, one warm-up and `steps` whole-population
+    evaluations."""
+    import torch
+    sys.path.insert(0, ROOT)
+    from paper_2603_12292_amd import api
+    from paper_2603_12292_amd import workloads as wl
+    w = wl.config_paper_shape()
+    progs = api.DevicePrograms.from_programset(w.programs, "cuda:0")
+    X = torch.from_numpy(w.data.X).cuda()
+    y = torch.from_numpy(w.data.y).cuda()
+    for _ in range(steps + 1):
+        api.evaluate(progs, X, y, kind)
+    torch.cuda.synchronize()
+    print(f"profiled {steps} evaluation(s) of {w.name}, {kind}", flush=True)
+
+
+def summarize_kernels(trace_dir, pmc_dirs, kernels, out_prefix, command, title):
+    """Per kernel whose name contains one of `kernels`: calls and average
+    duration from the kernel trace, and the mean per dispatch of every
+    counter of the counter runs."""
+    stats = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
+    rows = []
+    if stats:
+        with open(stats[0]) as f:
+            rows = list(csv.DictReader(f))
+    lines = [f"command: {command}", title, "", "kernel-trace statistics (ns):",
+             f"{'calls':>6} {'average':>12} {'total':>14} {'%':>6}  name"]
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    for r in rows[:16]:
+        lines.append(f"{int(r['Calls']):6d} {float(r['AverageNs']):12.1f} {float(r['TotalDurationNs']):14.1f} "
+                     f"{float(r['Percentage']):6.2f}  {r['Name'][:90]}")
+    rec = {}
+    for d in pmc_dirs:
+        per, names = _counter_rows(d)
+        for disp in sorted(per):
+            for k in kernels:
+                if k in names[disp]:
+                    name = names[disp][:names[disp].find("(")] if "(" in names[disp] else names[disp]
+                    slot = rec.setdefault(name, defaultdict(list))
+                    for c, v in per[disp].items():
+                        slot[c].append(v)
+    lines += ["", "counters, mean per dispatch:"]
+    summary = {}
+    for name, cs in sorted(rec.items()):
+        lines.append(f"  {name}")
+        summary[name] = {}
+        for c in sorted(cs):
+            v = sum(cs[c]) / len(cs[c])
+            summary[name][c] = v
+            lines.append(f"    {c:<22} {v:16.6g}   ({len(cs[c])} dispatches)")
+        w = summary[name].get("SQ_WAVES")
+        for c in ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM", "SQ_WAVE_CYCLES"):
+            if w and c in summary[name]:
+                lines.append(f"    {c + ' per wave':<34} {summary[name][c] / w:10.1f}")
+    with open(out_prefix + ".txt", "w") as f:
+        f.write("\n".join(lines) + "\n")
+    with open(out_prefix + ".json", "w") as f:
+        json.dump(summary, f, indent=1)
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -266,6 +337,16 @@ def main():
     s.add_argument("--out", required=True)
     s.add_argument("--command", default="")
     sub.add_parser("ops")
+    pp = sub.add_parser("paper")
+    pp.add_argument("--steps", type=int, default=2)
+    pp.add_argument("--kind", default="mse")
+    sk = sub.add_parser("summarize-kernels")
+    sk.add_argument("--trace", required=True)
+    sk.add_argument("--pmc", nargs="*", default=[])
+    sk.add_argument("--kernels", required=True, help="comma-separated name fragments")
+    sk.add_argument("--out", required=True)
+    sk.add_argument("--command", default="")
+    sk.add_argument("--title", default="")
     so = sub.add_parser("summarize-ops")
     so.add_argument("--pmc", required=True)
     so.add_argument("--out", required=True)
@@ -275,6 +356,10 @@ def main():
         run(a.steps, a.adjoint)
     elif a.cmd == "ops":
         run_ops()
+    elif a.cmd == "paper":
+        run_paper(a.steps, a.kind)
+    elif a.cmd == "summarize-kernels":
+        summarize_kernels(a.trace, a.pmc, a.kernels.split(","), a.out, a.command, a.title)
     elif a.cmd == "summarize-ops":
         summarize_ops(a.pmc, a.out, a.command)
     else:
