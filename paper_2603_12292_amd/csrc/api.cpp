@@ -198,6 +198,7 @@ beagle_status prepare(char* ws, const beagle_programs* P, const beagle_dataset* 
   pa.layout = reinterpret_cast<int32_t*>(ws + L.class_count) + 32;
   pa.owner = reinterpret_cast<int32_t*>(ws + L.owner);
   pa.cowner = adjoint ? reinterpret_cast<int32_t*>(ws + L.cowner) : nullptr;
+  pa.wave_programs = 64;
   // disjoint ranges (the fill and mark passes return at once when the
   // ranges are sorted and disjoint), then programs of at most 64 tokens,
   // then the ones longer than that
@@ -207,9 +208,16 @@ beagle_status prepare(char* ws, const beagle_programs* P, const beagle_dataset* 
   hipLaunchKernelGGL(bgl::k_layout_mark, dim3(std::min<uint32_t>(pgrid, 1024)), dim3(256), 0, s, pa);
   if (decoder == BEAGLE_DECODE_THREAD)
     hipLaunchKernelGGL(bgl::k_prepare, dim3((P->n_programs + 63) / 64), dim3(64), 0, s, pa);
-  else
+  else {
+    // programs per wave: 64 for large populations, fewer when that leaves
+    // under 4096 waves (16 per CU), so that small populations still fill the
+    // chip
+    const int64_t n = P->n_programs;
+    pa.wave_programs = int32_t(std::max<int64_t>(1, std::min<int64_t>(64, n / 4096)));
+    const int64_t waves = (n + pa.wave_programs - 1) / pa.wave_programs;
     hipLaunchKernelGGL(adjoint ? bgl::k_prepare_wave<true> : bgl::k_prepare_wave<false>,
-                       dim3((P->n_programs + 255) / 256), dim3(256), 0, s, pa);
+                       dim3(uint32_t((waves + 3) / 4)), dim3(256), 0, s, pa);
+  }
   hipLaunchKernelGGL(bgl::k_prepare_long, dim3(512), dim3(64), 0, s, pa);
   bgl::StageArgs sa;
   sa.X = d->X;

@@ -209,6 +209,7 @@ beagle_status beagle_eval_batched(beagle_ctx* ctx, const beagle_programs* progs,
     pa.layout = counts + int64_t(64) * i + 32;
     pa.owner = reinterpret_cast<int32_t*>(ws + o.owner);
     pa.cowner = nullptr;
+    pa.wave_programs = 64;
     t.X = d.X;
     t.y = d.y;
     t.Xt = reinterpret_cast<float*>(ws + o.Xt);

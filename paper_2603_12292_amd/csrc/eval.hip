@@ -538,12 +538,16 @@ __device__ __forceinline__ void eval_block(const EvalArgs& a, int p, int c, doub
 // items from an atomic counter, chunk-major so that the workgroups running
 // at any moment share one chunk of cases in L2.  Which workgroup takes which
 // item does not change any result: each item writes its own partial.
-// The 4-case class-0 variant is held to 72 VGPRs: seven waves per SIMD
-// instead of five at its natural 85 (eight would not fit the LDS of seven
-// workgroups' input tiles at D = 5 anyway); the values this moves to scratch
-// are per-item and per-tile bookkeeping, none inside the per-token loop.
+// The 4-case class-0 variant is held to CLASS0_NARROW_WAVES waves per SIMD
+// (7: 72 VGPRs instead of its natural 85, five waves; eight would not fit
+// the LDS of seven workgroups' input tiles at D = 5 anyway); the values this
+// moves to scratch are per-item and per-tile bookkeeping, none inside the
+// per-token loop.
+#ifndef CLASS0_NARROW_WAVES
+#define CLASS0_NARROW_WAVES 7
+#endif
 template <int KIND, int CLS, int KV>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CLS == 0 && KV == 1 ? 7 : 1)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CLS == 0 && KV == 1 ? CLASS0_NARROW_WAVES : 1)))
 k_eval_class(EvalArgs a) {
   constexpr int S = class_stack(CLS);
   constexpr int K = class_k(CLS, KV);

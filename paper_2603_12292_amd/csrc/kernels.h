@@ -51,6 +51,8 @@ struct PrepareArgs {
   int32_t* layout;
   int32_t* owner;   // [n_tokens]
   int32_t* cowner;  // [n_consts] (adjoint only)
+  // programs each wave of k_prepare_wave decodes (1..64)
+  int32_t wave_programs;
 };
 
 struct StageArgs {

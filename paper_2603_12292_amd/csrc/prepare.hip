@@ -804,13 +804,13 @@ __device__ static ListIds decode_wave(const PrepareArgs& a, int p, int64_t off, 
   return ListIds{};
 }
 
-// Four waves per workgroup, 64 consecutive programs per wave decoded one at
-// a time; a program longer than 64 tokens is appended to the long list for
-// k_prepare_long.  List appends as in k_prepare (one atomic per list and
-// wave).
-// The program headers of a wave's 64 programs are loaded once (lane j:
-// program j), and each program's tokens are loaded while the previous
-// program is decoded.
+// Four waves per workgroup, a.wave_programs (1..64) consecutive programs per
+// wave decoded one at a time (few per wave when the population is small, so
+// that the grid still fills the chip); a program longer than 64 tokens is
+// appended to the long list for k_prepare_long.  List appends as in
+// k_prepare (one atomic per list and wave).  The program headers of a
+// wave's programs are loaded once (lane j: program j), and each program's
+// tokens are loaded while the previous program is decoded.
 __device__ __forceinline__ int64_t lane64(int64_t v, int j) {
   const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(uint64_t(v)), j);
   const uint32_t hi = __builtin_amdgcn_readlane(uint32_t(uint64_t(v) >> 32), j);
@@ -821,14 +821,15 @@ template <bool ADJ>
 __global__ void __launch_bounds__(256) k_prepare_wave(PrepareArgs a) {
   __shared__ WaveDecLds lds[4];
   const int lane = int(threadIdx.x & 63u), w = int(threadIdx.x >> 6);
-  const int64_t base = (int64_t(blockIdx.x) * 4 + w) * 64;
+  const int ppw = a.wave_programs;
+  const int64_t base = (int64_t(blockIdx.x) * 4 + w) * ppw;
   const int64_t pl = base + lane;
-  const bool have = pl < a.n_programs;
+  const bool have = lane < ppw && pl < a.n_programs;
   const int32_t hL = have ? a.tok_len[pl] : 0;
   const int64_t hoff = have ? a.tok_offset[pl] : 0;
   const int64_t hcoff = have ? a.const_offset[pl] : 0;
   const int32_t hcc = have ? a.const_count[pl] : 0;
-  const int nb = base < a.n_programs ? int(a.n_programs - base < 64 ? a.n_programs - base : 64) : 0;
+  const int nb = base < a.n_programs ? int(a.n_programs - base < ppw ? a.n_programs - base : ppw) : 0;
   // the lane's token of program j, where program j is decoded here and its
   // token range lies within the array (else 0: the decoder reports it)
   auto fetch = [&](int j) -> uint32_t {
@@ -853,7 +854,7 @@ __global__ void __launch_bounds__(256) k_prepare_wave(PrepareArgs a) {
     cls = wdec::sel(lane == j, ids.cls, cls);
     lc = wdec::sel(lane == j, ids.lc, lc);
   }
-  const int p = int(base + lane);
+  const int p = int(base + lane);  // (lanes without a program append nothing)
   wave_append<1>(defer ? 0 : -1, p, a.long_count, a.long_list, 0);
   wave_append<N_CLASSES>(cls, p, a.class_count, a.class_list, a.n_programs);
   if (ADJ) wave_append<GRAD_LISTS>(lc, p, a.len_count, a.len_list, a.n_programs);

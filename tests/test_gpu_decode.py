@@ -122,12 +122,14 @@ def test_decoders_agree_on_gradients(kind):
     assert np.count_nonzero(gw.cpu().numpy()) > 5000
 
 
-def test_decoders_agree_on_a_large_population():
-    """2^16 programs of the benchmark's shape (many waves and workgroups, the
-    list appends of every wave), on 512 cases."""
+@pytest.mark.parametrize("log2n", [16, 18])
+def test_decoders_agree_on_a_large_population(log2n):
+    """2^16 and 2^18 programs of the benchmark's shape on 512 cases: many
+    waves and workgroups, 16 and 64 programs per wave of the wave decoder,
+    the list appends of every wave."""
     api = _api()
     cw, ct = _contexts()
-    ps = wl.random_population(39, 1 << 16, 5, 64, 5)
+    ps = wl.random_population(39, 1 << log2n, 5, 64, 5)
     data = wl.make_dataset(40, 512, 5, x_range=(1.0, 10.0), target_len=20)
     X, y = torch.from_numpy(data.X).cuda(), torch.from_numpy(data.y).cuda()
     P = api.DevicePrograms.from_programset(ps)
