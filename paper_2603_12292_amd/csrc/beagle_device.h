@@ -123,6 +123,8 @@ __device__ __forceinline__ float op_div_cr(float a, float b) { return b == 0.0f 
 
 // binary32 classes (the mask of v_cmp_class_f32): +-normal numbers
 constexpr int CLASS_NORMAL = (1 << 3) | (1 << 8);
+// NaN, +-Inf, +-0 and +-subnormal numbers
+constexpr int CLASS_NOT_NORMAL = 0x3FF & ~CLASS_NORMAL;
 // +-0 and +-subnormal numbers
 constexpr int CLASS_ZERO_SUB = (1 << 4) | (1 << 5) | (1 << 6) | (1 << 7);
 
@@ -133,26 +135,29 @@ constexpr int CLASS_ZERO_SUB = (1 << 4) | (1 << 5) | (1 << 6) | (1 << 7);
 // number (a zero divisor, a zero, subnormal, infinite or NaN quotient, or a
 // reciprocal out of range), or when |a| < 2^-100 (below about 2^-102 the
 // residual underflows and is no longer exact), the case takes the correctly
-// rounded protected quotient instead.  The choice depends on the case alone, so every grouping
-// of cases into waves gives the same values; the correctly rounded path runs
-// only when some lane of the wave needs it.
+// rounded protected quotient instead.  The choice depends on the case
+// alone, so every grouping of cases into waves gives the same values; the
+// correctly rounded path runs only when some lane of the wave needs it.
 template <int K>
 __device__ __forceinline__ void div_tile(const float (&a)[K], const float (&b)[K], float (&q)[K]) {
   uint64_t any = 0;
+  bool odd_any = false;
   bool bad[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const float r = __builtin_amdgcn_rcpf(b[k]);
     const float q0 = a[k] * r;
     q[k] = __builtin_fmaf(__builtin_fmaf(-b[k], q0, a[k]), r, q0);
-    // not normal: |q| outside [2^-126, FLT_MAX] (zeros, subnormals, infinities)
-    // or NaN, as one median and one comparison (NaN compares unequal)
-    const float aq = __builtin_fabsf(q[k]);
-    const bool odd = __builtin_amdgcn_fmed3f(aq, 0x1p-126f, 0x1.fffffep127f) != aq;
+    // q not a normal number (one class test), or a tiny dividend
+    const bool odd = __builtin_amdgcn_classf(q[k], CLASS_NOT_NORMAL);
     const bool tiny = __builtin_fabsf(a[k]) < 0x1p-100f;
-    bad[k] = odd || tiny;
-    any |= __builtin_amdgcn_ballot_w64(odd) | __builtin_amdgcn_ballot_w64(tiny);
+    bad[k] = odd | tiny;
+    odd_any |= odd;
+    any |= __builtin_amdgcn_ballot_w64(tiny);
   }
+  // (a comparison's ballot is its own result mask; the class tests' lane
+  // masks are OR-ed first and turned into one ballot)
+  any |= __builtin_amdgcn_ballot_w64(odd_any);
   if (any) {
 #pragma unroll
     for (int k = 0; k < K; ++k) q[k] = bad[k] ? op_div_cr(a[k], b[k]) : q[k];
@@ -199,8 +204,10 @@ __device__ __forceinline__ float op_sqrt(float x) {
   return tiny ? s * 0x1p-16f : s;
 }
 
-// Whether any of the K values of any lane satisfies `cond`: one compare
-// per value into a wave mask, the masks OR-ed in scalar registers.
+// Whether any of the K values of any lane satisfies `cond`, a comparison:
+// each comparison's result is already a wave mask, OR-ed in scalar
+// registers.  (A class test's result is not folded into its ballot that
+// way: those are OR-ed as lane masks first and balloted once.)
 template <int K, class F>
 __device__ __forceinline__ bool wave_any(F cond) {
   uint64_t m = 0;
@@ -231,7 +238,10 @@ __device__ __forceinline__ void exp_tile(float (&v)[K]) {
 
 template <int K>
 __device__ __forceinline__ void log_tile(float (&v)[K]) {
-  if (!wave_any<K>([&](int k) { return __builtin_amdgcn_classf(v[k], CLASS_ZERO_SUB); })) {
+  bool z = false;
+#pragma unroll
+  for (int k = 0; k < K; ++k) z |= __builtin_amdgcn_classf(v[k], CLASS_ZERO_SUB);
+  if (__builtin_amdgcn_ballot_w64(z) == 0) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const float y = __builtin_amdgcn_logf(__builtin_fabsf(v[k]));
