@@ -47,8 +47,8 @@ constexpr size_t MAX_GRAPHS = 8;
 
 struct Batch {
   bgl::BatchArgs args;
-  int max_d[bgl::N_LISTS];
-  int has[bgl::N_LISTS];
+  int max_d[bgl::N_BATCH_LISTS];
+  int has[bgl::N_BATCH_LISTS];
   int64_t n_programs = 0, n_cases = 0;
   int n = 0;
 };
@@ -124,8 +124,8 @@ beagle_status beagle_eval_batched(beagle_ctx* ctx, const beagle_programs* progs,
   // workspace layout
   Carve c;
   const size_t at_table = c.take<bgl::BatchProblem>(n);
-  const size_t at_items = c.take<int64_t>(size_t(bgl::N_LISTS) * (n + 1));
-  const size_t at_work = c.take<unsigned long long>(bgl::N_LISTS);
+  const size_t at_items = c.take<int64_t>(size_t(bgl::N_BATCH_LISTS) * (n + 1));
+  const size_t at_work = c.take<unsigned long long>(bgl::N_BATCH_LISTS);
   const size_t at_counts = c.take<int32_t>(size_t(64) * n);
   struct Off {
     size_t code, aux, cval, s_stack, s_start, s_need, owner, meta, class_list, len_list, Xt, yp, stats, part;
@@ -169,7 +169,7 @@ beagle_status beagle_eval_batched(beagle_ctx* ctx, const beagle_programs* progs,
   Batch b;
   std::memset(&b.args, 0, sizeof(b.args));
   b.n = n;
-  for (int v = 0; v < bgl::N_LISTS; ++v) b.max_d[v] = b.has[v] = 0;
+  for (int v = 0; v < bgl::N_BATCH_LISTS; ++v) b.max_d[v] = b.has[v] = 0;
   int32_t* counts = reinterpret_cast<int32_t*>(ws + at_counts);
   for (int i = 0; i < n; ++i) {
     const int q = active[i];
@@ -226,11 +226,13 @@ beagle_status beagle_eval_batched(beagle_ctx* ctx, const beagle_programs* progs,
     t.case_begin = b.n_cases;
     b.n_programs += P.n_programs;
     b.n_cases += o.Mp;
-    b.has[t.kv] = 1;
-    b.max_d[t.kv] = std::max(b.max_d[t.kv], int(d.D));
-    for (int v = 2; v < bgl::N_LISTS; ++v) {
-      b.has[v] = 1;
-      b.max_d[v] = std::max(b.max_d[v], int(d.D));
+    // the problem's lists: its class-0 tile variant and classes 1 and 2,
+    // in the bucket of its variable count
+    const int db = bgl::d_bucket(int(d.D));
+    for (int v : {int(t.kv), 2, 3}) {
+      const int vl = v * bgl::N_DBUCKETS + db;
+      b.has[vl] = 1;
+      b.max_d[vl] = std::max(b.max_d[vl], int(d.D));
     }
   }
   if (b.n_programs >= (int64_t(1) << 31)) return fail(BEAGLE_E_UNSUPPORTED, "more than 2^31 programs in a batch");

@@ -691,34 +691,48 @@ __global__ void __launch_bounds__(256) k_eval_resident(EvalArgs a) {
   }
 }
 
-// One work list of a batched evaluation: the same persistent scheme over the
-// (problem, chunk, program) items of every problem of the table, problem by
-// problem in table order and chunk-major within a problem.
+// One work list of a batched evaluation (list vl: a work list of the
+// class and tile variant, for one bucket of variable counts): the same
+// persistent scheme over the (problem, chunk, program) items of the table's
+// problems in that list, problem by problem in table order and chunk-major
+// within a problem.  Items are claimed in increasing order, so a
+// workgroup's next item lies in its previous item's problem or a later one:
+// the problem is found by stepping forward from there when it is near, by
+// bisection otherwise.
 template <int KIND, int CLS, int KV>
-__global__ void __launch_bounds__(256) k_eval_batch(BatchArgs b) {
+__global__ void __launch_bounds__(256) k_eval_batch(BatchArgs b, int vl) {
   constexpr int S = class_stack(CLS);
   constexpr int K = class_k(CLS, KV);
-  constexpr int V = CLS == 0 ? KV : CLS + 1;
   __shared__ double red[EVAL_WAVES * MAX_SUMS];
   __shared__ long long s_item;
   extern __shared__ float xtile[];
-  const int64_t* off = b.item_off + int64_t(V) * (b.n_problems + 1);
+  const int64_t* off = b.item_off + int64_t(vl) * (b.n_problems + 1);
   const int64_t items = off[b.n_problems];
+  int lo = 0;  // the problem of the previous item (a lower bound for the next)
   for (;;) {
-    if (threadIdx.x == 0) s_item = (long long)atomicAdd(b.work + V, 1ull);
+    if (threadIdx.x == 0) s_item = (long long)atomicAdd(b.work + vl, 1ull);
     __syncthreads();
     const uint64_t raw = uint64_t(s_item);
     __syncthreads();
     const int64_t it = int64_t((uint64_t(uint32_t(__builtin_amdgcn_readfirstlane(int(raw >> 32)))) << 32) |
                                uint32_t(__builtin_amdgcn_readfirstlane(int(raw))));
     if (it >= items) break;  // uniform across the workgroup
-    int lo = 0, hi = b.n_problems;
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (off[mid] <= it)
-        lo = mid;
-      else
-        hi = mid;
+    // the last problem q >= lo with off[q] <= it (problems without items in
+    // this list have empty ranges and are stepped over)
+    int steps = 0;
+    while (steps < 4 && lo + 1 < b.n_problems && off[lo + 1] <= it) {
+      ++lo;
+      ++steps;
+    }
+    if (steps == 4) {
+      int hi = b.n_problems;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= it)
+          lo = mid;
+        else
+          hi = mid;
+      }
     }
     const BatchProblem& P = b.table[lo];
     const int32_t count = P.prep.class_count[CLS];
@@ -922,15 +936,16 @@ __global__ void k_finalize_batch(BatchArgs b) {
 // First work item of every problem in each work list (exclusive prefix sums
 // in table order), from the class counts that k_prepare_batch produced.
 __global__ void k_batch_items(BatchArgs b) {
-  const int v = threadIdx.x;
-  if (v >= N_LISTS) return;
+  const int vl = threadIdx.x;  // list v, bucket db
+  if (vl >= N_BATCH_LISTS) return;
+  const int v = vl / N_DBUCKETS, db = vl % N_DBUCKETS;
   const int cls = v == 0 ? 0 : v - 1;
-  int64_t* off = b.item_off + int64_t(v) * (b.n_problems + 1);
+  int64_t* off = b.item_off + int64_t(vl) * (b.n_problems + 1);
   int64_t acc = 0;
   for (int q = 0; q < b.n_problems; ++q) {
     off[q] = acc;
     const BatchProblem& P = b.table[q];
-    if (v >= 2 || P.kv == v) acc += int64_t(P.prep.class_count[cls]) * P.n_chunks;
+    if ((v >= 2 || P.kv == v) && d_bucket(P.prep.D) == db) acc += int64_t(P.prep.class_count[cls]) * P.n_chunks;
   }
   off[b.n_problems] = acc;
 }
@@ -1044,36 +1059,54 @@ hipError_t launch_eval(int kind, int kv, const EvalArgs& a, hipStream_t s, hipEv
 }
 
 // Persistent grid of a work-list kernel: resident workgroups per CU at the
-// list's LDS tile size, times the CUs (cached per LDS size).
+// list's LDS tile size, times the CUs (cached per largest D, 1..MAX_D, so
+// that the occupancy queries all happen before a graph capture).
 template <int KIND, int CLS, int KV>
 static int list_grid(int max_d) {
-  const size_t lds = size_t(EVAL_WAVES) * max_d * ((class_k(CLS, KV) + 3) / 4) * 256 * sizeof(float);
-  static size_t cached_lds = size_t(-1);
-  static int cached = 0;
-  if (lds != cached_lds) {
+  static int cached[MAX_D + 1] = {0};
+  const int d = max_d < 1 ? 1 : (max_d > MAX_D ? MAX_D : max_d);
+  if (cached[d] == 0) {
+    const size_t lds = size_t(EVAL_WAVES) * d * ((class_k(CLS, KV) + 3) / 4) * 256 * sizeof(float);
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_batch<KIND, CLS, KV>, 256, lds) != hipSuccess ||
         nb < 1)
       nb = 1;
-    cached = nb * cu_count();
-    cached_lds = lds;
+    cached[d] = nb * cu_count();
   }
-  return cached;
+  return cached[d];
 }
 
 template <int KIND, int CLS, int KV>
-static hipError_t launch_list(const BatchArgs& b, int max_d, hipStream_t s) {
+static hipError_t launch_list(const BatchArgs& b, int vl, int max_d, hipStream_t s) {
   const size_t lds = size_t(EVAL_WAVES) * max_d * ((class_k(CLS, KV) + 3) / 4) * 256 * sizeof(float);
-  hipLaunchKernelGGL((k_eval_batch<KIND, CLS, KV>), dim3(list_grid<KIND, CLS, KV>(max_d)), dim3(256), lds, s, b);
+  hipLaunchKernelGGL((k_eval_batch<KIND, CLS, KV>), dim3(list_grid<KIND, CLS, KV>(max_d)), dim3(256), lds, s, b, vl);
   return hipGetLastError();
+}
+
+// every bucket of list v (its lists are v * N_DBUCKETS + bucket)
+template <int KIND, int CLS, int KV>
+static hipError_t launch_buckets(const BatchArgs& b, int v, const int* max_d, const int* has, hipStream_t s) {
+  for (int db = 0; db < N_DBUCKETS; ++db) {
+    const int vl = v * N_DBUCKETS + db;
+    if (!has[vl]) continue;
+    const hipError_t e = launch_list<KIND, CLS, KV>(b, vl, max_d[vl], s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <int KIND, int CLS, int KV>
+static void prime_buckets(int v, const int* max_d, const int* has) {
+  for (int db = 0; db < N_DBUCKETS; ++db)
+    if (has[v * N_DBUCKETS + db]) (void)list_grid<KIND, CLS, KV>(max_d[v * N_DBUCKETS + db]);
 }
 
 template <int KIND>
 static void prime_kind(const int* max_d, const int* has) {
-  if (has[0]) (void)list_grid<KIND, 0, 0>(max_d[0]);
-  if (has[1]) (void)list_grid<KIND, 0, 1>(max_d[1]);
-  if (has[2]) (void)list_grid<KIND, 1, 0>(max_d[2]);
-  if (has[3]) (void)list_grid<KIND, 2, 0>(max_d[3]);
+  prime_buckets<KIND, 0, 0>(0, max_d, has);
+  prime_buckets<KIND, 0, 1>(1, max_d, has);
+  prime_buckets<KIND, 1, 0>(2, max_d, has);
+  prime_buckets<KIND, 2, 0>(3, max_d, has);
 }
 
 void prime_eval_batch(int kind, const int* max_d, const int* has_items) {
@@ -1086,15 +1119,15 @@ void prime_eval_batch(int kind, const int* max_d, const int* has_items) {
 template <int KIND>
 static hipError_t launch_batch_kind(const BatchArgs& b, const int* max_d, const int* has, hipStream_t s,
                                     hipEvent_t ev0, hipEvent_t ev1) {
-  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, b.work, N_LISTS);
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, b.work, N_BATCH_LISTS);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (ev0) (void)hipEventRecord(ev0, s);
-  if (has[0] && (e = launch_list<KIND, 0, 0>(b, max_d[0], s)) != hipSuccess) return e;
-  if (has[1] && (e = launch_list<KIND, 0, 1>(b, max_d[1], s)) != hipSuccess) return e;
+  if ((e = launch_buckets<KIND, 0, 0>(b, 0, max_d, has, s)) != hipSuccess) return e;
+  if ((e = launch_buckets<KIND, 0, 1>(b, 1, max_d, has, s)) != hipSuccess) return e;
   if (ev1) (void)hipEventRecord(ev1, s);
-  if (has[2] && (e = launch_list<KIND, 1, 0>(b, max_d[2], s)) != hipSuccess) return e;
-  if (has[3] && (e = launch_list<KIND, 2, 0>(b, max_d[3], s)) != hipSuccess) return e;
+  if ((e = launch_buckets<KIND, 1, 0>(b, 2, max_d, has, s)) != hipSuccess) return e;
+  if ((e = launch_buckets<KIND, 2, 0>(b, 3, max_d, has, s)) != hipSuccess) return e;
   return hipSuccess;
 }
 

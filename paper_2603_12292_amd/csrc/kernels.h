@@ -150,8 +150,14 @@ struct BatchProblem {
 };
 
 // Work lists of a batched evaluation: class 0 wide tile, class 0 narrow
-// tile, class 1, class 2.
+// tile, class 1, class 2; each split by the problems' variable count into
+// N_DBUCKETS lists (D <= 3, 4..6, more), launched separately so that each
+// launch sizes its input tiles in LDS, and hence its occupancy, for its own
+// largest D instead of the batch's.
 constexpr int N_LISTS = 4;
+constexpr int N_DBUCKETS = 3;
+constexpr int N_BATCH_LISTS = N_LISTS * N_DBUCKETS;
+__host__ __device__ constexpr int d_bucket(int D) { return D <= 3 ? 0 : (D <= 6 ? 1 : 2); }
 
 struct BatchArgs {
   const BatchProblem* table;
@@ -159,8 +165,8 @@ struct BatchArgs {
   int32_t kind;
   int64_t n_programs;          // over the whole table
   int64_t n_cases;             // padded cases over the whole table
-  int64_t* item_off;           // [N_LISTS][n_problems + 1] first work item of each problem per list
-  unsigned long long* work;    // [N_LISTS] work-item counters, zero at launch
+  int64_t* item_off;           // [N_BATCH_LISTS][n_problems + 1] first work item of each problem per list
+  unsigned long long* work;    // [N_BATCH_LISTS] work-item counters, zero at launch
 };
 
 // The problem holding batch-wide index x of a prefix field (prog_begin or

@@ -6,10 +6,11 @@
 #       for FETCH_SIZE, WRITE_SIZE and SQ_INSTS_VALU + SQ_INSTS_SALU over
 #       `profiling run` (benchmark workload + calibration copy); writes
 #       PREFIX.txt and PREFIX_traffic.json
-#   paper_2603_12292_amd/profile.sh paper|adjoint OUTDIR PREFIX
+#   paper_2603_12292_amd/profile.sh paper|adjoint|ragged OUTDIR PREFIX
 #       kernel trace and counter passes (instruction mix, cycles and waits,
-#       FETCH_SIZE, WRITE_SIZE) over the paper-regime evaluation or the
-#       adjoint; writes PREFIX.txt and PREFIX.json (per-kernel means)
+#       FETCH_SIZE, WRITE_SIZE) over the paper-regime evaluation, the
+#       adjoint or the ragged batch; writes PREFIX.txt and PREFIX.json
+#       (per-kernel means)
 #   paper_2603_12292_amd/profile.sh ops OUTDIR PREFIX
 #       SQ_INSTS_VALU + SQ_INSTS_SALU over `profiling ops` (single-operator
 #       program shapes); writes PREFIX.txt
@@ -45,7 +46,7 @@ ops)
   python3 -m paper_2603_12292_amd.profiling summarize-ops --pmc "$out/pmc_ops" --out "$prefix" \
     --command "paper_2603_12292_amd/profile.sh ops OUTDIR PREFIX (rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_SALU -- python3 -m paper_2603_12292_amd.profiling ops)"
   ;;
-paper|adjoint)
+paper|adjoint|ragged)
   # kernel trace plus two counter passes (instruction mix, then cycles and
   # waits) over the paper-regime evaluation (decode + resident interpreter)
   # or the adjoint of the differentiation workload
@@ -53,6 +54,10 @@ paper|adjoint)
     run_cmd="python3 -m paper_2603_12292_amd.profiling paper --steps 2"
     kernels="k_prepare,k_eval_resident,k_eval_class,k_finalize,k_stage"
     title="paper regime: 2^20 programs (plain-mid x256, L~U{5..64}, D=5) on 512 cases, MSE"
+  elif [ "$what" = ragged ]; then
+    run_cmd="python3 -m paper_2603_12292_amd.profiling ragged --steps 2"
+    kernels="k_eval_batch,k_prepare,k_stage,k_finalize,k_eval_class,k_eval_resident,k_target"
+    title="ragged: 64 problems x 1024 programs, L~U{5..96}, D~U{1..9}, M=round(10^U(3,6)), MSE; batched (replayed graph), then one call per problem"
   else
     run_cmd="python3 -m paper_2603_12292_amd.profiling run --steps 2 --adjoint"
     kernels="k_grad,k_prepare,k_finalize"

@@ -277,6 +277,28 @@ def run_paper(steps: int, kind: str = "mse"):
     print(f"profiled {steps} evaluation(s) of {w.name}, {kind}", flush=True)
 
 
+def run_ragged(steps: int):
+    """The 64-problem ragged workload: one warm-up and `steps` batched
+    evaluations (MSE, one replayed graph), then the same problems one call
+    each."""
+    import torch
+    sys.path.insert(0, ROOT)
+    from paper_2603_12292_amd import api
+    from paper_2603_12292_amd import workloads as wl
+    ws = wl.ragged_problems()
+    dev = [(api.DevicePrograms.from_programset(w.programs, "cuda:0"), torch.from_numpy(w.data.X).cuda(),
+            torch.from_numpy(w.data.y).cuda()) for w in ws]
+    out = [torch.empty(p.n, dtype=torch.float64, device="cuda") for p, _, _ in dev]
+    ctx = api.context(0)
+    for _ in range(steps + 1):
+        api.evaluate_batched(dev, "mse", out=out, ctx=ctx)
+    torch.cuda.synchronize()
+    for p, X, y in dev:
+        api.evaluate(p, X, y, "mse", ctx=ctx)
+    torch.cuda.synchronize()
+    print(f"profiled {steps} batched evaluation(s) of the ragged workload and one sequential pass", flush=True)
+
+
 def summarize_kernels(trace_dir, pmc_dirs, kernels, out_prefix, command, title):
     """Per kernel whose name contains one of `kernels`: calls and average
     duration from the kernel trace, and the mean per dispatch of every
@@ -337,6 +359,8 @@ def main():
     s.add_argument("--out", required=True)
     s.add_argument("--command", default="")
     sub.add_parser("ops")
+    rg = sub.add_parser("ragged")
+    rg.add_argument("--steps", type=int, default=2)
     pp = sub.add_parser("paper")
     pp.add_argument("--steps", type=int, default=2)
     pp.add_argument("--kind", default="mse")
@@ -358,6 +382,8 @@ def main():
         run_ops()
     elif a.cmd == "paper":
         run_paper(a.steps, a.kind)
+    elif a.cmd == "ragged":
+        run_ragged(a.steps)
     elif a.cmd == "summarize-kernels":
         summarize_kernels(a.trace, a.pmc, a.kernels.split(","), a.out, a.command, a.title)
     elif a.cmd == "summarize-ops":
