@@ -138,14 +138,17 @@ constexpr int CLASS_ZERO_SUB = (1 << 4) | (1 << 5) | (1 << 6) | (1 << 7);
 // rounded protected quotient instead.  The choice depends on the case
 // alone, so every grouping of cases into waves gives the same values; the
 // correctly rounded path runs only when some lane of the wave needs it.
+// div_tile_r also returns the hardware reciprocals r[k] of b[k] it used
+// (the adjoint's derivatives 1/b and -a/b^2 take the same ones).
 template <int K>
-__device__ __forceinline__ void div_tile(const float (&a)[K], const float (&b)[K], float (&q)[K]) {
+__device__ __forceinline__ void div_tile_r(const float (&a)[K], const float (&b)[K], float (&q)[K], float (&rr)[K]) {
   uint64_t any = 0;
   bool odd_any = false;
   bool bad[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const float r = __builtin_amdgcn_rcpf(b[k]);
+    rr[k] = r;
     const float q0 = a[k] * r;
     q[k] = __builtin_fmaf(__builtin_fmaf(-b[k], q0, a[k]), r, q0);
     // q not a normal number (one class test), or a tiny dividend
@@ -162,6 +165,12 @@ __device__ __forceinline__ void div_tile(const float (&a)[K], const float (&b)[K
 #pragma unroll
     for (int k = 0; k < K; ++k) q[k] = bad[k] ? op_div_cr(a[k], b[k]) : q[k];
   }
+}
+
+template <int K>
+__device__ __forceinline__ void div_tile(const float (&a)[K], const float (&b)[K], float (&q)[K]) {
+  float r[K];
+  div_tile_r<K>(a, b, q, r);
 }
 
 __device__ __forceinline__ float op_div(float a, float b) {

@@ -65,6 +65,52 @@ __device__ __forceinline__ void dbinop(float A, float B, float& dA, float& dB) {
   }
 }
 
+// binop<O> and its partial derivatives on G cases per lane: the protected
+// quotients through div_tile_r, whose reciprocal the derivatives reuse
+// (the same values dbinop gives)
+template <uint32_t O, int G>
+__device__ __forceinline__ void dbinop_tile(const float (&A)[G], const float (&B)[G], float (&q)[G], float (&dA)[G],
+                                            float (&dB)[G]) {
+  if constexpr (O == B_DIV || O == B_RDIV) {
+    float r[G];
+    if constexpr (O == B_DIV)
+      div_tile_r<G>(A, B, q, r);
+    else
+      div_tile_r<G>(B, A, q, r);
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      if constexpr (O == B_DIV) {
+        const bool nz = B[k] != 0.0f;
+        dA[k] = nz ? r[k] : 0.0f;
+        dB[k] = nz ? -A[k] * r[k] * r[k] : 0.0f;
+      } else {
+        const bool nz = A[k] != 0.0f;
+        dA[k] = nz ? -B[k] * r[k] * r[k] : 0.0f;
+        dB[k] = nz ? r[k] : 0.0f;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      q[k] = gbinop<O>(A[k], B[k]);
+      dbinop<O>(A[k], B[k], dA[k], dB[k]);
+    }
+  }
+}
+
+// binop<O> on G cases per lane (values only)
+template <uint32_t O, int G>
+__device__ __forceinline__ void binop_tile_g(const float (&A)[G], const float (&B)[G], float (&q)[G]) {
+  if constexpr (O == B_DIV) {
+    div_tile<G>(A, B, q);
+  } else if constexpr (O == B_RDIV) {
+    div_tile<G>(B, A, q);
+  } else {
+#pragma unroll
+    for (int k = 0; k < G; ++k) q[k] = gbinop<O>(A[k], B[k]);
+  }
+}
+
 // sin (COS = false) or cos of one value per lane, the interpreter's functions
 template <bool COS>
 __device__ __forceinline__ float trig1(float x) {
@@ -519,12 +565,13 @@ __device__ __forceinline__ void dt_fwd(uint32_t fid, float cv, const float (&x)[
 #undef BGL_F_PUSH
 #define BGL_F_BIN(O, N)                                       \
   case I0_BIN + 3 * O + (N - 2): {                            \
-    float dA[G], dB[G];                                       \
+    float a_[G], b_[G], q_[G], dA[G], dB[G];                  \
     BGL_K(G) {                                                \
-      const float a = st[k][N - 2], b = st[k][N - 1];         \
-      st[k][N - 2] = gbinop<O>(a, b);                         \
-      dbinop<O>(a, b, dA[k], dB[k]);                          \
+      a_[k] = st[k][N - 2];                                   \
+      b_[k] = st[k][N - 1];                                   \
     }                                                         \
+    dbinop_tile<O, G>(a_, b_, q_, dA, dB);                    \
+    BGL_K(G) st[k][N - 2] = q_[k];                            \
     if constexpr (O == B_MUL || O == B_DIV || O == B_RDIV) {  \
       BGL_PUT(dA)                                             \
       BGL_PUT(dB)                                             \
@@ -546,42 +593,41 @@ __device__ __forceinline__ void dt_fwd(uint32_t fid, float cv, const float (&x)[
   }                                                            \
   case I0_UN + 1 * 4 + (N - 1): {                              \
     float v[G], d[G];                                          \
-    BGL_K(G) v[k] = d[k] = st[k][N - 1];                       \
-    trig_tile<true, G>(v);                                     \
-    trig_tile<false, G>(d);                                    \
-    BGL_K(G) {                                                 \
-      st[k][N - 1] = v[k];                                     \
-      d[k] = -d[k];                                            \
-    }                                                          \
+    BGL_K(G) v[k] = st[k][N - 1];                              \
+    cos_nsin_tile<G>(v, d);                                    \
+    BGL_K(G) st[k][N - 1] = v[k];                              \
     BGL_PUT(d)                                                 \
     break;                                                     \
   }                                                            \
   case I0_UN + 2 * 4 + (N - 1): {                              \
-    float d[G];                                                \
+    float u[G], v[G], d[G];                                    \
+    BGL_K(G) u[k] = v[k] = st[k][N - 1];                       \
+    exp_tile<G>(v);                                            \
     BGL_K(G) {                                                 \
-      const float u = st[k][N - 1];                            \
-      st[k][N - 1] = op_exp(u);                                \
-      d[k] = dunary(2u, u, st[k][N - 1]);                      \
+      st[k][N - 1] = v[k];                                     \
+      d[k] = dunary(2u, u[k], v[k]);                           \
     }                                                          \
     BGL_PUT(d)                                                 \
     break;                                                     \
   }                                                            \
   case I0_UN + 3 * 4 + (N - 1): {                              \
-    float d[G];                                                \
+    float u[G], v[G], d[G];                                    \
+    BGL_K(G) u[k] = v[k] = st[k][N - 1];                       \
+    log_tile<G>(v);                                            \
     BGL_K(G) {                                                 \
-      const float u = st[k][N - 1];                            \
-      st[k][N - 1] = op_log(u);                                \
-      d[k] = dunary(3u, u, 0.0f);                              \
+      st[k][N - 1] = v[k];                                     \
+      d[k] = dunary(3u, u[k], 0.0f);                           \
     }                                                          \
     BGL_PUT(d)                                                 \
     break;                                                     \
   }                                                            \
   case I0_UN + 4 * 4 + (N - 1): {                              \
-    float d[G];                                                \
+    float u[G], v[G], d[G];                                    \
+    BGL_K(G) u[k] = v[k] = st[k][N - 1];                       \
+    sqrt_tile<G>(v);                                           \
     BGL_K(G) {                                                 \
-      const float u = st[k][N - 1];                            \
-      st[k][N - 1] = op_sqrt(u);                               \
-      d[k] = dunary(4u, u, st[k][N - 1]);                      \
+      st[k][N - 1] = v[k];                                     \
+      d[k] = dunary(4u, u[k], v[k]);                           \
     }                                                          \
     BGL_PUT(d)                                                 \
     break;                                                     \
@@ -590,24 +636,23 @@ __device__ __forceinline__ void dt_fwd(uint32_t fid, float cv, const float (&x)[
 #undef BGL_F_UN
 #define BGL_F_FUSED(O, N)                                     \
   case I0_FUSED + 3 * O + (N - 1): {                          \
-    float dA[G], dB[G];                                       \
-    BGL_K(G) {                                                \
-      const float a = st[k][N - 1];                           \
-      st[k][N - 1] = gbinop<O>(a, x[k]);                      \
-      dbinop<O>(a, x[k], dA[k], dB[k]);                       \
-    }                                                         \
+    float a_[G], q_[G], dA[G], dB[G];                         \
+    BGL_K(G) a_[k] = st[k][N - 1];                            \
+    dbinop_tile<O, G>(a_, x, q_, dA, dB);                     \
+    BGL_K(G) st[k][N - 1] = q_[k];                            \
     if constexpr (O == B_MUL || O == B_DIV || O == B_RDIV) {  \
       BGL_PUT(dA)                                             \
     }                                                         \
     break;                                                    \
   }                                                           \
   case I0_FUSED + 3 * (6 + O) + (N - 1): {                    \
-    float dA[G], dB[G];                                       \
+    float a_[G], c_[G], q_[G], dA[G], dB[G];                  \
     BGL_K(G) {                                                \
-      const float a = st[k][N - 1];                           \
-      st[k][N - 1] = gbinop<O>(a, cv);                        \
-      dbinop<O>(a, cv, dA[k], dB[k]);                         \
+      a_[k] = st[k][N - 1];                                   \
+      c_[k] = cv;                                             \
     }                                                         \
+    dbinop_tile<O, G>(a_, c_, q_, dA, dB);                    \
+    BGL_K(G) st[k][N - 1] = q_[k];                            \
     if constexpr (O == B_RDIV) {                              \
       BGL_PUT(dA)                                             \
     }                                                         \
@@ -623,9 +668,16 @@ __device__ __forceinline__ void dt_fwd(uint32_t fid, float cv, const float (&x)[
 #undef BGL_F_FUSED
     // constant-free words: values only
 #define BGL_N_BIN(J, O, N)                                         \
-  case F_BIN_NT + 3 * J + (N - 2):                                 \
-    BGL_K(G) st[k][N - 2] = gbinop<O>(st[k][N - 2], st[k][N - 1]); \
-    break;
+  case F_BIN_NT + 3 * J + (N - 2): {                               \
+    float a_[G], b_[G], q_[G];                                     \
+    BGL_K(G) {                                                     \
+      a_[k] = st[k][N - 2];                                        \
+      b_[k] = st[k][N - 1];                                        \
+    }                                                              \
+    binop_tile_g<O, G>(a_, b_, q_);                                \
+    BGL_K(G) st[k][N - 2] = q_[k];                                 \
+    break;                                                         \
+  }
 #define BGL_N_BIN3(J, O) BGL_N_BIN(J, O, 2) BGL_N_BIN(J, O, 3) BGL_N_BIN(J, O, 4)
     BGL_N_BIN3(0, B_MUL) BGL_N_BIN3(1, B_DIV) BGL_N_BIN3(2, B_RDIV)
 #undef BGL_N_BIN3
@@ -645,21 +697,37 @@ __device__ __forceinline__ void dt_fwd(uint32_t fid, float cv, const float (&x)[
     BGL_K(G) st[k][N - 1] = v[k];                    \
     break;                                           \
   }                                                  \
-  case F_UN_NT + 2 * 4 + (N - 1):                    \
-    BGL_K(G) st[k][N - 1] = op_exp(st[k][N - 1]);    \
+  case F_UN_NT + 2 * 4 + (N - 1): {                  \
+    float v[G];                                      \
+    BGL_K(G) v[k] = st[k][N - 1];                    \
+    exp_tile<G>(v);                                  \
+    BGL_K(G) st[k][N - 1] = v[k];                    \
     break;                                           \
-  case F_UN_NT + 3 * 4 + (N - 1):                    \
-    BGL_K(G) st[k][N - 1] = op_log(st[k][N - 1]);    \
+  }                                                  \
+  case F_UN_NT + 3 * 4 + (N - 1): {                  \
+    float v[G];                                      \
+    BGL_K(G) v[k] = st[k][N - 1];                    \
+    log_tile<G>(v);                                  \
+    BGL_K(G) st[k][N - 1] = v[k];                    \
     break;                                           \
-  case F_UN_NT + 4 * 4 + (N - 1):                    \
-    BGL_K(G) st[k][N - 1] = op_sqrt(st[k][N - 1]);   \
-    break;
+  }                                                  \
+  case F_UN_NT + 4 * 4 + (N - 1): {                  \
+    float v[G];                                      \
+    BGL_K(G) v[k] = st[k][N - 1];                    \
+    sqrt_tile<G>(v);                                 \
+    BGL_K(G) st[k][N - 1] = v[k];                    \
+    break;                                           \
+  }
     BGL_N_UN(1) BGL_N_UN(2) BGL_N_UN(3) BGL_N_UN(4)
 #undef BGL_N_UN
 #define BGL_N_FV(J, O, N)                                 \
-  case F_FV_NT + 3 * J + (N - 1):                         \
-    BGL_K(G) st[k][N - 1] = gbinop<O>(st[k][N - 1], x[k]); \
-    break;
+  case F_FV_NT + 3 * J + (N - 1): {                       \
+    float a_[G], q_[G];                                   \
+    BGL_K(G) a_[k] = st[k][N - 1];                        \
+    binop_tile_g<O, G>(a_, x, q_);                        \
+    BGL_K(G) st[k][N - 1] = q_[k];                        \
+    break;                                                \
+  }
 #define BGL_N_FV3(J, O) BGL_N_FV(J, O, 1) BGL_N_FV(J, O, 2) BGL_N_FV(J, O, 3)
     BGL_N_FV3(0, B_MUL) BGL_N_FV3(1, B_DIV) BGL_N_FV3(2, B_RDIV)
 #undef BGL_N_FV3

@@ -173,4 +173,36 @@ __device__ __forceinline__ void sincos_tile(float (&s)[K], float (&c)[K]) {
   }
 }
 
+// cos x (the interpreter's value, bit for bit) and -sin x of K values per
+// lane from the cosine's reduction: with |x| = (j + 1/2) pi + r,
+// sin x = sign(x) (-1)^j cos r and cos r = sin(pi/2 - |r|), the argument
+// formed in binary64 -- as accurate as sincos_tile's cosine.  c holds x on
+// entry.  Large or non-finite arguments of any lane: the general path per
+// case.
+template <int K>
+__device__ __forceinline__ void cos_nsin_tile(float (&c)[K], float (&ns)[K]) {
+  uint64_t big = 0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) big |= __builtin_amdgcn_ballot_w64(!(__builtin_fabsf(c[k]) < TRIG_SMALL));
+  if (big == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const float x = c[k];
+      int p;
+      const double r = trig_reduce_small_d<true>(__builtin_fabsf(x), p);
+      c[k] = trig_finish(float(r), p, 0u);
+      const double u = (0x1.921fb54442d18p+0 - __builtin_fabs(r)) + 0x1.1a62633145c07p-54;
+      ns[k] = trig_finish(float(u), p, __float_as_uint(x) & 0x80000000u);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const float x = c[k];
+      c[k] = trig_any<true>(x);
+      ns[k] = -trig_any<false>(x);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
 }  // namespace bgl
