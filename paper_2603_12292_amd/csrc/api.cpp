@@ -233,6 +233,9 @@ beagle_status prepare(char* ws, const beagle_programs* P, const beagle_dataset* 
   return BEAGLE_OK;
 }
 
+// LDS of a values kernel: the case tile of D variables (256 floats each).
+size_t values_lds(int32_t D) { return size_t(D < 1 ? 1 : D) * 256 * sizeof(float); }
+
 beagle_status launch_values(char* ws, const beagle_programs* P, const beagle_dataset* d,
                             const EvalLayout& L, int64_t m, float* out, int shift_mode, hipStream_t s) {
   bgl::ValuesArgs va;
@@ -249,7 +252,7 @@ beagle_status launch_values(char* ws, const beagle_programs* P, const beagle_dat
   va.shift_mode = shift_mode;
   const int64_t tiles = (m + 63) / 64;
   if (tiles > 65535) return fail(BEAGLE_E_UNSUPPORTED, "predict: M > 4194240");
-  hipLaunchKernelGGL(bgl::k_values, dim3(P->n_programs, uint32_t(tiles)), dim3(64), 0, s, va);
+  hipLaunchKernelGGL(bgl::k_values, dim3(P->n_programs, uint32_t(tiles)), dim3(64), values_lds(d->D), s, va);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "values launch");
   return BEAGLE_OK;
@@ -275,12 +278,59 @@ beagle_status launch_shifts(char* ws, const beagle_programs* P, const beagle_dat
   va.n_programs = P->n_programs;
   va.out = nullptr;
   va.shift_mode = 1;
-  hipLaunchKernelGGL(bgl::k_values_deep, dim3(2048), dim3(64), 0, s, va,
+  hipLaunchKernelGGL(bgl::k_values_deep, dim3(2048), dim3(64), values_lds(d->D), s, va,
                      reinterpret_cast<const int32_t*>(ws + L.class_count),
                      reinterpret_cast<const int32_t*>(ws + L.class_list), P->n_programs);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "values launch");
   return BEAGLE_OK;
+}
+
+// Target statistics of data->y (correlation fitness, Eq. 2 score) into
+// `stats`.  They read nothing else, so with a context they run on its side
+// stream (default priority), forked from s here and beside the decoding and
+// staging that follow on s; *join is then the event s waits for before the
+// statistics are read.  Without a context they run on s (*join = null).
+beagle_status launch_target_stats(beagle_ctx* ctx, const beagle_dataset* data, double* stats, hipStream_t s,
+                                  hipEvent_t* join) {
+  *join = nullptr;
+  hipStream_t t = s;
+  if (ctx) {
+    if (!ctx->side) {
+      hipStream_t ns = nullptr;
+      hipEvent_t f = nullptr, j = nullptr;
+      hipError_t e = hipStreamCreateWithFlags(&ns, hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&f, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&j, hipEventDisableTiming);
+      if (e != hipSuccess) {
+        if (ns) (void)hipStreamDestroy(ns);
+        if (f) (void)hipEventDestroy(f);
+        return hip_fail(e, "side stream");
+      }
+      ctx->side = ns;
+      ctx->side_fork = f;
+      ctx->side_join = j;
+    }
+    hipError_t e = hipEventRecord(ctx->side_fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(ctx->side, ctx->side_fork, 0);
+    if (e != hipSuccess) return hip_fail(e, "side stream fork");
+    t = ctx->side;
+  }
+  hipLaunchKernelGGL(bgl::k_target_stats, dim3(1), dim3(1024), 0, t, data->y, data->M, stats);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "target statistics launch");
+  if (ctx) {
+    if ((e = hipEventRecord(ctx->side_join, t)) != hipSuccess) return hip_fail(e, "side stream join");
+    *join = ctx->side_join;
+  }
+  return BEAGLE_OK;
+}
+
+// s waits for the target statistics (when they ran on a side stream).
+beagle_status join_target_stats(hipEvent_t join, hipStream_t s) {
+  if (!join) return BEAGLE_OK;
+  const hipError_t e = hipStreamWaitEvent(s, join, 0);
+  return e == hipSuccess ? BEAGLE_OK : hip_fail(e, "side stream join");
 }
 
 // One evaluation slice for the tile-width tuner.
@@ -360,6 +410,9 @@ void beagle_ctx_destroy(beagle_ctx* ctx) {
     release_events(ctx);
     release_graphs(ctx);
     if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
+    if (ctx->side_fork) (void)hipEventDestroy(ctx->side_fork);
+    if (ctx->side_join) (void)hipEventDestroy(ctx->side_join);
     if (ctx->table_copied) (void)hipEventDestroy(ctx->table_copied);
     if (ctx->ws) (void)hipFree(ctx->ws);
   }
@@ -422,12 +475,17 @@ EvalLayout capped_layout(const beagle_programs* progs, const beagle_dataset* dat
 beagle_status evaluate_in(char* ws, const EvalLayout& L, int32_t slice, beagle_ctx* ctx,
                           const beagle_programs* progs, const beagle_dataset* data, int kind, double smax,
                           double* fitness, int8_t* status, hipStream_t s) {
-  beagle_status st = prepare(ws, progs, data, L, status, s, ctx ? ctx->decoder : BEAGLE_DECODE_WAVE);
+  const bool with_stats = kind == BEAGLE_FIT_CORR || kind == BEAGLE_FIT_R4;
+  hipEvent_t join = nullptr;
+  beagle_status st = BEAGLE_OK;
+  if (with_stats && (st = launch_target_stats(ctx, data, reinterpret_cast<double*>(ws + L.stats), s, &join)) !=
+                        BEAGLE_OK)
+    return st;
+  st = prepare(ws, progs, data, L, status, s, ctx ? ctx->decoder : BEAGLE_DECODE_WAVE);
   if (st != BEAGLE_OK) return st;
   bool shift_in_kernel = false;
-  if (kind == BEAGLE_FIT_CORR || kind == BEAGLE_FIT_R4) {
-    hipLaunchKernelGGL(bgl::k_target_stats, dim3(1), dim3(1024), 0, s, data->y, data->M,
-                       reinterpret_cast<double*>(ws + L.stats));
+  if (with_stats) {
+    if ((st = join_target_stats(join, s)) != BEAGLE_OK) return st;
     st = launch_shifts(ws, progs, data, L, s, &shift_in_kernel);
     if (st != BEAGLE_OK) return st;
   }
@@ -847,13 +905,15 @@ namespace {
 // The correlation evaluation of the whole population (target statistics,
 // shifts, interpreter, finalize) writing the fitness and the seed
 // coefficients of the correlation adjoint.
+// The target statistics were launched before the decoding; s waits for
+// them through `join`.
 beagle_status corr_pass(beagle_ctx* ctx, const beagle_programs* progs, const beagle_dataset* data,
-                        const EvalLayout& L, double* fitness, hipStream_t s) {
+                        const EvalLayout& L, double* fitness, hipEvent_t join, hipStream_t s) {
   char* ws = ctx->ws;
-  hipLaunchKernelGGL(bgl::k_target_stats, dim3(1), dim3(1024), 0, s, data->y, data->M,
-                     reinterpret_cast<double*>(ws + L.stats));
+  beagle_status st = join_target_stats(join, s);
+  if (st != BEAGLE_OK) return st;
   bool shift_in_kernel = false;
-  beagle_status st = launch_shifts(ws, progs, data, L, s, &shift_in_kernel);
+  st = launch_shifts(ws, progs, data, L, s, &shift_in_kernel);
   if (st != BEAGLE_OK) return st;
   bgl::EvalArgs ea;
   ea.code = reinterpret_cast<const uint32_t*>(ws + L.code);
@@ -922,13 +982,17 @@ beagle_status beagle_eval_grad(beagle_ctx* ctx, const beagle_programs* progs, co
   EvalLayout L = eval_layout(progs, data, corr ? 3 : 1, progs->n_programs, true);
   st = reserve(ctx, L.total);
   if (st != BEAGLE_OK) return st;
+  hipEvent_t join = nullptr;
+  if (corr && (st = launch_target_stats(ctx, data, reinterpret_cast<double*>(ctx->ws + L.stats), s, &join)) !=
+                  BEAGLE_OK)
+    return st;
   st = prepare(ctx->ws, progs, data, L, status, s, ctx->decoder, bgl::GRAD_LONG_WORDS, true);
   if (st != BEAGLE_OK) return st;
   char* ws = ctx->ws;
   if (corr) {
     // first pass: the correlation fitness and every program's seed
     // coefficients, by the evaluator (its own chunking)
-    st = corr_pass(ctx, progs, data, L, fitness, s);
+    st = corr_pass(ctx, progs, data, L, fitness, join, s);
     if (st != BEAGLE_OK) return st;
   }
   unsigned long long* work = reinterpret_cast<unsigned long long*>(ws + L.work);

@@ -13,6 +13,8 @@
 // fetched with v_readlane); constants come from a side table read the same
 // way.  The operand stack lives in registers with compile-time names: the
 // handler byte fixes the stack size at which a token runs.
+#include <hip/hip_ext.h>
+
 #include <cmath>
 
 #include "beagle_device.h"
@@ -798,8 +800,9 @@ __device__ static void values_program(const ValuesArgs& a, int p, int64_t tile, 
   }
 }
 
+// (dynamic LDS: D * 256 floats, so that more waves fit per CU for small D)
 __global__ void __launch_bounds__(64) k_values(ValuesArgs a) {
-  __shared__ float xl_all[MAX_D * 256];
+  extern __shared__ float xl_all[];
   values_program(a, blockIdx.x, blockIdx.y, xl_all);
 }
 
@@ -808,7 +811,7 @@ __global__ void __launch_bounds__(64) k_values(ValuesArgs a) {
 // list, no counters.
 __global__ void __launch_bounds__(64) k_values_deep(ValuesArgs a, const int32_t* class_count,
                                                     const int32_t* class_list, int32_t stride) {
-  __shared__ float xl_all[MAX_D * 256];
+  extern __shared__ float xl_all[];  // D * 256 floats
   const int32_t c2 = class_count[2];
   for (int32_t item = blockIdx.x; item < c2; item += gridDim.x) {
     values_program(a, class_list[2 * int64_t(stride) + item], 0, xl_all);
@@ -982,10 +985,14 @@ static int cu_count() {
 }
 
 template <int KIND, int CLS, int KV>
-static hipError_t launch_class(const EvalArgs& a, hipStream_t s) {
+static hipError_t launch_class(const EvalArgs& a, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
   const size_t lds = size_t(EVAL_WAVES) * a.D * ((class_k(CLS, KV) + 3) / 4) * 256 * sizeof(float);
   const int grid = resident_blocks<KIND, CLS, KV>(lds) * cu_count();
-  hipLaunchKernelGGL((k_eval_class<KIND, CLS, KV>), dim3(grid), dim3(256), lds, s, a);
+  // timing events, when asked for, are taken by the dispatch itself
+  if (ev0 || ev1)
+    hipExtLaunchKernelGGL((k_eval_class<KIND, CLS, KV>), dim3(grid), dim3(256), uint32_t(lds), s, ev0, ev1, 0u, a);
+  else
+    hipLaunchKernelGGL((k_eval_class<KIND, CLS, KV>), dim3(grid), dim3(256), lds, s, a);
   return hipGetLastError();
 }
 
@@ -1008,7 +1015,8 @@ bool resident_eligible(int64_t M, int32_t D, int32_t n_chunks, int32_t n_total) 
 static bool resident_eligible(const EvalArgs& a) { return resident_eligible(a.M, a.D, a.n_chunks, a.n_total); }
 
 template <int KIND, int K, int CLS>
-static hipError_t launch_resident(const EvalArgs& a, size_t lds, hipStream_t s) {
+static hipError_t launch_resident(const EvalArgs& a, size_t lds, hipStream_t s, hipEvent_t ev0 = nullptr,
+                                  hipEvent_t ev1 = nullptr) {
   static size_t cached_lds = size_t(-1);
   static int cached = 0;
   if (lds != cached_lds) {
@@ -1019,7 +1027,11 @@ static hipError_t launch_resident(const EvalArgs& a, size_t lds, hipStream_t s) 
     cached = nb;
     cached_lds = lds;
   }
-  hipLaunchKernelGGL((k_eval_resident<KIND, K, CLS>), dim3(cached * cu_count()), dim3(256), lds, s, a);
+  if (ev0 || ev1)
+    hipExtLaunchKernelGGL((k_eval_resident<KIND, K, CLS>), dim3(cached * cu_count()), dim3(256), uint32_t(lds), s,
+                          ev0, ev1, 0u, a);
+  else
+    hipLaunchKernelGGL((k_eval_resident<KIND, K, CLS>), dim3(cached * cu_count()), dim3(256), lds, s, a);
   return hipGetLastError();
 }
 
@@ -1028,15 +1040,13 @@ static hipError_t launch_kind(int kv, const EvalArgs& a, hipStream_t s, hipEvent
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, a.work, N_CLASSES);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (ev0) (void)hipEventRecord(ev0, s);
   const bool wide = kv == 0 && a.D <= WIDE_TILE_MAX_D;
   const bool resident = resident_eligible(a);
   if (resident)
-    e = wide ? launch_resident<KIND, 8, 0>(a, resident_bytes(a, 8), s)
-             : launch_resident<KIND, 4, 0>(a, resident_bytes(a, 4), s);
+    e = wide ? launch_resident<KIND, 8, 0>(a, resident_bytes(a, 8), s, ev0, ev1)
+             : launch_resident<KIND, 4, 0>(a, resident_bytes(a, 4), s, ev0, ev1);
   else
-    e = wide ? launch_class<KIND, 0, 0>(a, s) : launch_class<KIND, 0, 1>(a, s);
-  if (ev1) (void)hipEventRecord(ev1, s);
+    e = wide ? launch_class<KIND, 0, 0>(a, s, ev0, ev1) : launch_class<KIND, 0, 1>(a, s, ev0, ev1);
   if (e != hipSuccess) return e;
   // class 1 (register need 5..8, and every program with one of the further
   // operators) resident too when the shape allows, 4 cases per lane

@@ -40,6 +40,10 @@ struct beagle_ctx {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   int tuning = BEAGLE_TUNE_AUTO;
   int decoder = BEAGLE_DECODE_WAVE;  // decoder of programs of at most 64 tokens
+  // side stream of the target statistics (beside the decoding), created on
+  // first use, with its fork and join events
+  hipStream_t side = nullptr;
+  hipEvent_t side_fork = nullptr, side_join = nullptr;
   std::map<bgl::host::TuneKey, int> tuned;  // bucket -> tile variant (0 wide, 1 narrow)
   std::string tune_file;                    // BEAGLE_AUTOTUNE_CACHE at creation ("" = none)
   // batched evaluation

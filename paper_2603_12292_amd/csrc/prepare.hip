@@ -338,6 +338,36 @@ __device__ static void wave_append(int which, int p, int32_t* count, int32_t* li
   }
 }
 
+// The same appends for a whole workgroup of WAVES waves, one atomic per
+// list and workgroup: a list's slots go to the waves in wave order and,
+// within a wave, to the lanes in lane order.  Every thread of the
+// workgroup calls it (it synchronises the workgroup twice).
+template <int NL, int WAVES>
+__device__ static void block_append(int which, int p, int32_t* count, int32_t* list, int64_t stride,
+                                    int32_t (&cnt)[WAVES][8], int32_t (&base)[8]) {
+  static_assert(NL <= 8, "at most 8 lists");
+  const int lane = threadIdx.x & 63, w = int(threadIdx.x >> 6);
+  int rank = 0;
+  for (int l = 0; l < NL; ++l) {
+    const uint64_t m = __ballot(which == l);
+    if (which == l)
+      rank = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
+    if (lane == 0) cnt[w][l] = __popcll(m);
+  }
+  __syncthreads();
+  if (threadIdx.x < NL) {
+    int total = 0;
+    for (int v = 0; v < WAVES; ++v) total += cnt[v][threadIdx.x];
+    base[threadIdx.x] = total > 0 ? atomicAdd(count + threadIdx.x, total) : 0;
+  }
+  __syncthreads();
+  if (which >= 0 && which < NL) {
+    int slot = base[which] + rank;
+    for (int v = 0; v < w; ++v) slot += cnt[v][which];
+    list[int64_t(which) * stride + slot] = p;
+  }
+}
+
 // One program's list appends with one atomic each (the batched kernel:
 // neighbouring lanes belong to different problems).
 __device__ static void append_one(const PrepareArgs& a, int p, ListIds ids) {
@@ -807,8 +837,8 @@ __device__ static ListIds decode_wave(const PrepareArgs& a, int p, int64_t off, 
 // Four waves per workgroup, a.wave_programs (1..64) consecutive programs per
 // wave decoded one at a time (few per wave when the population is small, so
 // that the grid still fills the chip); a program longer than 64 tokens is
-// appended to the long list for k_prepare_long.  List appends as in
-// k_prepare (one atomic per list and wave).  The program headers of a
+// appended to the long list for k_prepare_long.  List appends: one atomic
+// per list and workgroup.  The program headers of a
 // wave's programs are loaded once (lane j: program j), and each program's
 // tokens are loaded while the previous program is decoded.
 __device__ __forceinline__ int64_t lane64(int64_t v, int j) {
@@ -855,9 +885,14 @@ __global__ void __launch_bounds__(256) k_prepare_wave(PrepareArgs a) {
     lc = wdec::sel(lane == j, ids.lc, lc);
   }
   const int p = int(base + lane);  // (lanes without a program append nothing)
-  wave_append<1>(defer ? 0 : -1, p, a.long_count, a.long_list, 0);
-  wave_append<N_CLASSES>(cls, p, a.class_count, a.class_list, a.n_programs);
-  if (ADJ) wave_append<GRAD_LISTS>(lc, p, a.len_count, a.len_list, a.n_programs);
+  __shared__ int32_t cnt[4][8], lbase[8];
+  block_append<1, 4>(defer ? 0 : -1, p, a.long_count, a.long_list, 0, cnt, lbase);
+  __syncthreads();
+  block_append<N_CLASSES, 4>(cls, p, a.class_count, a.class_list, a.n_programs, cnt, lbase);
+  if (ADJ) {
+    __syncthreads();
+    block_append<GRAD_LISTS, 4>(lc, p, a.len_count, a.len_list, a.n_programs, cnt, lbase);
+  }
 }
 
 template __global__ void k_prepare_wave<false>(PrepareArgs a);
@@ -995,15 +1030,25 @@ __global__ void k_stage_batch(BatchArgs b) {
 // target of a correlation fitness is valid): with n of them,
 //   ybar = y0 + sum(y - y0) / n  (y0 = y[0], or 0 when y[0] is invalid),
 //   w_i = y_i - ybar (binary64), stats = {ybar, sum w, sum w^2 - (sum w)^2 / n}.
+constexpr int STATS_UNROLL = 8;
+
 __device__ static void target_stats_block(const float* __restrict__ y, int64_t M, double* __restrict__ stats,
                                           double (&red)[2][1024]) {
   const int t = threadIdx.x;
   const double y0 = isfinite(y[0]) ? double(y[0]) : 0.0;
   double s = 0.0, cnt = 0.0;
-  for (int64_t i = t; i < M; i += 1024) {
-    const bool ok = isfinite(y[i]);
-    s += ok ? double(y[i]) - y0 : 0.0;
-    cnt += ok ? 1.0 : 0.0;
+  // each thread sums i = t, t + 1024, ... in that order; STATS_UNROLL of its
+  // loads are issued before the first of their additions
+  for (int64_t i0 = t; i0 < M; i0 += STATS_UNROLL * 1024) {
+    float v[STATS_UNROLL];
+#pragma unroll
+    for (int u = 0; u < STATS_UNROLL; ++u) v[u] = i0 + u * 1024 < M ? y[i0 + u * 1024] : __builtin_nanf("");
+#pragma unroll
+    for (int u = 0; u < STATS_UNROLL; ++u) {
+      const bool ok = isfinite(v[u]);
+      s += ok ? double(v[u]) - y0 : 0.0;
+      cnt += ok ? 1.0 : 0.0;
+    }
   }
   red[0][t] = s;
   red[1][t] = cnt;
@@ -1019,11 +1064,17 @@ __device__ static void target_stats_block(const float* __restrict__ y, int64_t M
   const double ybar = n > 0.0 ? y0 + red[0][0] / n : y0;
   __syncthreads();
   double s1 = 0.0, s2 = 0.0;
-  for (int64_t i = t; i < M; i += 1024) {
-    const bool ok = isfinite(y[i]);
-    const double w = ok ? double(y[i]) - ybar : 0.0;
-    s1 += w;
-    s2 += w * w;
+  for (int64_t i0 = t; i0 < M; i0 += STATS_UNROLL * 1024) {
+    float v[STATS_UNROLL];
+#pragma unroll
+    for (int u = 0; u < STATS_UNROLL; ++u) v[u] = i0 + u * 1024 < M ? y[i0 + u * 1024] : __builtin_nanf("");
+#pragma unroll
+    for (int u = 0; u < STATS_UNROLL; ++u) {
+      const bool ok = isfinite(v[u]);
+      const double w = ok ? double(v[u]) - ybar : 0.0;
+      s1 += w;
+      s2 += w * w;
+    }
   }
   red[0][t] = s1;
   red[1][t] = s2;

@@ -1,5 +1,6 @@
 """GPU evaluator parity against the CPU oracle (beagle_eval, beagle_predict)."""
 import math
+import time
 
 import numpy as np
 import pytest
@@ -405,6 +406,42 @@ def test_determinism():
     a, _ = _run(w.programs, w.data, ofit.CORR)
     b, _ = _run(w.programs, w.data, ofit.CORR)
     assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
+
+
+def test_back_to_back_targets_and_timing_events():
+    """Two correlation evaluations with different targets queued on one
+    stream without a synchronisation between them (the target statistics of
+    the second run beside its decoding, after the first call's work) give
+    the fitness of each run alone; kernel timing changes no bit and reports
+    one interpreter launch per call, shorter than the whole call."""
+    api = _api()
+    ps = wl.random_population(31, 3000, 5, 48, 4)
+    d1 = wl.make_dataset(32, 40_000, 4, x_range=(1.0, 5.0), target_len=10)
+    d2 = wl.make_dataset(33, 40_000, 4, x_range=(1.0, 5.0), target_len=12)
+    d2.X[:] = d1.X
+    ref1, _ = _run(ps, d1, ofit.CORR)
+    ref2, _ = _run(ps, d2, ofit.CORR)
+    assert not np.array_equal(ref1.view(np.uint64), ref2.view(np.uint64))
+    X, y1 = _xy(d1)
+    y2 = torch.from_numpy(d2.y).cuda()
+    progs = _dev(ps)
+    ctx = api.Context(0)
+    for timing in (False, True):
+        ctx.enable_timing(timing)
+        torch.cuda.synchronize()
+        f1 = api.evaluate(progs, X, y1, "corr", ctx=ctx)
+        f2 = api.evaluate(progs, X, y2, "corr", ctx=ctx)
+        torch.cuda.synchronize()
+        assert np.array_equal(f1.cpu().numpy().view(np.uint64), ref1.view(np.uint64))
+        assert np.array_equal(f2.cpu().numpy().view(np.uint64), ref2.view(np.uint64))
+    ms, n = ctx.kernel_time()
+    assert n == 2 and ms > 0.0
+    t0 = time.perf_counter()
+    api.evaluate(progs, X, y1, "corr", ctx=ctx)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3
+    ms3, n3 = ctx.kernel_time()
+    assert n3 == 3 and 0.0 < ms3 - ms < wall_ms
 
 
 def test_workspace_cap_gives_identical_results():
