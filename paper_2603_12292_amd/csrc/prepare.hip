@@ -579,7 +579,7 @@ struct WaveDecLds {
 // (wave-uniform).
 template <bool ADJ>
 __device__ static ListIds decode_wave(const PrepareArgs& a, int p, int64_t off, int32_t L, int64_t coff, int32_t cc,
-                                      uint32_t tok, WaveDecLds& sh) {
+                                      uint32_t tok, int lay_tok, int lay_const, WaveDecLds& sh) {
   using namespace wdec;
   const int lane = lane_id();
   int status = BEAGLE_PROG_OK;
@@ -590,11 +590,11 @@ __device__ static ListIds decode_wave(const PrepareArgs& a, int p, int64_t off, 
     status = L == 0 ? BEAGLE_PROG_EMPTY : BEAGLE_PROG_BAD_LAYOUT;
   } else if (off < 0 || off + L > a.n_tokens || cc < 0 || (cc > 0 && (coff < 0 || coff + cc > a.n_consts))) {
     status = BEAGLE_PROG_BAD_LAYOUT;
-  } else if (a.layout) {
+  } else if (lay_tok | lay_const) {
     // ranges not sorted and disjoint: every slot must carry p as its owner
     bool mine = true;
-    if (a.layout[0]) mine = __builtin_amdgcn_ballot_w64(lane < L && a.owner[off + lane] != p) == 0;
-    if (ADJ && mine && a.layout[1])
+    if (lay_tok) mine = __builtin_amdgcn_ballot_w64(lane < L && a.owner[off + lane] != p) == 0;
+    if (ADJ && mine && lay_const)
       for (int32_t j0 = 0; j0 < cc && mine; j0 += 64)
         mine = __builtin_amdgcn_ballot_w64(j0 + lane < cc && a.cowner[coff + j0 + lane] != p) == 0;
     if (!mine) status = BEAGLE_PROG_BAD_LAYOUT;
@@ -616,12 +616,15 @@ __device__ static ListIds decode_wave(const PrepareArgs& a, int p, int64_t off, 
                     : (op == OP_CONST) & (int(arg) >= cc) ? BEAGLE_PROG_BAD_CONST
                     : d < 1                             ? BEAGLE_PROG_UNDERFLOW
                                                         : 0;
-    const uint64_t em = __builtin_amdgcn_ballot_w64(act & (err != 0));
+    // lanes holding a token (L <= 64 here); ballots of lane conditions are
+    // masked with it on the scalar side
+    const uint64_t actm = L >= 64 ? ~0ull : (1ull << L) - 1ull;
+    const uint64_t em = __builtin_amdgcn_ballot_w64(err != 0) & actm;
     if (em) status = lane_value(err, first_lane(em));
     else if (lane_value(d, L - 1) != 1) status = BEAGLE_PROG_BAD_FINAL_DEPTH;
     if (status == BEAGLE_PROG_OK) {
       vmask = wave_or(act & (op == OP_VAR) ? 1u << arg : 0u);
-      ext = __builtin_amdgcn_ballot_w64(act & (op - uint32_t(OP_SQUARE) < uint32_t(N_OPCODES - OP_SQUARE))) != 0;
+      ext = (__builtin_amdgcn_ballot_w64(op - uint32_t(OP_SQUARE) < uint32_t(N_OPCODES - OP_SQUARE)) & actm) != 0;
       // ---- subtree starts: s = 1 + the last j < lane with d_j < d (d_{-1} = 0)
       int mn[6];
       mn[0] = d;
@@ -639,17 +642,22 @@ __device__ static ListIds decode_wave(const PrepareArgs& a, int p, int64_t off, 
       }
       const int st = q + 1;
       // ---- register need, bottom-up: leaves 1; unary: the child's;
-      // binary: the larger child's, plus one when both are equal
+      // binary: the larger child's, plus one when both are equal.  A need
+      // not yet known is NEED_UNKNOWN or more (known ones are at most 7):
+      // the larger-child rule then keeps it unknown without a test
       const int s_prev = from(st, lane > 0 ? lane - 1 : 0);  // start of the right operand
       const int lch = s_prev - 1;                              // left child (binary)
-      int need = ar == 0 ? 1 : 0;
+      constexpr int NEED_UNKNOWN = 1024;
+      int need = ar == 0 ? 1 : NEED_UNKNOWN;
       int nr = 0, nl = 0;
+      const int src_r = lane > 0 ? lane - 1 : 0, src_l = lch > 0 ? lch : 0;
+      const bool is_un = ar == 1, is_bin = ar == 2;
       for (;;) {
-        nr = from(need, lane > 0 ? lane - 1 : 0);
-        nl = from(need, lch > 0 ? lch : 0);
-        const int nb2 = sel((nl > 0) & (nr > 0), sel(nl == nr, nl + 1, max(nl, nr)), 0);
-        need = sel(ar == 1, nr, sel(ar == 2, nb2, need));
-        if (__builtin_amdgcn_ballot_w64(act & (need == 0)) == 0) break;
+        nr = from(need, src_r);
+        nl = from(need, src_l);
+        const int nb2 = max(nl, nr) + int(nl == nr);
+        need = sel(is_un, nr, sel(is_bin, nb2, need));
+        if ((__builtin_amdgcn_ballot_w64(need >= 64) & actm) == 0) break;
       }
       need_root = lane_value(need, L - 1);
       // ---- output order: parents tell children their offset within the
@@ -658,16 +666,18 @@ __device__ static ListIds decode_wave(const PrepareArgs& a, int p, int64_t off, 
       const int size_r = lane - s_prev;  // binary: the right operand's size
       const int st_l = from(st, lch > 0 ? lch : 0);
       const int size_l = lch - st_l + 1;
-      if (act && ar >= 1) sh.a[lane - 1] = uint32_t(lane) | (uint32_t(ar == 2 && !swap ? size_l : 0) << 8);
-      if (act && ar == 2) sh.a[lch] = uint32_t(lane) | (uint32_t(swap ? size_r : 0) << 8);
-      if (lane == L - 1) sh.a[lane] = uint32_t(lane);
+      // (the parent's lane times 4 in bits 2..7: the byte address of a
+      // lane read, with the offset from bit 8)
+      if (act && ar >= 1) sh.a[lane - 1] = uint32_t(lane << 2) | (uint32_t(ar == 2 && !swap ? size_l : 0) << 8);
+      if (act && ar == 2) sh.a[lch] = uint32_t(lane << 2) | (uint32_t(swap ? size_r : 0) << 8);
+      if (lane == L - 1) sh.a[lane] = uint32_t(lane << 2);
       __builtin_amdgcn_wave_barrier();
-      int pk = act ? int(sh.a[lane]) : lane;  // parent | offset << 8
+      int pk = act ? int(sh.a[lane]) : lane << 2;  // parent * 4 | offset << 8
       __builtin_amdgcn_wave_barrier();
 #pragma unroll
       for (int r = 0; r < 6; ++r) {
-        const int v = from(pk, pk & 0xFF);
-        pk = (pk & ~0xFF) + v;  // offsets add up, the parent pointer jumps
+        const int v = __builtin_amdgcn_ds_bpermute(pk & 0xFC, pk);
+        pk = (pk & ~0xFC) + v;  // offsets add up, the parent pointer jumps
       }
       const int ostart = pk >> 8;
       const int oend = ostart + (lane - st);
@@ -868,6 +878,9 @@ __global__ void __launch_bounds__(256) k_prepare_wave(PrepareArgs a) {
     const bool ok = L >= 1 && L <= PREP_NARROW && off >= 0 && off + L <= a.n_tokens && lane < L;
     return ok ? uint32_t(a.tokens[off + lane]) : 0u;
   };
+  // the disjoint-ranges flags (set before this kernel)
+  const int lay_tok = a.layout ? a.layout[0] : 0;
+  const int lay_const = a.layout && ADJ ? a.layout[1] : 0;
   int cls = -1, lc = -1;
   bool defer = false;
   uint32_t t_next = nb > 0 ? fetch(0) : 0u;
@@ -880,7 +893,7 @@ __global__ void __launch_bounds__(256) k_prepare_wave(PrepareArgs a) {
       continue;
     }
     const ListIds ids = decode_wave<ADJ>(a, int(base + j), lane64(hoff, j), L, lane64(hcoff, j),
-                                    __builtin_amdgcn_readlane(hcc, j), t, lds[w]);
+                                    __builtin_amdgcn_readlane(hcc, j), t, lay_tok, lay_const, lds[w]);
     cls = wdec::sel(lane == j, ids.cls, cls);
     lc = wdec::sel(lane == j, ids.lc, lc);
   }
