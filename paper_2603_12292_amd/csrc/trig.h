@@ -44,9 +44,11 @@ constexpr double TRIG_ROUND = 0x1.8p52;  // 1.5 * 2^52
 
 // r (in binary64) for a = |x| < 2^30, and in bit 0 of p the parity of k
 // (sine: a = k pi + r) or of j + 1 = k (cosine: a = (j + 1/2) pi + r).
+// Takes x itself: the absolute value is taken in binary64, where it is a
+// source modifier of the instructions that read it.
 template <bool COS>
-__device__ __forceinline__ double trig_reduce_small_d(float a, int& p) {
-  const double xd = double(a);
+__device__ __forceinline__ double trig_reduce_small_d(float x, int& p) {
+  const double xd = __builtin_fabs(double(x));
   // 1/pi; t = TRIG_ROUND + k
   const double t = COS ? __builtin_fma(xd, 0x1.45f306dc9c883p-2, 0.5) + TRIG_ROUND
                        : __builtin_fma(xd, 0x1.45f306dc9c883p-2, TRIG_ROUND);
@@ -58,8 +60,8 @@ __device__ __forceinline__ double trig_reduce_small_d(float a, int& p) {
 }
 
 template <bool COS>
-__device__ __forceinline__ float trig_reduce_small(float a, int& p) {
-  return float(trig_reduce_small_d<COS>(a, p));
+__device__ __forceinline__ float trig_reduce_small(float x, int& p) {
+  return float(trig_reduce_small_d<COS>(x, p));
 }
 
 // The same for a finite a >= 2^30 (exponent e >= 30).
@@ -95,16 +97,18 @@ __device__ __forceinline__ float trig_reduce_large(float a, int& p) {
   return float(double(v) * 0x1.921fb54442d18p-63);  // * pi * 2^-64
 }
 
-// (-1)^p sin r, sign bit also flipped by `neg`.
+// (-1)^p sin r, sign bit also flipped by `neg` (0 or the sign bit).  Adding
+// p << 31 flips the sign bit exactly as an exclusive or would (the carry
+// leaves the word), in one instruction with the shift.
 __device__ __forceinline__ float trig_finish(float r, int p, uint32_t neg) {
-  return __uint_as_float(__float_as_uint(sin_poly(r)) ^ (uint32_t(p) << 31) ^ neg);
+  return __uint_as_float((__float_as_uint(sin_poly(r)) + (uint32_t(p) << 31)) ^ neg);
 }
 
 // COS = false: sin x, true: cos x; for |x| < 2^30 only.
 template <bool COS>
 __device__ __forceinline__ float trig_small(float x) {
   int p;
-  const float r = trig_reduce_small<COS>(__builtin_fabsf(x), p);
+  const float r = trig_reduce_small<COS>(x, p);
   return trig_finish(r, p, COS ? 0u : (__float_as_uint(x) & 0x80000000u));
 }
 
@@ -120,6 +124,16 @@ __device__ __forceinline__ float trig_any(float x) {
   return trig_finish(r, p, COS ? 0u : (__float_as_uint(x) & 0x80000000u));
 }
 
+// x as a value the compiler cannot see through (an empty asm, no
+// instruction): |x| of the fast paths, taken in binary64 as a source
+// modifier, is then not merged with |x| of the range test, which would be
+// kept in a register by a separate AND.
+__device__ __forceinline__ float trig_fresh(float x) {
+  float y;
+  asm("" : "=v"(y) : "0"(x));
+  return y;
+}
+
 // sin or cos of K values per lane: the cheap reduction for the whole wave
 // when every argument of every lane is below 2^30, else one case at a time
 // through the general path.
@@ -130,7 +144,7 @@ __device__ __forceinline__ void trig_tile(float (&v)[K]) {
   for (int k = 0; k < K; ++k) big |= __builtin_amdgcn_ballot_w64(!(__builtin_fabsf(v[k]) < TRIG_SMALL));
   if (big == 0) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = trig_small<COS>(v[k]);
+    for (int k = 0; k < K; ++k) v[k] = trig_small<COS>(trig_fresh(v[k]));
   } else {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -155,9 +169,9 @@ __device__ __forceinline__ void sincos_tile(float (&s)[K], float (&c)[K]) {
   if (big == 0) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const float x = s[k];
+      const float x = trig_fresh(s[k]);
       int p;
-      const double r = trig_reduce_small_d<false>(__builtin_fabsf(x), p);
+      const double r = trig_reduce_small_d<false>(x, p);
       s[k] = trig_finish(float(r), p, __float_as_uint(x) & 0x80000000u);
       const double u = (0x1.921fb54442d18p+0 - __builtin_fabs(r)) + 0x1.1a62633145c07p-54;
       c[k] = trig_finish(float(u), p, 0u);
@@ -187,9 +201,9 @@ __device__ __forceinline__ void cos_nsin_tile(float (&c)[K], float (&ns)[K]) {
   if (big == 0) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const float x = c[k];
+      const float x = trig_fresh(c[k]);
       int p;
-      const double r = trig_reduce_small_d<true>(__builtin_fabsf(x), p);
+      const double r = trig_reduce_small_d<true>(x, p);
       c[k] = trig_finish(float(r), p, 0u);
       const double u = (0x1.921fb54442d18p+0 - __builtin_fabs(r)) + 0x1.1a62633145c07p-54;
       ns[k] = trig_finish(float(u), p, __float_as_uint(x) & 0x80000000u);
