@@ -137,10 +137,11 @@ EvalLayout eval_layout(const beagle_programs* P, const beagle_dataset* d, int n_
   L.cowner = with_grad ? c.take<int32_t>(std::max<int64_t>(P->n_consts, 1)) : 0;
   L.meta = c.take<bgl::ProgMeta>(N);
   L.class_count = c.take<int32_t>(64);  // [0..2] need classes, [8..9] length classes, [32..33] layout flags
+  // right behind the counters (256 bytes): one clear covers both
+  L.work = c.take<unsigned long long>(8);  // evaluation: one per class; adjoint: one per list
   L.class_list = c.take<int32_t>(size_t(bgl::N_CLASSES) * N);
   L.len_list = c.take<int32_t>(size_t(bgl::GRAD_LISTS) * N);
   L.long_list = c.take<int32_t>(size_t(N));
-  L.work = c.take<unsigned long long>(8);  // evaluation: one per class; adjoint: one per list
   L.Mp = round_up(d->M, bgl::CASES_PER_BLOCK_ITER);
   L.Xt = c.take<float>(size_t(d->D) * L.Mp);
   L.yp = c.take<float>(L.Mp);
@@ -166,7 +167,9 @@ EvalLayout eval_layout(const beagle_programs* P, const beagle_dataset* d, int n_
 beagle_status prepare(char* ws, const beagle_programs* P, const beagle_dataset* d, const EvalLayout& L,
                       int8_t* status, hipStream_t s, int decoder, int32_t max_words = bgl::MAX_LEN,
                       bool adjoint = false) {
-  zero_i32(reinterpret_cast<int32_t*>(ws + L.class_count), 64, s);
+  // the decoder's counters and flags, and the work counters of the first
+  // interpreter launch
+  zero_i32(reinterpret_cast<int32_t*>(ws + L.class_count), int64_t(L.work - L.class_count) / 4 + 16, s);
   bgl::PrepareArgs pa;
   pa.tokens = P->tokens;
   pa.n_tokens = P->n_tokens;
@@ -515,7 +518,12 @@ beagle_status evaluate_in(char* ws, const EvalLayout& L, int32_t slice, beagle_c
     return ea;
   };
   int kv = 1;
+  // the work counters are clear for the first launch unless the tuner's
+  // timed runs used them
+  bool counters_clear = true;
   if (ctx) {
+    counters_clear = known_tile_variant(ctx, kind, data->D, data->M,
+                                        double(progs->n_tokens) / progs->n_programs, &kv);
     TuneSlice ts{kind, slice_args(0, std::min(slice, progs->n_programs))};
     st = tile_variant(ctx, kind, data->D, data->M, double(progs->n_tokens) / progs->n_programs, s, run_slice, &ts,
                       &kv);
@@ -530,7 +538,7 @@ beagle_status evaluate_in(char* ws, const EvalLayout& L, int32_t slice, beagle_c
         return fail(BEAGLE_E_HIP, "hipEventCreate");
       ctx->events.emplace_back(ev0, ev1);
     }
-    hipError_t e = bgl::launch_eval(kind, kv, ea, s, ev0, ev1);
+    hipError_t e = bgl::launch_eval(kind, kv, ea, s, ev0, ev1, counters_clear && p0 == 0);
     if (e != hipSuccess) return hip_fail(e, "eval launch");
     bgl::FinalizeArgs fa;
     fa.meta = ea.meta;

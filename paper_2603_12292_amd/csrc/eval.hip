@@ -1036,8 +1036,9 @@ static hipError_t launch_resident(const EvalArgs& a, size_t lds, hipStream_t s, 
 }
 
 template <int KIND>
-static hipError_t launch_kind(int kv, const EvalArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, a.work, N_CLASSES);
+static hipError_t launch_kind(int kv, const EvalArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1,
+                              bool counters_clear) {
+  if (!counters_clear) hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, a.work, N_CLASSES);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const bool wide = kv == 0 && a.D <= WIDE_TILE_MAX_D;
@@ -1055,16 +1056,17 @@ static hipError_t launch_kind(int kv, const EvalArgs& a, hipStream_t s, hipEvent
   return launch_class<KIND, 2, 0>(a, s);
 }
 
-hipError_t launch_eval(int kind, int kv, const EvalArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+hipError_t launch_eval(int kind, int kv, const EvalArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1,
+                       bool counters_clear) {
   switch (kind) {
     case BEAGLE_FIT_MSE:
-      return launch_kind<BEAGLE_FIT_MSE>(kv, a, s, ev0, ev1);
+      return launch_kind<BEAGLE_FIT_MSE>(kv, a, s, ev0, ev1, counters_clear);
     case BEAGLE_FIT_CORR:
-      return launch_kind<BEAGLE_FIT_CORR>(kv, a, s, ev0, ev1);
+      return launch_kind<BEAGLE_FIT_CORR>(kv, a, s, ev0, ev1, counters_clear);
     case BEAGLE_FIT_POINT:
-      return launch_kind<BEAGLE_FIT_POINT>(kv, a, s, ev0, ev1);
+      return launch_kind<BEAGLE_FIT_POINT>(kv, a, s, ev0, ev1, counters_clear);
     default:
-      return launch_kind<BEAGLE_FIT_R4>(kv, a, s, ev0, ev1);
+      return launch_kind<BEAGLE_FIT_R4>(kv, a, s, ev0, ev1, counters_clear);
   }
 }
 

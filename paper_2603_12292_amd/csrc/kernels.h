@@ -239,7 +239,9 @@ bool resident_eligible(int64_t M, int32_t D, int32_t n_chunks, int32_t n_total);
 // fast-path kernel.
 // kv selects the tile variant of class 0 (forced to the narrow one above
 // WIDE_TILE_MAX_D variables).
-hipError_t launch_eval(int kind, int kv, const EvalArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
+// counters_clear: a.work is known to be zero (else it is cleared first).
+hipError_t launch_eval(int kind, int kv, const EvalArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1,
+                       bool counters_clear = false);
 // The work-list kernels of a batched evaluation; max_d[v] is the largest D
 // among the problems of list v (sizes the LDS tile), lists with
 // has_items[v] == 0 are skipped.

@@ -77,8 +77,9 @@ beagle_status tile_variant(beagle_ctx* ctx, int kind, int D, int64_t M, double m
     if (e0) (void)hipEventDestroy(e0);
     return hip_fail(e, "hipEventCreate");
   }
-  // one warm-up per variant, then three alternating timed runs; the median decides
-  constexpr int R = 3;
+  // one warm-up per variant, then five alternating timed runs; the fastest
+  // run of each decides (interference only ever slows a run down)
+  constexpr int R = 5;
   float t[2][R] = {};
   for (int v = 0; v < 2 && e == hipSuccess; ++v) e = run(user, v, s, nullptr, nullptr);
   for (int r = 0; r < R && e == hipSuccess; ++r) {
@@ -92,7 +93,7 @@ beagle_status tile_variant(beagle_ctx* ctx, int kind, int D, int64_t M, double m
   (void)hipEventDestroy(e1);
   if (e != hipSuccess) return hip_fail(e, "tile-width measurement");
   for (auto& row : t) std::sort(row, row + R);
-  *kv = t[1][R / 2] < t[0][R / 2] ? 1 : 0;
+  *kv = t[1][0] < t[0][0] ? 1 : 0;
   ctx->tuned[bucket(kind, D, M, mean_len)] = *kv;
   save_tune_file(ctx);
   return BEAGLE_OK;
