@@ -202,11 +202,20 @@ beagle_status prepare(char* ws, const beagle_programs* P, const beagle_dataset* 
   pa.owner = reinterpret_cast<int32_t*>(ws + L.owner);
   pa.cowner = adjoint ? reinterpret_cast<int32_t*>(ws + L.cowner) : nullptr;
   pa.wave_programs = 64;
-  // disjoint ranges (the fill and mark passes return at once when the
-  // ranges are sorted and disjoint), then programs of at most 64 tokens,
-  // then the ones longer than that
+  bgl::StageArgs sa;
+  sa.X = d->X;
+  sa.y = d->y;
+  sa.M = d->M;
+  sa.Mp = L.Mp;
+  sa.D = d->D;
+  sa.Xt = reinterpret_cast<float*>(ws + L.Xt);
+  sa.yp = reinterpret_cast<float*>(ws + L.yp);
+  // staging of the cases beside the disjoint-ranges check (the fill and
+  // mark passes return at once when the ranges are sorted and disjoint),
+  // then programs of at most 64 tokens, then the ones longer than that
   const uint32_t pgrid = uint32_t((P->n_programs + 255) / 256);
-  hipLaunchKernelGGL(bgl::k_layout_check, dim3(pgrid), dim3(256), 0, s, pa);
+  const uint32_t sgrid = uint32_t((L.Mp + 255) / 256);
+  hipLaunchKernelGGL(bgl::k_stage_and_check, dim3(sgrid + pgrid), dim3(256), 0, s, sa, pa, sgrid);
   hipLaunchKernelGGL(bgl::k_layout_fill, dim3(1024), dim3(256), 0, s, pa);
   hipLaunchKernelGGL(bgl::k_layout_mark, dim3(std::min<uint32_t>(pgrid, 1024)), dim3(256), 0, s, pa);
   if (decoder == BEAGLE_DECODE_THREAD)
@@ -222,15 +231,6 @@ beagle_status prepare(char* ws, const beagle_programs* P, const beagle_dataset* 
                        dim3(uint32_t((waves + 3) / 4)), dim3(256), 0, s, pa);
   }
   hipLaunchKernelGGL(bgl::k_prepare_long, dim3(512), dim3(64), 0, s, pa);
-  bgl::StageArgs sa;
-  sa.X = d->X;
-  sa.y = d->y;
-  sa.M = d->M;
-  sa.Mp = L.Mp;
-  sa.D = d->D;
-  sa.Xt = reinterpret_cast<float*>(ws + L.Xt);
-  sa.yp = reinterpret_cast<float*>(ws + L.yp);
-  hipLaunchKernelGGL(bgl::k_stage_cases, dim3(uint32_t((L.Mp + 255) / 256)), dim3(256), 0, s, sa);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "prepare launch");
   return BEAGLE_OK;

@@ -43,7 +43,7 @@ struct PrepareArgs {
   // Disjoint ranges: every program is decoded in place of its tokens, so the
   // token ranges of different programs (and, for the adjoint, whose gradient
   // output has the constants' layout, the constant ranges) must not overlap.
-  // layout[0], layout[1] (zero at launch): set by k_layout_check when the
+  // layout[0], layout[1] (zero at launch): set by k_stage_and_check when the
   // token / constant ranges are not sorted and disjoint by program index;
   // then owner / cowner hold, per token / constant slot, the lowest index of
   // a program whose range covers it, and a program finding another index in
@@ -205,7 +205,6 @@ __host__ __device__ constexpr int class_k(int c, int kv) { return c == 0 ? (kv =
 // the disjoint-ranges check before decoding (see PrepareArgs::layout):
 // neighbour comparison, then (only when that found unsorted or overlapping
 // ranges) the owner arrays filled and marked
-__global__ void k_layout_check(PrepareArgs a);
 __global__ void k_layout_fill(PrepareArgs a);
 __global__ void k_layout_mark(PrepareArgs a);
 __global__ void k_layout_check_batch(BatchArgs b);
@@ -216,7 +215,7 @@ __global__ void k_prepare(PrepareArgs a);
 template <bool ADJ>
 __global__ void k_prepare_wave(PrepareArgs a);
 __global__ void k_prepare_long(PrepareArgs a);
-__global__ void k_stage_cases(StageArgs a);
+__global__ void k_stage_and_check(StageArgs sa, PrepareArgs pa, uint32_t stage_blocks);
 __global__ void k_prepare_batch(BatchArgs b);
 __global__ void k_stage_batch(BatchArgs b);
 __global__ void k_target_stats_batch(BatchArgs b);

@@ -959,11 +959,6 @@ __device__ static void layout_mark(const PrepareArgs& a, int p) {
     for (int32_t i = 0; i < n; ++i) atomicMin(a.cowner + off + i, p);
 }
 
-__global__ void k_layout_check(PrepareArgs a) {
-  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (p < a.n_programs) layout_pair(a, int(p));
-}
-
 __global__ void k_layout_fill(PrepareArgs a) {
   layout_fill(a, int64_t(blockIdx.x) * blockDim.x + threadIdx.x, int64_t(gridDim.x) * blockDim.x);
 }
@@ -1016,9 +1011,17 @@ __device__ static void stage_case(const StageArgs& a, int64_t i) {
   a.yp[i] = a.y[src];
 }
 
-__global__ void k_stage_cases(StageArgs a) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < a.Mp) stage_case(a, i);
+// Staging and the disjoint-ranges check in one launch (neither reads what
+// the other writes): the first stage_blocks workgroups stage cases, the
+// rest check program pairs.
+__global__ void k_stage_and_check(StageArgs sa, PrepareArgs pa, uint32_t stage_blocks) {
+  if (blockIdx.x < stage_blocks) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < sa.Mp) stage_case(sa, i);
+  } else {
+    const int64_t p = int64_t(blockIdx.x - stage_blocks) * blockDim.x + threadIdx.x;
+    if (p < pa.n_programs) layout_pair(pa, int(p));
+  }
 }
 
 // One thread per padded case of every problem of the table.
