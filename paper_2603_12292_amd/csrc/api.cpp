@@ -488,9 +488,11 @@ beagle_status evaluate_in(char* ws, const EvalLayout& L, int32_t slice, beagle_c
   if (st != BEAGLE_OK) return st;
   bool shift_in_kernel = false;
   if (with_stats) {
-    if ((st = join_target_stats(join, s)) != BEAGLE_OK) return st;
+    // the shifts need only the decoded programs and the staged cases; the
+    // interpreter launches that follow read the statistics
     st = launch_shifts(ws, progs, data, L, s, &shift_in_kernel);
     if (st != BEAGLE_OK) return st;
+    if ((st = join_target_stats(join, s)) != BEAGLE_OK) return st;
   }
   auto slice_args = [&](int32_t p0, int32_t np) {
     bgl::EvalArgs ea;
@@ -918,11 +920,10 @@ namespace {
 beagle_status corr_pass(beagle_ctx* ctx, const beagle_programs* progs, const beagle_dataset* data,
                         const EvalLayout& L, double* fitness, hipEvent_t join, hipStream_t s) {
   char* ws = ctx->ws;
-  beagle_status st = join_target_stats(join, s);
-  if (st != BEAGLE_OK) return st;
   bool shift_in_kernel = false;
-  st = launch_shifts(ws, progs, data, L, s, &shift_in_kernel);
+  beagle_status st = launch_shifts(ws, progs, data, L, s, &shift_in_kernel);
   if (st != BEAGLE_OK) return st;
+  if ((st = join_target_stats(join, s)) != BEAGLE_OK) return st;
   bgl::EvalArgs ea;
   ea.code = reinterpret_cast<const uint32_t*>(ws + L.code);
   ea.cval = reinterpret_cast<const float*>(ws + L.cval);

@@ -559,6 +559,10 @@ k_eval_class(EvalArgs a) {
   const int32_t count = a.class_count[CLS];
   const int64_t items = int64_t(count) * a.n_chunks;
   const int32_t* list = a.class_list + int64_t(CLS) * a.n_total;
+  // workgroups beyond the item count leave at once: on a short (or empty)
+  // list, one same-address atomic per workgroup of the persistent grid
+  // would serialise at the counter for longer than the work takes
+  if (int64_t(blockIdx.x) >= items) return;
   for (;;) {
     if (threadIdx.x == 0) s_item = (long long)atomicAdd(a.work + CLS, 1ull);
     __syncthreads();
@@ -710,6 +714,7 @@ __global__ void __launch_bounds__(256) k_eval_batch(BatchArgs b, int vl) {
   extern __shared__ float xtile[];
   const int64_t* off = b.item_off + int64_t(vl) * (b.n_problems + 1);
   const int64_t items = off[b.n_problems];
+  if (int64_t(blockIdx.x) >= items) return;  // (as in k_eval_class)
   int lo = 0;  // the problem of the previous item (a lower bound for the next)
   for (;;) {
     if (threadIdx.x == 0) s_item = (long long)atomicAdd(b.work + vl, 1ull);

@@ -441,6 +441,8 @@ __global__ void __launch_bounds__(64) k_grad(GradArgs a) {
   const int32_t count = a.list_count[LONG ? 1 : 0];
   const int64_t items = int64_t(count) * a.n_chunks;
   const int32_t* list = a.list + (LONG ? int64_t(a.n_programs) : 0);
+  // waves beyond the item batches leave at once (no atomic on a short list)
+  if (int64_t(blockIdx.x) * GRAD_BATCH >= items) return;
   for (;;) {
     // as in k_grad_dtape: every lane in the atomic, a batch per atomic
     const unsigned long long it =
@@ -967,6 +969,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LIST ==
   const int32_t count = a.list_count[LIST];
   const int64_t items = int64_t(count) * a.n_chunks;
   const int32_t* list = a.list + LIST * int64_t(a.n_programs);
+  if (int64_t(blockIdx.x) * GRAD_BATCH >= items) return;  // (as in k_grad)
   for (;;) {
     // every lane takes part (lane 0 adds GRAD_BATCH): no divergent branch in
     // the persistent loop, the first item read from lane 0 explicitly; a
