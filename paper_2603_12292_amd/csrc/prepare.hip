@@ -844,6 +844,210 @@ __device__ static ListIds decode_wave(const PrepareArgs& a, int p, int64_t off, 
   return ListIds{};
 }
 
+// ---- several short programs per wave (evaluation only) -------------------
+// The same decoding, bit for bit, for 64 / SEG programs of at most SEG tokens
+// at once, program s in lanes s * SEG .. s * SEG + SEG - 1 (lane sb + i holds
+// its token i).  Every cross-lane step stays inside the segment: prefix sums
+// and maxima stop before the row broadcasts that would cross it, lane reads
+// add the segment's base, ballots are cut to the segment's bits, word
+// indices subtract the words of the segments below.  The program fields
+// (header, status, register need) are per lane, equal within a segment.
+namespace wdec {
+
+template <int SEG>
+__device__ __forceinline__ int seg_scan_add(int v) {
+  v += dpp<0x111, 0xF>(v);
+  v += dpp<0x112, 0xF>(v);
+  v += dpp<0x114, 0xF>(v);
+  v += dpp<0x118, 0xF>(v);
+  if constexpr (SEG >= 32) v += dpp<0x142, 0xA>(v);
+  return v;
+}
+// maximum / OR of non-negative values over the segment, on every lane
+template <int SEG>
+__device__ __forceinline__ int seg_max(int v, int last_lane) {
+  v = max(v, dpp<0x111, 0xF>(v));
+  v = max(v, dpp<0x112, 0xF>(v));
+  v = max(v, dpp<0x114, 0xF>(v));
+  v = max(v, dpp<0x118, 0xF>(v));
+  if constexpr (SEG >= 32) v = max(v, dpp<0x142, 0xA>(v));
+  return from(v, last_lane);
+}
+template <int SEG>
+__device__ __forceinline__ uint32_t seg_or(uint32_t u, int last_lane) {
+  int v = int(u);
+  v |= dpp<0x111, 0xF>(v);
+  v |= dpp<0x112, 0xF>(v);
+  v |= dpp<0x114, 0xF>(v);
+  v |= dpp<0x118, 0xF>(v);
+  if constexpr (SEG >= 32) v |= dpp<0x142, 0xA>(v);
+  return uint32_t(from(v, last_lane));
+}
+
+}  // namespace wdec
+
+template <int SEG>
+__device__ static ListIds decode_seg(const PrepareArgs& a, int p, int64_t off, int32_t L, int64_t coff, int32_t cc,
+                                     uint32_t tok, int lay_tok, WaveDecLds& sh) {
+  using namespace wdec;
+  static_assert(SEG == 16 || SEG == 32, "segments of 16 or 32 lanes");
+  constexpr int LOG = SEG == 16 ? 4 : 5;
+  constexpr uint64_t SEGMASK = (1ull << SEG) - 1ull;
+  const int lane = lane_id();
+  const int sb = lane & ~(SEG - 1);  // the segment's first lane
+  const int sl = lane - sb;          // position in the segment
+  // v of position i of this lane's segment (0 <= i < SEG where used)
+  auto sfrom = [&](int v, int i) { return from(v, sb + i); };
+  auto segbits = [&](uint64_t m) { return (m >> sb) & SEGMASK; };
+  int status = BEAGLE_PROG_OK;
+  if (L <= 0)
+    status = L == 0 ? BEAGLE_PROG_EMPTY : BEAGLE_PROG_BAD_LAYOUT;
+  else if (off < 0 || off + L > a.n_tokens || cc < 0 || (cc > 0 && (coff < 0 || coff + cc > a.n_consts)))
+    status = BEAGLE_PROG_BAD_LAYOUT;
+  if (lay_tok) {
+    // ranges not sorted and disjoint: every slot must carry p as its owner
+    const bool bad = status == BEAGLE_PROG_OK && sl < L && a.owner[off + sl] != p;
+    if (segbits(__builtin_amdgcn_ballot_w64(bad)) != 0) status = BEAGLE_PROG_BAD_LAYOUT;
+  }
+  const bool ok0 = status == BEAGLE_PROG_OK;
+  const bool act = ok0 & (sl < L);
+  const uint32_t t = act ? tok : 0u;
+  const uint32_t op = t & 0xFFu, arg = t >> 8;
+  const bool opok = op < N_OPCODES;
+  constexpr uint64_t ARITY = 0x5554155AAull;  // as in decode_wave
+  const int ar = opok ? int((ARITY >> (2u * op)) & 3u) : 0;
+  const int d = seg_scan_add<SEG>(act ? 1 - ar : 0);
+  const int err = !opok                              ? BEAGLE_PROG_BAD_OPCODE
+                  : (op == OP_VAR) & (int(arg) >= a.D)  ? BEAGLE_PROG_BAD_VAR
+                  : (op == OP_CONST) & (int(arg) >= cc) ? BEAGLE_PROG_BAD_CONST
+                  : d < 1                             ? BEAGLE_PROG_UNDERFLOW
+                                                      : 0;
+  const uint64_t em = segbits(__builtin_amdgcn_ballot_w64(act & (err != 0)));
+  const int first_err = em ? __ffsll((unsigned long long)em) - 1 : 0;
+  const int err_first = sfrom(err, first_err);
+  const int d_last = sfrom(d, L >= 1 ? L - 1 : 0);
+  if (ok0) status = em ? err_first : (d_last != 1 ? BEAGLE_PROG_BAD_FINAL_DEPTH : BEAGLE_PROG_OK);
+  const bool ok = status == BEAGLE_PROG_OK;  // the structural pass ran
+  const bool live = ok & (sl < L);
+  const uint32_t vmask = seg_or<SEG>(live & (op == OP_VAR) ? 1u << arg : 0u, sb + SEG - 1);
+  const bool ext =
+      segbits(__builtin_amdgcn_ballot_w64(live & (op - uint32_t(OP_SQUARE) < uint32_t(N_OPCODES - OP_SQUARE)))) != 0;
+  // ---- subtree starts (descent over minima of power-of-two windows)
+  int mn[LOG];
+  mn[0] = d;
+#pragma unroll
+  for (int k = 1; k < LOG; ++k) {
+    const int w = 1 << (k - 1);
+    const int u = sfrom(mn[k - 1], sl >= w ? sl - w : 0);
+    mn[k] = sel((sl >= w) & (u < mn[k - 1]), u, mn[k - 1]);
+  }
+  int q = sl - 1;
+#pragma unroll
+  for (int k = LOG - 1; k >= 0; --k) {
+    const int v = sfrom(mn[k], q > 0 ? q : 0);
+    q -= sel((q - (1 << k) + 1 >= 0) & (v >= d), 1 << k, 0);
+  }
+  const int st = q + 1;
+  // ---- register need (as in decode_wave)
+  const int s_prev = sfrom(st, sl > 0 ? sl - 1 : 0);
+  const int lch = s_prev - 1;
+  constexpr int NEED_UNKNOWN = 1024;
+  int need = ar == 0 ? 1 : NEED_UNKNOWN;
+  int nr = 0, nl = 0;
+  const int src_r = sl > 0 ? sl - 1 : 0, src_l = lch > 0 ? lch : 0;
+  const bool is_un = ar == 1, is_bin = ar == 2;
+  for (;;) {
+    nr = sfrom(need, src_r);
+    nl = sfrom(need, src_l);
+    const int nb2 = max(nl, nr) + int(nl == nr);
+    need = sel(is_un, nr, sel(is_bin, nb2, need));
+    if (__builtin_amdgcn_ballot_w64(live & (need >= 64)) == 0) break;
+  }
+  int need_root = sfrom(need, L >= 1 ? L - 1 : 0);
+  // ---- output order (parents' lanes as byte addresses)
+  const bool swap = (ar == 2) & (nr > nl);
+  const int size_r = sl - s_prev;
+  const int st_l = sfrom(st, lch > 0 ? lch : 0);
+  const int size_l = lch - st_l + 1;
+  if (live && ar >= 1) sh.a[lane - 1] = uint32_t(lane << 2) | (uint32_t(ar == 2 && !swap ? size_l : 0) << 8);
+  if (live && ar == 2) sh.a[sb + lch] = uint32_t(lane << 2) | (uint32_t(swap ? size_r : 0) << 8);
+  if (ok && sl == L - 1) sh.a[lane] = uint32_t(lane << 2);
+  __builtin_amdgcn_wave_barrier();
+  int pk = live ? int(sh.a[lane]) : lane << 2;
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int r = 0; r < LOG; ++r) {
+    const int v = __builtin_amdgcn_ds_bpermute(pk & 0xFC, pk);
+    pk = (pk & ~0xFC) + v;
+  }
+  const int ostart = pk >> 8;
+  const int oend = ostart + (sl - st);
+  const uint32_t op2 = sel(swap & (op == OP_SUB), 100u + B_RSUB, sel(swap & (op == OP_DIV), 100u + B_RDIV, op));
+  if (live) sh.b[sb + oend] = op2 | (arg << 8) | (uint32_t(ostart) << 16);
+  __builtin_amdgcn_wave_barrier();
+  const uint32_t e = live ? sh.b[lane] : 0xFFu;
+  __builtin_amdgcn_wave_barrier();
+  // ---- words, in output order (position sl holds output token sl)
+  const uint32_t o_op = e & 0xFFu, o_arg = (e >> 8) & 0xFFu;
+  const bool o_bin = (o_op < 4u) | (o_op - 100u < 6u);
+  const bool o_term = o_op - uint32_t(OP_VAR) < 2u;
+  const int o_delta = sel(live, sel(o_bin, -1, sel(o_term, 1, 0)), 0);
+  const int n_after = seg_scan_add<SEG>(o_delta);
+  const int n = n_after - o_delta;
+  const int nmax = seg_max<SEG>(live ? n_after : 0, sb + SEG - 1);
+  const uint32_t nxt = uint32_t(sfrom(int(o_op), sl < SEG - 1 ? sl + 1 : SEG - 1));
+  const bool nxt_bin = (sl + 1 < L) & ((nxt < 4u) | (nxt - 100u < 6u));
+  const bool fused = live & o_term & (n >= 1) & nxt_bin;
+  const bool absorbed = (sl > 0) & (((__builtin_amdgcn_ballot_w64(fused) << 1) >> lane) & 1u);
+  const bool ws = live & !absorbed;
+  const uint64_t wm = __builtin_amdgcn_ballot_w64(ws);
+  const uint64_t below = sb == 0 ? 0ull : wm & ((1ull << sb) - 1ull);  // words of the segments below
+  const int E = int(__builtin_amdgcn_mbcnt_hi(uint32_t(wm >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(wm), 0u))) -
+                __popcll(below);
+  const int widx = ws ? E : E - 1;
+  int L_dec = __popcll(segbits(wm));
+  const uint32_t un = uint32_t(n);
+  const uint32_t ob = nxt >= 100u ? nxt - 100u : nxt;
+  const uint32_t bo = o_op >= 100u ? o_op - 100u : o_op;
+  const bool isc = o_op == OP_CONST, isv = o_op == OP_VAR;
+  const uint32_t u = unary_index(o_op);
+  const uint32_t isc1 = isc ? 1u : 0u;
+  const int kind = fused ? 0 : o_term ? 1 : o_bin ? 2 : 3;
+  const uint32_t h = pick4(kind, H_FUSED + 6u * isc1 + ob, isv ? H_VAR : H_CONST, H_BIN + 15u * bo + (un - 2u),
+                           H_UN + u);
+  const uint32_t i0_f = I0_FUSED + 3u * (6u * isc1 + ob) + (un - 1u);
+  const uint32_t i0_t = (isv ? I0_PUSH_VAR : I0_PUSH_CONST) + un;
+  const uint32_t i0_b = I0_BIN + 3u * bo + (un - 2u);
+  const uint32_t i0_u = I0_UN + 4u * u + (un - 1u);
+  const uint32_t i0 = pick4(kind, sel(n <= 3, i0_f, I0_NONE), sel(n <= 3, i0_t, I0_NONE), sel(n <= 4, i0_b, I0_NONE),
+                            sel((n <= 4) & (u < U_FIRST_EXT), i0_u, I0_NONE));
+  const uint32_t wslot = n > 0 ? un - 1u : 0u;
+  const uint32_t warg = o_term ? o_arg : 0u;
+  const uint32_t word = h | (warg << 8) | (wslot << 16) | (i0 << 24);
+  need_root = nmax > need_root ? nmax : need_root;
+  if (ok && (need_root > MAX_STACK || L_dec > a.max_words)) status = BEAGLE_PROG_TOO_LONG;
+  if (ws) {
+    a.code[off + widx] = word;
+    if (isc) a.cval[off + widx] = a.consts[coff + o_arg];
+  }
+  ListIds ids;
+  if (status == BEAGLE_PROG_OK) {
+    ids.cls = need_class(need_root);
+    if (ext && ids.cls == 0) ids.cls = 1;
+  }
+  if (sl == 0) {
+    ProgMeta m;
+    m.status = status;
+    m.need = ok ? need_root : 0;  // (a program stopped by its length keeps its need)
+    m.len = status == BEAGLE_PROG_OK ? L_dec : 0;
+    m.shift = 0.0f;
+    m.vmask = status == BEAGLE_PROG_OK ? vmask : 0u;
+    a.meta[p] = m;
+    if (a.status_out) a.status_out[p] = int8_t(status);
+  }
+  return ids;
+}
+
 // Four waves per workgroup, a.wave_programs (1..64) consecutive programs per
 // wave decoded one at a time (few per wave when the population is small, so
 // that the grid still fills the chip); a program longer than 64 tokens is
@@ -856,9 +1060,15 @@ __device__ __forceinline__ int64_t lane64(int64_t v, int j) {
   const uint32_t hi = __builtin_amdgcn_readlane(uint32_t(uint64_t(v) >> 32), j);
   return int64_t((uint64_t(hi) << 32) | lo);
 }
+// v of lane src (any lane's own choice)
+__device__ __forceinline__ int64_t from64(int64_t v, int src) {
+  const uint32_t lo = uint32_t(wdec::from(int(uint32_t(uint64_t(v))), src));
+  const uint32_t hi = uint32_t(wdec::from(int(uint32_t(uint64_t(v) >> 32)), src));
+  return int64_t((uint64_t(hi) << 32) | lo);
+}
 
 template <bool ADJ>
-__global__ void __launch_bounds__(256) k_prepare_wave(PrepareArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ADJ ? 1 : 8))) k_prepare_wave(PrepareArgs a) {
   __shared__ WaveDecLds lds[4];
   const int lane = int(threadIdx.x & 63u), w = int(threadIdx.x >> 6);
   const int ppw = a.wave_programs;
@@ -883,19 +1093,82 @@ __global__ void __launch_bounds__(256) k_prepare_wave(PrepareArgs a) {
   const int lay_const = a.layout && ADJ ? a.layout[1] : 0;
   int cls = -1, lc = -1;
   bool defer = false;
-  uint32_t t_next = nb > 0 ? fetch(0) : 0u;
-  for (int j = 0; j < nb; ++j) {
-    const uint32_t t = t_next;
-    if (j + 1 < nb) t_next = fetch(j + 1);
-    const int32_t L = __builtin_amdgcn_readlane(hL, j);
-    if (L > PREP_NARROW) {
-      defer |= lane == j;
-      continue;
+  if constexpr (ADJ) {
+    uint32_t t_next = nb > 0 ? fetch(0) : 0u;
+    for (int j = 0; j < nb; ++j) {
+      const uint32_t t = t_next;
+      if (j + 1 < nb) t_next = fetch(j + 1);
+      const int32_t L = __builtin_amdgcn_readlane(hL, j);
+      if (L > PREP_NARROW) {
+        defer |= lane == j;
+        continue;
+      }
+      const ListIds ids = decode_wave<ADJ>(a, int(base + j), lane64(hoff, j), L, lane64(hcoff, j),
+                                      __builtin_amdgcn_readlane(hcc, j), t, lay_tok, lay_const, lds[w]);
+      cls = wdec::sel(lane == j, ids.cls, cls);
+      lc = wdec::sel(lane == j, ids.lc, lc);
     }
-    const ListIds ids = decode_wave<ADJ>(a, int(base + j), lane64(hoff, j), L, lane64(hcoff, j),
-                                    __builtin_amdgcn_readlane(hcc, j), t, lay_tok, lay_const, lds[w]);
-    cls = wdec::sel(lane == j, ids.cls, cls);
-    lc = wdec::sel(lane == j, ids.lc, lc);
+  } else {
+    // Programs of at most 16 tokens four to a wave, then (with those left
+    // over) programs of at most 32 tokens two to a wave, then the rest one at
+    // a time -- three loops one after another, so that the register needs
+    // of the two decoders do not add up.
+    const bool hold = lane < nb;
+    uint64_t m16 = __builtin_amdgcn_ballot_w64(hold && hL <= 16);
+    uint64_t m32 = __builtin_amdgcn_ballot_w64(hold && hL > 16 && hL <= 32);
+    uint64_t rest = __builtin_amdgcn_ballot_w64(hold) & ~(m16 | m32);
+    auto take = [](uint64_t& m) -> int {
+      const int j = __ffsll((unsigned long long)m) - 1;
+      m &= m - 1;
+      return j;
+    };
+    // tokens of program jj (this lane's segment) at position sl
+    auto fetch_seg = [&](int jj, int sl, int sz) -> uint32_t {
+      const int32_t Lp = wdec::from(hL, jj);
+      const int64_t offp = from64(hoff, jj);
+      const bool okp = Lp >= 1 && Lp <= sz && offp >= 0 && offp + Lp <= a.n_tokens && sl < Lp;
+      return okp ? uint32_t(a.tokens[offp + sl]) : 0u;
+    };
+    while (__popcll(m16) >= 4) {
+      const int j0 = take(m16), j1 = take(m16), j2 = take(m16), j3 = take(m16);
+      const int jj = wdec::pick4(lane >> 4, j0, j1, j2, j3);
+      const uint32_t t = fetch_seg(jj, lane & 15, 16);
+      const ListIds ids = decode_seg<16>(a, int(base + jj), from64(hoff, jj), wdec::from(hL, jj),
+                                         from64(hcoff, jj), wdec::from(hcc, jj), t, lay_tok, lds[w]);
+      // program j_s's lists come from its segment's first lane
+      const int s = wdec::sel(lane == j0, 0, wdec::sel(lane == j1, 1, wdec::sel(lane == j2, 2, 3)));
+      const int got = wdec::from(ids.cls, s * 16);
+      cls = wdec::sel((lane == j0) | (lane == j1) | (lane == j2) | (lane == j3), got, cls);
+    }
+    m32 |= m16;
+    while (__popcll(m32) >= 2) {
+      const int j0 = take(m32), j1 = take(m32);
+      const int jj = lane < 32 ? j0 : j1;
+      const uint32_t t = fetch_seg(jj, lane & 31, 32);
+      const ListIds ids = decode_seg<32>(a, int(base + jj), from64(hoff, jj), wdec::from(hL, jj),
+                                         from64(hcoff, jj), wdec::from(hcc, jj), t, lay_tok, lds[w]);
+      const int got = wdec::from(ids.cls, lane == j0 ? 0 : 32);
+      cls = wdec::sel((lane == j0) | (lane == j1), got, cls);
+    }
+    rest |= m32;
+    // one at a time, each program's tokens loaded while the previous one is
+    // decoded
+    int j = rest ? take(rest) : -1;
+    uint32_t t_next = j >= 0 ? fetch(j) : 0u;
+    while (j >= 0) {
+      const uint32_t t = t_next;
+      const int jn = rest ? take(rest) : -1;
+      if (jn >= 0) t_next = fetch(jn);
+      const int32_t L = __builtin_amdgcn_readlane(hL, j);
+      if (L > PREP_NARROW) {
+        defer |= lane == j;
+      } else {
+        const ListIds ids = decode_wave<false>(a, int(base + j), lane64(hoff, j), L, lane64(hcoff, j),
+                                               __builtin_amdgcn_readlane(hcc, j), t, lay_tok, 0, lds[w]);
+        cls = wdec::sel(lane == j, ids.cls, cls);
+      }
+      j = jn;
+    }
   }
   const int p = int(base + lane);  // (lanes without a program append nothing)
   __shared__ int32_t cnt[4][8], lbase[8];

@@ -63,6 +63,42 @@ def _mixed_population(seed, n, D):
     return wl.pack_programs(progs)
 
 
+def _short_population(seed, n, D, lmax):
+    """The mixed population's kinds with every program of at most lmax
+    tokens (lmax 0: lengths 1..16 half the time, 17..32 three times in ten,
+    33..64 otherwise), empty programs and final depth two among them, so that
+    the wave decoder takes its programs four (16 tokens), two (32) or one at
+    a time, in every mixture."""
+    rng = np.random.default_rng(seed)
+    ext = (wl.SIN, wl.COS, wl.EXP, wl.LOG, wl.SQRT, wl.SQUARE, wl.RECIP, wl.TAN, wl.ASIN, wl.ACOS, wl.ATAN,
+           wl.TANH)
+
+    def length():
+        if lmax:
+            return int(rng.integers(1, lmax + 1))
+        u = rng.random()
+        return int(rng.integers(1, 17)) if u < 0.5 else int(rng.integers(17, 33)) if u < 0.8 else \
+            int(rng.integers(33, 65))
+
+    progs = []
+    for i in range(n):
+        r = i % 10
+        if r < 6:
+            progs.append(wl.random_program(rng, length(), D))
+        elif r == 6:
+            progs.append(wl.random_program(rng, length(), D, unary=ext))
+        elif r == 7:
+            progs.append(([], []) if i % 20 == 7 else ([wl.tok(wl.VAR, 0), wl.tok(wl.VAR, 1)], []))
+        elif r == 8:
+            L = length()
+            toks = (rng.integers(0, 20, L) | (rng.integers(0, D + 2, L) << 8)).astype(int).tolist()
+            progs.append((toks, [0.5, -1.25, 2.0]))
+        else:
+            k = length() - 1
+            progs.append(([wl.tok(wl.VAR, 0)] + [wl.tok(int(rng.choice([wl.SIN, wl.SQRT, wl.EXP])))] * k, []))
+    return wl.pack_programs(progs)
+
+
 def _bits(t):
     return t.cpu().numpy().view(np.uint64 if t.dtype == torch.float64 else np.uint32)
 
@@ -138,3 +174,36 @@ def test_decoders_agree_on_a_large_population(log2n):
         ft, st = api.evaluate(P, X, y, kind, with_status=True, ctx=ct)
         assert np.all(sw.cpu().numpy() == 0) and np.all(st.cpu().numpy() == 0)
         assert np.array_equal(_bits(fw), _bits(ft))
+
+
+@pytest.mark.parametrize("lmax", [16, 32, 0])
+def test_decoders_agree_on_short_programs(lmax):
+    """36864 programs (nine per wave of the wave decoder) of at most 16 or
+    32 tokens, or of mixed lengths: programs decoded four or two to a wave
+    give the statuses, fitness and outputs of the thread decoder; also when
+    some programs share a lower-indexed program's tokens (BAD_LAYOUT for
+    the later ones, the ownership test inside a segment)."""
+    api = _api()
+    cw, ct = _contexts()
+    ps = _short_population(41 + lmax, 36864, 4, lmax)
+    data = wl.make_dataset(42, 300, 4, x_range=(-2.0, 5.0), target_len=8)
+    X, y = torch.from_numpy(data.X).cuda(), torch.from_numpy(data.y).cuda()
+    off = ps.tok_offset.astype(np.int64).copy()
+    lens = ps.tok_len.astype(np.int32).copy()
+    shared = np.arange(97, ps.n, 97)
+    off[shared], lens[shared] = off[shared - 1], lens[shared - 1]
+    layouts = [api.DevicePrograms.from_programset(ps),
+               api.DevicePrograms.from_arrays(ps.tokens, off, lens, ps.consts, ps.const_offset, ps.const_count)]
+    for P in layouts:
+        for kind in ("mse", "corr"):
+            fw, sw = api.evaluate(P, X, y, kind, with_status=True, ctx=cw)
+            ft, st = api.evaluate(P, X, y, kind, with_status=True, ctx=ct)
+            sw, st = sw.cpu().numpy(), st.cpu().numpy()
+            assert np.array_equal(sw, st)
+            assert np.array_equal(_bits(fw), _bits(ft))
+            assert (sw == 0).sum() > ps.n // 2
+        ow, sw = api.predict(P, X[:64], with_status=True, ctx=cw)
+        ot, st = api.predict(P, X[:64], with_status=True, ctx=ct)
+        assert np.array_equal(sw.cpu().numpy(), st.cpu().numpy())
+        assert np.array_equal(_bits(ow), _bits(ot))
+    assert set(np.unique(sw.cpu().numpy()).tolist()) >= {0, 1, 2, 3, 4, 5, 6, 8}
