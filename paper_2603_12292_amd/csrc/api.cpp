@@ -804,6 +804,7 @@ beagle_status beagle_generation(beagle_ctx* ctx, const beagle_programs* parents,
   a.child_len = child_len;
   a.child_consts = child_consts;
   a.child_const_count = child_const_count;
+  a.slots = nullptr;
   hipLaunchKernelGGL(bgl::k_generation, dim3((n + 63) / 64), dim3(64), 0, reinterpret_cast<hipStream_t>(stream),
                      a);
   hipError_t e = hipGetLastError();
@@ -842,6 +843,7 @@ beagle_status beagle_generation_microcosm(beagle_ctx* ctx, const beagle_programs
   const size_t o_ns = cv.take<int32_t>(1);
   const size_t o_off = cv.take<int32_t>(size_t(n_blocks));
   const size_t o_surv = cv.take<int32_t>(size_t(n));
+  const size_t o_slots = cv.take<int64_t>(5);
   st = reserve(ctx, cv.used);
   if (st != BEAGLE_OK) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -861,6 +863,9 @@ beagle_status beagle_generation_microcosm(beagle_ctx* ctx, const beagle_programs
   m.n_surv = n_survivors ? n_survivors : reinterpret_cast<int32_t*>(ctx->ws + o_ns);
   m.block_off = reinterpret_cast<int32_t*>(ctx->ws + o_off);
   m.surv = reinterpret_cast<int32_t*>(ctx->ws + o_surv);
+  m.tok_offset = parents->tok_offset;
+  m.const_offset = parents->const_offset;
+  m.slots = reinterpret_cast<int64_t*>(ctx->ws + o_slots);
   hipLaunchKernelGGL(bgl::k_micro_threshold, dim3(1), dim3(bgl::MICRO_MAX_SAMPLE), 0, s, m);
   hipLaunchKernelGGL(bgl::k_micro_count, dim3(n_blocks), dim3(bgl::MICRO_BLOCK), 0, s, m);
   hipLaunchKernelGGL(bgl::k_micro_scan, dim3(1), dim3(1024), 0, s, m);
@@ -900,6 +905,7 @@ beagle_status beagle_generation_microcosm(beagle_ctx* ctx, const beagle_programs
     a.child_len = child_len;
     a.child_consts = child_consts;
     a.child_const_count = child_const_count;
+    a.slots = m.slots;
     hipLaunchKernelGGL(bgl::k_generation, dim3((n_children + 63) / 64), dim3(64), 0, s, a);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "generation launch");

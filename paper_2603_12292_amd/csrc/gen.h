@@ -47,6 +47,11 @@ struct GenStepArgs {
   int32_t* child_len;
   float* child_consts;
   int32_t* child_const_count;
+  // the parents' layout when it is regular (slots[0] != 0: parent i's tokens
+  // at slots[1] + i * slots[2], its constants at slots[3] + i * slots[4]), so
+  // that a child need not read two header entries of a random parent; NULL:
+  // always read them
+  const int64_t* slots;
 };
 
 struct InitArgs {
@@ -76,6 +81,12 @@ struct MicroArgs {
   int32_t* block_off;  // [n_blocks] survivor counts, then their exclusive prefix sums
   int32_t* n_surv;     // [1] survivors in total
   int32_t* surv;       // [n] survivor indices in index order
+  // the parents' token and constant offsets, and [5] their layout test (see
+  // GenStepArgs::slots): k_micro_threshold writes the layout of the first
+  // two parents, k_micro_count clears slots[0] at any parent that breaks it
+  const int64_t* tok_offset;
+  const int64_t* const_offset;
+  int64_t* slots;
 };
 
 __global__ void k_generation(GenStepArgs a);

@@ -165,8 +165,12 @@ __global__ void k_generation(GenStepArgs a) {
     ia = tournament(s, 1, t, a.fitness, N);
     ib = tournament(s, 1 + t, t, a.fitness, N);
   }
-  const int64_t oa = a.tok_offset[ia], ob = a.tok_offset[ib];
-  const int64_t coa = a.const_offset[ia], cob = a.const_offset[ib];
+  // (a regular layout gives the offsets without reading them)
+  const bool reg = a.slots && a.slots[0] != 0;
+  const int64_t oa = reg ? a.slots[1] + int64_t(ia) * a.slots[2] : a.tok_offset[ia];
+  const int64_t ob = reg ? a.slots[1] + int64_t(ib) * a.slots[2] : a.tok_offset[ib];
+  const int64_t coa = reg ? a.slots[3] + int64_t(ia) * a.slots[4] : a.const_offset[ia];
+  const int64_t cob = reg ? a.slots[3] + int64_t(ib) * a.slots[4] : a.const_offset[ib];
   const int LA = a.tok_len[ia], LB = a.tok_len[ib];
   const int ca = a.const_count[ia], cb = a.const_count[ib];
   // a parent outside its arrays, empty or longer than a child slot gives an
@@ -253,6 +257,15 @@ __device__ __forceinline__ bool survives(double f, double tau) { return !isnan(f
 __global__ void __launch_bounds__(MICRO_MAX_SAMPLE) k_micro_threshold(MicroArgs a) {
   __shared__ double f[MICRO_MAX_SAMPLE];
   const int j = threadIdx.x;
+  if (j == 0 && a.slots) {
+    // the layout of parents 0 and 1, tested on every parent by k_micro_count
+    const int64_t t0 = a.tok_offset[0], c0 = a.const_offset[0];
+    a.slots[0] = 1;
+    a.slots[1] = t0;
+    a.slots[2] = a.n > 1 ? a.tok_offset[1] - t0 : 0;
+    a.slots[3] = c0;
+    a.slots[4] = a.n > 1 ? a.const_offset[1] - c0 : 0;
+  }
   if (j < a.sample) {
     Stream s(a.seed, MICRO_INDEX, a.generation, a.tag);
     f[j] = a.fitness[below(s.draw(j), uint32_t(a.n))];
@@ -277,6 +290,9 @@ __global__ void __launch_bounds__(MICRO_BLOCK) k_micro_count(MicroArgs a) {
   const int64_t i = int64_t(blockIdx.x) * MICRO_BLOCK + threadIdx.x;
   const double tau = *a.tau;
   const bool keep = i < a.n && survives(a.fitness[i], tau);
+  if (a.slots && i < a.n &&
+      (a.tok_offset[i] != a.slots[1] + i * a.slots[2] || a.const_offset[i] != a.slots[3] + i * a.slots[4]))
+    a.slots[0] = 0;  // (every writer stores the same value)
   const int n = __popcll(__builtin_amdgcn_ballot_w64(keep));
   if ((threadIdx.x & 63) == 0) wave_n[threadIdx.x >> 6] = n;
   __syncthreads();
@@ -323,6 +339,9 @@ __global__ void __launch_bounds__(MICRO_BLOCK) k_micro_scatter(MicroArgs a) {
   const int64_t i = int64_t(blockIdx.x) * MICRO_BLOCK + threadIdx.x;
   const double tau = *a.tau;
   const bool keep = i < a.n && survives(a.fitness[i], tau);
+  if (a.slots && i < a.n &&
+      (a.tok_offset[i] != a.slots[1] + i * a.slots[2] || a.const_offset[i] != a.slots[3] + i * a.slots[4]))
+    a.slots[0] = 0;  // (every writer stores the same value)
   const uint64_t m = __builtin_amdgcn_ballot_w64(keep);
   if ((threadIdx.x & 63) == 0) wave_n[threadIdx.x >> 6] = __popcll(m);
   __syncthreads();

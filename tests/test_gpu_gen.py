@@ -183,6 +183,49 @@ def test_microcosm_children_bit_exact(kw, n_children):
     assert 0 < int(ns.cpu()[0]) < 700
 
 
+@pytest.mark.parametrize("break_at", [None, 0, 699])
+def test_microcosm_children_from_slots_bit_exact(break_at):
+    """The same children when the parents sit in fixed slots (regular
+    offsets: the variation kernel computes them instead of reading them),
+    and when one parent's offsets break the slot pattern (first or last
+    parent: every offset read again)."""
+    api = _api()
+    op, ap = _params(api, p_crossover=0.0, p_mutation=1.0)
+    D, n, L = 4, 700, 64
+    ps, fit = _parents(43, n, D)
+    tok = np.zeros((n, L), np.uint16)
+    cst = np.zeros((n, 8), np.float32)
+    for i in range(n):
+        t, c = ps.program(i)
+        tok[i, :len(t)] = t
+        cst[i, :len(c)] = c
+    par = api.DevicePrograms.from_fixed(torch.from_numpy(tok.view(np.int16)).cuda(),
+                                        torch.from_numpy(ps.tok_len.astype(np.int32)).cuda(),
+                                        torch.from_numpy(cst).cuda(),
+                                        torch.from_numpy(ps.const_count.astype(np.int32)).cuda())
+    if break_at is not None:
+        # the parent's tokens and constants copied behind the last slot
+        extra_t = torch.from_numpy(tok[break_at].view(np.int16)).cuda()
+        extra_c = torch.from_numpy(cst[break_at]).cuda()
+        par.tokens = torch.cat([par.tokens, extra_t])
+        par.consts = torch.cat([par.consts, extra_c])
+        par.tok_offset = par.tok_offset.clone()
+        par.const_offset = par.const_offset.clone()
+        par.tok_offset[break_at] = n * L
+        par.const_offset[break_at] = n * 8
+    seed, g = 0x0BAD_5EED_0000_0003, 4
+    s, tau, ns = api.generation_microcosm(par, torch.from_numpy(fit).cuda(), ap, D, seed, g, 900, sample=100,
+                                          keep=0.4, with_selection=True)
+    torch.cuda.synchronize()
+    tk, ln, cs, cc = _slots_to_lists(s)
+    plist_t = [list(ps.program(p)[0]) for p in range(n)]
+    plist_c = [list(ps.program(p)[1]) for p in range(n)]
+    ref = gp.to_fixed(gp.generation_microcosm(plist_t, plist_c, fit, D, op, seed, g, 900, sample=100, keep=0.4),
+                      op.max_len, op.max_consts)
+    assert np.array_equal(ln, ref[1]) and np.array_equal(tk, ref[0])
+    assert np.array_equal(cc, ref[3]) and np.array_equal(cs.view(np.uint32), ref[2].view(np.uint32))
+
+
 def test_microcosm_no_survivor_uses_every_parent():
     """All-NaN fitness: no survivor (count 0), children drawn from every parent."""
     api = _api()
