@@ -214,7 +214,7 @@ beagle_status prepare(char* ws, const beagle_programs* P, const beagle_dataset* 
   // mark passes return at once when the ranges are sorted and disjoint),
   // then programs of at most 64 tokens, then the ones longer than that
   const uint32_t pgrid = uint32_t((P->n_programs + 255) / 256);
-  const uint32_t sgrid = uint32_t((L.Mp + 255) / 256);
+  const uint32_t sgrid = uint32_t(std::min<int64_t>((L.Mp + 255) / 256, 1 << 16));
   hipLaunchKernelGGL(bgl::k_stage_and_check, dim3(sgrid + pgrid), dim3(256), 0, s, sa, pa, sgrid);
   hipLaunchKernelGGL(bgl::k_layout_fill, dim3(1024), dim3(256), 0, s, pa);
   hipLaunchKernelGGL(bgl::k_layout_mark, dim3(std::min<uint32_t>(pgrid, 1024)), dim3(256), 0, s, pa);

@@ -1289,8 +1289,10 @@ __device__ static void stage_case(const StageArgs& a, int64_t i) {
 // rest check program pairs.
 __global__ void k_stage_and_check(StageArgs sa, PrepareArgs pa, uint32_t stage_blocks) {
   if (blockIdx.x < stage_blocks) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < sa.Mp) stage_case(sa, i);
+    // (grid-stride: the staging part of the grid is capped)
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < sa.Mp;
+         i += int64_t(stage_blocks) * blockDim.x)
+      stage_case(sa, i);
   } else {
     const int64_t p = int64_t(blockIdx.x - stage_blocks) * blockDim.x + threadIdx.x;
     if (p < pa.n_programs) layout_pair(pa, int(p));
