@@ -675,25 +675,31 @@ __global__ void __launch_bounds__(256) k_eval_resident(EvalArgs a) {
   // same-address atomic per program would serialise at the counter).
   const int32_t count = __builtin_amdgcn_readfirstlane(a.class_count[CLS]);
   const int32_t* list = a.class_list + int64_t(CLS) * a.n_total;
-  if (count <= 4 * n_waves) {
-    const int32_t wave_id = __builtin_amdgcn_readfirstlane(int32_t(blockIdx.x) * 4 + int32_t(threadIdx.x >> 6));
-    for (int32_t item = wave_id; item < count; item += n_waves) {
-      const int p = __builtin_amdgcn_readfirstlane(list[item] - a.prog_begin);
-      if (p >= 0 && p < a.n_programs) eval_wave_resident<KIND, K, CLS>(a, p, xres, passes);  // else another slice's
-    }
-    return;
-  }
+  // Both walks in one loop around one call of the per-program routine (two
+  // inlined copies of the interpreter would not fit the instruction cache
+  // together): the static walk steps by the wave count from the wave's
+  // index; the claimed walk steps by one through each claimed batch and
+  // claims the next one at its end.  Every value deciding a branch is
+  // wave-uniform, so the atomic runs on all lanes.
+  const bool claimed = count > 4 * n_waves;
+  const int32_t wave_id = __builtin_amdgcn_readfirstlane(int32_t(blockIdx.x) * 4 + int32_t(threadIdx.x >> 6));
+  int64_t item = claimed ? 0 : wave_id;
+  int64_t end = claimed ? 0 : count;  // the walk's current range [item, end)
+  const int64_t step = claimed ? 1 : n_waves;
   for (;;) {
-    const unsigned long long it = atomicAdd(a.work + CLS, lane == 0 ? (unsigned long long)RESIDENT_BATCH : 0ull);
-    const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(it), 0);
-    const uint32_t hi = __builtin_amdgcn_readlane(uint32_t(it >> 32), 0);
-    const int64_t first = int64_t((uint64_t(hi) << 32) | lo);
-    if (first >= count) break;
-    const int64_t end = first + RESIDENT_BATCH < count ? first + RESIDENT_BATCH : count;
-    for (int64_t item = first; item < end; ++item) {
-      const int p = __builtin_amdgcn_readfirstlane(list[item] - a.prog_begin);
-      if (p >= 0 && p < a.n_programs) eval_wave_resident<KIND, K, CLS>(a, p, xres, passes);  // else another slice's
+    if (item >= end) {
+      if (!claimed) break;
+      const unsigned long long it = atomicAdd(a.work + CLS, lane == 0 ? (unsigned long long)RESIDENT_BATCH : 0ull);
+      const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(it), 0);
+      const uint32_t hi = __builtin_amdgcn_readlane(uint32_t(it >> 32), 0);
+      const int64_t first = int64_t((uint64_t(hi) << 32) | lo);
+      if (first >= count) break;
+      item = first;
+      end = first + RESIDENT_BATCH < count ? first + RESIDENT_BATCH : count;
     }
+    const int p = __builtin_amdgcn_readfirstlane(list[item] - a.prog_begin);
+    if (p >= 0 && p < a.n_programs) eval_wave_resident<KIND, K, CLS>(a, p, xres, passes);  // else another slice's
+    item += step;
   }
 }
 
