@@ -431,7 +431,7 @@ struct Acc {
 //          over the cases where both are valid sum u, sum u^2, sum u*w,
 //          sum w, sum w^2.
 template <int KIND, int K, int S>
-__device__ __forceinline__ void eval_block(const EvalArgs& a, int p, int c, double* red, float* xtile) {
+__device__ __forceinline__ void eval_block(const EvalArgs& a, int p, int c, float* xtile) {
   const ProgMeta m = a.meta[p];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t off = a.tok_offset[p];
@@ -520,17 +520,23 @@ __device__ __forceinline__ void eval_block(const EvalArgs& a, int p, int c, doub
       }
     }
   }
+  // the waves' sums meet in the start of each wave's own tile (its tiles
+  // are done; no LDS beyond the tiles, so that eight workgroups of four
+  // waves fit a CU at D = 5)
   constexpr int NS = kind_sums(KIND);
+  const int wstride = a.D * G * 256;  // floats per wave tile
   double v[MAX_SUMS];
   acc.wave_sums(v);
   if (lane == 0) {
+    double* mine = reinterpret_cast<double*>(xw);
 #pragma unroll
-    for (int j = 0; j < NS; ++j) red[wave * MAX_SUMS + j] = v[j];
+    for (int j = 0; j < NS; ++j) mine[j] = v[j];
   }
   __syncthreads();
   if (threadIdx.x < NS) {
     const int j = threadIdx.x;
-    const double t = ((red[j] + red[MAX_SUMS + j]) + red[2 * MAX_SUMS + j]) + red[3 * MAX_SUMS + j];
+    auto red = [&](int w) { return reinterpret_cast<const double*>(xtile + w * wstride)[j]; };
+    const double t = ((red(0) + red(1)) + red(2)) + red(3);
     a.part[(int64_t(j) * a.n_chunks + c) * a.n_programs + p] = t;
   }
   __syncthreads();
@@ -553,9 +559,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CLS ==
 k_eval_class(EvalArgs a) {
   constexpr int S = class_stack(CLS);
   constexpr int K = class_k(CLS, KV);
-  __shared__ double red[EVAL_WAVES * MAX_SUMS];
-  __shared__ long long s_item;
   extern __shared__ float xtile[];
+  // the claimed item passes through the tiles' LDS (no tile is in use
+  // between items)
+  long long* s_item = reinterpret_cast<long long*>(xtile);
   const int32_t count = a.class_count[CLS];
   const int64_t items = int64_t(count) * a.n_chunks;
   const int32_t* list = a.class_list + int64_t(CLS) * a.n_total;
@@ -564,15 +571,15 @@ k_eval_class(EvalArgs a) {
   // would serialise at the counter for longer than the work takes
   if (int64_t(blockIdx.x) >= items) return;
   for (;;) {
-    if (threadIdx.x == 0) s_item = (long long)atomicAdd(a.work + CLS, 1ull);
+    if (threadIdx.x == 0) *s_item = (long long)atomicAdd(a.work + CLS, 1ull);
     __syncthreads();
-    const int64_t it = s_item;
+    const int64_t it = *s_item;
     __syncthreads();
     if (it >= items) break;  // uniform across the workgroup
     const int c = int(it / count);
     const int p = list[it % count] - a.prog_begin;
     if (p < 0 || p >= a.n_programs) continue;  // a program of another slice
-    eval_block<KIND, K, S>(a, p, c, red, xtile);
+    eval_block<KIND, K, S>(a, p, c, xtile);
   }
 }
 
@@ -715,17 +722,16 @@ template <int KIND, int CLS, int KV>
 __global__ void __launch_bounds__(256) k_eval_batch(BatchArgs b, int vl) {
   constexpr int S = class_stack(CLS);
   constexpr int K = class_k(CLS, KV);
-  __shared__ double red[EVAL_WAVES * MAX_SUMS];
-  __shared__ long long s_item;
   extern __shared__ float xtile[];
+  long long* s_item = reinterpret_cast<long long*>(xtile);  // (as in k_eval_class)
   const int64_t* off = b.item_off + int64_t(vl) * (b.n_problems + 1);
   const int64_t items = off[b.n_problems];
   if (int64_t(blockIdx.x) >= items) return;  // (as in k_eval_class)
   int lo = 0;  // the problem of the previous item (a lower bound for the next)
   for (;;) {
-    if (threadIdx.x == 0) s_item = (long long)atomicAdd(b.work + vl, 1ull);
+    if (threadIdx.x == 0) *s_item = (long long)atomicAdd(b.work + vl, 1ull);
     __syncthreads();
-    const uint64_t raw = uint64_t(s_item);
+    const uint64_t raw = uint64_t(*s_item);
     __syncthreads();
     const int64_t it = int64_t((uint64_t(uint32_t(__builtin_amdgcn_readfirstlane(int(raw >> 32)))) << 32) |
                                uint32_t(__builtin_amdgcn_readfirstlane(int(raw))));
@@ -772,7 +778,7 @@ __global__ void __launch_bounds__(256) k_eval_batch(BatchArgs b, int vl) {
     a.work = nullptr;
     a.n_total = P.prep.n_programs;
     a.prog_begin = 0;
-    eval_block<KIND, K, S>(a, p, c, red, xtile);
+    eval_block<KIND, K, S>(a, p, c, xtile);
   }
 }
 
