@@ -79,6 +79,10 @@ __device__ static void dtape_words(const uint32_t* code, uint32_t* aux, int L, S
 // list (-1: an invalid program joins none).
 struct ListIds {
   int cls = -1, lc = -1;
+  // the wave decoders' program header fields (ProgMeta): status | need << 8
+  // | len << 16, and the variable mask (shift is 0 after decoding)
+  int32_t head = 0;
+  uint32_t vmask = 0u;
 };
 
 // Whether program p holds its token range (and, for the adjoint, its
@@ -535,8 +539,19 @@ __device__ __forceinline__ int scan_add(int v) {
   v += dpp<0x143, 0xC>(v);
   return v;
 }
+// Inclusive prefix maximum of non-negative values, the same pattern (zero
+// never changes a result).
+__device__ __forceinline__ int scan_max(int v) {
+  v = max(v, dpp<0x111, 0xF>(v));
+  v = max(v, dpp<0x112, 0xF>(v));
+  v = max(v, dpp<0x114, 0xF>(v));
+  v = max(v, dpp<0x118, 0xF>(v));
+  v = max(v, dpp<0x142, 0xA>(v));
+  v = max(v, dpp<0x143, 0xC>(v));
+  return v;
+}
 // Maximum / bitwise OR over the 64 lanes of non-negative values, the same
-// pattern (zero never changes a result), read from lane 63 (uniform).
+// pattern, read from lane 63 (uniform).
 __device__ __forceinline__ int wave_max(int v) {
   v = max(v, dpp<0x111, 0xF>(v));
   v = max(v, dpp<0x112, 0xF>(v));
@@ -579,18 +594,15 @@ struct WaveDecLds {
 // (wave-uniform).
 template <bool ADJ>
 __device__ static ListIds decode_wave(const PrepareArgs& a, int p, int64_t off, int32_t L, int64_t coff, int32_t cc,
-                                      uint32_t tok, int lay_tok, int lay_const, WaveDecLds& sh) {
+                                      int hstat, uint32_t tok, int lay_tok, int lay_const, WaveDecLds& sh) {
   using namespace wdec;
   const int lane = lane_id();
-  int status = BEAGLE_PROG_OK;
+  // (hstat: the header's own checks, made before the call)
+  int status = hstat;
   int need_root = 0, L_dec = 0;
   uint32_t vmask = 0;
   bool ext = false;
-  if (L <= 0) {
-    status = L == 0 ? BEAGLE_PROG_EMPTY : BEAGLE_PROG_BAD_LAYOUT;
-  } else if (off < 0 || off + L > a.n_tokens || cc < 0 || (cc > 0 && (coff < 0 || coff + cc > a.n_consts))) {
-    status = BEAGLE_PROG_BAD_LAYOUT;
-  } else if (lay_tok | lay_const) {
+  if (status == BEAGLE_PROG_OK && (lay_tok | lay_const)) {
     // ranges not sorted and disjoint: every slot must carry p as its owner
     bool mine = true;
     if (lay_tok) mine = __builtin_amdgcn_ballot_w64(lane < L && a.owner[off + lane] != p) == 0;
@@ -648,17 +660,25 @@ __device__ static ListIds decode_wave(const PrepareArgs& a, int p, int64_t off, 
       const int s_prev = from(st, lane > 0 ? lane - 1 : 0);  // start of the right operand
       const int lch = s_prev - 1;                              // left child (binary)
       constexpr int NEED_UNKNOWN = 1024;
+      const bool is_un = ar == 1, is_bin = ar == 2;
+      // A unary operator's need is its operand's, and a run of unary
+      // operators stands on consecutive tokens (postfix), so a child's need
+      // is read at the bottom of its run: the last non-unary token at or
+      // before it (bot: that token + 1).  The relaxation then steps over
+      // binary levels only.
+      const int bot = scan_max(is_un ? 0 : lane + 1);
+      const int src_r = max(from(bot, lane > 0 ? lane - 1 : 0) - 1, 0);
+      const int src_l = max(from(bot, lch > 0 ? lch : 0) - 1, 0);
       int need = ar == 0 ? 1 : NEED_UNKNOWN;
       int nr = 0, nl = 0;
-      const int src_r = lane > 0 ? lane - 1 : 0, src_l = lch > 0 ? lch : 0;
-      const bool is_un = ar == 1, is_bin = ar == 2;
       for (;;) {
         nr = from(need, src_r);
         nl = from(need, src_l);
         const int nb2 = max(nl, nr) + int(nl == nr);
-        need = sel(is_un, nr, sel(is_bin, nb2, need));
-        if ((__builtin_amdgcn_ballot_w64(need >= 64) & actm) == 0) break;
+        need = sel(is_bin, nb2, need);
+        if ((__builtin_amdgcn_ballot_w64(!is_un & (need >= 64)) & actm) == 0) break;
       }
+      need = sel(is_un, from(need, max(bot - 1, 0)), need);
       need_root = lane_value(need, L - 1);
       // ---- output order: parents tell children their offset within the
       // parent's output range; the root's range starts at 0
@@ -818,30 +838,14 @@ __device__ static ListIds decode_wave(const PrepareArgs& a, int p, int64_t off, 
         if (ext && ids.cls == 0) ids.cls = 1;
         ids.lc = lc_short;
       }
-      if (lane == 0) {
-        ProgMeta m;
-        m.status = status;
-        m.need = need_root;
-        m.len = L_dec;
-        m.shift = 0.0f;
-        m.vmask = status == BEAGLE_PROG_OK ? vmask : 0u;
-        a.meta[p] = m;
-        if (a.status_out) a.status_out[p] = int8_t(status);
-      }
+      ids.head = status | (need_root << 8) | (L_dec << 16);
+      ids.vmask = status == BEAGLE_PROG_OK ? vmask : 0u;
       return ids;
     }
   }
-  if (lane == 0) {
-    ProgMeta m;
-    m.status = status;
-    m.need = 0;
-    m.len = 0;
-    m.shift = 0.0f;
-    m.vmask = 0u;
-    a.meta[p] = m;
-    if (a.status_out) a.status_out[p] = int8_t(status);
-  }
-  return ListIds{};
+  ListIds ids;
+  ids.head = status;
+  return ids;
 }
 
 // ---- several short programs per wave (evaluation only) -------------------
@@ -861,6 +865,15 @@ __device__ __forceinline__ int seg_scan_add(int v) {
   v += dpp<0x114, 0xF>(v);
   v += dpp<0x118, 0xF>(v);
   if constexpr (SEG >= 32) v += dpp<0x142, 0xA>(v);
+  return v;
+}
+template <int SEG>
+__device__ __forceinline__ int seg_scan_max(int v) {
+  v = max(v, dpp<0x111, 0xF>(v));
+  v = max(v, dpp<0x112, 0xF>(v));
+  v = max(v, dpp<0x114, 0xF>(v));
+  v = max(v, dpp<0x118, 0xF>(v));
+  if constexpr (SEG >= 32) v = max(v, dpp<0x142, 0xA>(v));
   return v;
 }
 // maximum / OR of non-negative values over the segment, on every lane
@@ -888,7 +901,7 @@ __device__ __forceinline__ uint32_t seg_or(uint32_t u, int last_lane) {
 
 template <int SEG>
 __device__ static ListIds decode_seg(const PrepareArgs& a, int p, int64_t off, int32_t L, int64_t coff, int32_t cc,
-                                     uint32_t tok, int lay_tok, WaveDecLds& sh) {
+                                     int hstat, uint32_t tok, int lay_tok, WaveDecLds& sh) {
   using namespace wdec;
   static_assert(SEG == 16 || SEG == 32, "segments of 16 or 32 lanes");
   constexpr int LOG = SEG == 16 ? 4 : 5;
@@ -899,11 +912,7 @@ __device__ static ListIds decode_seg(const PrepareArgs& a, int p, int64_t off, i
   // v of position i of this lane's segment (0 <= i < SEG where used)
   auto sfrom = [&](int v, int i) { return from(v, sb + i); };
   auto segbits = [&](uint64_t m) { return (m >> sb) & SEGMASK; };
-  int status = BEAGLE_PROG_OK;
-  if (L <= 0)
-    status = L == 0 ? BEAGLE_PROG_EMPTY : BEAGLE_PROG_BAD_LAYOUT;
-  else if (off < 0 || off + L > a.n_tokens || cc < 0 || (cc > 0 && (coff < 0 || coff + cc > a.n_consts)))
-    status = BEAGLE_PROG_BAD_LAYOUT;
+  int status = hstat;
   if (lay_tok) {
     // ranges not sorted and disjoint: every slot must carry p as its owner
     const bool bad = status == BEAGLE_PROG_OK && sl < L && a.owner[off + sl] != p;
@@ -952,17 +961,21 @@ __device__ static ListIds decode_seg(const PrepareArgs& a, int p, int64_t off, i
   const int s_prev = sfrom(st, sl > 0 ? sl - 1 : 0);
   const int lch = s_prev - 1;
   constexpr int NEED_UNKNOWN = 1024;
+  const bool is_un = ar == 1, is_bin = ar == 2;
+  // children's needs read at the bottom of their runs of unary operators
+  const int bot = seg_scan_max<SEG>(is_un ? 0 : sl + 1);
+  const int src_r = max(sfrom(bot, sl > 0 ? sl - 1 : 0) - 1, 0);
+  const int src_l = max(sfrom(bot, lch > 0 ? lch : 0) - 1, 0);
   int need = ar == 0 ? 1 : NEED_UNKNOWN;
   int nr = 0, nl = 0;
-  const int src_r = sl > 0 ? sl - 1 : 0, src_l = lch > 0 ? lch : 0;
-  const bool is_un = ar == 1, is_bin = ar == 2;
   for (;;) {
     nr = sfrom(need, src_r);
     nl = sfrom(need, src_l);
     const int nb2 = max(nl, nr) + int(nl == nr);
-    need = sel(is_un, nr, sel(is_bin, nb2, need));
-    if (__builtin_amdgcn_ballot_w64(live & (need >= 64)) == 0) break;
+    need = sel(is_bin, nb2, need);
+    if (__builtin_amdgcn_ballot_w64(live & !is_un & (need >= 64)) == 0) break;
   }
+  need = sel(is_un, sfrom(need, max(bot - 1, 0)), need);
   int need_root = sfrom(need, L >= 1 ? L - 1 : 0);
   // ---- output order (parents' lanes as byte addresses)
   const bool swap = (ar == 2) & (nr > nl);
@@ -1035,16 +1048,9 @@ __device__ static ListIds decode_seg(const PrepareArgs& a, int p, int64_t off, i
     ids.cls = need_class(need_root);
     if (ext && ids.cls == 0) ids.cls = 1;
   }
-  if (sl == 0) {
-    ProgMeta m;
-    m.status = status;
-    m.need = ok ? need_root : 0;  // (a program stopped by its length keeps its need)
-    m.len = status == BEAGLE_PROG_OK ? L_dec : 0;
-    m.shift = 0.0f;
-    m.vmask = status == BEAGLE_PROG_OK ? vmask : 0u;
-    a.meta[p] = m;
-    if (a.status_out) a.status_out[p] = int8_t(status);
-  }
+  // (a program stopped by its length keeps its need)
+  ids.head = status | ((ok ? need_root : 0) << 8) | ((status == BEAGLE_PROG_OK ? L_dec : 0) << 16);
+  ids.vmask = status == BEAGLE_PROG_OK ? vmask : 0u;
   return ids;
 }
 
@@ -1067,8 +1073,11 @@ __device__ __forceinline__ int64_t from64(int64_t v, int src) {
   return int64_t((uint64_t(hi) << 32) | lo);
 }
 
+#ifndef PREP_WAVE_WPE
+#define PREP_WAVE_WPE 8
+#endif
 template <bool ADJ>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ADJ ? 1 : 8))) k_prepare_wave(PrepareArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ADJ ? 1 : PREP_WAVE_WPE))) k_prepare_wave(PrepareArgs a) {
   __shared__ WaveDecLds lds[4];
   const int lane = int(threadIdx.x & 63u), w = int(threadIdx.x >> 6);
   const int ppw = a.wave_programs;
@@ -1080,18 +1089,28 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ADJ ? 
   const int64_t hcoff = have ? a.const_offset[pl] : 0;
   const int32_t hcc = have ? a.const_count[pl] : 0;
   const int nb = base < a.n_programs ? int(a.n_programs - base < ppw ? a.n_programs - base : ppw) : 0;
+  // the header's own checks (lane j: program j): no tokens, or token or
+  // constant range outside its array
+  const int hst = hL == 0 ? BEAGLE_PROG_EMPTY
+                  : hL < 0 || hoff < 0 || hoff + hL > a.n_tokens || hcc < 0 ||
+                            (hcc > 0 && (hcoff < 0 || hcoff + hcc > a.n_consts))
+                      ? BEAGLE_PROG_BAD_LAYOUT
+                      : BEAGLE_PROG_OK;
+  const uint64_t fetch_ok = __builtin_amdgcn_ballot_w64(hst == BEAGLE_PROG_OK && hL <= PREP_NARROW);
   // the lane's token of program j, where program j is decoded here and its
-  // token range lies within the array (else 0: the decoder reports it)
+  // header passed (else 0: the decoder reports the header's status)
   auto fetch = [&](int j) -> uint32_t {
     const int32_t L = __builtin_amdgcn_readlane(hL, j);
-    const int64_t off = lane64(hoff, j);
-    const bool ok = L >= 1 && L <= PREP_NARROW && off >= 0 && off + L <= a.n_tokens && lane < L;
-    return ok ? uint32_t(a.tokens[off + lane]) : 0u;
+    const bool ok = ((fetch_ok >> j) & 1u) && lane < L;
+    return ok ? uint32_t(a.tokens[lane64(hoff, j) + lane]) : 0u;
   };
   // the disjoint-ranges flags (set before this kernel)
   const int lay_tok = a.layout ? a.layout[0] : 0;
   const int lay_const = a.layout && ADJ ? a.layout[1] : 0;
   int cls = -1, lc = -1;
+  // program j's header fields, held by lane j and stored together at the end
+  int32_t head = 0;
+  uint32_t vmask = 0u;
   bool defer = false;
   if constexpr (ADJ) {
     uint32_t t_next = nb > 0 ? fetch(0) : 0u;
@@ -1104,9 +1123,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ADJ ? 
         continue;
       }
       const ListIds ids = decode_wave<ADJ>(a, int(base + j), lane64(hoff, j), L, lane64(hcoff, j),
-                                      __builtin_amdgcn_readlane(hcc, j), t, lay_tok, lay_const, lds[w]);
+                                           __builtin_amdgcn_readlane(hcc, j), __builtin_amdgcn_readlane(hst, j), t,
+                                           lay_tok, lay_const, lds[w]);
       cls = wdec::sel(lane == j, ids.cls, cls);
       lc = wdec::sel(lane == j, ids.lc, lc);
+      head = wdec::sel(lane == j, ids.head, head);
+      vmask = wdec::sel(lane == j, ids.vmask, vmask);
     }
   } else {
     // Programs of at most 16 tokens four to a wave, then (with those left
@@ -1122,37 +1144,42 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ADJ ? 
       m &= m - 1;
       return j;
     };
-    // tokens of program jj (this lane's segment) at position sl
-    auto fetch_seg = [&](int jj, int sl, int sz) -> uint32_t {
-      const int32_t Lp = wdec::from(hL, jj);
+    // tokens of program jj (this lane's segment) at position sl (the
+    // lane reads run on every lane, before the lane-dependent load: a read
+    // from a lane outside the active ones returns 0)
+    auto fetch_seg = [&](int jj, int sl) -> uint32_t {
+      const int hs = wdec::from(hst, jj), Lp = wdec::from(hL, jj);
       const int64_t offp = from64(hoff, jj);
-      const bool okp = Lp >= 1 && Lp <= sz && offp >= 0 && offp + Lp <= a.n_tokens && sl < Lp;
-      return okp ? uint32_t(a.tokens[offp + sl]) : 0u;
+      return (hs == BEAGLE_PROG_OK) & (sl < Lp) ? uint32_t(a.tokens[offp + sl]) : 0u;
     };
     while (__popcll(m16) >= 4) {
       const int j0 = take(m16), j1 = take(m16), j2 = take(m16), j3 = take(m16);
       const int jj = wdec::pick4(lane >> 4, j0, j1, j2, j3);
-      const uint32_t t = fetch_seg(jj, lane & 15, 16);
-      const ListIds ids = decode_seg<16>(a, int(base + jj), from64(hoff, jj), wdec::from(hL, jj),
-                                         from64(hcoff, jj), wdec::from(hcc, jj), t, lay_tok, lds[w]);
-      // program j_s's lists come from its segment's first lane
+      const uint32_t t = fetch_seg(jj, lane & 15);
+      const ListIds ids = decode_seg<16>(a, int(base + jj), from64(hoff, jj), wdec::from(hL, jj), from64(hcoff, jj),
+                                         wdec::from(hcc, jj), wdec::from(hst, jj), t, lay_tok, lds[w]);
+      // program j_s's lists and header come from its segment's first lane
       const int s = wdec::sel(lane == j0, 0, wdec::sel(lane == j1, 1, wdec::sel(lane == j2, 2, 3)));
-      const int got = wdec::from(ids.cls, s * 16);
-      cls = wdec::sel((lane == j0) | (lane == j1) | (lane == j2) | (lane == j3), got, cls);
+      const bool mine = (lane == j0) | (lane == j1) | (lane == j2) | (lane == j3);
+      cls = wdec::sel(mine, wdec::from(ids.cls, s * 16), cls);
+      head = wdec::sel(mine, wdec::from(ids.head, s * 16), head);
+      vmask = wdec::sel(mine, uint32_t(wdec::from(int(ids.vmask), s * 16)), vmask);
     }
     m32 |= m16;
     while (__popcll(m32) >= 2) {
       const int j0 = take(m32), j1 = take(m32);
       const int jj = lane < 32 ? j0 : j1;
-      const uint32_t t = fetch_seg(jj, lane & 31, 32);
-      const ListIds ids = decode_seg<32>(a, int(base + jj), from64(hoff, jj), wdec::from(hL, jj),
-                                         from64(hcoff, jj), wdec::from(hcc, jj), t, lay_tok, lds[w]);
-      const int got = wdec::from(ids.cls, lane == j0 ? 0 : 32);
-      cls = wdec::sel((lane == j0) | (lane == j1), got, cls);
+      const uint32_t t = fetch_seg(jj, lane & 31);
+      const ListIds ids = decode_seg<32>(a, int(base + jj), from64(hoff, jj), wdec::from(hL, jj), from64(hcoff, jj),
+                                         wdec::from(hcc, jj), wdec::from(hst, jj), t, lay_tok, lds[w]);
+      const int src = lane == j0 ? 0 : 32;
+      const bool mine = (lane == j0) | (lane == j1);
+      cls = wdec::sel(mine, wdec::from(ids.cls, src), cls);
+      head = wdec::sel(mine, wdec::from(ids.head, src), head);
+      vmask = wdec::sel(mine, uint32_t(wdec::from(int(ids.vmask), src)), vmask);
     }
     rest |= m32;
-    // one at a time, each program's tokens loaded while the previous one is
-    // decoded
+    // one at a time
     int j = rest ? take(rest) : -1;
     uint32_t t_next = j >= 0 ? fetch(j) : 0u;
     while (j >= 0) {
@@ -1164,13 +1191,28 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ADJ ? 
         defer |= lane == j;
       } else {
         const ListIds ids = decode_wave<false>(a, int(base + j), lane64(hoff, j), L, lane64(hcoff, j),
-                                               __builtin_amdgcn_readlane(hcc, j), t, lay_tok, 0, lds[w]);
+                                               __builtin_amdgcn_readlane(hcc, j), __builtin_amdgcn_readlane(hst, j),
+                                               t, lay_tok, 0, lds[w]);
         cls = wdec::sel(lane == j, ids.cls, cls);
+        head = wdec::sel(lane == j, ids.head, head);
+        vmask = wdec::sel(lane == j, ids.vmask, vmask);
       }
       j = jn;
     }
   }
   const int p = int(base + lane);  // (lanes without a program append nothing)
+  // the headers of the programs decoded here (a long program's header is
+  // written by k_prepare_long)
+  if (lane < nb && !defer) {
+    ProgMeta m;
+    m.status = head & 0xFF;
+    m.need = (head >> 8) & 0xFF;
+    m.len = head >> 16;
+    m.shift = 0.0f;
+    m.vmask = vmask;
+    a.meta[p] = m;
+    if (a.status_out) a.status_out[p] = int8_t(m.status);
+  }
   __shared__ int32_t cnt[4][8], lbase[8];
   block_append<1, 4>(defer ? 0 : -1, p, a.long_count, a.long_list, 0, cnt, lbase);
   __syncthreads();
