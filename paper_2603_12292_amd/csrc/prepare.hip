@@ -582,6 +582,37 @@ __device__ __forceinline__ int lane_value(int v, int lane) { return __builtin_am
 
 }  // namespace wdec
 
+// Handlers of a decoded word by its kind.  Key k: a binary operator word
+// (k = 0..3 and 18, 19 for ADD..DIV, RSUB, RDIV), a unary operator word (k =
+// its opcode), a VAR or CONST push (9, 10), a fused pair (20 + 6 * [CONST] +
+// the pair's binary operator).  Entry: the handler (bits 0..7, plus the stack
+// size when bit 8 is set), the small-stack handler (bits 9..16 plus the stack
+// size) for stack sizes below bits 17..19 (I0_NONE from there on).
+__device__ static uint32_t word_entry(uint32_t k) {
+  uint32_t h, step, i0, lim;
+  if (k < 4u || k == 18u || k == 19u) {
+    const uint32_t bo = k < 4u ? k : k - 14u;
+    h = H_BIN + 15u * bo - 2u, step = 1u, i0 = I0_BIN + 3u * bo - 2u, lim = 5u;
+  } else if (k == OP_VAR || k == OP_CONST) {
+    h = k == OP_VAR ? H_VAR : H_CONST, step = 0u, i0 = k == OP_VAR ? I0_PUSH_VAR : I0_PUSH_CONST, lim = 4u;
+  } else if (k < 20u) {
+    const uint32_t u = unary_index(k);
+    h = H_UN + u, step = 0u, i0 = I0_UN + 4u * u - 1u, lim = u < U_FIRST_EXT ? 5u : 0u;
+  } else {
+    const uint32_t f = k - 20u;  // 6 * [CONST] + operator
+    h = H_FUSED + f, step = 0u, i0 = I0_FUSED + 3u * f - 1u, lim = 4u;
+  }
+  return h | (step << 8) | (i0 << 9) | (lim << 17);
+}
+// The word of an output token from its table key and the stack size n
+// before it (the handler fields; operand and slot are added by the caller).
+__device__ __forceinline__ uint32_t word_handlers(const uint32_t* wt, uint32_t key, uint32_t n) {
+  const uint32_t te = wt[key & 31u];
+  const uint32_t h = (te & 0xFFu) + ((te & 0x100u) ? n : 0u);
+  const uint32_t i0 = n < (te >> 17) ? ((te >> 9) & 0xFFu) + n : I0_NONE;
+  return h | (i0 << 24);
+}
+
 // Per-wave LDS of the wave decoder.
 struct WaveDecLds {
   uint32_t a[64];
@@ -594,7 +625,8 @@ struct WaveDecLds {
 // (wave-uniform).
 template <bool ADJ>
 __device__ static ListIds decode_wave(const PrepareArgs& a, int p, int64_t off, int32_t L, int64_t coff, int32_t cc,
-                                      int hstat, uint32_t tok, int lay_tok, int lay_const, WaveDecLds& sh) {
+                                      int hstat, uint32_t tok, int lay_tok, int lay_const, WaveDecLds& sh,
+                                      const uint32_t* wt) {
   using namespace wdec;
   const int lane = lane_id();
   // (hstat: the header's own checks, made before the call)
@@ -734,17 +766,10 @@ __device__ static ListIds decode_wave(const PrepareArgs& a, int p, int64_t off, 
       const uint32_t u = unary_index(o_op);
       const uint32_t isc1 = isc ? 1u : 0u;
       const int kind = fused ? 0 : o_term ? 1 : o_bin ? 2 : 3;
-      const uint32_t h = pick4(kind, H_FUSED + 6u * isc1 + ob, isv ? H_VAR : H_CONST, H_BIN + 15u * bo + (un - 2u),
-                               H_UN + u);
-      const uint32_t i0_f = I0_FUSED + 3u * (6u * isc1 + ob) + (un - 1u);
-      const uint32_t i0_t = (isv ? I0_PUSH_VAR : I0_PUSH_CONST) + un;
-      const uint32_t i0_b = I0_BIN + 3u * bo + (un - 2u);
-      const uint32_t i0_u = I0_UN + 4u * u + (un - 1u);
-      const uint32_t i0 = pick4(kind, sel(n <= 3, i0_f, I0_NONE), sel(n <= 3, i0_t, I0_NONE), sel(n <= 4, i0_b, I0_NONE),
-                                sel((n <= 4) & (u < U_FIRST_EXT), i0_u, I0_NONE));
+      const uint32_t key = fused ? 20u + 6u * isc1 + ob : o_op >= 100u ? o_op - 86u : o_op;
       const uint32_t wslot = n > 0 ? un - 1u : 0u;
       const uint32_t warg = o_term ? o_arg : 0u;
-      const uint32_t word = h | (warg << 8) | (wslot << 16) | (i0 << 24);
+      const uint32_t word = word_handlers(wt, key, un) | (warg << 8) | (wslot << 16);
       need_root = nmax > need_root ? nmax : need_root;
       if (need_root > MAX_STACK || L_dec > a.max_words) status = BEAGLE_PROG_TOO_LONG;
       if (ws) {
@@ -901,7 +926,7 @@ __device__ __forceinline__ uint32_t seg_or(uint32_t u, int last_lane) {
 
 template <int SEG>
 __device__ static ListIds decode_seg(const PrepareArgs& a, int p, int64_t off, int32_t L, int64_t coff, int32_t cc,
-                                     int hstat, uint32_t tok, int lay_tok, WaveDecLds& sh) {
+                                     int hstat, uint32_t tok, int lay_tok, WaveDecLds& sh, const uint32_t* wt) {
   using namespace wdec;
   static_assert(SEG == 16 || SEG == 32, "segments of 16 or 32 lanes");
   constexpr int LOG = SEG == 16 ? 4 : 5;
@@ -1021,22 +1046,11 @@ __device__ static ListIds decode_seg(const PrepareArgs& a, int p, int64_t off, i
   int L_dec = __popcll(segbits(wm));
   const uint32_t un = uint32_t(n);
   const uint32_t ob = nxt >= 100u ? nxt - 100u : nxt;
-  const uint32_t bo = o_op >= 100u ? o_op - 100u : o_op;
-  const bool isc = o_op == OP_CONST, isv = o_op == OP_VAR;
-  const uint32_t u = unary_index(o_op);
-  const uint32_t isc1 = isc ? 1u : 0u;
-  const int kind = fused ? 0 : o_term ? 1 : o_bin ? 2 : 3;
-  const uint32_t h = pick4(kind, H_FUSED + 6u * isc1 + ob, isv ? H_VAR : H_CONST, H_BIN + 15u * bo + (un - 2u),
-                           H_UN + u);
-  const uint32_t i0_f = I0_FUSED + 3u * (6u * isc1 + ob) + (un - 1u);
-  const uint32_t i0_t = (isv ? I0_PUSH_VAR : I0_PUSH_CONST) + un;
-  const uint32_t i0_b = I0_BIN + 3u * bo + (un - 2u);
-  const uint32_t i0_u = I0_UN + 4u * u + (un - 1u);
-  const uint32_t i0 = pick4(kind, sel(n <= 3, i0_f, I0_NONE), sel(n <= 3, i0_t, I0_NONE), sel(n <= 4, i0_b, I0_NONE),
-                            sel((n <= 4) & (u < U_FIRST_EXT), i0_u, I0_NONE));
+  const bool isc = o_op == OP_CONST;
+  const uint32_t key = fused ? 20u + 6u * (isc ? 1u : 0u) + ob : o_op >= 100u ? o_op - 86u : o_op;
   const uint32_t wslot = n > 0 ? un - 1u : 0u;
   const uint32_t warg = o_term ? o_arg : 0u;
-  const uint32_t word = h | (warg << 8) | (wslot << 16) | (i0 << 24);
+  const uint32_t word = word_handlers(wt, key, un) | (warg << 8) | (wslot << 16);
   need_root = nmax > need_root ? nmax : need_root;
   if (ok && (need_root > MAX_STACK || L_dec > a.max_words)) status = BEAGLE_PROG_TOO_LONG;
   if (ws) {
@@ -1079,6 +1093,9 @@ __device__ __forceinline__ int64_t from64(int64_t v, int src) {
 template <bool ADJ>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ADJ ? 1 : PREP_WAVE_WPE))) k_prepare_wave(PrepareArgs a) {
   __shared__ WaveDecLds lds[4];
+  __shared__ uint32_t wt[32];
+  if (threadIdx.x < 32) wt[threadIdx.x] = word_entry(threadIdx.x);
+  __syncthreads();
   const int lane = int(threadIdx.x & 63u), w = int(threadIdx.x >> 6);
   const int ppw = a.wave_programs;
   const int64_t base = (int64_t(blockIdx.x) * 4 + w) * ppw;
@@ -1124,7 +1141,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ADJ ? 
       }
       const ListIds ids = decode_wave<ADJ>(a, int(base + j), lane64(hoff, j), L, lane64(hcoff, j),
                                            __builtin_amdgcn_readlane(hcc, j), __builtin_amdgcn_readlane(hst, j), t,
-                                           lay_tok, lay_const, lds[w]);
+                                           lay_tok, lay_const, lds[w], wt);
       cls = wdec::sel(lane == j, ids.cls, cls);
       lc = wdec::sel(lane == j, ids.lc, lc);
       head = wdec::sel(lane == j, ids.head, head);
@@ -1157,7 +1174,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ADJ ? 
       const int jj = wdec::pick4(lane >> 4, j0, j1, j2, j3);
       const uint32_t t = fetch_seg(jj, lane & 15);
       const ListIds ids = decode_seg<16>(a, int(base + jj), from64(hoff, jj), wdec::from(hL, jj), from64(hcoff, jj),
-                                         wdec::from(hcc, jj), wdec::from(hst, jj), t, lay_tok, lds[w]);
+                                         wdec::from(hcc, jj), wdec::from(hst, jj), t, lay_tok, lds[w], wt);
       // program j_s's lists and header come from its segment's first lane
       const int s = wdec::sel(lane == j0, 0, wdec::sel(lane == j1, 1, wdec::sel(lane == j2, 2, 3)));
       const bool mine = (lane == j0) | (lane == j1) | (lane == j2) | (lane == j3);
@@ -1171,7 +1188,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ADJ ? 
       const int jj = lane < 32 ? j0 : j1;
       const uint32_t t = fetch_seg(jj, lane & 31);
       const ListIds ids = decode_seg<32>(a, int(base + jj), from64(hoff, jj), wdec::from(hL, jj), from64(hcoff, jj),
-                                         wdec::from(hcc, jj), wdec::from(hst, jj), t, lay_tok, lds[w]);
+                                         wdec::from(hcc, jj), wdec::from(hst, jj), t, lay_tok, lds[w], wt);
       const int src = lane == j0 ? 0 : 32;
       const bool mine = (lane == j0) | (lane == j1);
       cls = wdec::sel(mine, wdec::from(ids.cls, src), cls);
@@ -1192,7 +1209,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ADJ ? 
       } else {
         const ListIds ids = decode_wave<false>(a, int(base + j), lane64(hoff, j), L, lane64(hcoff, j),
                                                __builtin_amdgcn_readlane(hcc, j), __builtin_amdgcn_readlane(hst, j),
-                                               t, lay_tok, 0, lds[w]);
+                                               t, lay_tok, 0, lds[w], wt);
         cls = wdec::sel(lane == j, ids.cls, cls);
         head = wdec::sel(lane == j, ids.head, head);
         vmask = wdec::sel(lane == j, ids.vmask, vmask);
