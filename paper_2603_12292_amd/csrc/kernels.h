@@ -151,13 +151,17 @@ struct BatchProblem {
 
 // Work lists of a batched evaluation: class 0 wide tile, class 0 narrow
 // tile, class 1, class 2; each split by the problems' variable count into
-// N_DBUCKETS lists (D <= 3, 4..6, more), launched separately so that each
-// launch sizes its input tiles in LDS, and hence its occupancy, for its own
-// largest D instead of the batch's.
+// N_DBUCKETS lists, launched separately so that each launch sizes its input
+// tiles in LDS, and hence its occupancy, for its own largest D instead of the
+// batch's.  The buckets (D <= 5, 6, 7..8, more) end where the workgroups
+// per CU change: the 8-case tiles fit four workgroups up to D = 5 (their
+// registers allow no more), three at 6, two at 7 and 8; the 4-case ones seven
+// up to 5, six at 6, five at 7 and 8, four at 9.
 constexpr int N_LISTS = 4;
-constexpr int N_DBUCKETS = 3;
+constexpr int N_DBUCKETS = 4;
 constexpr int N_BATCH_LISTS = N_LISTS * N_DBUCKETS;
-__host__ __device__ constexpr int d_bucket(int D) { return D <= 3 ? 0 : (D <= 6 ? 1 : 2); }
+static_assert(N_BATCH_LISTS <= 64, "one wave clears and offsets the work lists");
+__host__ __device__ constexpr int d_bucket(int D) { return D <= 5 ? 0 : (D == 6 ? 1 : (D <= 8 ? 2 : 3)); }
 
 struct BatchArgs {
   const BatchProblem* table;
