@@ -221,11 +221,13 @@ beagle_status prepare(char* ws, const beagle_programs* P, const beagle_dataset* 
   if (decoder == BEAGLE_DECODE_THREAD)
     hipLaunchKernelGGL(bgl::k_prepare, dim3((P->n_programs + 63) / 64), dim3(64), 0, s, pa);
   else {
-    // programs per wave: 64 for large populations, fewer when that leaves
-    // under 4096 waves (16 per CU), so that small populations still fill the
-    // chip
+    // programs per wave: 32 for large populations (more, shorter waves end
+    // more evenly; 64 left the last round's slowest waves alone on the chip:
+    // 1-2 % longer at 2^20 programs, though short programs pack better),
+    // fewer when that leaves under 4096 waves (16 per CU), so that small
+    // populations still fill the chip
     const int64_t n = P->n_programs;
-    pa.wave_programs = int32_t(std::max<int64_t>(1, std::min<int64_t>(64, n / 4096)));
+    pa.wave_programs = int32_t(std::max<int64_t>(1, std::min<int64_t>(32, n / 4096)));
     const int64_t waves = (n + pa.wave_programs - 1) / pa.wave_programs;
     hipLaunchKernelGGL(adjoint ? bgl::k_prepare_wave<true> : bgl::k_prepare_wave<false>,
                        dim3(uint32_t((waves + 3) / 4)), dim3(256), 0, s, pa);

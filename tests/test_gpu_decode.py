@@ -161,7 +161,7 @@ def test_decoders_agree_on_gradients(kind):
 @pytest.mark.parametrize("log2n", [16, 18])
 def test_decoders_agree_on_a_large_population(log2n):
     """2^16 and 2^18 programs of the benchmark's shape on 512 cases: many
-    waves and workgroups, 16 and 64 programs per wave of the wave decoder,
+    waves and workgroups, 16 and 32 programs per wave of the wave decoder,
     the list appends of every wave."""
     api = _api()
     cw, ct = _contexts()
