@@ -6,11 +6,11 @@
 #       for FETCH_SIZE, WRITE_SIZE and SQ_INSTS_VALU + SQ_INSTS_SALU over
 #       `profiling run` (benchmark workload + calibration copy); writes
 #       PREFIX.txt and PREFIX_traffic.json
-#   paper_2603_12292_amd/profile.sh paper|adjoint|ragged OUTDIR PREFIX
+#   paper_2603_12292_amd/profile.sh paper|adjoint|ragged|loop OUTDIR PREFIX
 #       kernel trace and counter passes (instruction mix, cycles and waits,
 #       FETCH_SIZE, WRITE_SIZE) over the paper-regime evaluation, the
-#       adjoint or the ragged batch; writes PREFIX.txt and PREFIX.json
-#       (per-kernel means)
+#       adjoint, the ragged batch or the paper's loop at 5e6 individuals;
+#       writes PREFIX.txt and PREFIX.json (per-kernel means)
 #   paper_2603_12292_amd/profile.sh ops OUTDIR PREFIX
 #       SQ_INSTS_VALU + SQ_INSTS_SALU over `profiling ops` (single-operator
 #       program shapes); writes PREFIX.txt
@@ -46,7 +46,7 @@ ops)
   python3 -m paper_2603_12292_amd.profiling summarize-ops --pmc "$out/pmc_ops" --out "$prefix" \
     --command "paper_2603_12292_amd/profile.sh ops OUTDIR PREFIX (rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_SALU -- python3 -m paper_2603_12292_amd.profiling ops)"
   ;;
-paper|adjoint|ragged)
+paper|adjoint|ragged|loop)
   # kernel trace plus two counter passes (instruction mix, then cycles and
   # waits) over the paper-regime evaluation (decode + resident interpreter)
   # or the adjoint of the differentiation workload
@@ -54,6 +54,10 @@ paper|adjoint|ragged)
     run_cmd="python3 -m paper_2603_12292_amd.profiling paper --steps 2"
     kernels="k_prepare,k_eval_resident,k_eval_class,k_finalize,k_stage"
     title="paper regime: 2^20 programs (plain-mid x256, L~U{5..64}, D=5) on 512 cases, MSE"
+  elif [ "$what" = loop ]; then
+    run_cmd="python3 -m paper_2603_12292_amd.profiling loop --generations 3"
+    kernels="k_generation,k_micro,k_init,k_prepare,k_eval_resident,k_eval_class,k_finalize,k_stage,k_target,k_values"
+    title="paper loop: 5e6 individuals (ramped half-and-half, depths 2..5, max length 64, 9 base operators), correlation fitness on 512 cases (D=5), microcosm selection (sample 100, keep 0.5), mutation only; one untimed and 3 profiled generations"
   elif [ "$what" = ragged ]; then
     run_cmd="python3 -m paper_2603_12292_amd.profiling ragged --steps 2"
     kernels="k_eval_batch,k_prepare,k_stage,k_finalize,k_eval_class,k_eval_resident,k_target"

@@ -277,6 +277,32 @@ def run_paper(steps: int, kind: str = "mse"):
     print(f"profiled {steps} evaluation(s) of {w.name}, {kind}", flush=True)
 
 
+def run_loop(generations: int, population: int = 5_000_000):
+    """The paper's loop at its largest population: a ramped half-and-half
+    population (depths 2..5, at most 64 tokens, the nine base operators) of
+    `population` individuals, then `generations` rounds of correlation
+    fitness on the paper-shape case set (512 cases, D = 5), microcosm
+    selection (sample 100, keep 0.5) and mutation-only variation at the same
+    size; one untimed round first."""
+    import torch
+    sys.path.insert(0, ROOT)
+    from paper_2603_12292_amd import api
+    from paper_2603_12292_amd import workloads as wl
+    data = wl.config_paper_shape().data
+    X = torch.from_numpy(data.X).cuda()
+    y = torch.from_numpy(data.y).cuda()
+    params = api.GenParams(tournament=1, p_crossover=0.0, p_mutation=1.0, max_len=64, max_consts=8,
+                           init_depth_min=2, init_depth_max=5)
+    ctx = api.context(0)
+    pop = api.init_population(population, data.D, params, 2612, ctx=ctx)
+    for g in range(generations + 1):
+        fit = api.evaluate(pop.programs(), X, y, "corr", ctx=ctx)
+        pop = api.generation_microcosm(pop.programs(), fit, params, data.D, 2612, g + 1, population,
+                                       sample=100, keep=0.5, ctx=ctx)
+    torch.cuda.synchronize()
+    print(f"profiled {generations} generation(s) of the paper loop at {population} individuals", flush=True)
+
+
 def run_ragged(steps: int):
     """The 64-problem ragged workload: one warm-up and `steps` batched
     evaluations (MSE, one replayed graph), then the same problems one call
@@ -359,6 +385,8 @@ def main():
     s.add_argument("--out", required=True)
     s.add_argument("--command", default="")
     sub.add_parser("ops")
+    lp = sub.add_parser("loop")
+    lp.add_argument("--generations", type=int, default=3)
     rg = sub.add_parser("ragged")
     rg.add_argument("--steps", type=int, default=2)
     pp = sub.add_parser("paper")
@@ -384,6 +412,8 @@ def main():
         run_paper(a.steps, a.kind)
     elif a.cmd == "ragged":
         run_ragged(a.steps)
+    elif a.cmd == "loop":
+        run_loop(a.generations)
     elif a.cmd == "summarize-kernels":
         summarize_kernels(a.trace, a.pmc, a.kernels.split(","), a.out, a.command, a.title)
     elif a.cmd == "summarize-ops":
