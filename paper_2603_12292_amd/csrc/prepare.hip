@@ -550,17 +550,8 @@ __device__ __forceinline__ int scan_max(int v) {
   v = max(v, dpp<0x143, 0xC>(v));
   return v;
 }
-// Maximum / bitwise OR over the 64 lanes of non-negative values, the same
-// pattern, read from lane 63 (uniform).
-__device__ __forceinline__ int wave_max(int v) {
-  v = max(v, dpp<0x111, 0xF>(v));
-  v = max(v, dpp<0x112, 0xF>(v));
-  v = max(v, dpp<0x114, 0xF>(v));
-  v = max(v, dpp<0x118, 0xF>(v));
-  v = max(v, dpp<0x142, 0xA>(v));
-  v = max(v, dpp<0x143, 0xC>(v));
-  return __builtin_amdgcn_readlane(v, 63);
-}
+// Bitwise OR over the 64 lanes, the same pattern, read from lane 63
+// (uniform).
 __device__ __forceinline__ uint32_t wave_or(uint32_t u) {
   int v = int(u);
   v |= dpp<0x111, 0xF>(v);
@@ -572,6 +563,8 @@ __device__ __forceinline__ uint32_t wave_or(uint32_t u) {
   return uint32_t(__builtin_amdgcn_readlane(v, 63));
 }
 __device__ __forceinline__ int first_lane(uint64_t m) { return __ffsll((unsigned long long)m) - 1; }
+// v of the lane below (lane 0: 0), one DPP whole-wave shift
+__device__ __forceinline__ int wave_shr1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, true); }
 // selections whose operands are evaluated first (a conditional expression
 // with computed operands can become a lane-divergent branch)
 template <class T>
@@ -746,11 +739,10 @@ __device__ static ListIds decode_wave(const PrepareArgs& a, int p, int64_t off, 
       const int o_delta = sel(act, sel(o_bin, -1, sel(o_term, 1, 0)), 0);
       const int n_after = scan_add(o_delta);
       const int n = n_after - o_delta;  // stack size before the token
-      const int nmax = wave_max(act ? n_after : 0);
       const uint32_t nxt = uint32_t(from(int(o_op), lane < 63 ? lane + 1 : 63));
       const bool nxt_bin = (lane + 1 < L) & ((nxt < 4u) | (nxt - 100u < 6u));
       const bool fused = act & o_term & (n >= 1) & nxt_bin;
-      const bool absorbed = (lane > 0) & (((__builtin_amdgcn_ballot_w64(fused) << 1) >> lane) & 1u);
+      const bool absorbed = wave_shr1(fused ? 1 : 0) != 0;  // the token before is a fused terminal
       const bool ws = act & !absorbed;
       const uint64_t wm = __builtin_amdgcn_ballot_w64(ws);
       const int E = int(__builtin_amdgcn_mbcnt_hi(uint32_t(wm >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(wm), 0u)));
@@ -770,7 +762,8 @@ __device__ static ListIds decode_wave(const PrepareArgs& a, int p, int64_t off, 
       const uint32_t wslot = n > 0 ? un - 1u : 0u;
       const uint32_t warg = o_term ? o_arg : 0u;
       const uint32_t word = word_handlers(wt, key, un) | (warg << 8) | (wslot << 16);
-      need_root = nmax > need_root ? nmax : need_root;
+      // (the largest stack size in output order equals need_root: the
+      // larger operand first reaches max(a, b + 1) for needs a >= b)
       if (need_root > MAX_STACK || L_dec > a.max_words) status = BEAGLE_PROG_TOO_LONG;
       if (ws) {
         a.code[off + widx] = word;
@@ -901,16 +894,7 @@ __device__ __forceinline__ int seg_scan_max(int v) {
   if constexpr (SEG >= 32) v = max(v, dpp<0x142, 0xA>(v));
   return v;
 }
-// maximum / OR of non-negative values over the segment, on every lane
-template <int SEG>
-__device__ __forceinline__ int seg_max(int v, int last_lane) {
-  v = max(v, dpp<0x111, 0xF>(v));
-  v = max(v, dpp<0x112, 0xF>(v));
-  v = max(v, dpp<0x114, 0xF>(v));
-  v = max(v, dpp<0x118, 0xF>(v));
-  if constexpr (SEG >= 32) v = max(v, dpp<0x142, 0xA>(v));
-  return from(v, last_lane);
-}
+// OR over the segment, on every lane
 template <int SEG>
 __device__ __forceinline__ uint32_t seg_or(uint32_t u, int last_lane) {
   int v = int(u);
@@ -1032,11 +1016,10 @@ __device__ static ListIds decode_seg(const PrepareArgs& a, int p, int64_t off, i
   const int o_delta = sel(live, sel(o_bin, -1, sel(o_term, 1, 0)), 0);
   const int n_after = seg_scan_add<SEG>(o_delta);
   const int n = n_after - o_delta;
-  const int nmax = seg_max<SEG>(live ? n_after : 0, sb + SEG - 1);
   const uint32_t nxt = uint32_t(sfrom(int(o_op), sl < SEG - 1 ? sl + 1 : SEG - 1));
   const bool nxt_bin = (sl + 1 < L) & ((nxt < 4u) | (nxt - 100u < 6u));
   const bool fused = live & o_term & (n >= 1) & nxt_bin;
-  const bool absorbed = (sl > 0) & (((__builtin_amdgcn_ballot_w64(fused) << 1) >> lane) & 1u);
+  const bool absorbed = (sl > 0) & (wave_shr1(fused ? 1 : 0) != 0);
   const bool ws = live & !absorbed;
   const uint64_t wm = __builtin_amdgcn_ballot_w64(ws);
   const uint64_t below = sb == 0 ? 0ull : wm & ((1ull << sb) - 1ull);  // words of the segments below
@@ -1051,7 +1034,6 @@ __device__ static ListIds decode_seg(const PrepareArgs& a, int p, int64_t off, i
   const uint32_t wslot = n > 0 ? un - 1u : 0u;
   const uint32_t warg = o_term ? o_arg : 0u;
   const uint32_t word = word_handlers(wt, key, un) | (warg << 8) | (wslot << 16);
-  need_root = nmax > need_root ? nmax : need_root;
   if (ok && (need_root > MAX_STACK || L_dec > a.max_words)) status = BEAGLE_PROG_TOO_LONG;
   if (ws) {
     a.code[off + widx] = word;
