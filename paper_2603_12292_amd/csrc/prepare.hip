@@ -671,13 +671,17 @@ __device__ static ListIds decode_wave(const PrepareArgs& a, int p, int64_t off, 
         const int u = from(mn[k - 1], lane - w);
         mn[k] = sel((lane >= w) & (u < mn[k - 1]), u, mn[k - 1]);  // min over [lane - 2^k + 1, lane]
       }
-      int q = lane - 1;
+      // descent: r moves down past windows [r - 2^k, r - 1] holding no
+      // smaller depth; a window cut off at position 0 (mn[k] then covers
+      // [0, r - 1]) leaves no earlier position, and r saturates at 0 (at r
+      // = 0 the read lane is unused: any step leaves 0)
+      uint32_t r = uint32_t(lane);
 #pragma unroll
       for (int k = 5; k >= 0; --k) {
-        const int v = from(mn[k], q > 0 ? q : 0);
-        q -= sel((q - (1 << k) + 1 >= 0) & (v >= d), 1 << k, 0);
+        const int v = __builtin_amdgcn_ds_bpermute(int(r << 2) - 4, mn[k]);
+        r = __builtin_elementwise_sub_sat(r, sel(v >= d, 1u << k, 0u));
       }
-      const int st = q + 1;
+      const int st = int(r);
       // ---- register need, bottom-up: leaves 1; unary: the child's;
       // binary: the larger child's, plus one when both are equal.  A need
       // not yet known is NEED_UNKNOWN or more (known ones are at most 7):
@@ -959,13 +963,13 @@ __device__ static ListIds decode_seg(const PrepareArgs& a, int p, int64_t off, i
     const int u = sfrom(mn[k - 1], sl >= w ? sl - w : 0);
     mn[k] = sel((sl >= w) & (u < mn[k - 1]), u, mn[k - 1]);
   }
-  int q = sl - 1;
+  uint32_t r = uint32_t(sl);  // (as in decode_wave)
 #pragma unroll
   for (int k = LOG - 1; k >= 0; --k) {
-    const int v = sfrom(mn[k], q > 0 ? q : 0);
-    q -= sel((q - (1 << k) + 1 >= 0) & (v >= d), 1 << k, 0);
+    const int v = __builtin_amdgcn_ds_bpermute(int((uint32_t(sb) + r) << 2) - 4, mn[k]);
+    r = __builtin_elementwise_sub_sat(r, sel(v >= d, 1u << k, 0u));
   }
-  const int st = q + 1;
+  const int st = int(r);
   // ---- register need (as in decode_wave)
   const int s_prev = sfrom(st, sl > 0 ? sl - 1 : 0);
   const int lch = s_prev - 1;
