@@ -647,18 +647,27 @@ __device__ static ListIds decode_wave(const PrepareArgs& a, int p, int64_t off, 
     const int ar = opok ? int((ARITY >> (2u * op)) & 3u) : 0;
     // depth after each token
     const int d = scan_add(act ? 1 - ar : 0);
-    // depth before < arity: underflow
-    const int err = !opok                              ? BEAGLE_PROG_BAD_OPCODE
-                    : (op == OP_VAR) & (int(arg) >= a.D)  ? BEAGLE_PROG_BAD_VAR
-                    : (op == OP_CONST) & (int(arg) >= cc) ? BEAGLE_PROG_BAD_CONST
-                    : d < 1                             ? BEAGLE_PROG_UNDERFLOW
-                                                        : 0;
     // lanes holding a token (L <= 64 here); ballots of lane conditions are
-    // masked with it on the scalar side
+    // masked with it and combined on the scalar side
     const uint64_t actm = L >= 64 ? ~0ull : (1ull << L) - 1ull;
-    const uint64_t em = __builtin_amdgcn_ballot_w64(err != 0) & actm;
-    if (em) status = lane_value(err, first_lane(em));
-    else if (lane_value(d, L - 1) != 1) status = BEAGLE_PROG_BAD_FINAL_DEPTH;
+    // faulty tokens: bad opcode, variable or constant slot out of range,
+    // depth before < arity (underflow); the first one's code is decided from
+    // its token on the scalar side, in that order of precedence
+    const uint64_t em = (__builtin_amdgcn_ballot_w64(!opok) |
+                         (__builtin_amdgcn_ballot_w64(op == OP_VAR) & __builtin_amdgcn_ballot_w64(int(arg) >= a.D)) |
+                         (__builtin_amdgcn_ballot_w64(op == OP_CONST) & __builtin_amdgcn_ballot_w64(int(arg) >= cc)) |
+                         __builtin_amdgcn_ballot_w64(d < 1)) &
+                        actm;
+    if (em) {
+      const uint32_t tj = uint32_t(lane_value(int(t), first_lane(em)));
+      const uint32_t opj = tj & 0xFFu, argj = tj >> 8;
+      status = opj >= uint32_t(N_OPCODES)                  ? BEAGLE_PROG_BAD_OPCODE
+               : (opj == OP_VAR) & (int(argj) >= a.D)      ? BEAGLE_PROG_BAD_VAR
+               : (opj == OP_CONST) & (int(argj) >= cc)     ? BEAGLE_PROG_BAD_CONST
+                                                           : BEAGLE_PROG_UNDERFLOW;
+    } else if (lane_value(d, L - 1) != 1) {
+      status = BEAGLE_PROG_BAD_FINAL_DEPTH;
+    }
     if (status == BEAGLE_PROG_OK) {
       vmask = wave_or(act & (op == OP_VAR) ? 1u << arg : 0u);
       ext = (__builtin_amdgcn_ballot_w64(op - uint32_t(OP_SQUARE) < uint32_t(N_OPCODES - OP_SQUARE)) & actm) != 0;
@@ -667,9 +676,10 @@ __device__ static ListIds decode_wave(const PrepareArgs& a, int p, int64_t off, 
       mn[0] = d;
 #pragma unroll
       for (int k = 1; k < 6; ++k) {
+        // min over [max(0, lane - 2^k + 1), lane]: lanes below w read their
+        // own value
         const int w = 1 << (k - 1);
-        const int u = from(mn[k - 1], lane - w);
-        mn[k] = sel((lane >= w) & (u < mn[k - 1]), u, mn[k - 1]);  // min over [lane - 2^k + 1, lane]
+        mn[k] = min(mn[k - 1], from(mn[k - 1], lane >= w ? lane - w : lane));
       }
       // descent: r moves down past windows [r - 2^k, r - 1] holding no
       // smaller depth; a window cut off at position 0 (mn[k] then covers
@@ -960,8 +970,7 @@ __device__ static ListIds decode_seg(const PrepareArgs& a, int p, int64_t off, i
 #pragma unroll
   for (int k = 1; k < LOG; ++k) {
     const int w = 1 << (k - 1);
-    const int u = sfrom(mn[k - 1], sl >= w ? sl - w : 0);
-    mn[k] = sel((sl >= w) & (u < mn[k - 1]), u, mn[k - 1]);
+    mn[k] = min(mn[k - 1], sfrom(mn[k - 1], sl >= w ? sl - w : sl));
   }
   uint32_t r = uint32_t(sl);  // (as in decode_wave)
 #pragma unroll
