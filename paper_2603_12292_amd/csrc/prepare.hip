@@ -610,7 +610,9 @@ __device__ __forceinline__ uint32_t word_handlers(const uint32_t* wt, uint32_t k
 struct WaveDecLds {
   uint32_t a[64];
   uint32_t b[64];
+  int32_t nd[68];  // register needs by lane; nd[NEED_ZERO] = 0
 };
+constexpr int NEED_ZERO = 64;
 
 // Decodes program p (at most 64 tokens, its header fields given, uniform)
 // with the calling wave; `tok` is the lane's token (lane < L, when the
@@ -699,25 +701,33 @@ __device__ static ListIds decode_wave(const PrepareArgs& a, int p, int64_t off, 
       const int s_prev = from(st, lane > 0 ? lane - 1 : 0);  // start of the right operand
       const int lch = s_prev - 1;                              // left child (binary)
       constexpr int NEED_UNKNOWN = 1024;
-      const bool is_un = ar == 1, is_bin = ar == 2;
+      const bool is_un = ar == 1;
       // A unary operator's need is its operand's, and a run of unary
       // operators stands on consecutive tokens (postfix), so a child's need
       // is read at the bottom of its run: the last non-unary token at or
       // before it (bot: that token + 1).  The relaxation then steps over
       // binary levels only.
       const int bot = scan_max(is_un ? 0 : lane + 1);
-      const int src_r = max(from(bot, lane > 0 ? lane - 1 : 0) - 1, 0);
-      const int src_l = max(from(bot, lch > 0 ? lch : 0) - 1, 0);
+      const int bot_r = max(from(bot, lane > 0 ? lane - 1 : 0) - 1, 0);
+      const int bot_l = max(from(bot, lch > 0 ? lch : 0) - 1, 0);
+      // The operands' needs are read from LDS, where slot NEED_ZERO holds 0:
+      // a leaf reads (0, 0) and keeps 1, a unary operator (its operand's, 0)
+      // and takes its operand's need -- one rule for every token, no
+      // selection per round.
+      const int src_r = sel(ar == 0, NEED_ZERO, bot_r);
+      const int src_l = sel(ar == 2, bot_l, NEED_ZERO);
+      if (lane == 0) sh.nd[NEED_ZERO] = 0;
       int need = ar == 0 ? 1 : NEED_UNKNOWN;
       int nr = 0, nl = 0;
       for (;;) {
-        nr = from(need, src_r);
-        nl = from(need, src_l);
-        const int nb2 = max(nl, nr) + int(nl == nr);
-        need = sel(is_bin, nb2, need);
-        if ((__builtin_amdgcn_ballot_w64(!is_un & (need >= 64)) & actm) == 0) break;
+        sh.nd[lane] = need;
+        __builtin_amdgcn_wave_barrier();
+        nr = sh.nd[src_r];
+        nl = sh.nd[src_l];
+        __builtin_amdgcn_wave_barrier();
+        need = max(nl, nr) + int(nl == nr);
+        if ((__builtin_amdgcn_ballot_w64(need >= 64) & actm) == 0) break;
       }
-      need = sel(is_un, from(need, max(bot - 1, 0)), need);
       need_root = lane_value(need, L - 1);
       // ---- output order: parents tell children their offset within the
       // parent's output range; the root's range starts at 0
@@ -983,21 +993,27 @@ __device__ static ListIds decode_seg(const PrepareArgs& a, int p, int64_t off, i
   const int s_prev = sfrom(st, sl > 0 ? sl - 1 : 0);
   const int lch = s_prev - 1;
   constexpr int NEED_UNKNOWN = 1024;
-  const bool is_un = ar == 1, is_bin = ar == 2;
+  const bool is_un = ar == 1;
   // children's needs read at the bottom of their runs of unary operators
   const int bot = seg_scan_max<SEG>(is_un ? 0 : sl + 1);
-  const int src_r = max(sfrom(bot, sl > 0 ? sl - 1 : 0) - 1, 0);
-  const int src_l = max(sfrom(bot, lch > 0 ? lch : 0) - 1, 0);
+  const int bot_r = sb + max(sfrom(bot, sl > 0 ? sl - 1 : 0) - 1, 0);
+  const int bot_l = sb + max(sfrom(bot, lch > 0 ? lch : 0) - 1, 0);
+  // (one rule for every token through the zero slot, as in decode_wave)
+  const int src_r = sel(ar == 0, NEED_ZERO, bot_r);
+  const int src_l = sel(ar == 2, bot_l, NEED_ZERO);
+  if (lane == 0) sh.nd[NEED_ZERO] = 0;
   int need = ar == 0 ? 1 : NEED_UNKNOWN;
   int nr = 0, nl = 0;
+  const uint64_t livem = __builtin_amdgcn_ballot_w64(live);  // (combined on the scalar side)
   for (;;) {
-    nr = sfrom(need, src_r);
-    nl = sfrom(need, src_l);
-    const int nb2 = max(nl, nr) + int(nl == nr);
-    need = sel(is_bin, nb2, need);
-    if (__builtin_amdgcn_ballot_w64(live & !is_un & (need >= 64)) == 0) break;
+    sh.nd[lane] = need;
+    __builtin_amdgcn_wave_barrier();
+    nr = sh.nd[src_r];
+    nl = sh.nd[src_l];
+    __builtin_amdgcn_wave_barrier();
+    need = max(nl, nr) + int(nl == nr);
+    if ((__builtin_amdgcn_ballot_w64(need >= 64) & livem) == 0) break;
   }
-  need = sel(is_un, sfrom(need, max(bot - 1, 0)), need);
   int need_root = sfrom(need, L >= 1 ? L - 1 : 0);
   // ---- output order (parents' lanes as byte addresses)
   const bool swap = (ar == 2) & (nr > nl);
