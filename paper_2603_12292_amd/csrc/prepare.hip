@@ -563,8 +563,6 @@ __device__ __forceinline__ uint32_t wave_or(uint32_t u) {
   return uint32_t(__builtin_amdgcn_readlane(v, 63));
 }
 __device__ __forceinline__ int first_lane(uint64_t m) { return __ffsll((unsigned long long)m) - 1; }
-// v of the lane below (lane 0: 0), one DPP whole-wave shift
-__device__ __forceinline__ int wave_shr1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, true); }
 // selections whose operands are evaluated first (a conditional expression
 // with computed operands can become a lane-divergent branch)
 template <class T>
@@ -764,11 +762,16 @@ __device__ static ListIds decode_wave(const PrepareArgs& a, int p, int64_t off, 
       const int n_after = scan_add(o_delta);
       const int n = n_after - o_delta;  // stack size before the token
       const uint32_t nxt = uint32_t(from(int(o_op), lane < 63 ? lane + 1 : 63));
-      const bool nxt_bin = (lane + 1 < L) & ((nxt < 4u) | (nxt - 100u < 6u));
-      const bool fused = act & o_term & (n >= 1) & nxt_bin;
-      const bool absorbed = wave_shr1(fused ? 1 : 0) != 0;  // the token before is a fused terminal
-      const bool ws = act & !absorbed;
-      const uint64_t wm = __builtin_amdgcn_ballot_w64(ws);
+      // fused pairs: a terminal on a non-empty stack followed by a binary
+      // operator; words: every token but such a terminal -- lane masks
+      // combined on the scalar side, turned back into lane conditions by
+      // inverse ballots (no VALU work)
+      const uint64_t fm = __builtin_amdgcn_ballot_w64(o_term) & __builtin_amdgcn_ballot_w64(n >= 1) &
+                          (__builtin_amdgcn_ballot_w64(nxt < 4u) | __builtin_amdgcn_ballot_w64(nxt - 100u < 6u)) &
+                          (actm >> 1);
+      const bool fused = __builtin_amdgcn_inverse_ballot_w64(fm);
+      const uint64_t wm = actm & ~(fm << 1);
+      const bool ws = __builtin_amdgcn_inverse_ballot_w64(wm);
       const int E = int(__builtin_amdgcn_mbcnt_hi(uint32_t(wm >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(wm), 0u)));
       const int widx = ws ? E : E - 1;  // word of each token (a fused pair's operator: the pair's word)
       L_dec = __popcll(wm);
@@ -953,6 +956,9 @@ __device__ static ListIds decode_seg(const PrepareArgs& a, int p, int64_t off, i
   }
   const bool ok0 = status == BEAGLE_PROG_OK;
   const bool act = ok0 & (sl < L);
+  // lane masks of lane conditions, combined on the scalar side
+  const uint64_t ltm = __builtin_amdgcn_ballot_w64(sl < L);
+  const uint64_t actm = __builtin_amdgcn_ballot_w64(ok0) & ltm;
   const uint32_t t = act ? tok : 0u;
   const uint32_t op = t & 0xFFu, arg = t >> 8;
   const bool opok = op < N_OPCODES;
@@ -964,16 +970,17 @@ __device__ static ListIds decode_seg(const PrepareArgs& a, int p, int64_t off, i
                   : (op == OP_CONST) & (int(arg) >= cc) ? BEAGLE_PROG_BAD_CONST
                   : d < 1                             ? BEAGLE_PROG_UNDERFLOW
                                                       : 0;
-  const uint64_t em = segbits(__builtin_amdgcn_ballot_w64(act & (err != 0)));
+  const uint64_t em = segbits(actm & __builtin_amdgcn_ballot_w64(err != 0));
   const int first_err = em ? __ffsll((unsigned long long)em) - 1 : 0;
   const int err_first = sfrom(err, first_err);
   const int d_last = sfrom(d, L >= 1 ? L - 1 : 0);
   if (ok0) status = em ? err_first : (d_last != 1 ? BEAGLE_PROG_BAD_FINAL_DEPTH : BEAGLE_PROG_OK);
   const bool ok = status == BEAGLE_PROG_OK;  // the structural pass ran
   const bool live = ok & (sl < L);
+  const uint64_t livem = __builtin_amdgcn_ballot_w64(ok) & ltm;
   const uint32_t vmask = seg_or<SEG>(live & (op == OP_VAR) ? 1u << arg : 0u, sb + SEG - 1);
   const bool ext =
-      segbits(__builtin_amdgcn_ballot_w64(live & (op - uint32_t(OP_SQUARE) < uint32_t(N_OPCODES - OP_SQUARE)))) != 0;
+      segbits(livem & __builtin_amdgcn_ballot_w64(op - uint32_t(OP_SQUARE) < uint32_t(N_OPCODES - OP_SQUARE))) != 0;
   // ---- subtree starts (descent over minima of power-of-two windows)
   int mn[LOG];
   mn[0] = d;
@@ -1004,7 +1011,6 @@ __device__ static ListIds decode_seg(const PrepareArgs& a, int p, int64_t off, i
   if (lane == 0) sh.nd[NEED_ZERO] = 0;
   int need = ar == 0 ? 1 : NEED_UNKNOWN;
   int nr = 0, nl = 0;
-  const uint64_t livem = __builtin_amdgcn_ballot_w64(live);  // (combined on the scalar side)
   for (;;) {
     sh.nd[lane] = need;
     __builtin_amdgcn_wave_barrier();
@@ -1046,11 +1052,16 @@ __device__ static ListIds decode_seg(const PrepareArgs& a, int p, int64_t off, i
   const int n_after = seg_scan_add<SEG>(o_delta);
   const int n = n_after - o_delta;
   const uint32_t nxt = uint32_t(sfrom(int(o_op), sl < SEG - 1 ? sl + 1 : SEG - 1));
-  const bool nxt_bin = (sl + 1 < L) & ((nxt < 4u) | (nxt - 100u < 6u));
-  const bool fused = live & o_term & (n >= 1) & nxt_bin;
-  const bool absorbed = (sl > 0) & (wave_shr1(fused ? 1 : 0) != 0);
-  const bool ws = live & !absorbed;
-  const uint64_t wm = __builtin_amdgcn_ballot_w64(ws);
+  // (as in decode_wave; the next token must be in the same segment, and a
+  // segment's first token absorbs nothing)
+  constexpr uint64_t SEGFIRST = SEG == 16 ? 0x0001000100010001ull : 0x0000000100000001ull;
+  constexpr uint64_t SEGLAST = SEGFIRST << (SEG - 1);
+  const uint64_t fm = __builtin_amdgcn_ballot_w64(o_term) & __builtin_amdgcn_ballot_w64(n >= 1) &
+                      (__builtin_amdgcn_ballot_w64(nxt < 4u) | __builtin_amdgcn_ballot_w64(nxt - 100u < 6u)) &
+                      (livem >> 1) & ~SEGLAST & livem;
+  const bool fused = __builtin_amdgcn_inverse_ballot_w64(fm);
+  const uint64_t wm = livem & ~((fm << 1) & ~SEGFIRST);
+  const bool ws = __builtin_amdgcn_inverse_ballot_w64(wm);
   const uint64_t below = sb == 0 ? 0ull : wm & ((1ull << sb) - 1ull);  // words of the segments below
   const int E = int(__builtin_amdgcn_mbcnt_hi(uint32_t(wm >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(wm), 0u))) -
                 __popcll(below);
