@@ -743,22 +743,27 @@ __device__ static ListIds decode_wave(const PrepareArgs& a, int p, int64_t off, 
       __builtin_amdgcn_wave_barrier();
 #pragma unroll
       for (int r = 0; r < 6; ++r) {
+        // (before the fifth and sixth rounds: done once every token's
+        // pointer has reached the root -- trees under 16 or 32 levels)
+        if (r >= 4 && (__builtin_amdgcn_ballot_w64((pk & 0xFC) != ((L - 1) << 2)) & actm) == 0) break;
         const int v = __builtin_amdgcn_ds_bpermute(pk & 0xFC, pk);
         pk = (pk & ~0xFC) + v;  // offsets add up, the parent pointer jumps
       }
       const int ostart = pk >> 8;
       const int oend = ostart + (lane - st);
       const uint32_t op2 = sel(swap & (op == OP_SUB), 100u + B_RSUB, sel(swap & (op == OP_DIV), 100u + B_RDIV, op));
-      if (act) sh.b[oend] = op2 | (arg << 8) | (uint32_t(ostart) << 16);
+      // (the token's arity rides along in bits 24..25)
+      if (act) sh.b[oend] = op2 | (arg << 8) | (uint32_t(ostart) << 16) | (uint32_t(ar) << 24);
       __builtin_amdgcn_wave_barrier();
-      const uint32_t e = act ? sh.b[lane] : 0xFFu;
+      const uint32_t e = act ? sh.b[lane] : 0x010000FFu;  // (no token: arity 1, stack unchanged)
       __builtin_amdgcn_wave_barrier();
       // ---- words, in output order (lane o holds output token o)
       const uint32_t o_op = e & 0xFFu, o_arg = (e >> 8) & 0xFFu;
-      const int o_st = int(e >> 16);  // start of its subtree
-      const bool o_bin = (o_op < 4u) | (o_op - 100u < 6u);
-      const bool o_term = o_op - uint32_t(OP_VAR) < 2u;  // VAR or CONST
-      const int o_delta = sel(act, sel(o_bin, -1, sel(o_term, 1, 0)), 0);
+      const int o_st = int((e >> 16) & 0xFFu);  // start of its subtree
+      const uint32_t o_ar = e >> 24;
+      const bool o_bin = o_ar == 2u;
+      const bool o_term = o_ar == 0u;  // VAR or CONST
+      const int o_delta = 1 - int(o_ar);
       const int n_after = scan_add(o_delta);
       const int n = n_after - o_delta;  // stack size before the token
       const uint32_t nxt = uint32_t(from(int(o_op), lane < 63 ? lane + 1 : 63));
@@ -1040,15 +1045,15 @@ __device__ static ListIds decode_seg(const PrepareArgs& a, int p, int64_t off, i
   const int ostart = pk >> 8;
   const int oend = ostart + (sl - st);
   const uint32_t op2 = sel(swap & (op == OP_SUB), 100u + B_RSUB, sel(swap & (op == OP_DIV), 100u + B_RDIV, op));
-  if (live) sh.b[sb + oend] = op2 | (arg << 8) | (uint32_t(ostart) << 16);
+  if (live) sh.b[sb + oend] = op2 | (arg << 8) | (uint32_t(ostart) << 16) | (uint32_t(ar) << 24);
   __builtin_amdgcn_wave_barrier();
-  const uint32_t e = live ? sh.b[lane] : 0xFFu;
+  const uint32_t e = live ? sh.b[lane] : 0x010000FFu;  // (as in decode_wave)
   __builtin_amdgcn_wave_barrier();
   // ---- words, in output order (position sl holds output token sl)
   const uint32_t o_op = e & 0xFFu, o_arg = (e >> 8) & 0xFFu;
-  const bool o_bin = (o_op < 4u) | (o_op - 100u < 6u);
-  const bool o_term = o_op - uint32_t(OP_VAR) < 2u;
-  const int o_delta = sel(live, sel(o_bin, -1, sel(o_term, 1, 0)), 0);
+  const uint32_t o_ar = e >> 24;
+  const bool o_term = o_ar == 0u;
+  const int o_delta = 1 - int(o_ar);
   const int n_after = seg_scan_add<SEG>(o_delta);
   const int n = n_after - o_delta;
   const uint32_t nxt = uint32_t(sfrom(int(o_op), sl < SEG - 1 ? sl + 1 : SEG - 1));
