@@ -759,6 +759,10 @@ __device__ static ListIds decode_wave(const PrepareArgs& a, int p, int64_t off, 
       __builtin_amdgcn_wave_barrier();
       // ---- words, in output order (lane o holds output token o)
       const uint32_t o_op = e & 0xFFu, o_arg = (e >> 8) & 0xFFu;
+      // a CONST word's value, loaded as soon as the slot is known (its
+      // latency then overlaps the word's assembly; stored with the word)
+      float cvv = 0.0f;
+      if (o_op == OP_CONST) cvv = a.consts[coff + o_arg];
       const int o_st = int((e >> 16) & 0xFFu);  // start of its subtree
       const uint32_t o_ar = e >> 24;
       const bool o_bin = o_ar == 2u;
@@ -799,7 +803,7 @@ __device__ static ListIds decode_wave(const PrepareArgs& a, int p, int64_t off, 
       if (need_root > MAX_STACK || L_dec > a.max_words) status = BEAGLE_PROG_TOO_LONG;
       if (ws) {
         a.code[off + widx] = word;
-        if (isc) a.cval[off + widx] = a.consts[coff + o_arg];
+        if (isc) a.cval[off + widx] = cvv;
       }
       int lc_short = -1;
       if constexpr (ADJ) {
@@ -1051,6 +1055,8 @@ __device__ static ListIds decode_seg(const PrepareArgs& a, int p, int64_t off, i
   __builtin_amdgcn_wave_barrier();
   // ---- words, in output order (position sl holds output token sl)
   const uint32_t o_op = e & 0xFFu, o_arg = (e >> 8) & 0xFFu;
+  float cvv = 0.0f;  // (loaded early, as in decode_wave)
+  if (o_op == OP_CONST) cvv = a.consts[coff + o_arg];
   const uint32_t o_ar = e >> 24;
   const bool o_term = o_ar == 0u;
   const int o_delta = 1 - int(o_ar);
@@ -1082,7 +1088,7 @@ __device__ static ListIds decode_seg(const PrepareArgs& a, int p, int64_t off, i
   if (ok && (need_root > MAX_STACK || L_dec > a.max_words)) status = BEAGLE_PROG_TOO_LONG;
   if (ws) {
     a.code[off + widx] = word;
-    if (isc) a.cval[off + widx] = a.consts[coff + o_arg];
+    if (isc) a.cval[off + widx] = cvv;
   }
   ListIds ids;
   if (status == BEAGLE_PROG_OK) {
